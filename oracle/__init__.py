@@ -1,0 +1,10 @@
+"""CPU oracle for the BI matrix-vector product (test infrastructure only).
+
+Only tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It shares no code with the GPU library.
+"""
+from .oracle import (build, rwg_table, matvec, pair_integrals, leaf_boxes, threads,
+                     OP_C, OP_EM, OP_BOTH, PRIM)
+
+__all__ = ["build", "rwg_table", "matvec", "pair_integrals", "leaf_boxes", "threads",
+           "OP_C", "OP_EM", "OP_BOTH", "PRIM"]

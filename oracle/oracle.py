@@ -1,0 +1,145 @@
+"""ctypes wrapper of bi_oracle.c (test infrastructure only; see bi_oracle.c)."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bi_oracle.c")
+_LIB = os.path.join(_HERE, "_bi_oracle.so")
+
+OP_C, OP_EM, OP_BOTH = 0, 1, 8
+PRIM = {"T": 2, "K": 3, "Tx": 4, "Kx": 5, "Gram": 6, "Gx": 7}
+KERNELS = {"full": 0, "static": 1, "sin": 2}
+
+_lib = None
+
+
+def build():
+    """Compile the oracle (gcc, OpenMP, IEEE double arithmetic)."""
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall",
+                           "-o", _LIB + ".tmp", _SRC, "-lm"])
+    os.replace(_LIB + ".tmp", _LIB)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_rwg.argtypes = [ctypes.c_int, P, ctypes.c_int, P, P, P]
+        lib.oracle_pair.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_int, P]
+        lib.oracle_matvec.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_int, P, P, ctypes.c_int, P, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int]
+        lib.oracle_boxes.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, P, P]
+        lib.oracle_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _mesh(verts, tris):
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    return v, t
+
+
+def threads():
+    return _load().oracle_threads()
+
+
+def rwg_table(verts, tris):
+    """(edges (N,2) with a < b, tri_pm (N,2) = (T+, T-))."""
+    v, t = _mesh(verts, tris)
+    n = 3 * len(t) // 2
+    e = np.zeros((n, 2), np.int32)
+    pm = np.zeros((n, 2), np.int32)
+    rc = _load().oracle_rwg(len(v), v.ctypes.data, len(t), t.ctypes.data, e.ctypes.data, pm.ctypes.data)
+    if rc < 0:
+        raise ValueError("oracle rejected the mesh (code %d)" % rc)
+    return e[:rc], pm[:rc]
+
+
+def leaf_boxes(verts, tris, leaf):
+    v, t = _mesh(verts, tris)
+    n = 3 * len(t) // 2
+    coords = np.zeros((n, 3), np.int32)
+    lev = ctypes.c_int(0)
+    rc = _load().oracle_boxes(len(v), v.ctypes.data, len(t), t.ctypes.data, leaf, coords.ctypes.data,
+                              ctypes.byref(lev))
+    if rc < 0:
+        raise ValueError("oracle rejected the mesh (code %d)" % rc)
+    return coords, lev.value
+
+
+def pair_integrals(ti, P, si, Q, k, nq=0, kernel="full", return_order=False):
+    """Local 4x3x3 integrals (T, K, Tx, Kx) of one triangle pair without RWG
+    coefficients; vertex ids ti/si decide which vertices are shared.
+    nq = 0 selects the converged order search (the order used is returned
+    with return_order=True)."""
+    ti = np.ascontiguousarray(ti, np.int32)
+    si = np.ascontiguousarray(si, np.int32)
+    P = np.ascontiguousarray(P, np.float64)
+    Q = np.ascontiguousarray(Q, np.float64)
+    out = np.zeros(72, np.float64)
+    rc = _load().oracle_pair(ti.ctypes.data, P.ctypes.data, si.ctypes.data, Q.ctypes.data,
+                             KERNELS[kernel], k, nq, out.ctypes.data)
+    if rc < 0 and nq > 0:
+        raise ValueError("bad arguments")
+    res = (out[0::2] + 1j * out[1::2]).reshape(4, 3, 3)
+    return (res, rc) if return_order else res
+
+
+def matvec(verts, tris, k, x, op=OP_C, rows=None, leaf=None, nq=0, classes=False):
+    """Dense Galerkin product.
+
+    x: (2N, nrhs) or (2N,) complex.  Returns y with shape (2*len(rows), nrhs)
+    (or (2N, nrhs)); rows [0, nr) are J/E-tested, [nr, 2nr) are M/H-tested.
+    op: OP_C, OP_EM, OP_BOTH (returns the pair (y_C, y_EM)), or a key of PRIM
+    (then only the J half of x is used and only the J half of y is filled).
+    With classes=True (needs leaf), returns (ncls, 2nr, nrhs): class 0 is the
+    near part (leaf boxes adjacent), class l >= 2 the part translated at level l.
+    """
+    v, t = _mesh(verts, tris)
+    N = 3 * len(t) // 2
+    x = np.asarray(x, dtype=np.complex128)
+    squeeze = x.ndim == 1
+    if squeeze:
+        x = x[:, None]
+    if x.shape[0] != 2 * N:
+        raise ValueError("x must have 2N rows")
+    nrhs = x.shape[1]
+    xf = np.asfortranarray(x)
+    opcode = PRIM[op] if isinstance(op, str) else int(op)
+    if rows is None:
+        rows_arr, nr = None, N
+    else:
+        rows_arr = np.ascontiguousarray(rows, np.int32)
+        nr = len(rows_arr)
+    if leaf is not None:
+        levels = leaf_boxes(verts, tris, leaf)[1]
+        ncls = max(levels, 1)
+    else:
+        ncls = 1
+    nops = 2 if opcode == OP_BOTH else 1
+    y = np.zeros((nops * ncls, nrhs, 2 * nr), np.complex128)
+    rc = _load().oracle_matvec(len(v), v.ctypes.data, len(t), t.ctypes.data, k, opcode, nrhs,
+                               xf.ctypes.data, None if rows_arr is None else rows_arr.ctypes.data,
+                               nr, y.ctypes.data, -1.0 if leaf is None else float(leaf), ncls, nq)
+    if rc < 0:
+        raise ValueError("oracle_matvec failed (code %d)" % rc)
+    y = np.transpose(y, (0, 2, 1))           # (nops*ncls, 2nr, nrhs)
+    res = []
+    for o in range(nops):
+        yo = y[o * ncls:(o + 1) * ncls]
+        if not classes:
+            yo = yo.sum(axis=0)
+            if squeeze:
+                yo = yo[:, 0]
+        elif squeeze:
+            yo = yo[:, :, 0]
+        res.append(yo)
+    return tuple(res) if nops == 2 else res[0]

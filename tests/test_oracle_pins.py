@@ -1,0 +1,384 @@
+"""Pins of the CPU oracle against what the mathematics fixes (no GPU).
+
+Each test names the passage of arXiv 2210.04892 or the identity it rests on.
+Together they are chosen so that a dropped term, a wrong sign, a wrong
+Jacobian or a transposed operand anywhere in the oracle fails one of them.
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import synth
+from pinmath import (K0, tri_area, tri_normal, tri_gauss, tri_radon7, linear_moment, potential,
+                     sph_j1, sph_y1, sphere_rule, rwg_coefficients)
+
+# two fixed, well-shaped but non-symmetric triangles sharing an edge (v0, v1)
+V0 = np.array([0.0, 0.0, 0.0])
+V1 = np.array([0.1, 0.0, 0.0])
+VA = np.array([0.03, 0.08, 0.01])
+VB = np.array([0.05, -0.07, 0.03])
+VC = np.array([-0.06, 0.02, 0.05])
+CASES = {
+    "coincident": ([0, 1, 2], np.array([V0, V1, VA]), [0, 1, 2], np.array([V0, V1, VA])),
+    "edge": ([0, 1, 2], np.array([V0, V1, VA]), [1, 0, 3], np.array([V1, V0, VB])),
+    "edge_coplanar": ([0, 1, 2], np.array([V0, V1, [0.03, 0.08, 0]]), [1, 0, 3],
+                      np.array([V1, V0, [0.05, -0.07, 0]])),
+    "vertex": ([0, 1, 2], np.array([V0, V1, VA]), [3, 4, 0], np.array([VB, VC, V0])),
+}
+
+
+def _dense(verts, tris, op):
+    """Primitive matrix from the oracle, column by column (tiny meshes)."""
+    N = 3 * len(tris) // 2
+    X = np.zeros((2 * N, N), complex)
+    X[:N] = np.eye(N)
+    return oracle.matvec(verts, tris, K0, X, op=op)[:N]
+
+
+# ------------------------------------------------------------------ RWG / mesh
+def test_rwg_convention_tetrahedron():
+    """RWG table convention: edges (a<b) in lexicographic order, T+ holds a->b
+    counter-clockwise (reading of the RWG pairs of the weak forms eqs. 32-33)."""
+    v, t = synth.tetrahedron()
+    e, pm = oracle.rwg_table(v, t)
+    assert len(e) == 6
+    assert [tuple(x) for x in e] == sorted(tuple(x) for x in e)
+    assert np.all(e[:, 0] < e[:, 1])
+    for (a, b), (tp, tm) in zip(e, pm):
+        cyc = lambda tr: [(tr[i], tr[(i + 1) % 3]) for i in range(3)]
+        assert (a, b) in cyc(list(t[tp]))
+        assert (b, a) in cyc(list(t[tm]))
+
+
+def test_mesh_rejections():
+    v, t = synth.octahedron()
+    flipped = t.copy()
+    flipped[0] = flipped[0][::-1]
+    with pytest.raises(ValueError):
+        oracle.rwg_table(v, flipped)           # inconsistent orientation
+    with pytest.raises(ValueError):
+        oracle.rwg_table(v, t[:, ::-1])        # inward normals
+    with pytest.raises(ValueError):
+        oracle.rwg_table(v, t[:-1])            # open surface
+
+
+# ------------------------------------------------------------------ P-H Gram
+@pytest.mark.parametrize("mesh", [synth.tetrahedron, synth.octahedron, synth.icosahedron])
+def test_gram_closed_form(mesh):
+    """Gram and twisted Gram (identity terms of eqs. 43, 44, 46) against the
+    exact moments of linear functions over a triangle."""
+    v, t = mesh()
+    e, pm = oracle.rwg_table(v, t)
+    N = len(e)
+    co = rwg_coefficients(v, t, e, pm)
+    G = np.zeros((N, N))
+    Gx = np.zeros((N, N))
+    for m in range(N):
+        for n in range(N):
+            for tm_, pmv, cm in co[m]:
+                for tn_, pnv, cn in co[n]:
+                    if tm_ != tn_:
+                        continue
+                    P = v[t[tm_]]
+                    G[m, n] += cm * cn * linear_moment(P, pmv, pnv)
+                    Gx[m, n] += cm * cn * linear_moment(P, pmv, pnv, twist=tri_normal(P))
+    Go = _dense(v, t, "Gram")
+    Gxo = _dense(v, t, "Gx")
+    assert np.abs(Go - G).max() <= 1e-13 * np.abs(G).max()
+    assert np.abs(Gxo - Gx).max() <= 1e-13 * np.abs(G).max()
+    assert np.all(np.linalg.eigvalsh(G) > 0)
+
+
+# ---------------------------------------------- transformations (smooth kernel)
+def _product_rule_sin(P, Q, k=K0, n=22):
+    """Reference local integrals with the entire kernel sin(kR)/(4 pi R) by
+    a plain product Gauss rule over the two triangles."""
+    x, wx = tri_gauss(P, n)
+    y, wy = tri_gauss(Q, n + 1)
+    nt = tri_normal(P)
+    d = x[:, None, :] - y[None, :, :]
+    R = np.linalg.norm(d, axis=2)
+    G = np.sin(k * R) / (4 * np.pi * R)
+    g1 = (k * R * np.cos(k * R) - np.sin(k * R)) / (4 * np.pi * R ** 3)
+    W = wx[:, None] * wy[None, :]
+    gG = g1[..., None] * d
+    out = np.zeros((4, 3, 3), complex)
+    for i in range(3):
+        a = x - P[i]
+        g = np.cross(nt, a)
+        for j in range(3):
+            b = y - Q[j]
+            c = np.cross(gG, b[None, :, :])
+            out[0, i, j] = np.sum(W * (-1j * k * (a @ b.T - 4 / k ** 2) * G))
+            out[1, i, j] = np.sum(W * np.einsum("pc,pqc->pq", a, c))
+            out[2, i, j] = np.sum(W * (-(-1j * k * (g @ b.T) * G - (2j / k) * np.einsum("pc,pqc->pq", g, gG))))
+            out[3, i, j] = np.sum(W * (-np.einsum("pc,pqc->pq", g, c)))
+    return out
+
+
+@pytest.mark.parametrize("case", ["coincident", "edge", "edge_coplanar", "vertex"])
+def test_touching_transformations_exact_for_smooth_kernel(case):
+    """The relative-coordinate transformations of touching pairs are exact
+    changes of variables: with an entire kernel they reproduce a plain
+    product rule to rounding (pins every Jacobian and sub-domain)."""
+    ti, P, si, Q = CASES[case]
+    ref = _product_rule_sin(P, Q)
+    got = oracle.pair_integrals(ti, P, si, Q, K0, nq=14, kernel="sin")
+    for op in range(4):
+        if case == "coincident" and op in (1, 3):
+            continue          # set to zero by definition on a flat triangle
+        assert np.abs(got[op] - ref[op]).max() <= 1e-12 * np.abs(ref[0]).max(), op
+
+
+# ------------------------------------------------ static singular closed forms
+def _split_static(ti, P, si, Q):
+    """Separate the two parts of the static-kernel T and Tx entries using two
+    wavenumbers: T/(-jk) = S_ab - 4 S_1 / k^2 and Tx/j = k U + (2/k) V."""
+    k1, k2 = 1.0, 3.0
+    o1 = oracle.pair_integrals(ti, P, si, Q, k1, kernel="static")
+    o2 = oracle.pair_integrals(ti, P, si, Q, k2, kernel="static")
+    X1, X2 = o1[0] / (-1j * k1), o2[0] / (-1j * k2)
+    S1 = (X1 - X2) / (4 / k2 ** 2 - 4 / k1 ** 2)
+    Y1, Y2 = o1[2] / 1j, o2[2] / 1j
+    # [k1 2/k1; k2 2/k2] [U V]^T = [Y1 Y2]^T
+    det = k1 * 2 / k2 - k2 * 2 / k1
+    V = (k1 * Y2 - k2 * Y1) / det
+    return S1.real, V.real
+
+
+def _outer_potential(P, Q):
+    """Int_P Int_Q 1/(4 pi R): closed-form inner potential, adaptive outer."""
+    A2 = 2 * tri_area(P)
+    f = lambda v_, u_: potential(P[0] + u_ * (P[1] - P[0]) + v_ * (P[2] - P[0]), Q)
+    val, _ = integrate.dblquad(f, 0, 1, 0, lambda u_: 1 - u_, epsabs=0, epsrel=1e-12)
+    return val * A2 / (4 * np.pi)
+
+
+def _contour_potential(P, Q, i):
+    """Int_P g_i . grad Phi_Q dA = sum over edges of P of Int Phi_Q (g_i . nu) dl
+    (divergence theorem; the surface divergence of n x (r - p_i) vanishes)."""
+    n = tri_normal(P)
+    tot = 0.0
+    for e in range(3):
+        A, B = P[e], P[(e + 1) % 3]
+        L = np.linalg.norm(B - A)
+        nu = np.cross(B - A, n) / L                      # outward in-plane normal
+        f = lambda s: potential(A + s * (B - A), Q) * np.dot(np.cross(n, A + s * (B - A) - P[i]), nu)
+        val, _ = integrate.quad(f, 0, 1, epsabs=0, epsrel=1e-13, limit=200)
+        tot += val * L
+    return tot / (4 * np.pi)
+
+
+def test_potential_closed_form_is_right():
+    """The closed-form potential used below against brute force off the triangle."""
+    Q = CASES["edge"][3]
+    for x in ([0.05, 0.03, 0.2], [0.3, -0.2, -0.05], [0.02, 0.01, 0.015]):
+        y, w = tri_gauss(Q, 120)
+        brute = np.sum(w / np.linalg.norm(y - np.array(x), axis=1))
+        assert abs(potential(x, Q) - brute) <= 1e-10 * abs(brute)
+
+
+@pytest.mark.parametrize("case", ["coincident", "edge", "edge_coplanar", "vertex"])
+def test_static_singular_integrals(case):
+    """Singular parts of touching pairs against closed forms: the 1/R double
+    integral and the 1/R^2 (grad G) term of Tx reduced to a contour integral."""
+    ti, P, si, Q = CASES[case]
+    S1, V = _split_static(ti, P, si, Q)
+    ref1 = _outer_potential(P, Q)
+    assert np.abs(S1 - ref1).max() <= 1e-9 * abs(ref1)
+    for i in range(3):
+        refV = _contour_potential(P, Q, i)
+        assert np.abs(V[i] - refV).max() <= 1e-8 * abs(ref1) * 10, (i, V[i], refV)
+
+
+# ------------------------------------------------------------- P-G coplanar
+def test_coplanar_K_vanishes():
+    """K and Kx vanish for coplanar triangle pairs: (x - y) x f_n is normal to
+    the plane while f_m and n x f_m are tangential (flat-plate pairs)."""
+    v, t = synth.flat_plate(0.3, 3)
+    for si in range(len(t)):
+        o = oracle.pair_integrals(t[0], v[t[0]], t[si], v[t[si]], K0)
+        scale = np.abs(o[0]).max()
+        assert np.abs(o[1]).max() <= 1e-14 * scale
+        assert np.abs(o[3]).max() <= 1e-14 * scale
+
+
+# ----------------------------------------------------------- P-F convergence
+@pytest.mark.parametrize("rel", [1, 2, 3])
+def test_touching_pairs_converged(rel):
+    """The order search returns values that a much higher fixed order confirms."""
+    v, t = synth.icosphere(8, 0.5)
+    t0 = t[37]
+    j = next(j for j in range(len(t)) if len(set(t0) & set(t[j])) == rel)
+    P, Q = v[t0], v[t[j]]
+    auto = oracle.pair_integrals(t0, P, t[j], Q, K0)
+    hi = oracle.pair_integrals(t0, P, t[j], Q, K0, nq=40)
+    for op in range(4):
+        scale = np.abs(hi[op]).max()
+        if scale > 0:
+            assert np.abs(auto[op] - hi[op]).max() <= 2e-12 * scale
+
+
+# ------------------------------------------------------------ P-B symmetry
+@pytest.mark.parametrize("mesh", [synth.tetrahedron, synth.octahedron, synth.icosahedron])
+def test_T_and_K_symmetric(mesh):
+    """<f_m, L f_n> and <f_m, Kbar f_n> are symmetric (symmetric kernel; grad G
+    odd under r <-> r'); touching pairs are computed with the test triangle
+    first, so this also cross-checks the singular rules against themselves."""
+    v, t = mesh()
+    T = _dense(v, t, "T")
+    Kk = _dense(v, t, "K")
+    assert np.abs(T - T.T).max() <= 1e-11 * np.abs(T).max()
+    assert np.abs(Kk - Kk.T).max() <= 1e-11 * np.abs(Kk).max()
+
+
+# -------------------------------------------------------- P-E radiating part
+def test_radiating_parts_equal_plane_wave_sums():
+    """sin(kR)/(4 pi R) = k/(16 pi^2) Int exp(-jk khat.(r - r')) dOmega, exactly.
+    Hence Re T, Im K, Re Tx and Im Kx of every entry are sphere sums of
+    radiation patterns, independent of the singular quadrature.  Non-touching
+    triangle pairs use the 7-point points (the matrix definition), touching
+    pairs converged patterns."""
+    v, t = synth.icosahedron(0.3)
+    e, pm = oracle.rwg_table(v, t)
+    N = len(e)
+    co = rwg_coefficients(v, t, e, pm)
+    khat, w = sphere_rule(20)
+    k = K0
+
+    def pats(P, rule):
+        x, wq = rule
+        ph = np.exp(1j * k * x @ khat.T)                      # (q, K)
+        nt = tri_normal(P)
+        vec = np.stack([np.einsum("q,qc,qK->Kc", wq, x - P[i], ph) for i in range(3)])
+        twv = np.stack([np.einsum("q,qc,qK->Kc", wq, np.cross(nt, x - P[i]), ph) for i in range(3)])
+        chg = np.einsum("q,qK->K", wq, ph)
+        return vec, twv, chg
+
+    p7 = [pats(v[tr], tri_radon7(v[tr])) for tr in t]
+    pc = [pats(v[tr], tri_gauss(v[tr], 14)) for tr in t]
+    c = k / (16 * np.pi ** 2)
+    kx = lambda R: np.cross(khat, R)
+
+    def block(A, B):
+        """(T, K, Tx, Kx) radiating parts between test pattern A[i] and
+        source pattern B[j] (vec (K,3), twisted vec (K,3), charge (K,))."""
+        Sm, Sgm, rm = np.conj(A[0]), np.conj(A[1]), 2 * np.conj(A[2])
+        Rn, rn = B[0], 2 * B[2]
+        T_ = -k * c * np.sum(w * (np.sum(Sm * Rn, -1) - rm * rn / k ** 2), -1)
+        K_ = -c * np.sum(w * np.sum(Sm * (-1j * k) * kx(Rn), -1), -1)
+        Tx_ = c * np.sum(w * (k * np.sum(Sgm * Rn, -1) - 1j * np.sum(Sgm * khat, -1) * rn), -1)
+        Kx_ = c * np.sum(w * np.sum(Sgm * (-1j * k) * kx(Rn), -1), -1)
+        return T_.real, K_.real, Tx_.real, Kx_.real
+
+    # local edge index of each RWG on each of its triangles
+    ref = {op: np.zeros((N, N)) for op in ("T", "K", "Tx", "Kx")}
+    loc = []
+    for lst in co:
+        loc.append([(tri, int(np.argmin(np.linalg.norm(v[t[tri]] - p, axis=1))), cf) for tri, p, cf in lst])
+    for m in range(N):
+        for n in range(N):
+            acc = np.zeros(4)
+            for tm_, i, cm in loc[m]:
+                for tn_, j, cn in loc[n]:
+                    touch = len(set(t[tm_]) & set(t[tn_])) > 0
+                    A, B = (pc[tm_], pc[tn_]) if touch else (p7[tm_], p7[tn_])
+                    acc += cm * cn * np.array(block((A[0][i], A[1][i], A[2]), (B[0][j], B[1][j], B[2])))
+            for key, val in zip(("T", "K", "Tx", "Kx"), acc):
+                ref[key][m, n] = val
+    T = _dense(v, t, "T")
+    Kk = _dense(v, t, "K")
+    Tx = _dense(v, t, "Tx")
+    Kx = _dense(v, t, "Kx")
+    assert np.abs(T.real - ref["T"]).max() <= 1e-11 * np.abs(T).max()
+    assert np.abs(Kk.imag - ref["K"]).max() <= 1e-11 * np.abs(Kk).max()
+    assert np.abs(Tx.real - ref["Tx"]).max() <= 1e-11 * np.abs(Tx).max()
+    assert np.abs(Kx.imag - ref["Kx"]).max() <= 1e-11 * np.abs(Kx).max()
+
+
+# ------------------------------------------------- P-D / P-C sphere physics
+def _project(v, t, field, order=8):
+    """b_m = <f_m, F> with a converged triangle rule (F: (q,3) -> (q,3))."""
+    e, pm = oracle.rwg_table(v, t)
+    co = rwg_coefficients(v, t, e, pm)
+    b = np.zeros(len(e), complex)
+    for m, lst in enumerate(co):
+        for tri, p, cm in lst:
+            x, wq = tri_gauss(v[t[tri]], order)
+            F = field(x, tri_normal(v[t[tri]]))
+            b[m] += cm * np.sum(wq[:, None] * (x - p) * F)
+    return b
+
+
+def _gram(v, t):
+    return _dense(v, t, "Gram").real
+
+
+@pytest.mark.slow
+def test_sphere_TE_eigenvalue():
+    """On a sphere of radius a, L maps the TE degree-1 current z x r to
+    -(ka)^2 j1(ka) h1(ka) times itself (addition theorem of G); at ka = pi this
+    is -1 + j/pi.  Rayleigh quotient of the Galerkin T; error O(h^2)."""
+    a = 0.5
+    exact = -(K0 * a) ** 2 * sph_j1(K0 * a) * (sph_j1(K0 * a) - 1j * sph_y1(K0 * a))
+    errs = []
+    for m in (4, 8):
+        v, t = synth.icosphere(m, a)
+        N = 3 * len(t) // 2
+        b = _project(v, t, lambda x, n: np.cross([0, 0, 1.0], x) / a)
+        x = np.linalg.solve(_gram(v, t), b)
+        X = np.zeros(2 * N, complex)
+        X[:N] = x
+        Tx_ = oracle.matvec(v, t, K0, X, op="T")[:N]
+        Gx_ = oracle.matvec(v, t, K0, X, op="Gram")[:N]
+        q = np.vdot(x, Tx_) / np.vdot(x, Gx_)
+        errs.append(abs(q - exact) / abs(exact))
+    print("TE eigenvalue relative errors (m=4, m=8):", errs)
+    assert errs[1] < 0.02 and errs[1] < errs[0]
+
+
+@pytest.mark.slow
+def test_extinction_plane_wave():
+    """Currents of an incident plane wave (J = n x H, M = -n x E) radiate -E,-H
+    inside and 0 outside, so on the surface the principal-value operators give
+    the average: T xJ - K xM = -<f,E>/2 and T xM + K xJ = -<f,H>/2 (eqs. 22,
+    24).  For the C block (eqs. 43-46, alpha = 1/2) the same identities give
+    C^JJ xJ + C^JM xM = <f, 3E/4 + 5 n x H/4> and
+    C^MJ xJ + C^MM xM = <f, H/4 - 3 n x E/4>: all K terms cancel, so any sign
+    error in the combination shows.  Discretisation error O(h)."""
+    khat = np.array([0.0, 0.0, 1.0])
+    pol = np.array([1.0, 0.0, 0.0])
+    Ei = lambda x: pol[None, :] * np.exp(-1j * K0 * x @ khat)[:, None]
+    Hi = lambda x: np.cross(khat, pol)[None, :] * np.exp(-1j * K0 * x @ khat)[:, None]
+    errs = []
+    for m in (4, 8):
+        v, t = synth.icosphere(m, 0.5)
+        N = 3 * len(t) // 2
+        G = _gram(v, t)
+        xJ = np.linalg.solve(G, _project(v, t, lambda x, n: np.cross(n, Hi(x))))
+        xM = np.linalg.solve(G, _project(v, t, lambda x, n: -np.cross(n, Ei(x))))
+        X = np.concatenate([xJ, xM])
+        yC, yEM = oracle.matvec(v, t, K0, X, op=oracle.OP_BOTH)
+        refs = [(yEM[:N], -0.5 * _project(v, t, lambda x, n: Ei(x))),
+                (yEM[N:], -0.5 * _project(v, t, lambda x, n: Hi(x))),
+                (yC[:N], _project(v, t, lambda x, n: 0.75 * Ei(x) + 1.25 * np.cross(n, Hi(x)))),
+                (yC[N:], _project(v, t, lambda x, n: 0.25 * Hi(x) - 0.75 * np.cross(n, Ei(x))))]
+        errs.append([np.linalg.norm(a - b) / np.linalg.norm(b) for a, b in refs])
+    errs = np.array(errs)
+    print("extinction relative errors [E, H, C-J, C-M] at m=4 / m=8:", errs)
+    assert np.all(errs[1] < 0.06), errs
+    assert np.all(errs[1] < errs[0]), errs
+
+
+# ------------------------------------------------------------- box rule
+@pytest.mark.parametrize("m,r,levels,boxes,near", [(8, 0.5, 3, 56, 846744)])
+def test_box_rule_counts(m, r, levels, boxes, near):
+    """Leaf boxes of the RWG centres (0.25 wavelength leaves): level count,
+    non-empty leaf boxes and near RWG pairs (Chebyshev distance <= 1)."""
+    v, t = synth.icosphere(m, r)
+    coords, lev = oracle.leaf_boxes(v, t, 0.25)
+    assert lev == levels
+    assert len({tuple(c) for c in coords}) == boxes
+    d = np.abs(coords[:, None, :] - coords[None, :, :]).max(axis=2)
+    assert int((d <= 1).sum()) == near
