@@ -1,0 +1,165 @@
+/*
+ * mlfma.h -- C ABI of the MI355X library for the boundary-integral (BI)
+ * matrix-vector product of the coupled HDG-BI method (arXiv 2210.04892),
+ * accelerated by the multilevel fast multipole algorithm (MLFMA).
+ *
+ * The product is the step of the hybrid solver's matrix-vector subroutine
+ * that multiplies the guess vector by the dense BI block (Sec. II-E, step
+ * 2(a), "Hybrid Solver"): y = C x with C = [[C^JJ, C^JM], [C^MJ, C^MM]]
+ * (entries eqs. 43-46, alpha = 1/2 as fixed in Sec. II-C), or the plain
+ * operator pair of the Stratton-Chu representation (eqs. 22a/b tested as in
+ * the EFIE/MFIE eqs. 24a/b).  Unknowns are the RWG coefficients of the
+ * equivalent currents J and M (expansions eqs. exp4-exp5); 2N of them for N
+ * RWG functions.
+ *
+ * Conventions (fixed readings where the paper is silent):
+ *  - time dependence e^{+j w t}; Green's function exp(-jkR)/(4 pi R);
+ *    fields normalised so that the EFIE operator L carries -jk and the MFIE
+ *    operator K carries 1 (Sec. II-A normalisation by sqrt(eps0/mu0));
+ *  - the surface is closed and its triangles are counter-clockwise seen
+ *    from outside (outward normal, Sec. II-A);
+ *  - RWG n lives on the edge (a,b), a < b, numbered in lexicographic order of
+ *    (a,b); T+ is the triangle in which a->b runs counter-clockwise;
+ *    f = (l/2A+)(r - p+) on T+ and (l/2A-)(p- - r) on T-;
+ *  - triangle pairs that share no vertex are integrated with the 7-point
+ *    degree-5 rule on both triangles; pairs that share a vertex, an edge or
+ *    the whole triangle are integrated to ~1e-12 relative accuracy.
+ *
+ * Vectors are complex, interleaved (re, im), column-major 2N x nrhs with a
+ * leading dimension; rows [0, N) hold J (op C) or the E-side (op EM)
+ * coefficients, rows [N, 2N) hold M (op C) or the H-side (op EM), in the RWG
+ * order above.  All functions return MLFMA_OK (0) or a negative error code;
+ * mlfma_last_error() then describes the failure (thread-local text).  No
+ * C++ exception crosses this boundary.
+ */
+#ifndef MLFMA_H
+#define MLFMA_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mlfma_ctx *mlfma_handle;
+
+enum {
+    MLFMA_OK = 0,
+    MLFMA_ERR_ARG = -1,          /* bad argument (null pointer, size, enum)        */
+    MLFMA_ERR_MESH = -2,         /* open, non-manifold, mis-oriented, degenerate   */
+    MLFMA_ERR_OOM = -3,          /* device memory exhausted or over the budget     */
+    MLFMA_ERR_HIP = -4,          /* HIP runtime error (launch or asynchronous)     */
+    MLFMA_ERR_STATE = -5,        /* call out of order (e.g. matvec before nearfield) */
+    MLFMA_ERR_TREE = -6,         /* touching triangles whose RWGs are not near     */
+    MLFMA_ERR_UNSUPPORTED = -7
+};
+
+enum { MLFMA_C128 = 0, MLFMA_C64 = 1 };     /* vector element type = arithmetic  */
+enum {
+    MLFMA_OP_C = 0,    /* y = C x, the BI block of eq. 42 (entries eqs. 43-46)        */
+    MLFMA_OP_EM = 1    /* y = [T xJ - K xM ; T xM + K xJ], T = <f,L f>, K = <f,Kbar f> */
+};
+
+typedef struct {
+    double wavenumber;   /* k in rad per length unit (k = 2 pi / lambda)            */
+    double leaf_size;    /* edge of the finest octree boxes, length units           */
+    int digits;          /* MLFMA accuracy parameter d0 of the truncation rule (3)  */
+    int interp_order;    /* Lagrange points per angular dimension (6)               */
+    int leaf_extra_L;    /* extra multipoles added at the leaf level (2)            */
+    int max_rhs;         /* right-hand sides the workspace is sized for (1)         */
+    int device;          /* HIP device ordinal (-1: the current device)             */
+    unsigned long long hbm_budget_bytes;   /* 0 = no limit                          */
+} mlfma_options;
+
+/* Fill *opt with defaults: k = 2 pi, leaf 0.25, d0 = 3, order 6, extra 2,
+ * one RHS, current device, no budget.  Returns MLFMA_ERR_ARG on NULL. */
+int mlfma_options_default(mlfma_options *opt);
+
+/*
+ * Validate the closed surface (Sec. II-B: the triangles of Gamma_h), build
+ * the RWG table, the octree over RWG centres (edge midpoints), the k-space
+ * sampling, interpolation stencils and translation operators of every level,
+ * and the leaf radiation/receive patterns on the device.
+ *   verts: n_verts x 3 doubles, row-major (host memory, copied);
+ *   tris : n_tris x 3 ints, row-major, counter-clockwise from outside.
+ * On success *out owns all device memory of the geometry.  Errors:
+ * MLFMA_ERR_MESH, MLFMA_ERR_TREE, MLFMA_ERR_OOM, MLFMA_ERR_HIP, MLFMA_ERR_ARG.
+ * Blocking (synchronises the device).
+ */
+int mlfma_build_tree(const double *verts, long long n_verts, const int *tris, long long n_tris,
+                     const mlfma_options *opt, mlfma_handle *out);
+
+/*
+ * Compute the near-field blocks in double precision on the device: for every
+ * pair of RWGs whose leaf boxes are adjacent, the entries of T, K, n x L and
+ * n x Kbar (the operators of eqs. 22-27 and 43-46), the identity terms of
+ * eqs. 43, 44, 46 (Gram matrices), and a single-precision copy.  Blocking.
+ * Errors: MLFMA_ERR_OOM, MLFMA_ERR_HIP, MLFMA_ERR_ARG.
+ */
+int mlfma_precompute_nearfield(mlfma_handle h);
+
+/*
+ * y = A x for A = C (op MLFMA_OP_C) or the EM pair (op MLFMA_OP_EM): the near
+ * part from the stored blocks, the far part by MLFMA (radiation, aggregation
+ * with Lagrange interpolation, diagonal translation, anterpolation and
+ * disaggregation, receive).  Sec. II-E step 2(a).
+ *   dtype: MLFMA_C128 (complex double in/out, double arithmetic) or MLFMA_C64
+ *          (complex float in/out, single arithmetic on tables precomputed in
+ *          double);
+ *   x, y : DEVICE pointers, 2N x nrhs column-major, leading dimensions ldx,
+ *          ldy >= 2N (elements); y is overwritten; x and y must not overlap;
+ *   hip_stream: hipStream_t to enqueue on (NULL = default stream).
+ * Asynchronous: returns after enqueueing.  Enqueue-time errors are returned;
+ * an asynchronous device error is reported by the next call on the handle.
+ * Grows the workspace (a blocking allocation) if nrhs exceeds what it was
+ * sized for.  Not thread-safe for concurrent calls on one handle.
+ * Errors: MLFMA_ERR_STATE (near field not computed), MLFMA_ERR_ARG,
+ * MLFMA_ERR_OOM, MLFMA_ERR_HIP.
+ */
+int mlfma_matvec_LK(mlfma_handle h, int op, int dtype, long long nrhs, const void *x, long long ldx,
+                    void *y, long long ldy, void *hip_stream);
+
+/*
+ * Diagnostic split of mlfma_matvec_LK (same arguments, same asynchrony):
+ *   part = MLFMA_PART_NEAR : near-field blocks (and identity terms) only;
+ *   part = MLFMA_PART_FAR  : MLFMA far field only;
+ *   part = MLFMA_PART_ALL  : both (identical to mlfma_matvec_LK);
+ *   part = MLFMA_PART_LEVEL + l : far field restricted to the translations
+ *          at octree level l (2 <= l < levels), the per-level error split.
+ * Errors as mlfma_matvec_LK, plus MLFMA_ERR_ARG for an unknown part.
+ */
+enum { MLFMA_PART_NEAR = 1, MLFMA_PART_FAR = 2, MLFMA_PART_ALL = 3, MLFMA_PART_LEVEL = 16 };
+int mlfma_matvec_part(mlfma_handle h, int op, int dtype, int part, long long nrhs, const void *x, long long ldx,
+                      void *y, long long ldy, void *hip_stream);
+
+/* Free every device and host resource of the handle.  NULL is accepted. */
+int mlfma_release(mlfma_handle h);
+
+/* Sizes: RWG count N, octree levels (root = level 0), bytes of device memory
+ * held by the handle.  Any output pointer may be NULL. */
+int mlfma_query(mlfma_handle h, long long *n_rwg, int *levels, unsigned long long *hbm_bytes);
+
+/* RWG table in the order of the vectors: edge_ab (N x 2, a < b) and tri_pm
+ * (N x 2, T+ then T-); host buffers supplied by the caller, either may be NULL. */
+int mlfma_rwg_table(mlfma_handle h, int *edge_ab, int *tri_pm);
+
+/* Per-level description: for level l (2 <= l < levels) writes
+ * info[0..5] = {boxes, L, K samples, translations, box edge * 1e6 (rounded),
+ * 0}.  Returns MLFMA_ERR_ARG for a level without translations. */
+int mlfma_level_info(mlfma_handle h, int level, long long info[6]);
+
+/* Text of the last error of the calling thread ("" if none). */
+const char *mlfma_last_error(void);
+
+/*
+ * Host utility (no device use): the diagonal translation operator
+ * T_L(khat, X) = sum_{l=0..L} (-j)^l (2l+1) h_l^(2)(k|X|) P_l(khat . X/|X|)
+ * for nk unit directions khat (nk x 3), written as nk complex (re, im) pairs.
+ * With it exp(-jk|X+d|)/(4 pi |X+d|) = -jk/(16 pi^2) Int exp(-jk khat.d) T_L dOmega
+ * for |d| < |X| (the plane-wave expansion MLFMA is built on).
+ */
+int mlfma_translation_operator(double k, int L, const double X[3], long long nk, const double *khat,
+                               double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

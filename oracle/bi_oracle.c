@@ -497,7 +497,7 @@ static void pair_integrals(const int ti[3], const double Praw[3][3], const int s
 /*
  * Touching pairs with an a-posteriori order check: orders 10, 13, 16, ... are
  * tried until two successive results agree to tol relative to the largest
- * entry of each operator (the last, higher-order result is returned).  With
+ * entry of the pair (the last, higher-order result is returned).  With
  * the exponential convergence of the transformed integrands the returned
  * value is then accurate to a small fraction of tol.
  */
@@ -512,17 +512,18 @@ static int pair_integrals_auto(const int ti[3], const double P[3][3], const int 
     if (!touching) { memcpy(out, prev, sizeof(prev)); return 0; }
     for (int nq = 13; nq <= 49; nq += 3) {
         pair_integrals(ti, P, si, Q, nt, kind, k, nq, out);
-        int ok = 1;
-        for (int o = 0; o < 4; o++) {
-            double scale = 0, diff = 0;
+        /* one scale for the four operators: they enter the products of
+         * eqs. 22-24 and 43-46 side by side, so an error is judged against
+         * the pair's largest entry (an operator that nearly vanishes, such as
+         * K on almost coplanar triangles, only has a rounding floor) */
+        double scale = 0, diff = 0;
+        for (int o = 0; o < 4; o++)
             for (int i = 0; i < 3; i++)
                 for (int j = 0; j < 3; j++) {
                     if (cabs(out[o][i][j]) > scale) scale = cabs(out[o][i][j]);
                     if (cabs(out[o][i][j] - prev[o][i][j]) > diff) diff = cabs(out[o][i][j] - prev[o][i][j]);
                 }
-            if (diff > tol * scale) ok = 0;
-        }
-        if (ok) return nq;
+        if (diff <= tol * scale) return nq;
         memcpy(prev, out, sizeof(prev));
     }
     return -1;   /* not converged at order 48: result kept, caller is told */

@@ -1,0 +1,180 @@
+"""Thin ctypes binding of the C ABI in include/mlfma.h.
+
+Argument marshalling only: every step of the product runs in the HIP
+library.  torch provides device memory and the current stream; it is
+imported before the library is loaded so both use one HIP runtime.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_mlfma.so")
+
+OP_C, OP_EM = 0, 1
+C128, C64 = 0, 1
+PART_NEAR, PART_FAR, PART_ALL, PART_LEVEL = 1, 2, 3, 16
+_OPS = {"C": OP_C, "EM": OP_EM, OP_C: OP_C, OP_EM: OP_EM}
+ERRORS = {-1: "MLFMA_ERR_ARG", -2: "MLFMA_ERR_MESH", -3: "MLFMA_ERR_OOM", -4: "MLFMA_ERR_HIP",
+          -5: "MLFMA_ERR_STATE", -6: "MLFMA_ERR_TREE", -7: "MLFMA_ERR_UNSUPPORTED"}
+
+
+class MlfmaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (ERRORS.get(code, code), msg))
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("wavenumber", ctypes.c_double), ("leaf_size", ctypes.c_double), ("digits", ctypes.c_int),
+                ("interp_order", ctypes.c_int), ("leaf_extra_L", ctypes.c_int), ("max_rhs", ctypes.c_int),
+                ("device", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_ulonglong)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is missing: run __graft_entry__.build() first" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, LL = ctypes.c_void_p, ctypes.c_longlong
+        L.mlfma_options_default.argtypes = [ctypes.POINTER(Options)]
+        L.mlfma_build_tree.argtypes = [P, LL, P, LL, ctypes.POINTER(Options), ctypes.POINTER(P)]
+        L.mlfma_precompute_nearfield.argtypes = [P]
+        L.mlfma_matvec_LK.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, P]
+        L.mlfma_matvec_part.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, P]
+        L.mlfma_release.argtypes = [P]
+        L.mlfma_query.argtypes = [P, ctypes.POINTER(LL), ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_ulonglong)]
+        L.mlfma_rwg_table.argtypes = [P, P, P]
+        L.mlfma_level_info.argtypes = [P, ctypes.c_int, P]
+        L.mlfma_last_error.restype = ctypes.c_char_p
+        L.mlfma_translation_operator.argtypes = [ctypes.c_double, ctypes.c_int, P, LL, P, P]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise MlfmaError(rc, lib().mlfma_last_error().decode())
+
+
+def default_options():
+    o = Options()
+    _check(lib().mlfma_options_default(ctypes.byref(o)))
+    return o
+
+
+class Geometry:
+    """A closed triangulated surface with its octree, tables and near field
+    resident on one GPU (mlfma_build_tree / mlfma_precompute_nearfield)."""
+
+    def __init__(self, verts, tris, k=2 * math.pi, leaf=0.25, digits=3, interp_order=6, leaf_extra_L=2,
+                 max_rhs=1, device=None, hbm_budget_bytes=0):
+        o = default_options()
+        o.wavenumber = k
+        o.leaf_size = leaf
+        o.digits = digits
+        o.interp_order = interp_order
+        o.leaf_extra_L = leaf_extra_L
+        o.max_rhs = max_rhs
+        o.device = torch.cuda.current_device() if device is None else int(device)
+        o.hbm_budget_bytes = hbm_budget_bytes
+        self.device = o.device
+        v = np.ascontiguousarray(verts, dtype=np.float64)
+        t = np.ascontiguousarray(tris, dtype=np.int32)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().mlfma_build_tree(v.ctypes.data, len(v), t.ctypes.data, len(t), ctypes.byref(o),
+                                          ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_longlong()
+        lev = ctypes.c_int()
+        _check(lib().mlfma_query(self._h, ctypes.byref(n), ctypes.byref(lev), None))
+        self.n_rwg = n.value
+        self.levels = lev.value
+
+    def precompute(self):
+        with torch.cuda.device(self.device):
+            _check(lib().mlfma_precompute_nearfield(self._h))
+        return self
+
+    @property
+    def hbm_bytes(self):
+        b = ctypes.c_ulonglong()
+        _check(lib().mlfma_query(self._h, None, None, ctypes.byref(b)))
+        return b.value
+
+    def rwg_table(self):
+        e = np.zeros((self.n_rwg, 2), np.int32)
+        pm = np.zeros((self.n_rwg, 2), np.int32)
+        _check(lib().mlfma_rwg_table(self._h, e.ctypes.data, pm.ctypes.data))
+        return e, pm
+
+    def level_info(self, level):
+        info = np.zeros(6, np.int64)
+        _check(lib().mlfma_level_info(self._h, level, info.ctypes.data))
+        return {"boxes": int(info[0]), "L": int(info[1]), "K": int(info[2]), "translations": int(info[3]),
+                "box_edge": info[4] * 1e-6}
+
+    def matvec(self, x, op="C", out=None, stream=None, part=PART_ALL):
+        """y = A x on the GPU; x: complex128 or complex64 CUDA tensor of shape
+        (2N,) or (2N, nrhs).  Returns y with the same shape and dtype.
+        part selects the diagnostic split of mlfma_matvec_part (PART_NEAR,
+        PART_FAR, PART_LEVEL + l); the default is the whole product."""
+        if not (isinstance(x, torch.Tensor) and x.is_cuda):
+            raise TypeError("x must be a CUDA tensor")
+        if x.dtype == torch.complex128:
+            dt = C128
+        elif x.dtype == torch.complex64:
+            dt = C64
+        else:
+            raise TypeError("x must be complex128 or complex64")
+        squeeze = x.dim() == 1
+        X = x[:, None] if squeeze else x
+        if X.shape[0] != 2 * self.n_rwg:
+            raise ValueError("x must have 2N = %d rows" % (2 * self.n_rwg))
+        nrhs = X.shape[1]
+        xt = X.t().contiguous()                         # column-major 2N x nrhs storage
+        yt = torch.empty_like(xt) if out is None else out
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        with torch.cuda.device(self.device):
+            if part == PART_ALL:
+                _check(lib().mlfma_matvec_LK(self._h, _OPS.get(op, op), dt, nrhs, xt.data_ptr(), 2 * self.n_rwg,
+                                             yt.data_ptr(), 2 * self.n_rwg, s.cuda_stream))
+            else:
+                _check(lib().mlfma_matvec_part(self._h, _OPS.get(op, op), dt, part, nrhs, xt.data_ptr(), 2 * self.n_rwg,
+                                               yt.data_ptr(), 2 * self.n_rwg, s.cuda_stream))
+        y = yt.t()
+        return y[:, 0] if squeeze else y
+
+    def matvec_raw(self, op, dtype, nrhs, x_ptr, ldx, y_ptr, ldy, stream_ptr):
+        """Direct call of mlfma_matvec_LK on device pointers (column-major)."""
+        _check(lib().mlfma_matvec_LK(self._h, _OPS.get(op, op), dtype, nrhs, x_ptr, ldx, y_ptr, ldy, stream_ptr))
+
+    def release(self):
+        if getattr(self, "_h", None):
+            lib().mlfma_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def translation_operator(k, L, X, khat):
+    """T_L(khat, X) (host utility of the library)."""
+    X = np.ascontiguousarray(X, np.float64)
+    kh = np.ascontiguousarray(khat, np.float64)
+    out = np.zeros(2 * len(kh))
+    _check(lib().mlfma_translation_operator(k, L, X.ctypes.data, len(kh), kh.ctypes.data, out.ctypes.data))
+    return out[0::2] + 1j * out[1::2]

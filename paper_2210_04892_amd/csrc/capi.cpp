@@ -1,0 +1,721 @@
+// C boundary of the library: handle life cycle, device tables, and the
+// launch sequence of one MLFMA matrix-vector product.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mlfma.h"
+#include "device.hpp"
+#include "nearfield.hpp"
+#include "setup.hpp"
+
+using namespace mlfma;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+#define HIPCHK(call)                                                                                     \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess)                                                                            \
+            throw Error(e_ == hipErrorOutOfMemory ? MLFMA_ERR_OOM : MLFMA_ERR_HIP,                       \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                             \
+    } while (0)
+
+// Scoped switch to the handle's device (restores the caller's device).
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (dev >= 0 && dev != prev) HIPCHK(hipSetDevice(dev));
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Per-level device tables in one precision.
+template <class T>
+struct PrecLevel {
+    cpx<T> *trans = nullptr, *shift = nullptr;
+    T *ath_w = nullptr, *aph_w = nullptr, *dph_w = nullptr, *dth_w = nullptr;
+};
+
+template <class T>
+struct Prec {
+    cpx<T> *R = nullptr, *Q = nullptr;           // leaf patterns, [rwg][sample][2]
+    T *wq = nullptr;                              // receive weights (c0 folded)
+    cpx<T> *near_em = nullptr, *near_c = nullptr; // near blocks, (A, B) per slot
+    T *id_w = nullptr;                            // identity terms (gram, gx)
+    std::vector<PrecLevel<T>> lv;
+};
+
+struct IntLevel {
+    int *il_start = nullptr, *il_box = nullptr, *il_off = nullptr;
+    int *child_start = nullptr, *parent = nullptr, *oct = nullptr;
+    int *ath_s = nullptr, *ath_c = nullptr, *aph_s = nullptr, *aph_c = nullptr;
+    int *dph_s = nullptr, *dph_c = nullptr, *dth_s = nullptr, *dth_c = nullptr;
+};
+
+}  // namespace
+
+struct mlfma_ctx {
+    mlfma_options opt{};
+    int device = 0;
+    Surface s;
+    RwgTable r;
+    Tree tr;
+    std::vector<void *> allocs;
+    unsigned long long bytes = 0;
+    // integer tables
+    int *perm = nullptr, *iperm = nullptr, *leaf_of = nullptr, *box_start = nullptr;
+    int *near_start = nullptr, *near_box = nullptr, *id_start = nullptr, *id_col = nullptr;
+    long long *val_off = nullptr;
+    std::vector<IntLevel> lv;
+    Prec<double> p64;
+    Prec<float> p32;
+    bool near_ready = false;
+    // workspace (sized in complex<double> units for `ws_rhs` right-hand sides)
+    int ws_rhs = 0;
+    std::vector<void *> ws_allocs;
+    void *X = nullptr, *Y = nullptr, *mid = nullptr;
+    std::vector<void *> U, V;
+
+    template <class T>
+    T *dalloc(size_t count, std::vector<void *> *list = nullptr)
+    {
+        size_t nbytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (opt.hbm_budget_bytes && bytes + nbytes > opt.hbm_budget_bytes)
+            throw Error(MLFMA_ERR_OOM, "device memory budget exceeded");
+        void *p = nullptr;
+        HIPCHK(hipMalloc(&p, nbytes));
+        (list ? list : &allocs)->push_back(p);
+        bytes += nbytes;
+        return static_cast<T *>(p);
+    }
+    template <class T>
+    T *upload(const std::vector<T> &h)
+    {
+        T *d = dalloc<T>(h.size());
+        if (!h.empty()) HIPCHK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+        return d;
+    }
+    void free_ws()
+    {
+        for (void *p : ws_allocs) (void)hipFree(p);
+        ws_allocs.clear();
+        ws_rhs = 0;
+    }
+    ~mlfma_ctx()
+    {
+        free_ws();
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+template <class T>
+std::vector<T> cast_vec(const std::vector<double> &v)
+{
+    return std::vector<T>(v.begin(), v.end());
+}
+
+template <class T>
+std::vector<cpx<T>> cast_cvec(const std::vector<cdouble> &v)
+{
+    std::vector<cpx<T>> o(v.size());
+    for (size_t i = 0; i < v.size(); i++) o[i] = {(T)v[i].real(), (T)v[i].imag()};
+    return o;
+}
+
+template <class T>
+void upload_level_tables(mlfma_ctx *c, Prec<T> &P, const std::vector<std::vector<cdouble>> &trans,
+                         const std::vector<std::vector<cdouble>> &shift)
+{
+    const Tree &tr = c->tr;
+    P.lv.assign(tr.levels, PrecLevel<T>());
+    for (int l = 2; l < tr.levels; l++) {
+        P.lv[l].trans = c->upload(cast_cvec<T>(trans[l]));
+        if (l + 1 < tr.levels) {
+            P.lv[l].shift = c->upload(cast_cvec<T>(shift[l]));
+            P.lv[l].ath_w = c->upload(cast_vec<T>(tr.agg_theta[l].w));
+            P.lv[l].aph_w = c->upload(cast_vec<T>(tr.agg_phi[l].w));
+            P.lv[l].dph_w = c->upload(cast_vec<T>(tr.dis_phi[l].w));
+            P.lv[l].dth_w = c->upload(cast_vec<T>(tr.dis_theta[l].w));
+        }
+    }
+}
+
+void build_device_tables(mlfma_ctx *c)
+{
+    const Tree &tr = c->tr;
+    const int N = c->r.n, leafl = tr.levels - 1;
+    const double k = c->opt.wavenumber;
+    c->perm = c->upload(tr.perm);
+    c->iperm = c->upload(tr.iperm);
+    c->leaf_of = c->upload(tr.leaf_of);
+    c->box_start = c->upload(tr.box_start);
+    c->near_start = c->upload(tr.near_start);
+    c->near_box = c->upload(tr.near_box);
+    c->lv.assign(tr.levels, IntLevel());
+    std::vector<std::vector<cdouble>> trans(tr.levels), shift(tr.levels);
+    for (int l = 2; l < tr.levels; l++) {
+        const Level &L = tr.lv[l];
+        IntLevel &I = c->lv[l];
+        I.il_start = c->upload(L.il_start);
+        I.il_box = c->upload(L.il_box);
+        I.il_off = c->upload(L.il_off);
+        I.parent = c->upload(L.parent);
+        I.oct = c->upload(L.child_oct);
+        std::vector<double> khat;
+        level_directions(L, khat);
+        // translation operators for the 7^3 offsets (unused entries stay 0)
+        trans[l].assign(343 * (size_t)L.K, cdouble(0, 0));
+        std::vector<cdouble> tl;
+        for (int o = 0; o < 343; o++) {
+            int d[3] = {o / 49 - 3, (o / 7) % 7 - 3, o % 7 - 3};
+            if (std::max(std::abs(d[0]), std::max(std::abs(d[1]), std::abs(d[2]))) < 2) continue;
+            double X[3] = {d[0] * L.a, d[1] * L.a, d[2] * L.a};
+            translation_table(k, L.L, X, khat, tl);
+            std::copy(tl.begin(), tl.end(), trans[l].begin() + (size_t)o * L.K);
+        }
+        if (l + 1 < tr.levels) {
+            const Level &C = tr.lv[l + 1];
+            std::vector<int> cs(L.nbox + 1, 0);
+            for (int b = 0; b < C.nbox; b++) cs[C.parent[b] + 1]++;
+            for (int b = 0; b < L.nbox; b++) cs[b + 1] += cs[b];
+            I.child_start = c->upload(cs);
+            // exp(+jk khat.(r_child - r_parent)), r_child - r_parent = (bit - 1/2) a_child
+            shift[l].resize(8 * (size_t)L.K);
+            for (int o = 0; o < 8; o++) {
+                double off[3] = {((o >> 2) & 1) - 0.5, ((o >> 1) & 1) - 0.5, (o & 1) - 0.5};
+                for (int q = 0; q < L.K; q++) {
+                    double ph = k * C.a * (khat[3 * q] * off[0] + khat[3 * q + 1] * off[1] + khat[3 * q + 2] * off[2]);
+                    shift[l][(size_t)o * L.K + q] = cdouble(std::cos(ph), std::sin(ph));
+                }
+            }
+            I.ath_s = c->upload(tr.agg_theta[l].start);
+            I.ath_c = c->upload(tr.agg_theta[l].col);
+            I.aph_s = c->upload(tr.agg_phi[l].start);
+            I.aph_c = c->upload(tr.agg_phi[l].col);
+            I.dph_s = c->upload(tr.dis_phi[l].start);
+            I.dph_c = c->upload(tr.dis_phi[l].col);
+            I.dth_s = c->upload(tr.dis_theta[l].start);
+            I.dth_c = c->upload(tr.dis_theta[l].col);
+        }
+    }
+    upload_level_tables<double>(c, c->p64, trans, shift);
+    upload_level_tables<float>(c, c->p32, trans, shift);
+
+    if (tr.levels >= 3) {
+        // leaf patterns on the device (double), then a single-precision copy
+        const Level &L = tr.lv[leafl];
+        std::vector<int> rtri(2 * (size_t)N), rloc(2 * (size_t)N);
+        std::vector<double> rcoef(2 * (size_t)N), cen(3 * (size_t)N), tv(9 * (size_t)c->s.nt);
+        for (int i = 0; i < N; i++) {
+            int u = tr.perm[i];
+            for (int h = 0; h < 2; h++) {
+                rtri[2 * i + h] = c->r.tri[h][u];
+                rloc[2 * i + h] = c->r.loc[h][u];
+                rcoef[2 * i + h] = c->r.coef[h][u];
+            }
+            for (int d = 0; d < 3; d++) cen[3 * i + d] = L.centre[3 * tr.leaf_of[i] + d];
+        }
+        for (int t = 0; t < c->s.nt; t++)
+            for (int a = 0; a < 3; a++)
+                for (int d = 0; d < 3; d++) tv[9 * (size_t)t + 3 * a + d] = c->s.v[3 * c->s.t[3 * t + a] + d];
+        std::vector<void *> tmp;
+        const unsigned long long bytes_before = c->bytes;
+        auto d_rtri = c->dalloc<int>(rtri.size(), &tmp);
+        auto d_rloc = c->dalloc<int>(rloc.size(), &tmp);
+        auto d_rcoef = c->dalloc<double>(rcoef.size(), &tmp);
+        auto d_cen = c->dalloc<double>(cen.size(), &tmp);
+        auto d_tv = c->dalloc<double>(tv.size(), &tmp);
+        auto d_tn = c->dalloc<double>(c->s.nrm.size(), &tmp);
+        auto d_ta = c->dalloc<double>(c->s.area.size(), &tmp);
+        auto d_ct = c->dalloc<double>(L.ct.size(), &tmp);
+        HIPCHK(hipMemcpy(d_rtri, rtri.data(), rtri.size() * 4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_rloc, rloc.data(), rloc.size() * 4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_rcoef, rcoef.data(), rcoef.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_cen, cen.data(), cen.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_tv, tv.data(), tv.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_tn, c->s.nrm.data(), c->s.nrm.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_ta, c->s.area.data(), c->s.area.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_ct, L.ct.data(), L.ct.size() * 8, hipMemcpyHostToDevice));
+        const unsigned long long tmp_bytes = c->bytes - bytes_before;
+        const size_t np = (size_t)N * L.K * 2;
+        c->p64.R = c->dalloc<cpx<double>>(np);
+        c->p64.Q = c->dalloc<cpx<double>>(np);
+        c->p32.R = c->dalloc<cpx<float>>(np);
+        c->p32.Q = c->dalloc<cpx<float>>(np);
+        launch_patterns(N, L.K, L.nph, d_ct, k, d_rtri, d_rcoef, d_rloc, d_tv, d_tn, d_ta, d_cen, c->p64.R, c->p64.Q,
+                        nullptr);
+        HIPCHK(hipGetLastError());
+        launch_to_float(c->p64.R, c->p32.R, (long long)np, nullptr);
+        launch_to_float(c->p64.Q, c->p32.Q, (long long)np, nullptr);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipDeviceSynchronize());
+        for (void *p : tmp) (void)hipFree(p);
+        c->bytes -= tmp_bytes;
+        // receive weights c0 * w_theta * 2 pi / nph, c0 = -k^2 / (16 pi^2)
+        std::vector<double> wq(L.K);
+        const double c0 = -k * k / (16 * M_PI * M_PI);
+        for (int q = 0; q < L.K; q++) wq[q] = c0 * L.wt[q / L.nph] * (2 * M_PI / L.nph);
+        c->p64.wq = c->upload(wq);
+        c->p32.wq = c->upload(cast_vec<float>(wq));
+    }
+}
+
+// ------------------------------------------------------------- near field
+double tri_quality(const Surface &s, int t)
+{
+    double l2 = 0;
+    for (int a = 0; a < 3; a++) {
+        const double *p = &s.v[3 * s.t[3 * t + a]], *q = &s.v[3 * s.t[3 * t + (a + 1) % 3]];
+        l2 += (p[0] - q[0]) * (p[0] - q[0]) + (p[1] - q[1]) * (p[1] - q[1]) + (p[2] - q[2]) * (p[2] - q[2]);
+    }
+    return 4 * std::sqrt(3.0) * s.area[t] / l2;   // 1 for the equilateral triangle
+}
+
+int rule_order(double q)
+{
+    if (q >= 0.55) return 14;
+    if (q >= 0.35) return 20;
+    return 28;
+}
+
+void precompute_near(mlfma_ctx *c)
+{
+    const Surface &s = c->s;
+    const Tree &tr = c->tr;
+    const RwgTable &r = c->r;
+    const int N = r.n, nt = s.nt, leafl = tr.levels - 1;
+    const double k = c->opt.wavenumber;
+    // ordered touching triangle pairs (CSR by test triangle)
+    std::vector<std::vector<int>> vt(s.nv);
+    for (int t = 0; t < nt; t++)
+        for (int a = 0; a < 3; a++) vt[s.t[3 * t + a]].push_back(t);
+    std::vector<int> tp_start(nt + 1, 0), tp_s;
+    std::vector<TouchPair> pairs;
+    std::vector<double> quality(nt);
+    for (int t = 0; t < nt; t++) quality[t] = tri_quality(s, t);
+    for (int t = 0; t < nt; t++) {
+        std::vector<int> part;
+        for (int a = 0; a < 3; a++)
+            for (int u : vt[s.t[3 * t + a]]) part.push_back(u);
+        std::sort(part.begin(), part.end());
+        part.erase(std::unique(part.begin(), part.end()), part.end());
+        for (int u : part) {
+            TouchPair tp{};
+            const int *tv = &s.t[3 * t], *uv = &s.t[3 * u];
+            // shared vertices in the test triangle's cyclic order
+            int sh_t[3], sh_u[3], ns = 0;
+            for (int a = 0; a < 3; a++)
+                for (int b = 0; b < 3; b++)
+                    if (tv[a] == uv[b]) { sh_t[ns] = a; sh_u[ns] = b; ns++; }
+            tp.rel = ns;
+            if (ns == 3) {
+                for (int a = 0; a < 3; a++) { tp.pi[a] = a; tp.qi[a] = sh_u[a]; }
+            } else if (ns == 2) {
+                // shared edge first, both triangles listing it in the same order
+                tp.pi[0] = sh_t[0]; tp.pi[1] = sh_t[1]; tp.pi[2] = 3 - sh_t[0] - sh_t[1];
+                tp.qi[0] = sh_u[0]; tp.qi[1] = sh_u[1]; tp.qi[2] = 3 - sh_u[0] - sh_u[1];
+            } else {
+                tp.pi[0] = sh_t[0]; tp.pi[1] = (sh_t[0] + 1) % 3; tp.pi[2] = (sh_t[0] + 2) % 3;
+                tp.qi[0] = sh_u[0]; tp.qi[1] = (sh_u[0] + 1) % 3; tp.qi[2] = (sh_u[0] + 2) % 3;
+            }
+            for (int a = 0; a < 3; a++)
+                for (int d = 0; d < 3; d++) {
+                    tp.P[3 * a + d] = s.v[3 * tv[tp.pi[a]] + d];
+                    tp.Q[3 * a + d] = s.v[3 * uv[tp.qi[a]] + d];
+                }
+            for (int d = 0; d < 3; d++) tp.nt[d] = s.nrm[3 * t + d];
+            tp.At = s.area[t];
+            tp.As = s.area[u];
+            tp.order = rule_order(std::min(quality[t], quality[u]));
+            pairs.push_back(tp);
+            tp_s.push_back(u);
+        }
+        tp_start[t + 1] = (int)tp_s.size();
+    }
+    // Gauss-Legendre nodes/weights on [0, 1] for the orders used
+    std::vector<double> gn;
+    std::vector<int> goff(65, 0);
+    for (int n : {14, 20, 28}) {
+        std::vector<double> x, w;
+        gauss_legendre(n, x, w);
+        goff[n] = (int)gn.size();
+        for (int i = 0; i < n; i++) gn.push_back(0.5 * (x[i] + 1));
+        for (int i = 0; i < n; i++) gn.push_back(0.5 * w[i]);
+    }
+    // slot layout: per leaf box, rows x (concatenated near columns)
+    const Level &L = tr.lv[leafl];
+    std::vector<long long> val_off(L.nbox + 1, 0);
+    for (int b = 0; b < L.nbox; b++) {
+        long long nc = 0;
+        for (int e = tr.near_start[b]; e < tr.near_start[b + 1]; e++) {
+            int nb = tr.near_box[e];
+            nc += tr.box_start[nb + 1] - tr.box_start[nb];
+        }
+        val_off[b + 1] = val_off[b] + (long long)(tr.box_start[b + 1] - tr.box_start[b]) * nc;
+    }
+    const long long nslot = val_off[L.nbox];
+    c->val_off = c->upload(val_off);
+    c->p64.near_em = c->dalloc<cpx<double>>(2 * (size_t)nslot);
+    c->p64.near_c = c->dalloc<cpx<double>>(2 * (size_t)nslot);
+    c->p32.near_em = c->dalloc<cpx<float>>(2 * (size_t)nslot);
+    c->p32.near_c = c->dalloc<cpx<float>>(2 * (size_t)nslot);
+    // per-RWG data in internal order, triangle data
+    std::vector<int> rtri(2 * (size_t)N), rloc(2 * (size_t)N);
+    std::vector<double> rcoef(2 * (size_t)N), tv(9 * (size_t)nt);
+    for (int i = 0; i < N; i++) {
+        int u = tr.perm[i];
+        for (int h = 0; h < 2; h++) {
+            rtri[2 * i + h] = r.tri[h][u];
+            rloc[2 * i + h] = r.loc[h][u];
+            rcoef[2 * i + h] = r.coef[h][u];
+        }
+    }
+    for (int t = 0; t < nt; t++)
+        for (int a = 0; a < 3; a++)
+            for (int d = 0; d < 3; d++) tv[9 * (size_t)t + 3 * a + d] = s.v[3 * s.t[3 * t + a] + d];
+    std::vector<void *> tmp;
+    auto up = [&](auto &h) {
+        using E = typename std::remove_reference<decltype(h)>::type::value_type;
+        E *d = c->dalloc<E>(h.size(), &tmp);
+        if (!h.empty()) HIPCHK(hipMemcpy(d, h.data(), h.size() * sizeof(E), hipMemcpyHostToDevice));
+        return d;
+    };
+    unsigned long long bytes_before = c->bytes;
+    int *d_rtri = up(rtri), *d_rloc = up(rloc), *d_tps = up(tp_start), *d_tp_s = up(tp_s), *d_goff = up(goff);
+    double *d_rcoef = up(rcoef), *d_tv = up(tv), *d_gn = up(gn);
+    std::vector<double> nrm(s.nrm), area(s.area);
+    double *d_tn = up(nrm), *d_ta = up(area);
+    TouchPair *d_pairs = up(pairs);
+    cpx<double> *d_touch = c->dalloc<cpx<double>>(36 * std::max<size_t>(pairs.size(), 1), &tmp);
+    launch_touch((int)pairs.size(), d_pairs, k, d_gn, d_goff, d_touch, nullptr);
+    HIPCHK(hipGetLastError());
+    launch_slots(L.nbox, c->box_start, c->near_start, c->near_box, c->val_off, d_rtri, d_rloc, d_rcoef, d_tv, d_tn,
+                 d_ta, d_tps, d_tp_s, d_touch, k, c->p64.near_em, c->p64.near_c, c->p32.near_em, c->p32.near_c,
+                 nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipDeviceSynchronize());
+    for (void *p : tmp) (void)hipFree(p);
+    c->bytes = bytes_before;
+    // identity terms of the C block: Gram and n x Gram on common triangles,
+    // 7-point rule (exact for these quadratic integrands)
+    std::vector<std::map<int, std::pair<double, double>>> rows(N);
+    const double s15 = std::sqrt(15.0), a7 = (6 - s15) / 21, b7 = (6 + s15) / 21;
+    const double bary[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {a7, a7, 1 - 2 * a7}, {a7, 1 - 2 * a7, a7},
+                               {1 - 2 * a7, a7, a7}, {b7, b7, 1 - 2 * b7}, {b7, 1 - 2 * b7, b7}, {1 - 2 * b7, b7, b7}};
+    const double w7[7] = {9.0 / 40, (155 - s15) / 1200, (155 - s15) / 1200, (155 - s15) / 1200,
+                          (155 + s15) / 1200, (155 + s15) / 1200, (155 + s15) / 1200};
+    for (int t = 0; t < nt; t++) {
+        const double *P[3] = {&s.v[3 * s.t[3 * t]], &s.v[3 * s.t[3 * t + 1]], &s.v[3 * s.t[3 * t + 2]]};
+        const double *n = &s.nrm[3 * t];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                int um = r.tri_rwg[3 * (size_t)t + i], un = r.tri_rwg[3 * (size_t)t + j];
+                double cm = r.tri[0][um] == t ? r.coef[0][um] : r.coef[1][um];
+                double cn = r.tri[0][un] == t ? r.coef[0][un] : r.coef[1][un];
+                double g = 0, gx = 0;
+                for (int p = 0; p < 7; p++) {
+                    double x[3], a[3], b[3], nb[3];
+                    for (int d = 0; d < 3; d++) {
+                        x[d] = bary[p][0] * P[0][d] + bary[p][1] * P[1][d] + bary[p][2] * P[2][d];
+                        a[d] = x[d] - P[i][d];
+                        b[d] = x[d] - P[j][d];
+                    }
+                    nb[0] = n[1] * b[2] - n[2] * b[1];
+                    nb[1] = n[2] * b[0] - n[0] * b[2];
+                    nb[2] = n[0] * b[1] - n[1] * b[0];
+                    g += w7[p] * (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
+                    gx += w7[p] * (a[0] * nb[0] + a[1] * nb[1] + a[2] * nb[2]);
+                }
+                auto &e = rows[tr.iperm[um]][tr.iperm[un]];
+                e.first += cm * cn * s.area[t] * g;
+                e.second += cm * cn * s.area[t] * gx;
+            }
+    }
+    std::vector<int> id_start(N + 1, 0), id_col;
+    std::vector<double> id_w;
+    for (int m = 0; m < N; m++) {
+        for (auto &kv : rows[m]) {
+            id_col.push_back(kv.first);
+            id_w.push_back(kv.second.first);
+            id_w.push_back(kv.second.second);
+        }
+        id_start[m + 1] = (int)id_col.size();
+    }
+    c->id_start = c->upload(id_start);
+    c->id_col = c->upload(id_col);
+    c->p64.id_w = c->upload(id_w);
+    c->p32.id_w = c->upload(cast_vec<float>(id_w));
+    c->near_ready = true;
+}
+
+// ---------------------------------------------------------------- workspace
+void ensure_workspace(mlfma_ctx *c, int nrhs)
+{
+    if (nrhs <= c->ws_rhs) return;
+    c->free_ws();
+    const Tree &tr = c->tr;
+    const size_t cd = sizeof(cpx<double>);
+    auto get = [&](size_t elems) { return (void *)c->dalloc<char>(elems * cd, &c->ws_allocs); };
+    const int N = c->r.n;
+    c->X = get((size_t)N * 2 * nrhs);
+    c->Y = get((size_t)N * 2 * nrhs);
+    c->U.assign(tr.levels, nullptr);
+    c->V.assign(tr.levels, nullptr);
+    size_t midmax = 1;
+    for (int l = 2; l < tr.levels; l++) {
+        const Level &L = tr.lv[l];
+        c->U[l] = get((size_t)L.nbox * L.K * 2 * nrhs);
+        c->V[l] = get((size_t)L.nbox * L.K * 2 * nrhs);
+        if (l + 1 < tr.levels) {
+            const Level &C = tr.lv[l + 1];
+            midmax = std::max(midmax, (size_t)C.nbox * L.nth * C.nph * 2 * nrhs);
+        }
+    }
+    c->mid = get(midmax);
+    c->ws_rhs = nrhs;
+}
+
+template <class T>
+void run_matvec(mlfma_ctx *c, Prec<T> &P, int op, int part, int nrhs, const cpx<T> *x, long long ldx, cpx<T> *y,
+                long long ldy, hipStream_t st)
+{
+    const Tree &tr = c->tr;
+    const int N = c->r.n, leafl = tr.levels - 1;
+    cpx<T> *X = (cpx<T> *)c->X, *Y = (cpx<T> *)c->Y, *mid = (cpx<T> *)c->mid;
+    launch_perm_in<T>(x, ldx, X, c->perm, N, nrhs, st);
+    const Level &Lf = tr.lv[leafl];
+    const int only_level = part >= MLFMA_PART_LEVEL ? part - MLFMA_PART_LEVEL : -1;
+    if (part & MLFMA_PART_NEAR)
+        launch_near<T>(Lf.nbox, c->box_start, c->near_start, c->near_box, c->val_off, nullptr,
+                       op == MLFMA_OP_EM ? P.near_em : P.near_c, op == MLFMA_OP_C ? c->id_start : nullptr, c->id_col,
+                       P.id_w, X, Y, nrhs, 27, st);
+    else
+        launch_zero<T>(Y, (long long)N * 2 * nrhs, st);
+    if (tr.levels >= 3 && (part & MLFMA_PART_FAR || only_level >= 0)) {
+        launch_radiate<T>(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)c->U[leafl], nrhs, st);
+        for (int l = leafl - 1; l >= 2; l--) {
+            const Level &L = tr.lv[l], &C = tr.lv[l + 1];
+            const IntLevel &I = c->lv[l];
+            const int midlen = L.nth * C.nph;
+            launch_interp<T>(C.nbox, midlen, C.K, I.ath_s, I.ath_c, P.lv[l].ath_w, (cpx<T> *)c->U[l + 1], mid, nrhs,
+                             false, st);
+            launch_agg_phi<T>(L.nbox, L.K, midlen, I.child_start, c->lv[l + 1].oct, P.lv[l].shift, I.aph_s, I.aph_c,
+                              P.lv[l].aph_w, mid, (cpx<T> *)c->U[l], nrhs, st);
+        }
+        for (int l = 2; l <= leafl; l++) {
+            const Level &L = tr.lv[l];
+            const IntLevel &I = c->lv[l];
+            if (only_level >= 0 && l != only_level)
+                launch_zero<T>((cpx<T> *)c->V[l], (long long)L.nbox * L.K * 2 * nrhs, st);
+            else
+                launch_translate<T>(L.nbox, L.K, I.il_start, I.il_box, I.il_off, P.lv[l].trans, (cpx<T> *)c->U[l],
+                                    (cpx<T> *)c->V[l], nrhs, st);
+        }
+        for (int l = 3; l <= leafl; l++) {
+            const Level &L = tr.lv[l], &Pl = tr.lv[l - 1];
+            const IntLevel &Ip = c->lv[l - 1];
+            const int midlen = Pl.nth * L.nph;
+            launch_disagg_mid<T>(L.nbox, midlen, Pl.K, c->lv[l].parent, c->lv[l].oct, P.lv[l - 1].shift, Ip.dph_s,
+                                 Ip.dph_c, P.lv[l - 1].dph_w, (cpx<T> *)c->V[l - 1], mid, nrhs, st);
+            launch_interp<T>(L.nbox, L.K, midlen, Ip.dth_s, Ip.dth_c, P.lv[l - 1].dth_w, mid, (cpx<T> *)c->V[l],
+                             nrhs, true, st);
+        }
+        launch_receive<T>(op, N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)c->V[leafl], Y, nrhs, st);
+    }
+    launch_perm_out<T>(Y, y, ldy, c->iperm, N, nrhs, st);
+}
+
+int fail(const Error &e)
+{
+    g_last_error = e.what();
+    return e.code;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char *mlfma_last_error(void) { return g_last_error.c_str(); }
+
+int mlfma_options_default(mlfma_options *opt)
+{
+    if (!opt) return MLFMA_ERR_ARG;
+    opt->wavenumber = 2 * M_PI;
+    opt->leaf_size = 0.25;
+    opt->digits = 3;
+    opt->interp_order = 6;
+    opt->leaf_extra_L = 2;
+    opt->max_rhs = 1;
+    opt->device = -1;
+    opt->hbm_budget_bytes = 0;
+    return MLFMA_OK;
+}
+
+int mlfma_build_tree(const double *verts, long long n_verts, const int *tris, long long n_tris,
+                     const mlfma_options *opt, mlfma_handle *out)
+{
+    g_last_error.clear();
+    if (!out) return fail(Error(MLFMA_ERR_ARG, "out handle pointer is NULL"));
+    *out = nullptr;
+    try {
+        std::unique_ptr<mlfma_ctx> c(new mlfma_ctx());
+        if (opt) c->opt = *opt;
+        else mlfma_options_default(&c->opt);
+        if (c->opt.max_rhs < 1) throw Error(MLFMA_ERR_ARG, "max_rhs must be >= 1");
+        build_surface(c->s, verts, n_verts, tris, n_tris);
+        build_rwg(c->s, c->r);
+        build_tree(c->s, c->r, c->opt.wavenumber, c->opt.leaf_size, c->opt.digits, c->opt.interp_order,
+                   c->opt.leaf_extra_L, c->tr);
+        check_touching_near(c->s, c->r, c->tr);
+        int dev = c->opt.device;
+        if (dev < 0) HIPCHK(hipGetDevice(&dev));
+        c->device = dev;
+        DeviceGuard g(dev);
+        build_device_tables(c.get());
+        ensure_workspace(c.get(), c->opt.max_rhs);
+        *out = c.release();
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error(MLFMA_ERR_OOM, "host memory exhausted"));
+    } catch (const std::exception &e) {
+        return fail(Error(MLFMA_ERR_HIP, e.what()));
+    }
+}
+
+int mlfma_precompute_nearfield(mlfma_handle h)
+{
+    g_last_error.clear();
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    try {
+        DeviceGuard g(h->device);
+        if (!h->near_ready) precompute_near(h);
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error(MLFMA_ERR_OOM, "host memory exhausted"));
+    }
+}
+
+int mlfma_matvec_part(mlfma_handle h, int op, int dtype, int part, long long nrhs, const void *x, long long ldx,
+                      void *y, long long ldy, void *hip_stream)
+{
+    g_last_error.clear();
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    if (!h->near_ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_precompute_nearfield has not been called"));
+    if (op != MLFMA_OP_C && op != MLFMA_OP_EM) return fail(Error(MLFMA_ERR_ARG, "unknown op"));
+    if (dtype != MLFMA_C128 && dtype != MLFMA_C64) return fail(Error(MLFMA_ERR_ARG, "unknown dtype"));
+    if (!(part >= 1 && part <= 3) && !(part >= MLFMA_PART_LEVEL + 2 && part < MLFMA_PART_LEVEL + h->tr.levels))
+        return fail(Error(MLFMA_ERR_ARG, "unknown part"));
+    const long long N2 = 2LL * h->r.n;
+    if (nrhs < 1 || nrhs > (1 << 20) || !x || !y || ldx < N2 || ldy < N2)
+        return fail(Error(MLFMA_ERR_ARG, "bad nrhs, pointer or leading dimension"));
+    const size_t esz = dtype == MLFMA_C128 ? 16 : 8;
+    const char *xb = (const char *)x, *yb = (const char *)y;
+    if (xb < yb + (size_t)(ldy * (nrhs - 1) + N2) * esz && yb < xb + (size_t)(ldx * (nrhs - 1) + N2) * esz)
+        return fail(Error(MLFMA_ERR_ARG, "x and y overlap"));
+    try {
+        DeviceGuard g(h->device);
+        HIPCHK(hipGetLastError());
+        ensure_workspace(h, (int)nrhs);
+        hipStream_t st = (hipStream_t)hip_stream;
+        if (dtype == MLFMA_C128)
+            run_matvec<double>(h, h->p64, op, part, (int)nrhs, (const cpx<double> *)x, ldx, (cpx<double> *)y, ldy,
+                               st);
+        else
+            run_matvec<float>(h, h->p32, op, part, (int)nrhs, (const cpx<float> *)x, ldx, (cpx<float> *)y, ldy, st);
+        HIPCHK(hipGetLastError());
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int mlfma_matvec_LK(mlfma_handle h, int op, int dtype, long long nrhs, const void *x, long long ldx, void *y,
+                    long long ldy, void *hip_stream)
+{
+    return mlfma_matvec_part(h, op, dtype, MLFMA_PART_ALL, nrhs, x, ldx, y, ldy, hip_stream);
+}
+
+int mlfma_release(mlfma_handle h)
+{
+    if (!h) return MLFMA_OK;
+    {
+        DeviceGuard g(h->device);
+        (void)hipDeviceSynchronize();
+        delete h;
+    }
+    return MLFMA_OK;
+}
+
+int mlfma_query(mlfma_handle h, long long *n_rwg, int *levels, unsigned long long *hbm_bytes)
+{
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    if (n_rwg) *n_rwg = h->r.n;
+    if (levels) *levels = h->tr.levels;
+    if (hbm_bytes) *hbm_bytes = h->bytes;
+    return MLFMA_OK;
+}
+
+int mlfma_rwg_table(mlfma_handle h, int *edge_ab, int *tri_pm)
+{
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    for (int n = 0; n < h->r.n; n++) {
+        if (edge_ab) {
+            edge_ab[2 * n] = h->r.a[n];
+            edge_ab[2 * n + 1] = h->r.b[n];
+        }
+        if (tri_pm) {
+            tri_pm[2 * n] = h->r.tri[0][n];
+            tri_pm[2 * n + 1] = h->r.tri[1][n];
+        }
+    }
+    return MLFMA_OK;
+}
+
+int mlfma_level_info(mlfma_handle h, int level, long long info[6])
+{
+    if (!h || !info || level < 2 || level >= h->tr.levels) return fail(Error(MLFMA_ERR_ARG, "bad level"));
+    const Level &L = h->tr.lv[level];
+    info[0] = L.nbox;
+    info[1] = L.L;
+    info[2] = L.K;
+    info[3] = (long long)L.il_box.size();
+    info[4] = (long long)std::llround(L.a * 1e6);
+    info[5] = 0;
+    return MLFMA_OK;
+}
+
+int mlfma_translation_operator(double k, int L, const double X[3], long long nk, const double *khat, double *out)
+{
+    if (!(k > 0) || L < 0 || !X || nk < 0 || (nk && (!khat || !out))) return fail(Error(MLFMA_ERR_ARG, "bad args"));
+    std::vector<double> kh(khat, khat + 3 * nk);
+    std::vector<cdouble> o;
+    translation_table(k, L, X, kh, o);
+    for (long long q = 0; q < nk; q++) {
+        out[2 * q] = o[q].real();
+        out[2 * q + 1] = o[q].imag();
+    }
+    return MLFMA_OK;
+}
+
+}  // extern "C"

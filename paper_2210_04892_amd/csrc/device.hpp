@@ -1,0 +1,86 @@
+// Device-side types and kernel launchers shared by the HIP sources.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace mlfma {
+
+template <class T>
+struct alignas(2 * sizeof(T)) cpx {
+    T re, im;
+};
+
+template <class T>
+__host__ __device__ inline cpx<T> mk(T r, T i) { return cpx<T>{r, i}; }
+template <class T>
+__host__ __device__ inline cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T>
+__host__ __device__ inline cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T>
+__host__ __device__ inline cpx<T> operator*(cpx<T> a, cpx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T>
+__host__ __device__ inline cpx<T> operator*(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
+template <class T>
+__host__ __device__ inline cpx<T> conjg(cpx<T> a) { return {a.re, -a.im}; }
+template <class T>
+__host__ __device__ inline void fma_to(cpx<T> &acc, cpx<T> a, cpx<T> b)
+{
+    acc.re += a.re * b.re - a.im * b.im;
+    acc.im += a.re * b.im + a.im * b.re;
+}
+
+// Per-level device tables of the far field (one precision).
+template <class T>
+struct DevLevel {
+    int nbox = 0, K = 0, nth = 0, nph = 0;
+    const int *il_start = nullptr, *il_box = nullptr, *il_off = nullptr;   // interaction lists
+    const cpx<T> *trans = nullptr;        // 343 x K translation operators (offset-major)
+    const cpx<T> *shift = nullptr;        // 8 x K: exp(+jk khat.(r_child - r_parent)) for children at this level + 1
+    const int *child_start = nullptr;     // nbox + 1: children (level + 1) of each box, contiguous
+    const int *parent = nullptr;          // parent box (level - 1) of each box
+    const int *oct = nullptr;             // octant of each box inside its parent
+    // stencils from level + 1 to this level
+    const int *ath_s = nullptr, *ath_c = nullptr; const T *ath_w = nullptr; int ath_rows = 0;
+    const int *aph_s = nullptr, *aph_c = nullptr; const T *aph_w = nullptr;
+    const int *dph_s = nullptr, *dph_c = nullptr; const T *dph_w = nullptr;
+    const int *dth_s = nullptr, *dth_c = nullptr; const T *dth_w = nullptr;   // dth: rows of level + 1
+};
+
+// Launchers of the hot path (matvec.hip).  X, Y internal vectors
+// [rwg][half][rhs]; U, V patterns [box][sample][component][rhs].
+template <class T>
+void launch_perm_in(const cpx<T> *x, long long ldx, cpx<T> *X, const int *perm, int N, int nrhs, hipStream_t s);
+template <class T>
+void launch_perm_out(const cpx<T> *Y, cpx<T> *y, long long ldy, const int *iperm, int N, int nrhs, hipStream_t s);
+template <class T>
+void launch_near(int nbox, const int *box_start, const int *near_start, const int *near_box, const long long *val_off,
+                 const int *ncols, const cpx<T> *vals, const int *id_start, const int *id_col, const T *id_w,
+                 const cpx<T> *X, cpx<T> *Y, int nrhs, int max_near, hipStream_t s);
+template <class T>
+void launch_radiate(int op, int nbox, int K, const int *box_start, const cpx<T> *R, const cpx<T> *X, cpx<T> *U,
+                    int nrhs, hipStream_t s);
+template <class T>
+void launch_interp(int nbox, int rows, int in_len, const int *st, const int *col, const T *w, const cpx<T> *in,
+                   cpx<T> *out, int nrhs, bool accumulate, hipStream_t s);
+template <class T>
+void launch_agg_phi(int nparent, int Kp, int mid_len, const int *child_start, const int *child_oct,
+                    const cpx<T> *shift, const int *st, const int *col, const T *w, const cpx<T> *mid, cpx<T> *Up,
+                    int nrhs, hipStream_t s);
+template <class T>
+void launch_translate(int nbox, int K, const int *il_start, const int *il_box, const int *il_off,
+                      const cpx<T> *trans, const cpx<T> *U, cpx<T> *V, int nrhs, hipStream_t s);
+template <class T>
+void launch_disagg_mid(int nchild, int mid_len, int Kp, const int *parent, const int *oct, const cpx<T> *shift,
+                       const int *st, const int *col, const T *w, const cpx<T> *Vp, cpx<T> *mid, int nrhs,
+                       hipStream_t s);
+template <class T>
+void launch_zero(cpx<T> *p, long long n, hipStream_t s);
+template <class T>
+void launch_receive(int op, int N, int K, const int *leaf_of, const cpx<T> *R, const cpx<T> *Q, const T *wq,
+                    const cpx<T> *V, cpx<T> *Y, int nrhs, hipStream_t s);
+
+}  // namespace mlfma

@@ -1,0 +1,522 @@
+// Hot-path kernels of the MLFMA matvec for CDNA4 (gfx950, wave64).
+//
+// Vector layout inside the library: X[rwg][half][rhs] (rwg in Morton order,
+// half 0 = J or E side, 1 = M or H side, rhs innermost).  Box patterns:
+// U[box][sample][component][rhs] with component 0 = theta, 1 = phi.
+// Every kernel is templated on the arithmetic type T (double or float) and
+// on NR, the number of right-hand sides handled per thread (rhs chunk).
+#include "device.hpp"
+
+namespace mlfma {
+
+constexpr int WAVE = 64;
+
+template <class T>
+__device__ inline cpx<T> shfl_xor(cpx<T> v, int m)
+{
+    return {__shfl_xor(v.re, m, WAVE), __shfl_xor(v.im, m, WAVE)};
+}
+
+template <class T>
+__device__ inline cpx<T> wave_sum(cpx<T> v)
+{
+#pragma unroll
+    for (int m = WAVE / 2; m >= 1; m >>= 1) v = v + shfl_xor(v, m);
+    return v;
+}
+
+static inline int nr_for(int nrhs) { return nrhs <= 1 ? 1 : (nrhs <= 4 ? 4 : 16); }
+
+// ------------------------------------------------------------------ permute
+template <class T>
+__global__ void k_perm_in(const cpx<T> *__restrict__ x, long long ldx, cpx<T> *__restrict__ X,
+                          const int *__restrict__ perm, int N, int nrhs)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long total = (long long)N * 2 * nrhs;
+    if (g >= total) return;
+    int r = (int)(g % nrhs);
+    long long ih = g / nrhs;
+    int h = (int)(ih & 1);
+    int i = (int)(ih >> 1);
+    X[g] = x[(long long)r * ldx + (long long)h * N + perm[i]];
+}
+
+template <class T>
+__global__ void k_perm_out(const cpx<T> *__restrict__ Y, cpx<T> *__restrict__ y, long long ldy,
+                           const int *__restrict__ iperm, int N, int nrhs)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long total = (long long)N * 2 * nrhs;
+    if (g >= total) return;
+    int u = (int)(g % N);            // user row (coalesced writes)
+    long long hr = g / N;
+    int h = (int)(hr & 1);
+    int r = (int)(hr >> 1);
+    y[(long long)r * ldy + (long long)h * N + u] = Y[((long long)iperm[u] * 2 + h) * nrhs + r];
+}
+
+// ---------------------------------------------------------------- near field
+// One workgroup per leaf box; each wave owns rows of the box, its lanes
+// stride over the row's near columns (the concatenated RWG ranges of the
+// adjacent boxes).  Values are stored row-major per box as (A, B) pairs:
+//   y1 += A x1 - B x2,  y2 += A x2 + B x1
+// (A, B) = (T, K) for the EM pair; (-(T + Kx)/2, (Tx - K)/2) for the C block,
+// whose Gram terms are the short per-row identity list (gram, gx):
+//   y1 += gram x1 + gx x2 / 2,  y2 += gram x2 / 2.
+template <class T, int NR>
+__global__ __launch_bounds__(256) void k_near(const int *__restrict__ box_start, const int *__restrict__ near_start,
+                                              const int *__restrict__ near_box, const long long *__restrict__ val_off,
+                                              const cpx<T> *__restrict__ vals, const int *__restrict__ id_start,
+                                              const int *__restrict__ id_col, const T *__restrict__ id_w,
+                                              const cpx<T> *__restrict__ X, cpx<T> *__restrict__ Y, int nrhs)
+{
+    __shared__ int cstart[32];
+    __shared__ int pre[33];
+    const int b = blockIdx.x;
+    const int r0 = blockIdx.y * NR;
+    const int nn = near_start[b + 1] - near_start[b];
+    if (threadIdx.x == 0) {
+        pre[0] = 0;
+        for (int q = 0; q < nn; q++) {
+            int nb = near_box[near_start[b] + q];
+            cstart[q] = box_start[nb];
+            pre[q + 1] = pre[q] + box_start[nb + 1] - box_start[nb];
+        }
+    }
+    __syncthreads();
+    const int ncols = pre[nn];
+    const int m0 = box_start[b], nb_rows = box_start[b + 1] - m0;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    for (int mr = wave; mr < nb_rows; mr += blockDim.x / WAVE) {
+        const cpx<T> *vrow = vals + 2 * (val_off[b] + (long long)mr * ncols);
+        cpx<T> a1[NR], a2[NR];
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) a1[rr] = a2[rr] = mk<T>(0, 0);
+        int q = 0;
+        for (int j = lane; j < ncols; j += WAVE) {
+            while (j >= pre[q + 1]) q++;
+            const long long col = cstart[q] + (j - pre[q]);
+            const cpx<T> A = vrow[2 * j], B = vrow[2 * j + 1];
+#pragma unroll
+            for (int rr = 0; rr < NR; rr++) {
+                if (NR > 1 && r0 + rr >= nrhs) continue;
+                const cpx<T> x1 = X[(col * 2) * nrhs + r0 + rr], x2 = X[(col * 2 + 1) * nrhs + r0 + rr];
+                a1[rr] = a1[rr] + A * x1 - B * x2;
+                a2[rr] = a2[rr] + A * x2 + B * x1;
+            }
+        }
+        const int m = m0 + mr;
+        if (id_start) {
+            const int e = id_start[m] + lane;
+            if (e < id_start[m + 1]) {
+                const long long col = id_col[e];
+                const T g = id_w[2 * e], gx = id_w[2 * e + 1];
+#pragma unroll
+                for (int rr = 0; rr < NR; rr++) {
+                    if (NR > 1 && r0 + rr >= nrhs) continue;
+                    const cpx<T> x1 = X[(col * 2) * nrhs + r0 + rr], x2 = X[(col * 2 + 1) * nrhs + r0 + rr];
+                    a1[rr] = a1[rr] + g * x1 + (T(0.5) * gx) * x2;
+                    a2[rr] = a2[rr] + (T(0.5) * g) * x2;
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            const cpx<T> s1 = wave_sum(a1[rr]), s2 = wave_sum(a2[rr]);
+            if (lane == 0 && (NR == 1 || r0 + rr < nrhs)) {
+                Y[((long long)m * 2) * nrhs + r0 + rr] = s1;
+                Y[((long long)m * 2 + 1) * nrhs + r0 + rr] = s2;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- radiation
+// U_b(k) = sum_{n in b} alpha_n R_n(k) + beta_n (khat x R_n)(k),
+// khat x (v_theta, v_phi) = (-v_phi, v_theta).
+// EM pair: alpha = x1, beta = -x2.  C block: alpha = x2 / 2, beta = x1 / 2.
+template <class T, int NR>
+__global__ __launch_bounds__(256) void k_radiate(int op, int nbox, int K, const int *__restrict__ box_start,
+                                                 const cpx<T> *__restrict__ R, const cpx<T> *__restrict__ X,
+                                                 cpx<T> *__restrict__ U, int nrhs)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)nbox * K) return;
+    const int b = (int)(g / K), q = (int)(g % K);
+    const int r0 = blockIdx.y * NR;
+    cpx<T> ut[NR], up[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) ut[rr] = up[rr] = mk<T>(0, 0);
+    for (int i = box_start[b]; i < box_start[b + 1]; i++) {
+        const cpx<T> Rt = R[((long long)i * K + q) * 2], Rp = R[((long long)i * K + q) * 2 + 1];
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            if (NR > 1 && r0 + rr >= nrhs) continue;
+            const cpx<T> x1 = X[((long long)i * 2) * nrhs + r0 + rr], x2 = X[((long long)i * 2 + 1) * nrhs + r0 + rr];
+            cpx<T> al, be;
+            if (op == 1) {
+                al = x1;
+                be = mk<T>(-x2.re, -x2.im);
+            } else {
+                al = T(0.5) * x2;
+                be = T(0.5) * x1;
+            }
+            ut[rr] = ut[rr] + al * Rt - be * Rp;
+            up[rr] = up[rr] + al * Rp + be * Rt;
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) {
+        if (NR > 1 && r0 + rr >= nrhs) continue;
+        U[((g * 2) * nrhs) + r0 + rr] = ut[rr];
+        U[((g * 2 + 1) * nrhs) + r0 + rr] = up[rr];
+    }
+}
+
+// ------------------------------------------------- sparse stencil (per box)
+// out[box][row] (=, +=) sum_e w_e in[box][col_e], both components, all rhs.
+template <class T, int NR>
+__global__ __launch_bounds__(256) void k_interp(int nbox, int rows, int in_len, const int *__restrict__ st,
+                                                const int *__restrict__ col, const T *__restrict__ w,
+                                                const cpx<T> *__restrict__ in, cpx<T> *__restrict__ out, int nrhs,
+                                                int accumulate)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)nbox * rows) return;
+    const int box = (int)(g / rows), row = (int)(g % rows);
+    const int r0 = blockIdx.y * NR;
+    cpx<T> a0[NR], a1[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) a0[rr] = a1[rr] = mk<T>(0, 0);
+    const long long base = (long long)box * in_len;
+    for (int e = st[row]; e < st[row + 1]; e++) {
+        const T we = w[e];
+        const long long src = (base + col[e]) * 2;
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            if (NR > 1 && r0 + rr >= nrhs) continue;
+            a0[rr] = a0[rr] + we * in[src * nrhs + r0 + rr];
+            a1[rr] = a1[rr] + we * in[(src + 1) * nrhs + r0 + rr];
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) {
+        if (NR > 1 && r0 + rr >= nrhs) continue;
+        cpx<T> *o0 = &out[(g * 2) * nrhs + r0 + rr];
+        cpx<T> *o1 = &out[(g * 2 + 1) * nrhs + r0 + rr];
+        if (accumulate) {
+            *o0 = *o0 + a0[rr];
+            *o1 = *o1 + a1[rr];
+        } else {
+            *o0 = a0[rr];
+            *o1 = a1[rr];
+        }
+    }
+}
+
+// ----------------------------------------- aggregation: phi stage + shift
+// U_P(k) = sum_{children c} exp(+jk khat.(r_c - r_P)) [A_phi mid_c](k)
+template <class T, int NR>
+__global__ __launch_bounds__(256) void k_agg_phi(int nparent, int Kp, int mid_len, const int *__restrict__ child_start,
+                                                 const int *__restrict__ child_oct, const cpx<T> *__restrict__ shift,
+                                                 const int *__restrict__ st, const int *__restrict__ col,
+                                                 const T *__restrict__ w, const cpx<T> *__restrict__ mid,
+                                                 cpx<T> *__restrict__ Up, int nrhs)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)nparent * Kp) return;
+    const int P = (int)(g / Kp), q = (int)(g % Kp);
+    const int r0 = blockIdx.y * NR;
+    cpx<T> a0[NR], a1[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) a0[rr] = a1[rr] = mk<T>(0, 0);
+    for (int c = child_start[P]; c < child_start[P + 1]; c++) {
+        cpx<T> s0[NR], s1[NR];
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) s0[rr] = s1[rr] = mk<T>(0, 0);
+        const long long base = (long long)c * mid_len;
+        for (int e = st[q]; e < st[q + 1]; e++) {
+            const T we = w[e];
+            const long long src = (base + col[e]) * 2;
+#pragma unroll
+            for (int rr = 0; rr < NR; rr++) {
+                if (NR > 1 && r0 + rr >= nrhs) continue;
+                s0[rr] = s0[rr] + we * mid[src * nrhs + r0 + rr];
+                s1[rr] = s1[rr] + we * mid[(src + 1) * nrhs + r0 + rr];
+            }
+        }
+        const cpx<T> sh = shift[(long long)child_oct[c] * Kp + q];
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            fma_to(a0[rr], sh, s0[rr]);
+            fma_to(a1[rr], sh, s1[rr]);
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) {
+        if (NR > 1 && r0 + rr >= nrhs) continue;
+        Up[(g * 2) * nrhs + r0 + rr] = a0[rr];
+        Up[(g * 2 + 1) * nrhs + r0 + rr] = a1[rr];
+    }
+}
+
+// ---------------------------------------------------------------- translation
+// V_A(k) = sum_{(B, o) in IL(A)} T_o(k) U_B(k)   (diagonal in k)
+template <class T, int NR>
+__global__ __launch_bounds__(256) void k_translate(int nbox, int K, const int *__restrict__ il_start,
+                                                   const int *__restrict__ il_box, const int *__restrict__ il_off,
+                                                   const cpx<T> *__restrict__ trans, const cpx<T> *__restrict__ U,
+                                                   cpx<T> *__restrict__ V, int nrhs)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)nbox * K) return;
+    const int A = (int)(g / K), q = (int)(g % K);
+    const int r0 = blockIdx.y * NR;
+    cpx<T> a0[NR], a1[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) a0[rr] = a1[rr] = mk<T>(0, 0);
+    for (int e = il_start[A]; e < il_start[A + 1]; e++) {
+        const cpx<T> t = trans[(long long)il_off[e] * K + q];
+        const long long src = ((long long)il_box[e] * K + q) * 2;
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            if (NR > 1 && r0 + rr >= nrhs) continue;
+            fma_to(a0[rr], t, U[src * nrhs + r0 + rr]);
+            fma_to(a1[rr], t, U[(src + 1) * nrhs + r0 + rr]);
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) {
+        if (NR > 1 && r0 + rr >= nrhs) continue;
+        V[(g * 2) * nrhs + r0 + rr] = a0[rr];
+        V[(g * 2 + 1) * nrhs + r0 + rr] = a1[rr];
+    }
+}
+
+// ------------------------------ disaggregation: shift + transposed phi stage
+// mid_c = (A_phi^T W_P) [exp(-jk khat.(r_c - r_P)) V_P]
+template <class T, int NR>
+__global__ __launch_bounds__(256) void k_disagg_mid(int nchild, int mid_len, int Kp, const int *__restrict__ parent,
+                                                    const int *__restrict__ oct, const cpx<T> *__restrict__ shift,
+                                                    const int *__restrict__ st, const int *__restrict__ col,
+                                                    const T *__restrict__ w, const cpx<T> *__restrict__ Vp,
+                                                    cpx<T> *__restrict__ mid, int nrhs)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)nchild * mid_len) return;
+    const int c = (int)(g / mid_len), row = (int)(g % mid_len);
+    const int r0 = blockIdx.y * NR;
+    const int P = parent[c];
+    const cpx<T> *sh = shift + (long long)oct[c] * Kp;
+    cpx<T> a0[NR], a1[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) a0[rr] = a1[rr] = mk<T>(0, 0);
+    for (int e = st[row]; e < st[row + 1]; e++) {
+        const int kp = col[e];
+        const cpx<T> f = w[e] * conjg(sh[kp]);
+        const long long src = ((long long)P * Kp + kp) * 2;
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            if (NR > 1 && r0 + rr >= nrhs) continue;
+            fma_to(a0[rr], f, Vp[src * nrhs + r0 + rr]);
+            fma_to(a1[rr], f, Vp[(src + 1) * nrhs + r0 + rr]);
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) {
+        if (NR > 1 && r0 + rr >= nrhs) continue;
+        mid[(g * 2) * nrhs + r0 + rr] = a0[rr];
+        mid[(g * 2 + 1) * nrhs + r0 + rr] = a1[rr];
+    }
+}
+
+// ---------------------------------------------------------------- receive
+// y1 += c0 sum_k w_k P_m(k) . V_b(k),  y2 += c0 sum_k w_k P_m(k) . (khat x V_b(k))
+// with P = conj(R) for the EM pair and P = Q for the C block; c0 and the
+// sphere weights are folded into wq.  One wave per RWG, lanes over samples.
+template <class T, int NR>
+__global__ __launch_bounds__(256) void k_receive(int op, int N, int K, const int *__restrict__ leaf_of,
+                                                 const cpx<T> *__restrict__ R, const cpx<T> *__restrict__ Q,
+                                                 const T *__restrict__ wq, const cpx<T> *__restrict__ V,
+                                                 cpx<T> *__restrict__ Y, int nrhs)
+{
+    const int m = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (m >= N) return;
+    const int r0 = blockIdx.y * NR;
+    const int b = leaf_of[m];
+    cpx<T> a1[NR], a2[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) a1[rr] = a2[rr] = mk<T>(0, 0);
+    const cpx<T> *pat = op == 1 ? R : Q;
+    for (int q = lane; q < K; q += WAVE) {
+        cpx<T> Pt = pat[((long long)m * K + q) * 2], Pp = pat[((long long)m * K + q) * 2 + 1];
+        if (op == 1) {
+            Pt = conjg(Pt);
+            Pp = conjg(Pp);
+        }
+        const T wk = wq[q];
+        Pt = wk * Pt;
+        Pp = wk * Pp;
+        const long long src = ((long long)b * K + q) * 2;
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            if (NR > 1 && r0 + rr >= nrhs) continue;
+            const cpx<T> Vt = V[src * nrhs + r0 + rr], Vp = V[(src + 1) * nrhs + r0 + rr];
+            a1[rr] = a1[rr] + Pt * Vt + Pp * Vp;
+            a2[rr] = a2[rr] + Pp * Vt - Pt * Vp;
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) {
+        const cpx<T> s1 = wave_sum(a1[rr]), s2 = wave_sum(a2[rr]);
+        if (lane == 0 && (NR == 1 || r0 + rr < nrhs)) {
+            cpx<T> &y1 = Y[((long long)m * 2) * nrhs + r0 + rr];
+            cpx<T> &y2 = Y[((long long)m * 2 + 1) * nrhs + r0 + rr];
+            y1 = y1 + s1;
+            y2 = y2 + s2;
+        }
+    }
+}
+
+// fill with zeros (used instead of a memset so the sequence stays capturable)
+template <class T>
+__global__ void k_zero(cpx<T> *__restrict__ p, long long n)
+{
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n) p[g] = mk<T>(0, 0);
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <class T>
+void launch_perm_in(const cpx<T> *x, long long ldx, cpx<T> *X, const int *perm, int N, int nrhs, hipStream_t s)
+{
+    long long n = (long long)N * 2 * nrhs;
+    hipLaunchKernelGGL(k_perm_in<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, ldx, X, perm, N, nrhs);
+}
+template <class T>
+void launch_perm_out(const cpx<T> *Y, cpx<T> *y, long long ldy, const int *iperm, int N, int nrhs, hipStream_t s)
+{
+    long long n = (long long)N * 2 * nrhs;
+    hipLaunchKernelGGL(k_perm_out<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, Y, y, ldy, iperm, N, nrhs);
+}
+
+#define DISPATCH_NR(nrhs, KERNEL_CALL)            \
+    do {                                          \
+        int nr_ = nr_for(nrhs);                   \
+        if (nr_ == 1) { constexpr int NR = 1; KERNEL_CALL; } \
+        else if (nr_ == 4) { constexpr int NR = 4; KERNEL_CALL; } \
+        else { constexpr int NR = 16; KERNEL_CALL; } \
+    } while (0)
+
+template <class T>
+void launch_near(int nbox, const int *box_start, const int *near_start, const int *near_box, const long long *val_off,
+                 const int *, const cpx<T> *vals, const int *id_start, const int *id_col, const T *id_w,
+                 const cpx<T> *X, cpx<T> *Y, int nrhs, int, hipStream_t s)
+{
+    DISPATCH_NR(nrhs, {
+        dim3 grid(nbox, (nrhs + NR - 1) / NR);
+        hipLaunchKernelGGL((k_near<T, NR>), grid, dim3(256), 0, s, box_start, near_start, near_box, val_off, vals,
+                           id_start, id_col, id_w, X, Y, nrhs);
+    });
+}
+
+template <class T>
+void launch_radiate(int op, int nbox, int K, const int *box_start, const cpx<T> *R, const cpx<T> *X, cpx<T> *U,
+                    int nrhs, hipStream_t s)
+{
+    DISPATCH_NR(nrhs, {
+        dim3 grid(blocks_for((long long)nbox * K, 256), (nrhs + NR - 1) / NR);
+        hipLaunchKernelGGL((k_radiate<T, NR>), grid, dim3(256), 0, s, op, nbox, K, box_start, R, X, U, nrhs);
+    });
+}
+
+template <class T>
+void launch_interp(int nbox, int rows, int in_len, const int *st, const int *col, const T *w, const cpx<T> *in,
+                   cpx<T> *out, int nrhs, bool accumulate, hipStream_t s)
+{
+    DISPATCH_NR(nrhs, {
+        dim3 grid(blocks_for((long long)nbox * rows, 256), (nrhs + NR - 1) / NR);
+        hipLaunchKernelGGL((k_interp<T, NR>), grid, dim3(256), 0, s, nbox, rows, in_len, st, col, w, in, out, nrhs,
+                           accumulate ? 1 : 0);
+    });
+}
+
+template <class T>
+void launch_agg_phi(int nparent, int Kp, int mid_len, const int *child_start, const int *child_oct,
+                    const cpx<T> *shift, const int *st, const int *col, const T *w, const cpx<T> *mid, cpx<T> *Up,
+                    int nrhs, hipStream_t s)
+{
+    DISPATCH_NR(nrhs, {
+        dim3 grid(blocks_for((long long)nparent * Kp, 256), (nrhs + NR - 1) / NR);
+        hipLaunchKernelGGL((k_agg_phi<T, NR>), grid, dim3(256), 0, s, nparent, Kp, mid_len, child_start, child_oct,
+                           shift, st, col, w, mid, Up, nrhs);
+    });
+}
+
+template <class T>
+void launch_translate(int nbox, int K, const int *il_start, const int *il_box, const int *il_off,
+                      const cpx<T> *trans, const cpx<T> *U, cpx<T> *V, int nrhs, hipStream_t s)
+{
+    DISPATCH_NR(nrhs, {
+        dim3 grid(blocks_for((long long)nbox * K, 256), (nrhs + NR - 1) / NR);
+        hipLaunchKernelGGL((k_translate<T, NR>), grid, dim3(256), 0, s, nbox, K, il_start, il_box, il_off, trans, U,
+                           V, nrhs);
+    });
+}
+
+template <class T>
+void launch_disagg_mid(int nchild, int mid_len, int Kp, const int *parent, const int *oct, const cpx<T> *shift,
+                       const int *st, const int *col, const T *w, const cpx<T> *Vp, cpx<T> *mid, int nrhs,
+                       hipStream_t s)
+{
+    DISPATCH_NR(nrhs, {
+        dim3 grid(blocks_for((long long)nchild * mid_len, 256), (nrhs + NR - 1) / NR);
+        hipLaunchKernelGGL((k_disagg_mid<T, NR>), grid, dim3(256), 0, s, nchild, mid_len, Kp, parent, oct, shift, st,
+                           col, w, Vp, mid, nrhs);
+    });
+}
+
+template <class T>
+void launch_zero(cpx<T> *p, long long n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_zero<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n);
+}
+
+template <class T>
+void launch_receive(int op, int N, int K, const int *leaf_of, const cpx<T> *R, const cpx<T> *Q, const T *wq,
+                    const cpx<T> *V, cpx<T> *Y, int nrhs, hipStream_t s)
+{
+    DISPATCH_NR(nrhs, {
+        dim3 grid(blocks_for(N, 4), (nrhs + NR - 1) / NR);
+        hipLaunchKernelGGL((k_receive<T, NR>), grid, dim3(256), 0, s, op, N, K, leaf_of, R, Q, wq, V, Y, nrhs);
+    });
+}
+
+#define INSTANTIATE(T)                                                                                              \
+    template void launch_perm_in<T>(const cpx<T> *, long long, cpx<T> *, const int *, int, int, hipStream_t);     \
+    template void launch_perm_out<T>(const cpx<T> *, cpx<T> *, long long, const int *, int, int, hipStream_t);    \
+    template void launch_near<T>(int, const int *, const int *, const int *, const long long *, const int *,     \
+                                 const cpx<T> *, const int *, const int *, const T *, const cpx<T> *, cpx<T> *, \
+                                 int, int, hipStream_t);                                                          \
+    template void launch_radiate<T>(int, int, int, const int *, const cpx<T> *, const cpx<T> *, cpx<T> *, int,   \
+                                    hipStream_t);                                                                 \
+    template void launch_interp<T>(int, int, int, const int *, const int *, const T *, const cpx<T> *, cpx<T> *, \
+                                   int, bool, hipStream_t);                                                       \
+    template void launch_agg_phi<T>(int, int, int, const int *, const int *, const cpx<T> *, const int *,        \
+                                    const int *, const T *, const cpx<T> *, cpx<T> *, int, hipStream_t);          \
+    template void launch_translate<T>(int, int, const int *, const int *, const int *, const cpx<T> *,           \
+                                      const cpx<T> *, cpx<T> *, int, hipStream_t);                                \
+    template void launch_disagg_mid<T>(int, int, int, const int *, const int *, const cpx<T> *, const int *,     \
+                                       const int *, const T *, const cpx<T> *, cpx<T> *, int, hipStream_t);       \
+    template void launch_zero<T>(cpx<T> *, long long, hipStream_t);                                               \
+    template void launch_receive<T>(int, int, int, const int *, const cpx<T> *, const cpx<T> *, const T *,       \
+                                    const cpx<T> *, cpx<T> *, int, hipStream_t);
+
+INSTANTIATE(double)
+INSTANTIATE(float)
+
+}  // namespace mlfma

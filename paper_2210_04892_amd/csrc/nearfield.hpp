@@ -1,0 +1,29 @@
+// Set-up kernels (double precision): patterns and near-field blocks.
+#pragma once
+#include "device.hpp"
+
+namespace mlfma {
+
+// One ordered pair of triangles that share at least one vertex, with both
+// triangles' vertices reordered so that the shared ones come first and in
+// the same order (rel = number of shared vertices: 1, 2 or 3).
+struct TouchPair {
+    double P[9], Q[9];      // test / source vertices, canonical order
+    double nt[3];           // unit outward normal of the test triangle
+    double At, As;          // areas
+    int rel, order;         // relation and Gauss order per dimension
+    int pi[3], qi[3];       // canonical local index -> caller's local index
+};
+
+void launch_patterns(int N, int K, int nph, const double *ct, double k, const int *rtri, const double *rcoef,
+                     const int *rloc, const double *tri_v, const double *tri_n, const double *tri_a,
+                     const double *centre, cpx<double> *R, cpx<double> *Q, hipStream_t s);
+void launch_touch(int npairs, const TouchPair *pairs, double k, const double *gnodes, const int *goff,
+                  cpx<double> *out, hipStream_t s);
+void launch_slots(int nbox, const int *box_start, const int *near_start, const int *near_box, const long long *val_off,
+                  const int *rtri, const int *rloc, const double *rcoef, const double *tri_v, const double *tri_n,
+                  const double *tri_a, const int *tp_start, const int *tp_s, const cpx<double> *touch, double k,
+                  cpx<double> *em64, cpx<double> *c64, cpx<float> *em32, cpx<float> *c32, hipStream_t s);
+void launch_to_float(const cpx<double> *a, cpx<float> *b, long long n, hipStream_t s);
+
+}  // namespace mlfma

@@ -1,0 +1,89 @@
+// Host-side geometry, octree and k-space set-up of the MLFMA matvec.
+#pragma once
+#include <complex>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace mlfma {
+
+using cdouble = std::complex<double>;
+
+// error carried from the set-up code to the C boundary
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+struct Surface {
+    int nv = 0, nt = 0;
+    std::vector<double> v;      // nv x 3
+    std::vector<int> t;         // nt x 3
+    std::vector<double> area;   // nt
+    std::vector<double> nrm;    // nt x 3, unit outward normal
+};
+
+// RWG functions in the canonical (user) order.
+struct RwgTable {
+    int n = 0;
+    std::vector<int> a, b;          // edge endpoints, a < b
+    std::vector<int> tri[2];        // T+ and T-
+    std::vector<int> loc[2];        // local vertex index of the free vertex in T+ / T-
+    std::vector<double> coef[2];    // +l/(2A+) and -l/(2A-): f = coef * (r - p)
+    std::vector<int> tri_rwg;       // nt x 3: RWG on the edge opposite local vertex j
+};
+
+// One octree level (only non-empty boxes are kept, in Morton order).
+struct Level {
+    int lev = 0;
+    double a = 0;                   // box edge
+    int nbox = 0;
+    std::vector<int> coord;         // nbox x 3 integer box coordinates
+    std::vector<double> centre;     // nbox x 3
+    std::vector<int> parent;        // index into the level above (lev - 1)
+    std::vector<int> child_oct;     // octant of this box inside its parent (0..7)
+    // k-space sampling (levels >= 2)
+    int L = 0, nth = 0, nph = 0, K = 0;
+    std::vector<double> ct, wt;     // cos(theta) Gauss-Legendre nodes/weights, theta ascending
+    // interaction list (levels >= 2), CSR over boxes: source box and offset id
+    std::vector<int> il_start, il_box, il_off;
+};
+
+// Sparse matrix with real weights in CSR form (rows -> (column, weight)).
+struct Csr {
+    int rows = 0, cols = 0;
+    std::vector<int> start, col;
+    std::vector<double> w;
+};
+
+struct Tree {
+    int levels = 0;                 // root = 0 .. leaf = levels - 1
+    double leaf = 0, side = 0, origin[3] = {0, 0, 0};
+    std::vector<int> perm;          // internal index -> user RWG index (Morton order)
+    std::vector<int> iperm;         // user RWG index -> internal index
+    std::vector<int> leaf_of;       // internal index -> leaf box
+    std::vector<Level> lv;          // per level
+    std::vector<int> box_start;     // leaf boxes: RWG ranges (nbox_leaf + 1)
+    std::vector<int> near_start, near_box;   // leaf near lists (Chebyshev distance <= 1, incl. self)
+    // interpolation stencils for the step from level l+1 (child) to l (parent)
+    std::vector<Csr> agg_theta, agg_phi, dis_phi, dis_theta;   // indexed by parent level l
+};
+
+void build_surface(Surface &s, const double *verts, long long nv, const int *tris, long long nt);
+void build_rwg(const Surface &s, RwgTable &r);
+void build_tree(const Surface &s, const RwgTable &r, double k, double leaf, int digits, int interp_order,
+                int leaf_extra_L, Tree &tr);
+void check_touching_near(const Surface &s, const RwgTable &r, const Tree &tr);
+
+// translation operator sum for one level and offset, at the level's samples
+void translation_table(double k, int L, const double X[3], const std::vector<double> &khat,
+                       std::vector<cdouble> &out);
+// unit vectors of the level's samples, sample index = itheta * nph + iphi
+void level_directions(const Level &l, std::vector<double> &khat);
+// truncation rule
+int truncation(double k, double box_edge, int digits);
+// Gauss-Legendre nodes/weights on [-1, 1], ascending
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
+
+}  // namespace mlfma

@@ -1,0 +1,209 @@
+"""GPU parity of the HIP library against the CPU oracle (MI355X only).
+
+Tolerances: the double-precision near field must reproduce the oracle's
+near part to 1e-10 (relative 2-norm); whole products (near + MLFMA far
+field) must be within 1e-3 of the oracle, in complex128 and complex64.
+Large workloads are compared on seeded row samples the oracle evaluates one
+by one, in the same launch configuration the benchmark times.
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+K0 = 2 * np.pi
+NEAR_TOL = 1e-10
+MLFMA_TOL = 1e-3
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+MESHES = {
+    "ico4_r0.5": lambda: synth.icosphere(4, 0.5),
+    "sphere_r0.5": lambda: synth.icosphere(8, 0.5),
+    "sphere_r3": lambda: synth.icosphere(36, 3.0),
+    "box_4x4x1": lambda: synth.rounded_box((4.0, 4.0, 1.0), 0.2, 0.073),
+    "octahedron": lambda: synth.octahedron(0.1),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def mesh(name):
+    return MESHES[name]()
+
+
+@functools.lru_cache(maxsize=None)
+def geometry(name, max_rhs=1):
+    import paper_2210_04892_amd as mf
+    _torch()
+    v, t = mesh(name)
+    print("[gpu] build %s" % name, flush=True)
+    return mf.Geometry(v, t, k=K0, max_rhs=max_rhs).precompute()
+
+
+@functools.lru_cache(maxsize=None)
+def reference(name, nrows, nrhs, seed):
+    """Oracle (op C and op EM, by class) on seeded rows (nrows=None: all)."""
+    v, t = mesh(name)
+    N = 3 * len(t) // 2
+    x = synth.gaussian_coeffs(2 * N, nrhs, seed)
+    rows = None if nrows is None else np.sort(np.random.default_rng(seed + 100).choice(N, nrows, replace=False))
+    print("[gpu] oracle %s rows=%s nrhs=%d" % (name, nrows, nrhs), flush=True)
+    yc, ye = oracle.matvec(v, t, K0, x, op=oracle.OP_BOTH, rows=rows, leaf=0.25, classes=True)
+    return x, rows, {"C": yc, "EM": ye}
+
+
+def _gpu(name, x, op, dtype, part=None):
+    import paper_2210_04892_amd as mf
+    torch = _torch()
+    g = geometry(name, max_rhs=x.shape[1])
+    xt = torch.from_numpy(x.astype(dtype)).cuda()
+    y = g.matvec(xt, op=op, part=mf.PART_ALL if part is None else part)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.complex128)
+
+
+def _pick(y, rows, N):
+    if rows is None:
+        return y
+    return np.concatenate([y[rows], y[N + rows]])
+
+
+CASES = [("ico4_r0.5", None), ("sphere_r0.5", 192), ("sphere_r3", 40), ("box_4x4x1", 40)]
+
+
+@pytest.mark.parametrize("name,nrows", CASES)
+@pytest.mark.parametrize("op", ["C", "EM"])
+def test_near_field_fp64(name, nrows, op):
+    import paper_2210_04892_amd as mf
+    x, rows, ref = reference(name, nrows, 1, 2)
+    N = x.shape[0] // 2
+    y = _gpu(name, x, op, np.complex128, part=mf.PART_NEAR)
+    err = _rel(_pick(y, rows, N), ref[op][0])
+    print("[gpu] %s op %s near c128 rel err %.3e" % (name, op, err), flush=True)
+    assert err <= NEAR_TOL
+
+
+@pytest.mark.parametrize("name,nrows", CASES)
+@pytest.mark.parametrize("op", ["C", "EM"])
+@pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
+def test_mlfma_matvec(name, nrows, op, dtype):
+    x, rows, ref = reference(name, nrows, 1, 2)
+    N = x.shape[0] // 2
+    y = _gpu(name, x, op, dtype)
+    full = ref[op].sum(axis=0)
+    err = _rel(_pick(y, rows, N), full)
+    far = ref[op][1:].sum(axis=0)
+    print("[gpu] %s op %s %s rel err %.3e (far part %.1f%% of the norm)"
+          % (name, op, np.dtype(dtype).name, err, 100 * np.linalg.norm(far) / np.linalg.norm(full)), flush=True)
+    assert err <= MLFMA_TOL
+
+
+def test_per_level_far_field():
+    """Each translation level's share of the far field against the oracle's
+    pairs of that interaction level (error stated per level)."""
+    import paper_2210_04892_amd as mf
+    name = "sphere_r3"
+    x, rows, ref = reference(name, 40, 1, 2)
+    N = x.shape[0] // 2
+    g = geometry(name)
+    norm = np.linalg.norm(ref["C"].sum(axis=0))
+    for lev in range(2, g.levels):
+        y = _gpu(name, x, "C", np.complex128, part=mf.PART_LEVEL + lev)
+        err = np.linalg.norm(_pick(y, rows, N) - ref["C"][lev]) / norm
+        print("[gpu] level %d: |y_l - ref_l| / |ref| = %.2e" % (lev, err), flush=True)
+        assert err <= MLFMA_TOL
+
+
+@pytest.mark.parametrize("nrhs", [3, 20])
+def test_multi_rhs(nrhs):
+    """Several right-hand sides in one launch (rhs chunks of 4 and 16 with a
+    ragged tail) against the oracle, both precisions."""
+    name = "ico4_r0.5"
+    x, rows, ref = reference(name, None, nrhs, 5)
+    for dtype in (np.complex128, np.complex64):
+        for op in ("C", "EM"):
+            y = _gpu(name, x, op, dtype)
+            full = ref[op].sum(axis=0)
+            errs = [_rel(y[:, r], full[:, r]) for r in range(nrhs)]
+            print("[gpu] nrhs %d %s %s max rel err %.3e" % (nrhs, op, np.dtype(dtype).name, max(errs)), flush=True)
+            assert max(errs) <= MLFMA_TOL
+
+
+def test_tiny_mesh_is_all_near():
+    """A mesh smaller than three octree levels has no far field: the whole
+    product is the double-precision near field."""
+    name = "octahedron"
+    x, rows, ref = reference(name, None, 2, 9)
+    g = geometry(name)
+    assert g.levels < 3
+    for op in ("C", "EM"):
+        y = _gpu(name, x, op, np.complex128)
+        assert _rel(y, ref[op].sum(axis=0)) <= NEAR_TOL
+
+
+def test_leading_dimension_and_stream():
+    """Padded leading dimensions and a non-default stream."""
+    torch = _torch()
+    import paper_2210_04892_amd as mf
+    name = "ico4_r0.5"
+    x, rows, ref = reference(name, None, 1, 2)
+    N2 = x.shape[0]
+    g = geometry(name)
+    ld = N2 + 5
+    xb = torch.zeros((2, ld), dtype=torch.complex128, device="cuda")
+    xb[0, :N2] = torch.from_numpy(x[:, 0])
+    xb[1, :N2] = torch.from_numpy(x[:, 0])
+    yb = torch.full((2, ld), 7.0, dtype=torch.complex128, device="cuda")
+    s = torch.cuda.Stream()
+    g.matvec_raw("C", mf.C128, 2, xb.data_ptr(), ld, yb.data_ptr(), ld, s.cuda_stream)
+    s.synchronize()
+    y = yb.cpu().numpy()
+    full = ref["C"].sum(axis=0)[:, 0]
+    assert _rel(y[0, :N2], full) <= MLFMA_TOL
+    assert np.array_equal(y[0, :N2], y[1, :N2])
+    assert np.all(y[:, N2:] == 7.0)          # padding untouched
+
+
+def test_error_paths():
+    torch = _torch()
+    import paper_2210_04892_amd as mf
+    v, t = mesh("ico4_r0.5")
+    g = mf.Geometry(v, t, k=K0)
+    x = torch.zeros(2 * g.n_rwg, dtype=torch.complex128, device="cuda")
+    with pytest.raises(mf.MlfmaError) as e:
+        g.matvec(x)
+    assert e.value.code == -5                  # near field not computed yet
+    g.precompute()
+    buf = torch.zeros(2 * g.n_rwg + 8, dtype=torch.complex128, device="cuda")
+    with pytest.raises(mf.MlfmaError) as e:
+        g.matvec_raw("C", mf.C128, 1, buf.data_ptr(), 2 * g.n_rwg, buf[4:].data_ptr(), 2 * g.n_rwg,
+                     torch.cuda.current_stream().cuda_stream)
+    assert e.value.code == -1                  # x and y overlap
+    with pytest.raises(mf.MlfmaError):
+        g.matvec(x, op=7)                      # unknown op
+    g.release()
+
+
+def test_budget_rejects_oversized_geometry():
+    torch = _torch()  # noqa: F841
+    import paper_2210_04892_amd as mf
+    v, t = mesh("ico4_r0.5")
+    with pytest.raises(mf.MlfmaError) as e:
+        mf.Geometry(v, t, k=K0, hbm_budget_bytes=1 << 16)
+    assert e.value.code == -3
