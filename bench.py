@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark of the MLFMA boundary-integral matvec on one MI355X.
+
+One step = one whole product y = C x (the BI block of the hybrid solver's
+matrix-vector subroutine: near-field blocks plus the MLFMA far field) over
+one batch of right-hand sides, inputs resident in HBM.  Default workload:
+sphere of radius 3 wavelengths meshed at lambda/10 (25 920 triangles,
+38 880 RWG, 77 760 unknowns), 6-level octree with 0.25-wavelength leaves,
+one seeded N(0,1) complex right-hand side.
+
+Prints one JSON line: throughput in unknowns*RHS/s for the complex64
+(single-precision) path, the complex128 path beside it, stage timings from
+HIP events recorded on the launch stream, the roofline of the dominant
+kernel, and the CPU oracle timed on a bounded sample of rows with the
+error of both GPU paths on those rows.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="sphere_r3")
+    p.add_argument("--nrhs", type=int, default=None, help="override the workload's RHS count")
+    p.add_argument("--cpu-rows", type=int, default=160, help="rows of the oracle sample (0 = skip)")
+    p.add_argument("--op", default="C", choices=["C", "EM"])
+    return p.parse_args()
+
+
+def stage_bytes(g, levels_info, n, nrhs, esz, op):
+    """Algorithmic HBM bytes of each stage for one product (every operand
+    read once, every result written once)."""
+    ni = g.near_info()
+    leaf = levels_info[max(levels_info)] if levels_info else None
+    vec = 2 * n * nrhs * esz
+    b = {}
+    b["permute_in"] = 2 * vec
+    b["permute_out"] = 2 * vec
+    ident = ni["identity"] * (4 + esz) if op == "C" else 0
+    b["near"] = ni["slots"] * 2 * esz + 2 * vec + ident
+    if leaf is None:
+        return b, ni
+    pat = n * leaf["K"] * 2 * esz
+    box = {l: d["boxes"] * d["K"] * 2 * esz * nrhs for l, d in levels_info.items()}
+    lmax = max(levels_info)
+    b["radiate"] = pat + vec + box[lmax]
+    b["aggregate"] = sum(box[l + 1] + box[l] for l in levels_info if l < lmax)
+    b["translate"] = sum(2 * box[l] + 316 * levels_info[l]["K"] * esz for l in levels_info)
+    b["disaggregate"] = sum(box[l - 1] + 2 * box[l] for l in levels_info if l > min(levels_info))
+    b["receive"] = pat + box[lmax] + 2 * vec
+    return b, ni
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the matvec shards by right-hand sides or geometries, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2210_04892_amd as mf
+
+    v, t, spec = synth.workload(a.workload)
+    nrhs = a.nrhs or spec["nrhs"]
+    k = 2 * math.pi
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    g = mf.Geometry(v, t, k=k, leaf=spec["leaf"], max_rhs=nrhs)
+    t1 = time.perf_counter()
+    g.precompute()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    N = g.n_rwg
+    levels_info = {l: g.level_info(l) for l in range(2, g.levels)} if g.levels >= 3 else {}
+    x = synth.gaussian_coeffs(2 * N, nrhs, spec["seed"])
+    stream = torch.cuda.current_stream()
+    results = {}
+    ys = {}
+    for name, dt, code in (("c64", np.complex64, mf.C64), ("c128", np.complex128, mf.C128)):
+        xt = torch.from_numpy(np.ascontiguousarray(x.T.astype(dt))).cuda()    # column-major 2N x nrhs
+        yt = torch.empty_like(xt)
+        run = lambda: g.matvec_raw(a.op, code, nrhs, xt.data_ptr(), 2 * N, yt.data_ptr(), 2 * N, stream.cuda_stream)
+        for _ in range(a.warmup):
+            run()
+        torch.cuda.synchronize()
+        g.profile(True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(a.steps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        w1 = time.perf_counter()
+        stages, calls = g.profile_read()
+        g.profile(False)
+        ms = e0.elapsed_time(e1) / a.steps
+        esz = np.dtype(dt).itemsize
+        sb, ni = stage_bytes(g, levels_info, N, nrhs, esz, a.op)
+        per = {s: stages[s] / max(calls, 1) for s in stages}
+        dom = max(per, key=per.get)
+        ach = sb[dom] / (per[dom] * 1e-3) / 1e9
+        results[name] = {
+            "ms_per_step": ms, "wall_ms_per_step": (w1 - w0) * 1e3 / a.steps,
+            "value": 2 * N * nrhs / (ms * 1e-3),
+            "stage_ms": {s: round(per[s], 5) for s in per},
+            "dominant": dom,
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                         "algorithmic_bytes": int(sb[dom])},
+            "near_roofline_GBs": round(sb["near"] / (per["near"] * 1e-3) / 1e9, 1),
+        }
+        ys[name] = yt.t().cpu().numpy().astype(np.complex128)
+    # consistency of the two precisions (same tables, same tree)
+    d = np.linalg.norm(ys["c64"] - ys["c128"]) / np.linalg.norm(ys["c128"])
+    cpu = None
+    errs = {}
+    if a.cpu_rows > 0:
+        import oracle
+        nr = min(a.cpu_rows, N)
+        rows = np.sort(np.random.default_rng(spec["seed"] + 1000).choice(N, nr, replace=False))
+        c0 = time.perf_counter()
+        ref = oracle.matvec(v, t, k, x, op=oracle.OP_C if a.op == "C" else oracle.OP_EM, rows=rows)
+        c1 = time.perf_counter()
+        secs = c1 - c0
+        # a full product evaluates N rows (each giving a J and an M unknown)
+        cpu = {"value": 2 * nr * nrhs / secs, "unit": "unknowns*RHS/s", "cores": oracle.threads(),
+               "kind": "oracle", "seconds": round(secs, 2),
+               "sample": "%d of %d RWG rows (both halves), %d RHS, dense Galerkin product with converged "
+                         "touching-pair quadrature; full-matvec time extrapolated as seconds * N / rows" % (nr, N, nrhs)}
+        for name in ys:
+            got = np.concatenate([ys[name][rows], ys[name][N + rows]])
+            errs[name] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    head = results["c64"]
+    out = {
+        "metric": "MLFMA L/K matvec unknowns*RHS/s at <=1e-3 rel err vs FP64",
+        "value": round(head["value"], 1),
+        "unit": "unknowns*RHS/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "%s: %s" % (spec["name"], {kk: vv for kk, vv in spec.items() if kk != "name"}),
+                   "op": a.op, "n_rwg": N, "unknowns": 2 * N, "nrhs": nrhs, "levels": g.levels,
+                   "parallelism": "single GPU"},
+        "roofline": head["roofline"],
+        "cpu_baseline": cpu,
+        "err_vs_oracle_sampled_rows": errs,
+        "c64_vs_c128_rel_diff": float(d),
+        "c128": {"value": round(results["c128"]["value"], 1), "ms_per_step": round(results["c128"]["ms_per_step"], 5),
+                 "roofline": results["c128"]["roofline"]},
+        "stage_ms": {"c64": head["stage_ms"], "c128": results["c128"]["stage_ms"]},
+        "near_GBs": {"c64": head["near_roofline_GBs"], "c128": results["c128"]["near_roofline_GBs"]},
+        "setup_s": {"tree_tables_patterns": round(t1 - t0, 3), "near_field": round(t2 - t1, 3)},
+        "hbm_bytes": g.hbm_bytes,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

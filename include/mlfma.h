@@ -146,6 +146,24 @@ int mlfma_rwg_table(mlfma_handle h, int *edge_ab, int *tri_pm);
  * 0}.  Returns MLFMA_ERR_ARG for a level without translations. */
 int mlfma_level_info(mlfma_handle h, int level, long long info[6]);
 
+/* Near-field sizes: info[0..3] = {stored RWG pairs (slots), identity-term
+ * entries, touching triangle pairs, leaf boxes}.  MLFMA_ERR_STATE before
+ * mlfma_precompute_nearfield. */
+int mlfma_near_info(mlfma_handle h, long long info[4]);
+
+/*
+ * Stage timing with HIP events recorded on the matvec's stream.  Stages:
+ * 0 permute in, 1 near field, 2 radiation, 3 aggregation, 4 translation,
+ * 5 disaggregation, 6 receive, 7 permute out.  mlfma_profile(h, 1) resets
+ * the totals and records events around every stage of every later matvec;
+ * mlfma_profile(h, 0) stops.  mlfma_profile_read waits for the recorded
+ * events and returns per-stage totals in milliseconds (ms[8]) and the number
+ * of profiled matvecs.
+ */
+enum { MLFMA_STAGES = 8 };
+int mlfma_profile(mlfma_handle h, int enable);
+int mlfma_profile_read(mlfma_handle h, double ms[8], long long *calls);
+
 /* Text of the last error of the calling thread ("" if none). */
 const char *mlfma_last_error(void);
 

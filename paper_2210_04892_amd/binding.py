@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "_mlfma.so")
 OP_C, OP_EM = 0, 1
 C128, C64 = 0, 1
 PART_NEAR, PART_FAR, PART_ALL, PART_LEVEL = 1, 2, 3, 16
+STAGES = ("permute_in", "near", "radiate", "aggregate", "translate", "disaggregate", "receive", "permute_out")
 _OPS = {"C": OP_C, "EM": OP_EM, OP_C: OP_C, OP_EM: OP_EM}
 ERRORS = {-1: "MLFMA_ERR_ARG", -2: "MLFMA_ERR_MESH", -3: "MLFMA_ERR_OOM", -4: "MLFMA_ERR_HIP",
           -5: "MLFMA_ERR_STATE", -6: "MLFMA_ERR_TREE", -7: "MLFMA_ERR_UNSUPPORTED"}
@@ -57,6 +58,9 @@ def lib():
         L.mlfma_level_info.argtypes = [P, ctypes.c_int, P]
         L.mlfma_last_error.restype = ctypes.c_char_p
         L.mlfma_translation_operator.argtypes = [ctypes.c_double, ctypes.c_int, P, LL, P, P]
+        L.mlfma_near_info.argtypes = [P, P]
+        L.mlfma_profile.argtypes = [P, ctypes.c_int]
+        L.mlfma_profile_read.argtypes = [P, P, ctypes.POINTER(LL)]
         _lib = L
     return _lib
 
@@ -123,6 +127,21 @@ class Geometry:
         _check(lib().mlfma_level_info(self._h, level, info.ctypes.data))
         return {"boxes": int(info[0]), "L": int(info[1]), "K": int(info[2]), "translations": int(info[3]),
                 "box_edge": info[4] * 1e-6}
+
+    def near_info(self):
+        info = np.zeros(4, np.int64)
+        _check(lib().mlfma_near_info(self._h, info.ctypes.data))
+        return {"slots": int(info[0]), "identity": int(info[1]), "touching_pairs": int(info[2]),
+                "leaf_boxes": int(info[3])}
+
+    def profile(self, enable=True):
+        _check(lib().mlfma_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        ms = np.zeros(8)
+        calls = ctypes.c_longlong()
+        _check(lib().mlfma_profile_read(self._h, ms.ctypes.data, ctypes.byref(calls)))
+        return dict(zip(STAGES, ms.tolist())), calls.value
 
     def matvec(self, x, op="C", out=None, stream=None, part=PART_ALL):
         """y = A x on the GPU; x: complex128 or complex64 CUDA tensor of shape

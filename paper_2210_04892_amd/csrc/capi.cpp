@@ -89,6 +89,13 @@ struct mlfma_ctx {
     std::vector<void *> ws_allocs;
     void *X = nullptr, *Y = nullptr, *mid = nullptr;
     std::vector<void *> U, V;
+    // stage profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::vector<hipEvent_t>> ev_pending;
+    double stage_ms[MLFMA_STAGES] = {0};
+    long long prof_calls = 0;
+    long long n_touch = 0, n_slots = 0, n_id = 0;
 
     template <class T>
     T *dalloc(size_t count, std::vector<void *> *list = nullptr)
@@ -115,8 +122,36 @@ struct mlfma_ctx {
         ws_allocs.clear();
         ws_rhs = 0;
     }
+    std::vector<hipEvent_t> take_events()
+    {
+        std::vector<hipEvent_t> ev(MLFMA_STAGES + 1);
+        for (auto &e : ev) {
+            if (!ev_free.empty()) {
+                e = ev_free.back();
+                ev_free.pop_back();
+            } else {
+                HIPCHK(hipEventCreate(&e));
+            }
+        }
+        return ev;
+    }
+    void drain_events()
+    {
+        for (auto &ev : ev_pending) {
+            (void)hipEventSynchronize(ev.back());
+            for (int s = 0; s < MLFMA_STAGES; s++) {
+                float ms = 0;
+                if (hipEventElapsedTime(&ms, ev[s], ev[s + 1]) == hipSuccess) stage_ms[s] += ms;
+            }
+            prof_calls++;
+            for (auto e : ev) ev_free.push_back(e);
+        }
+        ev_pending.clear();
+    }
     ~mlfma_ctx()
     {
+        drain_events();
+        for (auto e : ev_free) (void)hipEventDestroy(e);
         free_ws();
         for (void *p : allocs) (void)hipFree(p);
     }
@@ -370,6 +405,8 @@ void precompute_near(mlfma_ctx *c)
         val_off[b + 1] = val_off[b] + (long long)(tr.box_start[b + 1] - tr.box_start[b]) * nc;
     }
     const long long nslot = val_off[L.nbox];
+    c->n_slots = nslot;
+    c->n_touch = (long long)pairs.size();
     c->val_off = c->upload(val_off);
     c->p64.near_em = c->dalloc<cpx<double>>(2 * (size_t)nslot);
     c->p64.near_c = c->dalloc<cpx<double>>(2 * (size_t)nslot);
@@ -457,6 +494,7 @@ void precompute_near(mlfma_ctx *c)
         }
         id_start[m + 1] = (int)id_col.size();
     }
+    c->n_id = (long long)id_col.size();
     c->id_start = c->upload(id_start);
     c->id_col = c->upload(id_col);
     c->p64.id_w = c->upload(id_w);
@@ -498,17 +536,29 @@ void run_matvec(mlfma_ctx *c, Prec<T> &P, int op, int part, int nrhs, const cpx<
     const Tree &tr = c->tr;
     const int N = c->r.n, leafl = tr.levels - 1;
     cpx<T> *X = (cpx<T> *)c->X, *Y = (cpx<T> *)c->Y, *mid = (cpx<T> *)c->mid;
+    std::vector<hipEvent_t> ev;
+    if (c->prof) ev = c->take_events();
+    auto mark = [&](int i) {
+        if (c->prof) HIPCHK(hipEventRecord(ev[i], st));
+    };
+    mark(0);
     launch_perm_in<T>(x, ldx, X, c->perm, N, nrhs, st);
+    mark(1);
     const Level &Lf = tr.lv[leafl];
     const int only_level = part >= MLFMA_PART_LEVEL ? part - MLFMA_PART_LEVEL : -1;
-    if (part & MLFMA_PART_NEAR)
+    const bool want_near = only_level < 0 && (part & MLFMA_PART_NEAR);
+    const bool want_far = only_level >= 0 || (part & MLFMA_PART_FAR);
+    if (want_near)
         launch_near<T>(Lf.nbox, c->box_start, c->near_start, c->near_box, c->val_off, nullptr,
                        op == MLFMA_OP_EM ? P.near_em : P.near_c, op == MLFMA_OP_C ? c->id_start : nullptr, c->id_col,
                        P.id_w, X, Y, nrhs, 27, st);
     else
         launch_zero<T>(Y, (long long)N * 2 * nrhs, st);
-    if (tr.levels >= 3 && (part & MLFMA_PART_FAR || only_level >= 0)) {
-        launch_radiate<T>(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)c->U[leafl], nrhs, st);
+    mark(2);
+    const bool far = tr.levels >= 3 && want_far;
+    if (far) launch_radiate<T>(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)c->U[leafl], nrhs, st);
+    mark(3);
+    if (far) {
         for (int l = leafl - 1; l >= 2; l--) {
             const Level &L = tr.lv[l], &C = tr.lv[l + 1];
             const IntLevel &I = c->lv[l];
@@ -518,6 +568,9 @@ void run_matvec(mlfma_ctx *c, Prec<T> &P, int op, int part, int nrhs, const cpx<
             launch_agg_phi<T>(L.nbox, L.K, midlen, I.child_start, c->lv[l + 1].oct, P.lv[l].shift, I.aph_s, I.aph_c,
                               P.lv[l].aph_w, mid, (cpx<T> *)c->U[l], nrhs, st);
         }
+    }
+    mark(4);
+    if (far) {
         for (int l = 2; l <= leafl; l++) {
             const Level &L = tr.lv[l];
             const IntLevel &I = c->lv[l];
@@ -527,6 +580,9 @@ void run_matvec(mlfma_ctx *c, Prec<T> &P, int op, int part, int nrhs, const cpx<
                 launch_translate<T>(L.nbox, L.K, I.il_start, I.il_box, I.il_off, P.lv[l].trans, (cpx<T> *)c->U[l],
                                     (cpx<T> *)c->V[l], nrhs, st);
         }
+    }
+    mark(5);
+    if (far) {
         for (int l = 3; l <= leafl; l++) {
             const Level &L = tr.lv[l], &Pl = tr.lv[l - 1];
             const IntLevel &Ip = c->lv[l - 1];
@@ -536,9 +592,13 @@ void run_matvec(mlfma_ctx *c, Prec<T> &P, int op, int part, int nrhs, const cpx<
             launch_interp<T>(L.nbox, L.K, midlen, Ip.dth_s, Ip.dth_c, P.lv[l - 1].dth_w, mid, (cpx<T> *)c->V[l],
                              nrhs, true, st);
         }
-        launch_receive<T>(op, N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)c->V[leafl], Y, nrhs, st);
     }
+    mark(6);
+    if (far) launch_receive<T>(op, N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)c->V[leafl], Y, nrhs, st);
+    mark(7);
     launch_perm_out<T>(Y, y, ldy, c->iperm, N, nrhs, st);
+    mark(8);
+    if (c->prof) c->ev_pending.push_back(ev);
 }
 
 int fail(const Error &e)
@@ -703,6 +763,49 @@ int mlfma_level_info(mlfma_handle h, int level, long long info[6])
     info[4] = (long long)std::llround(L.a * 1e6);
     info[5] = 0;
     return MLFMA_OK;
+}
+
+int mlfma_near_info(mlfma_handle h, long long info[4])
+{
+    if (!h || !info) return fail(Error(MLFMA_ERR_ARG, "NULL argument"));
+    if (!h->near_ready) return fail(Error(MLFMA_ERR_STATE, "near field not computed"));
+    info[0] = h->n_slots;
+    info[1] = h->n_id;
+    info[2] = h->n_touch;
+    info[3] = h->tr.lv[h->tr.levels - 1].nbox;
+    return MLFMA_OK;
+}
+
+int mlfma_profile(mlfma_handle h, int enable)
+{
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    try {
+        DeviceGuard g(h->device);
+        h->drain_events();
+        if (enable) {
+            for (double &v : h->stage_ms) v = 0;
+            h->prof_calls = 0;
+        }
+        h->prof = enable != 0;
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int mlfma_profile_read(mlfma_handle h, double ms[8], long long *calls)
+{
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    try {
+        DeviceGuard g(h->device);
+        h->drain_events();
+        if (ms)
+            for (int s = 0; s < MLFMA_STAGES; s++) ms[s] = h->stage_ms[s];
+        if (calls) *calls = h->prof_calls;
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
 }
 
 int mlfma_translation_operator(double k, int L, const double X[3], long long nk, const double *khat, double *out)

@@ -33,23 +33,6 @@ __host__ __device__ inline void fma_to(cpx<T> &acc, cpx<T> a, cpx<T> b)
     acc.im += a.re * b.im + a.im * b.re;
 }
 
-// Per-level device tables of the far field (one precision).
-template <class T>
-struct DevLevel {
-    int nbox = 0, K = 0, nth = 0, nph = 0;
-    const int *il_start = nullptr, *il_box = nullptr, *il_off = nullptr;   // interaction lists
-    const cpx<T> *trans = nullptr;        // 343 x K translation operators (offset-major)
-    const cpx<T> *shift = nullptr;        // 8 x K: exp(+jk khat.(r_child - r_parent)) for children at this level + 1
-    const int *child_start = nullptr;     // nbox + 1: children (level + 1) of each box, contiguous
-    const int *parent = nullptr;          // parent box (level - 1) of each box
-    const int *oct = nullptr;             // octant of each box inside its parent
-    // stencils from level + 1 to this level
-    const int *ath_s = nullptr, *ath_c = nullptr; const T *ath_w = nullptr; int ath_rows = 0;
-    const int *aph_s = nullptr, *aph_c = nullptr; const T *aph_w = nullptr;
-    const int *dph_s = nullptr, *dph_c = nullptr; const T *dph_w = nullptr;
-    const int *dth_s = nullptr, *dth_c = nullptr; const T *dth_w = nullptr;   // dth: rows of level + 1
-};
-
 // Launchers of the hot path (matvec.hip).  X, Y internal vectors
 // [rwg][half][rhs]; U, V patterns [box][sample][component][rhs].
 template <class T>

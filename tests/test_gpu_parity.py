@@ -34,7 +34,7 @@ def _rel(a, b):
 
 
 MESHES = {
-    "ico4_r0.5": lambda: synth.icosphere(4, 0.5),
+    "ico6_r0.5": lambda: synth.icosphere(6, 0.5),
     "sphere_r0.5": lambda: synth.icosphere(8, 0.5),
     "sphere_r3": lambda: synth.icosphere(36, 3.0),
     "box_4x4x1": lambda: synth.rounded_box((4.0, 4.0, 1.0), 0.2, 0.073),
@@ -84,7 +84,7 @@ def _pick(y, rows, N):
     return np.concatenate([y[rows], y[N + rows]])
 
 
-CASES = [("ico4_r0.5", None), ("sphere_r0.5", 192), ("sphere_r3", 40), ("box_4x4x1", 40)]
+CASES = [("ico6_r0.5", None), ("sphere_r0.5", 192), ("sphere_r3", 40), ("box_4x4x1", 40)]
 
 
 @pytest.mark.parametrize("name,nrows", CASES)
@@ -134,7 +134,7 @@ def test_per_level_far_field():
 def test_multi_rhs(nrhs):
     """Several right-hand sides in one launch (rhs chunks of 4 and 16 with a
     ragged tail) against the oracle, both precisions."""
-    name = "ico4_r0.5"
+    name = "ico6_r0.5"
     x, rows, ref = reference(name, None, nrhs, 5)
     for dtype in (np.complex128, np.complex64):
         for op in ("C", "EM"):
@@ -161,7 +161,7 @@ def test_leading_dimension_and_stream():
     """Padded leading dimensions and a non-default stream."""
     torch = _torch()
     import paper_2210_04892_amd as mf
-    name = "ico4_r0.5"
+    name = "ico6_r0.5"
     x, rows, ref = reference(name, None, 1, 2)
     N2 = x.shape[0]
     g = geometry(name)
@@ -183,7 +183,7 @@ def test_leading_dimension_and_stream():
 def test_error_paths():
     torch = _torch()
     import paper_2210_04892_amd as mf
-    v, t = mesh("ico4_r0.5")
+    v, t = mesh("ico6_r0.5")
     g = mf.Geometry(v, t, k=K0)
     x = torch.zeros(2 * g.n_rwg, dtype=torch.complex128, device="cuda")
     with pytest.raises(mf.MlfmaError) as e:
@@ -203,7 +203,7 @@ def test_error_paths():
 def test_budget_rejects_oversized_geometry():
     torch = _torch()  # noqa: F841
     import paper_2210_04892_amd as mf
-    v, t = mesh("ico4_r0.5")
+    v, t = mesh("ico6_r0.5")
     with pytest.raises(mf.MlfmaError) as e:
         mf.Geometry(v, t, k=K0, hbm_budget_bytes=1 << 16)
     assert e.value.code == -3

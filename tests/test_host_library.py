@@ -60,3 +60,32 @@ def test_translation_operator_rejects_bad_args():
     import paper_2210_04892_amd as mf
     with pytest.raises(mf.MlfmaError):
         mf.translation_operator(-1.0, 8, [1.0, 0, 0], np.array([[0, 0, 1.0]]))
+
+
+def _build_rc(v, t):
+    import paper_2210_04892_amd.binding as b
+    o = b.default_options()
+    h = ctypes.c_void_p()
+    v = np.ascontiguousarray(v, np.float64)
+    t = np.ascontiguousarray(t, np.int32)
+    rc = b.lib().mlfma_build_tree(v.ctypes.data, len(v), t.ctypes.data, len(t), ctypes.byref(o), ctypes.byref(h))
+    if rc == 0:
+        b.lib().mlfma_release(h)
+    return rc
+
+
+def test_build_rejects_bad_meshes_before_any_device_use():
+    """Mesh and tree errors are reported from the host checks (MLFMA_ERR_MESH,
+    MLFMA_ERR_TREE) whether or not a GPU is present."""
+    import synth
+    v, t = synth.icosphere(6, 0.5)
+    flipped = t.copy()
+    flipped[3] = flipped[3][::-1]
+    assert _build_rc(v, flipped) == -2              # inconsistent orientation
+    assert _build_rc(v, t[:, ::-1]) == -2           # inward normals
+    assert _build_rc(v, t[:-2]) == -2               # open surface
+    bad = v.copy()
+    bad[t[0][1]] = bad[t[0][0]]                     # degenerate triangle
+    assert _build_rc(bad, t) == -2
+    vv, tt = synth.icosphere(4, 0.5)                # edges of 0.15 wavelength
+    assert _build_rc(vv, tt) == -6                  # touching RWGs beyond adjacent 0.25 leaves
