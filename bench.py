@@ -36,6 +36,11 @@ def parse():
     p.add_argument("--nrhs", type=int, default=None, help="override the workload's RHS count")
     p.add_argument("--cpu-rows", type=int, default=160, help="rows of the oracle sample (0 = skip)")
     p.add_argument("--op", default="C", choices=["C", "EM"])
+    p.add_argument("--leaf-extra", type=int, default=2, help="extra multipoles at the leaf level")
+    p.add_argument("--interp-order", type=int, default=8, help="Lagrange points per angle")
+    p.add_argument("--digits", type=int, default=3, help="MLFMA accuracy parameter d0")
+    p.add_argument("--serve-requests", type=int, default=512,
+                   help="requests of the serving measurement (0 = skip it)")
     return p.parse_args()
 
 
@@ -80,15 +85,21 @@ def main():
     k = 2 * math.pi
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    g = mf.Geometry(v, t, k=k, leaf=spec["leaf"], max_rhs=nrhs)
+    g = mf.Geometry(v, t, k=k, leaf=spec["leaf"], max_rhs=nrhs, digits=a.digits, interp_order=a.interp_order,
+                    leaf_extra_L=a.leaf_extra)
     t1 = time.perf_counter()
     g.precompute()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     N = g.n_rwg
     levels_info = {l: g.level_info(l) for l in range(2, g.levels)} if g.levels >= 3 else {}
-    x = synth.gaussian_coeffs(2 * N, nrhs, spec["seed"])
     stream = torch.cuda.current_stream()
+    if spec.get("rhs") == "plane_waves":
+        # incident plane waves projected on the RWG functions by the library (eqs. 49-50)
+        khat, pol = synth.plane_waves(nrhs, spec["seed"])
+        x = g.plane_wave_rhs(khat, pol).cpu().numpy()
+    else:
+        x = synth.gaussian_coeffs(2 * N, nrhs, spec["seed"])
     results = {}
     ys = {}
     for name, dt, code in (("c64", np.complex64, mf.C64), ("c128", np.complex128, mf.C128)):
@@ -128,6 +139,7 @@ def main():
             "near_roofline_GBs": round(sb["near"] / (per["near"] * 1e-3) / 1e9, 1),
         }
         ys[name] = yt.t().cpu().numpy().astype(np.complex128)
+    hbm_bytes = g.hbm_bytes
     # consistency of the two precisions (same tables, same tree)
     d = np.linalg.norm(ys["c64"] - ys["c128"]) / np.linalg.norm(ys["c128"])
     cpu = None
@@ -137,7 +149,10 @@ def main():
         nr = min(a.cpu_rows, N)
         rows = np.sort(np.random.default_rng(spec["seed"] + 1000).choice(N, nr, replace=False))
         c0 = time.perf_counter()
-        ref = oracle.matvec(v, t, k, x, op=oracle.OP_C if a.op == "C" else oracle.OP_EM, rows=rows)
+        xo = x
+        if spec.get("rhs") == "plane_waves":
+            xo = oracle.plane_wave_rhs(v, t, k, khat, pol)      # the oracle's own right-hand sides
+        ref = oracle.matvec(v, t, k, xo, op=oracle.OP_C if a.op == "C" else oracle.OP_EM, rows=rows)
         c1 = time.perf_counter()
         secs = c1 - c0
         # a full product evaluates N rows (each giving a J and an M unknown)
@@ -148,9 +163,15 @@ def main():
         for name in ys:
             got = np.concatenate([ys[name][rows], ys[name][N + rows]])
             errs[name] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    serving = None
+    if a.serve_requests > 0:
+        from paper_2210_04892_amd import serving as srv
+        g.release()
+        serving = srv.run(synth.serving_set(5), n_requests=a.serve_requests, seed=5,
+                          log=lambda m: print(m, file=sys.stderr, flush=True))
     head = results["c64"]
     out = {
-        "metric": "MLFMA L/K matvec unknowns*RHS/s at <=1e-3 rel err vs FP64",
+        "metric": "MLFMA L/K matvec unknowns*RHS/s at <=1e-3 rel err vs FP64; p50/p99 latency",
         "value": round(head["value"], 1),
         "unit": "unknowns*RHS/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -159,6 +180,7 @@ def main():
         "dtype": "c64", "data": "synthetic",
         "config": {"workload": "%s: %s" % (spec["name"], {kk: vv for kk, vv in spec.items() if kk != "name"}),
                    "op": a.op, "n_rwg": N, "unknowns": 2 * N, "nrhs": nrhs, "levels": g.levels,
+                   "digits": a.digits, "interp_order": a.interp_order, "leaf_extra_L": a.leaf_extra,
                    "parallelism": "single GPU"},
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
@@ -169,7 +191,8 @@ def main():
         "stage_ms": {"c64": head["stage_ms"], "c128": results["c128"]["stage_ms"]},
         "near_GBs": {"c64": head["near_roofline_GBs"], "c128": results["c128"]["near_roofline_GBs"]},
         "setup_s": {"tree_tables_patterns": round(t1 - t0, 3), "near_field": round(t2 - t1, 3)},
-        "hbm_bytes": g.hbm_bytes,
+        "hbm_bytes": hbm_bytes,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -62,14 +62,14 @@ typedef struct {
     double wavenumber;   /* k in rad per length unit (k = 2 pi / lambda)            */
     double leaf_size;    /* edge of the finest octree boxes, length units           */
     int digits;          /* MLFMA accuracy parameter d0 of the truncation rule (3)  */
-    int interp_order;    /* Lagrange points per angular dimension (6)               */
+    int interp_order;    /* Lagrange points per angular dimension (8)               */
     int leaf_extra_L;    /* extra multipoles added at the leaf level (2)            */
     int max_rhs;         /* right-hand sides the workspace is sized for (1)         */
     int device;          /* HIP device ordinal (-1: the current device)             */
     unsigned long long hbm_budget_bytes;   /* 0 = no limit                          */
 } mlfma_options;
 
-/* Fill *opt with defaults: k = 2 pi, leaf 0.25, d0 = 3, order 6, extra 2,
+/* Fill *opt with defaults: k = 2 pi, leaf 0.25, d0 = 3, order 8, extra 2,
  * one RHS, current device, no budget.  Returns MLFMA_ERR_ARG on NULL. */
 int mlfma_options_default(mlfma_options *opt);
 
@@ -129,6 +129,53 @@ int mlfma_matvec_LK(mlfma_handle h, int op, int dtype, long long nrhs, const voi
 enum { MLFMA_PART_NEAR = 1, MLFMA_PART_FAR = 2, MLFMA_PART_ALL = 3, MLFMA_PART_LEVEL = 16 };
 int mlfma_matvec_part(mlfma_handle h, int op, int dtype, int part, long long nrhs, const void *x, long long ldx,
                       void *y, long long ldy, void *hip_stream);
+
+/*
+ * Right-hand sides of the coupled system for incident plane waves (eqs. 49,
+ * 50, excitation of Sec. III with E0 = 1 in the normalised units):
+ *   b^J_m = <f_m, E/2 + n x H/2>,  b^M_m = <f_m, H/2 - n x E/2>,
+ *   E = pol exp(-jk khat.r),  H = khat x pol exp(-jk khat.r),
+ * 7-point rule per triangle.  khat, pol: host arrays nrhs x 3 (unit vectors,
+ * pol perpendicular to khat); b: DEVICE, 2N x nrhs column-major (ldb >= 2N),
+ * complex128 or complex64 by dtype.  Blocking on hip_stream.
+ */
+int mlfma_plane_wave_rhs(mlfma_handle h, int dtype, long long nrhs, const double *khat, const double *pol, void *b,
+                         long long ldb, void *hip_stream);
+
+/*
+ * Serving: concurrent Krylov clients submit products for resident
+ * geometries; the server batches continuously.  A scheduler thread merges
+ * queued requests of the same (geometry, op, dtype) into one multi-RHS
+ * product of at most max_batch_rhs columns and admits it to a free launch
+ * slot (one stream and one workspace arena each; the arenas together stay
+ * within hbm_budget_bytes, 0 = no limit); requests arriving while others run
+ * are admitted as soon as a slot frees, so products for different geometries
+ * overlap on the device.  x and y of a request are DEVICE buffers owned by
+ * the caller and must stay valid until mlfma_server_wait returns; results are
+ * the same as mlfma_matvec_LK's up to rounding.  Handles must outlive the
+ * server's use of them.  All calls are thread-safe.
+ */
+typedef struct mlfma_server_s *mlfma_server;
+typedef struct {
+    int streams;                          /* launch slots (1..16, default 4)      */
+    int max_batch_rhs;                    /* columns merged per product (16)      */
+    int device;                           /* -1: the current device               */
+    unsigned long long hbm_budget_bytes;  /* bound on the slots' arenas, 0 = none */
+} mlfma_server_opts;
+int mlfma_server_opts_default(mlfma_server_opts *opt);
+int mlfma_server_create(const mlfma_server_opts *opt, mlfma_server *out);
+/* Enqueue y = A x (arguments as mlfma_matvec_LK); *ticket identifies it. */
+int mlfma_server_submit(mlfma_server s, mlfma_handle h, int op, int dtype, long long nrhs, const void *x,
+                        long long ldx, void *y, long long ldy, long long *ticket);
+/* Wait for a ticket (timeout_s < 0: forever).  On return y is complete;
+ * *latency_s = completion - submission (seconds), *batch_rhs = columns of the
+ * product it ran in (either pointer may be NULL).  MLFMA_ERR_STATE on timeout
+ * (the ticket stays valid), MLFMA_ERR_OOM if it can never be admitted. */
+int mlfma_server_wait(mlfma_server s, long long ticket, double timeout_s, double *latency_s, int *batch_rhs);
+/* out[0..3] = {products launched, requests served, arena bytes, queued requests} */
+int mlfma_server_stats(mlfma_server s, long long out[4]);
+/* Stop the threads (queued requests are dropped), free slots.  NULL accepted. */
+int mlfma_server_destroy(mlfma_server s);
 
 /* Free every device and host resource of the handle.  NULL is accepted. */
 int mlfma_release(mlfma_handle h);

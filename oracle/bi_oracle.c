@@ -809,6 +809,57 @@ int oracle_matvec(int nv, const double *v, int nt, const int *t, double k, int o
     return quad_fail ? ORC_ERR_QUAD : ORC_OK;
 }
 
+/*
+ * Right-hand sides of the coupled system for incident plane waves (eqs. 49,
+ * 50): b^J_m = <f_m, E/2 + n x H/2>, b^M_m = <f_m, H/2 - n x E/2> with
+ * E = p exp(-jk khat.r), H = khat x p exp(-jk khat.r) (the plane wave of
+ * Sec. III with E0 = 1 in the normalised units), 7-point rule per triangle.
+ * khat, pol: nrhs x 3 (unit vectors); out: 2N x nrhs column-major complex.
+ */
+int oracle_plane_wave_rhs(int nv, const double *v, int nt, const int *t, double k, int nrhs, const double *khat,
+                          const double *pol, double *out)
+{
+    mesh_t m;
+    int rc = mesh_build(&m, nv, v, nt, t);
+    if (rc != ORC_OK) { mesh_free(&m); return rc; }
+    const int N = m.n;
+    cplx *b = (cplx *)out;
+    memset(b, 0, sizeof(cplx) * 2 * (size_t)N * nrhs);
+    double bary[7][3], w[7];
+    tri7(bary, w);
+    for (int q = 0; q < nrhs; q++) {
+        const double *kh = khat + 3 * q, *p = pol + 3 * q;
+        double h[3];
+        vcross(kh, p, h);
+        for (int ti = 0; ti < nt; ti++) {
+            double P[3][3];
+            for (int a = 0; a < 3; a++)
+                for (int c = 0; c < 3; c++) P[a][c] = v[3 * t[3 * ti + a] + c];
+            const double *nn = &m.nrm[3 * ti];
+            double nxe[3], nxh[3];
+            vcross(nn, p, nxe);
+            vcross(nn, h, nxh);
+            for (int i = 0; i < 3; i++) {
+                int r = m.tri_rwg[3 * ti + i];
+                double cm = rwg_coef(&m, ti, i);
+                cplx bj = 0, bm = 0;
+                for (int pt = 0; pt < 7; pt++) {
+                    double x[3], a[3];
+                    for (int c = 0; c < 3; c++) x[c] = bary[pt][0] * P[0][c] + bary[pt][1] * P[1][c] + bary[pt][2] * P[2][c];
+                    vsub(x, P[i], a);
+                    cplx ph = cexp(-I * k * vdot(kh, x)) * w[pt] * m.area[ti] * cm;
+                    bj += ph * 0.5 * (vdot(a, p) + vdot(a, nxh));
+                    bm += ph * 0.5 * (vdot(a, h) - vdot(a, nxe));
+                }
+                b[(size_t)q * 2 * N + r] += bj;
+                b[(size_t)q * 2 * N + N + r] += bm;
+            }
+        }
+    }
+    mesh_free(&m);
+    return ORC_OK;
+}
+
 /* Leaf-box coordinates and level count of the box rule (tests of the tree). */
 int oracle_boxes(int nv, const double *v, int nt, const int *t, double leaf, int *coords, int *levels)
 {

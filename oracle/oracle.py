@@ -37,6 +37,8 @@ def _load():
                                       ctypes.c_int, ctypes.c_int]
         lib.oracle_boxes.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, P, P]
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_plane_wave_rhs.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
+                                              P, P, P]
         _lib = lib
     return _lib
 
@@ -61,6 +63,20 @@ def rwg_table(verts, tris):
     if rc < 0:
         raise ValueError("oracle rejected the mesh (code %d)" % rc)
     return e[:rc], pm[:rc]
+
+
+def plane_wave_rhs(verts, tris, k, khat, pol):
+    """[b^J; b^M] of eqs. 49-50 for plane waves (khat, pol: (nrhs, 3)); (2N, nrhs)."""
+    v, t = _mesh(verts, tris)
+    kh = np.ascontiguousarray(np.atleast_2d(khat), np.float64)
+    po = np.ascontiguousarray(np.atleast_2d(pol), np.float64)
+    N = 3 * len(t) // 2
+    out = np.zeros((len(kh), 2 * N), np.complex128)
+    rc = _load().oracle_plane_wave_rhs(len(v), v.ctypes.data, len(t), t.ctypes.data, k, len(kh), kh.ctypes.data,
+                                       po.ctypes.data, out.ctypes.data)
+    if rc < 0:
+        raise ValueError("oracle rejected the mesh (code %d)" % rc)
+    return out.T
 
 
 def leaf_boxes(verts, tris, leaf):

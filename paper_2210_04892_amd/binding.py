@@ -35,6 +35,11 @@ class Options(ctypes.Structure):
                 ("device", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_ulonglong)]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_int), ("max_batch_rhs", ctypes.c_int), ("device", ctypes.c_int),
+                ("hbm_budget_bytes", ctypes.c_ulonglong)]
+
+
 _lib = None
 
 
@@ -59,6 +64,14 @@ def lib():
         L.mlfma_last_error.restype = ctypes.c_char_p
         L.mlfma_translation_operator.argtypes = [ctypes.c_double, ctypes.c_int, P, LL, P, P]
         L.mlfma_near_info.argtypes = [P, P]
+        L.mlfma_plane_wave_rhs.argtypes = [P, ctypes.c_int, LL, P, P, P, LL, P]
+        L.mlfma_server_opts_default.argtypes = [ctypes.POINTER(ServerOptions)]
+        L.mlfma_server_create.argtypes = [ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
+        L.mlfma_server_submit.argtypes = [P, P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, ctypes.POINTER(LL)]
+        L.mlfma_server_wait.argtypes = [P, LL, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int)]
+        L.mlfma_server_stats.argtypes = [P, P]
+        L.mlfma_server_destroy.argtypes = [P]
         L.mlfma_profile.argtypes = [P, ctypes.c_int]
         L.mlfma_profile_read.argtypes = [P, P, ctypes.POINTER(LL)]
         _lib = L
@@ -80,7 +93,7 @@ class Geometry:
     """A closed triangulated surface with its octree, tables and near field
     resident on one GPU (mlfma_build_tree / mlfma_precompute_nearfield)."""
 
-    def __init__(self, verts, tris, k=2 * math.pi, leaf=0.25, digits=3, interp_order=6, leaf_extra_L=2,
+    def __init__(self, verts, tris, k=2 * math.pi, leaf=0.25, digits=3, interp_order=8, leaf_extra_L=2,
                  max_rhs=1, device=None, hbm_budget_bytes=0):
         o = default_options()
         o.wavenumber = k
@@ -127,6 +140,20 @@ class Geometry:
         _check(lib().mlfma_level_info(self._h, level, info.ctypes.data))
         return {"boxes": int(info[0]), "L": int(info[1]), "K": int(info[2]), "translations": int(info[3]),
                 "box_edge": info[4] * 1e-6}
+
+    def plane_wave_rhs(self, khat, pol, dtype=torch.complex128):
+        """[b^J; b^M] (eqs. 49-50) for plane waves khat, pol (nrhs x 3) as a
+        (2N, nrhs) CUDA tensor."""
+        kh = np.ascontiguousarray(np.atleast_2d(khat), np.float64)
+        po = np.ascontiguousarray(np.atleast_2d(pol), np.float64)
+        nrhs = len(kh)
+        bt = torch.empty((nrhs, 2 * self.n_rwg), dtype=dtype, device="cuda:%d" % self.device)
+        dt = C128 if dtype == torch.complex128 else C64
+        s = torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().mlfma_plane_wave_rhs(self._h, dt, nrhs, kh.ctypes.data, po.ctypes.data, bt.data_ptr(),
+                                              2 * self.n_rwg, s.cuda_stream))
+        return bt.t()
 
     def near_info(self):
         info = np.zeros(4, np.int64)
@@ -186,6 +213,63 @@ class Geometry:
     def __del__(self):
         try:
             self.release()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server (mlfma_server_*): submit products for
+    resident geometries from any thread, wait for tickets."""
+
+    def __init__(self, streams=4, max_batch_rhs=16, hbm_budget_bytes=0, device=None):
+        o = ServerOptions()
+        _check(lib().mlfma_server_opts_default(ctypes.byref(o)))
+        o.streams = streams
+        o.max_batch_rhs = max_batch_rhs
+        o.hbm_budget_bytes = hbm_budget_bytes
+        o.device = torch.cuda.current_device() if device is None else int(device)
+        self.device = o.device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().mlfma_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._s = h
+        self._keep = {}
+
+    def submit(self, geom, x, y, op="C"):
+        """Enqueue y = A x; x, y: column-major storage given as (nrhs, 2N)
+        contiguous CUDA tensors (row r = right-hand side r).  Returns a ticket.
+        The tensors are kept alive until the ticket is waited for."""
+        dt = C128 if x.dtype == torch.complex128 else C64
+        nrhs, n2 = x.shape
+        t = ctypes.c_longlong()
+        _check(lib().mlfma_server_submit(self._s, geom._h, _OPS.get(op, op), dt, nrhs, x.data_ptr(), n2,
+                                         y.data_ptr(), n2, ctypes.byref(t)))
+        self._keep[t.value] = (x, y)
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        """Block until the ticket is done; returns (latency_s, batch_rhs)."""
+        lat = ctypes.c_double()
+        br = ctypes.c_int()
+        try:
+            _check(lib().mlfma_server_wait(self._s, ticket, timeout, ctypes.byref(lat), ctypes.byref(br)))
+        finally:
+            self._keep.pop(ticket, None)
+        return lat.value, br.value
+
+    def stats(self):
+        out = np.zeros(4, np.int64)
+        _check(lib().mlfma_server_stats(self._s, out.ctypes.data))
+        return {"launches": int(out[0]), "requests": int(out[1]), "arena_bytes": int(out[2]), "queued": int(out[3])}
+
+    def close(self):
+        if getattr(self, "_s", None):
+            lib().mlfma_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
 

@@ -66,6 +66,24 @@ struct IntLevel {
     int *dph_s = nullptr, *dph_c = nullptr, *dth_s = nullptr, *dth_c = nullptr;
 };
 
+// Per-product scratch: internal vectors, box patterns of every level and the
+// stencil intermediate, sized for `rhs` right-hand sides in complex double
+// units (the complex float path uses the first half of every buffer).
+struct Workspace {
+    int rhs = 0;
+    unsigned long long bytes = 0;
+    std::vector<void *> allocs;
+    void *X = nullptr, *Y = nullptr, *mid = nullptr;
+    std::vector<void *> U, V;
+    void release()
+    {
+        for (void *p : allocs) (void)hipFree(p);
+        allocs.clear();
+        rhs = 0;
+        bytes = 0;
+    }
+};
+
 }  // namespace
 
 struct mlfma_ctx {
@@ -80,15 +98,14 @@ struct mlfma_ctx {
     int *perm = nullptr, *iperm = nullptr, *leaf_of = nullptr, *box_start = nullptr;
     int *near_start = nullptr, *near_box = nullptr, *id_start = nullptr, *id_col = nullptr;
     long long *val_off = nullptr;
+    // geometry on the device (internal RWG order): triangles and RWG pieces
+    int *g_rtri = nullptr, *g_rloc = nullptr;
+    double *g_rcoef = nullptr, *g_tv = nullptr, *g_tn = nullptr, *g_ta = nullptr;
     std::vector<IntLevel> lv;
     Prec<double> p64;
     Prec<float> p32;
     bool near_ready = false;
-    // workspace (sized in complex<double> units for `ws_rhs` right-hand sides)
-    int ws_rhs = 0;
-    std::vector<void *> ws_allocs;
-    void *X = nullptr, *Y = nullptr, *mid = nullptr;
-    std::vector<void *> U, V;
+    Workspace ws;             // workspace of mlfma_matvec_LK / mlfma_matvec_part
     // stage profiling
     bool prof = false;
     std::vector<hipEvent_t> ev_free;
@@ -118,9 +135,8 @@ struct mlfma_ctx {
     }
     void free_ws()
     {
-        for (void *p : ws_allocs) (void)hipFree(p);
-        ws_allocs.clear();
-        ws_rhs = 0;
+        bytes -= ws.bytes;
+        ws.release();
     }
     std::vector<hipEvent_t> take_events()
     {
@@ -252,11 +268,10 @@ void build_device_tables(mlfma_ctx *c)
     upload_level_tables<double>(c, c->p64, trans, shift);
     upload_level_tables<float>(c, c->p32, trans, shift);
 
-    if (tr.levels >= 3) {
-        // leaf patterns on the device (double), then a single-precision copy
-        const Level &L = tr.lv[leafl];
+    // geometry in internal RWG order (kept: near field, plane waves)
+    {
         std::vector<int> rtri(2 * (size_t)N), rloc(2 * (size_t)N);
-        std::vector<double> rcoef(2 * (size_t)N), cen(3 * (size_t)N), tv(9 * (size_t)c->s.nt);
+        std::vector<double> rcoef(2 * (size_t)N), tv(9 * (size_t)c->s.nt);
         for (int i = 0; i < N; i++) {
             int u = tr.perm[i];
             for (int h = 0; h < 2; h++) {
@@ -264,28 +279,28 @@ void build_device_tables(mlfma_ctx *c)
                 rloc[2 * i + h] = c->r.loc[h][u];
                 rcoef[2 * i + h] = c->r.coef[h][u];
             }
-            for (int d = 0; d < 3; d++) cen[3 * i + d] = L.centre[3 * tr.leaf_of[i] + d];
         }
         for (int t = 0; t < c->s.nt; t++)
             for (int a = 0; a < 3; a++)
                 for (int d = 0; d < 3; d++) tv[9 * (size_t)t + 3 * a + d] = c->s.v[3 * c->s.t[3 * t + a] + d];
+        c->g_rtri = c->upload(rtri);
+        c->g_rloc = c->upload(rloc);
+        c->g_rcoef = c->upload(rcoef);
+        c->g_tv = c->upload(tv);
+        c->g_tn = c->upload(c->s.nrm);
+        c->g_ta = c->upload(c->s.area);
+    }
+    if (tr.levels >= 3) {
+        // leaf patterns on the device (double), then a single-precision copy
+        const Level &L = tr.lv[leafl];
+        std::vector<double> cen(3 * (size_t)N);
+        for (int i = 0; i < N; i++)
+            for (int d = 0; d < 3; d++) cen[3 * i + d] = L.centre[3 * tr.leaf_of[i] + d];
         std::vector<void *> tmp;
         const unsigned long long bytes_before = c->bytes;
-        auto d_rtri = c->dalloc<int>(rtri.size(), &tmp);
-        auto d_rloc = c->dalloc<int>(rloc.size(), &tmp);
-        auto d_rcoef = c->dalloc<double>(rcoef.size(), &tmp);
         auto d_cen = c->dalloc<double>(cen.size(), &tmp);
-        auto d_tv = c->dalloc<double>(tv.size(), &tmp);
-        auto d_tn = c->dalloc<double>(c->s.nrm.size(), &tmp);
-        auto d_ta = c->dalloc<double>(c->s.area.size(), &tmp);
         auto d_ct = c->dalloc<double>(L.ct.size(), &tmp);
-        HIPCHK(hipMemcpy(d_rtri, rtri.data(), rtri.size() * 4, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(d_rloc, rloc.data(), rloc.size() * 4, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(d_rcoef, rcoef.data(), rcoef.size() * 8, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(d_cen, cen.data(), cen.size() * 8, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(d_tv, tv.data(), tv.size() * 8, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(d_tn, c->s.nrm.data(), c->s.nrm.size() * 8, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(d_ta, c->s.area.data(), c->s.area.size() * 8, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(d_ct, L.ct.data(), L.ct.size() * 8, hipMemcpyHostToDevice));
         const unsigned long long tmp_bytes = c->bytes - bytes_before;
         const size_t np = (size_t)N * L.K * 2;
@@ -293,8 +308,8 @@ void build_device_tables(mlfma_ctx *c)
         c->p64.Q = c->dalloc<cpx<double>>(np);
         c->p32.R = c->dalloc<cpx<float>>(np);
         c->p32.Q = c->dalloc<cpx<float>>(np);
-        launch_patterns(N, L.K, L.nph, d_ct, k, d_rtri, d_rcoef, d_rloc, d_tv, d_tn, d_ta, d_cen, c->p64.R, c->p64.Q,
-                        nullptr);
+        launch_patterns(N, L.K, L.nph, d_ct, k, c->g_rtri, c->g_rcoef, c->g_rloc, c->g_tv, c->g_tn, c->g_ta, d_cen,
+                        c->p64.R, c->p64.Q, nullptr);
         HIPCHK(hipGetLastError());
         launch_to_float(c->p64.R, c->p32.R, (long long)np, nullptr);
         launch_to_float(c->p64.Q, c->p32.Q, (long long)np, nullptr);
@@ -412,20 +427,6 @@ void precompute_near(mlfma_ctx *c)
     c->p64.near_c = c->dalloc<cpx<double>>(2 * (size_t)nslot);
     c->p32.near_em = c->dalloc<cpx<float>>(2 * (size_t)nslot);
     c->p32.near_c = c->dalloc<cpx<float>>(2 * (size_t)nslot);
-    // per-RWG data in internal order, triangle data
-    std::vector<int> rtri(2 * (size_t)N), rloc(2 * (size_t)N);
-    std::vector<double> rcoef(2 * (size_t)N), tv(9 * (size_t)nt);
-    for (int i = 0; i < N; i++) {
-        int u = tr.perm[i];
-        for (int h = 0; h < 2; h++) {
-            rtri[2 * i + h] = r.tri[h][u];
-            rloc[2 * i + h] = r.loc[h][u];
-            rcoef[2 * i + h] = r.coef[h][u];
-        }
-    }
-    for (int t = 0; t < nt; t++)
-        for (int a = 0; a < 3; a++)
-            for (int d = 0; d < 3; d++) tv[9 * (size_t)t + 3 * a + d] = s.v[3 * s.t[3 * t + a] + d];
     std::vector<void *> tmp;
     auto up = [&](auto &h) {
         using E = typename std::remove_reference<decltype(h)>::type::value_type;
@@ -434,17 +435,15 @@ void precompute_near(mlfma_ctx *c)
         return d;
     };
     unsigned long long bytes_before = c->bytes;
-    int *d_rtri = up(rtri), *d_rloc = up(rloc), *d_tps = up(tp_start), *d_tp_s = up(tp_s), *d_goff = up(goff);
-    double *d_rcoef = up(rcoef), *d_tv = up(tv), *d_gn = up(gn);
-    std::vector<double> nrm(s.nrm), area(s.area);
-    double *d_tn = up(nrm), *d_ta = up(area);
+    int *d_tps = up(tp_start), *d_tp_s = up(tp_s), *d_goff = up(goff);
+    double *d_gn = up(gn);
     TouchPair *d_pairs = up(pairs);
     cpx<double> *d_touch = c->dalloc<cpx<double>>(36 * std::max<size_t>(pairs.size(), 1), &tmp);
     launch_touch((int)pairs.size(), d_pairs, k, d_gn, d_goff, d_touch, nullptr);
     HIPCHK(hipGetLastError());
-    launch_slots(L.nbox, c->box_start, c->near_start, c->near_box, c->val_off, d_rtri, d_rloc, d_rcoef, d_tv, d_tn,
-                 d_ta, d_tps, d_tp_s, d_touch, k, c->p64.near_em, c->p64.near_c, c->p32.near_em, c->p32.near_c,
-                 nullptr);
+    launch_slots(L.nbox, c->box_start, c->near_start, c->near_box, c->val_off, c->g_rtri, c->g_rloc, c->g_rcoef,
+                 c->g_tv, c->g_tn, c->g_ta, d_tps, d_tp_s, d_touch, k, c->p64.near_em, c->p64.near_c, c->p32.near_em,
+                 c->p32.near_c, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipDeviceSynchronize());
     for (void *p : tmp) (void)hipFree(p);
@@ -503,43 +502,109 @@ void precompute_near(mlfma_ctx *c)
 }
 
 // ---------------------------------------------------------------- workspace
-void ensure_workspace(mlfma_ctx *c, int nrhs)
+// Bytes of a workspace for nrhs right-hand sides.
+unsigned long long workspace_bytes(const mlfma_ctx *c, int nrhs)
 {
-    if (nrhs <= c->ws_rhs) return;
-    c->free_ws();
+    const Tree &tr = c->tr;
+    const unsigned long long cd = sizeof(cpx<double>);
+    unsigned long long n = 2ULL * (unsigned long long)c->r.n * 2 * nrhs;
+    unsigned long long midmax = 1;
+    for (int l = 2; l < tr.levels; l++) {
+        const Level &L = tr.lv[l];
+        n += 2ULL * L.nbox * L.K * 2 * nrhs;
+        if (l + 1 < tr.levels) {
+            const Level &C = tr.lv[l + 1];
+            midmax = std::max<unsigned long long>(midmax, (unsigned long long)C.nbox * L.nth * C.nph * 2 * nrhs);
+        }
+    }
+    return (n + midmax) * cd;
+}
+
+// Allocate w for nrhs right-hand sides (no budget check: the caller admits).
+void alloc_workspace(const mlfma_ctx *c, Workspace &w, int nrhs)
+{
+    w.release();
     const Tree &tr = c->tr;
     const size_t cd = sizeof(cpx<double>);
-    auto get = [&](size_t elems) { return (void *)c->dalloc<char>(elems * cd, &c->ws_allocs); };
+    auto get = [&](size_t elems) {
+        void *p = nullptr;
+        HIPCHK(hipMalloc(&p, std::max<size_t>(elems, 1) * cd));
+        w.allocs.push_back(p);
+        w.bytes += std::max<size_t>(elems, 1) * cd;
+        return p;
+    };
     const int N = c->r.n;
-    c->X = get((size_t)N * 2 * nrhs);
-    c->Y = get((size_t)N * 2 * nrhs);
-    c->U.assign(tr.levels, nullptr);
-    c->V.assign(tr.levels, nullptr);
+    w.X = get((size_t)N * 2 * nrhs);
+    w.Y = get((size_t)N * 2 * nrhs);
+    w.U.assign(tr.levels, nullptr);
+    w.V.assign(tr.levels, nullptr);
     size_t midmax = 1;
     for (int l = 2; l < tr.levels; l++) {
         const Level &L = tr.lv[l];
-        c->U[l] = get((size_t)L.nbox * L.K * 2 * nrhs);
-        c->V[l] = get((size_t)L.nbox * L.K * 2 * nrhs);
+        w.U[l] = get((size_t)L.nbox * L.K * 2 * nrhs);
+        w.V[l] = get((size_t)L.nbox * L.K * 2 * nrhs);
         if (l + 1 < tr.levels) {
             const Level &C = tr.lv[l + 1];
             midmax = std::max(midmax, (size_t)C.nbox * L.nth * C.nph * 2 * nrhs);
         }
     }
-    c->mid = get(midmax);
-    c->ws_rhs = nrhs;
+    w.mid = get(midmax);
+    w.rhs = nrhs;
+}
+
+// Lay a workspace for nrhs right-hand sides over an existing arena of at
+// least workspace_bytes(c, nrhs) bytes (no allocation).
+void carve_workspace(const mlfma_ctx *c, Workspace &w, char *base, int nrhs)
+{
+    const Tree &tr = c->tr;
+    const size_t cd = sizeof(cpx<double>);
+    size_t off = 0;
+    auto take = [&](size_t elems) {
+        void *p = base + off;
+        off += elems * cd;
+        return p;
+    };
+    const int N = c->r.n;
+    w.X = take((size_t)N * 2 * nrhs);
+    w.Y = take((size_t)N * 2 * nrhs);
+    w.U.assign(tr.levels, nullptr);
+    w.V.assign(tr.levels, nullptr);
+    size_t midmax = 1;
+    for (int l = 2; l < tr.levels; l++) {
+        const Level &L = tr.lv[l];
+        w.U[l] = take((size_t)L.nbox * L.K * 2 * nrhs);
+        w.V[l] = take((size_t)L.nbox * L.K * 2 * nrhs);
+        if (l + 1 < tr.levels) {
+            const Level &C = tr.lv[l + 1];
+            midmax = std::max(midmax, (size_t)C.nbox * L.nth * C.nph * 2 * nrhs);
+        }
+    }
+    w.mid = take(midmax);
+    w.rhs = nrhs;
+}
+
+void ensure_workspace(mlfma_ctx *c, int nrhs)
+{
+    if (nrhs <= c->ws.rhs) return;
+    c->free_ws();
+    const unsigned long long need = workspace_bytes(c, nrhs);
+    if (c->opt.hbm_budget_bytes && c->bytes + need > c->opt.hbm_budget_bytes)
+        throw Error(MLFMA_ERR_OOM, "device memory budget exceeded by the workspace");
+    alloc_workspace(c, c->ws, nrhs);
+    c->bytes += c->ws.bytes;
 }
 
 template <class T>
-void run_matvec(mlfma_ctx *c, Prec<T> &P, int op, int part, int nrhs, const cpx<T> *x, long long ldx, cpx<T> *y,
-                long long ldy, hipStream_t st)
+void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nrhs, const cpx<T> *x, long long ldx,
+                cpx<T> *y, long long ldy, hipStream_t st, bool profile)
 {
     const Tree &tr = c->tr;
     const int N = c->r.n, leafl = tr.levels - 1;
-    cpx<T> *X = (cpx<T> *)c->X, *Y = (cpx<T> *)c->Y, *mid = (cpx<T> *)c->mid;
+    cpx<T> *X = (cpx<T> *)w.X, *Y = (cpx<T> *)w.Y, *mid = (cpx<T> *)w.mid;
     std::vector<hipEvent_t> ev;
-    if (c->prof) ev = c->take_events();
+    if (profile) ev = c->take_events();
     auto mark = [&](int i) {
-        if (c->prof) HIPCHK(hipEventRecord(ev[i], st));
+        if (profile) HIPCHK(hipEventRecord(ev[i], st));
     };
     mark(0);
     launch_perm_in<T>(x, ldx, X, c->perm, N, nrhs, st);
@@ -549,24 +614,24 @@ void run_matvec(mlfma_ctx *c, Prec<T> &P, int op, int part, int nrhs, const cpx<
     const bool want_near = only_level < 0 && (part & MLFMA_PART_NEAR);
     const bool want_far = only_level >= 0 || (part & MLFMA_PART_FAR);
     if (want_near)
-        launch_near<T>(Lf.nbox, c->box_start, c->near_start, c->near_box, c->val_off, nullptr,
+        launch_near<T>(N, c->leaf_of, c->box_start, c->near_start, c->near_box, c->val_off,
                        op == MLFMA_OP_EM ? P.near_em : P.near_c, op == MLFMA_OP_C ? c->id_start : nullptr, c->id_col,
-                       P.id_w, X, Y, nrhs, 27, st);
+                       P.id_w, X, Y, nrhs, st);
     else
         launch_zero<T>(Y, (long long)N * 2 * nrhs, st);
     mark(2);
     const bool far = tr.levels >= 3 && want_far;
-    if (far) launch_radiate<T>(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)c->U[leafl], nrhs, st);
+    if (far) launch_radiate<T>(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)w.U[leafl], nrhs, st);
     mark(3);
     if (far) {
         for (int l = leafl - 1; l >= 2; l--) {
             const Level &L = tr.lv[l], &C = tr.lv[l + 1];
             const IntLevel &I = c->lv[l];
             const int midlen = L.nth * C.nph;
-            launch_interp<T>(C.nbox, midlen, C.K, I.ath_s, I.ath_c, P.lv[l].ath_w, (cpx<T> *)c->U[l + 1], mid, nrhs,
+            launch_interp<T>(C.nbox, midlen, C.K, I.ath_s, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], mid, nrhs,
                              false, st);
             launch_agg_phi<T>(L.nbox, L.K, midlen, I.child_start, c->lv[l + 1].oct, P.lv[l].shift, I.aph_s, I.aph_c,
-                              P.lv[l].aph_w, mid, (cpx<T> *)c->U[l], nrhs, st);
+                              P.lv[l].aph_w, mid, (cpx<T> *)w.U[l], nrhs, st);
         }
     }
     mark(4);
@@ -575,10 +640,10 @@ void run_matvec(mlfma_ctx *c, Prec<T> &P, int op, int part, int nrhs, const cpx<
             const Level &L = tr.lv[l];
             const IntLevel &I = c->lv[l];
             if (only_level >= 0 && l != only_level)
-                launch_zero<T>((cpx<T> *)c->V[l], (long long)L.nbox * L.K * 2 * nrhs, st);
+                launch_zero<T>((cpx<T> *)w.V[l], (long long)L.nbox * L.K * 2 * nrhs, st);
             else
-                launch_translate<T>(L.nbox, L.K, I.il_start, I.il_box, I.il_off, P.lv[l].trans, (cpx<T> *)c->U[l],
-                                    (cpx<T> *)c->V[l], nrhs, st);
+                launch_translate<T>(L.nbox, L.K, I.il_start, I.il_box, I.il_off, P.lv[l].trans, (cpx<T> *)w.U[l],
+                                    (cpx<T> *)w.V[l], nrhs, st);
         }
     }
     mark(5);
@@ -588,17 +653,17 @@ void run_matvec(mlfma_ctx *c, Prec<T> &P, int op, int part, int nrhs, const cpx<
             const IntLevel &Ip = c->lv[l - 1];
             const int midlen = Pl.nth * L.nph;
             launch_disagg_mid<T>(L.nbox, midlen, Pl.K, c->lv[l].parent, c->lv[l].oct, P.lv[l - 1].shift, Ip.dph_s,
-                                 Ip.dph_c, P.lv[l - 1].dph_w, (cpx<T> *)c->V[l - 1], mid, nrhs, st);
-            launch_interp<T>(L.nbox, L.K, midlen, Ip.dth_s, Ip.dth_c, P.lv[l - 1].dth_w, mid, (cpx<T> *)c->V[l],
+                                 Ip.dph_c, P.lv[l - 1].dph_w, (cpx<T> *)w.V[l - 1], mid, nrhs, st);
+            launch_interp<T>(L.nbox, L.K, midlen, Ip.dth_s, Ip.dth_c, P.lv[l - 1].dth_w, mid, (cpx<T> *)w.V[l],
                              nrhs, true, st);
         }
     }
     mark(6);
-    if (far) launch_receive<T>(op, N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)c->V[leafl], Y, nrhs, st);
+    if (far) launch_receive<T>(op, N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], Y, nrhs, st);
     mark(7);
     launch_perm_out<T>(Y, y, ldy, c->iperm, N, nrhs, st);
     mark(8);
-    if (c->prof) c->ev_pending.push_back(ev);
+    if (profile) c->ev_pending.push_back(ev);
 }
 
 int fail(const Error &e)
@@ -620,7 +685,7 @@ int mlfma_options_default(mlfma_options *opt)
     opt->wavenumber = 2 * M_PI;
     opt->leaf_size = 0.25;
     opt->digits = 3;
-    opt->interp_order = 6;
+    opt->interp_order = 8;
     opt->leaf_extra_L = 2;
     opt->max_rhs = 1;
     opt->device = -1;
@@ -699,10 +764,11 @@ int mlfma_matvec_part(mlfma_handle h, int op, int dtype, int part, long long nrh
         ensure_workspace(h, (int)nrhs);
         hipStream_t st = (hipStream_t)hip_stream;
         if (dtype == MLFMA_C128)
-            run_matvec<double>(h, h->p64, op, part, (int)nrhs, (const cpx<double> *)x, ldx, (cpx<double> *)y, ldy,
-                               st);
+            run_matvec<double>(h, h->ws, h->p64, op, part, (int)nrhs, (const cpx<double> *)x, ldx, (cpx<double> *)y,
+                               ldy, st, h->prof);
         else
-            run_matvec<float>(h, h->p32, op, part, (int)nrhs, (const cpx<float> *)x, ldx, (cpx<float> *)y, ldy, st);
+            run_matvec<float>(h, h->ws, h->p32, op, part, (int)nrhs, (const cpx<float> *)x, ldx, (cpx<float> *)y,
+                              ldy, st, h->prof);
         HIPCHK(hipGetLastError());
         return MLFMA_OK;
     } catch (const Error &e) {
@@ -808,6 +874,37 @@ int mlfma_profile_read(mlfma_handle h, double ms[8], long long *calls)
     }
 }
 
+int mlfma_plane_wave_rhs(mlfma_handle h, int dtype, long long nrhs, const double *khat, const double *pol, void *b,
+                         long long ldb, void *hip_stream)
+{
+    g_last_error.clear();
+    if (!h || !khat || !pol || !b || nrhs < 1 || ldb < 2LL * h->r.n || (dtype != MLFMA_C128 && dtype != MLFMA_C64))
+        return fail(Error(MLFMA_ERR_ARG, "bad arguments"));
+    try {
+        DeviceGuard g(h->device);
+        std::vector<double> dirs(6 * (size_t)nrhs);
+        for (long long r = 0; r < nrhs; r++)
+            for (int d = 0; d < 3; d++) {
+                dirs[6 * r + d] = khat[3 * r + d];
+                dirs[6 * r + 3 + d] = pol[3 * r + d];
+            }
+        std::vector<void *> tmp;
+        const unsigned long long before = h->bytes;
+        double *d_dirs = h->dalloc<double>(dirs.size(), &tmp);
+        HIPCHK(hipMemcpy(d_dirs, dirs.data(), dirs.size() * 8, hipMemcpyHostToDevice));
+        hipStream_t st = (hipStream_t)hip_stream;
+        launch_plane_wave(dtype == MLFMA_C64, h->r.n, (int)nrhs, h->opt.wavenumber, h->perm, h->g_rtri, h->g_rloc,
+                          h->g_rcoef, h->g_tv, h->g_tn, h->g_ta, d_dirs, b, ldb, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        for (void *p : tmp) (void)hipFree(p);
+        h->bytes = before;
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
 int mlfma_translation_operator(double k, int L, const double X[3], long long nk, const double *khat, double *out)
 {
     if (!(k > 0) || L < 0 || !X || nk < 0 || (nk && (!khat || !out))) return fail(Error(MLFMA_ERR_ARG, "bad args"));
@@ -818,6 +915,398 @@ int mlfma_translation_operator(double k, int L, const double X[3], long long nk,
         out[2 * q] = o[q].real();
         out[2 * q + 1] = o[q].imag();
     }
+    return MLFMA_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== serving
+// Continuous batching: client threads submit products for resident
+// geometries; a scheduler thread merges queued requests of the same
+// (geometry, op, dtype) into one multi-RHS product, admits it to a free
+// launch slot (a stream and a workspace arena; arenas are bounded by the
+// memory budget), gathers the requests' columns into the slot's batch buffer,
+// runs the product and scatters the columns back; a poller thread retires
+// finished slots.  Requests that arrive while others run are admitted as
+// soon as a slot frees, so work on different geometries overlaps on the GPU.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    long long ticket = 0;
+    mlfma_handle h = nullptr;
+    int op = 0, dtype = 0, nrhs = 0;
+    const void *x = nullptr;
+    void *y = nullptr;
+    long long ldx = 0, ldy = 0;
+    Clock::time_point t_submit, t_start, t_done;
+    int state = 0;        // 0 queued, 1 running, 2 done, < 0 error code
+    int batch_rhs = 0;    // right-hand sides of the product it ran in
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    char *arena = nullptr;
+    unsigned long long arena_bytes = 0;
+    char *xb = nullptr, *yb = nullptr;
+    unsigned long long io_bytes = 0;
+    bool busy = false;
+    std::vector<Request *> reqs;
+};
+
+}  // namespace
+
+struct mlfma_server_s {
+    mlfma_server_opts opt{};
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_done;
+    std::deque<Request *> queue;
+    std::unordered_map<long long, Request *> reqs;
+    std::vector<Slot> slots;
+    unsigned long long arena_total = 0;
+    long long next_ticket = 1;
+    long long launches = 0, batched_requests = 0;
+    bool stop = false;
+    std::string thread_error;
+    std::thread sched, poll;
+};
+
+namespace {
+
+unsigned long long io_bytes_for(mlfma_handle h, int rhs) { return 2ULL * h->r.n * rhs * sizeof(cpx<double>); }
+
+// Runs on the scheduler thread with the lock released.
+void launch_batch(mlfma_server_s *S, Slot &slot, std::vector<Request *> &batch, int total)
+{
+    mlfma_handle h = batch[0]->h;
+    const int op = batch[0]->op, dtype = batch[0]->dtype;
+    const size_t esz = dtype == MLFMA_C128 ? 16 : 8;
+    const long long N2 = 2LL * h->r.n;
+    int col = 0;
+    for (Request *r : batch) {
+        HIPCHK(hipMemcpy2DAsync(slot.xb + (size_t)col * N2 * esz, N2 * esz, r->x, r->ldx * esz, N2 * esz, r->nrhs,
+                                hipMemcpyDeviceToDevice, slot.stream));
+        col += r->nrhs;
+    }
+    Workspace w;
+    carve_workspace(h, w, slot.arena, total);
+    if (dtype == MLFMA_C128)
+        run_matvec<double>(h, w, h->p64, op, MLFMA_PART_ALL, total, (const cpx<double> *)slot.xb, N2,
+                           (cpx<double> *)slot.yb, N2, slot.stream, false);
+    else
+        run_matvec<float>(h, w, h->p32, op, MLFMA_PART_ALL, total, (const cpx<float> *)slot.xb, N2,
+                          (cpx<float> *)slot.yb, N2, slot.stream, false);
+    col = 0;
+    for (Request *r : batch) {
+        HIPCHK(hipMemcpy2DAsync(r->y, r->ldy * esz, slot.yb + (size_t)col * N2 * esz, N2 * esz, N2 * esz, r->nrhs,
+                                hipMemcpyDeviceToDevice, slot.stream));
+        col += r->nrhs;
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(slot.done, slot.stream));
+}
+
+void scheduler_loop(mlfma_server_s *S)
+{
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (!S->stop) {
+        if (S->queue.empty()) {
+            S->cv_sched.wait(lk);
+            continue;
+        }
+        Request *r0 = S->queue.front();
+        mlfma_handle h = r0->h;
+        const int maxb = std::max(S->opt.max_batch_rhs, r0->nrhs);
+        const unsigned long long need = workspace_bytes(h, maxb), ion = io_bytes_for(h, maxb);
+        // a free slot whose arena fits, else a free slot that may grow within the budget
+        int pick = -1;
+        for (size_t i = 0; i < S->slots.size(); i++)
+            if (!S->slots[i].busy && S->slots[i].arena_bytes >= need && S->slots[i].io_bytes >= ion) { pick = (int)i; break; }
+        bool grow = false;
+        if (pick < 0)
+            for (size_t i = 0; i < S->slots.size(); i++) {
+                const Slot &sl = S->slots[i];
+                if (sl.busy) continue;
+                unsigned long long after = S->arena_total - sl.arena_bytes - 2 * sl.io_bytes + need + 2 * ion;
+                if (!S->opt.hbm_budget_bytes || after <= S->opt.hbm_budget_bytes) { pick = (int)i; grow = true; break; }
+            }
+        if (pick < 0 && S->opt.hbm_budget_bytes) {
+            // room may be made by releasing the arenas of other idle slots
+            unsigned long long idle = 0;
+            int cand = -1;
+            for (size_t i = 0; i < S->slots.size(); i++)
+                if (!S->slots[i].busy) {
+                    idle += S->slots[i].arena_bytes + 2 * S->slots[i].io_bytes;
+                    if (cand < 0) cand = (int)i;
+                }
+            if (cand >= 0 && S->arena_total - idle + need + 2 * ion <= S->opt.hbm_budget_bytes) {
+                const Slot &cs = S->slots[cand];
+                for (size_t i = 0; i < S->slots.size(); i++) {
+                    if (S->arena_total - cs.arena_bytes - 2 * cs.io_bytes + need + 2 * ion <= S->opt.hbm_budget_bytes)
+                        break;
+                    Slot &sl = S->slots[i];
+                    if (sl.busy || (int)i == cand || !sl.arena_bytes) continue;
+                    (void)hipFree(sl.arena);
+                    (void)hipFree(sl.xb);
+                    (void)hipFree(sl.yb);
+                    sl.arena = sl.xb = sl.yb = nullptr;
+                    S->arena_total -= sl.arena_bytes + 2 * sl.io_bytes;
+                    sl.arena_bytes = sl.io_bytes = 0;
+                }
+                pick = cand;
+                grow = true;
+            }
+        }
+        if (pick < 0) {
+            bool any_busy = false;
+            for (auto &sl : S->slots) any_busy |= sl.busy;
+            if (!any_busy) {          // can never fit: fail the request
+                S->queue.pop_front();
+                r0->state = MLFMA_ERR_OOM;
+                r0->t_done = Clock::now();
+                S->cv_done.notify_all();
+                continue;
+            }
+            S->cv_sched.wait(lk);     // admitted when a slot frees
+            continue;
+        }
+        // merge queued requests of the same geometry, op and dtype
+        std::vector<Request *> batch;
+        int total = 0;
+        for (auto it = S->queue.begin(); it != S->queue.end();) {
+            Request *r = *it;
+            if (r->h == h && r->op == r0->op && r->dtype == r0->dtype && total + r->nrhs <= maxb) {
+                batch.push_back(r);
+                total += r->nrhs;
+                it = S->queue.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        Slot &slot = S->slots[pick];
+        slot.busy = true;
+        const auto now = Clock::now();
+        for (Request *r : batch) {
+            r->state = 1;
+            r->t_start = now;
+            r->batch_rhs = total;
+        }
+        lk.unlock();
+        int err = 0;
+        try {
+            if (grow) {
+                if (slot.arena) (void)hipFree(slot.arena);
+                if (slot.xb) (void)hipFree(slot.xb);
+                if (slot.yb) (void)hipFree(slot.yb);
+                slot.arena = slot.xb = slot.yb = nullptr;
+                lk.lock();
+                S->arena_total -= slot.arena_bytes + 2 * slot.io_bytes;
+                slot.arena_bytes = slot.io_bytes = 0;
+                lk.unlock();
+                HIPCHK(hipMalloc((void **)&slot.arena, need));
+                HIPCHK(hipMalloc((void **)&slot.xb, ion));
+                HIPCHK(hipMalloc((void **)&slot.yb, ion));
+                lk.lock();
+                slot.arena_bytes = need;
+                slot.io_bytes = ion;
+                S->arena_total += need + 2 * ion;
+                lk.unlock();
+            }
+            launch_batch(S, slot, batch, total);
+        } catch (const Error &e) {
+            err = e.code;
+            lk.lock();
+            S->thread_error = e.what();
+            lk.unlock();
+        }
+        lk.lock();
+        S->launches++;
+        S->batched_requests += (long long)batch.size();
+        if (err) {
+            for (Request *r : batch) {
+                r->state = err;
+                r->t_done = Clock::now();
+            }
+            slot.busy = false;
+            S->cv_done.notify_all();
+        } else {
+            slot.reqs = batch;
+        }
+    }
+}
+
+void poller_loop(mlfma_server_s *S)
+{
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (!S->stop) {
+        bool any = false;
+        for (auto &sl : S->slots) {
+            if (!sl.busy || sl.reqs.empty()) continue;
+            any = true;
+            hipError_t q = hipEventQuery(sl.done);
+            if (q == hipErrorNotReady) continue;
+            const auto now = Clock::now();
+            for (Request *r : sl.reqs) {
+                r->state = q == hipSuccess ? 2 : MLFMA_ERR_HIP;
+                r->t_done = now;
+            }
+            sl.reqs.clear();
+            sl.busy = false;
+            S->cv_done.notify_all();
+            S->cv_sched.notify_all();
+        }
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(any ? 20 : 200));
+        lk.lock();
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mlfma_server_opts_default(mlfma_server_opts *o)
+{
+    if (!o) return MLFMA_ERR_ARG;
+    o->streams = 4;
+    o->max_batch_rhs = 16;
+    o->device = -1;
+    o->hbm_budget_bytes = 0;
+    return MLFMA_OK;
+}
+
+int mlfma_server_create(const mlfma_server_opts *opt, mlfma_server *out)
+{
+    g_last_error.clear();
+    if (!out) return fail(Error(MLFMA_ERR_ARG, "NULL output"));
+    *out = nullptr;
+    try {
+        std::unique_ptr<mlfma_server_s> S(new mlfma_server_s());
+        if (opt) S->opt = *opt;
+        else mlfma_server_opts_default(&S->opt);
+        if (S->opt.streams < 1 || S->opt.streams > 16 || S->opt.max_batch_rhs < 1)
+            throw Error(MLFMA_ERR_ARG, "streams must be 1..16 and max_batch_rhs >= 1");
+        int dev = S->opt.device;
+        if (dev < 0) HIPCHK(hipGetDevice(&dev));
+        S->device = dev;
+        DeviceGuard g(dev);
+        S->slots.resize(S->opt.streams);
+        for (auto &sl : S->slots) {
+            HIPCHK(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+        }
+        mlfma_server_s *raw = S.get();
+        S->sched = std::thread(scheduler_loop, raw);
+        S->poll = std::thread(poller_loop, raw);
+        *out = S.release();
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int mlfma_server_submit(mlfma_server s, mlfma_handle h, int op, int dtype, long long nrhs, const void *x,
+                        long long ldx, void *y, long long ldy, long long *ticket)
+{
+    g_last_error.clear();
+    if (!s || !h || !ticket) return fail(Error(MLFMA_ERR_ARG, "NULL argument"));
+    if (!h->near_ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_precompute_nearfield has not been called"));
+    if (op != MLFMA_OP_C && op != MLFMA_OP_EM) return fail(Error(MLFMA_ERR_ARG, "unknown op"));
+    if (dtype != MLFMA_C128 && dtype != MLFMA_C64) return fail(Error(MLFMA_ERR_ARG, "unknown dtype"));
+    if (h->device != s->device) return fail(Error(MLFMA_ERR_ARG, "geometry lives on another device"));
+    const long long N2 = 2LL * h->r.n;
+    if (nrhs < 1 || nrhs > (1 << 16) || !x || !y || ldx < N2 || ldy < N2)
+        return fail(Error(MLFMA_ERR_ARG, "bad nrhs, pointer or leading dimension"));
+    Request *r = new Request();
+    r->h = h;
+    r->op = op;
+    r->dtype = dtype;
+    r->nrhs = (int)nrhs;
+    r->x = x;
+    r->y = y;
+    r->ldx = ldx;
+    r->ldy = ldy;
+    r->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        r->ticket = s->next_ticket++;
+        s->reqs[r->ticket] = r;
+        s->queue.push_back(r);
+    }
+    s->cv_sched.notify_all();
+    *ticket = r->ticket;
+    return MLFMA_OK;
+}
+
+int mlfma_server_wait(mlfma_server s, long long ticket, double timeout_s, double *latency_s, int *batch_rhs)
+{
+    g_last_error.clear();
+    if (!s) return fail(Error(MLFMA_ERR_ARG, "NULL server"));
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(Error(MLFMA_ERR_ARG, "unknown ticket"));
+    Request *r = it->second;
+    auto pred = [&] { return r->state == 2 || r->state < 0; };
+    if (timeout_s < 0) s->cv_done.wait(lk, pred);
+    else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred))
+        return fail(Error(MLFMA_ERR_STATE, "request not finished within the timeout"));
+    const int st = r->state;
+    if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+    if (batch_rhs) *batch_rhs = r->batch_rhs;
+    s->reqs.erase(it);
+    std::string why = s->thread_error;
+    delete r;
+    if (st < 0) return fail(Error(st, why.empty() ? "request failed" : why));
+    return MLFMA_OK;
+}
+
+int mlfma_server_stats(mlfma_server s, long long out[4])
+{
+    if (!s || !out) return fail(Error(MLFMA_ERR_ARG, "NULL argument"));
+    std::lock_guard<std::mutex> lk(s->mu);
+    out[0] = s->launches;
+    out[1] = s->batched_requests;
+    out[2] = (long long)s->arena_total;
+    out[3] = (long long)s->queue.size();
+    return MLFMA_OK;
+}
+
+int mlfma_server_destroy(mlfma_server s)
+{
+    if (!s) return MLFMA_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_sched.notify_all();
+    s->cv_done.notify_all();
+    if (s->sched.joinable()) s->sched.join();
+    if (s->poll.joinable()) s->poll.join();
+    {
+        DeviceGuard g(s->device);
+        for (auto &sl : s->slots) {
+            if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+            if (sl.arena) (void)hipFree(sl.arena);
+            if (sl.xb) (void)hipFree(sl.xb);
+            if (sl.yb) (void)hipFree(sl.yb);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        }
+    }
+    for (auto &kv : s->reqs) delete kv.second;
+    delete s;
     return MLFMA_OK;
 }
 

@@ -40,9 +40,9 @@ void launch_perm_in(const cpx<T> *x, long long ldx, cpx<T> *X, const int *perm, 
 template <class T>
 void launch_perm_out(const cpx<T> *Y, cpx<T> *y, long long ldy, const int *iperm, int N, int nrhs, hipStream_t s);
 template <class T>
-void launch_near(int nbox, const int *box_start, const int *near_start, const int *near_box, const long long *val_off,
-                 const int *ncols, const cpx<T> *vals, const int *id_start, const int *id_col, const T *id_w,
-                 const cpx<T> *X, cpx<T> *Y, int nrhs, int max_near, hipStream_t s);
+void launch_near(int N, const int *leaf_of, const int *box_start, const int *near_start, const int *near_box,
+                 const long long *val_off, const cpx<T> *vals, const int *id_start, const int *id_col, const T *id_w,
+                 const cpx<T> *X, cpx<T> *Y, int nrhs, hipStream_t s);
 template <class T>
 void launch_radiate(int op, int nbox, int K, const int *box_start, const cpx<T> *R, const cpx<T> *X, cpx<T> *U,
                     int nrhs, hipStream_t s);

@@ -1,8 +1,11 @@
 // Hot-path kernels of the MLFMA matvec for CDNA4 (gfx950, wave64).
 //
 // Vector layout inside the library: X[rwg][half][rhs] (rwg in Morton order,
-// half 0 = J or E side, 1 = M or H side, rhs innermost).  Box patterns:
-// U[box][sample][component][rhs] with component 0 = theta, 1 = phi.
+// half 0 = J or E side, 1 = M or H side, rhs innermost).  Box patterns and
+// stencil intermediates are sample-innermost: U[box][component][rhs][sample]
+// with component 0 = theta, 1 = phi, so that the threads of a wave, which
+// take consecutive samples, read and write consecutive addresses for every
+// right-hand side.
 // Every kernel is templated on the arithmetic type T (double or float) and
 // on NR, the number of right-hand sides handled per thread (rhs chunk).
 #include "device.hpp"
@@ -26,6 +29,27 @@ __device__ inline cpx<T> wave_sum(cpx<T> v)
 }
 
 static inline int nr_for(int nrhs) { return nrhs <= 1 ? 1 : (nrhs <= 4 ? 4 : 16); }
+
+// element (box b, component c, rhs r, sample q) of a pattern array with K
+// samples per box and nrhs right-hand sides
+__device__ inline long long pidx(long long b, int c, int r, int q, int nrhs, int K)
+{
+    return ((b * 2 + c) * nrhs + r) * (long long)K + q;
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin (hardware block b runs
+// on XCD b mod 8).  Remapping gives every XCD one contiguous range of logical
+// blocks, so neighbouring boxes (Morton order) share that XCD's L2.  The grid
+// is padded to a multiple of 8; padding blocks return -1.
+constexpr int NXCD = 8;
+__device__ inline long long xcd_block(long long nblk)
+{
+    const long long per = (nblk + NXCD - 1) / NXCD;
+    const long long hw = blockIdx.x;
+    const long long lb = (hw % NXCD) * per + hw / NXCD;
+    return lb < nblk ? lb : -1;
+}
+static inline unsigned xcd_grid(long long nblk) { return (unsigned)(((nblk + NXCD - 1) / NXCD) * NXCD); }
 
 // ------------------------------------------------------------------ permute
 template <class T>
@@ -65,70 +89,183 @@ __global__ void k_perm_out(const cpx<T> *__restrict__ Y, cpx<T> *__restrict__ y,
 // whose Gram terms are the short per-row identity list (gram, gx):
 //   y1 += gram x1 + gx x2 / 2,  y2 += gram x2 / 2.
 template <class T, int NR>
-__global__ __launch_bounds__(256) void k_near(const int *__restrict__ box_start, const int *__restrict__ near_start,
-                                              const int *__restrict__ near_box, const long long *__restrict__ val_off,
-                                              const cpx<T> *__restrict__ vals, const int *__restrict__ id_start,
-                                              const int *__restrict__ id_col, const T *__restrict__ id_w,
-                                              const cpx<T> *__restrict__ X, cpx<T> *__restrict__ Y, int nrhs)
+__global__ __launch_bounds__(256) void k_near(int N, const int *__restrict__ leaf_of, const int *__restrict__ box_start,
+                                              const int *__restrict__ near_start, const int *__restrict__ near_box,
+                                              const long long *__restrict__ val_off, const cpx<T> *__restrict__ vals,
+                                              const int *__restrict__ id_start, const int *__restrict__ id_col,
+                                              const T *__restrict__ id_w, const cpx<T> *__restrict__ X,
+                                              cpx<T> *__restrict__ Y, int nrhs)
 {
-    __shared__ int cstart[32];
-    __shared__ int pre[33];
-    const int b = blockIdx.x;
+    // one wave per output row m; the row's columns are the concatenated RWG
+    // ranges of the <= 27 boxes adjacent to its leaf box
+    __shared__ int cs_all[4][32], pre_all[4][33];
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const long long blk = xcd_block((N + 3) / 4);
+    if (blk < 0) return;                        // whole (padding) workgroup
+    const int m = (int)(blk * 4 + wave);
+    const bool valid = m < N;                   // every wave reaches the barrier
     const int r0 = blockIdx.y * NR;
-    const int nn = near_start[b + 1] - near_start[b];
-    if (threadIdx.x == 0) {
-        pre[0] = 0;
-        for (int q = 0; q < nn; q++) {
-            int nb = near_box[near_start[b] + q];
-            cstart[q] = box_start[nb];
-            pre[q + 1] = pre[q] + box_start[nb + 1] - box_start[nb];
+    int *cstart = cs_all[wave], *pre = pre_all[wave];
+    const int b = valid ? leaf_of[m] : 0;
+    const int nn = valid ? near_start[b + 1] - near_start[b] : 0;
+    int cnt = 0, st = 0;
+    if (lane < nn) {
+        const int nb = near_box[near_start[b] + lane];
+        st = box_start[nb];
+        cnt = box_start[nb + 1] - st;
+    }
+    // inclusive prefix sum of the column counts across the wave
+    int inc = cnt;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+        const int v = __shfl_up(inc, d, WAVE);
+        if (lane >= d) inc += v;
+    }
+    if (lane < nn) {
+        cstart[lane] = st;
+        pre[lane + 1] = inc;
+    }
+    if (lane == 0) pre[0] = 0;
+    __syncthreads();
+    if (!valid) return;
+    const int ncols = pre[nn];
+    const int mr = m - box_start[b];
+    const cpx<T> *vrow = vals + 2 * (val_off[b] + (long long)mr * ncols);
+    cpx<T> a1[NR], a2[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) a1[rr] = a2[rr] = mk<T>(0, 0);
+    int q = 0;
+    for (int j = lane; j < ncols; j += WAVE) {
+        while (j >= pre[q + 1]) q++;
+        const long long col = cstart[q] + (j - pre[q]);
+        const cpx<T> A = vrow[2 * j], B = vrow[2 * j + 1];
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            if (NR > 1 && r0 + rr >= nrhs) continue;
+            const cpx<T> x1 = X[(col * 2) * nrhs + r0 + rr], x2 = X[(col * 2 + 1) * nrhs + r0 + rr];
+            a1[rr] = a1[rr] + A * x1 - B * x2;
+            a2[rr] = a2[rr] + A * x2 + B * x1;
         }
     }
-    __syncthreads();
-    const int ncols = pre[nn];
-    const int m0 = box_start[b], nb_rows = box_start[b + 1] - m0;
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    for (int mr = wave; mr < nb_rows; mr += blockDim.x / WAVE) {
-        const cpx<T> *vrow = vals + 2 * (val_off[b] + (long long)mr * ncols);
-        cpx<T> a1[NR], a2[NR];
-#pragma unroll
-        for (int rr = 0; rr < NR; rr++) a1[rr] = a2[rr] = mk<T>(0, 0);
-        int q = 0;
-        for (int j = lane; j < ncols; j += WAVE) {
-            while (j >= pre[q + 1]) q++;
-            const long long col = cstart[q] + (j - pre[q]);
-            const cpx<T> A = vrow[2 * j], B = vrow[2 * j + 1];
+    if (id_start) {
+        const int e = id_start[m] + lane;
+        if (e < id_start[m + 1]) {
+            const long long col = id_col[e];
+            const T g = id_w[2 * e], gx = id_w[2 * e + 1];
 #pragma unroll
             for (int rr = 0; rr < NR; rr++) {
                 if (NR > 1 && r0 + rr >= nrhs) continue;
                 const cpx<T> x1 = X[(col * 2) * nrhs + r0 + rr], x2 = X[(col * 2 + 1) * nrhs + r0 + rr];
-                a1[rr] = a1[rr] + A * x1 - B * x2;
-                a2[rr] = a2[rr] + A * x2 + B * x1;
+                a1[rr] = a1[rr] + g * x1 + (T(0.5) * gx) * x2;
+                a2[rr] = a2[rr] + (T(0.5) * g) * x2;
             }
         }
-        const int m = m0 + mr;
-        if (id_start) {
-            const int e = id_start[m] + lane;
-            if (e < id_start[m + 1]) {
-                const long long col = id_col[e];
-                const T g = id_w[2 * e], gx = id_w[2 * e + 1];
+    }
 #pragma unroll
-                for (int rr = 0; rr < NR; rr++) {
-                    if (NR > 1 && r0 + rr >= nrhs) continue;
-                    const cpx<T> x1 = X[(col * 2) * nrhs + r0 + rr], x2 = X[(col * 2 + 1) * nrhs + r0 + rr];
-                    a1[rr] = a1[rr] + g * x1 + (T(0.5) * gx) * x2;
-                    a2[rr] = a2[rr] + (T(0.5) * g) * x2;
-                }
-            }
+    for (int rr = 0; rr < NR; rr++) {
+        const cpx<T> s1 = wave_sum(a1[rr]), s2 = wave_sum(a2[rr]);
+        if (lane == 0 && (NR == 1 || r0 + rr < nrhs)) {
+            Y[((long long)m * 2) * nrhs + r0 + rr] = s1;
+            Y[((long long)m * 2 + 1) * nrhs + r0 + rr] = s2;
         }
+    }
+}
+
+// Broadcast lane `src` of a wave (uniform src) through the scalar unit.
+__device__ inline float bcast(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ inline double bcast(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline int bcast(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+
+// Near field for many right-hand sides: one wave per output row, lane = one
+// right-hand side of a chunk of 64.  The row's (A, B) pairs and column
+// indices are loaded 64 at a time (one per lane, coalesced) and broadcast
+// through the scalar unit; every x load is coalesced over the lanes (rhs is
+// innermost in X), and each lane accumulates its own outputs.
+template <class T>
+__global__ __launch_bounds__(256) void k_near_rhs(int N, const int *__restrict__ leaf_of,
+                                                  const int *__restrict__ box_start, const int *__restrict__ near_start,
+                                                  const int *__restrict__ near_box, const long long *__restrict__ val_off,
+                                                  const cpx<T> *__restrict__ vals, const int *__restrict__ id_start,
+                                                  const int *__restrict__ id_col, const T *__restrict__ id_w,
+                                                  const cpx<T> *__restrict__ X, cpx<T> *__restrict__ Y, int nrhs)
+{
+    __shared__ int cs_all[4][32], pre_all[4][33];
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const long long blk = xcd_block((N + 3) / 4);
+    if (blk < 0) return;
+    const int m = (int)(blk * 4 + wave);
+    const bool valid = m < N;
+    int *cstart = cs_all[wave], *pre = pre_all[wave];
+    const int b = valid ? leaf_of[m] : 0;
+    const int nn = valid ? near_start[b + 1] - near_start[b] : 0;
+    int cnt = 0, st = 0;
+    if (lane < nn) {
+        const int nb = near_box[near_start[b] + lane];
+        st = box_start[nb];
+        cnt = box_start[nb + 1] - st;
+    }
+    int inc = cnt;
 #pragma unroll
-        for (int rr = 0; rr < NR; rr++) {
-            const cpx<T> s1 = wave_sum(a1[rr]), s2 = wave_sum(a2[rr]);
-            if (lane == 0 && (NR == 1 || r0 + rr < nrhs)) {
-                Y[((long long)m * 2) * nrhs + r0 + rr] = s1;
-                Y[((long long)m * 2 + 1) * nrhs + r0 + rr] = s2;
+    for (int d = 1; d < 32; d <<= 1) {
+        const int v = __shfl_up(inc, d, WAVE);
+        if (lane >= d) inc += v;
+    }
+    if (lane < nn) {
+        cstart[lane] = st;
+        pre[lane + 1] = inc;
+    }
+    if (lane == 0) pre[0] = 0;
+    __syncthreads();
+    if (!valid) return;
+    const int ncols = pre[nn];
+    const int mr = m - box_start[b];
+    const cpx<T> *vrow = vals + 2 * (val_off[b] + (long long)mr * ncols);
+    const int r = blockIdx.y * WAVE + lane;
+    const bool act = r < nrhs;
+    cpx<T> y1 = mk<T>(0, 0), y2 = mk<T>(0, 0);
+    int q = 0;
+    for (int j0 = 0; j0 < ncols; j0 += WAVE) {
+        const int j = j0 + lane;
+        cpx<T> A = mk<T>(0, 0), B = mk<T>(0, 0);
+        int col = 0;
+        if (j < ncols) {
+            while (j >= pre[q + 1]) q++;
+            col = cstart[q] + (j - pre[q]);
+            A = vrow[2 * j];
+            B = vrow[2 * j + 1];
+        }
+        const int cnt_j = ncols - j0 < WAVE ? ncols - j0 : WAVE;
+        for (int jj = 0; jj < cnt_j; jj++) {
+            const cpx<T> a = {bcast(A.re, jj), bcast(A.im, jj)}, bb = {bcast(B.re, jj), bcast(B.im, jj)};
+            const long long c = bcast(col, jj);
+            if (act) {
+                const cpx<T> x1 = X[(c * 2) * nrhs + r], x2 = X[(c * 2 + 1) * nrhs + r];
+                y1 = y1 + a * x1 - bb * x2;
+                y2 = y2 + a * x2 + bb * x1;
             }
         }
+    }
+    if (id_start && act) {
+        for (int e = id_start[m]; e < id_start[m + 1]; e++) {
+            const long long c = id_col[e];
+            const T g = id_w[2 * e], gx = id_w[2 * e + 1];
+            const cpx<T> x1 = X[(c * 2) * nrhs + r], x2 = X[(c * 2 + 1) * nrhs + r];
+            y1 = y1 + g * x1 + (T(0.5) * gx) * x2;
+            y2 = y2 + (T(0.5) * g) * x2;
+        }
+    }
+    if (act) {
+        Y[((long long)m * 2) * nrhs + r] = y1;
+        Y[((long long)m * 2 + 1) * nrhs + r] = y2;
     }
 }
 
@@ -169,13 +306,14 @@ __global__ __launch_bounds__(256) void k_radiate(int op, int nbox, int K, const 
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) {
         if (NR > 1 && r0 + rr >= nrhs) continue;
-        U[((g * 2) * nrhs) + r0 + rr] = ut[rr];
-        U[((g * 2 + 1) * nrhs) + r0 + rr] = up[rr];
+        U[pidx(b, 0, r0 + rr, q, nrhs, K)] = ut[rr];
+        U[pidx(b, 1, r0 + rr, q, nrhs, K)] = up[rr];
     }
 }
 
 // ------------------------------------------------- sparse stencil (per box)
-// out[box][row] (=, +=) sum_e w_e in[box][col_e], both components, all rhs.
+// out[box][row] (=, +=) sum_e w_e in[box][col_e], both components, all rhs
+// (in has in_len samples per box, out has rows).
 template <class T, int NR>
 __global__ __launch_bounds__(256) void k_interp(int nbox, int rows, int in_len, const int *__restrict__ st,
                                                 const int *__restrict__ col, const T *__restrict__ w,
@@ -189,22 +327,21 @@ __global__ __launch_bounds__(256) void k_interp(int nbox, int rows, int in_len, 
     cpx<T> a0[NR], a1[NR];
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) a0[rr] = a1[rr] = mk<T>(0, 0);
-    const long long base = (long long)box * in_len;
     for (int e = st[row]; e < st[row + 1]; e++) {
         const T we = w[e];
-        const long long src = (base + col[e]) * 2;
+        const int c = col[e];
 #pragma unroll
         for (int rr = 0; rr < NR; rr++) {
             if (NR > 1 && r0 + rr >= nrhs) continue;
-            a0[rr] = a0[rr] + we * in[src * nrhs + r0 + rr];
-            a1[rr] = a1[rr] + we * in[(src + 1) * nrhs + r0 + rr];
+            a0[rr] = a0[rr] + we * in[pidx(box, 0, r0 + rr, c, nrhs, in_len)];
+            a1[rr] = a1[rr] + we * in[pidx(box, 1, r0 + rr, c, nrhs, in_len)];
         }
     }
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) {
         if (NR > 1 && r0 + rr >= nrhs) continue;
-        cpx<T> *o0 = &out[(g * 2) * nrhs + r0 + rr];
-        cpx<T> *o1 = &out[(g * 2 + 1) * nrhs + r0 + rr];
+        cpx<T> *o0 = &out[pidx(box, 0, r0 + rr, row, nrhs, rows)];
+        cpx<T> *o1 = &out[pidx(box, 1, r0 + rr, row, nrhs, rows)];
         if (accumulate) {
             *o0 = *o0 + a0[rr];
             *o1 = *o1 + a1[rr];
@@ -235,15 +372,14 @@ __global__ __launch_bounds__(256) void k_agg_phi(int nparent, int Kp, int mid_le
         cpx<T> s0[NR], s1[NR];
 #pragma unroll
         for (int rr = 0; rr < NR; rr++) s0[rr] = s1[rr] = mk<T>(0, 0);
-        const long long base = (long long)c * mid_len;
         for (int e = st[q]; e < st[q + 1]; e++) {
             const T we = w[e];
-            const long long src = (base + col[e]) * 2;
+            const int cc = col[e];
 #pragma unroll
             for (int rr = 0; rr < NR; rr++) {
                 if (NR > 1 && r0 + rr >= nrhs) continue;
-                s0[rr] = s0[rr] + we * mid[src * nrhs + r0 + rr];
-                s1[rr] = s1[rr] + we * mid[(src + 1) * nrhs + r0 + rr];
+                s0[rr] = s0[rr] + we * mid[pidx(c, 0, r0 + rr, cc, nrhs, mid_len)];
+                s1[rr] = s1[rr] + we * mid[pidx(c, 1, r0 + rr, cc, nrhs, mid_len)];
             }
         }
         const cpx<T> sh = shift[(long long)child_oct[c] * Kp + q];
@@ -256,41 +392,75 @@ __global__ __launch_bounds__(256) void k_agg_phi(int nparent, int Kp, int mid_le
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) {
         if (NR > 1 && r0 + rr >= nrhs) continue;
-        Up[(g * 2) * nrhs + r0 + rr] = a0[rr];
-        Up[(g * 2 + 1) * nrhs + r0 + rr] = a1[rr];
+        Up[pidx(P, 0, r0 + rr, q, nrhs, Kp)] = a0[rr];
+        Up[pidx(P, 1, r0 + rr, q, nrhs, Kp)] = a1[rr];
     }
 }
 
 // ---------------------------------------------------------------- translation
 // V_A(k) = sum_{(B, o) in IL(A)} T_o(k) U_B(k)   (diagonal in k)
-template <class T, int NR>
+// One thread per (target box, sample); consecutive threads take consecutive
+// samples of one box, so the operator and pattern loads are coalesced for
+// every right-hand side.  The interaction-list loop is unrolled UNR deep so
+// that UNR independent (index, operator, pattern) load chains are in flight.
+template <class T, int NR, int UNR>
 __global__ __launch_bounds__(256) void k_translate(int nbox, int K, const int *__restrict__ il_start,
                                                    const int *__restrict__ il_box, const int *__restrict__ il_off,
                                                    const cpx<T> *__restrict__ trans, const cpx<T> *__restrict__ U,
                                                    cpx<T> *__restrict__ V, int nrhs)
 {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long blk = xcd_block(((long long)nbox * K + blockDim.x - 1) / blockDim.x);
+    if (blk < 0) return;
+    const long long g = blk * blockDim.x + threadIdx.x;
     if (g >= (long long)nbox * K) return;
     const int A = (int)(g / K), q = (int)(g % K);
     const int r0 = blockIdx.y * NR;
     cpx<T> a0[NR], a1[NR];
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) a0[rr] = a1[rr] = mk<T>(0, 0);
-    for (int e = il_start[A]; e < il_start[A + 1]; e++) {
-        const cpx<T> t = trans[(long long)il_off[e] * K + q];
-        const long long src = ((long long)il_box[e] * K + q) * 2;
+    const int e0 = il_start[A], e1 = il_start[A + 1];
+    int e = e0;
+    for (; e + UNR <= e1; e += UNR) {
+        int off[UNR], B[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            off[u] = il_off[e + u];
+            B[u] = il_box[e + u];
+        }
+        cpx<T> t[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; u++) t[u] = trans[(long long)off[u] * K + q];
 #pragma unroll
         for (int rr = 0; rr < NR; rr++) {
             if (NR > 1 && r0 + rr >= nrhs) continue;
-            fma_to(a0[rr], t, U[src * nrhs + r0 + rr]);
-            fma_to(a1[rr], t, U[(src + 1) * nrhs + r0 + rr]);
+            cpx<T> u0[UNR], u1[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                u0[u] = U[pidx(B[u], 0, r0 + rr, q, nrhs, K)];
+                u1[u] = U[pidx(B[u], 1, r0 + rr, q, nrhs, K)];
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                fma_to(a0[rr], t[u], u0[u]);
+                fma_to(a1[rr], t[u], u1[u]);
+            }
+        }
+    }
+    for (; e < e1; e++) {
+        const cpx<T> t = trans[(long long)il_off[e] * K + q];
+        const int B = il_box[e];
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            if (NR > 1 && r0 + rr >= nrhs) continue;
+            fma_to(a0[rr], t, U[pidx(B, 0, r0 + rr, q, nrhs, K)]);
+            fma_to(a1[rr], t, U[pidx(B, 1, r0 + rr, q, nrhs, K)]);
         }
     }
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) {
         if (NR > 1 && r0 + rr >= nrhs) continue;
-        V[(g * 2) * nrhs + r0 + rr] = a0[rr];
-        V[(g * 2 + 1) * nrhs + r0 + rr] = a1[rr];
+        V[pidx(A, 0, r0 + rr, q, nrhs, K)] = a0[rr];
+        V[pidx(A, 1, r0 + rr, q, nrhs, K)] = a1[rr];
     }
 }
 
@@ -315,19 +485,18 @@ __global__ __launch_bounds__(256) void k_disagg_mid(int nchild, int mid_len, int
     for (int e = st[row]; e < st[row + 1]; e++) {
         const int kp = col[e];
         const cpx<T> f = w[e] * conjg(sh[kp]);
-        const long long src = ((long long)P * Kp + kp) * 2;
 #pragma unroll
         for (int rr = 0; rr < NR; rr++) {
             if (NR > 1 && r0 + rr >= nrhs) continue;
-            fma_to(a0[rr], f, Vp[src * nrhs + r0 + rr]);
-            fma_to(a1[rr], f, Vp[(src + 1) * nrhs + r0 + rr]);
+            fma_to(a0[rr], f, Vp[pidx(P, 0, r0 + rr, kp, nrhs, Kp)]);
+            fma_to(a1[rr], f, Vp[pidx(P, 1, r0 + rr, kp, nrhs, Kp)]);
         }
     }
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) {
         if (NR > 1 && r0 + rr >= nrhs) continue;
-        mid[(g * 2) * nrhs + r0 + rr] = a0[rr];
-        mid[(g * 2 + 1) * nrhs + r0 + rr] = a1[rr];
+        mid[pidx(c, 0, r0 + rr, row, nrhs, mid_len)] = a0[rr];
+        mid[pidx(c, 1, r0 + rr, row, nrhs, mid_len)] = a1[rr];
     }
 }
 
@@ -359,11 +528,10 @@ __global__ __launch_bounds__(256) void k_receive(int op, int N, int K, const int
         const T wk = wq[q];
         Pt = wk * Pt;
         Pp = wk * Pp;
-        const long long src = ((long long)b * K + q) * 2;
 #pragma unroll
         for (int rr = 0; rr < NR; rr++) {
             if (NR > 1 && r0 + rr >= nrhs) continue;
-            const cpx<T> Vt = V[src * nrhs + r0 + rr], Vp = V[(src + 1) * nrhs + r0 + rr];
+            const cpx<T> Vt = V[pidx(b, 0, r0 + rr, q, nrhs, K)], Vp = V[pidx(b, 1, r0 + rr, q, nrhs, K)];
             a1[rr] = a1[rr] + Pt * Vt + Pp * Vp;
             a2[rr] = a2[rr] + Pp * Vt - Pt * Vp;
         }
@@ -413,14 +581,20 @@ void launch_perm_out(const cpx<T> *Y, cpx<T> *y, long long ldy, const int *iperm
     } while (0)
 
 template <class T>
-void launch_near(int nbox, const int *box_start, const int *near_start, const int *near_box, const long long *val_off,
-                 const int *, const cpx<T> *vals, const int *id_start, const int *id_col, const T *id_w,
-                 const cpx<T> *X, cpx<T> *Y, int nrhs, int, hipStream_t s)
+void launch_near(int N, const int *leaf_of, const int *box_start, const int *near_start, const int *near_box,
+                 const long long *val_off, const cpx<T> *vals, const int *id_start, const int *id_col, const T *id_w,
+                 const cpx<T> *X, cpx<T> *Y, int nrhs, hipStream_t s)
 {
+    if (nrhs >= 16) {
+        dim3 grid(xcd_grid((N + 3) / 4), (nrhs + WAVE - 1) / WAVE);
+        hipLaunchKernelGGL(k_near_rhs<T>, grid, dim3(256), 0, s, N, leaf_of, box_start, near_start, near_box,
+                           val_off, vals, id_start, id_col, id_w, X, Y, nrhs);
+        return;
+    }
     DISPATCH_NR(nrhs, {
-        dim3 grid(nbox, (nrhs + NR - 1) / NR);
-        hipLaunchKernelGGL((k_near<T, NR>), grid, dim3(256), 0, s, box_start, near_start, near_box, val_off, vals,
-                           id_start, id_col, id_w, X, Y, nrhs);
+        dim3 grid(xcd_grid((N + 3) / 4), (nrhs + NR - 1) / NR);
+        hipLaunchKernelGGL((k_near<T, NR>), grid, dim3(256), 0, s, N, leaf_of, box_start, near_start, near_box,
+                           val_off, vals, id_start, id_col, id_w, X, Y, nrhs);
     });
 }
 
@@ -462,9 +636,13 @@ void launch_translate(int nbox, int K, const int *il_start, const int *il_box, c
                       const cpx<T> *trans, const cpx<T> *U, cpx<T> *V, int nrhs, hipStream_t s)
 {
     DISPATCH_NR(nrhs, {
-        dim3 grid(blocks_for((long long)nbox * K, 256), (nrhs + NR - 1) / NR);
-        hipLaunchKernelGGL((k_translate<T, NR>), grid, dim3(256), 0, s, nbox, K, il_start, il_box, il_off, trans, U,
-                           V, nrhs);
+        dim3 grid(xcd_grid(blocks_for((long long)nbox * K, 256)), (nrhs + NR - 1) / NR);
+        if (NR <= 4)
+            hipLaunchKernelGGL((k_translate<T, NR, 4>), grid, dim3(256), 0, s, nbox, K, il_start, il_box, il_off,
+                               trans, U, V, nrhs);
+        else
+            hipLaunchKernelGGL((k_translate<T, NR, 2>), grid, dim3(256), 0, s, nbox, K, il_start, il_box, il_off,
+                               trans, U, V, nrhs);
     });
 }
 
@@ -499,9 +677,9 @@ void launch_receive(int op, int N, int K, const int *leaf_of, const cpx<T> *R, c
 #define INSTANTIATE(T)                                                                                              \
     template void launch_perm_in<T>(const cpx<T> *, long long, cpx<T> *, const int *, int, int, hipStream_t);     \
     template void launch_perm_out<T>(const cpx<T> *, cpx<T> *, long long, const int *, int, int, hipStream_t);    \
-    template void launch_near<T>(int, const int *, const int *, const int *, const long long *, const int *,     \
+    template void launch_near<T>(int, const int *, const int *, const int *, const int *, const long long *,     \
                                  const cpx<T> *, const int *, const int *, const T *, const cpx<T> *, cpx<T> *, \
-                                 int, int, hipStream_t);                                                          \
+                                 int, hipStream_t);                                                               \
     template void launch_radiate<T>(int, int, int, const int *, const cpx<T> *, const cpx<T> *, cpx<T> *, int,   \
                                     hipStream_t);                                                                 \
     template void launch_interp<T>(int, int, int, const int *, const int *, const T *, const cpx<T> *, cpx<T> *, \

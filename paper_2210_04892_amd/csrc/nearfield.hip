@@ -336,7 +336,62 @@ __global__ void k_to_float(const cpx<double> *__restrict__ a, cpx<float> *__rest
     if (g < n) b[g] = {(float)a[g].re, (float)a[g].im};
 }
 
+// ------------------------------------------------------------- plane waves
+// b^J = <f, E/2 + n x H/2>, b^M = <f, H/2 - n x E/2>, E = p e^{-jk khat.r},
+// H = khat x p e^{-jk khat.r}; 7-point rule on both triangles of the RWG.
+template <class T>
+__global__ void k_plane_wave(int N, int nrhs, double k, const int *__restrict__ perm, const int *__restrict__ rtri,
+                             const int *__restrict__ rloc, const double *__restrict__ rcoef,
+                             const double *__restrict__ tri_v, const double *__restrict__ tri_n,
+                             const double *__restrict__ tri_a, const double *__restrict__ dirs,
+                             cpx<T> *__restrict__ b, long long ldb)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)N * nrhs) return;
+    const int i = (int)(g % N), r = (int)(g / N);
+    const V3 kh = v3(dirs + 6 * r), p = v3(dirs + 6 * r + 3);
+    const V3 h = cross(kh, p);
+    cpx<double> bj{0, 0}, bm{0, 0};
+    for (int s = 0; s < 2; s++) {
+        const int t = rtri[2 * i + s];
+        const double cf = rcoef[2 * i + s] * tri_a[t];
+        const V3 P0 = v3(tri_v + 9LL * t), P1 = v3(tri_v + 9LL * t + 3), P2 = v3(tri_v + 9LL * t + 6);
+        const V3 pf = v3(tri_v + 9LL * t + 3 * rloc[2 * i + s]);
+        const V3 n = v3(tri_n + 3LL * t);
+        const V3 nxe = cross(n, p), nxh = cross(n, h);
+        for (int q = 0; q < 7; q++) {
+            double l0, l1, l2, w;
+            radon7(q, l0, l1, l2, w);
+            const V3 x = l0 * P0 + l1 * P1 + l2 * P2;
+            const V3 a = x - pf;
+            double sn, cs;
+            sincos(k * dot(kh, x), &sn, &cs);
+            const double fj = 0.5 * w * cf * (dot(a, p) + dot(a, nxh));
+            const double fm = 0.5 * w * cf * (dot(a, h) - dot(a, nxe));
+            bj.re += fj * cs; bj.im -= fj * sn;
+            bm.re += fm * cs; bm.im -= fm * sn;
+        }
+    }
+    const int u = perm[i];
+    b[(long long)r * ldb + u] = {(T)bj.re, (T)bj.im};
+    b[(long long)r * ldb + N + u] = {(T)bm.re, (T)bm.im};
+}
+
 // ---------------------------------------------------------------- launchers
+void launch_plane_wave(bool single, int N, int nrhs, double k, const int *perm, const int *rtri, const int *rloc,
+                       const double *rcoef, const double *tri_v, const double *tri_n, const double *tri_a,
+                       const double *dirs, void *b, long long ldb, hipStream_t s)
+{
+    long long n = (long long)N * nrhs;
+    dim3 grid((unsigned)((n + 255) / 256));
+    if (single)
+        hipLaunchKernelGGL(k_plane_wave<float>, grid, dim3(256), 0, s, N, nrhs, k, perm, rtri, rloc, rcoef, tri_v,
+                           tri_n, tri_a, dirs, (cpx<float> *)b, ldb);
+    else
+        hipLaunchKernelGGL(k_plane_wave<double>, grid, dim3(256), 0, s, N, nrhs, k, perm, rtri, rloc, rcoef, tri_v,
+                           tri_n, tri_a, dirs, (cpx<double> *)b, ldb);
+}
+
 void launch_patterns(int N, int K, int nph, const double *ct, double k, const int *rtri, const double *rcoef,
                      const int *rloc, const double *tri_v, const double *tri_n, const double *tri_a,
                      const double *centre, cpx<double> *R, cpx<double> *Q, hipStream_t s)

@@ -25,5 +25,10 @@ void launch_slots(int nbox, const int *box_start, const int *near_start, const i
                   const double *tri_a, const int *tp_start, const int *tp_s, const cpx<double> *touch, double k,
                   cpx<double> *em64, cpx<double> *c64, cpx<float> *em32, cpx<float> *c32, hipStream_t s);
 void launch_to_float(const cpx<double> *a, cpx<float> *b, long long n, hipStream_t s);
+// right-hand sides of eqs. 49-50 for plane waves, written in user RWG order
+// (dirs: nrhs x (khat, pol)); single = complex64 output, else complex128
+void launch_plane_wave(bool single, int N, int nrhs, double k, const int *perm, const int *rtri, const int *rloc,
+                       const double *rcoef, const double *tri_v, const double *tri_n, const double *tri_a,
+                       const double *dirs, void *b, long long ldb, hipStream_t s);
 
 }  // namespace mlfma

@@ -1,0 +1,153 @@
+"""Serving measurement: concurrent matvec requests over resident geometries.
+
+Drives the library's continuous-batching server (mlfma_server_*) with a
+seeded Poisson stream of requests and reports throughput and p50/p99
+latency next to one-at-a-time complex128 products served in arrival order.
+"""
+import math
+import threading
+import time
+
+import numpy as np
+import torch
+
+from . import binding as mf
+
+
+def _percentiles(lat):
+    a = np.sort(np.asarray(lat))
+    return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+def make_requests(geoms, n_requests, seed, dtype, max_rhs=16):
+    """Geometry uniform, nrhs ~ U{1..max_rhs}, coefficients N(0,1) + jN(0,1)."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(n_requests):
+        gi = int(rng.integers(len(geoms)))
+        nr = int(rng.integers(1, max_rhs + 1))
+        n2 = 2 * geoms[gi].n_rwg
+        x = (rng.standard_normal((nr, n2)) + 1j * rng.standard_normal((nr, n2))).astype(dtype)
+        reqs.append((gi, torch.from_numpy(x).cuda()))
+    return reqs
+
+
+def run_stream(server, geoms, reqs, arrivals, op="C"):
+    """Submit reqs at the given arrival offsets (seconds; None = all at once)
+    from one thread, wait from another; returns (latencies, wall seconds, batch sizes)."""
+    ys = [torch.empty_like(x) for _, x in reqs]
+    tickets = [None] * len(reqs)
+    ready = [threading.Event() for _ in reqs]
+    lat = [0.0] * len(reqs)
+    bsz = [0] * len(reqs)
+
+    errors = []
+
+    def waiter():
+        for i in range(len(reqs)):
+            ready[i].wait()
+            try:
+                lat[i], bsz[i] = server.wait(tickets[i])
+            except Exception as e:          # reported to the caller below
+                errors.append(e)
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for i, (gi, x) in enumerate(reqs):
+        if arrivals is not None:
+            dt = t0 + arrivals[i] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+        tickets[i] = server.submit(geoms[gi], x, ys[i], op=op)
+        ready[i].set()
+    th.join()
+    wall = time.perf_counter() - t0
+    if errors:
+        raise errors[0]
+    return lat, wall, bsz, ys
+
+
+def one_at_a_time(geoms, reqs, op="C"):
+    """Service time of each request alone as a plain complex128 product."""
+    svc = []
+    for gi, x in reqs:
+        x128 = x.to(torch.complex128)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        geoms[gi].matvec(x128.t(), op=op)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t0)
+    return svc
+
+
+def fifo_latencies(arrivals, service):
+    """Latencies of a single first-in-first-out server (Lindley recursion)."""
+    done = 0.0
+    lat = []
+    for a, s in zip(arrivals, service):
+        start = max(a, done)
+        done = start + s
+        lat.append(done - a)
+    return lat
+
+
+def run(geom_list, n_requests=512, seed=5, streams=4, max_batch_rhs=16, load=0.7, op="C",
+        dtype=np.complex64, log=print):
+    geoms = []
+    for name, v, t in geom_list:
+        g = mf.Geometry(v, t, max_rhs=max_batch_rhs).precompute()
+        geoms.append(g)
+        log("[serve] geometry %s: N=%d levels=%d" % (name, g.n_rwg, g.levels))
+    reqs = make_requests(geoms, n_requests, seed, dtype, max_rhs=16)
+    unknowns = sum(2 * geoms[gi].n_rwg * x.shape[0] for gi, x in reqs)
+    # arena footprint with every slot holding the largest geometry, and a
+    # budget below it so that admission by memory is exercised
+    from .binding import lib  # noqa: F401
+    probe = mf.Server(streams=streams, max_batch_rhs=max_batch_rhs)
+    lat, wall, bsz, _ = run_stream(probe, geoms, reqs[:64], None, op)
+    full = probe.stats()["arena_bytes"]
+    probe.close()
+    budget = int(0.75 * full) if full else 0
+    server = mf.Server(streams=streams, max_batch_rhs=max_batch_rhs, hbm_budget_bytes=budget)
+    # capacity: everything submitted at once (closed loop)
+    lat_c, wall_c, bsz_c, ys = run_stream(server, geoms, reqs, None, op)
+    capacity = len(reqs) / wall_c
+    log("[serve] capacity %.1f requests/s (batched, all queued at once)" % capacity)
+    # open loop: Poisson arrivals at `load` x capacity
+    rng = np.random.default_rng(seed + 1)
+    rate = load * capacity
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
+    lat_p, wall_p, bsz_p, ys_p = run_stream(server, geoms, reqs, arrivals, op)
+    p50, p99 = _percentiles(lat_p)
+    stats = server.stats()
+    # each result the same alone and in the mix (alone: a single product of
+    # the library with the request's own right-hand sides)
+    worst = 0.0
+    for i in range(0, len(reqs), max(1, len(reqs) // 32)):
+        gi, x = reqs[i]
+        alone = geoms[gi].matvec(x.t(), op=op).t()
+        d = float(torch.linalg.norm(alone - ys_p[i]) / torch.linalg.norm(alone))
+        worst = max(worst, d)
+    server.close()
+    # one-at-a-time complex128 products in arrival order
+    svc = one_at_a_time(geoms, reqs, op)
+    lat_b = fifo_latencies(arrivals, svc)
+    b50, b99 = _percentiles(lat_b)
+    res = {
+        "requests": len(reqs), "geometries": [g.n_rwg for g in geoms], "streams": streams,
+        "max_batch_rhs": max_batch_rhs, "dtype": np.dtype(dtype).name, "budget_bytes": budget,
+        "arena_bytes_all_slots_largest": full,
+        "capacity_requests_per_s": capacity,
+        "throughput_unknowns_rhs_per_s": unknowns / wall_c,
+        "poisson_rate_requests_per_s": rate,
+        "p50_ms": 1e3 * p50, "p99_ms": 1e3 * p99,
+        "mean_batch_rhs": float(np.mean(bsz_p)),
+        "launches": stats["launches"],
+        "max_rel_diff_alone_vs_mix": worst,
+        "one_at_a_time_c128": {"throughput_unknowns_rhs_per_s": unknowns / sum(svc),
+                               "p50_ms": 1e3 * b50, "p99_ms": 1e3 * b99},
+    }
+    for g in geoms:
+        g.release()
+    return res

@@ -7,8 +7,8 @@ Nothing in this package evaluates the boundary-integral method itself.
 """
 from .meshes import (icosphere, rounded_box, ellipsoid, tetrahedron, octahedron,
                      icosahedron, flat_plate, mesh_stats)
-from .vectors import (gaussian_coeffs, fibonacci_directions, workload)
+from .vectors import (gaussian_coeffs, fibonacci_directions, plane_waves, serving_set, workload)
 
 __all__ = ["icosphere", "rounded_box", "ellipsoid", "tetrahedron", "octahedron",
            "icosahedron", "flat_plate", "mesh_stats", "gaussian_coeffs",
-           "fibonacci_directions", "workload"]
+           "fibonacci_directions", "plane_waves", "serving_set", "workload"]

@@ -382,3 +382,22 @@ def test_box_rule_counts(m, r, levels, boxes, near):
     assert len({tuple(c) for c in coords}) == boxes
     d = np.abs(coords[:, None, :] - coords[None, :, :]).max(axis=2)
     assert int((d <= 1).sum()) == near
+
+
+def test_plane_wave_rhs_matches_projection():
+    """Right-hand sides of eqs. 49-50 for a plane wave (Sec. III excitation):
+    the oracle's 7-point values against an independent high-order projection
+    of E/2 + n x H/2 and H/2 - n x E/2 (agreement to the 7-point rule's error)."""
+    v, t = synth.icosphere(6, 0.5)
+    N = 3 * len(t) // 2
+    khat = np.array([0.3, -0.4, np.sqrt(1 - 0.25)])
+    khat /= np.linalg.norm(khat)
+    pol = np.cross(khat, [0.0, 0.0, 1.0])
+    pol /= np.linalg.norm(pol)
+    Ei = lambda x: pol[None, :] * np.exp(-1j * K0 * x @ khat)[:, None]
+    Hi = lambda x: np.cross(khat, pol)[None, :] * np.exp(-1j * K0 * x @ khat)[:, None]
+    bJ = _project(v, t, lambda x, n: 0.5 * Ei(x) + 0.5 * np.cross(n, Hi(x)))
+    bM = _project(v, t, lambda x, n: 0.5 * Hi(x) - 0.5 * np.cross(n, Ei(x)))
+    got = oracle.plane_wave_rhs(v, t, K0, khat[None, :], pol[None, :])[:, 0]
+    ref = np.concatenate([bJ, bM])
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-5
