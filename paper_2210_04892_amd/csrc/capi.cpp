@@ -628,10 +628,15 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
             const Level &L = tr.lv[l], &C = tr.lv[l + 1];
             const IntLevel &I = c->lv[l];
             const int midlen = L.nth * C.nph;
-            launch_interp<T>(C.nbox, midlen, C.K, I.ath_s, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], mid, nrhs,
-                             false, st);
-            launch_agg_phi<T>(L.nbox, L.K, midlen, I.child_start, c->lv[l + 1].oct, P.lv[l].shift, I.aph_s, I.aph_c,
-                              P.lv[l].aph_w, mid, (cpx<T> *)w.U[l], nrhs, st);
+            const int taps = c->opt.interp_order;
+            if (!launch_interp_fixed<T>(taps, C.nbox, midlen, C.K, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], mid,
+                                        nrhs, st))
+                launch_interp<T>(C.nbox, midlen, C.K, I.ath_s, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], mid,
+                                 nrhs, false, st);
+            if (!launch_agg_phi_fixed<T>(taps, L.nbox, L.K, midlen, I.child_start, c->lv[l + 1].oct, P.lv[l].shift,
+                                         I.aph_c, P.lv[l].aph_w, mid, (cpx<T> *)w.U[l], nrhs, st))
+                launch_agg_phi<T>(L.nbox, L.K, midlen, I.child_start, c->lv[l + 1].oct, P.lv[l].shift, I.aph_s,
+                                  I.aph_c, P.lv[l].aph_w, mid, (cpx<T> *)w.U[l], nrhs, st);
         }
     }
     mark(4);

@@ -49,6 +49,15 @@ void launch_radiate(int op, int nbox, int K, const int *box_start, const cpx<T> 
 template <class T>
 void launch_interp(int nbox, int rows, int in_len, const int *st, const int *col, const T *w, const cpx<T> *in,
                    cpx<T> *out, int nrhs, bool accumulate, hipStream_t s);
+// fixed-size forward stencils (taps = interpolation order 6, 8 or 10);
+// return false when the order has no fixed-size kernel
+template <class T>
+bool launch_interp_fixed(int taps, int nbox, int rows, int in_len, const int *col, const T *w, const cpx<T> *in,
+                         cpx<T> *out, int nrhs, hipStream_t s);
+template <class T>
+bool launch_agg_phi_fixed(int taps, int nparent, int Kp, int mid_len, const int *child_start, const int *child_oct,
+                          const cpx<T> *shift, const int *col, const T *w, const cpx<T> *mid, cpx<T> *Up, int nrhs,
+                          hipStream_t s);
 template <class T>
 void launch_agg_phi(int nparent, int Kp, int mid_len, const int *child_start, const int *child_oct,
                     const cpx<T> *shift, const int *st, const int *col, const T *w, const cpx<T> *mid, cpx<T> *Up,

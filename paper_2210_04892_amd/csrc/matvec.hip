@@ -327,7 +327,33 @@ __global__ __launch_bounds__(256) void k_interp(int nbox, int rows, int in_len, 
     cpx<T> a0[NR], a1[NR];
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) a0[rr] = a1[rr] = mk<T>(0, 0);
-    for (int e = st[row]; e < st[row + 1]; e++) {
+    const int e1 = st[row + 1];
+    int e = st[row];
+    for (; e + 4 <= e1; e += 4) {
+        int c[4];
+        T we[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            c[u] = col[e + u];
+            we[u] = w[e + u];
+        }
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            if (NR > 1 && r0 + rr >= nrhs) continue;
+            cpx<T> v0[4], v1[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                v0[u] = in[pidx(box, 0, r0 + rr, c[u], nrhs, in_len)];
+                v1[u] = in[pidx(box, 1, r0 + rr, c[u], nrhs, in_len)];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                a0[rr] = a0[rr] + we[u] * v0[u];
+                a1[rr] = a1[rr] + we[u] * v1[u];
+            }
+        }
+    }
+    for (; e < e1; e++) {
         const T we = w[e];
         const int c = col[e];
 #pragma unroll
@@ -349,6 +375,99 @@ __global__ __launch_bounds__(256) void k_interp(int nbox, int rows, int in_len, 
             *o0 = a0[rr];
             *o1 = a1[rr];
         }
+    }
+}
+
+// Forward theta stencil with exactly P taps per row (the interpolation
+// stencils are fixed-size): all P gathers are issued before the sums.
+template <class T, int NR, int P>
+__global__ __launch_bounds__(256) void k_interp_fixed(int nbox, int rows, int in_len, const int *__restrict__ col,
+                                                      const T *__restrict__ w, const cpx<T> *__restrict__ in,
+                                                      cpx<T> *__restrict__ out, int nrhs)
+{
+    const long long blk = xcd_block(((long long)nbox * rows + blockDim.x - 1) / blockDim.x);
+    if (blk < 0) return;
+    const long long g = blk * blockDim.x + threadIdx.x;
+    if (g >= (long long)nbox * rows) return;
+    const int box = (int)(g / rows), row = (int)(g % rows);
+    const int r0 = blockIdx.y * NR;
+    int c[P];
+    T wt[P];
+#pragma unroll
+    for (int t = 0; t < P; t++) {
+        c[t] = col[(long long)row * P + t];
+        wt[t] = w[(long long)row * P + t];
+    }
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) {
+        if (NR > 1 && r0 + rr >= nrhs) continue;
+#pragma unroll
+        for (int comp = 0; comp < 2; comp++) {
+            const cpx<T> *src = in + pidx(box, comp, r0 + rr, 0, nrhs, in_len);
+            cpx<T> v[P];
+#pragma unroll
+            for (int t = 0; t < P; t++) v[t] = src[c[t]];
+            cpx<T> acc = mk<T>(0, 0);
+#pragma unroll
+            for (int t = 0; t < P; t++) acc = acc + wt[t] * v[t];
+            out[pidx(box, comp, r0 + rr, row, nrhs, rows)] = acc;
+        }
+    }
+}
+
+// Aggregation phi stage with exactly P taps per parent sample.
+template <class T, int NR, int P>
+__global__ __launch_bounds__(256) void k_agg_phi_fixed(int nparent, int Kp, int mid_len,
+                                                       const int *__restrict__ child_start,
+                                                       const int *__restrict__ child_oct,
+                                                       const cpx<T> *__restrict__ shift, const int *__restrict__ col,
+                                                       const T *__restrict__ w, const cpx<T> *__restrict__ mid,
+                                                       cpx<T> *__restrict__ Up, int nrhs)
+{
+    const long long blk = xcd_block(((long long)nparent * Kp + blockDim.x - 1) / blockDim.x);
+    if (blk < 0) return;
+    const long long g = blk * blockDim.x + threadIdx.x;
+    if (g >= (long long)nparent * Kp) return;
+    const int Pb = (int)(g / Kp), q = (int)(g % Kp);
+    const int r0 = blockIdx.y * NR;
+    int c[P];
+    T wt[P];
+#pragma unroll
+    for (int t = 0; t < P; t++) {
+        c[t] = col[(long long)q * P + t];
+        wt[t] = w[(long long)q * P + t];
+    }
+    cpx<T> a0[NR], a1[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) a0[rr] = a1[rr] = mk<T>(0, 0);
+    for (int ch = child_start[Pb]; ch < child_start[Pb + 1]; ch++) {
+        const cpx<T> sh = shift[(long long)child_oct[ch] * Kp + q];
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            if (NR > 1 && r0 + rr >= nrhs) continue;
+            const cpx<T> *m0 = mid + pidx(ch, 0, r0 + rr, 0, nrhs, mid_len);
+            const cpx<T> *m1 = mid + pidx(ch, 1, r0 + rr, 0, nrhs, mid_len);
+            cpx<T> v0[P], v1[P];
+#pragma unroll
+            for (int t = 0; t < P; t++) {
+                v0[t] = m0[c[t]];
+                v1[t] = m1[c[t]];
+            }
+            cpx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+#pragma unroll
+            for (int t = 0; t < P; t++) {
+                s0 = s0 + wt[t] * v0[t];
+                s1 = s1 + wt[t] * v1[t];
+            }
+            fma_to(a0[rr], sh, s0);
+            fma_to(a1[rr], sh, s1);
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) {
+        if (NR > 1 && r0 + rr >= nrhs) continue;
+        Up[pidx(Pb, 0, r0 + rr, q, nrhs, Kp)] = a0[rr];
+        Up[pidx(Pb, 1, r0 + rr, q, nrhs, Kp)] = a1[rr];
     }
 }
 
@@ -482,7 +601,32 @@ __global__ __launch_bounds__(256) void k_disagg_mid(int nchild, int mid_len, int
     cpx<T> a0[NR], a1[NR];
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) a0[rr] = a1[rr] = mk<T>(0, 0);
-    for (int e = st[row]; e < st[row + 1]; e++) {
+    const int e1 = st[row + 1];
+    int e = st[row];
+    for (; e + 4 <= e1; e += 4) {
+        int kp[4];
+        cpx<T> f[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) kp[u] = col[e + u];
+#pragma unroll
+        for (int u = 0; u < 4; u++) f[u] = w[e + u] * conjg(sh[kp[u]]);
+#pragma unroll
+        for (int rr = 0; rr < NR; rr++) {
+            if (NR > 1 && r0 + rr >= nrhs) continue;
+            cpx<T> v0[4], v1[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                v0[u] = Vp[pidx(P, 0, r0 + rr, kp[u], nrhs, Kp)];
+                v1[u] = Vp[pidx(P, 1, r0 + rr, kp[u], nrhs, Kp)];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                fma_to(a0[rr], f[u], v0[u]);
+                fma_to(a1[rr], f[u], v1[u]);
+            }
+        }
+    }
+    for (; e < e1; e++) {
         const int kp = col[e];
         const cpx<T> f = w[e] * conjg(sh[kp]);
 #pragma unroll
@@ -620,6 +764,47 @@ void launch_interp(int nbox, int rows, int in_len, const int *st, const int *col
 }
 
 template <class T>
+bool launch_interp_fixed(int taps, int nbox, int rows, int in_len, const int *col, const T *w, const cpx<T> *in,
+                         cpx<T> *out, int nrhs, hipStream_t s)
+{
+    if (taps != 6 && taps != 8 && taps != 10) return false;
+    DISPATCH_NR(nrhs, {
+        dim3 grid(xcd_grid(blocks_for((long long)nbox * rows, 256)), (nrhs + NR - 1) / NR);
+        if (taps == 6)
+            hipLaunchKernelGGL((k_interp_fixed<T, NR, 6>), grid, dim3(256), 0, s, nbox, rows, in_len, col, w, in, out,
+                               nrhs);
+        else if (taps == 8)
+            hipLaunchKernelGGL((k_interp_fixed<T, NR, 8>), grid, dim3(256), 0, s, nbox, rows, in_len, col, w, in, out,
+                               nrhs);
+        else
+            hipLaunchKernelGGL((k_interp_fixed<T, NR, 10>), grid, dim3(256), 0, s, nbox, rows, in_len, col, w, in,
+                               out, nrhs);
+    });
+    return true;
+}
+
+template <class T>
+bool launch_agg_phi_fixed(int taps, int nparent, int Kp, int mid_len, const int *child_start, const int *child_oct,
+                          const cpx<T> *shift, const int *col, const T *w, const cpx<T> *mid, cpx<T> *Up, int nrhs,
+                          hipStream_t s)
+{
+    if (taps != 6 && taps != 8 && taps != 10) return false;
+    DISPATCH_NR(nrhs, {
+        dim3 grid(xcd_grid(blocks_for((long long)nparent * Kp, 256)), (nrhs + NR - 1) / NR);
+        if (taps == 6)
+            hipLaunchKernelGGL((k_agg_phi_fixed<T, NR, 6>), grid, dim3(256), 0, s, nparent, Kp, mid_len, child_start,
+                               child_oct, shift, col, w, mid, Up, nrhs);
+        else if (taps == 8)
+            hipLaunchKernelGGL((k_agg_phi_fixed<T, NR, 8>), grid, dim3(256), 0, s, nparent, Kp, mid_len, child_start,
+                               child_oct, shift, col, w, mid, Up, nrhs);
+        else
+            hipLaunchKernelGGL((k_agg_phi_fixed<T, NR, 10>), grid, dim3(256), 0, s, nparent, Kp, mid_len,
+                               child_start, child_oct, shift, col, w, mid, Up, nrhs);
+    });
+    return true;
+}
+
+template <class T>
 void launch_agg_phi(int nparent, int Kp, int mid_len, const int *child_start, const int *child_oct,
                     const cpx<T> *shift, const int *st, const int *col, const T *w, const cpx<T> *mid, cpx<T> *Up,
                     int nrhs, hipStream_t s)
@@ -680,6 +865,10 @@ void launch_receive(int op, int N, int K, const int *leaf_of, const cpx<T> *R, c
     template void launch_near<T>(int, const int *, const int *, const int *, const int *, const long long *,     \
                                  const cpx<T> *, const int *, const int *, const T *, const cpx<T> *, cpx<T> *, \
                                  int, hipStream_t);                                                               \
+    template bool launch_interp_fixed<T>(int, int, int, int, const int *, const T *, const cpx<T> *, cpx<T> *,    \
+                                         int, hipStream_t);                                                       \
+    template bool launch_agg_phi_fixed<T>(int, int, int, int, const int *, const int *, const cpx<T> *,          \
+                                          const int *, const T *, const cpx<T> *, cpx<T> *, int, hipStream_t);   \
     template void launch_radiate<T>(int, int, int, const int *, const cpx<T> *, const cpx<T> *, cpx<T> *, int,   \
                                     hipStream_t);                                                                 \
     template void launch_interp<T>(int, int, int, const int *, const int *, const T *, const cpx<T> *, cpx<T> *, \

@@ -444,8 +444,17 @@ void build_tree(const Surface &s, const RwgTable &r, double k, double leaf, int 
     tr.agg_phi.assign(levels, Csr());
     tr.dis_phi.assign(levels, Csr());
     tr.dis_theta.assign(levels, Csr());
-    for (int l = 2; l + 1 < levels; l++)
-        build_stencils(tr.lv[l + 1], tr.lv[l], order, tr.agg_theta[l], tr.agg_phi[l], tr.dis_phi[l], tr.dis_theta[l]);
+    for (int l = 2; l + 1 < levels; l++) {
+        const Level &C = tr.lv[l + 1];
+        if (order > C.nph || order > 3 * C.nth)
+            throw Error(MLFMA_ERR_ARG, "interpolation order exceeds the samples of level " + std::to_string(l + 1));
+        build_stencils(C, tr.lv[l], order, tr.agg_theta[l], tr.agg_phi[l], tr.dis_phi[l], tr.dis_theta[l]);
+        // the forward stencils have exactly `order` taps per row (the fixed-size kernels rely on it)
+        for (const Csr *a : {&tr.agg_theta[l], &tr.agg_phi[l]})
+            for (int r = 0; r < a->rows; r++)
+                if (a->start[r + 1] - a->start[r] != order)
+                    throw Error(MLFMA_ERR_ARG, "interpolation stencil with a wrong number of taps");
+    }
 }
 
 void check_touching_near(const Surface &s, const RwgTable &r, const Tree &tr)
