@@ -48,7 +48,12 @@ template <class T>
 struct PrecLevel {
     cpx<T> *trans = nullptr, *shift = nullptr;
     T *ath_w = nullptr, *aph_w = nullptr, *dph_w = nullptr, *dth_w = nullptr;
+    // translation tiles (a batch of sources fills 32 KB of LDS)
+    int ntile = 0;
+    int *tile_tgt = nullptr, *tile_bat = nullptr, *bat_src = nullptr, *src = nullptr;
+    int *bat_row = nullptr, *row = nullptr, *ent = nullptr;
 };
+
 
 template <class T>
 struct Prec {
@@ -197,6 +202,16 @@ void upload_level_tables(mlfma_ctx *c, Prec<T> &P, const std::vector<std::vector
     P.lv.assign(tr.levels, PrecLevel<T>());
     for (int l = 2; l < tr.levels; l++) {
         P.lv[l].trans = c->upload(cast_cvec<T>(trans[l]));
+        TransTiles tt;
+        build_translation_tiles(tr.lv[l], trans_smax<T>(), TRANS_TMAX, tt);
+        P.lv[l].ntile = (int)tt.tile_tgt.size() - 1;
+        P.lv[l].tile_tgt = c->upload(tt.tile_tgt);
+        P.lv[l].tile_bat = c->upload(tt.tile_bat);
+        P.lv[l].bat_src = c->upload(tt.bat_src);
+        P.lv[l].src = c->upload(tt.src);
+        P.lv[l].bat_row = c->upload(tt.bat_row);
+        P.lv[l].row = c->upload(tt.row);
+        P.lv[l].ent = c->upload(tt.ent);
         if (l + 1 < tr.levels) {
             P.lv[l].shift = c->upload(cast_cvec<T>(shift[l]));
             P.lv[l].ath_w = c->upload(cast_vec<T>(tr.agg_theta[l].w));
@@ -641,15 +656,30 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     }
     mark(4);
     if (far) {
+        TransArgs<T> ta;
+        ta.smax = trans_smax<T>();
         for (int l = 2; l <= leafl; l++) {
             const Level &L = tr.lv[l];
-            const IntLevel &I = c->lv[l];
-            if (only_level >= 0 && l != only_level)
+            const PrecLevel<T> &PL = P.lv[l];
+            if (only_level >= 0 && l != only_level) {
                 launch_zero<T>((cpx<T> *)w.V[l], (long long)L.nbox * L.K * 2 * nrhs, st);
-            else
-                launch_translate<T>(L.nbox, L.K, I.il_start, I.il_box, I.il_off, P.lv[l].trans, (cpx<T> *)w.U[l],
-                                    (cpx<T> *)w.V[l], nrhs, st);
+                continue;
+            }
+            TransLevel<T> &d = ta.lv[ta.nlev++];
+            d.K = L.K;
+            d.ntile = PL.ntile;
+            d.tile_tgt = PL.tile_tgt;
+            d.tile_bat = PL.tile_bat;
+            d.bat_src = PL.bat_src;
+            d.src = PL.src;
+            d.bat_row = PL.bat_row;
+            d.row = PL.row;
+            d.ent = PL.ent;
+            d.trans = PL.trans;
+            d.U = (const cpx<T> *)w.U[l];
+            d.V = (cpx<T> *)w.V[l];
         }
+        launch_translate_tiled<T>(ta, nrhs, st);
     }
     mark(5);
     if (far) {

@@ -26,11 +26,38 @@ template <class T>
 __host__ __device__ inline cpx<T> operator*(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
 template <class T>
 __host__ __device__ inline cpx<T> conjg(cpx<T> a) { return {a.re, -a.im}; }
+// fused multiply-add a b + c, rounded once
+template <class T>
+__host__ __device__ inline T fmad(T a, T b, T c);
+template <>
+__host__ __device__ inline float fmad<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__host__ __device__ inline double fmad<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// acc += a b (four fused multiply-adds)
 template <class T>
 __host__ __device__ inline void fma_to(cpx<T> &acc, cpx<T> a, cpx<T> b)
 {
-    acc.re += a.re * b.re - a.im * b.im;
-    acc.im += a.re * b.im + a.im * b.re;
+    acc.re = fmad(a.re, b.re, acc.re);
+    acc.re = fmad(-a.im, b.im, acc.re);
+    acc.im = fmad(a.re, b.im, acc.im);
+    acc.im = fmad(a.im, b.re, acc.im);
+}
+// acc -= a b
+template <class T>
+__host__ __device__ inline void fms_to(cpx<T> &acc, cpx<T> a, cpx<T> b)
+{
+    acc.re = fmad(-a.re, b.re, acc.re);
+    acc.re = fmad(a.im, b.im, acc.re);
+    acc.im = fmad(-a.re, b.im, acc.im);
+    acc.im = fmad(-a.im, b.re, acc.im);
+}
+// acc += s x for real s
+template <class T>
+__host__ __device__ inline void axpy_to(cpx<T> &acc, T s, cpx<T> x)
+{
+    acc.re = fmad(s, x.re, acc.re);
+    acc.im = fmad(s, x.im, acc.im);
 }
 
 // Launchers of the hot path (matvec.hip).  X, Y internal vectors
@@ -62,9 +89,33 @@ template <class T>
 void launch_agg_phi(int nparent, int Kp, int mid_len, const int *child_start, const int *child_oct,
                     const cpx<T> *shift, const int *st, const int *col, const T *w, const cpx<T> *mid, cpx<T> *Up,
                     int nrhs, hipStream_t s);
+// Tiled translation of every level in one launch.  Per level: the tile
+// tables of build_translation_tiles (device copies), the level's translation
+// operators (343 offsets x K samples) and its outgoing/incoming patterns.
+constexpr int TRANS_MAXLEV = 20;   // the octree has at most 20 levels
+constexpr int TRANS_TMAX = 16;      // targets per tile = waves per workgroup
+// sources per LDS batch: a batch holds 2 components x 64 (sample, rhs) lanes
+// of every source in 32 KB
 template <class T>
-void launch_translate(int nbox, int K, const int *il_start, const int *il_box, const int *il_off,
-                      const cpx<T> *trans, const cpx<T> *U, cpx<T> *V, int nrhs, hipStream_t s);
+constexpr int trans_smax() { return (32 * 1024) / (2 * 64 * (int)sizeof(cpx<T>)); }
+// a target's entries in one batch are fetched by the lanes of one wave
+static_assert(trans_smax<float>() <= 64 && trans_smax<double>() <= 64, "translation batch wider than a wave");
+template <class T>
+struct TransLevel {
+    int K = 0, ntile = 0;
+    int nqc = 0, first = 0;     // sample chunks and first workgroup (set by the launcher)
+    const int *tile_tgt = nullptr, *tile_bat = nullptr, *bat_src = nullptr, *src = nullptr;
+    const int *bat_row = nullptr, *row = nullptr, *ent = nullptr;
+    const cpx<T> *trans = nullptr, *U = nullptr;
+    cpx<T> *V = nullptr;
+};
+template <class T>
+struct TransArgs {
+    int nlev = 0, nblocks = 0, smax = 0;
+    TransLevel<T> lv[TRANS_MAXLEV];
+};
+template <class T>
+void launch_translate_tiled(const TransArgs<T> &a, int nrhs, hipStream_t s);
 template <class T>
 void launch_disagg_mid(int nchild, int mid_len, int Kp, const int *parent, const int *oct, const cpx<T> *shift,
                        const int *st, const int *col, const T *w, const cpx<T> *Vp, cpx<T> *mid, int nrhs,

@@ -143,8 +143,10 @@ __global__ __launch_bounds__(256) void k_near(int N, const int *__restrict__ lea
         for (int rr = 0; rr < NR; rr++) {
             if (NR > 1 && r0 + rr >= nrhs) continue;
             const cpx<T> x1 = X[(col * 2) * nrhs + r0 + rr], x2 = X[(col * 2 + 1) * nrhs + r0 + rr];
-            a1[rr] = a1[rr] + A * x1 - B * x2;
-            a2[rr] = a2[rr] + A * x2 + B * x1;
+            fma_to(a1[rr], A, x1);
+            fms_to(a1[rr], B, x2);
+            fma_to(a2[rr], A, x2);
+            fma_to(a2[rr], B, x1);
         }
     }
     if (id_start) {
@@ -156,8 +158,9 @@ __global__ __launch_bounds__(256) void k_near(int N, const int *__restrict__ lea
             for (int rr = 0; rr < NR; rr++) {
                 if (NR > 1 && r0 + rr >= nrhs) continue;
                 const cpx<T> x1 = X[(col * 2) * nrhs + r0 + rr], x2 = X[(col * 2 + 1) * nrhs + r0 + rr];
-                a1[rr] = a1[rr] + g * x1 + (T(0.5) * gx) * x2;
-                a2[rr] = a2[rr] + (T(0.5) * g) * x2;
+                axpy_to(a1[rr], g, x1);
+                axpy_to(a1[rr], T(0.5) * gx, x2);
+                axpy_to(a2[rr], T(0.5) * g, x2);
             }
         }
     }
@@ -249,8 +252,10 @@ __global__ __launch_bounds__(256) void k_near_rhs(int N, const int *__restrict__
             const long long c = bcast(col, jj);
             if (act) {
                 const cpx<T> x1 = X[(c * 2) * nrhs + r], x2 = X[(c * 2 + 1) * nrhs + r];
-                y1 = y1 + a * x1 - bb * x2;
-                y2 = y2 + a * x2 + bb * x1;
+                fma_to(y1, a, x1);
+                fms_to(y1, bb, x2);
+                fma_to(y2, a, x2);
+                fma_to(y2, bb, x1);
             }
         }
     }
@@ -259,8 +264,9 @@ __global__ __launch_bounds__(256) void k_near_rhs(int N, const int *__restrict__
             const long long c = id_col[e];
             const T g = id_w[2 * e], gx = id_w[2 * e + 1];
             const cpx<T> x1 = X[(c * 2) * nrhs + r], x2 = X[(c * 2 + 1) * nrhs + r];
-            y1 = y1 + g * x1 + (T(0.5) * gx) * x2;
-            y2 = y2 + (T(0.5) * g) * x2;
+            axpy_to(y1, g, x1);
+            axpy_to(y1, T(0.5) * gx, x2);
+            axpy_to(y2, T(0.5) * g, x2);
         }
     }
     if (act) {
@@ -299,8 +305,10 @@ __global__ __launch_bounds__(256) void k_radiate(int op, int nbox, int K, const 
                 al = T(0.5) * x2;
                 be = T(0.5) * x1;
             }
-            ut[rr] = ut[rr] + al * Rt - be * Rp;
-            up[rr] = up[rr] + al * Rp + be * Rt;
+            fma_to(ut[rr], al, Rt);
+            fms_to(ut[rr], be, Rp);
+            fma_to(up[rr], al, Rp);
+            fma_to(up[rr], be, Rt);
         }
     }
 #pragma unroll
@@ -348,8 +356,8 @@ __global__ __launch_bounds__(256) void k_interp(int nbox, int rows, int in_len, 
             }
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                a0[rr] = a0[rr] + we[u] * v0[u];
-                a1[rr] = a1[rr] + we[u] * v1[u];
+                axpy_to(a0[rr], we[u], v0[u]);
+                axpy_to(a1[rr], we[u], v1[u]);
             }
         }
     }
@@ -359,8 +367,8 @@ __global__ __launch_bounds__(256) void k_interp(int nbox, int rows, int in_len, 
 #pragma unroll
         for (int rr = 0; rr < NR; rr++) {
             if (NR > 1 && r0 + rr >= nrhs) continue;
-            a0[rr] = a0[rr] + we * in[pidx(box, 0, r0 + rr, c, nrhs, in_len)];
-            a1[rr] = a1[rr] + we * in[pidx(box, 1, r0 + rr, c, nrhs, in_len)];
+            axpy_to(a0[rr], we, in[pidx(box, 0, r0 + rr, c, nrhs, in_len)]);
+            axpy_to(a1[rr], we, in[pidx(box, 1, r0 + rr, c, nrhs, in_len)]);
         }
     }
 #pragma unroll
@@ -409,7 +417,7 @@ __global__ __launch_bounds__(256) void k_interp_fixed(int nbox, int rows, int in
             for (int t = 0; t < P; t++) v[t] = src[c[t]];
             cpx<T> acc = mk<T>(0, 0);
 #pragma unroll
-            for (int t = 0; t < P; t++) acc = acc + wt[t] * v[t];
+            for (int t = 0; t < P; t++) axpy_to(acc, wt[t], v[t]);
             out[pidx(box, comp, r0 + rr, row, nrhs, rows)] = acc;
         }
     }
@@ -456,8 +464,8 @@ __global__ __launch_bounds__(256) void k_agg_phi_fixed(int nparent, int Kp, int 
             cpx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
 #pragma unroll
             for (int t = 0; t < P; t++) {
-                s0 = s0 + wt[t] * v0[t];
-                s1 = s1 + wt[t] * v1[t];
+                axpy_to(s0, wt[t], v0[t]);
+                axpy_to(s1, wt[t], v1[t]);
             }
             fma_to(a0[rr], sh, s0);
             fma_to(a1[rr], sh, s1);
@@ -497,8 +505,8 @@ __global__ __launch_bounds__(256) void k_agg_phi(int nparent, int Kp, int mid_le
 #pragma unroll
             for (int rr = 0; rr < NR; rr++) {
                 if (NR > 1 && r0 + rr >= nrhs) continue;
-                s0[rr] = s0[rr] + we * mid[pidx(c, 0, r0 + rr, cc, nrhs, mid_len)];
-                s1[rr] = s1[rr] + we * mid[pidx(c, 1, r0 + rr, cc, nrhs, mid_len)];
+                axpy_to(s0[rr], we, mid[pidx(c, 0, r0 + rr, cc, nrhs, mid_len)]);
+                axpy_to(s1[rr], we, mid[pidx(c, 1, r0 + rr, cc, nrhs, mid_len)]);
             }
         }
         const cpx<T> sh = shift[(long long)child_oct[c] * Kp + q];
@@ -518,68 +526,91 @@ __global__ __launch_bounds__(256) void k_agg_phi(int nparent, int Kp, int mid_le
 
 // ---------------------------------------------------------------- translation
 // V_A(k) = sum_{(B, o) in IL(A)} T_o(k) U_B(k)   (diagonal in k)
-// One thread per (target box, sample); consecutive threads take consecutive
-// samples of one box, so the operator and pattern loads are coalesced for
-// every right-hand side.  The interaction-list loop is unrolled UNR deep so
-// that UNR independent (index, operator, pattern) load chains are in flight.
-template <class T, int NR, int UNR>
-__global__ __launch_bounds__(256) void k_translate(int nbox, int K, const int *__restrict__ il_start,
-                                                   const int *__restrict__ il_box, const int *__restrict__ il_off,
-                                                   const cpx<T> *__restrict__ trans, const cpx<T> *__restrict__ U,
-                                                   cpx<T> *__restrict__ V, int nrhs)
+// ------------------------------------------------------- translation, tiled
+// Workgroup = (tile, chunk of samples, group of right-hand sides), all levels
+// in one grid; wave j of the workgroup owns the tile's j-th target box.  The
+// lanes of a wave take QW consecutive samples for each of RW right-hand sides
+// (QW * RW = 64).  The source patterns of the tile (both components, the
+// chunk's samples and right-hand sides) are staged in LDS one batch at a time
+// and every wave sums T(offset, q) U_source(q) over its target's entries in
+// the batch, so each staged pattern is read from memory once per tile instead
+// of once per target.  Batches after the first add to what the first wrote
+// (the same lane revisits the same address).
+// read-only index tables in the constant address space: loads at
+// wave-uniform addresses become scalar loads
+typedef const __attribute__((address_space(4))) int cint;
+__device__ inline int ld_uniform(const int *p, int i) { return ((cint *)p)[i]; }
+
+template <class T, int RW>
+__global__ __launch_bounds__(TRANS_TMAX * WAVE) void k_translate_tiled(const TransArgs<T> a, int nrhs)
 {
-    const long long blk = xcd_block(((long long)nbox * K + blockDim.x - 1) / blockDim.x);
+    constexpr int QW = WAVE / RW;
+    extern __shared__ double trans_lds_raw[];
+    cpx<T> *lds = reinterpret_cast<cpx<T> *>(trans_lds_raw);
+    const long long blk = xcd_block(a.nblocks);
     if (blk < 0) return;
-    const long long g = blk * blockDim.x + threadIdx.x;
-    if (g >= (long long)nbox * K) return;
-    const int A = (int)(g / K), q = (int)(g % K);
-    const int r0 = blockIdx.y * NR;
-    cpx<T> a0[NR], a1[NR];
-#pragma unroll
-    for (int rr = 0; rr < NR; rr++) a0[rr] = a1[rr] = mk<T>(0, 0);
-    const int e0 = il_start[A], e1 = il_start[A + 1];
-    int e = e0;
-    for (; e + UNR <= e1; e += UNR) {
-        int off[UNR], B[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; u++) {
-            off[u] = il_off[e + u];
-            B[u] = il_box[e + u];
+    int l = 0;
+    while (l + 1 < a.nlev && blk >= a.lv[l + 1].first) l++;
+    const TransLevel<T> &L = a.lv[l];
+    const int lb = (int)(blk - L.first);
+    const int tile = lb % L.ntile, qc = lb / L.ntile;
+    const int K = L.K;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int nwave = blockDim.x / WAVE;
+    const int qi = lane % QW, ri = lane / QW;
+    const int q = qc * QW + qi, r = blockIdx.y * RW + ri;
+    const bool ok = q < K && r < nrhs;
+    const cpx<T> *tq = L.trans + (q < K ? q : K - 1);
+    const cpx<T> *Uq = L.U + pidx(0, 0, r < nrhs ? r : nrhs - 1, q < K ? q : K - 1, nrhs, K);
+    const int t0 = ld_uniform(L.tile_tgt, tile), nt = ld_uniform(L.tile_tgt, tile + 1) - t0;
+    const int b0 = ld_uniform(L.tile_bat, tile), b1 = ld_uniform(L.tile_bat, tile + 1);
+    for (int b = b0; b < b1; b++) {
+        const int s0 = ld_uniform(L.bat_src, b), ns = ld_uniform(L.bat_src, b + 1) - s0;
+        if (b > b0) __syncthreads();   // every wave is done with the previous batch
+        // stage: wave w copies (source, component) rows w, w + nwave, ...
+        for (int sc = wave; sc < 2 * ns; sc += nwave) {
+            const int B = ld_uniform(L.src, s0 + sc / 2);
+            lds[sc * WAVE + lane] = ok ? Uq[pidx(B, sc & 1, 0, 0, nrhs, K)] : mk<T>(0, 0);
         }
-        cpx<T> t[UNR];
+        __syncthreads();
+        if (wave >= nt) continue;
+        const int *rw = L.row + ld_uniform(L.bat_row, b);
+        const int e0 = ld_uniform(rw, wave), n = ld_uniform(rw, wave + 1) - e0;   // n <= ns <= 64
+        const int mine = lane < n ? L.ent[e0 + lane] : 0;
+        cpx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
+        int e = 0;
+        for (; e + 8 <= n; e += 8) {
+            int v[8];
+            cpx<T> t[8];
 #pragma unroll
-        for (int u = 0; u < UNR; u++) t[u] = trans[(long long)off[u] * K + q];
+            for (int u = 0; u < 8; u++) v[u] = __builtin_amdgcn_readlane(mine, e + u);
 #pragma unroll
-        for (int rr = 0; rr < NR; rr++) {
-            if (NR > 1 && r0 + rr >= nrhs) continue;
-            cpx<T> u0[UNR], u1[UNR];
+            for (int u = 0; u < 8; u++) t[u] = tq[(long long)(v[u] >> 16) * K];
 #pragma unroll
-            for (int u = 0; u < UNR; u++) {
-                u0[u] = U[pidx(B[u], 0, r0 + rr, q, nrhs, K)];
-                u1[u] = U[pidx(B[u], 1, r0 + rr, q, nrhs, K)];
+            for (int u = 0; u < 8; u++) {
+                const cpx<T> *p = lds + (v[u] & 0xffff) * 2 * WAVE + lane;
+                fma_to(a0, t[u], p[0]);
+                fma_to(a1, t[u], p[WAVE]);
             }
-#pragma unroll
-            for (int u = 0; u < UNR; u++) {
-                fma_to(a0[rr], t[u], u0[u]);
-                fma_to(a1[rr], t[u], u1[u]);
+        }
+        for (; e < n; e++) {
+            const int v = __builtin_amdgcn_readlane(mine, e);
+            const cpx<T> t = tq[(long long)(v >> 16) * K];
+            const cpx<T> *p = lds + (v & 0xffff) * 2 * WAVE + lane;
+            fma_to(a0, t, p[0]);
+            fma_to(a1, t, p[WAVE]);
+        }
+        if (ok) {
+            cpx<T> *v0 = L.V + pidx(t0 + wave, 0, r, q, nrhs, K), *v1 = L.V + pidx(t0 + wave, 1, r, q, nrhs, K);
+            if (b == b0) {
+                *v0 = a0;
+                *v1 = a1;
+            } else {
+                *v0 = *v0 + a0;
+                *v1 = *v1 + a1;
             }
         }
-    }
-    for (; e < e1; e++) {
-        const cpx<T> t = trans[(long long)il_off[e] * K + q];
-        const int B = il_box[e];
-#pragma unroll
-        for (int rr = 0; rr < NR; rr++) {
-            if (NR > 1 && r0 + rr >= nrhs) continue;
-            fma_to(a0[rr], t, U[pidx(B, 0, r0 + rr, q, nrhs, K)]);
-            fma_to(a1[rr], t, U[pidx(B, 1, r0 + rr, q, nrhs, K)]);
-        }
-    }
-#pragma unroll
-    for (int rr = 0; rr < NR; rr++) {
-        if (NR > 1 && r0 + rr >= nrhs) continue;
-        V[pidx(A, 0, r0 + rr, q, nrhs, K)] = a0[rr];
-        V[pidx(A, 1, r0 + rr, q, nrhs, K)] = a1[rr];
     }
 }
 
@@ -676,8 +707,10 @@ __global__ __launch_bounds__(256) void k_receive(int op, int N, int K, const int
         for (int rr = 0; rr < NR; rr++) {
             if (NR > 1 && r0 + rr >= nrhs) continue;
             const cpx<T> Vt = V[pidx(b, 0, r0 + rr, q, nrhs, K)], Vp = V[pidx(b, 1, r0 + rr, q, nrhs, K)];
-            a1[rr] = a1[rr] + Pt * Vt + Pp * Vp;
-            a2[rr] = a2[rr] + Pp * Vt - Pt * Vp;
+            fma_to(a1[rr], Pt, Vt);
+            fma_to(a1[rr], Pp, Vp);
+            fma_to(a2[rr], Pp, Vt);
+            fms_to(a2[rr], Pt, Vp);
         }
     }
 #pragma unroll
@@ -816,19 +849,30 @@ void launch_agg_phi(int nparent, int Kp, int mid_len, const int *child_start, co
     });
 }
 
+// right-hand sides per wave for the tiled translation
+static inline int trans_rw(int nrhs) { return nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1); }
+
 template <class T>
-void launch_translate(int nbox, int K, const int *il_start, const int *il_box, const int *il_off,
-                      const cpx<T> *trans, const cpx<T> *U, cpx<T> *V, int nrhs, hipStream_t s)
+void launch_translate_tiled(const TransArgs<T> &args, int nrhs, hipStream_t s)
 {
-    DISPATCH_NR(nrhs, {
-        dim3 grid(xcd_grid(blocks_for((long long)nbox * K, 256)), (nrhs + NR - 1) / NR);
-        if (NR <= 4)
-            hipLaunchKernelGGL((k_translate<T, NR, 4>), grid, dim3(256), 0, s, nbox, K, il_start, il_box, il_off,
-                               trans, U, V, nrhs);
-        else
-            hipLaunchKernelGGL((k_translate<T, NR, 2>), grid, dim3(256), 0, s, nbox, K, il_start, il_box, il_off,
-                               trans, U, V, nrhs);
-    });
+    if (args.nlev <= 0 || nrhs <= 0) return;
+    const int rw = trans_rw(nrhs), qw = WAVE / rw;
+    TransArgs<T> a = args;
+    a.nblocks = 0;
+    for (int l = 0; l < a.nlev; l++) {
+        a.lv[l].nqc = (a.lv[l].K + qw - 1) / qw;
+        a.lv[l].first = a.nblocks;
+        a.nblocks += a.lv[l].ntile * a.lv[l].nqc;
+    }
+    if (a.nblocks <= 0) return;
+    const size_t lds = (size_t)a.smax * 2 * WAVE * sizeof(cpx<T>);
+    const dim3 grid(xcd_grid(a.nblocks), (nrhs + rw - 1) / rw), block(TRANS_TMAX * WAVE);
+    if (rw == 4)
+        hipLaunchKernelGGL((k_translate_tiled<T, 4>), grid, block, lds, s, a, nrhs);
+    else if (rw == 2)
+        hipLaunchKernelGGL((k_translate_tiled<T, 2>), grid, block, lds, s, a, nrhs);
+    else
+        hipLaunchKernelGGL((k_translate_tiled<T, 1>), grid, block, lds, s, a, nrhs);
 }
 
 template <class T>
@@ -875,8 +919,7 @@ void launch_receive(int op, int N, int K, const int *leaf_of, const cpx<T> *R, c
                                    int, bool, hipStream_t);                                                       \
     template void launch_agg_phi<T>(int, int, int, const int *, const int *, const cpx<T> *, const int *,        \
                                     const int *, const T *, const cpx<T> *, cpx<T> *, int, hipStream_t);          \
-    template void launch_translate<T>(int, int, const int *, const int *, const int *, const cpx<T> *,           \
-                                      const cpx<T> *, cpx<T> *, int, hipStream_t);                                \
+    template void launch_translate_tiled<T>(const TransArgs<T> &, int, hipStream_t);                             \
     template void launch_disagg_mid<T>(int, int, int, const int *, const int *, const cpx<T> *, const int *,     \
                                        const int *, const T *, const cpx<T> *, cpx<T> *, int, hipStream_t);       \
     template void launch_zero<T>(cpx<T> *, long long, hipStream_t);                                               \

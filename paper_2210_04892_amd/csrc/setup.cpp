@@ -4,6 +4,7 @@
 #include "setup.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <numeric>
 #include <unordered_map>
@@ -537,6 +538,51 @@ void translation_table(double k, int L, const double X[3], const std::vector<dou
             acc += coef[l + 1] * p1;
         }
         out[q] = acc;
+    }
+}
+
+
+
+// ---------------------------------------------------------- translation tiles
+void build_translation_tiles(const Level &L, int smax, int tmax, TransTiles &t)
+{
+    if (smax < 1 || smax > 0xffff || tmax < 1) throw Error(MLFMA_ERR_ARG, "bad translation tile limits");
+    t = TransTiles();
+    t.tile_tgt.push_back(0);
+    t.tile_bat.push_back(0);
+    t.bat_src.push_back(0);
+    std::vector<int> uni;
+    int A0 = 0;
+    while (A0 < L.nbox) {
+        // the tile: consecutive targets of one 4x4x4 block, at most tmax of them
+        int A1 = A0 + 1;
+        auto block = [&](int A) {
+            return std::array<int, 3>{L.coord[3 * A] >> 2, L.coord[3 * A + 1] >> 2, L.coord[3 * A + 2] >> 2};
+        };
+        while (A1 < L.nbox && A1 - A0 < tmax && block(A1) == block(A0)) A1++;
+        uni.clear();
+        for (int A = A0; A < A1; A++)
+            for (int e = L.il_start[A]; e < L.il_start[A + 1]; e++) uni.push_back(L.il_box[e]);
+        std::sort(uni.begin(), uni.end());
+        uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
+        const int nbat = std::max(1, (int)((uni.size() + smax - 1) / smax));
+        for (int b = 0; b < nbat; b++) {
+            const int s0 = b * smax, s1 = std::min((int)uni.size(), s0 + smax);
+            t.src.insert(t.src.end(), uni.begin() + s0, uni.begin() + s1);
+            t.bat_src.push_back((int)t.src.size());
+            t.bat_row.push_back((int)t.row.size());
+            for (int A = A0; A < A1; A++) {
+                t.row.push_back((int)t.ent.size());
+                for (int e = L.il_start[A]; e < L.il_start[A + 1]; e++) {
+                    const int pos = (int)(std::lower_bound(uni.begin(), uni.end(), L.il_box[e]) - uni.begin());
+                    if (pos >= s0 && pos < s1) t.ent.push_back((L.il_off[e] << 16) | (pos - s0));
+                }
+            }
+            t.row.push_back((int)t.ent.size());
+        }
+        t.tile_tgt.push_back(A1);
+        t.tile_bat.push_back((int)t.bat_row.size());
+        A0 = A1;
     }
 }
 

@@ -70,6 +70,24 @@ struct Tree {
     std::vector<Csr> agg_theta, agg_phi, dis_phi, dis_theta;   // indexed by parent level l
 };
 
+// Interaction lists regrouped for the tiled translation.  A tile is a run of
+// consecutive target boxes (Morton order) inside one 4x4x4 block of the level;
+// the union of their source boxes is split into batches of at most `smax`
+// boxes, each small enough to be staged whole in LDS.  For batch b and the
+// tile's j-th target, ent[row[bat_row[b] + j] .. row[bat_row[b] + j + 1]) are
+// the target's interaction-list entries whose source lies in the batch, each
+// packed as (offset id << 16) | (position of the source inside the batch).
+struct TransTiles {
+    std::vector<int> tile_tgt;  // ntile + 1: first target box of each tile
+    std::vector<int> tile_bat;  // ntile + 1: first batch of each tile
+    std::vector<int> bat_src;   // nbatch + 1: first entry of each batch in src
+    std::vector<int> src;       // source boxes of every batch
+    std::vector<int> bat_row;   // nbatch: position of the batch's row pointers in row
+    std::vector<int> row;       // row pointers into ent
+    std::vector<int> ent;       // packed entries
+};
+void build_translation_tiles(const Level &L, int smax, int tmax, TransTiles &t);
+
 void build_surface(Surface &s, const double *verts, long long nv, const int *tris, long long nt);
 void build_rwg(const Surface &s, RwgTable &r);
 void build_tree(const Surface &s, const RwgTable &r, double k, double leaf, int digits, int interp_order,
