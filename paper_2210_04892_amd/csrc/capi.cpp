@@ -44,10 +44,20 @@ struct DeviceGuard {
 };
 
 // Per-level device tables in one precision.
+// theta-row chunks of one aggregation or disaggregation step (see LevelStep)
+struct StepPlan {
+    int rows = 0, nchunk = 0, wrows = 0;
+    int *win = nullptr;
+};
+
 template <class T>
 struct PrecLevel {
     cpx<T> *trans = nullptr, *shift = nullptr;
     T *ath_w = nullptr, *aph_w = nullptr, *dph_w = nullptr, *dth_w = nullptr;
+    StepPlan agg, dis;      // step from level l + 1 up to l, and from l down to l + 1
+    int tphi = 0, tth = 0;  // separable disaggregation stencils (0 = not separable)
+    int *phi_col = nullptr, *th_row = nullptr, *th_sh = nullptr;
+    T *phi_w = nullptr, *rowf = nullptr, *th_w = nullptr;
     // translation tiles (a batch of sources fills 32 KB of LDS)
     int ntile = 0;
     int *tile_tgt = nullptr, *tile_bat = nullptr, *bat_src = nullptr, *src = nullptr;
@@ -195,6 +205,30 @@ std::vector<cpx<T>> cast_cvec(const std::vector<cdouble> &v)
 }
 
 template <class T>
+void plan_level_steps(mlfma_ctx *c, int l, PrecLevel<T> &PL)
+{
+    const Tree &tr = c->tr;
+    const Level &L = tr.lv[l], &C = tr.lv[l + 1];
+    ChunkPlan cp;
+    plan_theta_chunks(tr.agg_theta[l], L.nth, C.nph, std::max(1, 512 / L.nph),
+                      [&](int wrows, int rows) { return agg_lds_bytes<T>(wrows, rows, C.nph); }, STEP_LDS_MAX, cp);
+    PL.agg = {cp.rows, cp.nchunk, cp.wrows, cp.rows ? c->upload(cp.win) : nullptr};
+    SepStencil sep;
+    if (!separable_disaggregation(L, C, tr.dis_phi[l], tr.dis_theta[l], sep)) return;
+    plan_theta_chunks(tr.dis_theta[l], C.nth, C.nph, std::max(1, 512 / C.nph),
+                      [&](int wrows, int) { return dis_lds_bytes<T>(wrows, L.nph, C.nph); }, STEP_LDS_MAX, cp);
+    PL.dis = {cp.rows, cp.nchunk, cp.wrows, cp.rows ? c->upload(cp.win) : nullptr};
+    PL.tphi = sep.tphi;
+    PL.tth = sep.tth;
+    PL.phi_col = c->upload(sep.phi_col);
+    PL.th_row = c->upload(sep.th_row);
+    PL.th_sh = c->upload(sep.th_sh);
+    PL.phi_w = c->upload(cast_vec<T>(sep.phi_w));
+    PL.rowf = c->upload(cast_vec<T>(sep.rowf));
+    PL.th_w = c->upload(cast_vec<T>(sep.th_w));
+}
+
+template <class T>
 void upload_level_tables(mlfma_ctx *c, Prec<T> &P, const std::vector<std::vector<cdouble>> &trans,
                          const std::vector<std::vector<cdouble>> &shift)
 {
@@ -218,6 +252,7 @@ void upload_level_tables(mlfma_ctx *c, Prec<T> &P, const std::vector<std::vector
             P.lv[l].aph_w = c->upload(cast_vec<T>(tr.agg_phi[l].w));
             P.lv[l].dph_w = c->upload(cast_vec<T>(tr.dis_phi[l].w));
             P.lv[l].dth_w = c->upload(cast_vec<T>(tr.dis_theta[l].w));
+            plan_level_steps<T>(c, l, P.lv[l]);
         }
     }
 }
@@ -609,6 +644,48 @@ void ensure_workspace(mlfma_ctx *c, int nrhs)
     c->bytes += c->ws.bytes;
 }
 
+// arguments of the fused step between parent level l and child level l + 1
+template <class T>
+LevelStep<T> step_args(mlfma_ctx *c, Prec<T> &P, int l, bool agg)
+{
+    const Tree &tr = c->tr;
+    const Level &L = tr.lv[l], &C = tr.lv[l + 1];
+    const IntLevel &I = c->lv[l];
+    const PrecLevel<T> &PL = P.lv[l];
+    const StepPlan &pl = agg ? PL.agg : PL.dis;
+    LevelStep<T> a;
+    a.nbox = agg ? L.nbox : C.nbox;
+    a.nth_p = L.nth;
+    a.nph_p = L.nph;
+    a.nth_c = C.nth;
+    a.nph_c = C.nph;
+    a.rows = pl.rows;
+    a.nchunk = pl.nchunk;
+    a.wrows = pl.wrows;
+    a.win = pl.win;
+    a.taps = c->opt.interp_order;
+    a.child_start = I.child_start;
+    a.parent = c->lv[l + 1].parent;
+    a.oct = c->lv[l + 1].oct;
+    a.shift = PL.shift;
+    if (agg) {
+        a.c1 = I.ath_c;
+        a.w1 = PL.ath_w;
+        a.c2 = I.aph_c;
+        a.w2 = PL.aph_w;
+    } else {
+        a.tphi = PL.tphi;
+        a.tth = PL.tth;
+        a.phi_col = PL.phi_col;
+        a.th_row = PL.th_row;
+        a.th_sh = PL.th_sh;
+        a.phi_w = PL.phi_w;
+        a.rowf = PL.rowf;
+        a.th_w = PL.th_w;
+    }
+    return a;
+}
+
 template <class T>
 void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nrhs, const cpx<T> *x, long long ldx,
                 cpx<T> *y, long long ldy, hipStream_t st, bool profile)
@@ -644,6 +721,10 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
             const IntLevel &I = c->lv[l];
             const int midlen = L.nth * C.nph;
             const int taps = c->opt.interp_order;
+            LevelStep<T> a = step_args<T>(c, P, l, true);
+            a.in = (const cpx<T> *)w.U[l + 1];
+            a.out = (cpx<T> *)w.U[l];
+            if (launch_aggregate_step<T>(a, nrhs, st)) continue;
             if (!launch_interp_fixed<T>(taps, C.nbox, midlen, C.K, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], mid,
                                         nrhs, st))
                 launch_interp<T>(C.nbox, midlen, C.K, I.ath_s, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], mid,
@@ -687,6 +768,10 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
             const Level &L = tr.lv[l], &Pl = tr.lv[l - 1];
             const IntLevel &Ip = c->lv[l - 1];
             const int midlen = Pl.nth * L.nph;
+            LevelStep<T> a = step_args<T>(c, P, l - 1, false);
+            a.in = (const cpx<T> *)w.V[l - 1];
+            a.out = (cpx<T> *)w.V[l];
+            if (launch_disaggregate_step<T>(a, nrhs, st)) continue;
             launch_disagg_mid<T>(L.nbox, midlen, Pl.K, c->lv[l].parent, c->lv[l].oct, P.lv[l - 1].shift, Ip.dph_s,
                                  Ip.dph_c, P.lv[l - 1].dph_w, (cpx<T> *)w.V[l - 1], mid, nrhs, st);
             launch_interp<T>(L.nbox, L.K, midlen, Ip.dth_s, Ip.dth_c, P.lv[l - 1].dth_w, mid, (cpx<T> *)w.V[l],

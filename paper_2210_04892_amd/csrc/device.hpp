@@ -116,6 +116,46 @@ struct TransArgs {
 };
 template <class T>
 void launch_translate_tiled(const TransArgs<T> &a, int nrhs, hipStream_t s);
+// One octree step of aggregation (children at level l+1 -> parents at l) or
+// disaggregation (parents -> children), done per box and chunk of theta rows
+// in LDS (levels.hip).  Sample index = theta row * nph + phi column.
+//  aggregation: workgroup = (parent, chunk of `rows` parent theta rows); the
+//    chunk needs child theta rows win[2 c] .. win[2 c + 1] (exclusive);
+//  disaggregation: workgroup = (child, chunk of `rows` child theta rows); the
+//    chunk needs parent (and intermediate) theta rows win[2 c] .. win[2 c + 1].
+// `wrows` is the largest window of any chunk.
+template <class T>
+struct LevelStep {
+    int nbox = 0;                       // parents (aggregation) or children (disaggregation)
+    int nth_p = 0, nph_p = 0, nth_c = 0, nph_c = 0;
+    int rows = 0, nchunk = 0, wrows = 0, taps = 0;
+    const int *win = nullptr;
+    const int *child_start = nullptr;   // aggregation: children of each parent
+    const int *parent = nullptr;        // disaggregation: parent of each child
+    const int *oct = nullptr;           // octant of each child in its parent
+    // aggregation: theta and phi stencils with `taps` entries per row
+    const int *c1 = nullptr, *c2 = nullptr;
+    const T *w1 = nullptr, *w2 = nullptr;
+    // disaggregation: separable transposed stencils (SepStencil on the host)
+    int tphi = 0, tth = 0;
+    const int *phi_col = nullptr, *th_row = nullptr, *th_sh = nullptr;
+    const T *phi_w = nullptr, *rowf = nullptr, *th_w = nullptr;
+    const cpx<T> *shift = nullptr;      // exp(+jk khat.(r_child - r_parent)), 8 x Kp
+    const cpx<T> *in = nullptr;
+    cpx<T> *out = nullptr;
+};
+// LDS bytes of a step (both components of the window and of the intermediate)
+template <class T>
+inline size_t agg_lds_bytes(int wrows, int rows, int nph_c) { return 2 * (size_t)(wrows + rows) * nph_c * sizeof(cpx<T>); }
+template <class T>
+inline size_t dis_lds_bytes(int wrows, int nph_p, int nph_c) { return 2 * (size_t)wrows * (nph_p + nph_c) * sizeof(cpx<T>); }
+constexpr size_t STEP_LDS_MAX = 64 * 1024;
+// return false when the step has no fused kernel (taps or LDS size)
+template <class T>
+bool launch_aggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s);
+template <class T>
+bool launch_disaggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s);
+
 template <class T>
 void launch_disagg_mid(int nchild, int mid_len, int Kp, const int *parent, const int *oct, const cpx<T> *shift,
                        const int *st, const int *col, const T *w, const cpx<T> *Vp, cpx<T> *mid, int nrhs,

@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256) void k_agg_phi(int nparent, int Kp, int mid_le
 
 // ---------------------------------------------------------------- translation
 // V_A(k) = sum_{(B, o) in IL(A)} T_o(k) U_B(k)   (diagonal in k)
-// ------------------------------------------------------- translation, tiled
+//
 // Workgroup = (tile, chunk of samples, group of right-hand sides), all levels
 // in one grid; wave j of the workgroup owns the tile's j-th target box.  The
 // lanes of a wave take QW consecutive samples for each of RW right-hand sides
@@ -534,8 +534,8 @@ __global__ __launch_bounds__(256) void k_agg_phi(int nparent, int Kp, int mid_le
 // chunk's samples and right-hand sides) are staged in LDS one batch at a time
 // and every wave sums T(offset, q) U_source(q) over its target's entries in
 // the batch, so each staged pattern is read from memory once per tile instead
-// of once per target.  Batches after the first add to what the first wrote
-// (the same lane revisits the same address).
+// of once per target.  The sums stay in registers across batches.
+
 // read-only index tables in the constant address space: loads at
 // wave-uniform addresses become scalar loads
 typedef const __attribute__((address_space(4))) int cint;
@@ -545,6 +545,8 @@ template <class T, int RW>
 __global__ __launch_bounds__(TRANS_TMAX * WAVE) void k_translate_tiled(const TransArgs<T> a, int nrhs)
 {
     constexpr int QW = WAVE / RW;
+    constexpr int ROWS = (2 * trans_smax<T>() + TRANS_TMAX - 1) / TRANS_TMAX;   // staged rows per wave
+    constexpr int UNR = sizeof(T) == 4 ? 16 : 8;                                // operator loads in flight
     extern __shared__ double trans_lds_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(trans_lds_raw);
     const long long blk = xcd_block(a.nblocks);
@@ -557,7 +559,6 @@ __global__ __launch_bounds__(TRANS_TMAX * WAVE) void k_translate_tiled(const Tra
     const int K = L.K;
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const int nwave = blockDim.x / WAVE;
     const int qi = lane % QW, ri = lane / QW;
     const int q = qc * QW + qi, r = blockIdx.y * RW + ri;
     const bool ok = q < K && r < nrhs;
@@ -565,30 +566,39 @@ __global__ __launch_bounds__(TRANS_TMAX * WAVE) void k_translate_tiled(const Tra
     const cpx<T> *Uq = L.U + pidx(0, 0, r < nrhs ? r : nrhs - 1, q < K ? q : K - 1, nrhs, K);
     const int t0 = ld_uniform(L.tile_tgt, tile), nt = ld_uniform(L.tile_tgt, tile + 1) - t0;
     const int b0 = ld_uniform(L.tile_bat, tile), b1 = ld_uniform(L.tile_bat, tile + 1);
+    cpx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
     for (int b = b0; b < b1; b++) {
         const int s0 = ld_uniform(L.bat_src, b), ns = ld_uniform(L.bat_src, b + 1) - s0;
+        // stage: wave w copies (source, component) rows w, w + TRANS_TMAX, ...;
+        // every load of the batch is issued before the first store
+        cpx<T> st[ROWS];
+#pragma unroll
+        for (int i = 0; i < ROWS; i++) {
+            const int sc = wave + i * TRANS_TMAX;
+            st[i] = mk<T>(0, 0);
+            if (sc < 2 * ns && ok) st[i] = Uq[pidx(ld_uniform(L.src, s0 + sc / 2), sc & 1, 0, 0, nrhs, K)];
+        }
         if (b > b0) __syncthreads();   // every wave is done with the previous batch
-        // stage: wave w copies (source, component) rows w, w + nwave, ...
-        for (int sc = wave; sc < 2 * ns; sc += nwave) {
-            const int B = ld_uniform(L.src, s0 + sc / 2);
-            lds[sc * WAVE + lane] = ok ? Uq[pidx(B, sc & 1, 0, 0, nrhs, K)] : mk<T>(0, 0);
+#pragma unroll
+        for (int i = 0; i < ROWS; i++) {
+            const int sc = wave + i * TRANS_TMAX;
+            if (sc < 2 * ns) lds[sc * WAVE + lane] = st[i];
         }
         __syncthreads();
         if (wave >= nt) continue;
         const int *rw = L.row + ld_uniform(L.bat_row, b);
         const int e0 = ld_uniform(rw, wave), n = ld_uniform(rw, wave + 1) - e0;   // n <= ns <= 64
         const int mine = lane < n ? L.ent[e0 + lane] : 0;
-        cpx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
         int e = 0;
-        for (; e + 8 <= n; e += 8) {
-            int v[8];
-            cpx<T> t[8];
+        for (; e + UNR <= n; e += UNR) {
+            int v[UNR];
+            cpx<T> t[UNR];
 #pragma unroll
-            for (int u = 0; u < 8; u++) v[u] = __builtin_amdgcn_readlane(mine, e + u);
+            for (int u = 0; u < UNR; u++) v[u] = __builtin_amdgcn_readlane(mine, e + u);
 #pragma unroll
-            for (int u = 0; u < 8; u++) t[u] = tq[(long long)(v[u] >> 16) * K];
+            for (int u = 0; u < UNR; u++) t[u] = tq[(long long)(v[u] >> 16) * K];
 #pragma unroll
-            for (int u = 0; u < 8; u++) {
+            for (int u = 0; u < UNR; u++) {
                 const cpx<T> *p = lds + (v[u] & 0xffff) * 2 * WAVE + lane;
                 fma_to(a0, t[u], p[0]);
                 fma_to(a1, t[u], p[WAVE]);
@@ -601,16 +611,10 @@ __global__ __launch_bounds__(TRANS_TMAX * WAVE) void k_translate_tiled(const Tra
             fma_to(a0, t, p[0]);
             fma_to(a1, t, p[WAVE]);
         }
-        if (ok) {
-            cpx<T> *v0 = L.V + pidx(t0 + wave, 0, r, q, nrhs, K), *v1 = L.V + pidx(t0 + wave, 1, r, q, nrhs, K);
-            if (b == b0) {
-                *v0 = a0;
-                *v1 = a1;
-            } else {
-                *v0 = *v0 + a0;
-                *v1 = *v1 + a1;
-            }
-        }
+    }
+    if (wave < nt && ok) {
+        L.V[pidx(t0 + wave, 0, r, q, nrhs, K)] = a0;
+        L.V[pidx(t0 + wave, 1, r, q, nrhs, K)] = a1;
     }
 }
 

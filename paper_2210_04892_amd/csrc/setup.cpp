@@ -586,4 +586,106 @@ void build_translation_tiles(const Level &L, int smax, int tmax, TransTiles &t)
     }
 }
 
+// ------------------------------------------------------- level-step chunks
+void plan_theta_chunks(const Csr &theta, int n_out, int nph, int rows0,
+                       const std::function<size_t(int, int)> &lds, size_t lds_max, ChunkPlan &pl)
+{
+    pl = ChunkPlan();
+    if (n_out < 1 || nph < 1 || theta.rows != n_out * nph) return;
+    // input theta rows [lo, hi) of each output theta row
+    std::vector<int> lo(n_out, 1 << 30), hi(n_out, -1);
+    for (int o = 0; o < n_out; o++)
+        for (int r = o * nph; r < (o + 1) * nph; r++)
+            for (int e = theta.start[r]; e < theta.start[r + 1]; e++) {
+                lo[o] = std::min(lo[o], theta.col[e] / nph);
+                hi[o] = std::max(hi[o], theta.col[e] / nph + 1);
+            }
+    for (int rows = std::max(1, std::min(rows0, n_out)); rows >= 1; rows = rows > 1 ? rows / 2 : 0) {
+        std::vector<int> win;
+        int wrows = 0;
+        for (int r0 = 0; r0 < n_out; r0 += rows) {
+            int a = 1 << 30, b = -1;
+            for (int o = r0; o < std::min(n_out, r0 + rows); o++) {
+                a = std::min(a, lo[o]);
+                b = std::max(b, hi[o]);
+            }
+            if (b < a) a = b = 0;
+            win.push_back(a);
+            win.push_back(b);
+            wrows = std::max(wrows, b - a);
+        }
+        if (lds(wrows, rows) <= lds_max) {
+            pl.rows = rows;
+            pl.nchunk = (n_out + rows - 1) / rows;
+            pl.wrows = wrows;
+            pl.win = std::move(win);
+            return;
+        }
+    }
+}
+
+// ------------------------------------------ separable disaggregation stencils
+bool separable_disaggregation(const Level &P, const Level &C, const Csr &dph, const Csr &dth, SepStencil &o)
+{
+    o = SepStencil();
+    const int nthp = P.nth, nphp = P.nph, nthc = C.nth, nphc = C.nph;
+    if (dph.rows != nthp * nphc || dth.rows != nthc * nphc) return false;
+    auto close = [](double a, double b) { return std::abs(a - b) <= 1e-12 * std::max(1.0, std::max(std::abs(a), std::abs(b))); };
+    // phi: row factor = the parent row's quadrature weight
+    o.rowf.resize(nthp);
+    for (int ip = 0; ip < nthp; ip++) o.rowf[ip] = P.wt[ip] * (2 * M_PI / nphp);
+    for (int j = 0; j < nphc; j++) o.tphi = std::max(o.tphi, dph.start[j + 1] - dph.start[j]);
+    o.phi_col.assign((size_t)nphc * o.tphi, 0);
+    o.phi_w.assign((size_t)nphc * o.tphi, 0.0);
+    for (int j = 0; j < nphc; j++)
+        for (int e = dph.start[j], t = 0; e < dph.start[j + 1]; e++, t++) {
+            o.phi_col[(size_t)j * o.tphi + t] = dph.col[e];
+            o.phi_w[(size_t)j * o.tphi + t] = dph.w[e] / o.rowf[0];
+        }
+    for (int ip = 1; ip < nthp; ip++)
+        for (int j = 0; j < nphc; j++) {
+            const int r = ip * nphc + j;
+            if (dph.start[r + 1] - dph.start[r] != dph.start[j + 1] - dph.start[j]) return false;
+            for (int e = dph.start[r], t = 0; e < dph.start[r + 1]; e++, t++)
+                if (dph.col[e] != ip * nphp + o.phi_col[(size_t)j * o.tphi + t] ||
+                    !close(dph.w[e], o.rowf[ip] * o.phi_w[(size_t)j * o.tphi + t]))
+                    return false;
+        }
+    // theta: per child row, (parent row, column shift, weight), in a fixed order
+    struct Tap { int row, sh; double w; };
+    auto taps_of = [&](int ic, int j) {
+        std::vector<Tap> v;
+        const int r = ic * nphc + j;
+        for (int e = dth.start[r]; e < dth.start[r + 1]; e++)
+            v.push_back({dth.col[e] / nphc, ((dth.col[e] % nphc - j) % nphc + nphc) % nphc, dth.w[e]});
+        std::sort(v.begin(), v.end(), [](const Tap &x, const Tap &y) { return x.row != y.row ? x.row < y.row : x.sh < y.sh; });
+        return v;
+    };
+    std::vector<std::vector<Tap>> t0(nthc);
+    for (int ic = 0; ic < nthc; ic++) {
+        t0[ic] = taps_of(ic, 0);
+        if (t0[ic].empty()) return false;
+        o.tth = std::max(o.tth, (int)t0[ic].size());
+    }
+    o.th_row.assign((size_t)nthc * o.tth, 0);
+    o.th_sh.assign((size_t)nthc * o.tth, 0);
+    o.th_w.assign((size_t)nthc * o.tth, 0.0);
+    for (int ic = 0; ic < nthc; ic++) {
+        const int n0 = (int)t0[ic].size();
+        for (int t = 0; t < o.tth; t++) {
+            const Tap &x = t0[ic][std::min(t, n0 - 1)];
+            o.th_row[(size_t)ic * o.tth + t] = x.row;
+            o.th_sh[(size_t)ic * o.tth + t] = x.sh;
+            o.th_w[(size_t)ic * o.tth + t] = t < n0 ? x.w : 0.0;
+        }
+        for (int j = 1; j < nphc; j++) {
+            const std::vector<Tap> v = taps_of(ic, j);
+            if ((int)v.size() != n0) return false;
+            for (int t = 0; t < n0; t++)
+                if (v[t].row != t0[ic][t].row || v[t].sh != t0[ic][t].sh || !close(v[t].w, t0[ic][t].w)) return false;
+        }
+    }
+    return true;
+}
+
 }  // namespace mlfma

@@ -2,6 +2,7 @@
 #pragma once
 #include <complex>
 #include <cstdint>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -87,6 +88,36 @@ struct TransTiles {
     std::vector<int> ent;       // packed entries
 };
 void build_translation_tiles(const Level &L, int smax, int tmax, TransTiles &t);
+
+// Theta-row chunks for a level step done in LDS.  `theta` is the step's theta
+// stencil, whose rows are (output theta row) * nph + phi column and whose
+// columns are (input theta row) * nph + phi column.  Output theta rows are cut
+// into chunks of `rows`; win[2 c], win[2 c + 1] bound the input theta rows
+// chunk c needs and wrows is the widest window.  The largest rows <= rows0
+// whose footprint lds(wrows, rows) is at most lds_max is taken (rows = 0 if
+// none is).
+struct ChunkPlan {
+    int rows = 0, nchunk = 0, wrows = 0;
+    std::vector<int> win;
+};
+void plan_theta_chunks(const Csr &theta, int n_out, int nph, int rows0,
+                       const std::function<size_t(int, int)> &lds, size_t lds_max, ChunkPlan &pl);
+
+// The disaggregation stencils of one step in separable form: the transposed
+// phi stencil is the same for every parent theta row up to the row's
+// quadrature weight, and the transposed theta stencil of a child theta row is
+// the same for every phi column up to the half-turn shift of the pole
+// extension.  Rows are padded with zero weights to a common width.
+//   intermediate(ip, j) = rowf[ip] * sum_t phi_w[j][t] * parent(ip, phi_col[j][t])
+//   child(ic, j) = sum_t th_w[ic][t] * intermediate(th_row[ic][t], (j + th_sh[ic][t]) mod nph_c)
+struct SepStencil {
+    int tphi = 0, tth = 0;
+    std::vector<int> phi_col, th_row, th_sh;
+    std::vector<double> phi_w, rowf, th_w;
+};
+// false when the step's stencils are not separable in this way
+bool separable_disaggregation(const Level &parent, const Level &child, const Csr &dph, const Csr &dth,
+                              SepStencil &out);
 
 void build_surface(Surface &s, const double *verts, long long nv, const int *tris, long long nt);
 void build_rwg(const Surface &s, RwgTable &r);
