@@ -8,6 +8,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mlfma.h"
@@ -713,7 +714,12 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
         launch_zero<T>(Y, (long long)N * 2 * nrhs, st);
     mark(2);
     const bool far = tr.levels >= 3 && want_far;
-    if (far) launch_radiate<T>(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)w.U[leafl], nrhs, st);
+    if (far) {
+        bool done = false;
+        if constexpr (std::is_same<T, float>::value)
+            done = launch_radiate_mfma(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)w.U[leafl], nrhs, st);
+        if (!done) launch_radiate<T>(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)w.U[leafl], nrhs, st);
+    }
     mark(3);
     if (far) {
         for (int l = leafl - 1; l >= 2; l--) {
@@ -779,7 +785,13 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
         }
     }
     mark(6);
-    if (far) launch_receive<T>(op, N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], Y, nrhs, st);
+    if (far) {
+        bool done = false;
+        if constexpr (std::is_same<T, float>::value)
+            done = launch_receive_mfma(op, Lf.nbox, Lf.K, c->box_start, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], Y,
+                                       nrhs, st);
+        if (!done) launch_receive<T>(op, N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], Y, nrhs, st);
+    }
     mark(7);
     launch_perm_out<T>(Y, y, ldy, c->iperm, N, nrhs, st);
     mark(8);

@@ -156,6 +156,13 @@ bool launch_aggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s);
 template <class T>
 bool launch_disaggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s);
 
+// Radiation and receive on the matrix cores (mfma.hip), complex float and
+// at least 16 right-hand sides; return false otherwise
+bool launch_radiate_mfma(int op, int nbox, int K, const int *box_start, const cpx<float> *R, const cpx<float> *X,
+                         cpx<float> *U, int nrhs, hipStream_t s);
+bool launch_receive_mfma(int op, int nbox, int K, const int *box_start, const cpx<float> *R, const cpx<float> *Q,
+                         const float *wq, const cpx<float> *V, cpx<float> *Y, int nrhs, hipStream_t s);
+
 template <class T>
 void launch_disagg_mid(int nchild, int mid_len, int Kp, const int *parent, const int *oct, const cpx<T> *shift,
                        const int *st, const int *col, const T *w, const cpx<T> *Vp, cpx<T> *mid, int nrhs,

@@ -1,0 +1,210 @@
+// Radiation and receive for many right-hand sides on the matrix cores.
+//
+// With nrhs right-hand sides both steps are dense complex products per leaf
+// box b (Sec. II-E; the single-pattern far field of the C block and the L/K
+// pair):
+//   radiation  U_b[c](q, r) = sum_{n in b} alpha_n(r) R_n[c](q) + beta_n(r) (khat x R_n)[c](q)
+//   receive    y_(m,h)(r)   += sum_{c, q} P_(m,h)[c](q) V_b[c](q, r)
+// Each complex product is four real 16x16x4 FP32 MFMAs (real part: re*re and
+// -im*im, imaginary part: re*im and im*re).  Lane layout of
+// v_mfma_f32_16x16x4f32 (wave64): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and holds D[(l / 16) * 4 + v][l % 16], v = 0..3.
+#include "device.hpp"
+#include "../../include/mlfma.h"
+
+namespace mlfma {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+constexpr int NXCD_M = 8;
+__device__ inline long long xcd_block_m(long long nblk)
+{
+    const long long per = (nblk + NXCD_M - 1) / NXCD_M;
+    const long long hw = blockIdx.x;
+    const long long lb = (hw % NXCD_M) * per + hw / NXCD_M;
+    return lb < nblk ? lb : -1;
+}
+inline unsigned xcd_grid_m(long long nblk) { return (unsigned)(((nblk + NXCD_M - 1) / NXCD_M) * NXCD_M); }
+
+__device__ inline long long pidx_m(long long b, int c, int r, int q, int nrhs, int K)
+{
+    return ((b * 2 + c) * nrhs + r) * (long long)K + q;
+}
+
+// complex D += A B on RT accumulator pairs sharing the B operand
+template <int RT>
+__device__ inline void cmfma(f4 (&dre)[RT], f4 (&dim)[RT], const cpx<float> (&a)[RT], cpx<float> b)
+{
+#pragma unroll
+    for (int t = 0; t < RT; t++) dre[t] = mfma4(a[t].re, b.re, dre[t]);
+#pragma unroll
+    for (int t = 0; t < RT; t++) dim[t] = mfma4(a[t].re, b.im, dim[t]);
+#pragma unroll
+    for (int t = 0; t < RT; t++) dre[t] = mfma4(-a[t].im, b.im, dre[t]);
+#pragma unroll
+    for (int t = 0; t < RT; t++) dim[t] = mfma4(a[t].im, b.re, dim[t]);
+}
+
+// Radiation.  Wave = (box, component c, tile of 16 samples) x RT tiles of 16
+// right-hand sides; D[i = rhs][j = sample], inner index k = (RWG, alpha|beta):
+// one MFMA step covers two RWGs.  EM pair: alpha = x1, beta = -x2; C block:
+// alpha = x2 / 2, beta = x1 / 2.
+template <int RT>
+__global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, int nqt,
+                                                      const int *__restrict__ box_start,
+                                                      const cpx<float> *__restrict__ R,
+                                                      const cpx<float> *__restrict__ X, cpx<float> *__restrict__ U,
+                                                      int nrhs)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tiles = 2 * nqt, per_box = (tiles + 3) / 4;
+    const int nrg = (nrhs + 16 * RT - 1) / (16 * RT);
+    const long long blk = xcd_block_m((long long)nbox * per_box * nrg);
+    if (blk < 0) return;
+    const int rg = (int)(blk % nrg);
+    const long long bt = blk / nrg;
+    const int b = (int)(bt / per_box), t = (int)(bt % per_box) * 4 + wave;
+    if (t >= tiles) return;
+    const int c = t / nqt, q0 = (t % nqt) * 16;
+    const int lo = lane & 15, kk = lane >> 4;
+    const int q = q0 + lo;
+    const bool qok = q < K;
+    const int s = kk & 1;
+    // which half of X feeds this lane's alpha/beta, and its factor
+    const int h = op == MLFMA_OP_EM ? s : 1 - s;
+    const float fac = op == MLFMA_OP_EM ? (s ? -1.0f : 1.0f) : 0.5f;
+    const int n0 = box_start[b], n1 = box_start[b + 1];
+    f4 dre[RT], dim[RT];
+#pragma unroll
+    for (int u = 0; u < RT; u++) dre[u] = dim[u] = f4{0, 0, 0, 0};
+    for (int n = n0; n < n1; n += 2) {
+        const int nn = n + (kk >> 1);
+        const bool nok = nn < n1;
+        cpx<float> bv = mk<float>(0, 0);
+        if (nok && qok) {
+            const cpx<float> *Rn = R + ((long long)nn * K + q) * 2;
+            if (s == 0) bv = Rn[c];
+            else if (c == 0) bv = mk<float>(-Rn[1].re, -Rn[1].im);   // khat x (vt, vp) = (-vp, vt)
+            else bv = Rn[0];
+        }
+        cpx<float> av[RT];
+#pragma unroll
+        for (int u = 0; u < RT; u++) {
+            const int r = (rg * RT + u) * 16 + lo;
+            av[u] = mk<float>(0, 0);
+            if (nok && r < nrhs) av[u] = fac * X[((long long)nn * 2 + h) * nrhs + r];
+        }
+        cmfma<RT>(dre, dim, av, bv);
+    }
+#pragma unroll
+    for (int u = 0; u < RT; u++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int r = (rg * RT + u) * 16 + kk * 4 + v;
+            if (qok && r < nrhs) U[pidx_m(b, c, r, q, nrhs, K)] = mk<float>(dre[u][v], dim[u][v]);
+        }
+}
+
+// Receive.  Workgroup = (box, group of RT x 16 right-hand sides); wave w takes
+// the box's row tiles w, w + 4, ... of 16 rows (RWG m, half h);
+// D[i = (m, h)][j = rhs], inner index k = (component, sample), four samples
+// per MFMA step.  Rows: h = 0 uses (Pt, Pp), h = 1 uses (Pp, -Pt), with
+// P = conj(R) for the EM pair and P = Q for the C block, weights wq folded in.
+template <int RT>
+__global__ __launch_bounds__(256) void k_receive_mfma(int op, int nbox, int K, const int *__restrict__ box_start,
+                                                      const cpx<float> *__restrict__ R,
+                                                      const cpx<float> *__restrict__ Q, const float *__restrict__ wq,
+                                                      const cpx<float> *__restrict__ V, cpx<float> *__restrict__ Y,
+                                                      int nrhs)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nrg = (nrhs + 16 * RT - 1) / (16 * RT);
+    const long long blk = xcd_block_m((long long)nbox * nrg);
+    if (blk < 0) return;
+    const int b = (int)(blk / nrg), rg = (int)(blk % nrg);
+    const int n0 = box_start[b], rows = 2 * (box_start[b + 1] - n0);
+    const int lo = lane & 15, kk = lane >> 4;
+    const cpx<float> *pat = op == MLFMA_OP_EM ? R : Q;
+    const bool cj = op == MLFMA_OP_EM;
+    for (int tile = wave; tile * 16 < rows; tile += 4) {
+        const int row = tile * 16 + lo;
+        const bool mok = row < rows;
+        const int m = n0 + (mok ? row / 2 : 0), h = row & 1;
+        const cpx<float> *pm = pat + (long long)m * K * 2;
+        f4 dre[RT], dim[RT];
+#pragma unroll
+        for (int u = 0; u < RT; u++) dre[u] = dim[u] = f4{0, 0, 0, 0};
+        for (int c = 0; c < 2; c++) {
+            const cpx<float> *Vc = V + pidx_m(b, c, 0, 0, nrhs, K);
+            for (int q0 = 0; q0 < K; q0 += 4) {
+                const int q = q0 + kk;
+                const bool qok = q < K;
+                cpx<float> a = mk<float>(0, 0);
+                if (mok && qok) {
+                    cpx<float> pt = pm[2 * q], pp = pm[2 * q + 1];
+                    if (cj) {
+                        pt = conjg(pt);
+                        pp = conjg(pp);
+                    }
+                    const cpx<float> sel = h == 0 ? (c == 0 ? pt : pp) : (c == 0 ? pp : mk<float>(-pt.re, -pt.im));
+                    a = wq[q] * sel;
+                }
+#pragma unroll
+                for (int u = 0; u < RT; u++) {
+                    const int r = (rg * RT + u) * 16 + lo;
+                    const cpx<float> bv = (qok && r < nrhs) ? Vc[(long long)r * K + q] : mk<float>(0, 0);
+                    // here the lane supplies A(row lo, k) and B(k, rhs lo)
+                    dre[u] = mfma4(a.re, bv.re, dre[u]);
+                    dim[u] = mfma4(a.re, bv.im, dim[u]);
+                    dre[u] = mfma4(-a.im, bv.im, dre[u]);
+                    dim[u] = mfma4(a.im, bv.re, dim[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RT; u++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int orow = tile * 16 + kk * 4 + v, r = (rg * RT + u) * 16 + lo;
+                if (orow < rows && r < nrhs) {
+                    cpx<float> &y = Y[((long long)(n0 + orow / 2) * 2 + (orow & 1)) * nrhs + r];
+                    y = y + mk<float>(dre[u][v], dim[u][v]);
+                }
+            }
+    }
+}
+
+}  // namespace
+
+bool launch_radiate_mfma(int op, int nbox, int K, const int *box_start, const cpx<float> *R, const cpx<float> *X,
+                         cpx<float> *U, int nrhs, hipStream_t s)
+{
+    if (nrhs < 16) return false;
+    const int nqt = (K + 15) / 16, per_box = (2 * nqt + 3) / 4;
+    const int rt = nrhs >= 64 ? 4 : (nrhs >= 32 ? 2 : 1);
+    const long long nblk = (long long)nbox * per_box * ((nrhs + 16 * rt - 1) / (16 * rt));
+    if (nblk <= 0) return true;
+    const dim3 grid(xcd_grid_m(nblk)), block(256);
+    if (rt == 4) hipLaunchKernelGGL(k_radiate_mfma<4>, grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
+    else if (rt == 2) hipLaunchKernelGGL(k_radiate_mfma<2>, grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
+    else hipLaunchKernelGGL(k_radiate_mfma<1>, grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
+    return true;
+}
+
+bool launch_receive_mfma(int op, int nbox, int K, const int *box_start, const cpx<float> *R, const cpx<float> *Q,
+                         const float *wq, const cpx<float> *V, cpx<float> *Y, int nrhs, hipStream_t s)
+{
+    if (nrhs < 16) return false;
+    // one rhs tile per workgroup: more workgroups, the box's patterns stay in L2
+    const long long nblk = (long long)nbox * ((nrhs + 15) / 16);
+    if (nblk <= 0) return true;
+    hipLaunchKernelGGL(k_receive_mfma<1>, dim3(xcd_grid_m(nblk)), dim3(256), 0, s, op, nbox, K, box_start, R, Q, wq,
+                       V, Y, nrhs);
+    return true;
+}
+
+}  // namespace mlfma
