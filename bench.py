@@ -43,6 +43,9 @@ def parse():
     p.add_argument("--digits", type=int, default=3, help="MLFMA accuracy parameter d0")
     p.add_argument("--serve-requests", type=int, default=512,
                    help="requests of the serving measurement (0 = skip it)")
+    p.add_argument("--copy-probe-mib", type=int, default=0,
+                   help="after the bench, run a plain elementwise copy (torch.neg) over this many MiB of float32 "
+                        "three times: the reference kernel that calibrates HBM byte counters")
     return p.parse_args()
 
 
@@ -247,6 +250,13 @@ def main():
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+    if a.copy_probe_mib > 0:
+        n = a.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -114,6 +114,11 @@ struct mlfma_ctx {
     int *perm = nullptr, *iperm = nullptr, *leaf_of = nullptr, *box_start = nullptr;
     int *near_start = nullptr, *near_box = nullptr, *id_start = nullptr, *id_col = nullptr;
     long long *val_off = nullptr;
+    // matrix-core near field and receive: (leaf box, row tile) work items and
+    // the column lists of the near-field block rows
+    int n_items = 0;
+    int2 *items = nullptr;
+    int *col_off = nullptr, *cols = nullptr;
     // geometry on the device (internal RWG order): triangles and RWG pieces
     int *g_rtri = nullptr, *g_rloc = nullptr;
     double *g_rcoef = nullptr, *g_tv = nullptr, *g_tn = nullptr, *g_ta = nullptr;
@@ -269,6 +274,21 @@ void build_device_tables(mlfma_ctx *c)
     c->box_start = c->upload(tr.box_start);
     c->near_start = c->upload(tr.near_start);
     c->near_box = c->upload(tr.near_box);
+    {
+        std::vector<int2> items;
+        std::vector<int> off(1, 0), cols;
+        for (size_t b = 0; b + 1 < tr.box_start.size(); b++) {
+            const int rows = 2 * (tr.box_start[b + 1] - tr.box_start[b]);
+            for (int t = 0; t * 16 < rows; t++) items.push_back(make_int2((int)b, t));
+            for (int e = tr.near_start[b]; e < tr.near_start[b + 1]; e++)
+                for (int i = tr.box_start[tr.near_box[e]]; i < tr.box_start[tr.near_box[e] + 1]; i++) cols.push_back(i);
+            off.push_back((int)cols.size());
+        }
+        c->n_items = (int)items.size();
+        c->items = c->upload(items);
+        c->col_off = c->upload(off);
+        c->cols = c->upload(cols);
+    }
     c->lv.assign(tr.levels, IntLevel());
     std::vector<std::vector<cdouble>> trans(tr.levels), shift(tr.levels);
     for (int l = 2; l < tr.levels; l++) {
@@ -706,12 +726,19 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     const int only_level = part >= MLFMA_PART_LEVEL ? part - MLFMA_PART_LEVEL : -1;
     const bool want_near = only_level < 0 && (part & MLFMA_PART_NEAR);
     const bool want_far = only_level >= 0 || (part & MLFMA_PART_FAR);
-    if (want_near)
-        launch_near<T>(N, c->leaf_of, c->box_start, c->near_start, c->near_box, c->val_off,
-                       op == MLFMA_OP_EM ? P.near_em : P.near_c, op == MLFMA_OP_C ? c->id_start : nullptr, c->id_col,
-                       P.id_w, X, Y, nrhs, st);
-    else
+    if (want_near) {
+        const cpx<T> *vals = op == MLFMA_OP_EM ? P.near_em : P.near_c;
+        const int *ids = op == MLFMA_OP_C ? c->id_start : nullptr;
+        bool done = false;
+        if constexpr (std::is_same<T, float>::value)
+            done = launch_near_mfma(c->n_items, c->items, c->box_start, c->col_off, c->cols, c->val_off, vals, ids,
+                                    c->id_col, P.id_w, X, Y, nrhs, st);
+        if (!done)
+            launch_near<T>(N, c->leaf_of, c->box_start, c->near_start, c->near_box, c->val_off, vals, ids, c->id_col,
+                           P.id_w, X, Y, nrhs, st);
+    } else {
         launch_zero<T>(Y, (long long)N * 2 * nrhs, st);
+    }
     mark(2);
     const bool far = tr.levels >= 3 && want_far;
     if (far) {
@@ -788,8 +815,8 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     if (far) {
         bool done = false;
         if constexpr (std::is_same<T, float>::value)
-            done = launch_receive_mfma(op, Lf.nbox, Lf.K, c->box_start, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], Y,
-                                       nrhs, st);
+            done = launch_receive_mfma(op, c->n_items, c->items, Lf.K, c->box_start, P.R, P.Q, P.wq,
+                                       (cpx<T> *)w.V[leafl], Y, nrhs, st);
         if (!done) launch_receive<T>(op, N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], Y, nrhs, st);
     }
     mark(7);

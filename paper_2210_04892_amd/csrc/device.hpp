@@ -156,12 +156,19 @@ bool launch_aggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s);
 template <class T>
 bool launch_disaggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s);
 
-// Radiation and receive on the matrix cores (mfma.hip), complex float and
-// at least 16 right-hand sides; return false otherwise
+// Radiation on the matrix cores (mfma.hip), complex float and at least 16
+// right-hand sides; return false otherwise
 bool launch_radiate_mfma(int op, int nbox, int K, const int *box_start, const cpx<float> *R, const cpx<float> *X,
                          cpx<float> *U, int nrhs, hipStream_t s);
-bool launch_receive_mfma(int op, int nbox, int K, const int *box_start, const cpx<float> *R, const cpx<float> *Q,
-                         const float *wq, const cpx<float> *V, cpx<float> *Y, int nrhs, hipStream_t s);
+// Near field and receive on the matrix cores (complex float, 16+ right-hand
+// sides).  items = (leaf box, row tile of 16 rows) pairs; cols[col_off[b] ..]
+// = the RWGs of leaf box b's adjacent boxes in block-row order.
+bool launch_near_mfma(int nitem, const int2 *items, const int *box_start, const int *col_off, const int *cols,
+                      const long long *val_off, const cpx<float> *vals, const int *id_start, const int *id_col,
+                      const float *id_w, const cpx<float> *X, cpx<float> *Y, int nrhs, hipStream_t s);
+bool launch_receive_mfma(int op, int nitem, const int2 *items, int K, const int *box_start, const cpx<float> *R,
+                         const cpx<float> *Q, const float *wq, const cpx<float> *V, cpx<float> *Y, int nrhs,
+                         hipStream_t s);
 
 template <class T>
 void launch_disagg_mid(int nchild, int mid_len, int Kp, const int *parent, const int *oct, const cpx<T> *shift,

@@ -109,76 +109,172 @@ __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, i
         }
 }
 
-// Receive.  Workgroup = (box, group of RT x 16 right-hand sides); wave w takes
-// the box's row tiles w, w + 4, ... of 16 rows (RWG m, half h);
-// D[i = (m, h)][j = rhs], inner index k = (component, sample), four samples
-// per MFMA step.  Rows: h = 0 uses (Pt, Pp), h = 1 uses (Pp, -Pt), with
-// P = conj(R) for the EM pair and P = Q for the C block, weights wq folded in.
-template <int RT>
-__global__ __launch_bounds__(256) void k_receive_mfma(int op, int nbox, int K, const int *__restrict__ box_start,
+// Receive.  Work item = (leaf box, row tile of 16 rows (RWG m, half h),
+// tile of 16 right-hand sides), one per wave, right-hand-side tiles
+// innermost; D[i = (m, h)][j = rhs], inner index k = (component, sample),
+// four samples per MFMA step, the next step's operands loaded before the
+// current step's MFMAs.  Rows: h = 0 uses (Pt, Pp), h = 1 uses (Pp, -Pt),
+// with P = conj(R) for the EM pair and P = Q for the C block, weights wq
+// folded in.
+__global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const int2 *__restrict__ items, int K,
+                                                      const int *__restrict__ box_start,
                                                       const cpx<float> *__restrict__ R,
                                                       const cpx<float> *__restrict__ Q, const float *__restrict__ wq,
                                                       const cpx<float> *__restrict__ V, cpx<float> *__restrict__ Y,
                                                       int nrhs)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nrg = (nrhs + 16 * RT - 1) / (16 * RT);
-    const long long blk = xcd_block_m((long long)nbox * nrg);
+    const int nrt = (nrhs + 15) / 16;
+    const long long blk = xcd_block_m(((long long)nitem * nrt + 3) / 4);
     if (blk < 0) return;
-    const int b = (int)(blk / nrg), rg = (int)(blk % nrg);
+    const long long w = blk * 4 + wave;
+    if (w >= (long long)nitem * nrt) return;
+    const int2 it = items[w / nrt];
+    const int rt = (int)(w % nrt);
+    const int b = it.x, tile = it.y;
     const int n0 = box_start[b], rows = 2 * (box_start[b + 1] - n0);
     const int lo = lane & 15, kk = lane >> 4;
     const cpx<float> *pat = op == MLFMA_OP_EM ? R : Q;
     const bool cj = op == MLFMA_OP_EM;
-    for (int tile = wave; tile * 16 < rows; tile += 4) {
-        const int row = tile * 16 + lo;
-        const bool mok = row < rows;
-        const int m = n0 + (mok ? row / 2 : 0), h = row & 1;
-        const cpx<float> *pm = pat + (long long)m * K * 2;
-        f4 dre[RT], dim[RT];
+    const int kq = (K + 3) / 4, nstep = 2 * kq;     // (component, 4 samples) steps
+    const int row = tile * 16 + lo, r = rt * 16 + lo;
+    const bool mok = row < rows, rok = r < nrhs;
+    const int h = row & 1;
+    const cpx<float> *pm = pat + (long long)(n0 + (mok ? row / 2 : 0)) * K * 2;
+    auto load = [&](int step, cpx<float> &a, cpx<float> &bv) {
+        const int c = step / kq, q = (step % kq) * 4 + kk;
+        const bool qok = q < K;
+        a = mk<float>(0, 0);
+        bv = mk<float>(0, 0);
+        if (mok && qok) {
+            cpx<float> pt = pm[2 * q], pp = pm[2 * q + 1];
+            if (cj) {
+                pt = conjg(pt);
+                pp = conjg(pp);
+            }
+            const cpx<float> sel = h == 0 ? (c == 0 ? pt : pp) : (c == 0 ? pp : mk<float>(-pt.re, -pt.im));
+            a = wq[q] * sel;
+        }
+        if (qok && rok) bv = V[pidx_m(b, c, r, q, nrhs, K)];
+    };
+    f4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+    cpx<float> a, bv, an, bn;
+    load(0, a, bv);
+    for (int step = 0; step < nstep; step++) {
+        if (step + 1 < nstep) load(step + 1, an, bn);
+        dre = mfma4(a.re, bv.re, dre);
+        dim = mfma4(a.re, bv.im, dim);
+        dre = mfma4(-a.im, bv.im, dre);
+        dim = mfma4(a.im, bv.re, dim);
+        a = an;
+        bv = bn;
+    }
 #pragma unroll
-        for (int u = 0; u < RT; u++) dre[u] = dim[u] = f4{0, 0, 0, 0};
-        for (int c = 0; c < 2; c++) {
-            const cpx<float> *Vc = V + pidx_m(b, c, 0, 0, nrhs, K);
-            for (int q0 = 0; q0 < K; q0 += 4) {
-                const int q = q0 + kk;
-                const bool qok = q < K;
-                cpx<float> a = mk<float>(0, 0);
-                if (mok && qok) {
-                    cpx<float> pt = pm[2 * q], pp = pm[2 * q + 1];
-                    if (cj) {
-                        pt = conjg(pt);
-                        pp = conjg(pp);
-                    }
-                    const cpx<float> sel = h == 0 ? (c == 0 ? pt : pp) : (c == 0 ? pp : mk<float>(-pt.re, -pt.im));
-                    a = wq[q] * sel;
-                }
+    for (int v = 0; v < 4; v++) {
+        const int orow = tile * 16 + kk * 4 + v;
+        if (orow < rows && rok) {
+            cpx<float> &y = Y[((long long)(n0 + orow / 2) * 2 + (orow & 1)) * nrhs + r];
+            y = y + mk<float>(dre[v], dim[v]);
+        }
+    }
+}
+
+// Near field.  Work item = (leaf box b, row tile of 16 rows (RWG m, half
+// h), tile of 16 right-hand sides), one per wave, right-hand-side tiles
+// innermost so that neighbouring waves share the value rows.  The box's
+// columns are the RWGs of its <= 27 adjacent boxes, concatenated (the order
+// the stored (A, B) rows follow), listed in cols[col_off[b] ..].
+// D[i = (m, h)][j = rhs] with inner index k = (column, half h'): two columns
+// per MFMA step, the next step's operands loaded before the current step's
+// MFMAs.  The 2 x 2 block of a pair is [[A, -B], [B, A]].  The identity
+// terms of the C block (Gram and rotated Gram, same triangle only) are added
+// in the epilogue; Y is overwritten.
+__global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__restrict__ items,
+                                                   const int *__restrict__ box_start,
+                                                   const int *__restrict__ col_off, const int *__restrict__ cols,
+                                                   const long long *__restrict__ val_off,
+                                                   const cpx<float> *__restrict__ vals,
+                                                   const int *__restrict__ id_start, const int *__restrict__ id_col,
+                                                   const float *__restrict__ id_w, const cpx<float> *__restrict__ X,
+                                                   cpx<float> *__restrict__ Y, int nrhs)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nrt = (nrhs + 15) / 16;
+    const long long blk = xcd_block_m(((long long)nitem * nrt + 3) / 4);
+    if (blk < 0) return;
+    const long long w = blk * 4 + wave;
+    if (w >= (long long)nitem * nrt) return;
+    const int2 it = items[w / nrt];
+    const int rt = (int)(w % nrt);
+    const int b = it.x, tile = it.y;
+    const int n0 = box_start[b], rows = 2 * (box_start[b + 1] - n0);
+    const int *cl = cols + col_off[b];
+    const int ncols = col_off[b + 1] - col_off[b];
+    const int lo = lane & 15, kk = lane >> 4;
+    const int jc = kk >> 1, hp = kk & 1;
+    const int row = tile * 16 + lo, r = rt * 16 + lo;
+    const bool mok = row < rows, rok = r < nrhs;
+    const int h = row & 1;
+    const cpx<float> *vr = vals + 2 * (val_off[b] + (long long)(mok ? row / 2 : 0) * ncols);
+    auto load = [&](int j0, cpx<float> &a, cpx<float> &bv) {
+        const int j = j0 + jc;
+        const bool jok = j < ncols;
+        a = mk<float>(0, 0);
+        bv = mk<float>(0, 0);
+        if (jok && mok) {
+            const cpx<float> A = vr[2 * j], B = vr[2 * j + 1];
+            a = h == hp ? A : (h == 0 ? mk<float>(-B.re, -B.im) : B);
+        }
+        if (jok && rok) bv = X[((long long)cl[j] * 2 + hp) * nrhs + r];
+    };
+    f4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+    cpx<float> a, bv, an, bn;
+    load(0, a, bv);
+    for (int j0 = 0; j0 < ncols; j0 += 2) {
+        if (j0 + 2 < ncols) load(j0 + 2, an, bn);
+        dre = mfma4(a.re, bv.re, dre);
+        dim = mfma4(a.re, bv.im, dim);
+        dre = mfma4(-a.im, bv.im, dre);
+        dim = mfma4(a.im, bv.re, dim);
+        a = an;
+        bv = bn;
+    }
 #pragma unroll
-                for (int u = 0; u < RT; u++) {
-                    const int r = (rg * RT + u) * 16 + lo;
-                    const cpx<float> bv = (qok && r < nrhs) ? Vc[(long long)r * K + q] : mk<float>(0, 0);
-                    // here the lane supplies A(row lo, k) and B(k, rhs lo)
-                    dre[u] = mfma4(a.re, bv.re, dre[u]);
-                    dim[u] = mfma4(a.re, bv.im, dim[u]);
-                    dre[u] = mfma4(-a.im, bv.im, dre[u]);
-                    dim[u] = mfma4(a.im, bv.re, dim[u]);
+    for (int v = 0; v < 4; v++) {
+        const int orow = tile * 16 + kk * 4 + v;
+        if (orow >= rows || !rok) continue;
+        const int m = n0 + orow / 2, oh = orow & 1;
+        cpx<float> y = mk<float>(dre[v], dim[v]);
+        if (id_start) {
+            for (int e = id_start[m]; e < id_start[m + 1]; e++) {
+                const long long col = id_col[e];
+                const float g = id_w[2 * e], gx = id_w[2 * e + 1];
+                const cpx<float> x1 = X[(col * 2) * nrhs + r], x2 = X[(col * 2 + 1) * nrhs + r];
+                if (oh == 0) {
+                    axpy_to(y, g, x1);
+                    axpy_to(y, 0.5f * gx, x2);
+                } else {
+                    axpy_to(y, 0.5f * g, x2);
                 }
             }
         }
-#pragma unroll
-        for (int u = 0; u < RT; u++)
-#pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int orow = tile * 16 + kk * 4 + v, r = (rg * RT + u) * 16 + lo;
-                if (orow < rows && r < nrhs) {
-                    cpx<float> &y = Y[((long long)(n0 + orow / 2) * 2 + (orow & 1)) * nrhs + r];
-                    y = y + mk<float>(dre[u][v], dim[u][v]);
-                }
-            }
+        Y[((long long)m * 2 + oh) * nrhs + r] = y;
     }
 }
 
 }  // namespace
+
+bool launch_near_mfma(int nitem, const int2 *items, const int *box_start, const int *col_off, const int *cols,
+                      const long long *val_off, const cpx<float> *vals, const int *id_start, const int *id_col,
+                      const float *id_w, const cpx<float> *X, cpx<float> *Y, int nrhs, hipStream_t s)
+{
+    if (nrhs < 16 || !items || !cols) return false;
+    const long long nblk = ((long long)nitem * ((nrhs + 15) / 16) + 3) / 4;
+    if (nblk <= 0) return true;
+    hipLaunchKernelGGL(k_near_mfma, dim3(xcd_grid_m(nblk)), dim3(256), 0, s, nitem, items, box_start, col_off, cols,
+                       val_off, vals, id_start, id_col, id_w, X, Y, nrhs);
+    return true;
+}
 
 bool launch_radiate_mfma(int op, int nbox, int K, const int *box_start, const cpx<float> *R, const cpx<float> *X,
                          cpx<float> *U, int nrhs, hipStream_t s)
@@ -195,15 +291,15 @@ bool launch_radiate_mfma(int op, int nbox, int K, const int *box_start, const cp
     return true;
 }
 
-bool launch_receive_mfma(int op, int nbox, int K, const int *box_start, const cpx<float> *R, const cpx<float> *Q,
-                         const float *wq, const cpx<float> *V, cpx<float> *Y, int nrhs, hipStream_t s)
+bool launch_receive_mfma(int op, int nitem, const int2 *items, int K, const int *box_start, const cpx<float> *R,
+                         const cpx<float> *Q, const float *wq, const cpx<float> *V, cpx<float> *Y, int nrhs,
+                         hipStream_t s)
 {
-    if (nrhs < 16) return false;
-    // one rhs tile per workgroup: more workgroups, the box's patterns stay in L2
-    const long long nblk = (long long)nbox * ((nrhs + 15) / 16);
+    if (nrhs < 16 || !items) return false;
+    const long long nblk = ((long long)nitem * ((nrhs + 15) / 16) + 3) / 4;
     if (nblk <= 0) return true;
-    hipLaunchKernelGGL(k_receive_mfma<1>, dim3(xcd_grid_m(nblk)), dim3(256), 0, s, op, nbox, K, box_start, R, Q, wq,
-                       V, Y, nrhs);
+    hipLaunchKernelGGL(k_receive_mfma, dim3(xcd_grid_m(nblk)), dim3(256), 0, s, op, nitem, items, K, box_start, R, Q,
+                       wq, V, Y, nrhs);
     return true;
 }
 

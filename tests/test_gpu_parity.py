@@ -145,6 +145,32 @@ def test_multi_rhs(nrhs):
             assert max(errs) <= MLFMA_TOL
 
 
+@pytest.mark.parametrize("nrhs", [1, 20, 64])
+@pytest.mark.parametrize("op", ["C", "EM"])
+def test_single_precision_parts(nrhs, op):
+    """complex64 near and far parts against the complex128 parts of the same
+    tree and tables.  One right-hand side runs the vector kernels; 20 and 64
+    run the matrix-core near field, radiation and receive (with a ragged
+    16-wide tile at 20).  The near parts differ by single-precision rounding
+    (about 1e-7).  The far parts differ by up to about 1e-3 of the far part:
+    at the finest levels the diagonal translation operators reach 1e4-1e5
+    in magnitude and the k-space sum cancels them to O(1), which amplifies
+    the rounding of the stored single-precision values.  The far part is a
+    few percent of the product, so the whole complex64 product stays within
+    the MLFMA tolerance of the oracle (test_mlfma_matvec)."""
+    import paper_2210_04892_amd as mf
+    name = "sphere_r0.5"
+    v, t = mesh(name)
+    N = 3 * len(t) // 2
+    x = synth.gaussian_coeffs(2 * N, nrhs, 11)
+    for part, tol in ((mf.PART_NEAR, 2e-5), (mf.PART_FAR, 2e-3)):
+        y64 = _gpu(name, x, op, np.complex128, part=part)
+        y32 = _gpu(name, x, op, np.complex64, part=part)
+        err = _rel(y32, y64)
+        print("[gpu] nrhs %d op %s part %d: complex64 vs complex128 rel diff %.2e" % (nrhs, op, part, err), flush=True)
+        assert err <= tol
+
+
 def test_tiny_mesh_is_all_near():
     """A mesh smaller than three octree levels has no far field: the whole
     product is the double-precision near field."""
