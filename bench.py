@@ -194,6 +194,7 @@ def main():
         }
         ys[name] = yt.t().cpu().numpy().astype(np.complex128)
     hbm_bytes = g.hbm_bytes
+    tuning = g.tuning()
     # consistency of the two precisions (same tables, same tree)
     d = np.linalg.norm(ys["c64"] - ys["c128"]) / np.linalg.norm(ys["c128"])
     cpu = None
@@ -247,6 +248,7 @@ def main():
         "near_GBs": {"c64": head["near_roofline_GBs"], "c128": results["c128"]["near_roofline_GBs"]},
         "setup_s": {"tree_tables_patterns": round(t1 - t0, 3), "near_field": round(t2 - t1, 3)},
         "hbm_bytes": hbm_bytes,
+        "translation_tile_shape": tuning,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

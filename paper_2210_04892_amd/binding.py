@@ -64,6 +64,7 @@ def lib():
         L.mlfma_last_error.restype = ctypes.c_char_p
         L.mlfma_translation_operator.argtypes = [ctypes.c_double, ctypes.c_int, P, LL, P, P]
         L.mlfma_near_info.argtypes = [P, P]
+        L.mlfma_tuning.argtypes = [P, ctypes.c_int, P, P]
         L.mlfma_plane_wave_rhs.argtypes = [P, ctypes.c_int, LL, P, P, P, LL, P]
         L.mlfma_server_opts_default.argtypes = [ctypes.POINTER(ServerOptions)]
         L.mlfma_server_create.argtypes = [ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
@@ -160,6 +161,17 @@ class Geometry:
         _check(lib().mlfma_near_info(self._h, info.ctypes.data))
         return {"slots": int(info[0]), "identity": int(info[1]), "touching_pairs": int(info[2]),
                 "leaf_boxes": int(info[3])}
+
+    def tuning(self):
+        """Translation tile shape picked by the autotuner, per precision:
+        {"c64": (targets per tile, sources per batch, ms), "c128": ...}."""
+        out = {}
+        for name, dt in (("c64", C64), ("c128", C128)):
+            sh = np.zeros(2, np.int32)
+            ms = ctypes.c_double(0)
+            _check(lib().mlfma_tuning(self._h, dt, sh.ctypes.data, ctypes.byref(ms)))
+            out[name] = (int(sh[0]), int(sh[1]), float(ms.value))
+        return out
 
     def profile(self, enable=True):
         _check(lib().mlfma_profile(self._h, 1 if enable else 0))

@@ -73,6 +73,8 @@ struct Prec {
     cpx<T> *near_em = nullptr, *near_c = nullptr; // near blocks, (A, B) per slot
     T *id_w = nullptr;                            // identity terms (gram, gx)
     std::vector<PrecLevel<T>> lv;
+    int trans_tmax = 0, trans_smax = 0;           // translation tile shape (autotuned)
+    double trans_ms = 0;                          // its timed translation, ms
 };
 
 struct IntLevel {
@@ -242,16 +244,6 @@ void upload_level_tables(mlfma_ctx *c, Prec<T> &P, const std::vector<std::vector
     P.lv.assign(tr.levels, PrecLevel<T>());
     for (int l = 2; l < tr.levels; l++) {
         P.lv[l].trans = c->upload(cast_cvec<T>(trans[l]));
-        TransTiles tt;
-        build_translation_tiles(tr.lv[l], trans_smax<T>(), TRANS_TMAX, tt);
-        P.lv[l].ntile = (int)tt.tile_tgt.size() - 1;
-        P.lv[l].tile_tgt = c->upload(tt.tile_tgt);
-        P.lv[l].tile_bat = c->upload(tt.tile_bat);
-        P.lv[l].bat_src = c->upload(tt.bat_src);
-        P.lv[l].src = c->upload(tt.src);
-        P.lv[l].bat_row = c->upload(tt.bat_row);
-        P.lv[l].row = c->upload(tt.row);
-        P.lv[l].ent = c->upload(tt.ent);
         if (l + 1 < tr.levels) {
             P.lv[l].shift = c->upload(cast_cvec<T>(shift[l]));
             P.lv[l].ath_w = c->upload(cast_vec<T>(tr.agg_theta[l].w));
@@ -261,6 +253,120 @@ void upload_level_tables(mlfma_ctx *c, Prec<T> &P, const std::vector<std::vector
             plan_level_steps<T>(c, l, P.lv[l]);
         }
     }
+}
+
+// translation tiles of every level for one tile shape; allocations go to
+// `list` (tuning trials) or to the handle
+template <class T>
+void upload_trans_tiles(mlfma_ctx *c, Prec<T> &P, int tmax, int smax, std::vector<void *> *list)
+{
+    const Tree &tr = c->tr;
+    for (int l = 2; l < tr.levels; l++) {
+        TransTiles tt;
+        build_translation_tiles(tr.lv[l], smax, tmax, tt);
+        PrecLevel<T> &PL = P.lv[l];
+        auto up = [&](const std::vector<int> &v) {
+            int *d = c->dalloc<int>(v.size(), list);
+            if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice));
+            return d;
+        };
+        PL.ntile = (int)tt.tile_tgt.size() - 1;
+        PL.tile_tgt = up(tt.tile_tgt);
+        PL.tile_bat = up(tt.tile_bat);
+        PL.bat_src = up(tt.bat_src);
+        PL.src = up(tt.src);
+        PL.bat_row = up(tt.bat_row);
+        PL.row = up(tt.row);
+        PL.ent = up(tt.ent);
+    }
+    P.trans_tmax = tmax;
+    P.trans_smax = smax;
+}
+
+// translation arguments of every level (only_level >= 0: that level alone)
+template <class T>
+TransArgs<T> trans_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level)
+{
+    const Tree &tr = c->tr;
+    TransArgs<T> ta;
+    ta.smax = P.trans_smax;
+    ta.tmax = P.trans_tmax;
+    for (int l = 2; l < tr.levels; l++) {
+        if (only_level >= 0 && l != only_level) continue;
+        const PrecLevel<T> &PL = P.lv[l];
+        TransLevel<T> &d = ta.lv[ta.nlev++];
+        d.K = tr.lv[l].K;
+        d.ntile = PL.ntile;
+        d.tile_tgt = PL.tile_tgt;
+        d.tile_bat = PL.tile_bat;
+        d.bat_src = PL.bat_src;
+        d.src = PL.src;
+        d.bat_row = PL.bat_row;
+        d.row = PL.row;
+        d.ent = PL.ent;
+        d.trans = PL.trans;
+        d.U = (const cpx<T> *)w.U[l];
+        d.V = (cpx<T> *)w.V[l];
+    }
+    return ta;
+}
+
+// Autotuner of the translation tile shape: every candidate (targets per
+// tile, sources per LDS batch) that fits 64 KB of LDS is built and its
+// translation of all levels timed on the device (HIP events, one warm-up
+// and three timed launches with the right-hand-side count the handle is
+// built for, capped at 16); the fastest shape is kept.
+template <class T>
+void tune_translation(mlfma_ctx *c, Prec<T> &P)
+{
+    const Tree &tr = c->tr;
+    if (tr.levels < 3) {
+        upload_trans_tiles<T>(c, P, 8, 16, nullptr);
+        return;
+    }
+    const int nrhs = std::min(c->opt.max_rhs, 16);
+    static const int shapes[][2] = {{4, 16}, {8, 16}, {8, 32}, {16, 32}, {16, 64}};
+    hipStream_t st;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best = 1e300;
+    int bt = 0, bs = 0;
+    for (auto &sh : shapes) {
+        const int tmax = sh[0], smax = sh[1];
+        if (!trans_shape_ok(tmax, smax) || trans_lds_bytes<T>(smax) > 64 * 1024) continue;
+        struct Trial {
+            mlfma_ctx *c;
+            unsigned long long b0;
+            std::vector<void *> list;
+            ~Trial()
+            {
+                for (void *p : list) (void)hipFree(p);
+                c->bytes = b0;
+            }
+        } trial{c, c->bytes, {}};
+        std::vector<void *> &list = trial.list;
+        upload_trans_tiles<T>(c, P, tmax, smax, &list);
+        const TransArgs<T> ta = trans_args<T>(c, P, c->ws, -1);
+        if (!launch_translate_tiled<T>(ta, nrhs, st)) throw Error(MLFMA_ERR_HIP, "invalid translation tile shape");
+        HIPCHK(hipEventRecord(e0, st));
+        for (int i = 0; i < 3; i++) launch_translate_tiled<T>(ta, nrhs, st);
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            bt = tmax;
+            bs = smax;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    upload_trans_tiles<T>(c, P, bt, bs, nullptr);
+    P.trans_ms = best / 3;
 }
 
 void build_device_tables(mlfma_ctx *c)
@@ -770,30 +876,11 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     }
     mark(4);
     if (far) {
-        TransArgs<T> ta;
-        ta.smax = trans_smax<T>();
-        for (int l = 2; l <= leafl; l++) {
-            const Level &L = tr.lv[l];
-            const PrecLevel<T> &PL = P.lv[l];
-            if (only_level >= 0 && l != only_level) {
-                launch_zero<T>((cpx<T> *)w.V[l], (long long)L.nbox * L.K * 2 * nrhs, st);
-                continue;
-            }
-            TransLevel<T> &d = ta.lv[ta.nlev++];
-            d.K = L.K;
-            d.ntile = PL.ntile;
-            d.tile_tgt = PL.tile_tgt;
-            d.tile_bat = PL.tile_bat;
-            d.bat_src = PL.bat_src;
-            d.src = PL.src;
-            d.bat_row = PL.bat_row;
-            d.row = PL.row;
-            d.ent = PL.ent;
-            d.trans = PL.trans;
-            d.U = (const cpx<T> *)w.U[l];
-            d.V = (cpx<T> *)w.V[l];
-        }
-        launch_translate_tiled<T>(ta, nrhs, st);
+        for (int l = 2; l <= leafl; l++)
+            if (only_level >= 0 && l != only_level)
+                launch_zero<T>((cpx<T> *)w.V[l], (long long)tr.lv[l].nbox * tr.lv[l].K * 2 * nrhs, st);
+        if (!launch_translate_tiled<T>(trans_args<T>(c, P, w, only_level), nrhs, st))
+            throw Error(MLFMA_ERR_STATE, "translation tiles missing");
     }
     mark(5);
     if (far) {
@@ -874,6 +961,8 @@ int mlfma_build_tree(const double *verts, long long n_verts, const int *tris, lo
         DeviceGuard g(dev);
         build_device_tables(c.get());
         ensure_workspace(c.get(), c->opt.max_rhs);
+        tune_translation<double>(c.get(), c->p64);
+        tune_translation<float>(c.get(), c->p32);
         *out = c.release();
         return MLFMA_OK;
     } catch (const Error &e) {
@@ -987,6 +1076,15 @@ int mlfma_level_info(mlfma_handle h, int level, long long info[6])
     info[3] = (long long)L.il_box.size();
     info[4] = (long long)std::llround(L.a * 1e6);
     info[5] = 0;
+    return MLFMA_OK;
+}
+
+int mlfma_tuning(mlfma_handle h, int dtype, int shape[2], double *ms)
+{
+    if (!h || !shape || (dtype != MLFMA_C128 && dtype != MLFMA_C64)) return fail(Error(MLFMA_ERR_ARG, "bad argument"));
+    shape[0] = dtype == MLFMA_C64 ? h->p32.trans_tmax : h->p64.trans_tmax;
+    shape[1] = dtype == MLFMA_C64 ? h->p32.trans_smax : h->p64.trans_smax;
+    if (ms) *ms = dtype == MLFMA_C64 ? h->p32.trans_ms : h->p64.trans_ms;
     return MLFMA_OK;
 }
 

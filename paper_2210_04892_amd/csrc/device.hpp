@@ -93,13 +93,19 @@ void launch_agg_phi(int nparent, int Kp, int mid_len, const int *child_start, co
 // tables of build_translation_tiles (device copies), the level's translation
 // operators (343 offsets x K samples) and its outgoing/incoming patterns.
 constexpr int TRANS_MAXLEV = 20;   // the octree has at most 20 levels
-constexpr int TRANS_TMAX = 16;      // targets per tile = waves per workgroup
-// sources per LDS batch: a batch holds 2 components x 64 (sample, rhs) lanes
-// of every source in 32 KB
+// Tile shape of the translation: tmax targets per tile (= waves per
+// workgroup, at most TRANS_TMAX_MAX) and smax sources per LDS batch (a
+// target's entries in one batch are fetched by the lanes of one wave, so
+// smax <= 64, and each wave stages at most TRANS_ROWS (source, component)
+// rows, so 2 smax <= TRANS_ROWS tmax).
+constexpr int TRANS_TMAX_MAX = 16;
+constexpr int TRANS_ROWS = 8;
+inline bool trans_shape_ok(int tmax, int smax)
+{
+    return tmax >= 1 && tmax <= TRANS_TMAX_MAX && smax >= 1 && smax <= 64 && 2 * smax <= TRANS_ROWS * tmax;
+}
 template <class T>
-constexpr int trans_smax() { return (32 * 1024) / (2 * 64 * (int)sizeof(cpx<T>)); }
-// a target's entries in one batch are fetched by the lanes of one wave
-static_assert(trans_smax<float>() <= 64 && trans_smax<double>() <= 64, "translation batch wider than a wave");
+inline size_t trans_lds_bytes(int smax) { return (size_t)smax * 2 * 64 * sizeof(cpx<T>); }
 template <class T>
 struct TransLevel {
     int K = 0, ntile = 0;
@@ -111,11 +117,12 @@ struct TransLevel {
 };
 template <class T>
 struct TransArgs {
-    int nlev = 0, nblocks = 0, smax = 0;
+    int nlev = 0, nblocks = 0, smax = 0, tmax = 0;
     TransLevel<T> lv[TRANS_MAXLEV];
 };
+// false when the tile shape is invalid
 template <class T>
-void launch_translate_tiled(const TransArgs<T> &a, int nrhs, hipStream_t s);
+bool launch_translate_tiled(const TransArgs<T> &a, int nrhs, hipStream_t s);
 // One octree step of aggregation (children at level l+1 -> parents at l) or
 // disaggregation (parents -> children), done per box and chunk of theta rows
 // in LDS (levels.hip).  Sample index = theta row * nph + phi column.

@@ -542,10 +542,9 @@ typedef const __attribute__((address_space(4))) int cint;
 __device__ inline int ld_uniform(const int *p, int i) { return ((cint *)p)[i]; }
 
 template <class T, int RW>
-__global__ __launch_bounds__(TRANS_TMAX * WAVE) void k_translate_tiled(const TransArgs<T> a, int nrhs)
+__global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const TransArgs<T> a, int nrhs)
 {
     constexpr int QW = WAVE / RW;
-    constexpr int ROWS = (2 * trans_smax<T>() + TRANS_TMAX - 1) / TRANS_TMAX;   // staged rows per wave
     constexpr int UNR = sizeof(T) == 4 ? 16 : 8;                                // operator loads in flight
     extern __shared__ double trans_lds_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(trans_lds_raw);
@@ -559,6 +558,7 @@ __global__ __launch_bounds__(TRANS_TMAX * WAVE) void k_translate_tiled(const Tra
     const int K = L.K;
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int nwave = blockDim.x / WAVE;
     const int qi = lane % QW, ri = lane / QW;
     const int q = qc * QW + qi, r = blockIdx.y * RW + ri;
     const bool ok = q < K && r < nrhs;
@@ -569,19 +569,19 @@ __global__ __launch_bounds__(TRANS_TMAX * WAVE) void k_translate_tiled(const Tra
     cpx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
     for (int b = b0; b < b1; b++) {
         const int s0 = ld_uniform(L.bat_src, b), ns = ld_uniform(L.bat_src, b + 1) - s0;
-        // stage: wave w copies (source, component) rows w, w + TRANS_TMAX, ...;
+        // stage: wave w copies (source, component) rows w, w + nwave, ...;
         // every load of the batch is issued before the first store
-        cpx<T> st[ROWS];
+        cpx<T> st[TRANS_ROWS];
 #pragma unroll
-        for (int i = 0; i < ROWS; i++) {
-            const int sc = wave + i * TRANS_TMAX;
+        for (int i = 0; i < TRANS_ROWS; i++) {
+            const int sc = wave + i * nwave;
             st[i] = mk<T>(0, 0);
             if (sc < 2 * ns && ok) st[i] = Uq[pidx(ld_uniform(L.src, s0 + sc / 2), sc & 1, 0, 0, nrhs, K)];
         }
         if (b > b0) __syncthreads();   // every wave is done with the previous batch
 #pragma unroll
-        for (int i = 0; i < ROWS; i++) {
-            const int sc = wave + i * TRANS_TMAX;
+        for (int i = 0; i < TRANS_ROWS; i++) {
+            const int sc = wave + i * nwave;
             if (sc < 2 * ns) lds[sc * WAVE + lane] = st[i];
         }
         __syncthreads();
@@ -857,9 +857,10 @@ void launch_agg_phi(int nparent, int Kp, int mid_len, const int *child_start, co
 static inline int trans_rw(int nrhs) { return nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1); }
 
 template <class T>
-void launch_translate_tiled(const TransArgs<T> &args, int nrhs, hipStream_t s)
+bool launch_translate_tiled(const TransArgs<T> &args, int nrhs, hipStream_t s)
 {
-    if (args.nlev <= 0 || nrhs <= 0) return;
+    if (!trans_shape_ok(args.tmax, args.smax)) return false;
+    if (args.nlev <= 0 || nrhs <= 0) return true;
     const int rw = trans_rw(nrhs), qw = WAVE / rw;
     TransArgs<T> a = args;
     a.nblocks = 0;
@@ -868,15 +869,16 @@ void launch_translate_tiled(const TransArgs<T> &args, int nrhs, hipStream_t s)
         a.lv[l].first = a.nblocks;
         a.nblocks += a.lv[l].ntile * a.lv[l].nqc;
     }
-    if (a.nblocks <= 0) return;
-    const size_t lds = (size_t)a.smax * 2 * WAVE * sizeof(cpx<T>);
-    const dim3 grid(xcd_grid(a.nblocks), (nrhs + rw - 1) / rw), block(TRANS_TMAX * WAVE);
+    if (a.nblocks <= 0) return true;
+    const size_t lds = trans_lds_bytes<T>(a.smax);
+    const dim3 grid(xcd_grid(a.nblocks), (nrhs + rw - 1) / rw), block(a.tmax * WAVE);
     if (rw == 4)
         hipLaunchKernelGGL((k_translate_tiled<T, 4>), grid, block, lds, s, a, nrhs);
     else if (rw == 2)
         hipLaunchKernelGGL((k_translate_tiled<T, 2>), grid, block, lds, s, a, nrhs);
     else
         hipLaunchKernelGGL((k_translate_tiled<T, 1>), grid, block, lds, s, a, nrhs);
+    return true;
 }
 
 template <class T>
@@ -923,7 +925,7 @@ void launch_receive(int op, int N, int K, const int *leaf_of, const cpx<T> *R, c
                                    int, bool, hipStream_t);                                                       \
     template void launch_agg_phi<T>(int, int, int, const int *, const int *, const cpx<T> *, const int *,        \
                                     const int *, const T *, const cpx<T> *, cpx<T> *, int, hipStream_t);          \
-    template void launch_translate_tiled<T>(const TransArgs<T> &, int, hipStream_t);                             \
+    template bool launch_translate_tiled<T>(const TransArgs<T> &, int, hipStream_t);                             \
     template void launch_disagg_mid<T>(int, int, int, const int *, const int *, const cpx<T> *, const int *,     \
                                        const int *, const T *, const cpx<T> *, cpx<T> *, int, hipStream_t);       \
     template void launch_zero<T>(cpx<T> *, long long, hipStream_t);                                               \
