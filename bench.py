@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP32_PEAK_TFS = 157.3          # MI355X vector FP32
+FP32_PEAK_TFS = 157.3          # MI355X FP32, vector and dense MFMA alike
 FP64_PEAK_TFS = 78.6           # MI355X vector FP64
 
 
@@ -73,6 +73,37 @@ def stage_bytes(g, levels_info, n, nrhs, esz, op):
     return b, ni
 
 
+def kernel_sources_sha1():
+    """sha1 over the library's kernel and ABI sources (file name, then bytes)."""
+    import glob
+    import hashlib
+    h = hashlib.sha1()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2210_04892_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "mlfma.h"))
+    for f in files:
+        if f.endswith((".hip", ".cpp", ".hpp", ".h")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, stage):
+    """Calibrated HBM bytes per product of one stage from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (profiles/traffic.json), or None
+    when they were taken on other kernel sources than the ones built now."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha1") != kernel_sources_sha1():
+        return None
+    st = t.get("workloads", {}).get(workload, {}).get("stages", {}).get(stage)
+    return None if st is None else st["bytes"]
+
+
 def stage_flops(g, levels_info, n, nrhs, op, taps):
     """Algorithmic real flops of each stage for one product (complex
     multiply-add = 8, real-times-complex multiply-add = 4)."""
@@ -98,15 +129,20 @@ def stage_flops(g, levels_info, n, nrhs, op, taps):
     return f
 
 
-def roofline(stage, secs, nbytes, nflops, dtype_bits):
-    """Roofline of one stage: bound by HBM bytes or by vector-ALU flops,
-    whichever takes longer at the published peaks."""
+MFMA_STAGES = ("near", "radiate", "receive")   # on the matrix cores for complex64 and 16+ RHS
+
+
+def roofline(stage, secs, nbytes, nflops, dtype_bits, nrhs=1):
+    """Roofline of one stage: bound by HBM bytes or by flops (vector ALU, or
+    the matrix cores for the stages that run on them), whichever takes longer
+    at the published peaks."""
     fpeak = FP32_PEAK_TFS if dtype_bits == 32 else FP64_PEAK_TFS
+    mfma = dtype_bits == 32 and nrhs >= 16 and stage in MFMA_STAGES
     t_mem = nbytes / (HBM_PEAK_GBS * 1e9)
     t_alu = nflops / (fpeak * 1e12)
     if t_alu > t_mem:
         ach = nflops / secs / 1e12
-        return {"bound": "alu", "achieved": round(ach, 2), "peak": fpeak, "unit": "TFLOP/s",
+        return {"bound": "mfma" if mfma else "alu", "achieved": round(ach, 2), "peak": fpeak, "unit": "TFLOP/s",
                 "frac": round(ach / fpeak, 4), "traffic": None, "kernel": stage,
                 "algorithmic_flops": int(nflops), "algorithmic_bytes": int(nbytes)}
     ach = nbytes / secs / 1e9
@@ -180,7 +216,7 @@ def main():
         sf = stage_flops(g, levels_info, N, nrhs, a.op, a.interp_order)
         per = {s: stages[s] / max(calls, 1) for s in stages}
         dom = max(per, key=per.get)
-        rl = roofline(dom, per[dom] * 1e-3, sb[dom], sf.get(dom, 0), 32 if name == "c64" else 64)
+        rl = roofline(dom, per[dom] * 1e-3, sb[dom], sf.get(dom, 0), 32 if name == "c64" else 64, nrhs)
         results[name] = {
             "ms_per_step": ms, "wall_ms_per_step": (w1 - w0) * 1e3 / a.steps,
             "value": 2 * N * nrhs / (ms * 1e-3),
@@ -188,7 +224,7 @@ def main():
             "dominant": dom,
             "roofline": rl,
             "stage_roofline": {st_: roofline(st_, per[st_] * 1e-3, sb[st_], sf.get(st_, 0),
-                                             32 if name == "c64" else 64)["frac"]
+                                             32 if name == "c64" else 64, nrhs)["frac"]
                                for st_ in per if per[st_] > 0 and st_ in sb},
             "near_roofline_GBs": round(sb["near"] / (per["near"] * 1e-3) / 1e9, 1),
         }
@@ -225,6 +261,7 @@ def main():
         serving = srv.run(synth.serving_set(5), n_requests=a.serve_requests, seed=5,
                           log=lambda m: print(m, file=sys.stderr, flush=True))
     head = results["c64"]
+    head["roofline"]["traffic"] = measured_traffic(spec["name"], head["roofline"]["kernel"])
     out = {
         "metric": "MLFMA L/K matvec unknowns*RHS/s at <=1e-3 rel err vs FP64; p50/p99 latency",
         "value": round(head["value"], 1),
