@@ -199,13 +199,13 @@ int mlfma_level_info(mlfma_handle h, int level, long long info[6]);
 int mlfma_near_info(mlfma_handle h, long long info[4]);
 
 /* Translation tile shape chosen by the autotuner that mlfma_build_tree runs
- * (Sec. II-E diagonal translations; every shape that fits 64 KB of LDS is
- * timed on the device with the handle's right-hand-side count, capped at
- * 16): shape[0] = target boxes per tile (= waves per workgroup), shape[1] =
- * source boxes per LDS batch; *ms (may be NULL) = the timed translation of
- * all levels, milliseconds.  dtype MLFMA_C128 or MLFMA_C64; MLFMA_ERR_ARG
- * otherwise. */
-int mlfma_tuning(mlfma_handle h, int dtype, int shape[2], double *ms);
+ * (Sec. II-E diagonal translations; every shape within the kernel's LDS and
+ * register limits is timed on the device with the handle's right-hand-side
+ * count, capped at 16): shape[0] = target boxes per tile (= waves per
+ * workgroup), shape[1] = source boxes per LDS batch, shape[2] = right-hand
+ * sides per lane; *ms (may be NULL) = the timed translation of all levels,
+ * milliseconds.  dtype MLFMA_C128 or MLFMA_C64; MLFMA_ERR_ARG otherwise. */
+int mlfma_tuning(mlfma_handle h, int dtype, int shape[3], double *ms);
 
 /*
  * Stage timing with HIP events recorded on the matvec's stream.  Stages:

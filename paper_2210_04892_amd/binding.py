@@ -164,13 +164,13 @@ class Geometry:
 
     def tuning(self):
         """Translation tile shape picked by the autotuner, per precision:
-        {"c64": (targets per tile, sources per batch, ms), "c128": ...}."""
+        {"c64": (targets per tile, sources per batch, rhs per lane, ms), "c128": ...}."""
         out = {}
         for name, dt in (("c64", C64), ("c128", C128)):
-            sh = np.zeros(2, np.int32)
+            sh = np.zeros(3, np.int32)
             ms = ctypes.c_double(0)
             _check(lib().mlfma_tuning(self._h, dt, sh.ctypes.data, ctypes.byref(ms)))
-            out[name] = (int(sh[0]), int(sh[1]), float(ms.value))
+            out[name] = (int(sh[0]), int(sh[1]), int(sh[2]), float(ms.value))
         return out
 
     def profile(self, enable=True):

@@ -73,7 +73,7 @@ struct Prec {
     cpx<T> *near_em = nullptr, *near_c = nullptr; // near blocks, (A, B) per slot
     T *id_w = nullptr;                            // identity terms (gram, gx)
     std::vector<PrecLevel<T>> lv;
-    int trans_tmax = 0, trans_smax = 0;           // translation tile shape (autotuned)
+    int trans_tmax = 0, trans_smax = 0, trans_rb = 1;   // translation tile shape (autotuned)
     double trans_ms = 0;                          // its timed translation, ms
 };
 
@@ -291,6 +291,7 @@ TransArgs<T> trans_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level)
     TransArgs<T> ta;
     ta.smax = P.trans_smax;
     ta.tmax = P.trans_tmax;
+    ta.rb = P.trans_rb;
     for (int l = 2; l < tr.levels; l++) {
         if (only_level >= 0 && l != only_level) continue;
         const PrecLevel<T> &PL = P.lv[l];
@@ -312,60 +313,67 @@ TransArgs<T> trans_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level)
 }
 
 // Autotuner of the translation tile shape: every candidate (targets per
-// tile, sources per LDS batch) that fits 64 KB of LDS is built and its
-// translation of all levels timed on the device (HIP events, one warm-up
-// and three timed launches with the right-hand-side count the handle is
-// built for, capped at 16); the fastest shape is kept.
+// tile 4/8/16, LDS batch of 16/32/64 KB, 1/2/4 right-hand sides per lane)
+// that satisfies the kernel's limits is built and its translation of all
+// levels timed on the device (HIP events, one warm-up and three timed
+// launches with the right-hand-side count the handle is built for, capped at
+// 16); the fastest shape is kept.
 template <class T>
 void tune_translation(mlfma_ctx *c, Prec<T> &P)
 {
     const Tree &tr = c->tr;
     if (tr.levels < 3) {
+        P.trans_rb = 1;
         upload_trans_tiles<T>(c, P, 8, 16, nullptr);
         return;
     }
     const int nrhs = std::min(c->opt.max_rhs, 16);
-    static const int shapes[][2] = {{4, 16}, {8, 16}, {8, 32}, {16, 32}, {16, 64}};
     hipStream_t st;
     HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     double best = 1e300;
-    int bt = 0, bs = 0;
-    for (auto &sh : shapes) {
-        const int tmax = sh[0], smax = sh[1];
-        if (!trans_shape_ok(tmax, smax) || trans_lds_bytes<T>(smax) > 64 * 1024) continue;
-        struct Trial {
-            mlfma_ctx *c;
-            unsigned long long b0;
-            std::vector<void *> list;
-            ~Trial()
-            {
-                for (void *p : list) (void)hipFree(p);
-                c->bytes = b0;
+    int bt = 0, bs = 0, bb = 1;
+    for (int rb : {1, 2, 4}) {
+        if (rb > 1 && (trans_rw(nrhs) != 4 || nrhs < 4 * rb)) continue;
+        for (int tmax : {4, 8, 16})
+            for (int kb : {16, 32, 64}) {
+                const int smax = (kb * 1024) / (int)(2 * 64 * rb * sizeof(cpx<T>));
+                if (!trans_shape_ok(tmax, smax, rb)) continue;
+                struct Trial {
+                    mlfma_ctx *c;
+                    unsigned long long b0;
+                    std::vector<void *> list;
+                    ~Trial()
+                    {
+                        for (void *p : list) (void)hipFree(p);
+                        c->bytes = b0;
+                    }
+                } trial{c, c->bytes, {}};
+                upload_trans_tiles<T>(c, P, tmax, smax, &trial.list);
+                P.trans_rb = rb;
+                const TransArgs<T> ta = trans_args<T>(c, P, c->ws, -1);
+                if (!launch_translate_tiled<T>(ta, nrhs, st)) throw Error(MLFMA_ERR_HIP, "invalid translation tile shape");
+                HIPCHK(hipEventRecord(e0, st));
+                for (int i = 0; i < 3; i++) launch_translate_tiled<T>(ta, nrhs, st);
+                HIPCHK(hipEventRecord(e1, st));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    bt = tmax;
+                    bs = smax;
+                    bb = rb;
+                }
             }
-        } trial{c, c->bytes, {}};
-        std::vector<void *> &list = trial.list;
-        upload_trans_tiles<T>(c, P, tmax, smax, &list);
-        const TransArgs<T> ta = trans_args<T>(c, P, c->ws, -1);
-        if (!launch_translate_tiled<T>(ta, nrhs, st)) throw Error(MLFMA_ERR_HIP, "invalid translation tile shape");
-        HIPCHK(hipEventRecord(e0, st));
-        for (int i = 0; i < 3; i++) launch_translate_tiled<T>(ta, nrhs, st);
-        HIPCHK(hipEventRecord(e1, st));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
-            bt = tmax;
-            bs = smax;
-        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(st);
     upload_trans_tiles<T>(c, P, bt, bs, nullptr);
+    P.trans_rb = bb;
     P.trans_ms = best / 3;
 }
 
@@ -1079,11 +1087,12 @@ int mlfma_level_info(mlfma_handle h, int level, long long info[6])
     return MLFMA_OK;
 }
 
-int mlfma_tuning(mlfma_handle h, int dtype, int shape[2], double *ms)
+int mlfma_tuning(mlfma_handle h, int dtype, int shape[3], double *ms)
 {
     if (!h || !shape || (dtype != MLFMA_C128 && dtype != MLFMA_C64)) return fail(Error(MLFMA_ERR_ARG, "bad argument"));
     shape[0] = dtype == MLFMA_C64 ? h->p32.trans_tmax : h->p64.trans_tmax;
     shape[1] = dtype == MLFMA_C64 ? h->p32.trans_smax : h->p64.trans_smax;
+    shape[2] = dtype == MLFMA_C64 ? h->p32.trans_rb : h->p64.trans_rb;
     if (ms) *ms = dtype == MLFMA_C64 ? h->p32.trans_ms : h->p64.trans_ms;
     return MLFMA_OK;
 }

@@ -94,18 +94,22 @@ void launch_agg_phi(int nparent, int Kp, int mid_len, const int *child_start, co
 // operators (343 offsets x K samples) and its outgoing/incoming patterns.
 constexpr int TRANS_MAXLEV = 20;   // the octree has at most 20 levels
 // Tile shape of the translation: tmax targets per tile (= waves per
-// workgroup, at most TRANS_TMAX_MAX) and smax sources per LDS batch (a
-// target's entries in one batch are fetched by the lanes of one wave, so
-// smax <= 64, and each wave stages at most TRANS_ROWS (source, component)
-// rows, so 2 smax <= TRANS_ROWS tmax).
+// workgroup, at most TRANS_TMAX_MAX), smax sources per LDS batch and rb
+// right-hand sides per lane (1, 2 or 4; above 1 only with four right-hand
+// sides across the lanes of a wave).  A target's entries in one batch are
+// fetched by the lanes of one wave, so smax <= 64, and each wave stages at
+// most TRANS_ROWS rows of 64 lanes, so 2 smax rb <= TRANS_ROWS tmax.
 constexpr int TRANS_TMAX_MAX = 16;
 constexpr int TRANS_ROWS = 8;
-inline bool trans_shape_ok(int tmax, int smax)
+inline bool trans_shape_ok(int tmax, int smax, int rb)
 {
-    return tmax >= 1 && tmax <= TRANS_TMAX_MAX && smax >= 1 && smax <= 64 && 2 * smax <= TRANS_ROWS * tmax;
+    return tmax >= 1 && tmax <= TRANS_TMAX_MAX && smax >= 1 && smax <= 64 && (rb == 1 || rb == 2 || rb == 4) &&
+           2 * smax * rb <= TRANS_ROWS * tmax;
 }
 template <class T>
-inline size_t trans_lds_bytes(int smax) { return (size_t)smax * 2 * 64 * sizeof(cpx<T>); }
+inline size_t trans_lds_bytes(int smax, int rb) { return (size_t)smax * 2 * 64 * rb * sizeof(cpx<T>); }
+// right-hand sides across the lanes of a wave
+inline int trans_rw(int nrhs) { return nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1); }
 template <class T>
 struct TransLevel {
     int K = 0, ntile = 0;
@@ -117,7 +121,7 @@ struct TransLevel {
 };
 template <class T>
 struct TransArgs {
-    int nlev = 0, nblocks = 0, smax = 0, tmax = 0;
+    int nlev = 0, nblocks = 0, smax = 0, tmax = 0, rb = 1;
     TransLevel<T> lv[TRANS_MAXLEV];
 };
 // false when the tile shape is invalid

@@ -541,11 +541,12 @@ __global__ __launch_bounds__(256) void k_agg_phi(int nparent, int Kp, int mid_le
 typedef const __attribute__((address_space(4))) int cint;
 __device__ inline int ld_uniform(const int *p, int i) { return ((cint *)p)[i]; }
 
-template <class T, int RW>
+template <class T, int RW, int RB>
 __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const TransArgs<T> a, int nrhs)
 {
     constexpr int QW = WAVE / RW;
-    constexpr int UNR = sizeof(T) == 4 ? 16 : 8;                                // operator loads in flight
+    constexpr int UNR = (sizeof(T) == 4 ? 16 : 8) / (RB > 2 ? 2 : 1);   // operator loads in flight
+    constexpr int SRC = 2 * RB * WAVE;                                  // LDS elements per staged source
     extern __shared__ double trans_lds_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(trans_lds_raw);
     const long long blk = xcd_block(a.nblocks);
@@ -560,29 +561,35 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int nwave = blockDim.x / WAVE;
     const int qi = lane % QW, ri = lane / QW;
-    const int q = qc * QW + qi, r = blockIdx.y * RW + ri;
-    const bool ok = q < K && r < nrhs;
-    const cpx<T> *tq = L.trans + (q < K ? q : K - 1);
-    const cpx<T> *Uq = L.U + pidx(0, 0, r < nrhs ? r : nrhs - 1, q < K ? q : K - 1, nrhs, K);
+    const int q = qc * QW + qi;
+    const int rbase = blockIdx.y * RW * RB + ri;   // this lane's right-hand sides: rbase + j RW, j < RB
+    const bool qok = q < K;
+    const cpx<T> *tq = L.trans + (qok ? q : K - 1);
+    const cpx<T> *Uq = L.U + (qok ? q : K - 1);
     const int t0 = ld_uniform(L.tile_tgt, tile), nt = ld_uniform(L.tile_tgt, tile + 1) - t0;
     const int b0 = ld_uniform(L.tile_bat, tile), b1 = ld_uniform(L.tile_bat, tile + 1);
-    cpx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
+    cpx<T> a0[RB], a1[RB];
+#pragma unroll
+    for (int j = 0; j < RB; j++) a0[j] = a1[j] = mk<T>(0, 0);
     for (int b = b0; b < b1; b++) {
         const int s0 = ld_uniform(L.bat_src, b), ns = ld_uniform(L.bat_src, b + 1) - s0;
-        // stage: wave w copies (source, component) rows w, w + nwave, ...;
-        // every load of the batch is issued before the first store
+        // stage: LDS row (source s, component c, register j) holds 64 lanes;
+        // wave w copies rows w, w + nwave, ...; every load of the batch is
+        // issued before the first store
         cpx<T> st[TRANS_ROWS];
 #pragma unroll
         for (int i = 0; i < TRANS_ROWS; i++) {
             const int sc = wave + i * nwave;
             st[i] = mk<T>(0, 0);
-            if (sc < 2 * ns && ok) st[i] = Uq[pidx(ld_uniform(L.src, s0 + sc / 2), sc & 1, 0, 0, nrhs, K)];
+            const int j = sc % RB, c = (sc / RB) & 1, rr = rbase + j * RW;
+            if (sc < 2 * RB * ns && qok && rr < nrhs)
+                st[i] = Uq[pidx(ld_uniform(L.src, s0 + sc / (2 * RB)), c, rr, 0, nrhs, K)];
         }
         if (b > b0) __syncthreads();   // every wave is done with the previous batch
 #pragma unroll
         for (int i = 0; i < TRANS_ROWS; i++) {
             const int sc = wave + i * nwave;
-            if (sc < 2 * ns) lds[sc * WAVE + lane] = st[i];
+            if (sc < 2 * RB * ns) lds[sc * WAVE + lane] = st[i];
         }
         __syncthreads();
         if (wave >= nt) continue;
@@ -599,22 +606,34 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
             for (int u = 0; u < UNR; u++) t[u] = tq[(long long)(v[u] >> 16) * K];
 #pragma unroll
             for (int u = 0; u < UNR; u++) {
-                const cpx<T> *p = lds + (v[u] & 0xffff) * 2 * WAVE + lane;
-                fma_to(a0, t[u], p[0]);
-                fma_to(a1, t[u], p[WAVE]);
+                const cpx<T> *p = lds + (v[u] & 0xffff) * SRC + lane;
+#pragma unroll
+                for (int j = 0; j < RB; j++) {
+                    fma_to(a0[j], t[u], p[j * WAVE]);
+                    fma_to(a1[j], t[u], p[(RB + j) * WAVE]);
+                }
             }
         }
         for (; e < n; e++) {
             const int v = __builtin_amdgcn_readlane(mine, e);
             const cpx<T> t = tq[(long long)(v >> 16) * K];
-            const cpx<T> *p = lds + (v & 0xffff) * 2 * WAVE + lane;
-            fma_to(a0, t, p[0]);
-            fma_to(a1, t, p[WAVE]);
+            const cpx<T> *p = lds + (v & 0xffff) * SRC + lane;
+#pragma unroll
+            for (int j = 0; j < RB; j++) {
+                fma_to(a0[j], t, p[j * WAVE]);
+                fma_to(a1[j], t, p[(RB + j) * WAVE]);
+            }
         }
     }
-    if (wave < nt && ok) {
-        L.V[pidx(t0 + wave, 0, r, q, nrhs, K)] = a0;
-        L.V[pidx(t0 + wave, 1, r, q, nrhs, K)] = a1;
+    if (wave < nt && qok) {
+#pragma unroll
+        for (int j = 0; j < RB; j++) {
+            const int rr = rbase + j * RW;
+            if (rr < nrhs) {
+                L.V[pidx(t0 + wave, 0, rr, q, nrhs, K)] = a0[j];
+                L.V[pidx(t0 + wave, 1, rr, q, nrhs, K)] = a1[j];
+            }
+        }
     }
 }
 
@@ -853,16 +872,17 @@ void launch_agg_phi(int nparent, int Kp, int mid_len, const int *child_start, co
     });
 }
 
-// right-hand sides per wave for the tiled translation
-static inline int trans_rw(int nrhs) { return nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1); }
 
 template <class T>
 bool launch_translate_tiled(const TransArgs<T> &args, int nrhs, hipStream_t s)
 {
-    if (!trans_shape_ok(args.tmax, args.smax)) return false;
+    if (!trans_shape_ok(args.tmax, args.smax, args.rb)) return false;
     if (args.nlev <= 0 || nrhs <= 0) return true;
-    const int rw = trans_rw(nrhs), qw = WAVE / rw;
+    // right-hand sides per lane only when four of them span the lanes (the
+    // tiles do not depend on it, and one per lane needs less LDS)
+    const int rw = trans_rw(nrhs), qw = WAVE / rw, rb = rw == 4 ? args.rb : 1;
     TransArgs<T> a = args;
+    a.rb = rb;
     a.nblocks = 0;
     for (int l = 0; l < a.nlev; l++) {
         a.lv[l].nqc = (a.lv[l].K + qw - 1) / qw;
@@ -870,14 +890,18 @@ bool launch_translate_tiled(const TransArgs<T> &args, int nrhs, hipStream_t s)
         a.nblocks += a.lv[l].ntile * a.lv[l].nqc;
     }
     if (a.nblocks <= 0) return true;
-    const size_t lds = trans_lds_bytes<T>(a.smax);
-    const dim3 grid(xcd_grid(a.nblocks), (nrhs + rw - 1) / rw), block(a.tmax * WAVE);
-    if (rw == 4)
-        hipLaunchKernelGGL((k_translate_tiled<T, 4>), grid, block, lds, s, a, nrhs);
+    const size_t lds = trans_lds_bytes<T>(a.smax, rb);
+    const dim3 grid(xcd_grid(a.nblocks), (nrhs + rw * rb - 1) / (rw * rb)), block(a.tmax * WAVE);
+    if (rw == 4 && rb == 4)
+        hipLaunchKernelGGL((k_translate_tiled<T, 4, 4>), grid, block, lds, s, a, nrhs);
+    else if (rw == 4 && rb == 2)
+        hipLaunchKernelGGL((k_translate_tiled<T, 4, 2>), grid, block, lds, s, a, nrhs);
+    else if (rw == 4)
+        hipLaunchKernelGGL((k_translate_tiled<T, 4, 1>), grid, block, lds, s, a, nrhs);
     else if (rw == 2)
-        hipLaunchKernelGGL((k_translate_tiled<T, 2>), grid, block, lds, s, a, nrhs);
+        hipLaunchKernelGGL((k_translate_tiled<T, 2, 1>), grid, block, lds, s, a, nrhs);
     else
-        hipLaunchKernelGGL((k_translate_tiled<T, 1>), grid, block, lds, s, a, nrhs);
+        hipLaunchKernelGGL((k_translate_tiled<T, 1, 1>), grid, block, lds, s, a, nrhs);
     return true;
 }
 
