@@ -37,33 +37,41 @@ __device__ inline long long pat(long long b, int c, int r, int q, int nrhs, int 
 constexpr int STEP_THREADS = 256;
 constexpr int STEP_OUT = 4;     // outputs per thread: a chunk has at most 4 * 256 of them
 
-// aggregation: workgroup = (parent, chunk of parent theta rows), one rhs
-template <class T, int P>
+// aggregation: workgroup = (parent, chunk of parent theta rows, RB
+// right-hand sides); the stencil taps are loaded once for all RB of them
+// (the launcher uses RB = 1)
+template <class T, int P, int RB>
 __global__ __launch_bounds__(STEP_THREADS) void k_aggregate(const LevelStep<T> a, int nrhs)
 {
     extern __shared__ double step_lds_raw[];
     const long long blk = xcd_block_l((long long)a.nbox * a.nchunk);
     if (blk < 0) return;
     const int Pb = (int)(blk / a.nchunk), ch = (int)(blk % a.nchunk);
-    const int r = blockIdx.y;
+    const int r0 = blockIdx.y * RB;
     const int Kc = a.nth_c * a.nph_c, Kp = a.nth_p * a.nph_p;
     const int i0 = ch * a.rows, i1 = min(a.nth_p, i0 + a.rows);
     const int w0 = a.win[2 * ch], w1 = a.win[2 * ch + 1];
     const int wlen = (w1 - w0) * a.nph_c, wmax = a.wrows * a.nph_c;
     const int mlen = (i1 - i0) * a.nph_c, mmax = a.rows * a.nph_c;
     const int olen = (i1 - i0) * a.nph_p;
-    cpx<T> *cw = reinterpret_cast<cpx<T> *>(step_lds_raw);   // [2][wmax] child window
-    cpx<T> *mid = cw + 2 * wmax;                              // [2][mmax] intermediate
-    cpx<T> acc0[STEP_OUT], acc1[STEP_OUT];
+    cpx<T> *cw = reinterpret_cast<cpx<T> *>(step_lds_raw);   // [RB][2][wmax] child windows
+    cpx<T> *mid = cw + 2 * RB * wmax;                         // [RB][2][mmax] intermediates
+    cpx<T> acc0[STEP_OUT][RB], acc1[STEP_OUT][RB];
 #pragma unroll
-    for (int k = 0; k < STEP_OUT; k++) acc0[k] = acc1[k] = mk<T>(0, 0);
+    for (int k = 0; k < STEP_OUT; k++)
+#pragma unroll
+        for (int j = 0; j < RB; j++) acc0[k][j] = acc1[k][j] = mk<T>(0, 0);
     const int cb = a.child_start[Pb], ce = a.child_start[Pb + 1];
     for (int c = cb; c < ce; c++) {
-        const cpx<T> *u0 = a.in + pat(c, 0, r, w0 * a.nph_c, nrhs, Kc);
-        const cpx<T> *u1 = a.in + pat(c, 1, r, w0 * a.nph_c, nrhs, Kc);
-        for (int i = threadIdx.x; i < wlen; i += STEP_THREADS) {
-            cw[i] = u0[i];
-            cw[wmax + i] = u1[i];
+#pragma unroll
+        for (int j = 0; j < RB; j++) {
+            const int r = min(r0 + j, nrhs - 1);
+            const cpx<T> *u0 = a.in + pat(c, 0, r, w0 * a.nph_c, nrhs, Kc);
+            const cpx<T> *u1 = a.in + pat(c, 1, r, w0 * a.nph_c, nrhs, Kc);
+            for (int i = threadIdx.x; i < wlen; i += STEP_THREADS) {
+                cw[(2 * j) * wmax + i] = u0[i];
+                cw[(2 * j + 1) * wmax + i] = u1[i];
+            }
         }
         __syncthreads();
         // theta: mid row (parent theta i, child phi j) from the child window
@@ -76,14 +84,18 @@ __global__ __launch_bounds__(STEP_THREADS) void k_aggregate(const LevelStep<T> a
                 cc[t] = a.c1[row * P + t] - w0 * a.nph_c;
                 ww[t] = a.w1[row * P + t];
             }
-            cpx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
 #pragma unroll
-            for (int t = 0; t < P; t++) {
-                axpy_to(s0, ww[t], cw[cc[t]]);
-                axpy_to(s1, ww[t], cw[wmax + cc[t]]);
+            for (int j = 0; j < RB; j++) {
+                const cpx<T> *w0p = cw + (2 * j) * wmax, *w1p = cw + (2 * j + 1) * wmax;
+                cpx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+#pragma unroll
+                for (int t = 0; t < P; t++) {
+                    axpy_to(s0, ww[t], w0p[cc[t]]);
+                    axpy_to(s1, ww[t], w1p[cc[t]]);
+                }
+                mid[(2 * j) * mmax + m] = s0;
+                mid[(2 * j + 1) * mmax + m] = s1;
             }
-            mid[m] = s0;
-            mid[mmax + m] = s1;
         }
         __syncthreads();
         // phi, then the shift to the parent centre
@@ -93,127 +105,182 @@ __global__ __launch_bounds__(STEP_THREADS) void k_aggregate(const LevelStep<T> a
             const int o = threadIdx.x + k * STEP_THREADS;
             if (o < olen) {
                 const long long q = (long long)i0 * a.nph_p + o;
-                cpx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+                int cc[P];
+                T ww[P];
 #pragma unroll
                 for (int t = 0; t < P; t++) {
-                    const int j = a.c2[q * P + t] - i0 * a.nph_c;
-                    const T wt = a.w2[q * P + t];
-                    axpy_to(s0, wt, mid[j]);
-                    axpy_to(s1, wt, mid[mmax + j]);
+                    cc[t] = a.c2[q * P + t] - i0 * a.nph_c;
+                    ww[t] = a.w2[q * P + t];
                 }
                 const cpx<T> f = sh[q];
-                fma_to(acc0[k], f, s0);
-                fma_to(acc1[k], f, s1);
+#pragma unroll
+                for (int j = 0; j < RB; j++) {
+                    const cpx<T> *m0 = mid + (2 * j) * mmax, *m1 = mid + (2 * j + 1) * mmax;
+                    cpx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+#pragma unroll
+                    for (int t = 0; t < P; t++) {
+                        axpy_to(s0, ww[t], m0[cc[t]]);
+                        axpy_to(s1, ww[t], m1[cc[t]]);
+                    }
+                    fma_to(acc0[k][j], f, s0);
+                    fma_to(acc1[k][j], f, s1);
+                }
             }
         }
-        __syncthreads();   // the next child reuses the window and the intermediate
+        __syncthreads();   // the next child reuses the windows and the intermediates
     }
 #pragma unroll
     for (int k = 0; k < STEP_OUT; k++) {
         const int o = threadIdx.x + k * STEP_THREADS;
-        if (o < olen) {
-            const int q = i0 * a.nph_p + o;
-            a.out[pat(Pb, 0, r, q, nrhs, Kp)] = acc0[k];
-            a.out[pat(Pb, 1, r, q, nrhs, Kp)] = acc1[k];
+        if (o >= olen) continue;
+        const int q = i0 * a.nph_p + o;
+#pragma unroll
+        for (int j = 0; j < RB; j++) {
+            if (r0 + j >= nrhs) continue;
+            a.out[pat(Pb, 0, r0 + j, q, nrhs, Kp)] = acc0[k][j];
+            a.out[pat(Pb, 1, r0 + j, q, nrhs, Kp)] = acc1[k][j];
         }
     }
 }
 
-// disaggregation: workgroup = (child, chunk of child theta rows), one rhs;
-// out (the child's incoming pattern) += anterpolated, shifted parent pattern
-template <class T>
+// disaggregation: workgroup = (child, chunk of child theta rows, RB
+// right-hand sides); out (the child's incoming pattern) += anterpolated,
+// shifted parent pattern
+template <class T, int RB>
 __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate(const LevelStep<T> a, int nrhs)
 {
     extern __shared__ double step_lds_raw[];
     const long long blk = xcd_block_l((long long)a.nbox * a.nchunk);
     if (blk < 0) return;
     const int c = (int)(blk / a.nchunk), ch = (int)(blk % a.nchunk);
-    const int r = blockIdx.y;
+    const int r0 = blockIdx.y * RB;
     const int Kc = a.nth_c * a.nph_c, Kp = a.nth_p * a.nph_p;
     const int i0 = ch * a.rows, i1 = min(a.nth_c, i0 + a.rows);
     const int w0 = a.win[2 * ch], w1 = a.win[2 * ch + 1];
     const int plen = (w1 - w0) * a.nph_p, pmax = a.wrows * a.nph_p;
     const int mlen = (w1 - w0) * a.nph_c, mmax = a.wrows * a.nph_c;
     const int olen = (i1 - i0) * a.nph_c;
-    cpx<T> *pw = reinterpret_cast<cpx<T> *>(step_lds_raw);   // [2][pmax] shifted parent rows
-    cpx<T> *mid = pw + 2 * pmax;                              // [2][mmax] intermediate rows
+    cpx<T> *pw = reinterpret_cast<cpx<T> *>(step_lds_raw);   // [RB][2][pmax] shifted parent rows
+    cpx<T> *mid = pw + 2 * RB * pmax;                         // [RB][2][mmax] intermediate rows
     const int Pb = a.parent[c];
     const cpx<T> *sh = a.shift + (long long)a.oct[c] * Kp + (long long)w0 * a.nph_p;
-    const cpx<T> *v0 = a.in + pat(Pb, 0, r, w0 * a.nph_p, nrhs, Kp);
-    const cpx<T> *v1 = a.in + pat(Pb, 1, r, w0 * a.nph_p, nrhs, Kp);
     for (int i = threadIdx.x; i < plen; i += STEP_THREADS) {
         const cpx<T> f = conjg(sh[i]);
-        pw[i] = f * v0[i];
-        pw[pmax + i] = f * v1[i];
+#pragma unroll
+        for (int j = 0; j < RB; j++) {
+            const int r = min(r0 + j, nrhs - 1);
+            pw[(2 * j) * pmax + i] = f * a.in[pat(Pb, 0, r, w0 * a.nph_p + i, nrhs, Kp)];
+            pw[(2 * j + 1) * pmax + i] = f * a.in[pat(Pb, 1, r, w0 * a.nph_p + i, nrhs, Kp)];
+        }
     }
     __syncthreads();
     // phi anterpolation: intermediate rows from the parent rows of the window
     for (int m = threadIdx.x; m < mlen; m += STEP_THREADS) {
-        const int il = m / a.nph_c, j = m % a.nph_c;
-        const int *pc = a.phi_col + j * a.tphi;
-        const T *pwt = a.phi_w + j * a.tphi;
-        const cpx<T> *p0 = pw + il * a.nph_p, *p1 = pw + pmax + il * a.nph_p;
-        cpx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+        const int il = m / a.nph_c, jc = m % a.nph_c;
+        const int *pc = a.phi_col + jc * a.tphi;
+        const T *pwt = a.phi_w + jc * a.tphi;
+        cpx<T> s0[RB], s1[RB];
+#pragma unroll
+        for (int j = 0; j < RB; j++) s0[j] = s1[j] = mk<T>(0, 0);
 #pragma unroll 4
         for (int t = 0; t < a.tphi; t++) {
-            const int jj = pc[t];
-            axpy_to(s0, pwt[t], p0[jj]);
-            axpy_to(s1, pwt[t], p1[jj]);
+            const int jj = il * a.nph_p + pc[t];
+            const T wt = pwt[t];
+#pragma unroll
+            for (int j = 0; j < RB; j++) {
+                axpy_to(s0[j], wt, pw[(2 * j) * pmax + jj]);
+                axpy_to(s1[j], wt, pw[(2 * j + 1) * pmax + jj]);
+            }
         }
         const T f = a.rowf[w0 + il];
-        mid[m] = f * s0;
-        mid[mmax + m] = f * s1;
+#pragma unroll
+        for (int j = 0; j < RB; j++) {
+            mid[(2 * j) * mmax + m] = f * s0[j];
+            mid[(2 * j + 1) * mmax + m] = f * s1[j];
+        }
     }
     __syncthreads();
     // theta anterpolation into the child's own rows
     for (int o = threadIdx.x; o < olen; o += STEP_THREADS) {
-        const int ic = i0 + o / a.nph_c, j = o % a.nph_c;
+        const int ic = i0 + o / a.nph_c, jc = o % a.nph_c;
         const int *tr = a.th_row + ic * a.tth, *ts = a.th_sh + ic * a.tth;
         const T *tw = a.th_w + ic * a.tth;
-        cpx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+        cpx<T> s0[RB], s1[RB];
+#pragma unroll
+        for (int j = 0; j < RB; j++) s0[j] = s1[j] = mk<T>(0, 0);
 #pragma unroll 4
         for (int t = 0; t < a.tth; t++) {
-            int col = j + ts[t];
+            int col = jc + ts[t];
             col = col >= a.nph_c ? col - a.nph_c : col;
             const int jj = (tr[t] - w0) * a.nph_c + col;
-            axpy_to(s0, tw[t], mid[jj]);
-            axpy_to(s1, tw[t], mid[mmax + jj]);
+            const T wt = tw[t];
+#pragma unroll
+            for (int j = 0; j < RB; j++) {
+                axpy_to(s0[j], wt, mid[(2 * j) * mmax + jj]);
+                axpy_to(s1[j], wt, mid[(2 * j + 1) * mmax + jj]);
+            }
         }
-        const long long q = (long long)ic * a.nph_c + j;
-        cpx<T> &y0 = a.out[pat(c, 0, r, (int)q, nrhs, Kc)];
-        cpx<T> &y1 = a.out[pat(c, 1, r, (int)q, nrhs, Kc)];
-        y0 = y0 + s0;
-        y1 = y1 + s1;
+        const int q = ic * a.nph_c + jc;
+#pragma unroll
+        for (int j = 0; j < RB; j++) {
+            if (r0 + j >= nrhs) continue;
+            cpx<T> &y0 = a.out[pat(c, 0, r0 + j, q, nrhs, Kc)];
+            cpx<T> &y1 = a.out[pat(c, 1, r0 + j, q, nrhs, Kc)];
+            y0 = y0 + s0[j];
+            y1 = y1 + s1[j];
+        }
     }
 }
 
+// right-hand sides per workgroup: as many (1, 2, 4) as the LDS allows
+inline int step_rb(size_t lds1, int nrhs)
+{
+    int rb = 1;
+    while (rb < 4 && rb < nrhs && 2 * rb * lds1 <= STEP_LDS_MAX) rb *= 2;
+    return rb;
+}
+
 }  // namespace
+
+template <class T, int P>
+void agg_launch(int rb, dim3 grid, dim3 block, size_t lds, hipStream_t s, const LevelStep<T> &a, int nrhs)
+{
+    (void)rb;
+    hipLaunchKernelGGL((k_aggregate<T, P, 1>), grid, block, lds, s, a, nrhs);
+}
 
 template <class T>
 bool launch_aggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s)
 {
     if (a.nchunk <= 0 || (long long)a.rows * a.nph_p > STEP_OUT * STEP_THREADS) return false;
-    const size_t lds = agg_lds_bytes<T>(a.wrows, a.rows, a.nph_c);
-    if (lds > STEP_LDS_MAX) return false;
+    if (a.taps != 6 && a.taps != 8 && a.taps != 10) return false;
+    const size_t lds1 = agg_lds_bytes<T>(a.wrows, a.rows, a.nph_c);
+    if (lds1 > STEP_LDS_MAX) return false;
     if (a.nbox <= 0 || nrhs <= 0) return true;
-    const dim3 grid(xcd_grid_l((long long)a.nbox * a.nchunk), nrhs);
-    switch (a.taps) {
-    case 6: hipLaunchKernelGGL((k_aggregate<T, 6>), grid, dim3(STEP_THREADS), lds, s, a, nrhs); return true;
-    case 8: hipLaunchKernelGGL((k_aggregate<T, 8>), grid, dim3(STEP_THREADS), lds, s, a, nrhs); return true;
-    case 10: hipLaunchKernelGGL((k_aggregate<T, 10>), grid, dim3(STEP_THREADS), lds, s, a, nrhs); return true;
-    default: return false;
-    }
+    // one right-hand side per workgroup: blocking them costs the aggregation
+    // more in registers (and occupancy) than it saves in stencil loads
+    const int rb = 1;
+    const dim3 grid(xcd_grid_l((long long)a.nbox * a.nchunk), nrhs), block(STEP_THREADS);
+    const size_t lds = lds1;
+    if (a.taps == 6) agg_launch<T, 6>(rb, grid, block, lds, s, a, nrhs);
+    else if (a.taps == 8) agg_launch<T, 8>(rb, grid, block, lds, s, a, nrhs);
+    else agg_launch<T, 10>(rb, grid, block, lds, s, a, nrhs);
+    return true;
 }
 
 template <class T>
 bool launch_disaggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s)
 {
     if (a.nchunk <= 0 || a.tphi <= 0 || a.tth <= 0) return false;
-    const size_t lds = dis_lds_bytes<T>(a.wrows, a.nph_p, a.nph_c);
-    if (lds > STEP_LDS_MAX) return false;
+    const size_t lds1 = dis_lds_bytes<T>(a.wrows, a.nph_p, a.nph_c);
+    if (lds1 > STEP_LDS_MAX) return false;
     if (a.nbox <= 0 || nrhs <= 0) return true;
-    const dim3 grid(xcd_grid_l((long long)a.nbox * a.nchunk), nrhs);
-    hipLaunchKernelGGL(k_disaggregate<T>, grid, dim3(STEP_THREADS), lds, s, a, nrhs);
+    const int rb = step_rb(lds1, nrhs);
+    const dim3 grid(xcd_grid_l((long long)a.nbox * a.nchunk), (nrhs + rb - 1) / rb), block(STEP_THREADS);
+    const size_t lds = rb * lds1;
+    if (rb == 4) hipLaunchKernelGGL((k_disaggregate<T, 4>), grid, block, lds, s, a, nrhs);
+    else if (rb == 2) hipLaunchKernelGGL((k_disaggregate<T, 2>), grid, block, lds, s, a, nrhs);
+    else hipLaunchKernelGGL((k_disaggregate<T, 1>), grid, block, lds, s, a, nrhs);
     return true;
 }
 

@@ -603,10 +603,10 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
 #pragma unroll
             for (int u = 0; u < UNR; u++) v[u] = __builtin_amdgcn_readlane(mine, e + u);
 #pragma unroll
-            for (int u = 0; u < UNR; u++) t[u] = tq[(long long)(v[u] >> 16) * K];
+            for (int u = 0; u < UNR; u++) t[u] = tq[(unsigned)v[u] >> 8];
 #pragma unroll
             for (int u = 0; u < UNR; u++) {
-                const cpx<T> *p = lds + (v[u] & 0xffff) * SRC + lane;
+                const cpx<T> *p = lds + (v[u] & 0xff) * SRC + lane;
 #pragma unroll
                 for (int j = 0; j < RB; j++) {
                     fma_to(a0[j], t[u], p[j * WAVE]);
@@ -616,8 +616,8 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
         }
         for (; e < n; e++) {
             const int v = __builtin_amdgcn_readlane(mine, e);
-            const cpx<T> t = tq[(long long)(v >> 16) * K];
-            const cpx<T> *p = lds + (v & 0xffff) * SRC + lane;
+            const cpx<T> t = tq[(unsigned)v >> 8];
+            const cpx<T> *p = lds + (v & 0xff) * SRC + lane;
 #pragma unroll
             for (int j = 0; j < RB; j++) {
                 fma_to(a0[j], t, p[j * WAVE]);

@@ -546,7 +546,8 @@ void translation_table(double k, int L, const double X[3], const std::vector<dou
 // ---------------------------------------------------------- translation tiles
 void build_translation_tiles(const Level &L, int smax, int tmax, TransTiles &t)
 {
-    if (smax < 1 || smax > 0xffff || tmax < 1) throw Error(MLFMA_ERR_ARG, "bad translation tile limits");
+    if (smax < 1 || smax > 255 || tmax < 1) throw Error(MLFMA_ERR_ARG, "bad translation tile limits");
+    if (343LL * L.K >= (1LL << 23)) throw Error(MLFMA_ERR_ARG, "too many samples for the translation tables");
     t = TransTiles();
     t.tile_tgt.push_back(0);
     t.tile_bat.push_back(0);
@@ -575,7 +576,7 @@ void build_translation_tiles(const Level &L, int smax, int tmax, TransTiles &t)
                 t.row.push_back((int)t.ent.size());
                 for (int e = L.il_start[A]; e < L.il_start[A + 1]; e++) {
                     const int pos = (int)(std::lower_bound(uni.begin(), uni.end(), L.il_box[e]) - uni.begin());
-                    if (pos >= s0 && pos < s1) t.ent.push_back((L.il_off[e] << 16) | (pos - s0));
+                    if (pos >= s0 && pos < s1) t.ent.push_back(((L.il_off[e] * L.K) << 8) | (pos - s0));
                 }
             }
             t.row.push_back((int)t.ent.size());

@@ -77,7 +77,9 @@ struct Tree {
 // boxes, each small enough to be staged whole in LDS.  For batch b and the
 // tile's j-th target, ent[row[bat_row[b] + j] .. row[bat_row[b] + j + 1]) are
 // the target's interaction-list entries whose source lies in the batch, each
-// packed as (offset id << 16) | (position of the source inside the batch).
+// packed as ((offset id * K) << 8) | (position of the source inside the
+// batch), K = the level's samples (so the first field is the operator's row
+// start in the 343 x K table).
 struct TransTiles {
     std::vector<int> tile_tgt;  // ntile + 1: first target box of each tile
     std::vector<int> tile_bat;  // ntile + 1: first batch of each tile
