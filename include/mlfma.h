@@ -155,6 +155,24 @@ int mlfma_plane_wave_rhs(mlfma_handle h, int dtype, long long nrhs, const double
  * the same as mlfma_matvec_LK's up to rounding.  Handles must outlive the
  * server's use of them.  All calls are thread-safe.
  */
+/* ------------------------------------------------------------------------
+ * Captured products (HIP graphs).  mlfma_graph_create records the whole
+ * product y = A x of mlfma_matvec_LK (same arguments and checks; op, dtype,
+ * nrhs and the x / y pointers are fixed in the graph) into an instantiated
+ * HIP graph; mlfma_graph_launch replays it on hip_stream with no further
+ * host work per kernel.  The graph uses the handle's workspace: replays and
+ * products on the same handle must not overlap, the handle must outlive the
+ * graph, and a replay returns MLFMA_ERR_STATE once a product with more
+ * right-hand sides has reallocated that workspace.  The captured sequence
+ * contains kernels only (memory is cleared by kernels, not memset nodes).
+ * ------------------------------------------------------------------------ */
+typedef struct mlfma_graph_s *mlfma_graph;
+int mlfma_graph_create(mlfma_handle h, int op, int dtype, long long nrhs, const void *x, long long ldx, void *y,
+                       long long ldy, mlfma_graph *out);
+int mlfma_graph_launch(mlfma_graph g, void *hip_stream);
+/* NULL accepted. */
+int mlfma_graph_destroy(mlfma_graph g);
+
 typedef struct mlfma_server_s *mlfma_server;
 typedef struct {
     int streams;                          /* launch slots (1..16, default 4)      */

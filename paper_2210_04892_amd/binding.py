@@ -65,6 +65,9 @@ def lib():
         L.mlfma_translation_operator.argtypes = [ctypes.c_double, ctypes.c_int, P, LL, P, P]
         L.mlfma_near_info.argtypes = [P, P]
         L.mlfma_tuning.argtypes = [P, ctypes.c_int, P, P]
+        L.mlfma_graph_create.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, ctypes.POINTER(P)]
+        L.mlfma_graph_launch.argtypes = [P, P]
+        L.mlfma_graph_destroy.argtypes = [P]
         L.mlfma_plane_wave_rhs.argtypes = [P, ctypes.c_int, LL, P, P, P, LL, P]
         L.mlfma_server_opts_default.argtypes = [ctypes.POINTER(ServerOptions)]
         L.mlfma_server_create.argtypes = [ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
@@ -217,6 +220,11 @@ class Geometry:
         """Direct call of mlfma_matvec_LK on device pointers (column-major)."""
         _check(lib().mlfma_matvec_LK(self._h, _OPS.get(op, op), dtype, nrhs, x_ptr, ldx, y_ptr, ldy, stream_ptr))
 
+    def capture(self, op, dtype, nrhs, x_ptr, ldx, y_ptr, ldy):
+        """mlfma_graph_create: the whole product on fixed device pointers
+        (column-major) as a replayable HIP graph."""
+        return Graph(self, op, dtype, nrhs, x_ptr, ldx, y_ptr, ldy)
+
     def release(self):
         if getattr(self, "_h", None):
             lib().mlfma_release(self._h)
@@ -225,6 +233,31 @@ class Geometry:
     def __del__(self):
         try:
             self.release()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured product (mlfma_graph_*); keeps its geometry alive."""
+
+    def __init__(self, geom, op, dtype, nrhs, x_ptr, ldx, y_ptr, ldy):
+        self.geom = geom
+        g = ctypes.c_void_p()
+        _check(lib().mlfma_graph_create(geom._h, _OPS.get(op, op), dtype, nrhs, x_ptr, ldx, y_ptr, ldy,
+                                        ctypes.byref(g)))
+        self._g = g
+
+    def launch(self, stream_ptr):
+        _check(lib().mlfma_graph_launch(self._g, stream_ptr))
+
+    def close(self):
+        if getattr(self, "_g", None):
+            lib().mlfma_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
 

@@ -129,6 +129,7 @@ struct mlfma_ctx {
     Prec<float> p32;
     bool near_ready = false;
     Workspace ws;             // workspace of mlfma_matvec_LK / mlfma_matvec_part
+    long long ws_gen = 0;     // bumped whenever ws is reallocated (captured graphs refer to it)
     // stage profiling
     bool prof = false;
     std::vector<hipEvent_t> ev_free;
@@ -777,6 +778,7 @@ void ensure_workspace(mlfma_ctx *c, int nrhs)
         throw Error(MLFMA_ERR_OOM, "device memory budget exceeded by the workspace");
     alloc_workspace(c, c->ws, nrhs);
     c->bytes += c->ws.bytes;
+    c->ws_gen++;
 }
 
 // arguments of the fused step between parent level l and child level l + 1
@@ -1030,6 +1032,95 @@ int mlfma_matvec_part(mlfma_handle h, int op, int dtype, int part, long long nrh
     } catch (const Error &e) {
         return fail(e);
     }
+}
+
+// ------------------------------------------------------------ graph capture
+struct mlfma_graph_s {
+    mlfma_handle h = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    long long ws_gen = 0;
+};
+
+int mlfma_graph_create(mlfma_handle h, int op, int dtype, long long nrhs, const void *x, long long ldx, void *y,
+                       long long ldy, mlfma_graph *out)
+{
+    g_last_error.clear();
+    if (!out) return fail(Error(MLFMA_ERR_ARG, "out graph pointer is NULL"));
+    *out = nullptr;
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    if (!h->near_ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_precompute_nearfield has not been called"));
+    if (op != MLFMA_OP_C && op != MLFMA_OP_EM) return fail(Error(MLFMA_ERR_ARG, "unknown op"));
+    if (dtype != MLFMA_C128 && dtype != MLFMA_C64) return fail(Error(MLFMA_ERR_ARG, "unknown dtype"));
+    const long long N2 = 2LL * h->r.n;
+    if (nrhs < 1 || nrhs > (1 << 20) || !x || !y || ldx < N2 || ldy < N2)
+        return fail(Error(MLFMA_ERR_ARG, "bad nrhs, pointer or leading dimension"));
+    const size_t esz = dtype == MLFMA_C128 ? 16 : 8;
+    const char *xb = (const char *)x, *yb = (const char *)y;
+    if (xb < yb + (size_t)(ldy * (nrhs - 1) + N2) * esz && yb < xb + (size_t)(ldx * (nrhs - 1) + N2) * esz)
+        return fail(Error(MLFMA_ERR_ARG, "x and y overlap"));
+    std::unique_ptr<mlfma_graph_s> g(new mlfma_graph_s());
+    hipStream_t cs = nullptr;
+    try {
+        DeviceGuard dg(h->device);
+        HIPCHK(hipGetLastError());
+        ensure_workspace(h, (int)nrhs);
+        HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+            if (dtype == MLFMA_C128)
+                run_matvec<double>(h, h->ws, h->p64, op, MLFMA_PART_ALL, (int)nrhs, (const cpx<double> *)x, ldx,
+                                   (cpx<double> *)y, ldy, cs, false);
+            else
+                run_matvec<float>(h, h->ws, h->p32, op, MLFMA_PART_ALL, (int)nrhs, (const cpx<float> *)x, ldx,
+                                  (cpx<float> *)y, ldy, cs, false);
+        } catch (...) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(cs, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            throw;
+        }
+        HIPCHK(hipStreamEndCapture(cs, &g->graph));
+        HIPCHK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        (void)hipStreamDestroy(cs);
+        cs = nullptr;
+        g->h = h;
+        g->ws_gen = h->ws_gen;
+        *out = g.release();
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        if (cs) (void)hipStreamDestroy(cs);
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        return fail(e);
+    }
+}
+
+int mlfma_graph_launch(mlfma_graph g, void *hip_stream)
+{
+    g_last_error.clear();
+    if (!g || !g->exec) return fail(Error(MLFMA_ERR_ARG, "NULL graph"));
+    if (g->ws_gen != g->h->ws_gen)
+        return fail(Error(MLFMA_ERR_STATE, "the handle's workspace was reallocated after the capture"));
+    try {
+        DeviceGuard dg(g->h->device);
+        HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)hip_stream));
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int mlfma_graph_destroy(mlfma_graph g)
+{
+    if (!g) return MLFMA_OK;
+    {
+        DeviceGuard dg(g->h->device);
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+    }
+    delete g;
+    return MLFMA_OK;
 }
 
 int mlfma_matvec_LK(mlfma_handle h, int op, int dtype, long long nrhs, const void *x, long long ldx, void *y,

@@ -171,6 +171,49 @@ def test_single_precision_parts(nrhs, op):
         assert err <= tol
 
 
+def test_captured_graph_replays_match_eager():
+    """mlfma_graph_*: a captured product is replayed several times with eager
+    work (fills, eager products on the same handle) and synchronisations in
+    between; every replay equals the eager product bit for bit (same kernels
+    in the same order, no atomics).  After a product with more right-hand
+    sides has reallocated the workspace the graph refuses to replay."""
+    torch = _torch()
+    import paper_2210_04892_amd as mf
+    v, t = mesh("sphere_r0.5")
+    N2 = 3 * len(t)
+    g = mf.Geometry(v, t, k=K0, max_rhs=20).precompute()
+    stream = torch.cuda.current_stream().cuda_stream
+    for dtype, code, nrhs in ((torch.complex64, mf.C64, 1), (torch.complex64, mf.C64, 20),
+                              (torch.complex128, mf.C128, 3)):
+        x = torch.from_numpy(np.ascontiguousarray(synth.gaussian_coeffs(N2, nrhs, 13).T)).to(dtype).cuda()
+        x2 = torch.from_numpy(np.ascontiguousarray(synth.gaussian_coeffs(N2, nrhs, 14).T)).to(dtype).cuda()
+        y_eager = torch.empty_like(x)
+        y_other = torch.empty_like(x)
+        g.matvec_raw("C", code, nrhs, x.data_ptr(), N2, y_eager.data_ptr(), N2, stream)
+        yg = torch.empty_like(x)
+        gr = g.capture("C", code, nrhs, x.data_ptr(), N2, yg.data_ptr(), N2)
+        for rep in range(4):
+            yg.fill_(7.0)
+            gr.launch(stream)
+            torch.cuda.synchronize()
+            print("[gpu] graph replay %d nrhs %d %s" % (rep, nrhs, dtype), flush=True)
+            assert torch.equal(yg, y_eager)
+            g.matvec_raw("C", code, nrhs, x2.data_ptr(), N2, y_other.data_ptr(), N2, stream)
+            torch.cuda.synchronize()
+        gr.close()
+    x = torch.zeros((1, N2), dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    gr = g.capture("C", mf.C64, 1, x.data_ptr(), N2, y.data_ptr(), N2)
+    big = torch.zeros((40, N2), dtype=torch.complex64, device="cuda")
+    big_y = torch.empty_like(big)
+    g.matvec_raw("C", mf.C64, 40, big.data_ptr(), N2, big_y.data_ptr(), N2, stream)
+    torch.cuda.synchronize()
+    with pytest.raises(mf.MlfmaError):
+        gr.launch(stream)
+    gr.close()
+    g.release()
+
+
 def test_tiny_mesh_is_all_near():
     """A mesh smaller than three octree levels has no far field: the whole
     product is the double-precision near field."""
