@@ -179,6 +179,9 @@ typedef struct {
     int max_batch_rhs;                    /* columns merged per product (16)      */
     int device;                           /* -1: the current device               */
     unsigned long long hbm_budget_bytes;  /* bound on the slots' arenas, 0 = none */
+    int use_graphs;                       /* 1 (default): each slot replays its products as captured HIP
+                                             graphs, one per (geometry, op, dtype, width), captured on
+                                             first use; 0: every kernel launched from the host */
 } mlfma_server_opts;
 int mlfma_server_opts_default(mlfma_server_opts *opt);
 int mlfma_server_create(const mlfma_server_opts *opt, mlfma_server *out);
@@ -190,8 +193,9 @@ int mlfma_server_submit(mlfma_server s, mlfma_handle h, int op, int dtype, long 
  * product it ran in (either pointer may be NULL).  MLFMA_ERR_STATE on timeout
  * (the ticket stays valid), MLFMA_ERR_OOM if it can never be admitted. */
 int mlfma_server_wait(mlfma_server s, long long ticket, double timeout_s, double *latency_s, int *batch_rhs);
-/* out[0..3] = {products launched, requests served, arena bytes, queued requests} */
-int mlfma_server_stats(mlfma_server s, long long out[4]);
+/* out[0..4] = {products launched, requests served, arena bytes, queued
+ * requests, products captured as graphs} */
+int mlfma_server_stats(mlfma_server s, long long out[5]);
 /* Stop the threads (queued requests are dropped), free slots.  NULL accepted. */
 int mlfma_server_destroy(mlfma_server s);
 

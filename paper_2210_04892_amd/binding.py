@@ -37,7 +37,7 @@ class Options(ctypes.Structure):
 
 class ServerOptions(ctypes.Structure):
     _fields_ = [("streams", ctypes.c_int), ("max_batch_rhs", ctypes.c_int), ("device", ctypes.c_int),
-                ("hbm_budget_bytes", ctypes.c_ulonglong)]
+                ("hbm_budget_bytes", ctypes.c_ulonglong), ("use_graphs", ctypes.c_int)]
 
 
 _lib = None
@@ -266,12 +266,13 @@ class Server:
     """Continuous-batching server (mlfma_server_*): submit products for
     resident geometries from any thread, wait for tickets."""
 
-    def __init__(self, streams=4, max_batch_rhs=16, hbm_budget_bytes=0, device=None):
+    def __init__(self, streams=4, max_batch_rhs=16, hbm_budget_bytes=0, device=None, use_graphs=True):
         o = ServerOptions()
         _check(lib().mlfma_server_opts_default(ctypes.byref(o)))
         o.streams = streams
         o.max_batch_rhs = max_batch_rhs
         o.hbm_budget_bytes = hbm_budget_bytes
+        o.use_graphs = 1 if use_graphs else 0
         o.device = torch.cuda.current_device() if device is None else int(device)
         self.device = o.device
         h = ctypes.c_void_p()
@@ -303,9 +304,10 @@ class Server:
         return lat.value, br.value
 
     def stats(self):
-        out = np.zeros(4, np.int64)
+        out = np.zeros(5, np.int64)
         _check(lib().mlfma_server_stats(self._s, out.ctypes.data))
-        return {"launches": int(out[0]), "requests": int(out[1]), "arena_bytes": int(out[2]), "queued": int(out[3])}
+        return {"launches": int(out[0]), "requests": int(out[1]), "arena_bytes": int(out[2]), "queued": int(out[3]),
+                "graph_captures": int(out[4])}
 
     def close(self):
         if getattr(self, "_s", None):

@@ -3,9 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <string>
 #include <type_traits>
@@ -130,6 +132,7 @@ struct mlfma_ctx {
     bool near_ready = false;
     Workspace ws;             // workspace of mlfma_matvec_LK / mlfma_matvec_part
     long long ws_gen = 0;     // bumped whenever ws is reallocated (captured graphs refer to it)
+    long long uid = 0;        // unique over the process (keys of the server's captured products)
     // stage profiling
     bool prof = false;
     std::vector<hipEvent_t> ev_free;
@@ -957,6 +960,8 @@ int mlfma_build_tree(const double *verts, long long n_verts, const int *tris, lo
     *out = nullptr;
     try {
         std::unique_ptr<mlfma_ctx> c(new mlfma_ctx());
+        static std::atomic<long long> next_uid{1};
+        c->uid = next_uid++;
         if (opt) c->opt = *opt;
         else mlfma_options_default(&c->opt);
         if (c->opt.max_rhs < 1) throw Error(MLFMA_ERR_ARG, "max_rhs must be >= 1");
@@ -1318,7 +1323,17 @@ struct Slot {
     unsigned long long io_bytes = 0;
     bool busy = false;
     std::vector<Request *> reqs;
+    // captured products of this slot's arena: (geometry uid, op, dtype, rhs)
+    std::map<std::tuple<long long, int, int, int>, hipGraphExec_t> graphs;
 };
+
+constexpr size_t SLOT_GRAPHS_MAX = 64;
+
+void clear_graphs(Slot &sl)
+{
+    for (auto &kv : sl.graphs) (void)hipGraphExecDestroy(kv.second);
+    sl.graphs.clear();
+}
 
 }  // namespace
 
@@ -1336,6 +1351,8 @@ struct mlfma_server_s {
     bool stop = false;
     std::string thread_error;
     std::thread sched, poll;
+    hipStream_t capture = nullptr;     // stream the scheduler captures products on
+    long long graph_captures = 0;
 };
 
 namespace {
@@ -1357,12 +1374,42 @@ void launch_batch(mlfma_server_s *S, Slot &slot, std::vector<Request *> &batch, 
     }
     Workspace w;
     carve_workspace(h, w, slot.arena, total);
-    if (dtype == MLFMA_C128)
-        run_matvec<double>(h, w, h->p64, op, MLFMA_PART_ALL, total, (const cpx<double> *)slot.xb, N2,
-                           (cpx<double> *)slot.yb, N2, slot.stream, false);
-    else
-        run_matvec<float>(h, w, h->p32, op, MLFMA_PART_ALL, total, (const cpx<float> *)slot.xb, N2,
-                          (cpx<float> *)slot.yb, N2, slot.stream, false);
+    auto product = [&](hipStream_t st) {
+        if (dtype == MLFMA_C128)
+            run_matvec<double>(h, w, h->p64, op, MLFMA_PART_ALL, total, (const cpx<double> *)slot.xb, N2,
+                               (cpx<double> *)slot.yb, N2, st, false);
+        else
+            run_matvec<float>(h, w, h->p32, op, MLFMA_PART_ALL, total, (const cpx<float> *)slot.xb, N2,
+                              (cpx<float> *)slot.yb, N2, st, false);
+    };
+    if (S->opt.use_graphs) {
+        // replay the product captured for this slot, geometry, op, dtype and
+        // width; capture it the first time
+        const auto key = std::make_tuple(h->uid, op, dtype, total);
+        auto it = slot.graphs.find(key);
+        if (it == slot.graphs.end()) {
+            if (slot.graphs.size() >= SLOT_GRAPHS_MAX) clear_graphs(slot);
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(S->capture, hipStreamCaptureModeThreadLocal));
+            try {
+                product(S->capture);
+            } catch (...) {
+                (void)hipStreamEndCapture(S->capture, &graph);
+                if (graph) (void)hipGraphDestroy(graph);
+                throw;
+            }
+            HIPCHK(hipStreamEndCapture(S->capture, &graph));
+            hipGraphExec_t exec = nullptr;
+            const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIPCHK(e);
+            it = slot.graphs.emplace(key, exec).first;
+            S->graph_captures++;
+        }
+        HIPCHK(hipGraphLaunch(it->second, slot.stream));
+    } else {
+        product(slot.stream);
+    }
     col = 0;
     for (Request *r : batch) {
         HIPCHK(hipMemcpy2DAsync(r->y, r->ldy * esz, slot.yb + (size_t)col * N2 * esz, N2 * esz, N2 * esz, r->nrhs,
@@ -1414,6 +1461,7 @@ void scheduler_loop(mlfma_server_s *S)
                         break;
                     Slot &sl = S->slots[i];
                     if (sl.busy || (int)i == cand || !sl.arena_bytes) continue;
+                    clear_graphs(sl);
                     (void)hipFree(sl.arena);
                     (void)hipFree(sl.xb);
                     (void)hipFree(sl.yb);
@@ -1463,6 +1511,7 @@ void scheduler_loop(mlfma_server_s *S)
         int err = 0;
         try {
             if (grow) {
+                clear_graphs(slot);
                 if (slot.arena) (void)hipFree(slot.arena);
                 if (slot.xb) (void)hipFree(slot.xb);
                 if (slot.yb) (void)hipFree(slot.yb);
@@ -1541,6 +1590,7 @@ int mlfma_server_opts_default(mlfma_server_opts *o)
     o->max_batch_rhs = 16;
     o->device = -1;
     o->hbm_budget_bytes = 0;
+    o->use_graphs = 1;
     return MLFMA_OK;
 }
 
@@ -1564,6 +1614,7 @@ int mlfma_server_create(const mlfma_server_opts *opt, mlfma_server *out)
             HIPCHK(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
         }
+        HIPCHK(hipStreamCreateWithFlags(&S->capture, hipStreamNonBlocking));
         mlfma_server_s *raw = S.get();
         S->sched = std::thread(scheduler_loop, raw);
         S->poll = std::thread(poller_loop, raw);
@@ -1629,7 +1680,7 @@ int mlfma_server_wait(mlfma_server s, long long ticket, double timeout_s, double
     return MLFMA_OK;
 }
 
-int mlfma_server_stats(mlfma_server s, long long out[4])
+int mlfma_server_stats(mlfma_server s, long long out[5])
 {
     if (!s || !out) return fail(Error(MLFMA_ERR_ARG, "NULL argument"));
     std::lock_guard<std::mutex> lk(s->mu);
@@ -1637,6 +1688,7 @@ int mlfma_server_stats(mlfma_server s, long long out[4])
     out[1] = s->batched_requests;
     out[2] = (long long)s->arena_total;
     out[3] = (long long)s->queue.size();
+    out[4] = s->graph_captures;
     return MLFMA_OK;
 }
 
@@ -1655,12 +1707,14 @@ int mlfma_server_destroy(mlfma_server s)
         DeviceGuard g(s->device);
         for (auto &sl : s->slots) {
             if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+            clear_graphs(sl);
             if (sl.arena) (void)hipFree(sl.arena);
             if (sl.xb) (void)hipFree(sl.xb);
             if (sl.yb) (void)hipFree(sl.yb);
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
         }
+        if (s->capture) (void)hipStreamDestroy(s->capture);
     }
     for (auto &kv : s->reqs) delete kv.second;
     delete s;

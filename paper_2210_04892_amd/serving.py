@@ -93,7 +93,7 @@ def fifo_latencies(arrivals, service):
 
 
 def run(geom_list, n_requests=512, seed=5, streams=4, max_batch_rhs=16, load=0.7, op="C",
-        dtype=np.complex64, log=print):
+        dtype=np.complex64, log=print, use_graphs=True):
     geoms = []
     for name, v, t in geom_list:
         g = mf.Geometry(v, t, max_rhs=max_batch_rhs).precompute()
@@ -104,12 +104,12 @@ def run(geom_list, n_requests=512, seed=5, streams=4, max_batch_rhs=16, load=0.7
     # arena footprint with every slot holding the largest geometry, and a
     # budget below it so that admission by memory is exercised
     from .binding import lib  # noqa: F401
-    probe = mf.Server(streams=streams, max_batch_rhs=max_batch_rhs)
+    probe = mf.Server(streams=streams, max_batch_rhs=max_batch_rhs, use_graphs=use_graphs)
     lat, wall, bsz, _ = run_stream(probe, geoms, reqs[:64], None, op)
     full = probe.stats()["arena_bytes"]
     probe.close()
     budget = int(0.75 * full) if full else 0
-    server = mf.Server(streams=streams, max_batch_rhs=max_batch_rhs, hbm_budget_bytes=budget)
+    server = mf.Server(streams=streams, max_batch_rhs=max_batch_rhs, hbm_budget_bytes=budget, use_graphs=use_graphs)
     # capacity: everything submitted at once (closed loop)
     lat_c, wall_c, bsz_c, ys = run_stream(server, geoms, reqs, None, op)
     capacity = len(reqs) / wall_c
@@ -144,6 +144,7 @@ def run(geom_list, n_requests=512, seed=5, streams=4, max_batch_rhs=16, load=0.7
         "p50_ms": 1e3 * p50, "p99_ms": 1e3 * p99,
         "mean_batch_rhs": float(np.mean(bsz_p)),
         "launches": stats["launches"],
+        "graphs": bool(use_graphs), "graph_captures": stats["graph_captures"],
         "max_rel_diff_alone_vs_mix": worst,
         "one_at_a_time_c128": {"throughput_unknowns_rhs_per_s": unknowns / sum(svc),
                                "p50_ms": 1e3 * b50, "p99_ms": 1e3 * b99},
