@@ -173,6 +173,28 @@ int mlfma_graph_launch(mlfma_graph g, void *hip_stream);
 /* NULL accepted. */
 int mlfma_graph_destroy(mlfma_graph g);
 
+/* ------------------------------------------------------------------------
+ * Outer Krylov solver.  The hybrid solver of Sec. II-E wraps the product in
+ * GMRES (its experiments stop at a relative residual of 1e-3).  mlfma_gmres
+ * solves A x = b for the operator op (MLFMA_OP_C: the BI block C of eqs.
+ * 43-46 alone; MLFMA_OP_EM: the L/K pair) with restarted GMRES(restart), one
+ * Krylov space per right-hand-side column, every Arnoldi step one batched
+ * product of all columns (classical Gram-Schmidt applied twice, inner
+ * products in double precision, on hip_stream; rotations on the host).
+ *   b, x: device, column-major 2N x nrhs (ldb, ldx >= 2N), must not overlap;
+ *         x holds the initial guess on entry and the solution on return.
+ *   All columns iterate until the largest estimated relative residual is at
+ *   most tol or max_iters Arnoldi steps were taken; *iters (may be NULL) =
+ *   steps taken; relres (host, nrhs doubles) = true ||b - A x|| / ||b|| per
+ *   column, recomputed at exit (0 for a zero column of b).
+ * Synchronous: returns after the solve (it reads the Hessenberg entries on
+ * the host every step).  Allocates its Krylov basis ((restart + 1) x 2N x
+ * nrhs) for the call.  Errors as mlfma_matvec_LK; MLFMA_ERR_ARG for restart
+ * outside 1..512, max_iters < 1 or tol <= 0.
+ * ------------------------------------------------------------------------ */
+int mlfma_gmres(mlfma_handle h, int op, int dtype, long long nrhs, const void *b, long long ldb, void *x,
+                long long ldx, int restart, int max_iters, double tol, int *iters, double *relres, void *hip_stream);
+
 typedef struct mlfma_server_s *mlfma_server;
 typedef struct {
     int streams;                          /* launch slots (1..16, default 4)      */

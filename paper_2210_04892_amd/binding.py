@@ -68,6 +68,8 @@ def lib():
         L.mlfma_graph_create.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, ctypes.POINTER(P)]
         L.mlfma_graph_launch.argtypes = [P, P]
         L.mlfma_graph_destroy.argtypes = [P]
+        L.mlfma_gmres.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_double, ctypes.POINTER(ctypes.c_int), P, P]
         L.mlfma_plane_wave_rhs.argtypes = [P, ctypes.c_int, LL, P, P, P, LL, P]
         L.mlfma_server_opts_default.argtypes = [ctypes.POINTER(ServerOptions)]
         L.mlfma_server_create.argtypes = [ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
@@ -219,6 +221,31 @@ class Geometry:
     def matvec_raw(self, op, dtype, nrhs, x_ptr, ldx, y_ptr, ldy, stream_ptr):
         """Direct call of mlfma_matvec_LK on device pointers (column-major)."""
         _check(lib().mlfma_matvec_LK(self._h, _OPS.get(op, op), dtype, nrhs, x_ptr, ldx, y_ptr, ldy, stream_ptr))
+
+    def gmres(self, b, op="C", x0=None, restart=30, max_iters=300, tol=1e-3, stream=None):
+        """Solve A x = b (mlfma_gmres).  b: complex CUDA tensor (2N,) or
+        (2N, nrhs).  Returns (x, Arnoldi steps, true relative residual per
+        column)."""
+        if b.dtype == torch.complex128:
+            dt = C128
+        elif b.dtype == torch.complex64:
+            dt = C64
+        else:
+            raise TypeError("b must be complex128 or complex64")
+        squeeze = b.dim() == 1
+        B = b[:, None] if squeeze else b
+        nrhs = B.shape[1]
+        bt = B.t().contiguous()
+        xt = torch.zeros_like(bt) if x0 is None else (x0[:, None] if squeeze else x0).t().contiguous()
+        rel = np.zeros(nrhs)
+        its = ctypes.c_int()
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        with torch.cuda.device(self.device):
+            _check(lib().mlfma_gmres(self._h, _OPS.get(op, op), dt, nrhs, bt.data_ptr(), 2 * self.n_rwg,
+                                     xt.data_ptr(), 2 * self.n_rwg, restart, max_iters, tol, ctypes.byref(its),
+                                     rel.ctypes.data, s.cuda_stream))
+        x = xt.t()
+        return (x[:, 0] if squeeze else x), its.value, rel
 
     def capture(self, op, dtype, nrhs, x_ptr, ldx, y_ptr, ldy):
         """mlfma_graph_create: the whole product on fixed device pointers

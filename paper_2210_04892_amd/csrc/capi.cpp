@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -925,6 +926,170 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     if (profile) c->ev_pending.push_back(ev);
 }
 
+// Restarted GMRES(m) on y = A x (op, precision T), one Krylov space per
+// right-hand-side column; every Arnoldi step is one batched product of all
+// columns.  Classical Gram-Schmidt applied twice on the device (inner
+// products in double), complex Givens rotations and the triangular solve on
+// the host.  All columns iterate until the largest estimated relative
+// residual reaches tol (or max_iters steps); relres returns the true
+// relative residual ||b - A x|| / ||b|| of every column, recomputed at exit.
+template <class T>
+void gmres(mlfma_ctx *c, Prec<T> &P, int op, int nrhs, const cpx<T> *b, long long ldb, cpx<T> *x, long long ldx,
+           int m, int max_iters, double tol, int *iters_out, double *relres, hipStream_t st)
+{
+    typedef std::complex<double> C;
+    const long long n = 2LL * c->r.n;
+    const int nchunk = (int)std::min<long long>(256, std::max<long long>(1, n / 2048));
+    std::vector<void *> list;
+    struct Free {
+        std::vector<void *> &l;
+        ~Free()
+        {
+            for (void *p : l) (void)hipFree(p);
+        }
+    } fr{list};
+    auto dev = [&](size_t bytes) {
+        void *p = nullptr;
+        HIPCHK(hipMalloc(&p, std::max<size_t>(bytes, 1)));
+        list.push_back(p);
+        return p;
+    };
+    const long long vstride = n * nrhs;
+    cpx<T> *V = (cpx<T> *)dev(sizeof(cpx<T>) * (size_t)vstride * (m + 1));
+    cpx<T> *w = (cpx<T> *)dev(sizeof(cpx<T>) * (size_t)vstride);
+    cpx<double> *part = (cpx<double> *)dev(sizeof(cpx<double>) * (size_t)(m + 1) * nchunk * nrhs);
+    cpx<double> *hd = (cpx<double> *)dev(sizeof(cpx<double>) * (size_t)(m + 1) * nrhs);
+    cpx<double> *hd2 = (cpx<double> *)dev(sizeof(cpx<double>) * (size_t)(m + 1) * nrhs);
+    cpx<double> *ca = (cpx<double> *)dev(sizeof(cpx<double>) * nrhs);
+    cpx<double> *cb = (cpx<double> *)dev(sizeof(cpx<double>) * nrhs);
+    auto matvec = [&](const cpx<T> *in, long long ldi, cpx<T> *out, long long ldo) {
+        run_matvec<T>(c, c->ws, P, op, MLFMA_PART_ALL, nrhs, in, ldi, out, ldo, st, false);
+    };
+    auto fetch = [&](const cpx<double> *d, int count, std::vector<C> &h) {
+        std::vector<cpx<double>> tmp((size_t)count);
+        HIPCHK(hipMemcpyAsync(tmp.data(), d, sizeof(cpx<double>) * count, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        h.resize(count);
+        for (int i = 0; i < count; i++) h[i] = C(tmp[i].re, tmp[i].im);
+    };
+    auto put = [&](cpx<double> *d, const std::vector<C> &h) {
+        std::vector<cpx<double>> tmp(h.size());
+        for (size_t i = 0; i < h.size(); i++) tmp[i] = {h[i].real(), h[i].imag()};
+        HIPCHK(hipMemcpyAsync(d, tmp.data(), sizeof(cpx<double>) * tmp.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    };
+    auto norms = [&](const cpx<T> *v, long long ld, std::vector<double> &out) {
+        std::vector<C> d;
+        krylov_dots<T>(v, 0, ld, 1, v, ld, n, nrhs, part, nchunk, hd, st);
+        fetch(hd, nrhs, d);
+        out.resize(nrhs);
+        for (int r = 0; r < nrhs; r++) out[r] = std::sqrt(std::max(0.0, d[r].real()));
+    };
+    std::vector<double> bnorm;
+    norms(b, ldb, bnorm);
+    std::vector<C> ones(nrhs, C(1, 0)), mones(nrhs, C(-1, 0));
+    int iters = 0;
+    bool done = false;
+    while (!done) {
+        // r = b - A x, V_0 = r / |r|
+        matvec(x, ldx, w, n);
+        put(ca, ones);
+        put(cb, mones);
+        krylov_axpby<T>(ca, b, ldb, cb, w, n, V, n, n, nrhs, st);
+        std::vector<double> beta;
+        norms(V, n, beta);
+        std::vector<C> sc(nrhs);
+        for (int r = 0; r < nrhs; r++) sc[r] = beta[r] > 0 ? C(1.0 / beta[r], 0) : C(0, 0);
+        put(ca, sc);
+        krylov_axpby<T>(ca, V, n, nullptr, nullptr, 0, V, n, n, nrhs, st);
+        // Hessenberg columns, rotations and right-hand side per column
+        std::vector<std::vector<C>> H(nrhs, std::vector<C>((size_t)(m + 1) * m, C(0, 0)));
+        std::vector<std::vector<double>> cs(nrhs, std::vector<double>(m, 1.0));
+        std::vector<std::vector<C>> sn(nrhs, std::vector<C>(m, C(0, 0)));
+        std::vector<std::vector<C>> g(nrhs, std::vector<C>(m + 1, C(0, 0)));
+        double worst = 0;
+        for (int r = 0; r < nrhs; r++) {
+            g[r][0] = C(beta[r], 0);
+            worst = std::max(worst, bnorm[r] > 0 ? beta[r] / bnorm[r] : 0.0);
+        }
+        if (worst <= tol) break;
+        int j = 0;
+        for (; j < m && iters < max_iters; j++) {
+            matvec(V + (size_t)j * vstride, n, w, n);
+            std::vector<C> h1, h2;
+            krylov_dots<T>(V, vstride, n, j + 1, w, n, n, nrhs, part, nchunk, hd, st);
+            krylov_combine<T>(V, vstride, n, j + 1, hd, -1.0, w, n, n, nrhs, st);
+            krylov_dots<T>(V, vstride, n, j + 1, w, n, n, nrhs, part, nchunk, hd2, st);
+            krylov_combine<T>(V, vstride, n, j + 1, hd2, -1.0, w, n, n, nrhs, st);
+            fetch(hd, (j + 1) * nrhs, h1);
+            fetch(hd2, (j + 1) * nrhs, h2);
+            std::vector<double> hn;
+            norms(w, n, hn);
+            for (int r = 0; r < nrhs; r++) sc[r] = hn[r] > 0 ? C(1.0 / hn[r], 0) : C(0, 0);
+            put(ca, sc);
+            krylov_axpby<T>(ca, w, n, nullptr, nullptr, 0, V + (size_t)(j + 1) * vstride, n, n, nrhs, st);
+            iters++;
+            worst = 0;
+            for (int r = 0; r < nrhs; r++) {
+                std::vector<C> col(j + 2);
+                for (int i = 0; i <= j; i++) col[i] = h1[i * nrhs + r] + h2[i * nrhs + r];
+                col[j + 1] = C(hn[r], 0);
+                for (int i = 0; i < j; i++) {   // earlier rotations
+                    const C a = col[i], bb = col[i + 1];
+                    col[i] = cs[r][i] * a + sn[r][i] * bb;
+                    col[i + 1] = -std::conj(sn[r][i]) * a + cs[r][i] * bb;
+                }
+                const C a = col[j];
+                const double bb = col[j + 1].real(), t = std::sqrt(std::norm(a) + bb * bb);
+                if (t == 0) {
+                    cs[r][j] = 1;
+                    sn[r][j] = 0;
+                } else if (std::abs(a) == 0) {
+                    cs[r][j] = 0;
+                    sn[r][j] = 1;
+                } else {
+                    cs[r][j] = std::abs(a) / t;
+                    sn[r][j] = (a / std::abs(a)) * (bb / t);
+                }
+                col[j] = cs[r][j] * a + sn[r][j] * col[j + 1];
+                col[j + 1] = 0;
+                for (int i = 0; i <= j; i++) H[r][(size_t)i * m + j] = col[i];
+                g[r][j + 1] = -std::conj(sn[r][j]) * g[r][j];
+                g[r][j] = cs[r][j] * g[r][j];
+                worst = std::max(worst, bnorm[r] > 0 ? std::abs(g[r][j + 1]) / bnorm[r] : 0.0);
+            }
+            if (worst <= tol) {
+                j++;
+                done = true;
+                break;
+            }
+        }
+        if (iters >= max_iters) done = true;
+        // x += V y with H y = g (upper triangular, j columns)
+        if (j > 0) {
+            std::vector<C> y((size_t)j * nrhs, C(0, 0));
+            for (int r = 0; r < nrhs; r++)
+                for (int i = j - 1; i >= 0; i--) {
+                    C s = g[r][i];
+                    for (int k = i + 1; k < j; k++) s -= H[r][(size_t)i * m + k] * y[(size_t)k * nrhs + r];
+                    const C d = H[r][(size_t)i * m + i];
+                    y[(size_t)i * nrhs + r] = std::abs(d) > 0 ? s / d : C(0, 0);
+                }
+            put(hd, y);
+            krylov_combine<T>(V, vstride, n, j, hd, 1.0, x, ldx, n, nrhs, st);
+        }
+    }
+    // true residual
+    matvec(x, ldx, w, n);
+    put(ca, ones);
+    put(cb, mones);
+    krylov_axpby<T>(ca, b, ldb, cb, w, n, w, n, n, nrhs, st);
+    std::vector<double> rn;
+    norms(w, n, rn);
+    for (int r = 0; r < nrhs; r++) relres[r] = bnorm[r] > 0 ? rn[r] / bnorm[r] : 0.0;
+    if (iters_out) *iters_out = iters;
+}
+
 int fail(const Error &e)
 {
     g_last_error = e.what();
@@ -1110,6 +1275,40 @@ int mlfma_graph_launch(mlfma_graph g, void *hip_stream)
     try {
         DeviceGuard dg(g->h->device);
         HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)hip_stream));
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int mlfma_gmres(mlfma_handle h, int op, int dtype, long long nrhs, const void *b, long long ldb, void *x,
+                long long ldx, int restart, int max_iters, double tol, int *iters, double *relres, void *hip_stream)
+{
+    g_last_error.clear();
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    if (!h->near_ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_precompute_nearfield has not been called"));
+    if (op != MLFMA_OP_C && op != MLFMA_OP_EM) return fail(Error(MLFMA_ERR_ARG, "unknown op"));
+    if (dtype != MLFMA_C128 && dtype != MLFMA_C64) return fail(Error(MLFMA_ERR_ARG, "unknown dtype"));
+    const long long N2 = 2LL * h->r.n;
+    if (nrhs < 1 || nrhs > 4096 || !b || !x || !relres || ldb < N2 || ldx < N2 || restart < 1 || restart > 512 ||
+        max_iters < 1 || !(tol > 0))
+        return fail(Error(MLFMA_ERR_ARG, "bad nrhs, pointer, leading dimension, restart, max_iters or tol"));
+    const size_t esz = dtype == MLFMA_C128 ? 16 : 8;
+    const char *bb = (const char *)b, *xb = (const char *)x;
+    if (bb < xb + (size_t)(ldx * (nrhs - 1) + N2) * esz && xb < bb + (size_t)(ldb * (nrhs - 1) + N2) * esz)
+        return fail(Error(MLFMA_ERR_ARG, "b and x overlap"));
+    try {
+        DeviceGuard g(h->device);
+        HIPCHK(hipGetLastError());
+        ensure_workspace(h, (int)nrhs);
+        hipStream_t st = (hipStream_t)hip_stream;
+        if (dtype == MLFMA_C128)
+            gmres<double>(h, h->p64, op, (int)nrhs, (const cpx<double> *)b, ldb, (cpx<double> *)x, ldx, restart,
+                          max_iters, tol, iters, relres, st);
+        else
+            gmres<float>(h, h->p32, op, (int)nrhs, (const cpx<float> *)b, ldb, (cpx<float> *)x, ldx, restart,
+                         max_iters, tol, iters, relres, st);
+        HIPCHK(hipGetLastError());
         return MLFMA_OK;
     } catch (const Error &e) {
         return fail(e);

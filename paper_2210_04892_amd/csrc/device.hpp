@@ -181,6 +181,22 @@ bool launch_receive_mfma(int op, int nitem, const int2 *items, int K, const int 
                          const cpx<float> *Q, const float *wq, const cpx<float> *V, cpx<float> *Y, int nrhs,
                          hipStream_t s);
 
+// Outer GMRES vector kernels (krylov.hip); column-major blocks, element
+// (n, r) at r * ld + n; basis vector i of V starts at V + i * vstride.
+// out[i * nrhs + r] = <V_i(:, r), w(:, r)> (conjugate-linear in V), i < nv,
+// accumulated in double; part holds nv x nchunk x nrhs partial sums.
+template <class T>
+void krylov_dots(const cpx<T> *V, long long vstride, long long ldv, int nv, const cpx<T> *w, long long ldw, long long n,
+                 int nrhs, cpx<double> *part, int nchunk, cpx<double> *out, hipStream_t s);
+// w(:, r) += sign * sum_i V_i(:, r) h[i * nrhs + r]
+template <class T>
+void krylov_combine(const cpx<T> *V, long long vstride, long long ldv, int nv, const cpx<double> *h, double sign,
+                    cpx<T> *w, long long ldw, long long n, int nrhs, hipStream_t s);
+// y(:, r) = a[r] x(:, r) + b[r] z(:, r)  (z = null: the second term is dropped)
+template <class T>
+void krylov_axpby(const cpx<double> *a, const cpx<T> *x, long long ldx, const cpx<double> *b, const cpx<T> *z,
+                  long long ldz, cpx<T> *y, long long ldy, long long n, int nrhs, hipStream_t s);
+
 template <class T>
 void launch_disagg_mid(int nchild, int mid_len, int Kp, const int *parent, const int *oct, const cpx<T> *shift,
                        const int *st, const int *col, const T *w, const cpx<T> *Vp, cpx<T> *mid, int nrhs,
