@@ -860,6 +860,73 @@ int oracle_plane_wave_rhs(int nv, const double *v, int nt, const int *t, double 
     return ORC_OK;
 }
 
+/*
+ * Far field of the surface currents J = sum_n xJ_n f_n, M = sum_n xM_n f_n
+ * (the radar cross section of Sec. III is computed from it).  In the
+ * normalised units of the operators above the field E = L{J} - K{M} behaves
+ * far away as exp(-jkr)/r F(khat), with the plane-wave limits
+ * L -> -jk (I - khat khat) and K -> -jk khat x:
+ *
+ *   F(khat) = (-jk / 4 pi) [ P_J - khat (khat . P_J) - khat x P_M ],
+ *   P_X(khat) = Int X(r') exp(+jk khat . r') ds'   (7-point rule per triangle).
+ *
+ * Output: F . theta_hat and F . phi_hat of each direction khat (theta_hat =
+ * (cos t cos p, cos t sin p, -sin t), phi_hat = (-sin p, cos p, 0) with
+ * t = acos(khat_z), p = atan2(khat_y, khat_x)); x: 2N x nrhs column-major
+ * (J rows then M rows); dirs: ndir x 3 unit vectors; out: ndir x 2 x nrhs
+ * complex, row-major.  sigma = 4 pi |F|^2 for a unit incident field.
+ */
+int oracle_far_field(int nv, const double *v, int nt, const int *t, double k, int nrhs, const double *xin,
+                     int ndir, const double *dirs, double *out)
+{
+    mesh_t m;
+    int rc = mesh_build(&m, nv, v, nt, t);
+    if (rc != ORC_OK) { mesh_free(&m); return rc; }
+    const int N = m.n;
+    const cplx *x = (const cplx *)xin;
+    cplx *F = (cplx *)out;
+    double bary[7][3], w[7];
+    tri7(bary, w);
+    for (int d = 0; d < ndir; d++)
+        for (int q = 0; q < nrhs; q++) {
+            const double *kh = dirs + 3 * d;
+            cplx PJ[3] = {0, 0, 0}, PM[3] = {0, 0, 0};
+            for (int ti = 0; ti < nt; ti++) {
+                double P[3][3];
+                for (int a = 0; a < 3; a++)
+                    for (int c = 0; c < 3; c++) P[a][c] = v[3 * t[3 * ti + a] + c];
+                for (int pt = 0; pt < 7; pt++) {
+                    double r[3];
+                    for (int c = 0; c < 3; c++) r[c] = bary[pt][0] * P[0][c] + bary[pt][1] * P[1][c] + bary[pt][2] * P[2][c];
+                    const cplx ph = cexp(I * k * vdot(kh, r)) * w[pt] * m.area[ti];
+                    for (int i = 0; i < 3; i++) {
+                        const int n = m.tri_rwg[3 * ti + i];
+                        const double cm = rwg_coef(&m, ti, i);
+                        double a[3];
+                        vsub(r, P[i], a);
+                        const cplx xj = x[(size_t)q * 2 * N + n], xm = x[(size_t)q * 2 * N + N + n];
+                        for (int c = 0; c < 3; c++) {
+                            PJ[c] += ph * cm * a[c] * xj;
+                            PM[c] += ph * cm * a[c] * xm;
+                        }
+                    }
+                }
+            }
+            const cplx kpj = kh[0] * PJ[0] + kh[1] * PJ[1] + kh[2] * PJ[2];
+            cplx Fv[3];
+            Fv[0] = PJ[0] - kh[0] * kpj - (kh[1] * PM[2] - kh[2] * PM[1]);
+            Fv[1] = PJ[1] - kh[1] * kpj - (kh[2] * PM[0] - kh[0] * PM[2]);
+            Fv[2] = PJ[2] - kh[2] * kpj - (kh[0] * PM[1] - kh[1] * PM[0]);
+            const double th = acos(fmax(-1.0, fmin(1.0, kh[2]))), phi = atan2(kh[1], kh[0]);
+            const double tv[3] = {cos(th) * cos(phi), cos(th) * sin(phi), -sin(th)}, pv[3] = {-sin(phi), cos(phi), 0};
+            const cplx pre = -I * k / (4 * M_PI);
+            F[((size_t)d * 2 + 0) * nrhs + q] = pre * (Fv[0] * tv[0] + Fv[1] * tv[1] + Fv[2] * tv[2]);
+            F[((size_t)d * 2 + 1) * nrhs + q] = pre * (Fv[0] * pv[0] + Fv[1] * pv[1] + Fv[2] * pv[2]);
+        }
+    mesh_free(&m);
+    return ORC_OK;
+}
+
 /* Leaf-box coordinates and level count of the box rule (tests of the tree). */
 int oracle_boxes(int nv, const double *v, int nt, const int *t, double leaf, int *coords, int *levels)
 {

@@ -37,6 +37,8 @@ def _load():
                                       ctypes.c_int, ctypes.c_int]
         lib.oracle_boxes.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, P, P]
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_far_field.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P,
+                                         ctypes.c_int, P, P]
         lib.oracle_plane_wave_rhs.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
                                               P, P, P]
         _lib = lib
@@ -77,6 +79,21 @@ def plane_wave_rhs(verts, tris, k, khat, pol):
     if rc < 0:
         raise ValueError("oracle rejected the mesh (code %d)" % rc)
     return out.T
+
+
+def far_field(verts, tris, k, x, dirs):
+    """(F . theta_hat, F . phi_hat) of the far field of the currents x
+    (2N x nrhs, J rows then M rows) in the directions dirs (ndir x 3):
+    array (ndir, 2, nrhs).  F = (-jk/4pi)[P_J - khat(khat.P_J) - khat x P_M]."""
+    v, t = _mesh(verts, tris)
+    X = np.asfortranarray(np.atleast_2d(np.asarray(x, np.complex128).T).T)
+    d = np.ascontiguousarray(np.atleast_2d(dirs), np.float64)
+    out = np.zeros((len(d), 2, X.shape[1]), np.complex128)
+    rc = _load().oracle_far_field(len(v), v.ctypes.data, len(t), t.ctypes.data, k, X.shape[1], X.ctypes.data,
+                                  len(d), d.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_far_field failed (%d)" % rc)
+    return out
 
 
 def leaf_boxes(verts, tris, leaf):

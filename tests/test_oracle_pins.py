@@ -401,3 +401,61 @@ def test_plane_wave_rhs_matches_projection():
     got = oracle.plane_wave_rhs(v, t, K0, khat[None, :], pol[None, :])[:, 0]
     ref = np.concatenate([bJ, bM])
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-5
+
+
+# ------------------------------------------------------------- far field
+def _sph_units(kh):
+    th, ph = np.arccos(np.clip(kh[2], -1, 1)), np.arctan2(kh[1], kh[0])
+    return (np.array([np.cos(th) * np.cos(ph), np.cos(th) * np.sin(ph), -np.sin(th)]),
+            np.array([-np.sin(ph), np.cos(ph), 0.0]))
+
+
+def test_far_field_dipole_limit():
+    """As k -> 0 the far field of one RWG tends to (-jk/4pi) times the
+    transverse part of its moment m = Int f ds = sum over its triangles of
+    sigma l/(2A) * A (centroid - free vertex) for an electric current, and
+    to (-jk/4pi) (-khat x m) for a magnetic one (closed form, independent of
+    the quadrature)."""
+    v, t = synth.octahedron(0.4)
+    e, pm = oracle.rwg_table(v, t)
+    co = rwg_coefficients(v, t, e, pm)
+    N = len(e)
+    k = 1e-9
+    dirs = synth.fibonacci_directions(9, 3)[0]
+    for n in (0, 5):
+        m = sum(cm * tri_area(v[t[tri]]) * (v[t[tri]].mean(axis=0) - p) for tri, p, cm in co[n])
+        for half in (0, 1):
+            x = np.zeros((2 * N, 1), complex)
+            x[half * N + n] = 1.0
+            F = oracle.far_field(v, t, k, x, dirs)[:, :, 0] / (-1j * k / (4 * np.pi))
+            for d, kh in enumerate(dirs):
+                vec = m - kh * (kh @ m) if half == 0 else -np.cross(kh, m)
+                tv, pv = _sph_units(kh)
+                ref = np.array([tv @ vec, pv @ vec])
+                assert np.allclose(F[d], ref, rtol=1e-9, atol=1e-9 * np.linalg.norm(m)), (n, half, d, F[d], ref)
+
+
+@pytest.mark.slow
+def test_far_field_extinction():
+    """The equivalent currents of an incident plane wave (J = n x H,
+    M = -n x E) radiate nothing outside the surface (the same extinction as
+    on the surface), so their far field vanishes up to discretisation
+    error, while the fields of J and of M alone do not.  Checks the relative
+    sign and scale of the J and M terms and the sign of the phase."""
+    khat = np.array([0.0, 0.0, 1.0])
+    pol = np.array([1.0, 0.0, 0.0])
+    Ei = lambda x: pol[None, :] * np.exp(-1j * K0 * x @ khat)[:, None]
+    Hi = lambda x: np.cross(khat, pol)[None, :] * np.exp(-1j * K0 * x @ khat)[:, None]
+    dirs = synth.fibonacci_directions(40, 7)[0]
+    ratios = []
+    for m in (4, 8):
+        v, t = synth.icosphere(m, 0.5)
+        N = 3 * len(t) // 2
+        G = _gram(v, t)
+        xJ = np.linalg.solve(G, _project(v, t, lambda x, n: np.cross(n, Hi(x))))
+        xM = np.linalg.solve(G, _project(v, t, lambda x, n: -np.cross(n, Ei(x))))
+        X = np.stack([np.concatenate([xJ, xM]), np.concatenate([xJ, 0 * xM])], axis=1)
+        F = oracle.far_field(v, t, K0, X, dirs)
+        ratios.append(np.linalg.norm(F[:, :, 0]) / np.linalg.norm(F[:, :, 1]))
+    print("far-field extinction |F(J,M)| / |F(J)| at m=4 / m=8:", ratios)
+    assert ratios[1] < 0.05 and ratios[1] < ratios[0]
