@@ -241,6 +241,15 @@ def main():
         xs, its, rel = g.gmres(b0.to(dt), op=a.op, restart=30, max_iters=300, tol=1e-3)
         torch.cuda.synchronize()
         gm[name] = {"steps": its, "seconds": round(time.perf_counter() - t_0, 4), "true_rel_residual": float(rel[0])}
+        # radar cross section cut of the solution's currents: theta = 0..180 deg, phi = 0
+        th = np.radians(np.arange(181.0))
+        cut = np.stack([np.sin(th), 0 * th, np.cos(th)], axis=1)
+        t_0 = time.perf_counter()
+        F = g.far_field(xs, cut)
+        torch.cuda.synchronize()
+        gm[name]["rcs_cut_181_seconds"] = round(time.perf_counter() - t_0, 4)
+        sig = 4 * np.pi * (F.abs() ** 2).sum(dim=1)[:, 0].double().cpu().numpy()
+        gm[name]["rcs_dBsm_theta_0_90_180"] = [round(float(10 * np.log10(max(sig[i], 1e-300))), 2) for i in (0, 90, 180)]
     # consistency of the two precisions (same tables, same tree)
     d = np.linalg.norm(ys["c64"] - ys["c128"]) / np.linalg.norm(ys["c128"])
     cpu = None
@@ -297,7 +306,7 @@ def main():
         "hbm_bytes": hbm_bytes,
         "translation_tile_shape": tuning,
         "serving": serving,
-        "gmres_tol_1e-3": gm,
+        "gmres_tol_1e-3_and_rcs": gm,
     }
     print(json.dumps(out), flush=True)
     if a.copy_probe_mib > 0:

@@ -142,6 +142,23 @@ int mlfma_matvec_part(mlfma_handle h, int op, int dtype, int part, long long nrh
 int mlfma_plane_wave_rhs(mlfma_handle h, int dtype, long long nrhs, const double *khat, const double *pol, void *b,
                          long long ldb, void *hip_stream);
 
+/* Far field of the surface currents x (radar cross section, Sec. III):
+ * with E = L{J} - K{M} (the operators of Sec. II-C) the scattered field is
+ * exp(-jkr)/r F(khat) far away, F = (-jk/4pi)[P_J - khat (khat . P_J) -
+ * khat x P_M], P_X = Int X exp(+jk khat . r) ds (7-point rule on every
+ * triangle, double-precision sums); sigma = 4 pi |F|^2 for a unit incident
+ * field.
+ *   x:    device, column-major 2N x nrhs (ldx >= 2N), J rows then M rows
+ *   dirs: host, ndir x 3 unit vectors (observation directions khat)
+ *   F:    device, ndir x 2 x nrhs complex of dtype (row-major):
+ *         F . theta_hat and F . phi_hat, theta_hat = (cos t cos p, cos t
+ *         sin p, -sin t), phi_hat = (-sin p, cos p, 0), t = acos(khat_z),
+ *         p = atan2(khat_y, khat_x)
+ * Enqueued on hip_stream and waited for before returning.  MLFMA_ERR_ARG for
+ * a null pointer, a bad count or a direction that is not a unit vector. */
+int mlfma_far_field(mlfma_handle h, int dtype, long long nrhs, const void *x, long long ldx, long long ndir,
+                    const double *dirs, void *F, void *hip_stream);
+
 /*
  * Serving: concurrent Krylov clients submit products for resident
  * geometries; the server batches continuously.  A scheduler thread merges

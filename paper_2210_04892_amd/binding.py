@@ -71,6 +71,7 @@ def lib():
         L.mlfma_gmres.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_double, ctypes.POINTER(ctypes.c_int), P, P]
         L.mlfma_plane_wave_rhs.argtypes = [P, ctypes.c_int, LL, P, P, P, LL, P]
+        L.mlfma_far_field.argtypes = [P, ctypes.c_int, LL, P, LL, LL, P, P, P]
         L.mlfma_server_opts_default.argtypes = [ctypes.POINTER(ServerOptions)]
         L.mlfma_server_create.argtypes = [ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
         L.mlfma_server_submit.argtypes = [P, P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, ctypes.POINTER(LL)]
@@ -160,6 +161,28 @@ class Geometry:
             _check(lib().mlfma_plane_wave_rhs(self._h, dt, nrhs, kh.ctypes.data, po.ctypes.data, bt.data_ptr(),
                                               2 * self.n_rwg, s.cuda_stream))
         return bt.t()
+
+    def far_field(self, x, dirs):
+        """mlfma_far_field: (F . theta_hat, F . phi_hat) of the currents x
+        (complex CUDA tensor (2N,) or (2N, nrhs)) in the directions dirs
+        (ndir x 3 unit vectors): tensor (ndir, 2, nrhs) of x's dtype.  The radar
+        cross section is 4 pi |F|^2."""
+        if x.dtype == torch.complex128:
+            dt = C128
+        elif x.dtype == torch.complex64:
+            dt = C64
+        else:
+            raise TypeError("x must be complex128 or complex64")
+        X = x[:, None] if x.dim() == 1 else x
+        nrhs = X.shape[1]
+        xt = X.t().contiguous()
+        d = np.ascontiguousarray(np.atleast_2d(dirs), np.float64)
+        F = torch.empty((len(d), 2, nrhs), dtype=x.dtype, device=x.device)
+        s = torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().mlfma_far_field(self._h, dt, nrhs, xt.data_ptr(), 2 * self.n_rwg, len(d), d.ctypes.data,
+                                         F.data_ptr(), s.cuda_stream))
+        return F
 
     def near_info(self):
         info = np.zeros(4, np.int64)

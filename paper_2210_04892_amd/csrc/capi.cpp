@@ -1466,6 +1466,44 @@ int mlfma_plane_wave_rhs(mlfma_handle h, int dtype, long long nrhs, const double
     }
 }
 
+int mlfma_far_field(mlfma_handle h, int dtype, long long nrhs, const void *x, long long ldx, long long ndir,
+                    const double *dirs, void *F, void *hip_stream)
+{
+    g_last_error.clear();
+    if (!h || !x || !F || !dirs || nrhs < 1 || nrhs > 65535 || ndir < 1 || ndir > (1LL << 30) ||
+        ldx < 2LL * h->r.n || (dtype != MLFMA_C128 && dtype != MLFMA_C64))
+        return fail(Error(MLFMA_ERR_ARG, "bad arguments"));
+    for (long long d = 0; d < ndir; d++) {
+        const double n2 = dirs[3 * d] * dirs[3 * d] + dirs[3 * d + 1] * dirs[3 * d + 1] + dirs[3 * d + 2] * dirs[3 * d + 2];
+        if (!(std::abs(n2 - 1.0) <= 1e-9)) return fail(Error(MLFMA_ERR_ARG, "directions must be unit vectors"));
+    }
+    std::vector<void *> tmp;
+    const unsigned long long before = h->bytes;
+    struct Free {
+        mlfma_ctx *h;
+        std::vector<void *> &l;
+        unsigned long long b;
+        ~Free()
+        {
+            for (void *p : l) (void)hipFree(p);
+            h->bytes = b;
+        }
+    } fr{h, tmp, before};
+    try {
+        DeviceGuard g(h->device);
+        double *d_dirs = h->dalloc<double>(3 * (size_t)ndir, &tmp);
+        HIPCHK(hipMemcpy(d_dirs, dirs, 3 * (size_t)ndir * 8, hipMemcpyHostToDevice));
+        hipStream_t st = (hipStream_t)hip_stream;
+        launch_far_field(dtype == MLFMA_C64, h->r.n, h->opt.wavenumber, h->perm, h->g_rtri, h->g_rloc, h->g_rcoef,
+                         h->g_tv, h->g_ta, d_dirs, (int)ndir, x, ldx, F, (int)nrhs, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
 int mlfma_translation_operator(double k, int L, const double X[3], long long nk, const double *khat, double *out)
 {
     if (!(k > 0) || L < 0 || !X || nk < 0 || (nk && (!khat || !out))) return fail(Error(MLFMA_ERR_ARG, "bad args"));

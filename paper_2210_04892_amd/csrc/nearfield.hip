@@ -377,7 +377,110 @@ __global__ void k_plane_wave(int N, int nrhs, double k, const int *__restrict__ 
     b[(long long)r * ldb + N + u] = {(T)bm.re, (T)bm.im};
 }
 
+// -------------------------------------------------------------- far field
+// F(khat) = (-jk/4pi)[P_J - khat (khat . P_J) - khat x P_M], the far-zone
+// limit of E = L{J} - K{M} (plane-wave limits L -> -jk(I - khat khat),
+// K -> -jk khat x); P_X = Int X exp(+jk khat . r) ds with the 7-point rule on
+// both triangles of every RWG; the radar cross section of Sec. III is
+// 4 pi |F|^2.  Workgroup = (direction, right-hand side), threads over RWGs,
+// double-precision sums reduced in LDS; output F . theta_hat, F . phi_hat.
+template <class T>
+__global__ __launch_bounds__(256) void k_far_field(int N, double k, const int *__restrict__ perm,
+                                                   const int *__restrict__ rtri, const int *__restrict__ rloc,
+                                                   const double *__restrict__ rcoef, const double *__restrict__ tri_v,
+                                                   const double *__restrict__ tri_a, const double *__restrict__ dirs,
+                                                   const cpx<T> *__restrict__ x, long long ldx, cpx<T> *__restrict__ F,
+                                                   int nrhs)
+{
+    __shared__ double red[12][256];
+    const int d = blockIdx.x, r = blockIdx.y;
+    const V3 kh = v3(dirs + 3 * d);
+    double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // P_J (re, im) xyz, then P_M
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int u = perm[i];
+        const cpx<T> xj = x[(long long)r * ldx + u], xm = x[(long long)r * ldx + N + u];
+        for (int s2 = 0; s2 < 2; s2++) {
+            const int t = rtri[2 * i + s2];
+            const double cf = rcoef[2 * i + s2] * tri_a[t];
+            const V3 P0 = v3(tri_v + 9LL * t), P1 = v3(tri_v + 9LL * t + 3), P2 = v3(tri_v + 9LL * t + 6);
+            const V3 pf = v3(tri_v + 9LL * t + 3 * rloc[2 * i + s2]);
+            for (int q = 0; q < 7; q++) {
+                double l0, l1, l2, w;
+                radon7(q, l0, l1, l2, w);
+                const V3 xq = l0 * P0 + l1 * P1 + l2 * P2;
+                const V3 a = (w * cf) * (xq - pf);
+                double sn, cs;
+                sincos(k * dot(kh, xq), &sn, &cs);
+                // a e^{+j phase} times the coefficients
+                const double pjr = cs * xj.re - sn * xj.im, pji = cs * xj.im + sn * xj.re;
+                const double pmr = cs * xm.re - sn * xm.im, pmi = cs * xm.im + sn * xm.re;
+                const double av[3] = {a.x, a.y, a.z};
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    acc[2 * c] += av[c] * pjr;
+                    acc[2 * c + 1] += av[c] * pji;
+                    acc[6 + 2 * c] += av[c] * pmr;
+                    acc[6 + 2 * c + 1] += av[c] * pmi;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 12; c++) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+#pragma unroll
+            for (int c = 0; c < 12; c++) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double kk[3] = {kh.x, kh.y, kh.z};
+    double PJr[3], PJi[3], PMr[3], PMi[3];
+    for (int c = 0; c < 3; c++) {
+        PJr[c] = red[2 * c][0];
+        PJi[c] = red[2 * c + 1][0];
+        PMr[c] = red[6 + 2 * c][0];
+        PMi[c] = red[6 + 2 * c + 1][0];
+    }
+    const double kpr = kk[0] * PJr[0] + kk[1] * PJr[1] + kk[2] * PJr[2];
+    const double kpi = kk[0] * PJi[0] + kk[1] * PJi[1] + kk[2] * PJi[2];
+    double Fr[3], Fi[3];
+    for (int c = 0; c < 3; c++) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        Fr[c] = PJr[c] - kk[c] * kpr - (kk[c1] * PMr[c2] - kk[c2] * PMr[c1]);
+        Fi[c] = PJi[c] - kk[c] * kpi - (kk[c1] * PMi[c2] - kk[c2] * PMi[c1]);
+    }
+    const double th = acos(fmax(-1.0, fmin(1.0, kk[2]))), ph = atan2(kk[1], kk[0]);
+    const double tv[3] = {cos(th) * cos(ph), cos(th) * sin(ph), -sin(th)}, pv[3] = {-sin(ph), cos(ph), 0.0};
+    const double pre = k / (4 * M_PI);   // F = -j pre (...)
+    double ftr = 0, fti = 0, fpr = 0, fpi = 0;
+    for (int c = 0; c < 3; c++) {
+        ftr += Fr[c] * tv[c];
+        fti += Fi[c] * tv[c];
+        fpr += Fr[c] * pv[c];
+        fpi += Fi[c] * pv[c];
+    }
+    // -j (a + jb) = b - ja
+    F[((long long)d * 2) * nrhs + r] = {(T)(pre * fti), (T)(-pre * ftr)};
+    F[((long long)d * 2 + 1) * nrhs + r] = {(T)(pre * fpi), (T)(-pre * fpr)};
+}
+
 // ---------------------------------------------------------------- launchers
+void launch_far_field(bool single, int N, double k, const int *perm, const int *rtri, const int *rloc,
+                      const double *rcoef, const double *tri_v, const double *tri_a, const double *dirs, int ndir,
+                      const void *x, long long ldx, void *F, int nrhs, hipStream_t s)
+{
+    if (ndir <= 0 || nrhs <= 0) return;
+    const dim3 grid(ndir, nrhs);
+    if (single)
+        hipLaunchKernelGGL(k_far_field<float>, grid, dim3(256), 0, s, N, k, perm, rtri, rloc, rcoef, tri_v, tri_a,
+                           dirs, (const cpx<float> *)x, ldx, (cpx<float> *)F, nrhs);
+    else
+        hipLaunchKernelGGL(k_far_field<double>, grid, dim3(256), 0, s, N, k, perm, rtri, rloc, rcoef, tri_v, tri_a,
+                           dirs, (const cpx<double> *)x, ldx, (cpx<double> *)F, nrhs);
+}
+
 void launch_plane_wave(bool single, int N, int nrhs, double k, const int *perm, const int *rtri, const int *rloc,
                        const double *rcoef, const double *tri_v, const double *tri_n, const double *tri_a,
                        const double *dirs, void *b, long long ldb, hipStream_t s)

@@ -31,4 +31,11 @@ void launch_plane_wave(bool single, int N, int nrhs, double k, const int *perm, 
                        const double *rcoef, const double *tri_v, const double *tri_n, const double *tri_a,
                        const double *dirs, void *b, long long ldb, hipStream_t s);
 
+// far field F . theta_hat, F . phi_hat of the currents x (user RWG order,
+// 2N x nrhs) in ndir directions (dirs: device, ndir x 3): F is ndir x 2 x
+// nrhs; single = complex64 input/output, else complex128
+void launch_far_field(bool single, int N, double k, const int *perm, const int *rtri, const int *rloc,
+                      const double *rcoef, const double *tri_v, const double *tri_a, const double *dirs, int ndir,
+                      const void *x, long long ldx, void *F, int nrhs, hipStream_t s);
+
 }  // namespace mlfma

@@ -239,6 +239,27 @@ def test_gmres_solves_the_oracle_system():
         assert err <= check
 
 
+@pytest.mark.parametrize("name", ["ico6_r0.5", "sphere_r3"])
+def test_far_field_matches_oracle(name):
+    """mlfma_far_field against the oracle's direct quadrature (the same
+    7-point sums, so complex128 agrees to rounding; complex64 to single
+    precision), for random currents over the principal cut phi = 0 and a
+    Fibonacci set of directions (poles included in the cut)."""
+    torch = _torch()
+    v, t = mesh(name)
+    N2 = 3 * len(t)
+    x = synth.gaussian_coeffs(N2, 2, 31)
+    th = np.linspace(0, np.pi, 13)
+    dirs = np.concatenate([np.stack([np.sin(th), 0 * th, np.cos(th)], axis=1), synth.fibonacci_directions(11, 4)[0]])
+    ref = oracle.far_field(v, t, K0, x, dirs)
+    g = geometry(name)
+    for dtype, tol in ((torch.complex128, 1e-11), (torch.complex64, 2e-5)):
+        F = g.far_field(torch.from_numpy(x).to(dtype).cuda(), dirs).cpu().numpy().astype(np.complex128)
+        err = _rel(F, ref)
+        print("[gpu] %s far field %s rel err %.2e" % (name, dtype, err), flush=True)
+        assert err <= tol
+
+
 def test_tiny_mesh_is_all_near():
     """A mesh smaller than three octree levels has no far field: the whole
     product is the double-precision near field."""
