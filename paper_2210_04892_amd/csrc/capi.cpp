@@ -853,6 +853,11 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
         if constexpr (std::is_same<T, float>::value)
             done = launch_near_mfma(c->n_items, c->items, c->box_start, c->col_off, c->cols, c->val_off, vals, ids,
                                     c->id_col, P.id_w, X, Y, nrhs, st);
+        if (!done && nrhs == 1) {
+            launch_near_tile<T>(c->n_items, c->items, c->box_start, c->col_off, c->cols, c->val_off, vals, ids,
+                                c->id_col, P.id_w, X, Y, st);
+            done = true;
+        }
         if (!done)
             launch_near<T>(N, c->leaf_of, c->box_start, c->near_start, c->near_box, c->val_off, vals, ids, c->id_col,
                            P.id_w, X, Y, nrhs, st);

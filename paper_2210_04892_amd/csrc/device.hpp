@@ -70,6 +70,12 @@ template <class T>
 void launch_near(int N, const int *leaf_of, const int *box_start, const int *near_start, const int *near_box,
                  const long long *val_off, const cpx<T> *vals, const int *id_start, const int *id_col, const T *id_w,
                  const cpx<T> *X, cpx<T> *Y, int nrhs, hipStream_t s);
+// near field, one right-hand side: wave per (leaf box, tile of 8 RWGs) work
+// item, columns of the box from cols[col_off[b] ..]
+template <class T>
+void launch_near_tile(int nitem, const int2 *items, const int *box_start, const int *col_off, const int *cols,
+                      const long long *val_off, const cpx<T> *vals, const int *id_start, const int *id_col,
+                      const T *id_w, const cpx<T> *X, cpx<T> *Y, hipStream_t s);
 template <class T>
 void launch_radiate(int op, int nbox, int K, const int *box_start, const cpx<T> *R, const cpx<T> *X, cpx<T> *U,
                     int nrhs, hipStream_t s);

@@ -174,6 +174,73 @@ __global__ __launch_bounds__(256) void k_near(int N, const int *__restrict__ lea
     }
 }
 
+// Near field for one right-hand side.  Wave = (leaf box, tile of up to 8
+// RWGs of the box, i.e. one (box, 16-row tile) work item); lanes over the
+// box's columns (the RWGs of its adjacent boxes, concatenated in cols), so
+// every column's x is loaded once for the 8 rows and the column structure
+// is not rebuilt per row.  Rows are written (=), identity terms of the C
+// block added by the lane that owns the row.
+template <class T>
+__global__ __launch_bounds__(256) void k_near_tile(int nitem, const int2 *__restrict__ items,
+                                                   const int *__restrict__ box_start, const int *__restrict__ col_off,
+                                                   const int *__restrict__ cols, const long long *__restrict__ val_off,
+                                                   const cpx<T> *__restrict__ vals, const int *__restrict__ id_start,
+                                                   const int *__restrict__ id_col, const T *__restrict__ id_w,
+                                                   const cpx<T> *__restrict__ X, cpx<T> *__restrict__ Y)
+{
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const long long blk = xcd_block((nitem + 3) / 4);
+    if (blk < 0) return;
+    const long long w = blk * 4 + wave;
+    if (w >= nitem) return;
+    const int2 it = items[w];
+    const int b = it.x, m0 = it.y * 8;
+    const int n0 = box_start[b], nr = min(8, box_start[b + 1] - n0 - m0);
+    const int *cl = cols + col_off[b];
+    const int ncols = col_off[b + 1] - col_off[b];
+    const cpx<T> *vr = vals + 2 * (val_off[b] + (long long)m0 * ncols);
+    cpx<T> a1[8], a2[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) a1[i] = a2[i] = mk<T>(0, 0);
+    for (int j = lane; j < ncols; j += WAVE) {
+        const long long col = cl[j];
+        const cpx<T> x1 = X[col * 2], x2 = X[col * 2 + 1];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            if (i >= nr) break;
+            const cpx<T> A = vr[2 * ((long long)i * ncols + j)], B = vr[2 * ((long long)i * ncols + j) + 1];
+            fma_to(a1[i], A, x1);
+            fms_to(a1[i], B, x2);
+            fma_to(a2[i], A, x2);
+            fma_to(a2[i], B, x1);
+        }
+    }
+    cpx<T> y1 = mk<T>(0, 0), y2 = mk<T>(0, 0);
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        if (i >= nr) break;
+        const cpx<T> s1 = wave_sum(a1[i]), s2 = wave_sum(a2[i]);
+        if (lane == i) {
+            y1 = s1;
+            y2 = s2;
+        }
+    }
+    if (lane >= nr) return;
+    const int m = n0 + m0 + lane;
+    if (id_start) {
+        for (int e = id_start[m]; e < id_start[m + 1]; e++) {
+            const long long col = id_col[e];
+            const T g = id_w[2 * e], gx = id_w[2 * e + 1];
+            const cpx<T> x1 = X[col * 2], x2 = X[col * 2 + 1];
+            axpy_to(y1, g, x1);
+            axpy_to(y1, T(0.5) * gx, x2);
+            axpy_to(y2, T(0.5) * g, x2);
+        }
+    }
+    Y[(long long)m * 2] = y1;
+    Y[(long long)m * 2 + 1] = y2;
+}
+
 // Broadcast lane `src` of a wave (uniform src) through the scalar unit.
 __device__ inline float bcast(float v, int src)
 {
@@ -291,6 +358,7 @@ __global__ __launch_bounds__(256) void k_radiate(int op, int nbox, int K, const 
     cpx<T> ut[NR], up[NR];
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) ut[rr] = up[rr] = mk<T>(0, 0);
+#pragma unroll 4
     for (int i = box_start[b]; i < box_start[b + 1]; i++) {
         const cpx<T> Rt = R[((long long)i * K + q) * 2], Rp = R[((long long)i * K + q) * 2 + 1];
 #pragma unroll
@@ -781,6 +849,16 @@ void launch_perm_out(const cpx<T> *Y, cpx<T> *y, long long ldy, const int *iperm
     } while (0)
 
 template <class T>
+void launch_near_tile(int nitem, const int2 *items, const int *box_start, const int *col_off, const int *cols,
+                      const long long *val_off, const cpx<T> *vals, const int *id_start, const int *id_col,
+                      const T *id_w, const cpx<T> *X, cpx<T> *Y, hipStream_t s)
+{
+    if (nitem <= 0) return;
+    hipLaunchKernelGGL(k_near_tile<T>, dim3(xcd_grid((nitem + 3) / 4)), dim3(256), 0, s, nitem, items, box_start,
+                       col_off, cols, val_off, vals, id_start, id_col, id_w, X, Y);
+}
+
+template <class T>
 void launch_near(int N, const int *leaf_of, const int *box_start, const int *near_start, const int *near_box,
                  const long long *val_off, const cpx<T> *vals, const int *id_start, const int *id_col, const T *id_w,
                  const cpx<T> *X, cpx<T> *Y, int nrhs, hipStream_t s)
@@ -936,6 +1014,9 @@ void launch_receive(int op, int N, int K, const int *leaf_of, const cpx<T> *R, c
 #define INSTANTIATE(T)                                                                                              \
     template void launch_perm_in<T>(const cpx<T> *, long long, cpx<T> *, const int *, int, int, hipStream_t);     \
     template void launch_perm_out<T>(const cpx<T> *, cpx<T> *, long long, const int *, int, int, hipStream_t);    \
+    template void launch_near_tile<T>(int, const int2 *, const int *, const int *, const int *, const long long *, \
+                                      const cpx<T> *, const int *, const int *, const T *, const cpx<T> *, cpx<T> *, \
+                                      hipStream_t);                                                               \
     template void launch_near<T>(int, const int *, const int *, const int *, const int *, const long long *,     \
                                  const cpx<T> *, const int *, const int *, const T *, const cpx<T> *, cpx<T> *, \
                                  int, hipStream_t);                                                               \
