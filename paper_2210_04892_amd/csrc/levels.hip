@@ -13,6 +13,8 @@
 // needs in LDS with coalesced loads, forms the intermediate (parent theta x
 // child phi) rows in LDS, and writes only its own outputs.  The intermediate
 // never goes to memory.
+#include <algorithm>
+
 #include "device.hpp"
 
 namespace mlfma {
@@ -37,44 +39,44 @@ __device__ inline long long pat(long long b, int c, int r, int q, int nrhs, int 
 constexpr int STEP_THREADS = 256;
 constexpr int STEP_OUT = 4;     // outputs per thread: a chunk has at most 4 * 256 of them
 
-// aggregation: workgroup = (parent, chunk of parent theta rows, RB
-// right-hand sides); the stencil taps are loaded once for all RB of them
-// (the launcher uses RB = 1)
-template <class T, int P, int RB>
-__global__ __launch_bounds__(STEP_THREADS) void k_aggregate(const LevelStep<T> a, int nrhs)
+// aggregation: workgroup = (parent, chunk of parent theta rows, one right-
+// hand side); the parent's children are taken in groups of G: the group's
+// windows are staged together, their intermediates formed together, then the
+// phi stencil and the shift accumulate over the group (three barriers per
+// group instead of per child)
+template <class T, int P, bool GROUPED>
+__global__ __launch_bounds__(STEP_THREADS) void k_aggregate(const LevelStep<T> a, int nrhs, int Gr)
 {
+    const int G = GROUPED ? Gr : 1;
     extern __shared__ double step_lds_raw[];
     const long long blk = xcd_block_l((long long)a.nbox * a.nchunk);
     if (blk < 0) return;
     const int Pb = (int)(blk / a.nchunk), ch = (int)(blk % a.nchunk);
-    const int r0 = blockIdx.y * RB;
+    const int r = blockIdx.y;
     const int Kc = a.nth_c * a.nph_c, Kp = a.nth_p * a.nph_p;
     const int i0 = ch * a.rows, i1 = min(a.nth_p, i0 + a.rows);
     const int w0 = a.win[2 * ch], w1 = a.win[2 * ch + 1];
     const int wlen = (w1 - w0) * a.nph_c, wmax = a.wrows * a.nph_c;
     const int mlen = (i1 - i0) * a.nph_c, mmax = a.rows * a.nph_c;
     const int olen = (i1 - i0) * a.nph_p;
-    cpx<T> *cw = reinterpret_cast<cpx<T> *>(step_lds_raw);   // [RB][2][wmax] child windows
-    cpx<T> *mid = cw + 2 * RB * wmax;                         // [RB][2][mmax] intermediates
-    cpx<T> acc0[STEP_OUT][RB], acc1[STEP_OUT][RB];
+    cpx<T> *cw = reinterpret_cast<cpx<T> *>(step_lds_raw);   // [G][2][wmax] child windows
+    cpx<T> *mid = cw + 2 * (size_t)G * wmax;                  // [G][2][mmax] intermediates
+    cpx<T> acc0[STEP_OUT], acc1[STEP_OUT];
 #pragma unroll
-    for (int k = 0; k < STEP_OUT; k++)
-#pragma unroll
-        for (int j = 0; j < RB; j++) acc0[k][j] = acc1[k][j] = mk<T>(0, 0);
+    for (int k = 0; k < STEP_OUT; k++) acc0[k] = acc1[k] = mk<T>(0, 0);
     const int cb = a.child_start[Pb], ce = a.child_start[Pb + 1];
-    for (int c = cb; c < ce; c++) {
-#pragma unroll
-        for (int j = 0; j < RB; j++) {
-            const int r = min(r0 + j, nrhs - 1);
-            const cpx<T> *u0 = a.in + pat(c, 0, r, w0 * a.nph_c, nrhs, Kc);
-            const cpx<T> *u1 = a.in + pat(c, 1, r, w0 * a.nph_c, nrhs, Kc);
+    for (int cg = cb; cg < ce; cg += G) {
+        const int ng = GROUPED ? min(G, ce - cg) : 1;
+        for (int g = 0; g < ng; g++) {
+            const cpx<T> *u0 = a.in + pat(cg + g, 0, r, w0 * a.nph_c, nrhs, Kc);
+            const cpx<T> *u1 = u0 + (long long)nrhs * Kc;
             for (int i = threadIdx.x; i < wlen; i += STEP_THREADS) {
-                cw[(2 * j) * wmax + i] = u0[i];
-                cw[(2 * j + 1) * wmax + i] = u1[i];
+                cw[(2 * g) * wmax + i] = u0[i];
+                cw[(2 * g + 1) * wmax + i] = u1[i];
             }
         }
         __syncthreads();
-        // theta: mid row (parent theta i, child phi j) from the child window
+        // theta: mid row (parent theta i, child phi j) of every child of the group
         for (int m = threadIdx.x; m < mlen; m += STEP_THREADS) {
             const long long row = (long long)i0 * a.nph_c + m;
             int cc[P];
@@ -84,62 +86,54 @@ __global__ __launch_bounds__(STEP_THREADS) void k_aggregate(const LevelStep<T> a
                 cc[t] = a.c1[row * P + t] - w0 * a.nph_c;
                 ww[t] = a.w1[row * P + t];
             }
-#pragma unroll
-            for (int j = 0; j < RB; j++) {
-                const cpx<T> *w0p = cw + (2 * j) * wmax, *w1p = cw + (2 * j + 1) * wmax;
+            for (int g = 0; g < ng; g++) {
+                const cpx<T> *c0 = cw + (2 * g) * wmax, *c1 = cw + (2 * g + 1) * wmax;
                 cpx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
 #pragma unroll
                 for (int t = 0; t < P; t++) {
-                    axpy_to(s0, ww[t], w0p[cc[t]]);
-                    axpy_to(s1, ww[t], w1p[cc[t]]);
+                    axpy_to(s0, ww[t], c0[cc[t]]);
+                    axpy_to(s1, ww[t], c1[cc[t]]);
                 }
-                mid[(2 * j) * mmax + m] = s0;
-                mid[(2 * j + 1) * mmax + m] = s1;
+                mid[(2 * g) * mmax + m] = s0;
+                mid[(2 * g + 1) * mmax + m] = s1;
             }
         }
         __syncthreads();
-        // phi, then the shift to the parent centre
-        const cpx<T> *sh = a.shift + (long long)a.oct[c] * Kp;
+        // phi and the shift to the parent centre, summed over the group
 #pragma unroll
         for (int k = 0; k < STEP_OUT; k++) {
             const int o = threadIdx.x + k * STEP_THREADS;
-            if (o < olen) {
-                const long long q = (long long)i0 * a.nph_p + o;
-                int cc[P];
-                T ww[P];
+            if (o >= olen) continue;
+            const long long q = (long long)i0 * a.nph_p + o;
+            int cc[P];
+            T ww[P];
+#pragma unroll
+            for (int t = 0; t < P; t++) {
+                cc[t] = a.c2[q * P + t] - i0 * a.nph_c;
+                ww[t] = a.w2[q * P + t];
+            }
+            for (int g = 0; g < ng; g++) {
+                const cpx<T> *m0 = mid + (2 * g) * mmax, *m1 = mid + (2 * g + 1) * mmax;
+                cpx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
 #pragma unroll
                 for (int t = 0; t < P; t++) {
-                    cc[t] = a.c2[q * P + t] - i0 * a.nph_c;
-                    ww[t] = a.w2[q * P + t];
+                    axpy_to(s0, ww[t], m0[cc[t]]);
+                    axpy_to(s1, ww[t], m1[cc[t]]);
                 }
-                const cpx<T> f = sh[q];
-#pragma unroll
-                for (int j = 0; j < RB; j++) {
-                    const cpx<T> *m0 = mid + (2 * j) * mmax, *m1 = mid + (2 * j + 1) * mmax;
-                    cpx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
-#pragma unroll
-                    for (int t = 0; t < P; t++) {
-                        axpy_to(s0, ww[t], m0[cc[t]]);
-                        axpy_to(s1, ww[t], m1[cc[t]]);
-                    }
-                    fma_to(acc0[k][j], f, s0);
-                    fma_to(acc1[k][j], f, s1);
-                }
+                const cpx<T> f = a.shift[(long long)a.oct[cg + g] * Kp + q];
+                fma_to(acc0[k], f, s0);
+                fma_to(acc1[k], f, s1);
             }
         }
-        __syncthreads();   // the next child reuses the windows and the intermediates
+        __syncthreads();   // the next group reuses the windows and the intermediates
     }
 #pragma unroll
     for (int k = 0; k < STEP_OUT; k++) {
         const int o = threadIdx.x + k * STEP_THREADS;
         if (o >= olen) continue;
         const int q = i0 * a.nph_p + o;
-#pragma unroll
-        for (int j = 0; j < RB; j++) {
-            if (r0 + j >= nrhs) continue;
-            a.out[pat(Pb, 0, r0 + j, q, nrhs, Kp)] = acc0[k][j];
-            a.out[pat(Pb, 1, r0 + j, q, nrhs, Kp)] = acc1[k][j];
-        }
+        a.out[pat(Pb, 0, r, q, nrhs, Kp)] = acc0[k];
+        a.out[pat(Pb, 1, r, q, nrhs, Kp)] = acc1[k];
     }
 }
 
@@ -243,10 +237,10 @@ inline int step_rb(size_t lds1, int nrhs)
 }  // namespace
 
 template <class T, int P>
-void agg_launch(int rb, dim3 grid, dim3 block, size_t lds, hipStream_t s, const LevelStep<T> &a, int nrhs)
+void agg_launch(int G, dim3 grid, dim3 block, size_t lds, hipStream_t s, const LevelStep<T> &a, int nrhs)
 {
-    (void)rb;
-    hipLaunchKernelGGL((k_aggregate<T, P, 1>), grid, block, lds, s, a, nrhs);
+    if (G > 1) hipLaunchKernelGGL((k_aggregate<T, P, true>), grid, block, lds, s, a, nrhs, G);
+    else hipLaunchKernelGGL((k_aggregate<T, P, false>), grid, block, lds, s, a, nrhs, 1);
 }
 
 template <class T>
@@ -254,17 +248,19 @@ bool launch_aggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s)
 {
     if (a.nchunk <= 0 || (long long)a.rows * a.nph_p > STEP_OUT * STEP_THREADS) return false;
     if (a.taps != 6 && a.taps != 8 && a.taps != 10) return false;
-    const size_t lds1 = agg_lds_bytes<T>(a.wrows, a.rows, a.nph_c);
+    const size_t lds1 = agg_lds_bytes<T>(a.wrows, a.rows, a.nph_c);   // one child
     if (lds1 > STEP_LDS_MAX) return false;
     if (a.nbox <= 0 || nrhs <= 0) return true;
-    // one right-hand side per workgroup: blocking them costs the aggregation
-    // more in registers (and occupancy) than it saves in stencil loads
-    const int rb = 1;
+    // children per group: with few right-hand sides the grid is small and
+    // the per-child barriers dominate, so up to all eight children that fit
+    // the LDS budget are grouped; with more, one child at a time keeps the
+    // LDS per workgroup (and so the occupancy) low
+    const int G = nrhs < 4 ? (int)std::min<size_t>(8, STEP_LDS_MAX / lds1) : 1;
     const dim3 grid(xcd_grid_l((long long)a.nbox * a.nchunk), nrhs), block(STEP_THREADS);
-    const size_t lds = lds1;
-    if (a.taps == 6) agg_launch<T, 6>(rb, grid, block, lds, s, a, nrhs);
-    else if (a.taps == 8) agg_launch<T, 8>(rb, grid, block, lds, s, a, nrhs);
-    else agg_launch<T, 10>(rb, grid, block, lds, s, a, nrhs);
+    const size_t lds = G * lds1;
+    if (a.taps == 6) agg_launch<T, 6>(G, grid, block, lds, s, a, nrhs);
+    else if (a.taps == 8) agg_launch<T, 8>(G, grid, block, lds, s, a, nrhs);
+    else agg_launch<T, 10>(G, grid, block, lds, s, a, nrhs);
     return true;
 }
 
