@@ -4,7 +4,8 @@ Only tests, the smoke check and the CPU-baseline leg of the benchmark may
 import this package.  It shares no code with the GPU library.
 """
 from .oracle import (build, rwg_table, matvec, pair_integrals, leaf_boxes, threads, plane_wave_rhs, far_field,
-                     OP_C, OP_EM, OP_BOTH, PRIM)
+                     entries, blocks, OP_C, OP_EM, OP_BOTH, PRIM)
+from . import sai
 
 __all__ = ["build", "rwg_table", "matvec", "pair_integrals", "leaf_boxes", "threads", "plane_wave_rhs", "far_field",
-           "OP_C", "OP_EM", "OP_BOTH", "PRIM"]
+           "entries", "blocks", "sai", "OP_C", "OP_EM", "OP_BOTH", "PRIM"]

@@ -112,7 +112,7 @@ static int mesh_build(mesh_t *m, int nv, const double *v, int nt, const int *t)
     if (nv < 4 || nt < 4) return ORC_ERR_MESH;
     m->area = malloc(sizeof(double) * nt);
     m->nrm = malloc(sizeof(double) * 3 * nt);
-    double vol6 = 0.0, maxa = 0.0;
+    double maxa = 0.0;
     for (int i = 0; i < nt; i++) {
         for (int c = 0; c < 3; c++)
             if (t[3 * i + c] < 0 || t[3 * i + c] >= nv) return ORC_ERR_MESH;
@@ -123,13 +123,9 @@ static int mesh_build(mesh_t *m, int nv, const double *v, int nt, const int *t)
         m->area[i] = 0.5 * a2;
         if (m->area[i] > maxa) maxa = m->area[i];
         for (int k = 0; k < 3; k++) m->nrm[3 * i + k] = a2 > 0 ? c[k] / a2 : 0.0;
-        double pc[3];
-        vcross(p1, p2, pc);
-        vol6 += vdot(p0, pc);
     }
     for (int i = 0; i < nt; i++)
         if (!(m->area[i] > 1e-12 * maxa)) return ORC_ERR_MESH;
-    if (!(vol6 > 0)) return ORC_ERR_MESH;          /* normals must point outward */
 
     half_edge *h = malloc(sizeof(half_edge) * 3 * nt);
     for (int i = 0; i < nt; i++)
@@ -162,7 +158,33 @@ static int mesh_build(mesh_t *m, int nv, const double *v, int nt, const int *t)
         m->tri_rwg[3 * q->tri + q->loc] = r; m->tri_sgn[3 * q->tri + q->loc] = -1.0;
     }
     free(h);
-    return ORC_OK;
+    /* Several disconnected scatterers may share one surface mesh (the BI
+     * equations then hold on each closed surface, Sec. II-E remarks): every
+     * connected surface must enclose a positive volume (outward normals).
+     * Connected pieces are found by joining the two triangles of each RWG. */
+    int *root = malloc(sizeof(int) * nt);
+    double *vol6 = calloc(nt, sizeof(double));
+    for (int i = 0; i < nt; i++) root[i] = i;
+    for (int r = 0; r < n; r++) {
+        int a = m->tp[r], b = m->tm[r];
+        while (root[a] != a) { root[a] = root[root[a]]; a = root[a]; }
+        while (root[b] != b) { root[b] = root[root[b]]; b = root[b]; }
+        if (a != b) root[a < b ? b : a] = a < b ? a : b;
+    }
+    for (int i = 0; i < nt; i++) {
+        int a = i;
+        while (root[a] != a) { root[a] = root[root[a]]; a = root[a]; }
+        const double *p0 = v + 3 * t[3 * i], *p1 = v + 3 * t[3 * i + 1], *p2 = v + 3 * t[3 * i + 2];
+        double pc[3];
+        vcross(p1, p2, pc);
+        vol6[a] += vdot(p0, pc);
+    }
+    int inward = 0;
+    for (int i = 0; i < nt; i++)
+        if (root[i] == i && !(vol6[i] > 0)) inward = 1;
+    free(root);
+    free(vol6);
+    return inward ? ORC_ERR_MESH : ORC_OK;
 }
 
 /* coefficient of (r - p_j) for the RWG on local edge j of triangle i */
@@ -805,6 +827,85 @@ int oracle_matvec(int nv, const double *v, int nt, const int *t, double k, int o
     }
     for (int r = 0; r < nr; r++) omp_destroy_lock(&locks[r]);
     free(locks); free(acc_all); free(gram); free(need); free(outpos); free(coords);
+    mesh_free(&m);
+    return quad_fail ? ORC_ERR_QUAD : ORC_OK;
+}
+
+/*
+ * Primitive matrix entries of explicit RWG pairs (test m, source n):
+ * out[6 e + o] (complex, interleaved) = T, K, Tx, Kx, Gram, Gx of pair e, by
+ * the same rules as oracle_matvec (7 x 7 points for triangle pairs sharing
+ * no vertex, converged singular rules otherwise, 7-point Gram terms).  The
+ * sum over the four triangle pairs of the two RWGs is written out here; the
+ * product oracle sums the same local integrals in another order.
+ */
+int oracle_entries(int nv, const double *v, int nt, const int *t, double k, int npairs, const int *pairs,
+                   double *out_)
+{
+    if (npairs < 0 || k <= 0) return ORC_ERR_ARG;
+    mesh_t m;
+    int rc = mesh_build(&m, nv, v, nt, t);
+    if (rc != ORC_OK) { mesh_free(&m); return rc; }
+    for (int e = 0; e < npairs; e++)
+        if (pairs[2 * e] < 0 || pairs[2 * e] >= m.n || pairs[2 * e + 1] < 0 || pairs[2 * e + 1] >= m.n) {
+            mesh_free(&m);
+            return ORC_ERR_ARG;
+        }
+    cplx *out = (cplx *)out_;
+    int quad_fail = 0;
+    double bary[7][3], w[7];
+    tri7(bary, w);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int e = 0; e < npairs; e++) {
+        const int mr = pairs[2 * e], nr_ = pairs[2 * e + 1];
+        const int ttri[2] = {m.tp[mr], m.tm[mr]}, stri[2] = {m.tp[nr_], m.tm[nr_]};
+        cplx acc[6] = {0, 0, 0, 0, 0, 0};
+        for (int a = 0; a < 2; a++) {
+            const int ti = ttri[a];
+            int i = 0;
+            while (m.tri_rwg[3 * ti + i] != mr) i++;
+            double P[3][3];
+            int tv[3];
+            for (int q = 0; q < 3; q++) {
+                tv[q] = t[3 * ti + q];
+                for (int c = 0; c < 3; c++) P[q][c] = v[3 * tv[q] + c];
+            }
+            const double cm = rwg_coef(&m, ti, i);
+            for (int b = 0; b < 2; b++) {
+                const int si = stri[b];
+                int j = 0;
+                while (m.tri_rwg[3 * si + j] != nr_) j++;
+                double Q[3][3];
+                int sv[3];
+                for (int q = 0; q < 3; q++) {
+                    sv[q] = t[3 * si + q];
+                    for (int c = 0; c < 3; c++) Q[q][c] = v[3 * sv[q] + c];
+                }
+                const double cn = rwg_coef(&m, si, j);
+                cplx loc[4][3][3];
+                if (pair_integrals_auto(tv, P, sv, Q, &m.nrm[3 * ti], KER_FULL, k, AUTO_TOL, loc) < 0) {
+#pragma omp atomic write
+                    quad_fail = 1;
+                }
+                for (int o = 0; o < 4; o++) acc[o] += cm * cn * loc[o][i][j];
+                if (ti == si) {          /* Gram and Gx: common triangle, exact 7-point rule */
+                    const double *nn = &m.nrm[3 * ti];
+                    double g = 0, gx = 0;
+                    for (int p = 0; p < 7; p++) {
+                        double r[3], x1[3], x2[3], nb[3];
+                        for (int c = 0; c < 3; c++)
+                            r[c] = bary[p][0] * P[0][c] + bary[p][1] * P[1][c] + bary[p][2] * P[2][c];
+                        vsub(r, P[i], x1); vsub(r, P[j], x2); vcross(nn, x2, nb);
+                        g += w[p] * m.area[ti] * vdot(x1, x2);
+                        gx += w[p] * m.area[ti] * vdot(x1, nb);
+                    }
+                    acc[4] += cm * cn * g;
+                    acc[5] += cm * cn * gx;
+                }
+            }
+        }
+        for (int o = 0; o < 6; o++) out[6 * (size_t)e + o] = acc[o];
+    }
     mesh_free(&m);
     return quad_fail ? ORC_ERR_QUAD : ORC_OK;
 }

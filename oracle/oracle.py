@@ -39,6 +39,7 @@ def _load():
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_far_field.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P,
                                          ctypes.c_int, P, P]
+        lib.oracle_entries.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P, P]
         lib.oracle_plane_wave_rhs.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
                                               P, P, P]
         _lib = lib
@@ -65,6 +66,33 @@ def rwg_table(verts, tris):
     if rc < 0:
         raise ValueError("oracle rejected the mesh (code %d)" % rc)
     return e[:rc], pm[:rc]
+
+
+def entries(verts, tris, k, pairs):
+    """Primitive entries of RWG pairs (test m, source n) = rows of `pairs`
+    (npairs, 2): array (npairs, 6) complex with columns T, K, Tx, Kx, Gram, Gx."""
+    v, t = _mesh(verts, tris)
+    pr = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
+    out = np.zeros((len(pr), 6), np.complex128)
+    rc = _load().oracle_entries(len(v), v.ctypes.data, len(t), t.ctypes.data, k, len(pr), pr.ctypes.data,
+                                out.ctypes.data)
+    if rc < 0:
+        raise ValueError("oracle_entries failed (code %d)" % rc)
+    return out
+
+
+def blocks(E, op=OP_C):
+    """2 x 2 blocks [[JJ, JM], [MJ, MM]] of each pair, shape (npairs, 2, 2),
+    from primitive entries E (npairs, 6).  op C: eqs. 43-46 with alpha = 1/2;
+    op EM: [[T, -K], [K, T]] (eqs. 22/24)."""
+    T, K, Tx, Kx, G, Gx = (E[:, i] for i in range(6))
+    if op == OP_C:
+        b = [[G - T / 2 - Kx / 2, Gx / 2 - Tx / 2 + K / 2], [Tx / 2 - K / 2, G / 2 - T / 2 - Kx / 2]]
+    elif op == OP_EM:
+        b = [[T, -K], [K, T]]
+    else:
+        raise ValueError("op must be OP_C or OP_EM")
+    return np.stack([np.stack(r, axis=-1) for r in b], axis=-2)
 
 
 def plane_wave_rhs(verts, tris, k, khat, pol):

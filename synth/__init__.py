@@ -6,9 +6,9 @@ coefficient vectors and seeded plane-wave directions/polarisation angles.
 Nothing in this package evaluates the boundary-integral method itself.
 """
 from .meshes import (icosphere, rounded_box, ellipsoid, tetrahedron, octahedron,
-                     icosahedron, flat_plate, mesh_stats)
+                     icosahedron, flat_plate, scene, mesh_stats)
 from .vectors import (gaussian_coeffs, fibonacci_directions, plane_waves, serving_set, workload)
 
 __all__ = ["icosphere", "rounded_box", "ellipsoid", "tetrahedron", "octahedron",
-           "icosahedron", "flat_plate", "mesh_stats", "gaussian_coeffs",
+           "icosahedron", "flat_plate", "scene", "mesh_stats", "gaussian_coeffs",
            "fibonacci_directions", "plane_waves", "serving_set", "workload"]

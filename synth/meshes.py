@@ -186,6 +186,17 @@ def flat_plate(size, n):
     return v, np.array(t, dtype=np.int32)
 
 
+def scene(*parts):
+    """Several closed surfaces in one mesh: parts are (verts, tris, offset)
+    with offset a translation (3,); vertex indices are renumbered."""
+    vs, ts, base = [], [], 0
+    for v, t, off in parts:
+        vs.append(np.asarray(v, np.float64) + np.asarray(off, np.float64))
+        ts.append(np.asarray(t, np.int32) + base)
+        base += len(v)
+    return np.concatenate(vs), np.concatenate(ts).astype(np.int32)
+
+
 def mesh_stats(verts, tris):
     e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]])
     e = np.unique(np.sort(e, axis=1), axis=0)

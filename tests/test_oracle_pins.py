@@ -63,6 +63,23 @@ def test_mesh_rejections():
         oracle.rwg_table(v, t[:-1])            # open surface
 
 
+def test_disconnected_surfaces():
+    """Disconnected scatterers in one mesh (Sec. II-E remarks: BI equations
+    on each surface): accepted when every closed surface is outward; one
+    inward surface is rejected even where the total enclosed volume is
+    positive.  RWGs never join two surfaces."""
+    a = synth.icosphere(2, 0.5)
+    b = synth.octahedron(0.2)
+    v, t = synth.scene((a[0], a[1], (0, 0, 0)), (b[0], b[1], (1.5, 0, 0)))
+    e, pm = oracle.rwg_table(v, t)
+    na = len(a[1])
+    assert len(e) == 3 * len(t) // 2
+    assert np.all((pm[:, 0] < na) == (pm[:, 1] < na))
+    v2, t2 = synth.scene((a[0], a[1], (0, 0, 0)), (b[0], b[1][:, ::-1], (1.5, 0, 0)))
+    with pytest.raises(ValueError):
+        oracle.rwg_table(v2, t2)
+
+
 # ------------------------------------------------------------------ P-H Gram
 @pytest.mark.parametrize("mesh", [synth.tetrahedron, synth.octahedron, synth.icosahedron])
 def test_gram_closed_form(mesh):
