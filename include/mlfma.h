@@ -212,6 +212,45 @@ int mlfma_graph_destroy(mlfma_graph g);
 int mlfma_gmres(mlfma_handle h, int op, int dtype, long long nrhs, const void *b, long long ldb, void *x,
                 long long ldx, int restart, int max_iters, double tol, int *iters, double *relres, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Sparse approximate inverse (SAI) preconditioner.  The paper preconditions
+ * GMRES with an SAI built from the BI block C alone (Sec. III, dielectric
+ * plate, citing the Frobenius-norm SAI of Lee et al.).  M minimises
+ * || I - C_near M ||_F column by column, where C_near holds the entries of
+ * op's matrix for RWG pairs in adjacent leaf boxes (the near field the
+ * library stores; for MLFMA_OP_C with its Gram terms): the columns (n, J)
+ * and (n, M) live on the J and M unknowns of pattern(n) = the k_nearest
+ * RWGs whose centres (edge midpoints) are nearest to n's among the RWGs of
+ * the leaf boxes adjacent to n's (n itself included; every RWG tied with the
+ * k-th distance to 1e-9 relative is included), and solve min || C_near m -
+ * e ||_2 over all rows of C_near by its normal equations (double precision,
+ * on the device).  Stored in complex128 and complex64.
+ *
+ * mlfma_sai_build: after mlfma_precompute_nearfield; k_nearest in 1..32.
+ *   Synchronous.  Replaces an earlier SAI of the same op.  Allocates
+ *   N x 2 x 64 entries in each precision plus index lists (counted against
+ *   the handle's budget).  MLFMA_ERR_UNSUPPORTED if ties push a pattern past
+ *   32 RWGs or a Gram matrix is not numerically positive definite.
+ * mlfma_sai_apply: y = M x for device x, y (column-major 2N x nrhs in user
+ *   RWG order, J rows then M rows; ldx, ldy >= 2N; must not overlap),
+ *   enqueued on hip_stream.  MLFMA_ERR_STATE before mlfma_sai_build.
+ * mlfma_sai_info: RWG-pair entries of M (each a 2 x 2 block), the largest
+ *   pattern, build time in ms (host + device) and device bytes held.
+ * mlfma_gmres_precond: mlfma_gmres with precond = MLFMA_PRECOND_SAI (right
+ *   preconditioning: GMRES on A M u = b, x = x0 + M u; the residuals and tol
+ *   are those of A x = b) or MLFMA_PRECOND_NONE (= mlfma_gmres).
+ *   MLFMA_ERR_STATE if the SAI of op was not built.
+ * ------------------------------------------------------------------------ */
+enum { MLFMA_PRECOND_NONE = 0, MLFMA_PRECOND_SAI = 1 };
+int mlfma_sai_build(mlfma_handle h, int op, int k_nearest);
+int mlfma_sai_apply(mlfma_handle h, int op, int dtype, long long nrhs, const void *x, long long ldx, void *y,
+                    long long ldy, void *hip_stream);
+int mlfma_sai_info(mlfma_handle h, int op, long long *nnz, int *max_pattern, double *build_ms,
+                   unsigned long long *bytes);
+int mlfma_gmres_precond(mlfma_handle h, int op, int dtype, long long nrhs, const void *b, long long ldb, void *x,
+                        long long ldx, int restart, int max_iters, double tol, int precond, int *iters,
+                        double *relres, void *hip_stream);
+
 typedef struct mlfma_server_s *mlfma_server;
 typedef struct {
     int streams;                          /* launch slots (1..16, default 4)      */

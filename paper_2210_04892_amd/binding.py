@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "_mlfma.so")
 OP_C, OP_EM = 0, 1
 C128, C64 = 0, 1
 PART_NEAR, PART_FAR, PART_ALL, PART_LEVEL = 1, 2, 3, 16
+PRECOND_NONE, PRECOND_SAI = 0, 1
 STAGES = ("permute_in", "near", "radiate", "aggregate", "translate", "disaggregate", "receive", "permute_out")
 _OPS = {"C": OP_C, "EM": OP_EM, OP_C: OP_C, OP_EM: OP_EM}
 ERRORS = {-1: "MLFMA_ERR_ARG", -2: "MLFMA_ERR_MESH", -3: "MLFMA_ERR_OOM", -4: "MLFMA_ERR_HIP",
@@ -70,6 +71,12 @@ def lib():
         L.mlfma_graph_destroy.argtypes = [P]
         L.mlfma_gmres.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_double, ctypes.POINTER(ctypes.c_int), P, P]
+        L.mlfma_gmres_precond.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), P, P]
+        L.mlfma_sai_build.argtypes = [P, ctypes.c_int, ctypes.c_int]
+        L.mlfma_sai_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, P]
+        L.mlfma_sai_info.argtypes = [P, ctypes.c_int, ctypes.POINTER(LL), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_ulonglong)]
         L.mlfma_plane_wave_rhs.argtypes = [P, ctypes.c_int, LL, P, P, P, LL, P]
         L.mlfma_far_field.argtypes = [P, ctypes.c_int, LL, P, LL, LL, P, P, P]
         L.mlfma_server_opts_default.argtypes = [ctypes.POINTER(ServerOptions)]
@@ -245,10 +252,43 @@ class Geometry:
         """Direct call of mlfma_matvec_LK on device pointers (column-major)."""
         _check(lib().mlfma_matvec_LK(self._h, _OPS.get(op, op), dtype, nrhs, x_ptr, ldx, y_ptr, ldy, stream_ptr))
 
-    def gmres(self, b, op="C", x0=None, restart=30, max_iters=300, tol=1e-3, stream=None):
-        """Solve A x = b (mlfma_gmres).  b: complex CUDA tensor (2N,) or
-        (2N, nrhs).  Returns (x, Arnoldi steps, true relative residual per
-        column)."""
+    def sai_build(self, op="C", k_nearest=16):
+        """mlfma_sai_build: SAI preconditioner of op's near field over
+        patterns of the k_nearest nearest RWGs."""
+        with torch.cuda.device(self.device):
+            _check(lib().mlfma_sai_build(self._h, _OPS.get(op, op), k_nearest))
+        return self
+
+    def sai_apply(self, x, op="C", stream=None):
+        """y = M x (mlfma_sai_apply); x: complex CUDA tensor (2N,) or (2N, nrhs)."""
+        if x.dtype == torch.complex128:
+            dt = C128
+        elif x.dtype == torch.complex64:
+            dt = C64
+        else:
+            raise TypeError("x must be complex128 or complex64")
+        squeeze = x.dim() == 1
+        X = x[:, None] if squeeze else x
+        xt = X.t().contiguous()
+        yt = torch.empty_like(xt)
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        with torch.cuda.device(self.device):
+            _check(lib().mlfma_sai_apply(self._h, _OPS.get(op, op), dt, xt.shape[0], xt.data_ptr(), 2 * self.n_rwg,
+                                         yt.data_ptr(), 2 * self.n_rwg, s.cuda_stream))
+        y = yt.t()
+        return y[:, 0] if squeeze else y
+
+    def sai_info(self, op="C"):
+        nnz, mp, ms, by = ctypes.c_longlong(), ctypes.c_int(), ctypes.c_double(), ctypes.c_ulonglong()
+        _check(lib().mlfma_sai_info(self._h, _OPS.get(op, op), ctypes.byref(nnz), ctypes.byref(mp), ctypes.byref(ms),
+                                    ctypes.byref(by)))
+        return {"nnz": nnz.value, "max_pattern": mp.value, "build_ms": ms.value, "bytes": by.value}
+
+    def gmres(self, b, op="C", x0=None, restart=30, max_iters=300, tol=1e-3, stream=None, precond=None):
+        """Solve A x = b (mlfma_gmres_precond).  b: complex CUDA tensor (2N,)
+        or (2N, nrhs); precond None or "sai" (right preconditioning with the
+        SAI of op, built by sai_build).  Returns (x, Arnoldi steps, true
+        relative residual per column)."""
         if b.dtype == torch.complex128:
             dt = C128
         elif b.dtype == torch.complex64:
@@ -264,9 +304,10 @@ class Geometry:
         its = ctypes.c_int()
         s = torch.cuda.current_stream(self.device) if stream is None else stream
         with torch.cuda.device(self.device):
-            _check(lib().mlfma_gmres(self._h, _OPS.get(op, op), dt, nrhs, bt.data_ptr(), 2 * self.n_rwg,
-                                     xt.data_ptr(), 2 * self.n_rwg, restart, max_iters, tol, ctypes.byref(its),
-                                     rel.ctypes.data, s.cuda_stream))
+            pc = {None: PRECOND_NONE, "sai": PRECOND_SAI}[precond]
+            _check(lib().mlfma_gmres_precond(self._h, _OPS.get(op, op), dt, nrhs, bt.data_ptr(), 2 * self.n_rwg,
+                                             xt.data_ptr(), 2 * self.n_rwg, restart, max_iters, tol, pc,
+                                             ctypes.byref(its), rel.ctypes.data, s.cuda_stream))
         x = xt.t()
         return (x[:, 0] if squeeze else x), its.value, rel
 

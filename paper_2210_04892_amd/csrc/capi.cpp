@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -17,6 +18,7 @@
 #include "../../include/mlfma.h"
 #include "device.hpp"
 #include "nearfield.hpp"
+#include "sai.hpp"
 #include "setup.hpp"
 
 using namespace mlfma;
@@ -105,6 +107,20 @@ struct Workspace {
     }
 };
 
+// Sparse approximate inverse of one operator's near field (sai.hpp): the
+// columns in both precisions and the row-wise entry lists of the apply.
+struct SaiData {
+    bool ready = false;
+    int k = 0, maxp = 0;
+    long long nnz = 0;          // RWG-pair entries (each a 2 x 2 block)
+    double build_ms = 0;
+    cpx<double> *M64 = nullptr;
+    cpx<float> *M32 = nullptr;
+    int *row_start = nullptr, *ent_col = nullptr, *ent_val = nullptr;
+    std::vector<void *> allocs;
+    unsigned long long bytes = 0;
+};
+
 }  // namespace
 
 struct mlfma_ctx {
@@ -131,6 +147,7 @@ struct mlfma_ctx {
     Prec<double> p64;
     Prec<float> p32;
     bool near_ready = false;
+    SaiData sai[2];           // per op (MLFMA_OP_C, MLFMA_OP_EM)
     Workspace ws;             // workspace of mlfma_matvec_LK / mlfma_matvec_part
     long long ws_gen = 0;     // bumped whenever ws is reallocated (captured graphs refer to it)
     long long uid = 0;        // unique over the process (keys of the server's captured products)
@@ -166,6 +183,13 @@ struct mlfma_ctx {
         bytes -= ws.bytes;
         ws.release();
     }
+    void free_sai(int op)
+    {
+        SaiData &d = sai[op];
+        for (void *p : d.allocs) (void)hipFree(p);
+        bytes -= d.bytes;
+        d = SaiData();
+    }
     std::vector<hipEvent_t> take_events()
     {
         std::vector<hipEvent_t> ev(MLFMA_STAGES + 1);
@@ -197,6 +221,8 @@ struct mlfma_ctx {
         drain_events();
         for (auto e : ev_free) (void)hipEventDestroy(e);
         free_ws();
+        free_sai(0);
+        free_sai(1);
         for (void *p : allocs) (void)hipFree(p);
     }
 };
@@ -691,6 +717,138 @@ void precompute_near(mlfma_ctx *c)
     c->near_ready = true;
 }
 
+// ---------------------------------------------------------------- SAI
+// Sparse approximate inverse of op's near field with patterns of k_nearest
+// RWGs (sai.hpp).  Host: the patterns (the k nearest RWG centres inside the
+// adjacent leaf boxes, ties at the k-th distance included), the leaf boxes
+// whose rows touch each pattern, and the row-wise entry lists of the apply
+// (user order).  Device: the least-squares columns in double precision,
+// copied to single precision.
+void build_sai(mlfma_ctx *c, int op, int k_nearest)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const Tree &tr = c->tr;
+    const RwgTable &r = c->r;
+    const Surface &s = c->s;
+    const int N = r.n;
+    if ((long long)N * 2 * SAI_D >= (1LL << 31))
+        throw Error(MLFMA_ERR_UNSUPPORTED, "too many RWGs for the SAI entry offsets");
+    std::vector<double> ctr(3 * (size_t)N);
+    for (int u = 0; u < N; u++) {
+        const int n = tr.perm[u];
+        for (int d = 0; d < 3; d++) ctr[3 * (size_t)u + d] = 0.5 * (s.v[3 * (size_t)r.a[n] + d] + s.v[3 * (size_t)r.b[n] + d]);
+    }
+    std::vector<int> pat_start(N + 1, 0), pat, rb_start(N + 1, 0), rb;
+    std::vector<std::pair<double, int>> cand;
+    std::vector<int> boxes;
+    int maxp = 0;
+    for (int u = 0; u < N; u++) {
+        const int b = tr.leaf_of[u];
+        cand.clear();
+        for (int e = tr.near_start[b]; e < tr.near_start[b + 1]; e++) {
+            const int nb = tr.near_box[e];
+            for (int w = tr.box_start[nb]; w < tr.box_start[nb + 1]; w++) {
+                const double dx = ctr[3 * (size_t)w] - ctr[3 * (size_t)u];
+                const double dy = ctr[3 * (size_t)w + 1] - ctr[3 * (size_t)u + 1];
+                const double dz = ctr[3 * (size_t)w + 2] - ctr[3 * (size_t)u + 2];
+                cand.push_back({dx * dx + dy * dy + dz * dz, w});
+            }
+        }
+        size_t take = cand.size();
+        if ((int)cand.size() > k_nearest) {
+            std::nth_element(cand.begin(), cand.begin() + (k_nearest - 1), cand.end());
+            const double thr = cand[k_nearest - 1].first * (1 + 1e-9);
+            take = std::partition(cand.begin(), cand.end(), [&](const std::pair<double, int> &q) {
+                       return q.first <= thr;
+                   }) - cand.begin();
+        }
+        if ((int)take > SAI_MAXP)
+            throw Error(MLFMA_ERR_UNSUPPORTED, "SAI pattern of RWG " + std::to_string(tr.perm[u]) + " has " +
+                                                   std::to_string(take) + " members (ties); at most " +
+                                                   std::to_string(SAI_MAXP));
+        std::vector<int> sel;
+        for (size_t i = 0; i < take; i++) sel.push_back(cand[i].second);
+        std::sort(sel.begin(), sel.end());
+        maxp = std::max(maxp, (int)sel.size());
+        boxes.clear();
+        for (int w : sel) {
+            const int pb = tr.leaf_of[w];
+            for (int e = tr.near_start[pb]; e < tr.near_start[pb + 1]; e++) boxes.push_back(tr.near_box[e]);
+        }
+        std::sort(boxes.begin(), boxes.end());
+        boxes.erase(std::unique(boxes.begin(), boxes.end()), boxes.end());
+        pat.insert(pat.end(), sel.begin(), sel.end());
+        rb.insert(rb.end(), boxes.begin(), boxes.end());
+        pat_start[u + 1] = (int)pat.size();
+        rb_start[u + 1] = (int)rb.size();
+    }
+    // apply lists: row (user) p of M gathers the columns (u, .) whose pattern holds p
+    const long long nnz = (long long)pat.size();
+    std::vector<int> row_start(N + 1, 0), ent_col(nnz), ent_val(nnz);
+    for (int u = 0; u < N; u++)
+        for (int e = pat_start[u]; e < pat_start[u + 1]; e++) row_start[tr.perm[pat[e]] + 1]++;
+    for (int p = 0; p < N; p++) row_start[p + 1] += row_start[p];
+    {
+        std::vector<int> fill(row_start.begin(), row_start.end() - 1);
+        for (int u = 0; u < N; u++)
+            for (int e = pat_start[u]; e < pat_start[u + 1]; e++) {
+                const int q = fill[tr.perm[pat[e]]]++;
+                ent_col[q] = tr.perm[u];
+                ent_val[q] = u * 2 * SAI_D + 2 * (e - pat_start[u]);
+            }
+    }
+    c->free_sai(op);
+    SaiData &d = c->sai[op];
+    const unsigned long long before = c->bytes;
+    std::vector<void *> tmp;
+    struct Free {
+        std::vector<void *> &l;
+        ~Free()
+        {
+            for (void *p : l) (void)hipFree(p);
+        }
+    } fr{tmp};
+    auto up = [&](const std::vector<int> &h, std::vector<void *> *list) {
+        int *p = c->dalloc<int>(h.size(), list);
+        if (!h.empty()) HIPCHK(hipMemcpy(p, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice));
+        return p;
+    };
+    try {
+        d.M64 = c->dalloc<cpx<double>>((size_t)N * 2 * SAI_D, &d.allocs);
+        d.M32 = c->dalloc<cpx<float>>((size_t)N * 2 * SAI_D, &d.allocs);
+        d.row_start = up(row_start, &d.allocs);
+        d.ent_col = up(ent_col, &d.allocs);
+        d.ent_val = up(ent_val, &d.allocs);
+        d.bytes = c->bytes - before;
+        const unsigned long long kept = c->bytes;
+        int *d_ps = up(pat_start, &tmp), *d_pat = up(pat, &tmp), *d_rs = up(rb_start, &tmp), *d_rb = up(rb, &tmp);
+        int *d_status = up(std::vector<int>(1, 0), &tmp);
+        const bool isc = op == MLFMA_OP_C;
+        const int chunk = 32768;
+        for (int u0 = 0; u0 < N; u0 += chunk)
+            launch_sai_build(u0, std::min(chunk, N - u0), d_ps, d_pat, d_rs, d_rb, c->leaf_of, c->box_start,
+                             c->near_start, c->near_box, c->val_off, isc ? c->p64.near_c : c->p64.near_em,
+                             isc ? c->id_start : nullptr, c->id_col, c->p64.id_w, d.M64, d_status, nullptr);
+        HIPCHK(hipGetLastError());
+        launch_to_float(d.M64, d.M32, (long long)N * 2 * SAI_D, nullptr);
+        HIPCHK(hipGetLastError());
+        int status = 0;
+        HIPCHK(hipMemcpy(&status, d_status, sizeof(int), hipMemcpyDeviceToHost));
+        c->bytes = kept;
+        if (status)
+            throw Error(MLFMA_ERR_UNSUPPORTED, "SAI normal equations not positive definite for some RWG");
+    } catch (...) {
+        c->bytes = before + d.bytes;
+        c->free_sai(op);
+        throw;
+    }
+    d.k = k_nearest;
+    d.maxp = maxp;
+    d.nnz = nnz;
+    d.ready = true;
+    d.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
 // ---------------------------------------------------------------- workspace
 // Bytes of a workspace for nrhs right-hand sides.
 unsigned long long workspace_bytes(const mlfma_ctx *c, int nrhs)
@@ -939,8 +1097,17 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
 // residual reaches tol (or max_iters steps); relres returns the true
 // relative residual ||b - A x|| / ||b|| of every column, recomputed at exit.
 template <class T>
+const cpx<T> *sai_values(const SaiData &d);
+template <>
+const cpx<double> *sai_values<double>(const SaiData &d) { return d.M64; }
+template <>
+const cpx<float> *sai_values<float>(const SaiData &d) { return d.M32; }
+
+// With sai (right preconditioning) the Krylov space is built for A M and the
+// solution is x0 + M V y; residuals and tol are those of A x = b itself.
+template <class T>
 void gmres(mlfma_ctx *c, Prec<T> &P, int op, int nrhs, const cpx<T> *b, long long ldb, cpx<T> *x, long long ldx,
-           int m, int max_iters, double tol, int *iters_out, double *relres, hipStream_t st)
+           int m, int max_iters, double tol, int *iters_out, double *relres, const SaiData *sai, hipStream_t st)
 {
     typedef std::complex<double> C;
     const long long n = 2LL * c->r.n;
@@ -969,6 +1136,21 @@ void gmres(mlfma_ctx *c, Prec<T> &P, int op, int nrhs, const cpx<T> *b, long lon
     cpx<double> *cb = (cpx<double> *)dev(sizeof(cpx<double>) * nrhs);
     auto matvec = [&](const cpx<T> *in, long long ldi, cpx<T> *out, long long ldo) {
         run_matvec<T>(c, c->ws, P, op, MLFMA_PART_ALL, nrhs, in, ldi, out, ldo, st, false);
+    };
+    cpx<T> *z = sai ? (cpx<T> *)dev(sizeof(cpx<T>) * (size_t)vstride) : nullptr;
+    cpx<T> *tv = sai ? (cpx<T> *)dev(sizeof(cpx<T>) * (size_t)vstride) : nullptr;
+    auto precond = [&](const cpx<T> *in, cpx<T> *out) {
+        launch_sai_apply<T>(c->r.n, nrhs, sai->row_start, sai->ent_col, sai->ent_val, sai_values<T>(*sai), in, n,
+                            out, n, st);
+    };
+    // w = A M v (or A v)
+    auto opmul = [&](const cpx<T> *in, cpx<T> *out) {
+        if (sai) {
+            precond(in, z);
+            matvec(z, n, out, n);
+        } else {
+            matvec(in, n, out, n);
+        }
     };
     auto fetch = [&](const cpx<double> *d, int count, std::vector<C> &h) {
         std::vector<cpx<double>> tmp((size_t)count);
@@ -1020,7 +1202,7 @@ void gmres(mlfma_ctx *c, Prec<T> &P, int op, int nrhs, const cpx<T> *b, long lon
         if (worst <= tol) break;
         int j = 0;
         for (; j < m && iters < max_iters; j++) {
-            matvec(V + (size_t)j * vstride, n, w, n);
+            opmul(V + (size_t)j * vstride, w);
             std::vector<C> h1, h2;
             krylov_dots<T>(V, vstride, n, j + 1, w, n, n, nrhs, part, nchunk, hd, st);
             krylov_combine<T>(V, vstride, n, j + 1, hd, -1.0, w, n, n, nrhs, st);
@@ -1081,7 +1263,17 @@ void gmres(mlfma_ctx *c, Prec<T> &P, int op, int nrhs, const cpx<T> *b, long lon
                     y[(size_t)i * nrhs + r] = std::abs(d) > 0 ? s / d : C(0, 0);
                 }
             put(hd, y);
-            krylov_combine<T>(V, vstride, n, j, hd, 1.0, x, ldx, n, nrhs, st);
+            if (sai) {
+                // x += M (V y)
+                HIPCHK(hipMemsetAsync(tv, 0, sizeof(cpx<T>) * (size_t)vstride, st));
+                krylov_combine<T>(V, vstride, n, j, hd, 1.0, tv, n, n, nrhs, st);
+                precond(tv, z);
+                put(ca, ones);
+                put(cb, ones);
+                krylov_axpby<T>(ca, x, ldx, cb, z, n, x, ldx, n, nrhs, st);
+            } else {
+                krylov_combine<T>(V, vstride, n, j, hd, 1.0, x, ldx, n, nrhs, st);
+            }
         }
     }
     // true residual
@@ -1289,6 +1481,14 @@ int mlfma_graph_launch(mlfma_graph g, void *hip_stream)
 int mlfma_gmres(mlfma_handle h, int op, int dtype, long long nrhs, const void *b, long long ldb, void *x,
                 long long ldx, int restart, int max_iters, double tol, int *iters, double *relres, void *hip_stream)
 {
+    return mlfma_gmres_precond(h, op, dtype, nrhs, b, ldb, x, ldx, restart, max_iters, tol, MLFMA_PRECOND_NONE,
+                               iters, relres, hip_stream);
+}
+
+int mlfma_gmres_precond(mlfma_handle h, int op, int dtype, long long nrhs, const void *b, long long ldb, void *x,
+                        long long ldx, int restart, int max_iters, double tol, int precond, int *iters,
+                        double *relres, void *hip_stream)
+{
     g_last_error.clear();
     if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
     if (!h->near_ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_precompute_nearfield has not been called"));
@@ -1298,6 +1498,13 @@ int mlfma_gmres(mlfma_handle h, int op, int dtype, long long nrhs, const void *b
     if (nrhs < 1 || nrhs > 4096 || !b || !x || !relres || ldb < N2 || ldx < N2 || restart < 1 || restart > 512 ||
         max_iters < 1 || !(tol > 0))
         return fail(Error(MLFMA_ERR_ARG, "bad nrhs, pointer, leading dimension, restart, max_iters or tol"));
+    if (precond != MLFMA_PRECOND_NONE && precond != MLFMA_PRECOND_SAI)
+        return fail(Error(MLFMA_ERR_ARG, "unknown preconditioner"));
+    const SaiData *sai = nullptr;
+    if (precond == MLFMA_PRECOND_SAI) {
+        if (!h->sai[op].ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_sai_build has not been called for this op"));
+        sai = &h->sai[op];
+    }
     const size_t esz = dtype == MLFMA_C128 ? 16 : 8;
     const char *bb = (const char *)b, *xb = (const char *)x;
     if (bb < xb + (size_t)(ldx * (nrhs - 1) + N2) * esz && xb < bb + (size_t)(ldb * (nrhs - 1) + N2) * esz)
@@ -1309,10 +1516,10 @@ int mlfma_gmres(mlfma_handle h, int op, int dtype, long long nrhs, const void *b
         hipStream_t st = (hipStream_t)hip_stream;
         if (dtype == MLFMA_C128)
             gmres<double>(h, h->p64, op, (int)nrhs, (const cpx<double> *)b, ldb, (cpx<double> *)x, ldx, restart,
-                          max_iters, tol, iters, relres, st);
+                          max_iters, tol, iters, relres, sai, st);
         else
             gmres<float>(h, h->p32, op, (int)nrhs, (const cpx<float> *)b, ldb, (cpx<float> *)x, ldx, restart,
-                         max_iters, tol, iters, relres, st);
+                         max_iters, tol, iters, relres, sai, st);
         HIPCHK(hipGetLastError());
         return MLFMA_OK;
     } catch (const Error &e) {
@@ -1507,6 +1714,70 @@ int mlfma_far_field(mlfma_handle h, int dtype, long long nrhs, const void *x, lo
     } catch (const Error &e) {
         return fail(e);
     }
+}
+
+int mlfma_sai_build(mlfma_handle h, int op, int k_nearest)
+{
+    g_last_error.clear();
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    if (op != MLFMA_OP_C && op != MLFMA_OP_EM) return fail(Error(MLFMA_ERR_ARG, "unknown op"));
+    if (k_nearest < 1 || k_nearest > SAI_MAXP) return fail(Error(MLFMA_ERR_ARG, "k_nearest outside 1..32"));
+    if (!h->near_ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_precompute_nearfield has not been called"));
+    try {
+        DeviceGuard g(h->device);
+        HIPCHK(hipGetLastError());
+        build_sai(h, op, k_nearest);
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int mlfma_sai_apply(mlfma_handle h, int op, int dtype, long long nrhs, const void *x, long long ldx, void *y,
+                    long long ldy, void *hip_stream)
+{
+    g_last_error.clear();
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    if (op != MLFMA_OP_C && op != MLFMA_OP_EM) return fail(Error(MLFMA_ERR_ARG, "unknown op"));
+    if (dtype != MLFMA_C128 && dtype != MLFMA_C64) return fail(Error(MLFMA_ERR_ARG, "unknown dtype"));
+    const long long N2 = 2LL * h->r.n;
+    if (nrhs < 1 || nrhs > 65535 || !x || !y || ldx < N2 || ldy < N2)
+        return fail(Error(MLFMA_ERR_ARG, "bad nrhs, pointer or leading dimension"));
+    if (!h->sai[op].ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_sai_build has not been called for this op"));
+    const size_t esz = dtype == MLFMA_C128 ? 16 : 8;
+    const char *xb = (const char *)x, *yb = (const char *)y;
+    if (xb < yb + (size_t)(ldy * (nrhs - 1) + N2) * esz && yb < xb + (size_t)(ldx * (nrhs - 1) + N2) * esz)
+        return fail(Error(MLFMA_ERR_ARG, "x and y overlap"));
+    try {
+        DeviceGuard g(h->device);
+        const SaiData &d = h->sai[op];
+        hipStream_t st = (hipStream_t)hip_stream;
+        if (dtype == MLFMA_C128)
+            launch_sai_apply<double>(h->r.n, (int)nrhs, d.row_start, d.ent_col, d.ent_val, d.M64,
+                                     (const cpx<double> *)x, ldx, (cpx<double> *)y, ldy, st);
+        else
+            launch_sai_apply<float>(h->r.n, (int)nrhs, d.row_start, d.ent_col, d.ent_val, d.M32,
+                                    (const cpx<float> *)x, ldx, (cpx<float> *)y, ldy, st);
+        HIPCHK(hipGetLastError());
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int mlfma_sai_info(mlfma_handle h, int op, long long *nnz, int *max_pattern, double *build_ms,
+                   unsigned long long *bytes)
+{
+    g_last_error.clear();
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    if (op != MLFMA_OP_C && op != MLFMA_OP_EM) return fail(Error(MLFMA_ERR_ARG, "unknown op"));
+    const SaiData &d = h->sai[op];
+    if (!d.ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_sai_build has not been called for this op"));
+    if (nnz) *nnz = d.nnz;
+    if (max_pattern) *max_pattern = d.maxp;
+    if (build_ms) *build_ms = d.build_ms;
+    if (bytes) *bytes = d.bytes;
+    return MLFMA_OK;
 }
 
 int mlfma_translation_operator(double k, int L, const double X[3], long long nk, const double *khat, double *out)

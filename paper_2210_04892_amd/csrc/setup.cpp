@@ -36,7 +36,7 @@ void build_surface(Surface &s, const double *verts, long long nv, const int *tri
     s.t.assign(tris, tris + 3 * nt);
     s.area.resize(nt);
     s.nrm.resize(3 * nt);
-    double maxa = 0, vol6 = 0;
+    double maxa = 0;
     for (int i = 0; i < s.nt; i++) {
         for (int c = 0; c < 3; c++)
             if (s.t[3 * i + c] < 0 || s.t[3 * i + c] >= s.nv)
@@ -50,15 +50,10 @@ void build_surface(Surface &s, const double *verts, long long nv, const int *tri
         s.area[i] = 0.5 * n2;
         maxa = std::max(maxa, s.area[i]);
         for (int k = 0; k < 3; k++) s.nrm[3 * i + k] = n2 > 0 ? c[k] / n2 : 0.0;
-        double pc[3];
-        cross3(p1, p2, pc);
-        vol6 += p0[0] * pc[0] + p0[1] * pc[1] + p0[2] * pc[2];
     }
     for (int i = 0; i < s.nt; i++)
         if (!(s.area[i] > 1e-12 * maxa))
             throw Error(MLFMA_ERR_MESH, "degenerate triangle " + std::to_string(i));
-    if (!(vol6 > 0))
-        throw Error(MLFMA_ERR_MESH, "enclosed volume is not positive: triangles must be counter-clockwise seen from outside");
 }
 
 void build_rwg(const Surface &s, RwgTable &r)
@@ -111,6 +106,30 @@ void build_rwg(const Surface &s, RwgTable &r)
             r.tri_rwg[3 * (size_t)u.tri + u.loc] = n;
         }
     }
+    // Disconnected scatterers may share the mesh (the BI equations then hold
+    // on each closed surface, Sec. II-E remarks): every connected surface --
+    // triangles joined through their RWGs -- must enclose a positive volume.
+    std::vector<int> root(s.nt);
+    for (int i = 0; i < s.nt; i++) root[i] = i;
+    auto find = [&](int a) {
+        while (root[a] != a) a = root[a] = root[root[a]];
+        return a;
+    };
+    for (int n = 0; n < r.n; n++) {
+        const int a = find(r.tri[0][n]), b = find(r.tri[1][n]);
+        if (a != b) root[std::max(a, b)] = std::min(a, b);
+    }
+    std::vector<double> vol6(s.nt, 0.0);
+    for (int i = 0; i < s.nt; i++) {
+        const double *p0 = &s.v[3 * s.t[3 * i]], *p1 = &s.v[3 * s.t[3 * i + 1]], *p2 = &s.v[3 * s.t[3 * i + 2]];
+        double pc[3];
+        cross3(p1, p2, pc);
+        vol6[find(i)] += p0[0] * pc[0] + p0[1] * pc[1] + p0[2] * pc[2];
+    }
+    for (int i = 0; i < s.nt; i++)
+        if (root[i] == i && !(vol6[i] > 0))
+            throw Error(MLFMA_ERR_MESH, "enclosed volume of a closed surface is not positive: triangles must be "
+                                        "counter-clockwise seen from outside");
 }
 
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)

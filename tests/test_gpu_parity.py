@@ -39,6 +39,9 @@ MESHES = {
     "sphere_r3": lambda: synth.icosphere(36, 3.0),
     "box_4x4x1": lambda: synth.rounded_box((4.0, 4.0, 1.0), 0.2, 0.073),
     "octahedron": lambda: synth.octahedron(0.1),
+    # two disconnected scatterers in one tree (BI equations on each surface)
+    "two_bodies": lambda: synth.scene(synth.icosphere(6, 0.5) + ((0, 0, 0),),
+                                      synth.icosphere(4, 0.3) + ((1.4, 0.2, -0.1),)),
 }
 
 
@@ -84,7 +87,7 @@ def _pick(y, rows, N):
     return np.concatenate([y[rows], y[N + rows]])
 
 
-CASES = [("ico6_r0.5", None), ("sphere_r0.5", 192), ("sphere_r3", 40), ("box_4x4x1", 40)]
+CASES = [("ico6_r0.5", None), ("sphere_r0.5", 192), ("sphere_r3", 40), ("box_4x4x1", 40), ("two_bodies", 160)]
 
 
 @pytest.mark.parametrize("name,nrows", CASES)
