@@ -202,17 +202,24 @@ __global__ __launch_bounds__(256) void k_near_tile(int nitem, const int2 *__rest
     cpx<T> a1[8], a2[8];
 #pragma unroll
     for (int i = 0; i < 8; i++) a1[i] = a2[i] = mk<T>(0, 0);
+    // rows past the tile's last re-read that row (branch-free, so that all
+    // loads of an iteration are in flight together); their sums are dropped
     for (int j = lane; j < ncols; j += WAVE) {
         const long long col = cl[j];
+        cpx<T> A[8], B[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const long long o = 2 * ((long long)(i < nr ? i : nr - 1) * ncols + j);
+            A[i] = vr[o];
+            B[i] = vr[o + 1];
+        }
         const cpx<T> x1 = X[col * 2], x2 = X[col * 2 + 1];
 #pragma unroll
         for (int i = 0; i < 8; i++) {
-            if (i >= nr) break;
-            const cpx<T> A = vr[2 * ((long long)i * ncols + j)], B = vr[2 * ((long long)i * ncols + j) + 1];
-            fma_to(a1[i], A, x1);
-            fms_to(a1[i], B, x2);
-            fma_to(a2[i], A, x2);
-            fma_to(a2[i], B, x1);
+            fma_to(a1[i], A[i], x1);
+            fms_to(a1[i], B[i], x2);
+            fma_to(a2[i], A[i], x2);
+            fma_to(a2[i], B[i], x1);
         }
     }
     cpx<T> y1 = mk<T>(0, 0), y2 = mk<T>(0, 0);

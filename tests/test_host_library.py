@@ -89,3 +89,8 @@ def test_build_rejects_bad_meshes_before_any_device_use():
     assert _build_rc(bad, t) == -2
     vv, tt = synth.icosphere(4, 0.5)                # edges of 0.15 wavelength
     assert _build_rc(vv, tt) == -6                  # touching RWGs beyond adjacent 0.25 leaves
+    # two closed surfaces, the small one inward: the total enclosed volume is
+    # positive, but every surface must be outward on its own
+    a, c = synth.icosphere(6, 0.5), synth.icosphere(6, 0.2)
+    v2, t2 = synth.scene(a + ((0, 0, 0),), (c[0], c[1][:, ::-1], (1.5, 0, 0)))
+    assert _build_rc(v2, t2) == -2
