@@ -98,6 +98,11 @@ struct Workspace {
     std::vector<void *> allocs;
     void *X = nullptr, *Y = nullptr, *mid = nullptr;
     std::vector<void *> U, V;
+    // optional second stream (not owned): the near field then runs beside
+    // the far-field chain, forked after the permutation and joined before the
+    // receive step
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     void release()
     {
         for (void *p : allocs) (void)hipFree(p);
@@ -148,6 +153,8 @@ struct mlfma_ctx {
     Prec<float> p32;
     bool near_ready = false;
     SaiData sai[2];           // per op (MLFMA_OP_C, MLFMA_OP_EM)
+    hipStream_t side = nullptr;                    // near-field stream of ws
+    hipEvent_t fork = nullptr, join = nullptr;
     Workspace ws;             // workspace of mlfma_matvec_LK / mlfma_matvec_part
     long long ws_gen = 0;     // bumped whenever ws is reallocated (captured graphs refer to it)
     long long uid = 0;        // unique over the process (keys of the server's captured products)
@@ -223,6 +230,9 @@ struct mlfma_ctx {
         free_ws();
         free_sai(0);
         free_sai(1);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (side) (void)hipStreamDestroy(side);
         for (void *p : allocs) (void)hipFree(p);
     }
 };
@@ -941,6 +951,14 @@ void ensure_workspace(mlfma_ctx *c, int nrhs)
     alloc_workspace(c, c->ws, nrhs);
     c->bytes += c->ws.bytes;
     c->ws_gen++;
+    if (!c->side) {
+        HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
+    }
+    c->ws.side = c->side;
+    c->ws.fork = c->fork;
+    c->ws.join = c->join;
 }
 
 // arguments of the fused step between parent level l and child level l + 1
@@ -1004,26 +1022,35 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     const int only_level = part >= MLFMA_PART_LEVEL ? part - MLFMA_PART_LEVEL : -1;
     const bool want_near = only_level < 0 && (part & MLFMA_PART_NEAR);
     const bool want_far = only_level >= 0 || (part & MLFMA_PART_FAR);
+    const bool far = tr.levels >= 3 && want_far;
+    // the near field beside the far-field chain (stage timing keeps them in sequence)
+    const bool overlap = !profile && want_near && far && w.side;
+    hipStream_t sn = st;
+    if (overlap) {
+        HIPCHK(hipEventRecord(w.fork, st));
+        HIPCHK(hipStreamWaitEvent(w.side, w.fork, 0));
+        sn = w.side;
+    }
     if (want_near) {
         const cpx<T> *vals = op == MLFMA_OP_EM ? P.near_em : P.near_c;
         const int *ids = op == MLFMA_OP_C ? c->id_start : nullptr;
         bool done = false;
         if constexpr (std::is_same<T, float>::value)
             done = launch_near_mfma(c->n_items, c->items, c->box_start, c->col_off, c->cols, c->val_off, vals, ids,
-                                    c->id_col, P.id_w, X, Y, nrhs, st);
+                                    c->id_col, P.id_w, X, Y, nrhs, sn);
         if (!done && nrhs == 1) {
             launch_near_tile<T>(c->n_items, c->items, c->box_start, c->col_off, c->cols, c->val_off, vals, ids,
-                                c->id_col, P.id_w, X, Y, st);
+                                c->id_col, P.id_w, X, Y, sn);
             done = true;
         }
         if (!done)
             launch_near<T>(N, c->leaf_of, c->box_start, c->near_start, c->near_box, c->val_off, vals, ids, c->id_col,
-                           P.id_w, X, Y, nrhs, st);
+                           P.id_w, X, Y, nrhs, sn);
     } else {
         launch_zero<T>(Y, (long long)N * 2 * nrhs, st);
     }
+    if (overlap) HIPCHK(hipEventRecord(w.join, w.side));
     mark(2);
-    const bool far = tr.levels >= 3 && want_far;
     if (far) {
         bool done = false;
         if constexpr (std::is_same<T, float>::value)
@@ -1076,6 +1103,7 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
         }
     }
     mark(6);
+    if (overlap) HIPCHK(hipStreamWaitEvent(st, w.join, 0));
     if (far) {
         bool done = false;
         if constexpr (std::is_same<T, float>::value)
@@ -1089,13 +1117,6 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     if (profile) c->ev_pending.push_back(ev);
 }
 
-// Restarted GMRES(m) on y = A x (op, precision T), one Krylov space per
-// right-hand-side column; every Arnoldi step is one batched product of all
-// columns.  Classical Gram-Schmidt applied twice on the device (inner
-// products in double), complex Givens rotations and the triangular solve on
-// the host.  All columns iterate until the largest estimated relative
-// residual reaches tol (or max_iters steps); relres returns the true
-// relative residual ||b - A x|| / ||b|| of every column, recomputed at exit.
 template <class T>
 const cpx<T> *sai_values(const SaiData &d);
 template <>
@@ -1103,6 +1124,13 @@ const cpx<double> *sai_values<double>(const SaiData &d) { return d.M64; }
 template <>
 const cpx<float> *sai_values<float>(const SaiData &d) { return d.M32; }
 
+// Restarted GMRES(m) on y = A x (op, precision T), one Krylov space per
+// right-hand-side column; every Arnoldi step is one batched product of all
+// columns.  Classical Gram-Schmidt applied twice on the device (inner
+// products in double), complex Givens rotations and the triangular solve on
+// the host.  All columns iterate until the largest estimated relative
+// residual reaches tol (or max_iters steps); relres returns the true
+// relative residual ||b - A x|| / ||b|| of every column, recomputed at exit.
 // With sai (right preconditioning) the Krylov space is built for A M and the
 // solution is x0 + M V y; residuals and tol are those of A x = b itself.
 template <class T>
