@@ -1023,15 +1023,12 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     const bool want_near = only_level < 0 && (part & MLFMA_PART_NEAR);
     const bool want_far = only_level >= 0 || (part & MLFMA_PART_FAR);
     const bool far = tr.levels >= 3 && want_far;
-    // the near field beside the far-field chain (stage timing keeps them in sequence)
+    // the near field beside the far-field chain (stage timing keeps them in
+    // sequence): forked after the radiation, whose memory traffic it would
+    // otherwise compete with, so that it shares the GPU with the
+    // latency-bound level steps and translation
     const bool overlap = !profile && want_near && far && w.side;
-    hipStream_t sn = st;
-    if (overlap) {
-        HIPCHK(hipEventRecord(w.fork, st));
-        HIPCHK(hipStreamWaitEvent(w.side, w.fork, 0));
-        sn = w.side;
-    }
-    if (want_near) {
+    auto near = [&](hipStream_t sn) {
         const cpx<T> *vals = op == MLFMA_OP_EM ? P.near_em : P.near_c;
         const int *ids = op == MLFMA_OP_C ? c->id_start : nullptr;
         bool done = false;
@@ -1046,16 +1043,21 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
         if (!done)
             launch_near<T>(N, c->leaf_of, c->box_start, c->near_start, c->near_box, c->val_off, vals, ids, c->id_col,
                            P.id_w, X, Y, nrhs, sn);
-    } else {
-        launch_zero<T>(Y, (long long)N * 2 * nrhs, st);
-    }
-    if (overlap) HIPCHK(hipEventRecord(w.join, w.side));
+    };
+    if (!want_near) launch_zero<T>(Y, (long long)N * 2 * nrhs, st);
+    else if (!overlap) near(st);
     mark(2);
     if (far) {
         bool done = false;
         if constexpr (std::is_same<T, float>::value)
             done = launch_radiate_mfma(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)w.U[leafl], nrhs, st);
         if (!done) launch_radiate<T>(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)w.U[leafl], nrhs, st);
+    }
+    if (overlap) {
+        HIPCHK(hipEventRecord(w.fork, st));
+        HIPCHK(hipStreamWaitEvent(w.side, w.fork, 0));
+        near(w.side);
+        HIPCHK(hipEventRecord(w.join, w.side));
     }
     mark(3);
     if (far) {
