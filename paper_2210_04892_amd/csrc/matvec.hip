@@ -353,6 +353,57 @@ __global__ __launch_bounds__(256) void k_near_rhs(int N, const int *__restrict__
 // U_b(k) = sum_{n in b} alpha_n R_n(k) + beta_n (khat x R_n)(k),
 // khat x (v_theta, v_phi) = (-v_phi, v_theta).
 // EM pair: alpha = x1, beta = -x2.  C block: alpha = x2 / 2, beta = x1 / 2.
+// Radiation for one right-hand side: one wave per (leaf box, chunk of 64
+// samples), so that every lane of a wave belongs to the same box and the
+// box's coefficients are wave-uniform (scalar loads); the patterns of eight
+// RWGs (four in double precision) are loaded before they are used.
+template <class T>
+__global__ __launch_bounds__(256) void k_radiate1(int op, int nbox, int K, int nqc, const int *__restrict__ box_start,
+                                                  const cpx<T> *__restrict__ R, const cpx<T> *__restrict__ X,
+                                                  cpx<T> *__restrict__ U)
+{
+    constexpr int G = sizeof(T) == 4 ? 8 : 4;
+    const int lane = threadIdx.x % WAVE;
+    const long long blk = xcd_block(((long long)nbox * nqc + 3) / 4);
+    if (blk < 0) return;
+    const long long w = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    if (w >= (long long)nbox * nqc) return;
+    const int b = (int)(w / nqc), q = (int)(w % nqc) * WAVE + lane;
+    const bool qok = q < K;
+    const int qq = qok ? q : K - 1;
+    const int n0 = box_start[b], n1 = box_start[b + 1];
+    cpx<T> ut = mk<T>(0, 0), up = ut;
+    for (int i0 = n0; i0 < n1; i0 += G) {
+        cpx<T> Rt[G], Rp[G], al[G], be[G];
+#pragma unroll
+        for (int u = 0; u < G; u++) {
+            const int i = min(i0 + u, n1 - 1);
+            Rt[u] = R[((long long)i * K + qq) * 2];
+            Rp[u] = R[((long long)i * K + qq) * 2 + 1];
+            const cpx<T> x1 = X[(long long)i * 2], x2 = X[(long long)i * 2 + 1];
+            const T z = i0 + u < n1 ? T(1) : T(0);   // RWGs past the box contribute nothing
+            if (op == 1) {
+                al[u] = z * x1;
+                be[u] = mk<T>(-z * x2.re, -z * x2.im);
+            } else {
+                al[u] = (T(0.5) * z) * x2;
+                be[u] = (T(0.5) * z) * x1;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < G; u++) {
+            fma_to(ut, al[u], Rt[u]);
+            fms_to(ut, be[u], Rp[u]);
+            fma_to(up, al[u], Rp[u]);
+            fma_to(up, be[u], Rt[u]);
+        }
+    }
+    if (qok) {
+        U[pidx(b, 0, 0, q, 1, K)] = ut;
+        U[pidx(b, 1, 0, q, 1, K)] = up;
+    }
+}
+
 template <class T, int NR>
 __global__ __launch_bounds__(256) void k_radiate(int op, int nbox, int K, const int *__restrict__ box_start,
                                                  const cpx<T> *__restrict__ R, const cpx<T> *__restrict__ X,
@@ -887,6 +938,14 @@ template <class T>
 void launch_radiate(int op, int nbox, int K, const int *box_start, const cpx<T> *R, const cpx<T> *X, cpx<T> *U,
                     int nrhs, hipStream_t s)
 {
+    if (nrhs == 1) {
+        const int nqc = (K + WAVE - 1) / WAVE;
+        const long long nw = (long long)nbox * nqc;
+        if (nw > 0)
+            hipLaunchKernelGGL(k_radiate1<T>, dim3(xcd_grid((nw + 3) / 4)), dim3(256), 0, s, op, nbox, K, nqc,
+                               box_start, R, X, U);
+        return;
+    }
     DISPATCH_NR(nrhs, {
         dim3 grid(blocks_for((long long)nbox * K, 256), (nrhs + NR - 1) / NR);
         hipLaunchKernelGGL((k_radiate<T, NR>), grid, dim3(256), 0, s, op, nbox, K, box_start, R, X, U, nrhs);
