@@ -204,23 +204,35 @@ __global__ __launch_bounds__(256) void k_near_tile(int nitem, const int2 *__rest
     for (int i = 0; i < 8; i++) a1[i] = a2[i] = mk<T>(0, 0);
     // rows past the tile's last re-read that row (branch-free, so that all
     // loads of an iteration are in flight together); their sums are dropped
-    for (int j = lane; j < ncols; j += WAVE) {
-        const long long col = cl[j];
-        cpx<T> A[8], B[8];
+    // one column chunk per pass (more chunks lower the occupancy more than
+    // they add loads in flight); columns past the row end re-read its last
+    // column with weight zero
+    constexpr int CH = 1;
+    for (int j0 = lane; j0 < ncols; j0 += CH * WAVE) {
+        cpx<T> A[CH][8], B[CH][8], x1[CH], x2[CH];
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const long long o = 2 * ((long long)(i < nr ? i : nr - 1) * ncols + j);
-            A[i] = vr[o];
-            B[i] = vr[o + 1];
-        }
-        const cpx<T> x1 = X[col * 2], x2 = X[col * 2 + 1];
+        for (int c = 0; c < CH; c++) {
+            const int j = min(j0 + c * WAVE, ncols - 1);
+            const long long col = cl[j];
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            fma_to(a1[i], A[i], x1);
-            fms_to(a1[i], B[i], x2);
-            fma_to(a2[i], A[i], x2);
-            fma_to(a2[i], B[i], x1);
+            for (int i = 0; i < 8; i++) {
+                const long long o = 2 * ((long long)(i < nr ? i : nr - 1) * ncols + j);
+                A[c][i] = vr[o];
+                B[c][i] = vr[o + 1];
+            }
+            const T z = j0 + c * WAVE < ncols ? T(1) : T(0);
+            x1[c] = z * X[col * 2];
+            x2[c] = z * X[col * 2 + 1];
         }
+#pragma unroll
+        for (int c = 0; c < CH; c++)
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                fma_to(a1[i], A[c][i], x1[c]);
+                fms_to(a1[i], B[c][i], x2[c]);
+                fma_to(a2[i], A[c][i], x2[c]);
+                fma_to(a2[i], B[c][i], x1[c]);
+            }
     }
     cpx<T> y1 = mk<T>(0, 0), y2 = mk<T>(0, 0);
 #pragma unroll
@@ -828,6 +840,56 @@ __global__ __launch_bounds__(256) void k_disagg_mid(int nchild, int mid_len, int
 // y1 += c0 sum_k w_k P_m(k) . V_b(k),  y2 += c0 sum_k w_k P_m(k) . (khat x V_b(k))
 // with P = conj(R) for the EM pair and P = Q for the C block; c0 and the
 // sphere weights are folded into wq.  One wave per RWG, lanes over samples.
+// Receive for one right-hand side: wave per RWG row, lanes over samples,
+// the row's pattern and the box's incoming pattern loaded for four chunks of
+// 64 samples (two in double precision) before they are used.
+template <class T>
+__global__ __launch_bounds__(256) void k_receive1(int op, int N, int K, const int *__restrict__ leaf_of,
+                                                  const cpx<T> *__restrict__ R, const cpx<T> *__restrict__ Q,
+                                                  const T *__restrict__ wq, const cpx<T> *__restrict__ V,
+                                                  cpx<T> *__restrict__ Y)
+{
+    constexpr int CH = sizeof(T) == 4 ? 4 : 2;
+    const int m = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (m >= N) return;
+    const int b = leaf_of[m];
+    const cpx<T> *pat = op == 1 ? R : Q;
+    cpx<T> a1 = mk<T>(0, 0), a2 = a1;
+    for (int q0 = lane; q0 < K; q0 += CH * WAVE) {
+        cpx<T> Pt[CH], Pp[CH], Vt[CH], Vp[CH];
+        T wk[CH];
+#pragma unroll
+        for (int c = 0; c < CH; c++) {
+            const int q = min(q0 + c * WAVE, K - 1);
+            Pt[c] = pat[((long long)m * K + q) * 2];
+            Pp[c] = pat[((long long)m * K + q) * 2 + 1];
+            Vt[c] = V[pidx(b, 0, 0, q, 1, K)];
+            Vp[c] = V[pidx(b, 1, 0, q, 1, K)];
+            wk[c] = q0 + c * WAVE < K ? wq[q] : T(0);    // samples past K contribute nothing
+        }
+#pragma unroll
+        for (int c = 0; c < CH; c++) {
+            cpx<T> pt = Pt[c], pp = Pp[c];
+            if (op == 1) {
+                pt = conjg(pt);
+                pp = conjg(pp);
+            }
+            pt = wk[c] * pt;
+            pp = wk[c] * pp;
+            fma_to(a1, pt, Vt[c]);
+            fma_to(a1, pp, Vp[c]);
+            fma_to(a2, pp, Vt[c]);
+            fms_to(a2, pt, Vp[c]);
+        }
+    }
+    const cpx<T> s1 = wave_sum(a1), s2 = wave_sum(a2);
+    if (lane == 0) {
+        Y[(long long)m * 2] = Y[(long long)m * 2] + s1;
+        Y[(long long)m * 2 + 1] = Y[(long long)m * 2 + 1] + s2;
+    }
+}
+
 template <class T, int NR>
 __global__ __launch_bounds__(256) void k_receive(int op, int N, int K, const int *__restrict__ leaf_of,
                                                  const cpx<T> *__restrict__ R, const cpx<T> *__restrict__ Q,
@@ -1071,6 +1133,12 @@ template <class T>
 void launch_receive(int op, int N, int K, const int *leaf_of, const cpx<T> *R, const cpx<T> *Q, const T *wq,
                     const cpx<T> *V, cpx<T> *Y, int nrhs, hipStream_t s)
 {
+    if (nrhs == 1) {
+        if (N > 0)
+            hipLaunchKernelGGL(k_receive1<T>, dim3(blocks_for(N, 4)), dim3(256), 0, s, op, N, K, leaf_of, R, Q, wq, V,
+                               Y);
+        return;
+    }
     DISPATCH_NR(nrhs, {
         dim3 grid(blocks_for(N, 4), (nrhs + NR - 1) / NR);
         hipLaunchKernelGGL((k_receive<T, NR>), grid, dim3(256), 0, s, op, N, K, leaf_of, R, Q, wq, V, Y, nrhs);
