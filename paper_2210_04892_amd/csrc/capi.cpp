@@ -61,6 +61,7 @@ struct PrecLevel {
     cpx<T> *trans = nullptr, *shift = nullptr;
     T *ath_w = nullptr, *aph_w = nullptr, *dph_w = nullptr, *dth_w = nullptr;
     StepPlan agg, dis;      // step from level l + 1 up to l, and from l down to l + 1
+    StepPlan agg1, dis1;    // the same with smaller chunks (more workgroups) for fewer than four RHS
     int tphi = 0, tth = 0;  // separable disaggregation stencils (0 = not separable)
     int *phi_col = nullptr, *th_row = nullptr, *th_sh = nullptr;
     T *phi_w = nullptr, *rowf = nullptr, *th_w = nullptr;
@@ -258,15 +259,24 @@ void plan_level_steps(mlfma_ctx *c, int l, PrecLevel<T> &PL)
 {
     const Tree &tr = c->tr;
     const Level &L = tr.lv[l], &C = tr.lv[l + 1];
+    // chunks of about 512 outputs; for few right-hand sides about 256, which
+    // doubles the workgroups of the small coarse levels
     ChunkPlan cp;
-    plan_theta_chunks(tr.agg_theta[l], L.nth, C.nph, std::max(1, 512 / L.nph),
-                      [&](int wrows, int rows) { return agg_lds_bytes<T>(wrows, rows, C.nph); }, STEP_LDS_MAX, cp);
-    PL.agg = {cp.rows, cp.nchunk, cp.wrows, cp.rows ? c->upload(cp.win) : nullptr};
+    for (int small = 0; small < 2; small++) {
+        const int per = small ? 256 : 512;
+        plan_theta_chunks(tr.agg_theta[l], L.nth, C.nph, std::max(1, per / L.nph),
+                          [&](int wrows, int rows) { return agg_lds_bytes<T>(wrows, rows, C.nph); }, STEP_LDS_MAX,
+                          cp);
+        (small ? PL.agg1 : PL.agg) = {cp.rows, cp.nchunk, cp.wrows, cp.rows ? c->upload(cp.win) : nullptr};
+    }
     SepStencil sep;
     if (!separable_disaggregation(L, C, tr.dis_phi[l], tr.dis_theta[l], sep)) return;
-    plan_theta_chunks(tr.dis_theta[l], C.nth, C.nph, std::max(1, 512 / C.nph),
-                      [&](int wrows, int) { return dis_lds_bytes<T>(wrows, L.nph, C.nph); }, STEP_LDS_MAX, cp);
-    PL.dis = {cp.rows, cp.nchunk, cp.wrows, cp.rows ? c->upload(cp.win) : nullptr};
+    for (int small = 0; small < 2; small++) {
+        const int per = small ? 256 : 512;
+        plan_theta_chunks(tr.dis_theta[l], C.nth, C.nph, std::max(1, per / C.nph),
+                          [&](int wrows, int) { return dis_lds_bytes<T>(wrows, L.nph, C.nph); }, STEP_LDS_MAX, cp);
+        (small ? PL.dis1 : PL.dis) = {cp.rows, cp.nchunk, cp.wrows, cp.rows ? c->upload(cp.win) : nullptr};
+    }
     PL.tphi = sep.tphi;
     PL.tth = sep.tth;
     PL.phi_col = c->upload(sep.phi_col);
@@ -963,13 +973,14 @@ void ensure_workspace(mlfma_ctx *c, int nrhs)
 
 // arguments of the fused step between parent level l and child level l + 1
 template <class T>
-LevelStep<T> step_args(mlfma_ctx *c, Prec<T> &P, int l, bool agg)
+LevelStep<T> step_args(mlfma_ctx *c, Prec<T> &P, int l, bool agg, int nrhs)
 {
     const Tree &tr = c->tr;
     const Level &L = tr.lv[l], &C = tr.lv[l + 1];
     const IntLevel &I = c->lv[l];
     const PrecLevel<T> &PL = P.lv[l];
-    const StepPlan &pl = agg ? PL.agg : PL.dis;
+    const bool small = nrhs < 4;
+    const StepPlan &pl = agg ? (small ? PL.agg1 : PL.agg) : (small ? PL.dis1 : PL.dis);
     LevelStep<T> a;
     a.nbox = agg ? L.nbox : C.nbox;
     a.nth_p = L.nth;
@@ -1066,7 +1077,7 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
             const IntLevel &I = c->lv[l];
             const int midlen = L.nth * C.nph;
             const int taps = c->opt.interp_order;
-            LevelStep<T> a = step_args<T>(c, P, l, true);
+            LevelStep<T> a = step_args<T>(c, P, l, true, nrhs);
             a.in = (const cpx<T> *)w.U[l + 1];
             a.out = (cpx<T> *)w.U[l];
             if (launch_aggregate_step<T>(a, nrhs, st)) continue;
@@ -1094,7 +1105,7 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
             const Level &L = tr.lv[l], &Pl = tr.lv[l - 1];
             const IntLevel &Ip = c->lv[l - 1];
             const int midlen = Pl.nth * L.nph;
-            LevelStep<T> a = step_args<T>(c, P, l - 1, false);
+            LevelStep<T> a = step_args<T>(c, P, l - 1, false, nrhs);
             a.in = (const cpx<T> *)w.V[l - 1];
             a.out = (cpx<T> *)w.V[l];
             if (launch_disaggregate_step<T>(a, nrhs, st)) continue;
