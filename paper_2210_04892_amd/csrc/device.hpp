@@ -119,7 +119,7 @@ inline int trans_rw(int nrhs) { return nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1); }
 template <class T>
 struct TransLevel {
     int K = 0, ntile = 0;
-    int nqc = 0, first = 0;     // sample chunks and first workgroup (set by the launcher)
+    int nqc = 0, first = 0;     // sample chunks; first position in each XCD's workgroup sequence (launcher)
     const int *tile_tgt = nullptr, *tile_bat = nullptr, *bat_src = nullptr, *src = nullptr;
     const int *bat_row = nullptr, *row = nullptr, *ent = nullptr;
     const cpx<T> *trans = nullptr, *U = nullptr;
@@ -127,7 +127,7 @@ struct TransLevel {
 };
 template <class T>
 struct TransArgs {
-    int nlev = 0, nblocks = 0, smax = 0, tmax = 0, rb = 1;
+    int nlev = 0, nblocks = 0, smax = 0, tmax = 0, rb = 1;   // nblocks: workgroups per XCD
     TransLevel<T> lv[TRANS_MAXLEV];
 };
 // false when the tile shape is invalid

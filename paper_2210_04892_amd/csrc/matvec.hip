@@ -687,12 +687,17 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
     constexpr int SRC = 2 * RB * WAVE;                                  // LDS elements per staged source
     extern __shared__ double trans_lds_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(trans_lds_raw);
-    const long long blk = xcd_block(a.nblocks);
-    if (blk < 0) return;
+    // every XCD takes an eighth of every level, coarse levels first (their
+    // few, long workgroups then overlap the many short ones of the leaf
+    // level), each eighth a contiguous range of tiles for the XCD's L2
+    const int xcd = blockIdx.x % NXCD, pos = blockIdx.x / NXCD;
+    if (pos >= a.nblocks) return;
     int l = 0;
-    while (l + 1 < a.nlev && blk >= a.lv[l + 1].first) l++;
+    while (l + 1 < a.nlev && pos >= a.lv[l + 1].first) l++;
     const TransLevel<T> &L = a.lv[l];
-    const int lb = (int)(blk - L.first);
+    const int nblk = L.ntile * L.nqc, per = (nblk + NXCD - 1) / NXCD;
+    const int lb = xcd * per + (pos - L.first);
+    if (lb >= nblk) return;
     const int tile = lb % L.ntile, qc = lb / L.ntile;
     const int K = L.K;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -709,12 +714,16 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
     cpx<T> a0[RB], a1[RB];
 #pragma unroll
     for (int j = 0; j < RB; j++) a0[j] = a1[j] = mk<T>(0, 0);
-    for (int b = b0; b < b1; b++) {
+    // stage: LDS row (source s, component c, register j) holds 64 lanes; wave
+    // w copies rows w, w + nwave, ...; every load of a batch is issued before
+    // the first store.  With several right-hand sides per lane (PIPE) the
+    // loads of batch b + 1 are issued right after batch b is in LDS, so they
+    // are in flight while batch b is summed; with one, the registers this
+    // holds would cost more occupancy than the overlap gains.
+    constexpr bool PIPE = RW == 4;
+    cpx<T> st[TRANS_ROWS];
+    auto stage_load = [&](int b) {
         const int s0 = ld_uniform(L.bat_src, b), ns = ld_uniform(L.bat_src, b + 1) - s0;
-        // stage: LDS row (source s, component c, register j) holds 64 lanes;
-        // wave w copies rows w, w + nwave, ...; every load of the batch is
-        // issued before the first store
-        cpx<T> st[TRANS_ROWS];
 #pragma unroll
         for (int i = 0; i < TRANS_ROWS; i++) {
             const int sc = wave + i * nwave;
@@ -723,6 +732,11 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
             if (sc < 2 * RB * ns && qok && rr < nrhs)
                 st[i] = Uq[pidx(ld_uniform(L.src, s0 + sc / (2 * RB)), c, rr, 0, nrhs, K)];
         }
+    };
+    if (PIPE && b0 < b1) stage_load(b0);
+    for (int b = b0; b < b1; b++) {
+        const int ns = ld_uniform(L.bat_src, b + 1) - ld_uniform(L.bat_src, b);
+        if (!PIPE) stage_load(b);
         if (b > b0) __syncthreads();   // every wave is done with the previous batch
 #pragma unroll
         for (int i = 0; i < TRANS_ROWS; i++) {
@@ -730,6 +744,7 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
             if (sc < 2 * RB * ns) lds[sc * WAVE + lane] = st[i];
         }
         __syncthreads();
+        if (PIPE && b + 1 < b1) stage_load(b + 1);
         if (wave >= nt) continue;
         const int *rw = L.row + ld_uniform(L.bat_row, b);
         const int e0 = ld_uniform(rw, wave), n = ld_uniform(rw, wave + 1) - e0;   // n <= ns <= 64
@@ -1089,15 +1104,17 @@ bool launch_translate_tiled(const TransArgs<T> &args, int nrhs, hipStream_t s)
     const int rw = trans_rw(nrhs), qw = WAVE / rw, rb = rw == 4 ? args.rb : 1;
     TransArgs<T> a = args;
     a.rb = rb;
+    // nblocks: workgroups per XCD over all levels; first: a level's first
+    // position in that per-XCD sequence
     a.nblocks = 0;
     for (int l = 0; l < a.nlev; l++) {
         a.lv[l].nqc = (a.lv[l].K + qw - 1) / qw;
         a.lv[l].first = a.nblocks;
-        a.nblocks += a.lv[l].ntile * a.lv[l].nqc;
+        a.nblocks += (a.lv[l].ntile * a.lv[l].nqc + NXCD - 1) / NXCD;
     }
     if (a.nblocks <= 0) return true;
     const size_t lds = trans_lds_bytes<T>(a.smax, rb);
-    const dim3 grid(xcd_grid(a.nblocks), (nrhs + rw * rb - 1) / (rw * rb)), block(a.tmax * WAVE);
+    const dim3 grid((unsigned)a.nblocks * NXCD, (nrhs + rw * rb - 1) / (rw * rb)), block(a.tmax * WAVE);
     if (rw == 4 && rb == 4)
         hipLaunchKernelGGL((k_translate_tiled<T, 4, 4>), grid, block, lds, s, a, nrhs);
     else if (rw == 4 && rb == 2)
