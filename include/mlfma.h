@@ -227,7 +227,8 @@ int mlfma_gmres(mlfma_handle h, int op, int dtype, long long nrhs, const void *b
  * on the device).  Stored in complex128 and complex64.
  *
  * mlfma_sai_build: after mlfma_precompute_nearfield; k_nearest in 1..32.
- *   Synchronous.  Replaces an earlier SAI of the same op.  Allocates
+ *   Synchronous.  Replaces an earlier SAI of the same op (after a failed
+ *   build the op has none).  Allocates
  *   N x 2 x 64 entries in each precision plus index lists (counted against
  *   the handle's budget).  MLFMA_ERR_UNSUPPORTED if ties push a pattern past
  *   32 RWGs or a Gram matrix is not numerically positive definite.

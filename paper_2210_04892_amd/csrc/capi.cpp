@@ -747,6 +747,7 @@ void precompute_near(mlfma_ctx *c)
 void build_sai(mlfma_ctx *c, int op, int k_nearest)
 {
     const auto t0 = std::chrono::steady_clock::now();
+    c->free_sai(op);     // a failed build leaves the op without an SAI
     const Tree &tr = c->tr;
     const RwgTable &r = c->r;
     const Surface &s = c->s;
@@ -817,7 +818,6 @@ void build_sai(mlfma_ctx *c, int op, int k_nearest)
                 ent_val[q] = u * 2 * SAI_D + 2 * (e - pat_start[u]);
             }
     }
-    c->free_sai(op);
     SaiData &d = c->sai[op];
     const unsigned long long before = c->bytes;
     std::vector<void *> tmp;

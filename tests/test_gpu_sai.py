@@ -47,12 +47,14 @@ def _mesh(name):
             "ico6_r0.5": lambda: synth.icosphere(6, 0.5)}[name]()
 
 
-@pytest.mark.parametrize("op", ["C", "EM"])
-def test_sai_columns_match_oracle(op):
+@pytest.mark.parametrize("op,k", [("C", 16), ("EM", 16), ("C", 1), ("C", 28)])
+def test_sai_columns_match_oracle(op, k):
     """Columns (n, J), (n, M) of M for seeded RWGs n: M applied to unit
-    vectors equals the oracle's least-squares columns."""
+    vectors equals the oracle's least-squares columns.  k = 1 is the
+    degenerate pattern of the RWG alone (a 2 x 2 least-squares problem per
+    RWG); k = 28 a pattern near the largest (32 RWGs with ties)."""
     torch = _torch()
-    name, k = "sphere_r0.5", 16
+    name = "sphere_r0.5"
     v, t = _mesh(name)
     N = 3 * len(t) // 2
     rwgs = sorted(np.random.default_rng(31).choice(N, 4, replace=False).tolist())
@@ -75,9 +77,11 @@ def test_sai_columns_match_oracle(op):
 
 
 def test_sai_apply_multi_rhs_and_errors():
-    """Several right-hand sides in one apply equal column-by-column applies;
-    apply before build and a bad k are refused."""
+    """Several right-hand sides in one apply equal column-by-column applies
+    (also with padded leading dimensions on a side stream, padding left
+    untouched); apply before build and a bad k are refused."""
     torch = _torch()
+    import ctypes
     import paper_2210_04892_amd as mf
     g = _geometry("ico6_r0.5", 12, "C")
     N2 = 2 * g.n_rwg
@@ -85,33 +89,55 @@ def test_sai_apply_multi_rhs_and_errors():
     y = g.sai_apply(x)
     for r in range(5):
         assert torch.equal(y[:, r], g.sai_apply(x[:, r].contiguous()))
+    ld = N2 + 3
+    xb = torch.zeros((5, ld), dtype=torch.complex128, device="cuda")
+    xb[:, :N2] = x.t()
+    yb = torch.full((5, ld), 7.0, dtype=torch.complex128, device="cuda")
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    rc = mf.binding.lib().mlfma_sai_apply(g._h, mf.OP_C, mf.C128, 5, ctypes.c_void_p(xb.data_ptr()), ld,
+                                          ctypes.c_void_p(yb.data_ptr()), ld, ctypes.c_void_p(st.cuda_stream))
+    assert rc == 0
+    st.synchronize()
+    assert torch.equal(yb[:, :N2].t(), y)
+    assert torch.all(yb[:, N2:] == 7.0)
     with pytest.raises(mf.MlfmaError):
         g.sai_apply(x, op="EM")                  # not built for op EM
     with pytest.raises(mf.MlfmaError):
         g.sai_build("C", 0)
     with pytest.raises(mf.MlfmaError):
         g.sai_build("C", 33)
+    # k = 32 on the icosphere: RWGs tied with the 32nd distance push a
+    # pattern past 32 members, which is refused (the earlier SAI is dropped)
+    g2 = _geometry("sphere_r0.5", 16, "EM")
+    with pytest.raises(mf.MlfmaError, match="UNSUPPORTED"):
+        g2.sai_build("EM", 32)
+    with pytest.raises(mf.MlfmaError, match="STATE"):
+        g2.sai_info("EM")
+    g2.sai_build("EM", 16)
 
 
-def test_gmres_with_sai_takes_fewer_steps():
-    """GMRES on op C with plane-wave right-hand sides: with the SAI the true
-    residual meets the same tolerance in fewer Arnoldi steps, and the
-    oracle's dense product of the solution reproduces b."""
+@pytest.mark.parametrize("op", ["C", "EM"])
+def test_gmres_with_sai_takes_fewer_steps(op):
+    """GMRES with plane-wave right-hand sides: with the SAI of the same op
+    the true residual meets the same tolerance in fewer Arnoldi steps, and
+    the oracle's dense product of the solution reproduces b."""
     torch = _torch()
     name = "ico6_r0.5"
     v, t = _mesh(name)
     khat, pol = synth.plane_waves(2, 21)
     b = oracle.plane_wave_rhs(v, t, K0, khat, pol)
-    g = _geometry(name, 16, "C")
+    g = _geometry(name, 16, op)
+    oop = oracle.OP_C if op == "C" else oracle.OP_EM
     for dtype, tol, check in ((torch.complex128, 1e-6, 2e-3), (torch.complex64, 1e-3, 3e-3)):
         bt = torch.from_numpy(np.ascontiguousarray(b)).to(dtype).cuda()
-        x0, it0, rel0 = g.gmres(bt, op="C", restart=30, max_iters=300, tol=tol)
-        x1, it1, rel1 = g.gmres(bt, op="C", restart=30, max_iters=300, tol=tol, precond="sai")
+        x0, it0, rel0 = g.gmres(bt, op=op, restart=30, max_iters=300, tol=tol)
+        x1, it1, rel1 = g.gmres(bt, op=op, restart=30, max_iters=300, tol=tol, precond="sai")
         torch.cuda.synchronize()
         xs = x1.cpu().numpy().astype(np.complex128)
-        err = np.linalg.norm(oracle.matvec(v, t, K0, xs, op=oracle.OP_C) - b) / np.linalg.norm(b)
-        print("[gpu] gmres %s: %d steps plain, %d with SAI; true residual %s / %s; oracle |Cx-b|/|b| %.2e"
-              % (dtype, it0, it1, " ".join("%.1e" % q for q in rel0), " ".join("%.1e" % q for q in rel1), err),
+        err = np.linalg.norm(oracle.matvec(v, t, K0, xs, op=oop) - b) / np.linalg.norm(b)
+        print("[gpu] gmres op %s %s: %d steps plain, %d with SAI; true residual %s / %s; oracle |Ax-b|/|b| %.2e"
+              % (op, dtype, it0, it1, " ".join("%.1e" % q for q in rel0), " ".join("%.1e" % q for q in rel1), err),
               flush=True)
         assert np.all(rel1 <= tol * 1.001)
         assert it1 < it0
