@@ -226,11 +226,12 @@ __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate(const LevelStep<T
     }
 }
 
-// right-hand sides per workgroup: as many (1, 2, 4) as the LDS allows
+// right-hand sides per workgroup: two where the LDS allows (four would hold
+// more LDS per workgroup than the sharing of the parent rows saves)
 inline int step_rb(size_t lds1, int nrhs)
 {
     int rb = 1;
-    while (rb < 4 && rb < nrhs && 2 * rb * lds1 <= STEP_LDS_MAX) rb *= 2;
+    while (rb < 2 && rb < nrhs && 2 * rb * lds1 <= STEP_LDS_MAX) rb *= 2;
     return rb;
 }
 
