@@ -216,16 +216,24 @@ __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__rest
     const bool mok = row < rows, rok = r < nrhs;
     const int h = row & 1;
     const cpx<float> *vr = vals + 2 * (val_off[b] + (long long)(mok ? row / 2 : 0) * ncols);
+    // column indices 64 at a time, one per lane, handed out by lane shuffles
+    // (so the x load of a step does not wait for an index load)
+    int cbase = -64, myc = 0;
     auto load = [&](int j0, cpx<float> &a, cpx<float> &bv) {
+        if (j0 >= cbase + 64) {              // j0 is even: a step never straddles two groups
+            cbase = j0;
+            myc = cl[min(cbase + lane, ncols - 1)];
+        }
         const int j = j0 + jc;
         const bool jok = j < ncols;
+        const int col = __shfl(myc, j - cbase);
         a = mk<float>(0, 0);
         bv = mk<float>(0, 0);
         if (jok && mok) {
             const cpx<float> A = vr[2 * j], B = vr[2 * j + 1];
             a = h == hp ? A : (h == 0 ? mk<float>(-B.re, -B.im) : B);
         }
-        if (jok && rok) bv = X[((long long)cl[j] * 2 + hp) * nrhs + r];
+        if (jok && rok) bv = X[((long long)col * 2 + hp) * nrhs + r];
     };
     f4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
     cpx<float> a, bv, an, bn;
