@@ -34,6 +34,20 @@ __host__ __device__ inline float fmad<float>(float a, float b, float c) { return
 template <>
 __host__ __device__ inline double fmad<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// p[0], p[1] with one 16-byte load in single precision (p must be 16-byte
+// aligned there: an even index into a buffer from the allocator)
+__device__ inline void load_pair(const cpx<float> *p, cpx<float> &a, cpx<float> &b)
+{
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    a = {v.x, v.y};
+    b = {v.z, v.w};
+}
+__device__ inline void load_pair(const cpx<double> *p, cpx<double> &a, cpx<double> &b)
+{
+    a = p[0];
+    b = p[1];
+}
+
 // acc += a b (four fused multiply-adds)
 template <class T>
 __host__ __device__ inline void fma_to(cpx<T> &acc, cpx<T> a, cpx<T> b)

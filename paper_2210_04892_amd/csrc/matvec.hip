@@ -217,8 +217,7 @@ __global__ __launch_bounds__(256) void k_near_tile(int nitem, const int2 *__rest
 #pragma unroll
             for (int i = 0; i < 8; i++) {
                 const long long o = 2 * ((long long)(i < nr ? i : nr - 1) * ncols + j);
-                A[c][i] = vr[o];
-                B[c][i] = vr[o + 1];
+                load_pair(vr + o, A[c][i], B[c][i]);
             }
             const T z = j0 + c * WAVE < ncols ? T(1) : T(0);
             x1[c] = z * X[col * 2];
@@ -390,8 +389,7 @@ __global__ __launch_bounds__(256) void k_radiate1(int op, int nbox, int K, int n
 #pragma unroll
         for (int u = 0; u < G; u++) {
             const int i = min(i0 + u, n1 - 1);
-            Rt[u] = R[((long long)i * K + qq) * 2];
-            Rp[u] = R[((long long)i * K + qq) * 2 + 1];
+            load_pair(R + ((long long)i * K + qq) * 2, Rt[u], Rp[u]);
             const cpx<T> x1 = X[(long long)i * 2], x2 = X[(long long)i * 2 + 1];
             const T z = i0 + u < n1 ? T(1) : T(0);   // RWGs past the box contribute nothing
             if (op == 1) {
@@ -877,8 +875,7 @@ __global__ __launch_bounds__(256) void k_receive1(int op, int N, int K, const in
 #pragma unroll
         for (int c = 0; c < CH; c++) {
             const int q = min(q0 + c * WAVE, K - 1);
-            Pt[c] = pat[((long long)m * K + q) * 2];
-            Pp[c] = pat[((long long)m * K + q) * 2 + 1];
+            load_pair(pat + ((long long)m * K + q) * 2, Pt[c], Pp[c]);
             Vt[c] = V[pidx(b, 0, 0, q, 1, K)];
             Vp[c] = V[pidx(b, 1, 0, q, 1, K)];
             wk[c] = q0 + c * WAVE < K ? wq[q] : T(0);    // samples past K contribute nothing

@@ -147,7 +147,8 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
         a = mk<float>(0, 0);
         bv = mk<float>(0, 0);
         if (mok && qok) {
-            cpx<float> pt = pm[2 * q], pp = pm[2 * q + 1];
+            cpx<float> pt, pp;
+            load_pair(pm + 2 * q, pt, pp);
             if (cj) {
                 pt = conjg(pt);
                 pp = conjg(pp);
@@ -230,7 +231,8 @@ __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__rest
         a = mk<float>(0, 0);
         bv = mk<float>(0, 0);
         if (jok && mok) {
-            const cpx<float> A = vr[2 * j], B = vr[2 * j + 1];
+            cpx<float> A, B;
+            load_pair(vr + 2 * j, A, B);
             a = h == hp ? A : (h == 0 ? mk<float>(-B.re, -B.im) : B);
         }
         if (jok && rok) bv = X[((long long)col * 2 + hp) * nrhs + r];
