@@ -253,10 +253,12 @@ bool launch_aggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s)
     if (lds1 > STEP_LDS_MAX) return false;
     if (a.nbox <= 0 || nrhs <= 0) return true;
     // children per group: with few right-hand sides the grid is small and
-    // the per-child barriers dominate, so up to all eight children that fit
-    // the LDS budget are grouped; with more, one child at a time keeps the
-    // LDS per workgroup (and so the occupancy) low
-    const int G = nrhs < 4 ? (int)std::min<size_t>(8, STEP_LDS_MAX / lds1) : 1;
+    // the per-child barriers dominate, so several children are grouped (four
+    // in single, two in double precision: a parent on a surface has about
+    // four, and larger groups hold LDS that costs occupancy); with more
+    // right-hand sides, one child at a time keeps the LDS per workgroup low
+    const int gmax = sizeof(T) == 4 ? 4 : 2;
+    const int G = nrhs < 4 ? (int)std::min<size_t>(gmax, STEP_LDS_MAX / lds1) : 1;
     const dim3 grid(xcd_grid_l((long long)a.nbox * a.nchunk), nrhs), block(STEP_THREADS);
     const size_t lds = G * lds1;
     if (a.taps == 6) agg_launch<T, 6>(G, grid, block, lds, s, a, nrhs);
