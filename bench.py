@@ -36,7 +36,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--workload", default="sphere_r3")
     p.add_argument("--nrhs", type=int, default=None, help="override the workload's RHS count")
-    p.add_argument("--cpu-rows", type=int, default=160, help="rows of the oracle sample (0 = skip)")
+    p.add_argument("--cpu-rows", type=int, default=320, help="rows of the oracle sample (0 = skip)")
     p.add_argument("--op", default="C", choices=["C", "EM"])
     p.add_argument("--leaf-extra", type=int, default=2, help="extra multipoles at the leaf level")
     p.add_argument("--interp-order", type=int, default=8, help="Lagrange points per angle")
