@@ -110,7 +110,11 @@ int mlfma_precompute_nearfield(mlfma_handle h);
  * Asynchronous: returns after enqueueing.  Enqueue-time errors are returned;
  * an asynchronous device error is reported by the next call on the handle.
  * Grows the workspace (a blocking allocation) if nrhs exceeds what it was
- * sized for.  Not thread-safe for concurrent calls on one handle.
+ * sized for.  Not thread-safe for concurrent calls on one handle; products
+ * on one handle share its workspace, so products enqueued on different
+ * streams must be ordered by the caller.  The near part runs on a second
+ * stream of the handle, forked from and joined back into hip_stream (so the
+ * call is also valid inside a stream capture of hip_stream).
  * Errors: MLFMA_ERR_STATE (near field not computed), MLFMA_ERR_ARG,
  * MLFMA_ERR_OOM, MLFMA_ERR_HIP.
  */
