@@ -121,6 +121,28 @@ int mlfma_precompute_nearfield(mlfma_handle h);
 int mlfma_matvec_LK(mlfma_handle h, int op, int dtype, long long nrhs, const void *x, long long ldx,
                     void *y, long long ldy, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Several products in one call (the batched form of Sec. II-E step 2(a) for
+ * many geometries or operators): every item is y = A x as in
+ * mlfma_matvec_LK.  Items of different geometries run concurrently on
+ * streams of their handles, forked from and joined back into hip_stream;
+ * items of one geometry run in list order (they share its workspace).  All
+ * items are checked before anything is enqueued (the first bad one is
+ * reported, "item i: ..."); all handles must live on one device.
+ * Asynchronous like mlfma_matvec_LK; valid inside a stream capture of
+ * hip_stream.  Grows workspaces as mlfma_matvec_LK does.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    mlfma_handle h;
+    int op, dtype;           /* MLFMA_OP_*, MLFMA_C128 / MLFMA_C64              */
+    long long nrhs;
+    const void *x;           /* device, 2N x nrhs column-major, ldx >= 2N        */
+    long long ldx;
+    void *y;                 /* device, overwritten; must not overlap x          */
+    long long ldy;
+} mlfma_batch_item;
+int mlfma_matvec_batch(const mlfma_batch_item *items, int n_items, void *hip_stream);
+
 /*
  * Diagnostic split of mlfma_matvec_LK (same arguments, same asynchrony):
  *   part = MLFMA_PART_NEAR : near-field blocks (and identity terms) only;

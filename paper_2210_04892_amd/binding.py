@@ -36,6 +36,11 @@ class Options(ctypes.Structure):
                 ("device", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_ulonglong)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_void_p), ("op", ctypes.c_int), ("dtype", ctypes.c_int), ("nrhs", ctypes.c_longlong),
+                ("x", ctypes.c_void_p), ("ldx", ctypes.c_longlong), ("y", ctypes.c_void_p), ("ldy", ctypes.c_longlong)]
+
+
 class ServerOptions(ctypes.Structure):
     _fields_ = [("streams", ctypes.c_int), ("max_batch_rhs", ctypes.c_int), ("device", ctypes.c_int),
                 ("hbm_budget_bytes", ctypes.c_ulonglong), ("use_graphs", ctypes.c_int)]
@@ -77,6 +82,7 @@ def lib():
         L.mlfma_sai_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, P]
         L.mlfma_sai_info.argtypes = [P, ctypes.c_int, ctypes.POINTER(LL), ctypes.POINTER(ctypes.c_int),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_ulonglong)]
+        L.mlfma_matvec_batch.argtypes = [P, ctypes.c_int, P]
         L.mlfma_plane_wave_rhs.argtypes = [P, ctypes.c_int, LL, P, P, P, LL, P]
         L.mlfma_far_field.argtypes = [P, ctypes.c_int, LL, P, LL, LL, P, P, P]
         L.mlfma_server_opts_default.argtypes = [ctypes.POINTER(ServerOptions)]
@@ -410,6 +416,38 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def matvec_batch(items, stream=None):
+    """mlfma_matvec_batch: items = [(geometry, x, op), ...] with x complex CUDA
+    tensors (2N,) or (2N, nrhs); returns the products in the same order.
+    Products of different geometries run concurrently."""
+    arr = (BatchItem * len(items))()
+    keep, outs = [], []
+    for i, (g, x, op) in enumerate(items):
+        if x.dtype == torch.complex128:
+            dt = C128
+        elif x.dtype == torch.complex64:
+            dt = C64
+        else:
+            raise TypeError("x must be complex128 or complex64")
+        squeeze = x.dim() == 1
+        X = x[:, None] if squeeze else x
+        xt = X.t().contiguous()
+        yt = torch.empty_like(xt)
+        keep.append(xt)
+        outs.append((yt, squeeze))
+        arr[i] = BatchItem(g._h, _OPS.get(op, op), dt, X.shape[1], xt.data_ptr(), 2 * g.n_rwg, yt.data_ptr(),
+                           2 * g.n_rwg)
+    dev = items[0][0].device if items else 0
+    s = torch.cuda.current_stream(dev) if stream is None else stream
+    with torch.cuda.device(dev):
+        _check(lib().mlfma_matvec_batch(ctypes.cast(arr, ctypes.c_void_p), len(items), s.cuda_stream))
+    res = []
+    for yt, squeeze in outs:
+        y = yt.t()
+        res.append(y[:, 0] if squeeze else y)
+    return res
 
 
 def translation_operator(k, L, X, khat):

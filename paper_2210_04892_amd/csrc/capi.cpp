@@ -156,6 +156,8 @@ struct mlfma_ctx {
     SaiData sai[2];           // per op (MLFMA_OP_C, MLFMA_OP_EM)
     hipStream_t side = nullptr;                    // near-field stream of ws
     hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t bstream = nullptr;                 // this handle's products in mlfma_matvec_batch
+    hipEvent_t bfork = nullptr, bjoin = nullptr;
     Workspace ws;             // workspace of mlfma_matvec_LK / mlfma_matvec_part
     long long ws_gen = 0;     // bumped whenever ws is reallocated (captured graphs refer to it)
     long long uid = 0;        // unique over the process (keys of the server's captured products)
@@ -234,6 +236,9 @@ struct mlfma_ctx {
         if (fork) (void)hipEventDestroy(fork);
         if (join) (void)hipEventDestroy(join);
         if (side) (void)hipStreamDestroy(side);
+        if (bfork) (void)hipEventDestroy(bfork);
+        if (bjoin) (void)hipEventDestroy(bjoin);
+        if (bstream) (void)hipStreamDestroy(bstream);
         for (void *p : allocs) (void)hipFree(p);
     }
 };
@@ -1435,6 +1440,77 @@ int mlfma_matvec_part(mlfma_handle h, int op, int dtype, int part, long long nrh
         else
             run_matvec<float>(h, h->ws, h->p32, op, part, (int)nrhs, (const cpx<float> *)x, ldx, (cpx<float> *)y,
                               ldy, st, h->prof);
+        HIPCHK(hipGetLastError());
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int mlfma_matvec_batch(const mlfma_batch_item *items, int n_items, void *hip_stream)
+{
+    g_last_error.clear();
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(Error(MLFMA_ERR_ARG, "bad item list"));
+    if (n_items == 0) return MLFMA_OK;
+    // every item is checked before anything is enqueued
+    for (int i = 0; i < n_items; i++) {
+        const mlfma_batch_item &it = items[i];
+        const std::string at = "item " + std::to_string(i) + ": ";
+        if (!it.h) return fail(Error(MLFMA_ERR_ARG, at + "NULL handle"));
+        if (!it.h->near_ready)
+            return fail(Error(MLFMA_ERR_STATE, at + "mlfma_precompute_nearfield has not been called"));
+        if (it.h->device != items[0].h->device) return fail(Error(MLFMA_ERR_ARG, at + "geometry on another device"));
+        if (it.op != MLFMA_OP_C && it.op != MLFMA_OP_EM) return fail(Error(MLFMA_ERR_ARG, at + "unknown op"));
+        if (it.dtype != MLFMA_C128 && it.dtype != MLFMA_C64) return fail(Error(MLFMA_ERR_ARG, at + "unknown dtype"));
+        const long long N2 = 2LL * it.h->r.n;
+        if (it.nrhs < 1 || it.nrhs > (1 << 20) || !it.x || !it.y || it.ldx < N2 || it.ldy < N2)
+            return fail(Error(MLFMA_ERR_ARG, at + "bad nrhs, pointer or leading dimension"));
+        const size_t esz = it.dtype == MLFMA_C128 ? 16 : 8;
+        const char *xb = (const char *)it.x, *yb = (const char *)it.y;
+        if (xb < yb + (size_t)(it.ldy * (it.nrhs - 1) + N2) * esz &&
+            yb < xb + (size_t)(it.ldx * (it.nrhs - 1) + N2) * esz)
+            return fail(Error(MLFMA_ERR_ARG, at + "x and y overlap"));
+    }
+    try {
+        DeviceGuard g(items[0].h->device);
+        HIPCHK(hipGetLastError());
+        // geometries in order of first appearance, with their widest product
+        std::vector<std::pair<mlfma_handle, long long>> hs;
+        for (int i = 0; i < n_items; i++) {
+            auto f = std::find_if(hs.begin(), hs.end(), [&](const auto &p) { return p.first == items[i].h; });
+            if (f == hs.end()) hs.push_back({items[i].h, items[i].nrhs});
+            else f->second = std::max(f->second, items[i].nrhs);
+        }
+        for (auto &p : hs) {
+            ensure_workspace(p.first, (int)p.second);
+            if (!p.first->bstream) {
+                HIPCHK(hipStreamCreateWithFlags(&p.first->bstream, hipStreamNonBlocking));
+                HIPCHK(hipEventCreateWithFlags(&p.first->bfork, hipEventDisableTiming));
+                HIPCHK(hipEventCreateWithFlags(&p.first->bjoin, hipEventDisableTiming));
+            }
+        }
+        hipStream_t st = (hipStream_t)hip_stream;
+        const bool fork = hs.size() > 1;
+        if (fork) {
+            HIPCHK(hipEventRecord(hs[0].first->bfork, st));
+            for (auto &p : hs) HIPCHK(hipStreamWaitEvent(p.first->bstream, hs[0].first->bfork, 0));
+        }
+        for (int i = 0; i < n_items; i++) {
+            const mlfma_batch_item &it = items[i];
+            mlfma_ctx *h = it.h;
+            hipStream_t s = fork ? h->bstream : st;
+            if (it.dtype == MLFMA_C128)
+                run_matvec<double>(h, h->ws, h->p64, it.op, MLFMA_PART_ALL, (int)it.nrhs, (const cpx<double> *)it.x,
+                                   it.ldx, (cpx<double> *)it.y, it.ldy, s, h->prof);
+            else
+                run_matvec<float>(h, h->ws, h->p32, it.op, MLFMA_PART_ALL, (int)it.nrhs, (const cpx<float> *)it.x,
+                                  it.ldx, (cpx<float> *)it.y, it.ldy, s, h->prof);
+        }
+        if (fork)
+            for (auto &p : hs) {
+                HIPCHK(hipEventRecord(p.first->bjoin, p.first->bstream));
+                HIPCHK(hipStreamWaitEvent(st, p.first->bjoin, 0));
+            }
         HIPCHK(hipGetLastError());
         return MLFMA_OK;
     } catch (const Error &e) {

@@ -277,8 +277,7 @@ bool launch_disaggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s)
     const int rb = step_rb(lds1, nrhs);
     const dim3 grid(xcd_grid_l((long long)a.nbox * a.nchunk), (nrhs + rb - 1) / rb), block(STEP_THREADS);
     const size_t lds = rb * lds1;
-    if (rb == 4) hipLaunchKernelGGL((k_disaggregate<T, 4>), grid, block, lds, s, a, nrhs);
-    else if (rb == 2) hipLaunchKernelGGL((k_disaggregate<T, 2>), grid, block, lds, s, a, nrhs);
+    if (rb == 2) hipLaunchKernelGGL((k_disaggregate<T, 2>), grid, block, lds, s, a, nrhs);
     else hipLaunchKernelGGL((k_disaggregate<T, 1>), grid, block, lds, s, a, nrhs);
     return true;
 }

@@ -363,3 +363,34 @@ def test_box_plane_waves_64_rhs():
           % (block, np.median(errs), errs.max()), flush=True)
     assert block <= MLFMA_TOL
     assert errs.max() <= MLFMA_TOL
+
+
+def test_matvec_batch_matches_single_products():
+    """mlfma_matvec_batch over two geometries (three items, both precisions
+    and both ops, two of them on one handle) equals the products made one by
+    one, bit for bit; one bad item refuses the whole batch before anything
+    runs."""
+    torch = _torch()
+    import ctypes
+    import paper_2210_04892_amd as mf
+    g1, g2 = geometry("ico6_r0.5"), geometry("sphere_r0.5")
+    n1, n2 = 2 * g1.n_rwg, 2 * g2.n_rwg
+    x1 = torch.from_numpy(synth.gaussian_coeffs(n1, 3, 41)).to(torch.complex64).cuda()
+    x2 = torch.from_numpy(synth.gaussian_coeffs(n2, 1, 42)[:, 0]).cuda()
+    x3 = torch.from_numpy(synth.gaussian_coeffs(n1, 1, 43)[:, 0]).cuda()
+    items = [(g1, x1, "C"), (g2, x2, "EM"), (g1, x3, "EM")]
+    ys = mf.matvec_batch(items)
+    torch.cuda.synchronize()
+    for (g, x, op), y in zip(items, ys):
+        assert torch.equal(y, g.matvec(x, op=op))
+    # a leading dimension below 2N in the second item: nothing is enqueued
+    xt = x1.t().contiguous()
+    yt = torch.full_like(xt, 5.0)
+    arr = (mf.binding.BatchItem * 2)()
+    arr[0] = mf.binding.BatchItem(g1._h, mf.OP_C, mf.C64, 3, xt.data_ptr(), n1, yt.data_ptr(), n1)
+    arr[1] = mf.binding.BatchItem(g2._h, mf.OP_C, mf.C64, 1, xt.data_ptr(), n2 - 1, yt.data_ptr(), n2)
+    rc = mf.binding.lib().mlfma_matvec_batch(ctypes.cast(arr, ctypes.c_void_p), 2, None)
+    assert rc == -1
+    assert b"item 1" in mf.binding.lib().mlfma_last_error()
+    torch.cuda.synchronize()
+    assert torch.all(yt == 5.0)
