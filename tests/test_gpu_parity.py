@@ -39,6 +39,7 @@ MESHES = {
     "sphere_r3": lambda: synth.icosphere(36, 3.0),
     "box_4x4x1": lambda: synth.rounded_box((4.0, 4.0, 1.0), 0.2, 0.073),
     "octahedron": lambda: synth.octahedron(0.1),
+    "sphere_r8": lambda: synth.icosphere(96, 8.0),
     # two disconnected scatterers in one tree (BI equations on each surface)
     "two_bodies": lambda: synth.scene(synth.icosphere(6, 0.5) + ((0, 0, 0),),
                                       synth.icosphere(4, 0.3) + ((1.4, 0.2, -0.1),)),
@@ -130,6 +131,30 @@ def test_per_level_far_field():
         y = _gpu(name, x, "C", np.complex128, part=mf.PART_LEVEL + lev)
         err = np.linalg.norm(_pick(y, rows, N) - ref["C"][lev]) / norm
         print("[gpu] level %d: |y_l - ref_l| / |ref| = %.2e" % (lev, err), flush=True)
+        assert err <= MLFMA_TOL
+
+
+def test_sphere_r8_sampled_rows_per_level():
+    """The large single geometry (sphere r = 8, 276 480 RWGs, 7 levels) with
+    16 right-hand sides, the benchmark's launch configuration: the whole
+    product in both precisions and every level's far-field share against the
+    oracle on 48 seeded rows (error stated per level)."""
+    import paper_2210_04892_amd as mf
+    name = "sphere_r8"
+    x, rows, ref = reference(name, 48, 16, 4)
+    N = x.shape[0] // 2
+    full = ref["C"].sum(axis=0)
+    for dtype in (np.complex64, np.complex128):
+        err = _rel(_pick(_gpu(name, x, "C", dtype), rows, N), full)
+        print("[gpu] sphere_r8 16 RHS %s rel err %.2e" % (np.dtype(dtype).name, err), flush=True)
+        assert err <= MLFMA_TOL
+    g = geometry(name, max_rhs=16)
+    norm = np.linalg.norm(full)
+    for lev in range(2, g.levels):
+        y = _gpu(name, x, "C", np.complex64, part=mf.PART_LEVEL + lev)
+        err = np.linalg.norm(_pick(y, rows, N) - ref["C"][lev]) / norm
+        print("[gpu] sphere_r8 level %d: |y_l - ref_l| / |ref| = %.2e (share %.2e)"
+              % (lev, err, np.linalg.norm(ref["C"][lev]) / norm), flush=True)
         assert err <= MLFMA_TOL
 
 
