@@ -158,10 +158,11 @@ def test_sphere_r8_sampled_rows_per_level():
         assert err <= MLFMA_TOL
 
 
-@pytest.mark.parametrize("nrhs", [3, 20])
+@pytest.mark.parametrize("nrhs", [3, 20, 40])
 def test_multi_rhs(nrhs):
-    """Several right-hand sides in one launch (rhs chunks of 4 and 16 with a
-    ragged tail) against the oracle, both precisions."""
+    """Several right-hand sides in one launch (rhs chunks of 4 and 16, one or
+    several 16-wide matrix-core tiles, with a ragged tail) against the
+    oracle, both precisions."""
     name = "ico6_r0.5"
     x, rows, ref = reference(name, None, nrhs, 5)
     for dtype in (np.complex128, np.complex64):
