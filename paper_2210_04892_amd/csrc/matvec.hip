@@ -174,13 +174,13 @@ __global__ __launch_bounds__(256) void k_near(int N, const int *__restrict__ lea
     }
 }
 
-// Near field for one right-hand side.  Wave = (leaf box, tile of up to 8
-// RWGs of the box, i.e. one (box, 16-row tile) work item); lanes over the
-// box's columns (the RWGs of its adjacent boxes, concatenated in cols), so
-// every column's x is loaded once for the 8 rows and the column structure
-// is not rebuilt per row.  Rows are written (=), identity terms of the C
+// Near field for one right-hand side.  Wave = (leaf box, RWV of the up to 8
+// RWGs of one (box, 16-row tile) work item); lanes over the box's columns
+// (the RWGs of its adjacent boxes, concatenated in cols), so every column's
+// x is loaded once for the wave's rows and the column structure is not
+// rebuilt per row.  Rows are written (=), identity terms of the C
 // block added by the lane that owns the row.
-template <class T>
+template <class T, int RWV>
 __global__ __launch_bounds__(256) void k_near_tile(int nitem, const int2 *__restrict__ items,
                                                    const int *__restrict__ box_start, const int *__restrict__ col_off,
                                                    const int *__restrict__ cols, const long long *__restrict__ val_off,
@@ -189,19 +189,21 @@ __global__ __launch_bounds__(256) void k_near_tile(int nitem, const int2 *__rest
                                                    const cpx<T> *__restrict__ X, cpx<T> *__restrict__ Y)
 {
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
-    const long long blk = xcd_block((nitem + 3) / 4);
+    constexpr int SUB = 8 / RWV;                 // waves per work item
+    const long long blk = xcd_block(((long long)nitem * SUB + 3) / 4);
     if (blk < 0) return;
     const long long w = blk * 4 + wave;
-    if (w >= nitem) return;
-    const int2 it = items[w];
-    const int b = it.x, m0 = it.y * 8;
-    const int n0 = box_start[b], nr = min(8, box_start[b + 1] - n0 - m0);
+    if (w >= (long long)nitem * SUB) return;
+    const int2 it = items[w / SUB];
+    const int b = it.x, m0 = it.y * 8 + (int)(w % SUB) * RWV;
+    const int n0 = box_start[b], nr = min(RWV, box_start[b + 1] - n0 - m0);
+    if (nr <= 0) return;
     const int *cl = cols + col_off[b];
     const int ncols = col_off[b + 1] - col_off[b];
     const cpx<T> *vr = vals + 2 * (val_off[b] + (long long)m0 * ncols);
-    cpx<T> a1[8], a2[8];
+    cpx<T> a1[RWV], a2[RWV];
 #pragma unroll
-    for (int i = 0; i < 8; i++) a1[i] = a2[i] = mk<T>(0, 0);
+    for (int i = 0; i < RWV; i++) a1[i] = a2[i] = mk<T>(0, 0);
     // rows past the tile's last re-read that row (branch-free, so that all
     // loads of an iteration are in flight together); their sums are dropped
     // one column chunk per pass (more chunks lower the occupancy more than
@@ -209,13 +211,13 @@ __global__ __launch_bounds__(256) void k_near_tile(int nitem, const int2 *__rest
     // column with weight zero
     constexpr int CH = 1;
     for (int j0 = lane; j0 < ncols; j0 += CH * WAVE) {
-        cpx<T> A[CH][8], B[CH][8], x1[CH], x2[CH];
+        cpx<T> A[CH][RWV], B[CH][RWV], x1[CH], x2[CH];
 #pragma unroll
         for (int c = 0; c < CH; c++) {
             const int j = min(j0 + c * WAVE, ncols - 1);
             const long long col = cl[j];
 #pragma unroll
-            for (int i = 0; i < 8; i++) {
+            for (int i = 0; i < RWV; i++) {
                 const long long o = 2 * ((long long)(i < nr ? i : nr - 1) * ncols + j);
                 load_pair(vr + o, A[c][i], B[c][i]);
             }
@@ -226,7 +228,7 @@ __global__ __launch_bounds__(256) void k_near_tile(int nitem, const int2 *__rest
 #pragma unroll
         for (int c = 0; c < CH; c++)
 #pragma unroll
-            for (int i = 0; i < 8; i++) {
+            for (int i = 0; i < RWV; i++) {
                 fma_to(a1[i], A[c][i], x1[c]);
                 fms_to(a1[i], B[c][i], x2[c]);
                 fma_to(a2[i], A[c][i], x2[c]);
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(256) void k_near_tile(int nitem, const int2 *__rest
     }
     cpx<T> y1 = mk<T>(0, 0), y2 = mk<T>(0, 0);
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
+    for (int i = 0; i < RWV; i++) {
         if (i >= nr) break;
         const cpx<T> s1 = wave_sum(a1[i]), s2 = wave_sum(a2[i]);
         if (lane == i) {
@@ -986,8 +988,11 @@ void launch_near_tile(int nitem, const int2 *items, const int *box_start, const 
                       const T *id_w, const cpx<T> *X, cpx<T> *Y, hipStream_t s)
 {
     if (nitem <= 0) return;
-    hipLaunchKernelGGL(k_near_tile<T>, dim3(xcd_grid((nitem + 3) / 4)), dim3(256), 0, s, nitem, items, box_start,
-                       col_off, cols, val_off, vals, id_start, id_col, id_w, X, Y);
+    // rows per wave: four in single and two in double precision (a wave per
+    // 8-RWG item holds registers that cut the occupancy, most in double)
+    constexpr int RWV = sizeof(T) == 4 ? 4 : 2;
+    hipLaunchKernelGGL((k_near_tile<T, RWV>), dim3(xcd_grid(((long long)nitem * (8 / RWV) + 3) / 4)), dim3(256), 0, s,
+                       nitem, items, box_start, col_off, cols, val_off, vals, id_start, id_col, id_w, X, Y);
 }
 
 template <class T>
