@@ -44,7 +44,7 @@ constexpr int STEP_OUT = 4;     // outputs per thread: a chunk has at most 4 * 2
 // windows are staged together, their intermediates formed together, then the
 // phi stencil and the shift accumulate over the group (three barriers per
 // group instead of per child)
-template <class T, int P, bool GROUPED>
+template <class T, int P, bool GROUPED, int OUT>
 __global__ __launch_bounds__(STEP_THREADS) void k_aggregate(const LevelStep<T> a, int nrhs, int Gr)
 {
     const int G = GROUPED ? Gr : 1;
@@ -61,9 +61,9 @@ __global__ __launch_bounds__(STEP_THREADS) void k_aggregate(const LevelStep<T> a
     const int olen = (i1 - i0) * a.nph_p;
     cpx<T> *cw = reinterpret_cast<cpx<T> *>(step_lds_raw);   // [G][2][wmax] child windows
     cpx<T> *mid = cw + 2 * (size_t)G * wmax;                  // [G][2][mmax] intermediates
-    cpx<T> acc0[STEP_OUT], acc1[STEP_OUT];
+    cpx<T> acc0[OUT], acc1[OUT];
 #pragma unroll
-    for (int k = 0; k < STEP_OUT; k++) acc0[k] = acc1[k] = mk<T>(0, 0);
+    for (int k = 0; k < OUT; k++) acc0[k] = acc1[k] = mk<T>(0, 0);
     const int cb = a.child_start[Pb], ce = a.child_start[Pb + 1];
     for (int cg = cb; cg < ce; cg += G) {
         const int ng = GROUPED ? min(G, ce - cg) : 1;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(STEP_THREADS) void k_aggregate(const LevelStep<T> a
         __syncthreads();
         // phi and the shift to the parent centre, summed over the group
 #pragma unroll
-        for (int k = 0; k < STEP_OUT; k++) {
+        for (int k = 0; k < OUT; k++) {
             const int o = threadIdx.x + k * STEP_THREADS;
             if (o >= olen) continue;
             const long long q = (long long)i0 * a.nph_p + o;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(STEP_THREADS) void k_aggregate(const LevelStep<T> a
         __syncthreads();   // the next group reuses the windows and the intermediates
     }
 #pragma unroll
-    for (int k = 0; k < STEP_OUT; k++) {
+    for (int k = 0; k < OUT; k++) {
         const int o = threadIdx.x + k * STEP_THREADS;
         if (o >= olen) continue;
         const int q = i0 * a.nph_p + o;
@@ -237,11 +237,16 @@ inline int step_rb(size_t lds1, int nrhs)
 
 }  // namespace
 
+// outputs per thread: two where the chunk has at most 512 of them (fewer
+// registers), else four
 template <class T, int P>
 void agg_launch(int G, dim3 grid, dim3 block, size_t lds, hipStream_t s, const LevelStep<T> &a, int nrhs)
 {
-    if (G > 1) hipLaunchKernelGGL((k_aggregate<T, P, true>), grid, block, lds, s, a, nrhs, G);
-    else hipLaunchKernelGGL((k_aggregate<T, P, false>), grid, block, lds, s, a, nrhs, 1);
+    const bool two = (long long)a.rows * a.nph_p <= 2 * STEP_THREADS;
+    if (G > 1 && two) hipLaunchKernelGGL((k_aggregate<T, P, true, 2>), grid, block, lds, s, a, nrhs, G);
+    else if (G > 1) hipLaunchKernelGGL((k_aggregate<T, P, true, STEP_OUT>), grid, block, lds, s, a, nrhs, G);
+    else if (two) hipLaunchKernelGGL((k_aggregate<T, P, false, 2>), grid, block, lds, s, a, nrhs, 1);
+    else hipLaunchKernelGGL((k_aggregate<T, P, false, STEP_OUT>), grid, block, lds, s, a, nrhs, 1);
 }
 
 template <class T>
