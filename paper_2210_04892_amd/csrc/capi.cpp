@@ -100,7 +100,7 @@ struct Workspace {
     void *X = nullptr, *Y = nullptr, *mid = nullptr;
     std::vector<void *> U, V;
     // optional second stream (not owned): the near field then runs beside
-    // the far-field chain, forked after the permutation and joined before the
+    // the far-field chain, forked after the radiation and joined before the
     // receive step
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
