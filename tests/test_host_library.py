@@ -62,6 +62,23 @@ def test_translation_operator_rejects_bad_args():
         mf.translation_operator(-1.0, 8, [1.0, 0, 0], np.array([[0, 0, 1.0]]))
 
 
+def test_null_handle_and_empty_batch_checks():
+    """Argument checks that need no device: an empty batch is a no-op, a
+    negative count or a missing item list is refused, NULL handles are
+    refused by the SAI and batch calls and accepted by release."""
+    import paper_2210_04892_amd.binding as b
+    L = b.lib()
+    assert L.mlfma_matvec_batch(None, 0, None) == 0
+    assert L.mlfma_matvec_batch(None, -1, None) == -1
+    assert L.mlfma_matvec_batch(None, 2, None) == -1
+    items = (b.BatchItem * 1)()
+    assert L.mlfma_matvec_batch(ctypes.cast(items, ctypes.c_void_p), 1, None) == -1     # NULL handle
+    assert b"item 0" in L.mlfma_last_error()
+    assert L.mlfma_sai_build(None, 0, 16) == -1
+    assert L.mlfma_sai_apply(None, 0, 0, 1, None, 1, None, 1, None) == -1
+    assert L.mlfma_release(None) == 0
+
+
 def _build_rc(v, t):
     import paper_2210_04892_amd.binding as b
     o = b.default_options()
