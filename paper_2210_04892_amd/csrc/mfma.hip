@@ -136,39 +136,41 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
     const int lo = lane & 15, kk = lane >> 4;
     const cpx<float> *pat = op == MLFMA_OP_EM ? R : Q;
     const bool cj = op == MLFMA_OP_EM;
-    const int kq = (K + 3) / 4, nstep = 2 * kq;     // (component, 4 samples) steps
+    const int kq = (K + 3) / 4;                     // steps of 4 samples per component
     const int row = tile * 16 + lo, r = rt * 16 + lo;
     const bool mok = row < rows, rok = r < nrhs;
     const int h = row & 1;
     const cpx<float> *pm = pat + (long long)(n0 + (mok ? row / 2 : 0)) * K * 2;
-    auto load = [&](int step, cpx<float> &a, cpx<float> &bv) {
-        const int c = step / kq, q = (step % kq) * 4 + kk;
-        const bool qok = q < K;
-        a = mk<float>(0, 0);
-        bv = mk<float>(0, 0);
-        if (mok && qok) {
-            cpx<float> pt, pp;
-            load_pair(pm + 2 * q, pt, pp);
-            if (cj) {
-                pt = conjg(pt);
-                pp = conjg(pp);
-            }
-            const cpx<float> sel = h == 0 ? (c == 0 ? pt : pp) : (c == 0 ? pp : mk<float>(-pt.re, -pt.im));
-            a = wq[q] * sel;
-        }
-        if (qok && rok) bv = V[pidx_m(b, c, r, q, nrhs, K)];
-    };
     f4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
-    cpx<float> a, bv, an, bn;
-    load(0, a, bv);
-    for (int step = 0; step < nstep; step++) {
-        if (step + 1 < nstep) load(step + 1, an, bn);
-        dre = mfma4(a.re, bv.re, dre);
-        dim = mfma4(a.re, bv.im, dim);
-        dre = mfma4(-a.im, bv.im, dre);
-        dim = mfma4(a.im, bv.re, dim);
-        a = an;
-        bv = bn;
+    for (int c = 0; c < 2; c++) {
+        // the lane's A operand is one component of its row's pattern: theta
+        // for (h, c) = (0, 0), phi for (0, 1) and (1, 0), minus theta for (1, 1)
+        const int comp = (h == 0) == (c == 0) ? 0 : 1;
+        const float sg = (h == 1 && c == 1) ? -1.0f : 1.0f;
+        const cpx<float> *vc = V + ((long long)(b * 2 + c) * nrhs + (rok ? r : 0)) * K;
+        auto load = [&](int qs, cpx<float> &a, cpx<float> &bv) {
+            const int q = qs * 4 + kk;
+            const bool qok = q < K;
+            a = mk<float>(0, 0);
+            bv = mk<float>(0, 0);
+            if (mok && qok) {
+                cpx<float> p = pm[2 * q + comp];
+                if (cj) p = conjg(p);
+                a = (sg * wq[q]) * p;
+            }
+            if (qok && rok) bv = vc[q];
+        };
+        cpx<float> a, bv, an, bn;
+        load(0, a, bv);
+        for (int qs = 0; qs < kq; qs++) {
+            if (qs + 1 < kq) load(qs + 1, an, bn);
+            dre = mfma4(a.re, bv.re, dre);
+            dim = mfma4(a.re, bv.im, dim);
+            dre = mfma4(-a.im, bv.im, dre);
+            dim = mfma4(a.im, bv.re, dim);
+            a = an;
+            bv = bn;
+        }
     }
 #pragma unroll
     for (int v = 0; v < 4; v++) {
@@ -217,6 +219,8 @@ __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__rest
     const bool mok = row < rows, rok = r < nrhs;
     const int h = row & 1;
     const cpx<float> *vr = vals + 2 * (val_off[b] + (long long)(mok ? row / 2 : 0) * ncols);
+    const int vsel = h == hp ? 0 : 1;
+    const float vsg = (h == 0 && hp == 1) ? -1.0f : 1.0f;
     // column indices 64 at a time, one per lane, handed out by lane shuffles
     // (so the x load of a step does not wait for an index load)
     int cbase = -64, myc = 0;
@@ -231,9 +235,9 @@ __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__rest
         a = mk<float>(0, 0);
         bv = mk<float>(0, 0);
         if (jok && mok) {
-            cpx<float> A, B;
-            load_pair(vr + 2 * j, A, B);
-            a = h == hp ? A : (h == 0 ? mk<float>(-B.re, -B.im) : B);
+            // [[A, -B], [B, A]]: the lane needs A on the diagonal, B (or -B) off it
+            const cpx<float> v = vr[2 * j + vsel];
+            a = mk<float>(vsg * v.re, vsg * v.im);
         }
         if (jok && rok) bv = X[((long long)col * 2 + hp) * nrhs + r];
     };
