@@ -77,6 +77,8 @@ __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, i
     // which half of X feeds this lane's alpha/beta, and its factor
     const int h = op == MLFMA_OP_EM ? s : 1 - s;
     const float fac = op == MLFMA_OP_EM ? (s ? -1.0f : 1.0f) : 0.5f;
+    const int rcomp = s == 0 ? c : 1 - c;
+    const float rsg = (s == 1 && c == 0) ? -1.0f : 1.0f;
     const int n0 = box_start[b], n1 = box_start[b + 1];
     f4 dre[RT], dim[RT];
 #pragma unroll
@@ -86,10 +88,9 @@ __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, i
         const bool nok = nn < n1;
         cpx<float> bv = mk<float>(0, 0);
         if (nok && qok) {
-            const cpx<float> *Rn = R + ((long long)nn * K + q) * 2;
-            if (s == 0) bv = Rn[c];
-            else if (c == 0) bv = mk<float>(-Rn[1].re, -Rn[1].im);   // khat x (vt, vp) = (-vp, vt)
-            else bv = Rn[0];
+            // alpha lanes take R[c]; beta lanes (khat x R)[c]: (-R_phi, R_theta)
+            const cpx<float> v = R[((long long)nn * K + q) * 2 + rcomp];
+            bv = mk<float>(rsg * v.re, rsg * v.im);
         }
         cpx<float> av[RT];
 #pragma unroll
