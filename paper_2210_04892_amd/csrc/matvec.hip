@@ -8,6 +8,8 @@
 // right-hand side.
 // Every kernel is templated on the arithmetic type T (double or float) and
 // on NR, the number of right-hand sides handled per thread (rhs chunk).
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace mlfma {
@@ -767,14 +769,46 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
                 }
             }
         }
-        for (; e < n; e++) {
-            const int v = __builtin_amdgcn_readlane(mine, e);
-            const cpx<T> t = tq[(unsigned)v >> 8];
-            const cpx<T> *p = lds + (v & 0xff) * SRC + lane;
+        // one right-hand side per lane: the remaining n - e < UNR entries in
+        // blocks of 8, 4, 2 and 1, each with all its operator loads issued
+        // before its sums (a wave has about ten entries per batch: one by one,
+        // every load latency would be exposed; padding to a full block costs
+        // redundant loads).  With several right-hand sides per lane the
+        // registers of the blocks cost more occupancy than they save.
+        auto block = [&](auto width) {
+            constexpr int NB = decltype(width)::value;
+            int v[NB];
+            cpx<T> t[NB];
 #pragma unroll
-            for (int j = 0; j < RB; j++) {
-                fma_to(a0[j], t, p[j * WAVE]);
-                fma_to(a1[j], t, p[(RB + j) * WAVE]);
+            for (int u = 0; u < NB; u++) v[u] = __builtin_amdgcn_readlane(mine, e + u);
+#pragma unroll
+            for (int u = 0; u < NB; u++) t[u] = tq[(unsigned)v[u] >> 8];
+#pragma unroll
+            for (int u = 0; u < NB; u++) {
+                const cpx<T> *p = lds + (v[u] & 0xff) * SRC + lane;
+#pragma unroll
+                for (int j = 0; j < RB; j++) {
+                    fma_to(a0[j], t[u], p[j * WAVE]);
+                    fma_to(a1[j], t[u], p[(RB + j) * WAVE]);
+                }
+            }
+            e += NB;
+        };
+        if constexpr (RW == 1) {
+            if (UNR > 8 && n - e >= 8) block(std::integral_constant<int, 8>());
+            if (UNR > 4 && n - e >= 4) block(std::integral_constant<int, 4>());
+            if (n - e >= 2) block(std::integral_constant<int, 2>());
+            if (n - e >= 1) block(std::integral_constant<int, 1>());
+        } else {
+            for (; e < n; e++) {
+                const int v = __builtin_amdgcn_readlane(mine, e);
+                const cpx<T> t = tq[(unsigned)v >> 8];
+                const cpx<T> *p = lds + (v & 0xff) * SRC + lane;
+#pragma unroll
+                for (int j = 0; j < RB; j++) {
+                    fma_to(a0[j], t, p[j * WAVE]);
+                    fma_to(a1[j], t, p[(RB + j) * WAVE]);
+                }
             }
         }
     }
