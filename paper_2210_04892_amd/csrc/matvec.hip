@@ -739,6 +739,17 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
     for (int b = b0; b < b1; b++) {
         const int ns = ld_uniform(L.bat_src, b + 1) - ld_uniform(L.bat_src, b);
         if (!PIPE) stage_load(b);
+        // this wave's entries of the batch (n <= ns <= 64), loaded before the
+        // barriers so that their latency overlaps the staging (without PIPE;
+        // with it the registers would cost occupancy)
+        int n = 0, mine = 0;
+        auto entries = [&]() {
+            const int *rw = L.row + ld_uniform(L.bat_row, b);
+            const int e0 = ld_uniform(rw, wave);
+            n = ld_uniform(rw, wave + 1) - e0;
+            mine = lane < n ? L.ent[e0 + lane] : 0;
+        };
+        if (!PIPE && wave < nt) entries();
         if (b > b0) __syncthreads();   // every wave is done with the previous batch
 #pragma unroll
         for (int i = 0; i < TRANS_ROWS; i++) {
@@ -748,9 +759,7 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
         __syncthreads();
         if (PIPE && b + 1 < b1) stage_load(b + 1);
         if (wave >= nt) continue;
-        const int *rw = L.row + ld_uniform(L.bat_row, b);
-        const int e0 = ld_uniform(rw, wave), n = ld_uniform(rw, wave + 1) - e0;   // n <= ns <= 64
-        const int mine = lane < n ? L.ent[e0 + lane] : 0;
+        if (PIPE) entries();
         int e = 0;
         for (; e + UNR <= n; e += UNR) {
             int v[UNR];
