@@ -47,6 +47,16 @@ __device__ inline void load_pair(const cpx<double> *p, cpx<double> &a, cpx<doubl
     a = p[0];
     b = p[1];
 }
+// the same for data read once (non-temporal: streamed past the caches)
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ inline void load_pair_once(const cpx<float> *p, cpx<float> &a, cpx<float> &b)
+{
+    const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
+    a = {v.x, v.y};
+    b = {v.z, v.w};
+}
+// (double pairs: plain loads measured faster)
+__device__ inline void load_pair_once(const cpx<double> *p, cpx<double> &a, cpx<double> &b) { load_pair(p, a, b); }
 
 // acc += a b (four fused multiply-adds)
 template <class T>

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void k_near_tile(int nitem, const int2 *__rest
 #pragma unroll
             for (int i = 0; i < RWV; i++) {
                 const long long o = 2 * ((long long)(i < nr ? i : nr - 1) * ncols + j);
-                load_pair(vr + o, A[c][i], B[c][i]);
+                load_pair_once(vr + o, A[c][i], B[c][i]);
             }
             const T z = j0 + c * WAVE < ncols ? T(1) : T(0);
             x1[c] = z * X[col * 2];
@@ -723,22 +723,52 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
     // are in flight while batch b is summed; with one, the registers this
     // holds would cost more occupancy than the overlap gains.
     constexpr bool PIPE = RW == 4;
+    const int S = 2 * nrhs * K;   // elements of one box's patterns
     cpx<T> st[TRANS_ROWS];
-    auto stage_load = [&](int b) {
+    // the batch's source boxes, lane i holding the i-th: one vector load per
+    // batch, issued a batch ahead, instead of a dependent scalar load per
+    // staged row
+    auto batch_sources = [&](int b) {
         const int s0 = ld_uniform(L.bat_src, b), ns = ld_uniform(L.bat_src, b + 1) - s0;
+        return lane < ns ? L.src[s0 + lane] : 0;
+    };
+    // lanes past the last sample or right-hand side stage a duplicate of a
+    // valid element: a staged element is read only by the lane that staged
+    // it, and the sums of those lanes are never stored
+    auto stage_load = [&](int b, int srcv) {
+        const int ns = ld_uniform(L.bat_src, b + 1) - ld_uniform(L.bat_src, b);
+        // every row's source is taken from srcv before the first load, so
+        // that no row waits for the loads of the rows before it
+        int src[TRANS_ROWS];
+#pragma unroll
+        for (int i = 0; i < TRANS_ROWS; i++)
+            src[i] = __builtin_amdgcn_readlane(srcv, ((wave + i * nwave) / (2 * RB)) & (WAVE - 1));
+        // the row offsets are formed where they are used, not held in
+        // registers across the batch loop: a uniform offset stays whole in
+        // scalar registers, and with several right-hand sides per lane the
+        // lane's base is taken afresh for every batch
+        int rb = rbase;
+        if constexpr (RW > 1) asm volatile("" : "+v"(rb));
 #pragma unroll
         for (int i = 0; i < TRANS_ROWS; i++) {
             const int sc = wave + i * nwave;
-            st[i] = mk<T>(0, 0);
-            const int j = sc % RB, c = (sc / RB) & 1, rr = rbase + j * RW;
-            if (sc < 2 * RB * ns && qok && rr < nrhs)
-                st[i] = Uq[pidx(ld_uniform(L.src, s0 + sc / (2 * RB)), c, rr, 0, nrhs, K)];
+            st[i] = mk<T>(0, 0);   // not carried over from the previous batch
+            if (sc < 2 * RB * ns) {
+                const int j = sc % RB, c = (sc / RB) & 1, rr = min(rb + j * RW, nrhs - 1);
+                long long off = (long long)src[i] * S + (long long)(c * nrhs + rr) * K;
+                if constexpr (RW == 1) asm volatile("" : "+s"(off));
+                st[i] = Uq[off];
+            }
         }
     };
-    if (PIPE && b0 < b1) stage_load(b0);
+    int srcv = b0 < b1 ? batch_sources(b0) : 0;
+    if (PIPE && b0 < b1) stage_load(b0, srcv);
     for (int b = b0; b < b1; b++) {
         const int ns = ld_uniform(L.bat_src, b + 1) - ld_uniform(L.bat_src, b);
-        if (!PIPE) stage_load(b);
+        if (!PIPE) {
+            stage_load(b, srcv);
+            if (b + 1 < b1) srcv = batch_sources(b + 1);   // in flight while this batch is summed
+        }
         // this wave's entries of the batch (n <= ns <= 64), loaded before the
         // barriers so that their latency overlaps the staging (without PIPE;
         // with it the registers would cost occupancy)
@@ -756,8 +786,11 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
             const int sc = wave + i * nwave;
             if (sc < 2 * RB * ns) lds[sc * WAVE + lane] = st[i];
         }
+        // with PIPE the next batch's sources are loaded here, where the
+        // staged registers are free, and arrive during the barrier
+        if (PIPE && b + 1 < b1) srcv = batch_sources(b + 1);
         __syncthreads();
-        if (PIPE && b + 1 < b1) stage_load(b + 1);
+        if (PIPE && b + 1 < b1) stage_load(b + 1, srcv);
         if (wave >= nt) continue;
         if (PIPE) entries();
         int e = 0;
