@@ -794,16 +794,36 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
         if (wave >= nt) continue;
         if (PIPE) entries();
         int e = 0;
+        // entry = (operator element offset << 8) | staged source.  With four
+        // right-hand sides per lane the batch's entries are decoded at once,
+        // as byte offsets of the operator sample and of the staged source
+        // (two vector instructions per batch instead of four scalar ones per
+        // entry); with one right-hand side per lane that measured slower
+        constexpr bool VDEC = RW == 4;
+        const unsigned opb = ((unsigned)mine >> 8) * (unsigned)sizeof(cpx<T>);
+        const unsigned ldb = (unsigned)(mine & 0xff) * (unsigned)(SRC * sizeof(cpx<T>));
+        auto op_at = [&](int i) {
+            if constexpr (VDEC)
+                return *reinterpret_cast<const cpx<T> *>(reinterpret_cast<const char *>(tq) +
+                                                         (unsigned)__builtin_amdgcn_readlane((int)opb, i));
+            else
+                return tq[(unsigned)__builtin_amdgcn_readlane(mine, i) >> 8];
+        };
+        auto src_at = [&](int i) {
+            if constexpr (VDEC)
+                return reinterpret_cast<const cpx<T> *>(reinterpret_cast<const char *>(lds + lane) +
+                                                        (unsigned)__builtin_amdgcn_readlane((int)ldb, i));
+            else
+                return lds + (__builtin_amdgcn_readlane(mine, i) & 0xff) * SRC + lane;
+        };
         for (; e + UNR <= n; e += UNR) {
-            int v[UNR];
             cpx<T> t[UNR];
 #pragma unroll
-            for (int u = 0; u < UNR; u++) v[u] = __builtin_amdgcn_readlane(mine, e + u);
-#pragma unroll
-            for (int u = 0; u < UNR; u++) t[u] = tq[(unsigned)v[u] >> 8];
+            for (int u = 0; u < UNR; u++) t[u] = op_at(e + u);
+            if constexpr (VDEC) __builtin_amdgcn_sched_barrier(0);   // every operator load issued before the sums
 #pragma unroll
             for (int u = 0; u < UNR; u++) {
-                const cpx<T> *p = lds + (v[u] & 0xff) * SRC + lane;
+                const cpx<T> *p = src_at(e + u);
 #pragma unroll
                 for (int j = 0; j < RB; j++) {
                     fma_to(a0[j], t[u], p[j * WAVE]);
@@ -819,15 +839,13 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
         // registers of the blocks cost more occupancy than they save.
         auto block = [&](auto width) {
             constexpr int NB = decltype(width)::value;
-            int v[NB];
             cpx<T> t[NB];
 #pragma unroll
-            for (int u = 0; u < NB; u++) v[u] = __builtin_amdgcn_readlane(mine, e + u);
-#pragma unroll
-            for (int u = 0; u < NB; u++) t[u] = tq[(unsigned)v[u] >> 8];
+            for (int u = 0; u < NB; u++) t[u] = op_at(e + u);
+            if constexpr (VDEC) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < NB; u++) {
-                const cpx<T> *p = lds + (v[u] & 0xff) * SRC + lane;
+                const cpx<T> *p = src_at(e + u);
 #pragma unroll
                 for (int j = 0; j < RB; j++) {
                     fma_to(a0[j], t[u], p[j * WAVE]);
@@ -843,9 +861,8 @@ __global__ __launch_bounds__(TRANS_TMAX_MAX * WAVE) void k_translate_tiled(const
             if (n - e >= 1) block(std::integral_constant<int, 1>());
         } else {
             for (; e < n; e++) {
-                const int v = __builtin_amdgcn_readlane(mine, e);
-                const cpx<T> t = tq[(unsigned)v >> 8];
-                const cpx<T> *p = lds + (v & 0xff) * SRC + lane;
+                const cpx<T> t = op_at(e);
+                const cpx<T> *p = src_at(e);
 #pragma unroll
                 for (int j = 0; j < RB; j++) {
                     fma_to(a0[j], t, p[j * WAVE]);
