@@ -1031,9 +1031,6 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     auto mark = [&](int i) {
         if (profile) HIPCHK(hipEventRecord(ev[i], st));
     };
-    mark(0);
-    launch_perm_in<T>(x, ldx, X, c->perm, N, nrhs, st);
-    mark(1);
     const Level &Lf = tr.lv[leafl];
     const int only_level = part >= MLFMA_PART_LEVEL ? part - MLFMA_PART_LEVEL : -1;
     const bool want_near = only_level < 0 && (part & MLFMA_PART_NEAR);
@@ -1044,6 +1041,14 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     // otherwise compete with, so that it shares the GPU with the
     // latency-bound level steps and translation
     const bool overlap = !profile && want_near && far && w.side;
+    // with one right-hand side and the near field after the radiation, the
+    // radiation reads x through the permutation (and stores the tree-order
+    // copy the near field reads) and the receive writes y in user order: two
+    // launches fewer on the critical path
+    const bool fold = overlap && nrhs == 1;
+    mark(0);
+    if (!fold) launch_perm_in<T>(x, ldx, X, c->perm, N, nrhs, st);
+    mark(1);
     auto near = [&](hipStream_t sn) {
         const cpx<T> *vals = op == MLFMA_OP_EM ? P.near_em : P.near_c;
         const int *ids = op == MLFMA_OP_C ? c->id_start : nullptr;
@@ -1063,7 +1068,9 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     if (!want_near) launch_zero<T>(Y, (long long)N * 2 * nrhs, st);
     else if (!overlap) near(st);
     mark(2);
-    if (far) {
+    if (fold) {
+        launch_radiate1_user<T>(op, Lf.nbox, Lf.K, c->box_start, P.R, x, c->perm, N, X, (cpx<T> *)w.U[leafl], st);
+    } else if (far) {
         bool done = false;
         if constexpr (std::is_same<T, float>::value)
             done = launch_radiate_mfma(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)w.U[leafl], nrhs, st);
@@ -1122,7 +1129,9 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     }
     mark(6);
     if (overlap) HIPCHK(hipStreamWaitEvent(st, w.join, 0));
-    if (far) {
+    if (fold) {
+        launch_receive1_user<T>(op, N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], Y, y, c->perm, st);
+    } else if (far) {
         bool done = false;
         if constexpr (std::is_same<T, float>::value)
             done = launch_receive_mfma(op, c->n_items, c->items, Lf.K, c->box_start, P.R, P.Q, P.wq,
@@ -1130,7 +1139,7 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
         if (!done) launch_receive<T>(op, N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], Y, nrhs, st);
     }
     mark(7);
-    launch_perm_out<T>(Y, y, ldy, c->iperm, N, nrhs, st);
+    if (!fold) launch_perm_out<T>(Y, y, ldy, c->iperm, N, nrhs, st);
     mark(8);
     if (profile) c->ev_pending.push_back(ev);
 }

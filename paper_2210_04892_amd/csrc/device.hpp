@@ -236,5 +236,16 @@ void launch_zero(cpx<T> *p, long long n, hipStream_t s);
 template <class T>
 void launch_receive(int op, int N, int K, const int *leaf_of, const cpx<T> *R, const cpx<T> *Q, const T *wq,
                     const cpx<T> *V, cpx<T> *Y, int nrhs, hipStream_t s);
+// One right-hand side with the permutations folded in: the radiation reads
+// the caller's vector x (user order, J half then M half) through perm (tree
+// position -> user RWG) and also stores it in tree order in X; the receive
+// adds the far field to the tree-order near field Y and writes the sum to y
+// in user order.
+template <class T>
+void launch_radiate1_user(int op, int nbox, int K, const int *box_start, const cpx<T> *R, const cpx<T> *x,
+                          const int *perm, int N, cpx<T> *X, cpx<T> *U, hipStream_t s);
+template <class T>
+void launch_receive1_user(int op, int N, int K, const int *leaf_of, const cpx<T> *R, const cpx<T> *Q, const T *wq,
+                          const cpx<T> *V, const cpx<T> *Y, cpx<T> *y, const int *perm, hipStream_t s);
 
 }  // namespace mlfma

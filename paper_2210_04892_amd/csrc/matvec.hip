@@ -372,10 +372,11 @@ __global__ __launch_bounds__(256) void k_near_rhs(int N, const int *__restrict__
 // samples), so that every lane of a wave belongs to the same box and the
 // box's coefficients are wave-uniform (scalar loads); the patterns of eight
 // RWGs (four in double precision) are loaded before they are used.
-template <class T>
+template <class T, bool PERM>
 __global__ __launch_bounds__(256) void k_radiate1(int op, int nbox, int K, int nqc, const int *__restrict__ box_start,
                                                   const cpx<T> *__restrict__ R, const cpx<T> *__restrict__ X,
-                                                  cpx<T> *__restrict__ U)
+                                                  cpx<T> *__restrict__ U, const cpx<T> *__restrict__ xu,
+                                                  const int *__restrict__ perm, int N, cpx<T> *__restrict__ Xw)
 {
     constexpr int G = sizeof(T) == 4 ? 8 : 4;
     const int lane = threadIdx.x % WAVE;
@@ -388,29 +389,57 @@ __global__ __launch_bounds__(256) void k_radiate1(int op, int nbox, int K, int n
     const int qq = qok ? q : K - 1;
     const int n0 = box_start[b], n1 = box_start[b + 1];
     cpx<T> ut = mk<T>(0, 0), up = ut;
-    for (int i0 = n0; i0 < n1; i0 += G) {
-        cpx<T> Rt[G], Rp[G], al[G], be[G];
+    // RWGs i0 .. i1 - 1, G at a time; xat(i, x1, x2) gives the coefficients
+    auto rwgs = [&](int i0, int i1, auto xat) {
+        for (int j0 = i0; j0 < i1; j0 += G) {
+            cpx<T> Rt[G], Rp[G], al[G], be[G];
 #pragma unroll
-        for (int u = 0; u < G; u++) {
-            const int i = min(i0 + u, n1 - 1);
-            load_pair(R + ((long long)i * K + qq) * 2, Rt[u], Rp[u]);
-            const cpx<T> x1 = X[(long long)i * 2], x2 = X[(long long)i * 2 + 1];
-            const T z = i0 + u < n1 ? T(1) : T(0);   // RWGs past the box contribute nothing
-            if (op == 1) {
-                al[u] = z * x1;
-                be[u] = mk<T>(-z * x2.re, -z * x2.im);
-            } else {
-                al[u] = (T(0.5) * z) * x2;
-                be[u] = (T(0.5) * z) * x1;
+            for (int u = 0; u < G; u++) {
+                const int i = min(j0 + u, i1 - 1);
+                load_pair(R + ((long long)i * K + qq) * 2, Rt[u], Rp[u]);
+                cpx<T> x1, x2;
+                xat(i, x1, x2);
+                const T z = j0 + u < i1 ? T(1) : T(0);   // RWGs past the box contribute nothing
+                if (op == 1) {
+                    al[u] = z * x1;
+                    be[u] = mk<T>(-z * x2.re, -z * x2.im);
+                } else {
+                    al[u] = (T(0.5) * z) * x2;
+                    be[u] = (T(0.5) * z) * x1;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < G; u++) {
+                fma_to(ut, al[u], Rt[u]);
+                fms_to(ut, be[u], Rp[u]);
+                fma_to(up, al[u], Rp[u]);
+                fma_to(up, be[u], Rt[u]);
             }
         }
-#pragma unroll
-        for (int u = 0; u < G; u++) {
-            fma_to(ut, al[u], Rt[u]);
-            fms_to(ut, be[u], Rp[u]);
-            fma_to(up, al[u], Rp[u]);
-            fma_to(up, be[u], Rt[u]);
+    };
+    if constexpr (PERM) {
+        // coefficients taken from the caller's vector (user order) through
+        // the permutation, 32 RWGs at a time: lane 2 r + h holds half h of
+        // RWG c0 + r and broadcasts it; the box's first sample chunk also
+        // stores them in tree order for the near field
+        for (int c0 = n0; c0 < n1; c0 += WAVE / 2) {
+            const int c1 = min(c0 + WAVE / 2, n1);
+            cpx<T> xv = mk<T>(0, 0);
+            if (lane < 2 * (c1 - c0)) {
+                xv = xu[(long long)(lane & 1) * N + perm[c0 + (lane >> 1)]];
+                if (w % nqc == 0) Xw[2LL * c0 + lane] = xv;
+            }
+            rwgs(c0, c1, [&](int i, cpx<T> &x1, cpx<T> &x2) {
+                const int l = 2 * (i - c0);
+                x1 = mk<T>(bcast(xv.re, l), bcast(xv.im, l));
+                x2 = mk<T>(bcast(xv.re, l + 1), bcast(xv.im, l + 1));
+            });
         }
+    } else {
+        rwgs(n0, n1, [&](int i, cpx<T> &x1, cpx<T> &x2) {
+            x1 = X[(long long)i * 2];
+            x2 = X[(long long)i * 2 + 1];
+        });
     }
     if (qok) {
         U[pidx(b, 0, 0, q, 1, K)] = ut;
@@ -951,11 +980,12 @@ __global__ __launch_bounds__(256) void k_disagg_mid(int nchild, int mid_len, int
 // Receive for one right-hand side: wave per RWG row, lanes over samples,
 // the row's pattern and the box's incoming pattern loaded for four chunks of
 // 64 samples (two in double precision) before they are used.
-template <class T>
+template <class T, bool PERM>
 __global__ __launch_bounds__(256) void k_receive1(int op, int N, int K, const int *__restrict__ leaf_of,
                                                   const cpx<T> *__restrict__ R, const cpx<T> *__restrict__ Q,
                                                   const T *__restrict__ wq, const cpx<T> *__restrict__ V,
-                                                  cpx<T> *__restrict__ Y)
+                                                  cpx<T> *__restrict__ Y, cpx<T> *__restrict__ yu,
+                                                  const int *__restrict__ perm)
 {
     constexpr int CH = sizeof(T) == 4 ? 4 : 2;
     const int m = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
@@ -992,8 +1022,16 @@ __global__ __launch_bounds__(256) void k_receive1(int op, int N, int K, const in
     }
     const cpx<T> s1 = wave_sum(a1), s2 = wave_sum(a2);
     if (lane == 0) {
-        Y[(long long)m * 2] = Y[(long long)m * 2] + s1;
-        Y[(long long)m * 2 + 1] = Y[(long long)m * 2 + 1] + s2;
+        const cpx<T> r1 = Y[(long long)m * 2] + s1, r2 = Y[(long long)m * 2 + 1] + s2;
+        if constexpr (PERM) {
+            // the caller's vector in user order: J half, then M half
+            const long long u = perm[m];
+            yu[u] = r1;
+            yu[N + u] = r2;
+        } else {
+            Y[(long long)m * 2] = r1;
+            Y[(long long)m * 2 + 1] = r2;
+        }
     }
 }
 
@@ -1114,8 +1152,8 @@ void launch_radiate(int op, int nbox, int K, const int *box_start, const cpx<T> 
         const int nqc = (K + WAVE - 1) / WAVE;
         const long long nw = (long long)nbox * nqc;
         if (nw > 0)
-            hipLaunchKernelGGL(k_radiate1<T>, dim3(xcd_grid((nw + 3) / 4)), dim3(256), 0, s, op, nbox, K, nqc,
-                               box_start, R, X, U);
+            hipLaunchKernelGGL((k_radiate1<T, false>), dim3(xcd_grid((nw + 3) / 4)), dim3(256), 0, s, op, nbox, K, nqc,
+                               box_start, R, X, U, nullptr, nullptr, 0, nullptr);
         return;
     }
     DISPATCH_NR(nrhs, {
@@ -1247,8 +1285,8 @@ void launch_receive(int op, int N, int K, const int *leaf_of, const cpx<T> *R, c
 {
     if (nrhs == 1) {
         if (N > 0)
-            hipLaunchKernelGGL(k_receive1<T>, dim3(blocks_for(N, 4)), dim3(256), 0, s, op, N, K, leaf_of, R, Q, wq, V,
-                               Y);
+            hipLaunchKernelGGL((k_receive1<T, false>), dim3(blocks_for(N, 4)), dim3(256), 0, s, op, N, K, leaf_of, R,
+                               Q, wq, V, Y, nullptr, nullptr);
         return;
     }
     DISPATCH_NR(nrhs, {
@@ -1257,7 +1295,31 @@ void launch_receive(int op, int N, int K, const int *leaf_of, const cpx<T> *R, c
     });
 }
 
+template <class T>
+void launch_radiate1_user(int op, int nbox, int K, const int *box_start, const cpx<T> *R, const cpx<T> *x,
+                          const int *perm, int N, cpx<T> *X, cpx<T> *U, hipStream_t s)
+{
+    const int nqc = (K + WAVE - 1) / WAVE;
+    const long long nw = (long long)nbox * nqc;
+    if (nw > 0)
+        hipLaunchKernelGGL((k_radiate1<T, true>), dim3(xcd_grid((nw + 3) / 4)), dim3(256), 0, s, op, nbox, K, nqc,
+                           box_start, R, (const cpx<T> *)nullptr, U, x, perm, N, X);
+}
+
+template <class T>
+void launch_receive1_user(int op, int N, int K, const int *leaf_of, const cpx<T> *R, const cpx<T> *Q, const T *wq,
+                          const cpx<T> *V, const cpx<T> *Y, cpx<T> *y, const int *perm, hipStream_t s)
+{
+    if (N > 0)
+        hipLaunchKernelGGL((k_receive1<T, true>), dim3(blocks_for(N, 4)), dim3(256), 0, s, op, N, K, leaf_of, R, Q,
+                           wq, V, const_cast<cpx<T> *>(Y), y, perm);
+}
+
 #define INSTANTIATE(T)                                                                                              \
+    template void launch_radiate1_user<T>(int, int, int, const int *, const cpx<T> *, const cpx<T> *, const int *, \
+                                          int, cpx<T> *, cpx<T> *, hipStream_t);                                  \
+    template void launch_receive1_user<T>(int, int, int, const int *, const cpx<T> *, const cpx<T> *, const T *,  \
+                                          const cpx<T> *, const cpx<T> *, cpx<T> *, const int *, hipStream_t);    \
     template void launch_perm_in<T>(const cpx<T> *, long long, cpx<T> *, const int *, int, int, hipStream_t);     \
     template void launch_perm_out<T>(const cpx<T> *, cpx<T> *, long long, const int *, int, int, hipStream_t);    \
     template void launch_near_tile<T>(int, const int2 *, const int *, const int *, const int *, const long long *, \
