@@ -244,15 +244,36 @@ __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__rest
     };
     f4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
     cpx<float> a, bv, an, bn;
-    load(0, a, bv);
-    for (int j0 = 0; j0 < ncols; j0 += 2) {
-        if (j0 + 2 < ncols) load(j0 + 2, an, bn);
+    auto step = [&]() {
         dre = mfma4(a.re, bv.re, dre);
         dim = mfma4(a.re, bv.im, dim);
         dre = mfma4(-a.im, bv.im, dre);
         dim = mfma4(a.im, bv.re, dim);
         a = an;
         bv = bn;
+    };
+    load(0, a, bv);
+    int j0 = 0;
+    // steps whose successor lies wholly inside the row: the successor's
+    // operands without predicates (rows past the tile and right-hand sides
+    // past nrhs read clamped, valid elements; only their own outputs, which
+    // are never stored, see them)
+    const int rc = rok ? r : 0;
+    for (; j0 + 4 <= ncols; j0 += 2) {
+        const int j = j0 + 2 + jc;
+        if (j0 + 2 >= cbase + 64) {
+            cbase = j0 + 2;
+            myc = cl[min(cbase + lane, ncols - 1)];
+        }
+        const int col = __shfl(myc, j - cbase);
+        const cpx<float> v = vr[2 * j + vsel];
+        an = mk<float>(vsg * v.re, vsg * v.im);
+        bn = X[((long long)col * 2 + hp) * nrhs + rc];
+        step();
+    }
+    for (; j0 < ncols; j0 += 2) {
+        if (j0 + 2 < ncols) load(j0 + 2, an, bn);
+        step();
     }
 #pragma unroll
     for (int v = 0; v < 4; v++) {
