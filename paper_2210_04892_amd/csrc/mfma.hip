@@ -83,7 +83,24 @@ __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, i
     f4 dre[RT], dim[RT];
 #pragma unroll
     for (int u = 0; u < RT; u++) dre[u] = dim[u] = f4{0, 0, 0, 0};
-    for (int n = n0; n < n1; n += 2) {
+    int n = n0;
+    // steps with both RWGs inside the box: operands without predicates
+    // (samples past K and right-hand sides past nrhs read clamped, valid
+    // elements; only their own outputs, which are never stored, see them)
+    const int qq = qok ? q : K - 1;
+    for (; n + 1 < n1; n += 2) {
+        const int nn = n + (kk >> 1);
+        const cpx<float> v = R[((long long)nn * K + qq) * 2 + rcomp];
+        const cpx<float> bv = mk<float>(rsg * v.re, rsg * v.im);
+        cpx<float> av[RT];
+#pragma unroll
+        for (int u = 0; u < RT; u++) {
+            const int r = min((rg * RT + u) * 16 + lo, nrhs - 1);
+            av[u] = fac * X[((long long)nn * 2 + h) * nrhs + r];
+        }
+        cmfma<RT>(dre, dim, av, bv);
+    }
+    for (; n < n1; n += 2) {
         const int nn = n + (kk >> 1);
         const bool nok = nn < n1;
         cpx<float> bv = mk<float>(0, 0);
@@ -163,7 +180,25 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
         };
         cpx<float> a, bv, an, bn;
         load(0, a, bv);
-        for (int qs = 0; qs < kq; qs++) {
+        int qs = 0;
+        // steps whose successor has all four samples inside K: its operands
+        // without predicates (rows past the tile and right-hand sides past
+        // nrhs read clamped, valid elements; only their own outputs, which
+        // are never stored, see them)
+        for (; qs + 1 < K / 4; qs++) {
+            const int q = (qs + 1) * 4 + kk;
+            cpx<float> p = pm[2 * q + comp];
+            if (cj) p = conjg(p);
+            an = (sg * wq[q]) * p;
+            bn = vc[q];
+            dre = mfma4(a.re, bv.re, dre);
+            dim = mfma4(a.re, bv.im, dim);
+            dre = mfma4(-a.im, bv.im, dre);
+            dim = mfma4(a.im, bv.re, dim);
+            a = an;
+            bv = bn;
+        }
+        for (; qs < kq; qs++) {
             if (qs + 1 < kq) load(qs + 1, an, bn);
             dre = mfma4(a.re, bv.re, dre);
             dim = mfma4(a.re, bv.im, dim);
