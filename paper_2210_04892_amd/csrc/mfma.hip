@@ -182,14 +182,17 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
         load(0, a, bv);
         int qs = 0;
         // steps whose successor has all four samples inside K: its operands
-        // without predicates (rows past the tile and right-hand sides past
-        // nrhs read clamped, valid elements; only their own outputs, which
-        // are never stored, see them)
+        // without sample predicates (right-hand sides past nrhs read clamped,
+        // valid elements; only their own outputs, which are never stored,
+        // see them)
         for (; qs + 1 < K / 4; qs++) {
             const int q = (qs + 1) * 4 + kk;
-            cpx<float> p = pm[2 * q + comp];
-            if (cj) p = conjg(p);
-            an = (sg * wq[q]) * p;
+            an = mk<float>(0, 0);
+            if (mok) {   // rows past the tile: no loads (fewer requests for small boxes)
+                cpx<float> p = pm[2 * q + comp];
+                if (cj) p = conjg(p);
+                an = (sg * wq[q]) * p;
+            }
             bn = vc[q];
             dre = mfma4(a.re, bv.re, dre);
             dim = mfma4(a.re, bv.im, dim);
