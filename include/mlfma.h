@@ -278,6 +278,51 @@ int mlfma_gmres_precond(mlfma_handle h, int op, int dtype, long long nrhs, const
                         long long ldx, int restart, int max_iters, double tol, int precond, int *iters,
                         double *relres, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Hybrid product of the reduced system (Sec. II-E "Hybrid Solver", eq. 52):
+ *   y = (C - D^{X Lambda} Q^{-1} D^{Lambda X}) x,
+ * steps 2(a)-(e) of the hybrid solver's matrix-vector subroutine: (a) y_d =
+ * C x by MLFMA (mlfma_matvec_LK, op C), (b) x1 = D^{Lambda X} x, (c) x2 =
+ * Q^{-1} x1 by the caller's solve (the paper factorises the sparse HDG
+ * block Q once with a sparse direct solver; here the caller supplies that
+ * solve), (d) y_s = -D^{X Lambda} x2, (e) y = y_d + y_s.  D^{Lambda X}
+ * (n_hdg x 2N) and D^{X Lambda} (2N x n_hdg) are the sparse couplings of
+ * eq. 51 between the HDG unknowns Lambda and the BI unknowns X = [J; M]
+ * (rows / columns in the RWG order of the vectors, J then M).
+ *
+ * mlfma_hybrid_create: host CSR arrays (copied to the device, values kept
+ *   in complex128 and complex64): *_ptr (rows + 1 int64, ptr[0] = 0,
+ *   non-decreasing), *_col (int32 column indices), *_val (complex128
+ *   values, interleaved re/im).  solve(user, dtype, n, nrhs, b, ldb, xq,
+ *   ldxq, hip_stream) must write xq = Q^{-1} b for the n x nrhs
+ *   column-major DEVICE blocks it is given (complex128 or complex64 by
+ *   dtype), ordered after the work enqueued on hip_stream, and return 0 (a
+ *   non-zero return fails the product with MLFMA_ERR_ARG).  b and xq are
+ *   always the caller's buffers buf1 and buf2 (device, ldbuf >= n_hdg,
+ *   room for max_rhs columns of complex128; owned by the caller, alive as
+ *   long as the operator).  The handle must outlive the operator.
+ * mlfma_hybrid_matvec: arguments and asynchrony of mlfma_matvec_LK (op C
+ *   implied), nrhs <= max_rhs.
+ * mlfma_hybrid_gmres: mlfma_gmres_precond on the reduced operator (the SAI
+ *   preconditioner, when asked for, is the one built from C alone).
+ * Errors: MLFMA_ERR_ARG (bad CSR, sizes or pointers), MLFMA_ERR_OOM,
+ *   MLFMA_ERR_HIP, and those of the product.
+ * ------------------------------------------------------------------------ */
+typedef int (*mlfma_qsolve_fn)(void *user, int dtype, long long n, long long nrhs, const void *b, long long ldb,
+                               void *xq, long long ldxq, void *hip_stream);
+typedef struct mlfma_hybrid_s *mlfma_hybrid;
+int mlfma_hybrid_create(mlfma_handle h, long long n_hdg, const long long *dlx_ptr, const int *dlx_col,
+                        const double *dlx_val, const long long *dxl_ptr, const int *dxl_col, const double *dxl_val,
+                        mlfma_qsolve_fn solve, void *user, void *buf1, void *buf2, long long ldbuf,
+                        long long max_rhs, mlfma_hybrid *out);
+int mlfma_hybrid_matvec(mlfma_hybrid hy, int dtype, long long nrhs, const void *x, long long ldx, void *y,
+                        long long ldy, void *hip_stream);
+int mlfma_hybrid_gmres(mlfma_hybrid hy, int dtype, long long nrhs, const void *b, long long ldb, void *x,
+                       long long ldx, int restart, int max_iters, double tol, int precond, int *iters,
+                       double *relres, void *hip_stream);
+/* NULL accepted; waits for the device. */
+int mlfma_hybrid_destroy(mlfma_hybrid hy);
+
 typedef struct mlfma_server_s *mlfma_server;
 typedef struct {
     int streams;                          /* launch slots (1..16, default 4)      */
@@ -290,9 +335,13 @@ typedef struct {
 } mlfma_server_opts;
 int mlfma_server_opts_default(mlfma_server_opts *opt);
 int mlfma_server_create(const mlfma_server_opts *opt, mlfma_server *out);
-/* Enqueue y = A x (arguments as mlfma_matvec_LK); *ticket identifies it. */
+/* Enqueue y = A x (arguments as mlfma_matvec_LK); *ticket identifies it.
+ * The server reads x and writes y only after the work enqueued on hip_stream
+ * (the caller's stream, NULL = default stream) before this call: an x that
+ * the caller has just computed on its stream is used as computed.
+ * MLFMA_ERR_STATE while the server is being destroyed. */
 int mlfma_server_submit(mlfma_server s, mlfma_handle h, int op, int dtype, long long nrhs, const void *x,
-                        long long ldx, void *y, long long ldy, long long *ticket);
+                        long long ldx, void *y, long long ldy, void *hip_stream, long long *ticket);
 /* Wait for a ticket (timeout_s < 0: forever).  On return y is complete;
  * *latency_s = completion - submission (seconds), *batch_rhs = columns of the
  * product it ran in (either pointer may be NULL).  MLFMA_ERR_STATE on timeout
@@ -301,7 +350,10 @@ int mlfma_server_wait(mlfma_server s, long long ticket, double timeout_s, double
 /* out[0..4] = {products launched, requests served, arena bytes, queued
  * requests, products captured as graphs} */
 int mlfma_server_stats(mlfma_server s, long long out[5]);
-/* Stop the threads (queued requests are dropped), free slots.  NULL accepted. */
+/* Stop the threads and free the slots.  Requests still queued or running
+ * fail with MLFMA_ERR_STATE (their buffers are no longer touched once this
+ * returns); threads blocked in mlfma_server_wait return before the server is
+ * freed.  No call on s may start once destroy has begun.  NULL accepted. */
 int mlfma_server_destroy(mlfma_server s);
 
 /* Free every device and host resource of the handle.  NULL is accepted. */
@@ -346,6 +398,19 @@ int mlfma_tuning(mlfma_handle h, int dtype, int shape[3], double *ms);
 enum { MLFMA_STAGES = 8 };
 int mlfma_profile(mlfma_handle h, int enable);
 int mlfma_profile_read(mlfma_handle h, double ms[8], long long *calls);
+
+/*
+ * Machine ceilings measured on the device (diagnostic; allocates and frees
+ * its own buffers, synchronous): kind 0 = HBM bandwidth of a plain 1 GiB
+ * copy in GB/s (read + write bytes), kind 1 = FP32 matrix-core rate of
+ * v_mfma_f32_16x16x4f32 in TFLOP/s, kind 2 = FP32 vector fused
+ * multiply-add rate (non-packed instructions, as the library's kernels are
+ * built) in TFLOP/s.  device < 0: the current device.  These are the
+ * measured ceilings beside the published ones that the stages' roofline
+ * fractions are stated against.  Errors: MLFMA_ERR_ARG, MLFMA_ERR_OOM,
+ * MLFMA_ERR_HIP (mlfma_last_error is not set).
+ */
+int mlfma_peak_probe(int kind, int device, double *value);
 
 /* Text of the last error of the calling thread ("" if none). */
 const char *mlfma_last_error(void);

@@ -551,6 +551,300 @@ static int pair_integrals_auto(const int ti[3], const double P[3][3], const int 
     return -1;   /* not converged at order 48: result kept, caller is told */
 }
 
+/* ---------------------------------- touching pairs: singularity subtraction */
+/*
+ * Second, independent route for pairs that share a vertex, an edge or the
+ * whole triangle.  The kernels are split into closed-form static parts and
+ * smooth remainders (Taylor series of exp(-jkR) about R = 0):
+ *
+ *   G  = (1/4pi) [ R^-1 - (k^2/2) R + (k^4/24) R^3 ] + G_r
+ *   g1 = -(1/4pi) [ R^-3 + (k^2/2) R^-1 - (k^4/8) R + (k^6/144) R^3 ] + g1_r
+ *
+ * (grad_x G = g1 (x - y); the parts removed are every odd power of R up to
+ * R^3, so G_r and g1_r (x - y) are C^4 and C^5 at R = 0).  For a test point
+ * x the source-triangle integrals of the static parts are closed forms of
+ * the flat triangle (line integrals K_n = Int_edge R^n by their recursion,
+ * surface integrals I_n = Int R^n and the vectors W_n = Int (y - x) R^n by
+ * the divergence theorem in the plane of the triangle; Wilton et al. 1984,
+ * Graglia 1993), the remainders are integrated by a Gauss product rule over
+ * the source triangle.  Every operator of a triangle pair then needs only
+ *   S0 = Int G,  S1 = Int (y - x) G,  V = Int g1 (x - y)  (= grad_x S0)
+ * at the test point, because with b = y - q_j:
+ *   Int b G = S1 + (x - q_j) S0,   Int grad G x b = V x (x - q_j).
+ * The test-triangle integral uses Gauss rules on geometrically graded
+ * intervals of sweep coordinates x = (1-h)(B0 + s (B1 - B0)) + h C, graded
+ * towards the set the pair shares (the whole boundary for the coincident
+ * pair, split into three sweeps from its edges to the centroid; the shared
+ * edge; the shared vertex), where the static parts are not smooth.
+ */
+
+/* Closed-form integrals over the flat triangle Q for the point x:
+ *   I[0..2] = Int R^-1, Int R, Int R^3
+ *   W[0..3] = Int (y - x) R^n, n = -3 (principal value), -1, 1, 3. */
+static void static_integrals(const double Q[3][3], const double *x, double In[3], double W[4][3])
+{
+    double e1[3], e2[3], nn[3];
+    vsub(Q[1], Q[0], e1);
+    vsub(Q[2], Q[0], e2);
+    vcross(e1, e2, nn);
+    double nl = vnorm(nn);
+    for (int c = 0; c < 3; c++) nn[c] /= nl;
+    double d[3];
+    vsub(x, Q[0], d);
+    const double h = vdot(d, nn), ah = fabs(h);
+    double rho[3];
+    for (int c = 0; c < 3; c++) rho[c] = x[c] - h * nn[c];
+    double omega = 0, st_m1 = 0, st_1 = 0, st_3 = 0;
+    double Mm1[3] = {0, 0, 0}, M1[3] = {0, 0, 0}, M3[3] = {0, 0, 0}, M5[3] = {0, 0, 0};
+    for (int i = 0; i < 3; i++) {
+        const double *A = Q[i], *B = Q[(i + 1) % 3];
+        double l[3], m[3], ar[3], br[3];
+        vsub(B, A, l);
+        double len = vnorm(l);
+        for (int c = 0; c < 3; c++) l[c] /= len;
+        vcross(l, nn, m);                       /* outward in-plane normal of the edge */
+        vsub(A, rho, ar);
+        vsub(B, rho, br);
+        const double t0 = vdot(ar, m), lm = vdot(ar, l), lp = vdot(br, l);
+        const double R0sq = t0 * t0 + h * h;
+        const double Rm = sqrt(lm * lm + R0sq), Rp = sqrt(lp * lp + R0sq);
+        double Km1;
+        if (lm >= 0) Km1 = log((Rp + lp) / (Rm + lm));
+        else if (lp <= 0) Km1 = log((Rm - lm) / (Rp - lp));
+        else Km1 = log((Rp + lp) * (Rm - lm) / R0sq);     /* projection inside the edge */
+        const double R0K = R0sq > 0 ? R0sq * Km1 : 0.0;
+        const double K1 = 0.5 * (R0K + lp * Rp - lm * Rm);
+        const double K3 = 0.25 * (3.0 * R0sq * K1 + lp * Rp * Rp * Rp - lm * Rm * Rm * Rm);
+        const double K5 = (5.0 * R0sq * K3 + lp * pow(Rp, 5) - lm * pow(Rm, 5)) / 6.0;
+        if (t0 != 0) {
+            omega += atan(t0 * lp / (R0sq + ah * Rp)) - atan(t0 * lm / (R0sq + ah * Rm));
+            st_m1 += t0 * Km1;
+        }
+        st_1 += t0 * K1;
+        st_3 += t0 * K3;
+        for (int c = 0; c < 3; c++) {
+            if (R0sq > 0 || !(lm < 0 && lp > 0)) Mm1[c] += m[c] * Km1;
+            M1[c] += m[c] * K1;
+            M3[c] += m[c] * K3;
+            M5[c] += m[c] * K5;
+        }
+    }
+    const double Im1 = st_m1 - ah * omega;
+    const double I1 = (h * h * Im1 + st_1) / 3.0;
+    const double I3 = (3.0 * h * h * I1 + st_3) / 5.0;
+    const double sg = h > 0 ? 1.0 : (h < 0 ? -1.0 : 0.0);
+    In[0] = Im1;
+    In[1] = I1;
+    In[2] = I3;
+    for (int c = 0; c < 3; c++) {
+        W[0][c] = -Mm1[c] - sg * omega * nn[c];
+        W[1][c] = M1[c] - h * nn[c] * Im1;
+        W[2][c] = M3[c] / 3.0 - h * nn[c] * I1;
+        W[3][c] = M5[c] / 5.0 - h * nn[c] * I3;
+    }
+}
+
+/* Remainders G_r(R) and g1_r(R) of the split above. */
+static void kernel_remainder(double k, double R, cplx *Gr, cplx *g1r)
+{
+    const double f = 1.0 / (4.0 * M_PI);
+    if (k * R < 2.0) {
+        /* G = f sum (-jk)^n R^(n-1) / n!,  g1 = -f sum (-jk)^n (1-n)/n! R^(n-3),
+         * without the terms n = 0, 2, 4 (G) and n = 0, 2, 4, 6 (g1) */
+        cplx term = 1.0;     /* (-jk)^n / n! */
+        cplx sG = 0, sg = 0;
+        double Rp = 1.0 / (R * R * R);   /* R^(n-3) */
+        for (int n = 0; n <= 60; n++) {
+            if (n != 0 && n != 2 && n != 4) sG += term * Rp * R * R;
+            if (n != 0 && n != 2 && n != 4 && n != 6) sg += term * (1.0 - n) * Rp;
+            term *= -I * k / (n + 1);
+            Rp *= R;
+            if (n > 10 && cabs(term) * Rp * R * R < 1e-30) break;
+        }
+        *Gr = f * sG;
+        *g1r = -f * sg;
+    } else {
+        const double k2 = k * k, k4 = k2 * k2, k6 = k4 * k2, R3 = R * R * R;
+        cplx e = cexp(-I * k * R);
+        *Gr = f * e / R - f * (1.0 / R - 0.5 * k2 * R + k4 / 24.0 * R3);
+        *g1r = -f * (1.0 + I * k * R) * e / R3 + f * (1.0 / R3 + 0.5 * k2 / R - k4 / 8.0 * R + k6 / 144.0 * R3);
+    }
+}
+
+/* Collapsed Gauss-Legendre product rule with n x n points on Q (exact for
+ * polynomials of degree 2n - 2); returns the point count. */
+static int tri_gauss_rule(const double Q[3][3], int n, double (*pts)[3], double *wts)
+{
+    double gx[64], gw[64];
+    gauss01(n, gx, gw);
+    double e1[3], e2[3], c[3];
+    vsub(Q[1], Q[0], e1);
+    vsub(Q[2], Q[0], e2);
+    vcross(e1, e2, c);
+    const double A2 = vnorm(c);
+    int np = 0;
+    for (int a = 0; a < n; a++)
+        for (int b = 0; b < n; b++) {
+            const double u = gx[a], v = gx[b];
+            const double l1 = u * (1 - v), l2 = u * v;
+            for (int cc = 0; cc < 3; cc++) pts[np][cc] = Q[0][cc] + l1 * e1[cc] + l2 * e2[cc];
+            wts[np] = gw[a] * gw[b] * u * A2;
+            np++;
+        }
+    return np;
+}
+
+/* Gauss rule on [0,1] over geometrically graded intervals: side 0 grades
+ * towards 0, side 1 towards 1, side 2 towards both ends (halves), side 3 is
+ * no grading (levels equal intervals).  Ratio sigma between neighbouring
+ * interval lengths, n points each.  Returns the point count. */
+static int graded_rule(int side, double sigma, int levels, int n, double *x, double *w)
+{
+    double gx[64], gw[64];
+    gauss01(n, gx, gw);
+    int np = 0;
+    double br[130];
+    int nb = 0;
+    if (side == 3) {
+        for (int i = 0; i <= levels; i++) br[nb++] = (double)i / levels;
+    } else {
+        const double span = side == 2 ? 0.5 : 1.0;
+        double tmp[66];
+        int nt = 0;
+        tmp[nt++] = 0.0;
+        for (int i = levels; i >= 1; i--) tmp[nt++] = span * pow(sigma, i);
+        tmp[nt++] = span;
+        if (side == 0 || side == 2) for (int i = 0; i < nt; i++) br[nb++] = tmp[i];
+        if (side == 1) for (int i = nt - 1; i >= 0; i--) br[nb++] = 1.0 - tmp[i];
+        if (side == 2) for (int i = nt - 2; i >= 0; i--) br[nb++] = 1.0 - tmp[i];
+    }
+    for (int b = 0; b + 1 < nb; b++) {
+        const double a0 = br[b], len = br[b + 1] - br[b];
+        if (len <= 0) continue;
+        for (int i = 0; i < n; i++) {
+            x[np] = a0 + len * gx[i];
+            w[np] = len * gw[i];
+            np++;
+        }
+    }
+    return np;
+}
+
+/* Test-triangle rule: grading ratio sigma; towards the singular edge or
+ * vertex (sweep coordinate h) `levels` intervals of n points; along the
+ * sweep base (s) s_levels intervals towards each graded end of n_s points;
+ * n_inner x n_inner points for the remainders on the source triangle. */
+typedef struct { double sigma; int levels, n, n_inner, n_s, s_levels; } subtract_opts;
+
+/* Accumulate the four operators' integrands at the test point x with weight
+ * wt (local edges as in accumulate(): a = x - P_i, b = y - Q_j). */
+static void accumulate_sub(const double *x, const double P[3][3], const double Q[3][3], const double *nt, double k,
+                           double wt, int n_inner, cplx out[4][3][3])
+{
+    double Is[3], Ws[4][3];
+    static_integrals(Q, x, Is, Ws);
+    const double f = 1.0 / (4.0 * M_PI), k2 = k * k, k4 = k2 * k2, k6 = k4 * k2;
+    cplx S0 = f * (Is[0] - 0.5 * k2 * Is[1] + k4 / 24.0 * Is[2]);
+    cplx S1[3], V[3];
+    for (int c = 0; c < 3; c++) {
+        S1[c] = f * (Ws[1][c] - 0.5 * k2 * Ws[2][c] + k4 / 24.0 * Ws[3][c]);
+        V[c] = f * (Ws[0][c] + 0.5 * k2 * Ws[1][c] - k4 / 8.0 * Ws[2][c] + k6 / 144.0 * Ws[3][c]);
+    }
+    /* smooth remainders by the Gauss rule on Q */
+    double pts[64 * 64][3], wts[64 * 64];
+    const int np = tri_gauss_rule(Q, n_inner, pts, wts);
+    for (int q = 0; q < np; q++) {
+        double d[3];
+        vsub(pts[q], x, d);                   /* y - x */
+        const double R = vnorm(d);
+        cplx Gr, g1r;
+        kernel_remainder(k, R, &Gr, &g1r);
+        S0 += wts[q] * Gr;
+        for (int c = 0; c < 3; c++) {
+            S1[c] += wts[q] * d[c] * Gr;
+            V[c] -= wts[q] * d[c] * g1r;       /* g1 (x - y) */
+        }
+    }
+    for (int i = 0; i < 3; i++) {
+        double a[3], g[3];
+        vsub(x, P[i], a);
+        vcross(nt, a, g);
+        for (int j = 0; j < 3; j++) {
+            double xq[3];
+            vsub(x, Q[j], xq);
+            cplx Bv[3], VxC[3];
+            for (int c = 0; c < 3; c++) Bv[c] = S1[c] + xq[c] * S0;           /* Int b G */
+            VxC[0] = V[1] * xq[2] - V[2] * xq[1];                              /* Int grad G x b */
+            VxC[1] = V[2] * xq[0] - V[0] * xq[2];
+            VxC[2] = V[0] * xq[1] - V[1] * xq[0];
+            const cplx aB = a[0] * Bv[0] + a[1] * Bv[1] + a[2] * Bv[2];
+            const cplx gB = g[0] * Bv[0] + g[1] * Bv[1] + g[2] * Bv[2];
+            const cplx gV = g[0] * V[0] + g[1] * V[1] + g[2] * V[2];
+            const cplx aX = a[0] * VxC[0] + a[1] * VxC[1] + a[2] * VxC[2];
+            const cplx gX = g[0] * VxC[0] + g[1] * VxC[1] + g[2] * VxC[2];
+            out[0][i][j] += wt * (-I * k) * (aB - 4.0 / k2 * S0);
+            out[1][i][j] += wt * aX;
+            out[2][i][j] += wt * -(-I * k * gB - (2.0 * I / k) * gV);
+            out[3][i][j] += wt * -gX;
+        }
+    }
+}
+
+/* Test-triangle integral over the sweep of base B0 -> B1 to apex C with the
+ * given grading of s (along the base) and h (towards the apex). */
+static void sweep_sub(const double B0[3], const double B1[3], const double C[3], int sside, int hside,
+                      const subtract_opts *o, const double P[3][3], const double Q[3][3], const double *nt, double k,
+                      cplx out[4][3][3])
+{
+    double sx[2048], sw[2048], hx[2048], hw[2048];
+    /* the vertex sweep is smooth along its base: two plain intervals */
+    const int ns = sside == 3 ? graded_rule(3, 0, 2, o->n_s, sx, sw)
+                              : graded_rule(sside, o->sigma, o->s_levels, o->n_s, sx, sw);
+    const int nh = graded_rule(hside, o->sigma, o->levels, o->n, hx, hw);
+    double e1[3], e2[3], c[3];
+    vsub(B1, B0, e1);
+    vsub(C, B0, e2);
+    vcross(e1, e2, c);
+    const double A2 = vnorm(c);               /* twice the sweep's area */
+    for (int a = 0; a < ns; a++)
+        for (int b = 0; b < nh; b++) {
+            const double s = sx[a], h = hx[b];
+            double x[3];
+            for (int cc = 0; cc < 3; cc++) x[cc] = (1 - h) * (B0[cc] + s * e1[cc]) + h * C[cc];
+            accumulate_sub(x, P, Q, nt, k, sw[a] * hw[b] * (1 - h) * A2, o->n_inner, out);
+        }
+}
+
+/* Defaults of the second route: agreement with the first route to about
+ * 1e-13 of the pair's largest entry on the pins' meshes. */
+static const subtract_opts SUB_DEFAULT = {0.35, 24, 10, 6, 8, 12};
+
+/* T, K, Tx, Kx of a touching pair (caller's vertex order, as pair_integrals). */
+static void pair_integrals_sub(const int ti[3], const double P[3][3], const int si[3], const double Q[3][3],
+                               const double *nt, double k, const subtract_opts *o, cplx out[4][3][3])
+{
+    memset(out, 0, sizeof(cplx) * 36);
+    int shared = 0, sp[3], sq[3];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            if (ti[i] == si[j]) { sp[shared] = i; sq[shared] = j; shared++; }
+    (void)sq;
+    if (shared == 3) {
+        double cen[3];
+        for (int c = 0; c < 3; c++) cen[c] = (P[0][c] + P[1][c] + P[2][c]) / 3.0;
+        for (int e = 0; e < 3; e++) sweep_sub(P[e], P[(e + 1) % 3], cen, 2, 0, o, P, Q, nt, k, out);
+        /* K and Kx vanish on a flat triangle (see pair_coincident) */
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) { out[1][i][j] = 0; out[3][i][j] = 0; }
+    } else if (shared == 2) {
+        const int third = 3 - sp[0] - sp[1];
+        sweep_sub(P[sp[0]], P[sp[1]], P[third], 2, 0, o, P, Q, nt, k, out);
+    } else if (shared == 1) {
+        const int v = sp[0];
+        sweep_sub(P[(v + 1) % 3], P[(v + 2) % 3], P[v], 3, 1, o, P, Q, nt, k, out);
+    }
+}
+
 /* ------------------------------------------------------------- box rule */
 /* Leaf box of every RWG (centre = edge midpoint): root cube centred on the
  * vertex bounding box, edge leaf * 2^(levels-1), levels = ceil(log2(extent /
@@ -641,6 +935,32 @@ int oracle_pair(const int *ti, const double *P, const int *si, const double *Q, 
     return used;
 }
 
+/* Raw local integrals of one touching pair by singularity subtraction
+ * (the second route); params = {sigma, levels, n, n_inner, n_s}. */
+int oracle_pair_sub(const int *ti, const double *P, const int *si, const double *Q, double k, const double *params,
+                    double *out)
+{
+    subtract_opts o = {params[0], (int)params[1], (int)params[2], (int)params[3], (int)params[4], (int)params[5]};
+    if (o.n < 1 || o.n > 64 || o.n_inner < 1 || o.n_inner > 64 || o.levels < 1 || o.levels > 60 || o.n_s < 1 ||
+        o.n_s > 64 || o.s_levels < 1 || o.s_levels > 60 || (o.levels + 2) * 2 * o.n > 2048 ||
+        (o.s_levels + 2) * 2 * o.n_s > 2048 || !(o.sigma > 0 && o.sigma < 1))
+        return ORC_ERR_ARG;
+    double Pm[3][3], Qm[3][3], nt[3];
+    memcpy(Pm, P, sizeof(Pm));
+    memcpy(Qm, Q, sizeof(Qm));
+    double e1[3], e2[3], c[3];
+    vsub(Pm[1], Pm[0], e1); vsub(Pm[2], Pm[0], e2); vcross(e1, e2, c);
+    double a2 = vnorm(c);
+    for (int i = 0; i < 3; i++) nt[i] = c[i] / a2;
+    cplx o4[4][3][3];
+    pair_integrals_sub(ti, Pm, si, Qm, nt, k, &o, o4);
+    for (int q = 0; q < 36; q++) {
+        out[2 * q] = creal(((cplx *)o4)[q]);
+        out[2 * q + 1] = cimag(((cplx *)o4)[q]);
+    }
+    return ORC_OK;
+}
+
 /*
  * Dense Galerkin products, by classes.
  *   x    : 2N x nrhs column-major complex (interleaved), rows [0,N) = J
@@ -656,14 +976,17 @@ int oracle_pair(const int *ti, const double *P, const int *si, const double *Q, 
  *          8 = both 0 and 1 (y then holds 2*ncls blocks: op C, then op EM).
  *   leaf : leaf box edge (> 0 enables classes: class 0 = near, class l =
  *          interaction level l; ncls must be >= levels), or <= 0 (ncls = 1).
- *   nq   : Gauss order per dimension for touching pairs, or 0 for the
- *          order search of pair_integrals_auto (the default).
+ *   nq   : Gauss order per dimension for touching pairs, 0 for the order
+ *          search of pair_integrals_auto (the default), or -1 for the
+ *          second route (singularity subtraction, pair_integrals_sub).
+ *   Source triangles on which every RWG coefficient of x is zero add
+ *   nothing and are skipped.
  *   Returns ORC_ERR_QUAD if some touching pair did not converge.
  */
 int oracle_matvec(int nv, const double *v, int nt, const int *t, double k, int op, int nrhs,
                   const double *x_in, const int *rows, int nrows, double *y_out, double leaf, int ncls, int nq)
 {
-    if (nrhs < 1 || k <= 0 || nq < 0 || nq > 64 || op < 0 || op > 8) return ORC_ERR_ARG;
+    if (nrhs < 1 || k <= 0 || nq < -1 || nq > 64 || op < 0 || op > 8) return ORC_ERR_ARG;
     int quad_fail = 0;
     mesh_t m;
     int rc = mesh_build(&m, nv, v, nt, t);
@@ -691,6 +1014,14 @@ int oracle_matvec(int nv, const double *v, int nt, const int *t, double k, int o
     char *need = calloc(nt, 1);
     for (int r = 0; r < N; r++)
         if (outpos[r] >= 0) { need[m.tp[r]] = 1; need[m.tm[r]] = 1; }
+    /* source triangles that carry a non-zero coefficient */
+    char *active = calloc(nt, 1);
+    for (int r = 0; r < N; r++) {
+        int nz = 0;
+        for (int h = 0; h < 2 && !nz; h++)
+            for (int q = 0; q < nrhs && !nz; q++) nz = x[(size_t)q * 2 * N + (size_t)h * N + r] != 0;
+        if (nz) { active[m.tp[r]] = 1; active[m.tm[r]] = 1; }
+    }
 
     /* per output row: acc[cls][opnd(4)][xhalf(2)][rhs] -- gathered per test
      * triangle, then combined into y.  Work per test triangle is private. */
@@ -713,6 +1044,7 @@ int oracle_matvec(int nv, const double *v, int nt, const int *t, double k, int o
                 for (int c = 0; c < 3; c++) P[a][c] = v[3 * tv[a] + c];
             }
             for (int si = 0; si < nt; si++) {
+                if (!active[si]) continue;
                 double Q[3][3];
                 int sv[3];
                 for (int a = 0; a < 3; a++) {
@@ -720,7 +1052,11 @@ int oracle_matvec(int nv, const double *v, int nt, const int *t, double k, int o
                     for (int c = 0; c < 3; c++) Q[a][c] = v[3 * sv[a] + c];
                 }
                 cplx loc[4][3][3];
-                if (nq > 0) pair_integrals(tv, P, sv, Q, &m.nrm[3 * ti], KER_FULL, k, nq, loc);
+                int touch = 0;
+                for (int a = 0; a < 3; a++)
+                    for (int b = 0; b < 3; b++) touch |= tv[a] == sv[b];
+                if (nq < 0 && touch) pair_integrals_sub(tv, P, sv, Q, &m.nrm[3 * ti], k, &SUB_DEFAULT, loc);
+                else if (nq > 0) pair_integrals(tv, P, sv, Q, &m.nrm[3 * ti], KER_FULL, k, nq, loc);
                 else if (pair_integrals_auto(tv, P, sv, Q, &m.nrm[3 * ti], KER_FULL, k, AUTO_TOL, loc) < 0) {
 #pragma omp atomic write
                     quad_fail = 1;
@@ -826,7 +1162,7 @@ int oracle_matvec(int nv, const double *v, int nt, const int *t, double k, int o
         }
     }
     for (int r = 0; r < nr; r++) omp_destroy_lock(&locks[r]);
-    free(locks); free(acc_all); free(gram); free(need); free(outpos); free(coords);
+    free(locks); free(acc_all); free(gram); free(need); free(active); free(outpos); free(coords);
     mesh_free(&m);
     return quad_fail ? ORC_ERR_QUAD : ORC_OK;
 }
@@ -1039,3 +1375,85 @@ int oracle_boxes(int nv, const double *v, int nt, const int *t, double leaf, int
 }
 
 int oracle_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------- interaction classes by box */
+/* Open-addressing set of 64-bit keys (key + 1 stored, 0 = empty). */
+typedef struct { unsigned long long *slot; size_t cap, n; } keyset;
+
+static int keyset_add(keyset *s, unsigned long long key)
+{
+    if (2 * (s->n + 1) > s->cap) {
+        size_t ncap = s->cap ? 2 * s->cap : 1024;
+        unsigned long long *ns = calloc(ncap, sizeof(*ns));
+        if (!ns) return ORC_ERR_ARG;
+        for (size_t i = 0; i < s->cap; i++)
+            if (s->slot[i]) {
+                size_t h = (size_t)((s->slot[i] * 0x9E3779B97F4A7C15ULL) >> 7) & (ncap - 1);
+                while (ns[h]) h = (h + 1) & (ncap - 1);
+                ns[h] = s->slot[i];
+            }
+        free(s->slot);
+        s->slot = ns;
+        s->cap = ncap;
+    }
+    unsigned long long v = key + 1;
+    size_t h = (size_t)((v * 0x9E3779B97F4A7C15ULL) >> 7) & (s->cap - 1);
+    while (s->slot[h]) {
+        if (s->slot[h] == v) return 0;
+        h = (h + 1) & (s->cap - 1);
+    }
+    s->slot[h] = v;
+    s->n++;
+    return 1;
+}
+
+/* For every level l >= 2, the number of distinct ordered pairs of octree
+ * boxes (A, B) at level l for which some RWG in A and some RWG in B have
+ * interaction class l (pair_class above): the translations the MLFMA has to
+ * make at that level.  counts[l] for l < levels (counts[0], counts[1] = 0).
+ * Every RWG of one leaf box has the same class against any other RWG, so one
+ * representative RWG per occupied leaf box is enough. */
+int oracle_class_box_pairs(int nv, const double *v, int nt, const int *t, double leaf, long long *counts,
+                           int max_levels)
+{
+    mesh_t m;
+    int rc = mesh_build(&m, nv, v, nt, t);
+    if (rc != ORC_OK) { mesh_free(&m); return rc; }
+    int *coords = malloc(sizeof(int) * 3 * (size_t)m.n);
+    int levels = 0;
+    leaf_boxes(&m, leaf, &levels, coords);
+    if (levels > max_levels) { free(coords); mesh_free(&m); return ORC_ERR_ARG; }
+    for (int l = 0; l < max_levels; l++) counts[l] = 0;
+    const int leafl = levels - 1;
+    const long long nb = 1LL << leafl;
+    /* one representative RWG per occupied leaf box */
+    keyset seen = {0};
+    int *rep = malloc(sizeof(int) * (size_t)m.n);
+    int nrep = 0;
+    for (int r = 0; r < m.n; r++) {
+        unsigned long long key = ((unsigned long long)coords[3 * r] * nb + coords[3 * r + 1]) * nb + coords[3 * r + 2];
+        if (keyset_add(&seen, key) == 1) rep[nrep++] = r;
+    }
+    free(seen.slot);
+    keyset pairs[32];
+    memset(pairs, 0, sizeof(pairs));
+    for (int i = 0; i < nrep; i++)
+        for (int j = 0; j < nrep; j++) {
+            int cls = pair_class(coords, levels, rep[i], rep[j]);
+            if (cls < 2) continue;
+            int sh = leafl - cls;
+            long long nl = 1LL << cls;
+            const int *a = coords + 3 * rep[i], *b = coords + 3 * rep[j];
+            unsigned long long ka = ((unsigned long long)(a[0] >> sh) * nl + (a[1] >> sh)) * nl + (a[2] >> sh);
+            unsigned long long kb = ((unsigned long long)(b[0] >> sh) * nl + (b[1] >> sh)) * nl + (b[2] >> sh);
+            keyset_add(&pairs[cls], ka * (unsigned long long)(nl * nl * nl) + kb);
+        }
+    for (int l = 2; l < levels && l < 32; l++) {
+        counts[l] = (long long)pairs[l].n;
+        free(pairs[l].slot);
+    }
+    free(rep);
+    free(coords);
+    mesh_free(&m);
+    return levels;
+}

@@ -32,11 +32,13 @@ def _load():
         P = ctypes.c_void_p
         lib.oracle_rwg.argtypes = [ctypes.c_int, P, ctypes.c_int, P, P, P]
         lib.oracle_pair.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_int, P]
+        lib.oracle_pair_sub.argtypes = [P, P, P, P, ctypes.c_double, P, P]
         lib.oracle_matvec.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
                                       ctypes.c_int, P, P, ctypes.c_int, P, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int]
         lib.oracle_boxes.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, P, P]
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_class_box_pairs.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, P, ctypes.c_int]
         lib.oracle_far_field.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P,
                                          ctypes.c_int, P, P]
         lib.oracle_entries.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P, P]
@@ -136,6 +138,17 @@ def leaf_boxes(verts, tris, leaf):
     return coords, lev.value
 
 
+def class_box_pairs(verts, tris, leaf):
+    """{level: number of distinct ordered box pairs (A, B) at that level that
+    hold an RWG pair of that interaction class} for levels >= 2."""
+    v, t = _mesh(verts, tris)
+    out = np.zeros(32, np.int64)
+    rc = _load().oracle_class_box_pairs(len(v), v.ctypes.data, len(t), t.ctypes.data, leaf, out.ctypes.data, 32)
+    if rc < 0:
+        raise ValueError("oracle rejected the mesh (code %d)" % rc)
+    return {l: int(out[l]) for l in range(2, rc)}
+
+
 def pair_integrals(ti, P, si, Q, k, nq=0, kernel="full", return_order=False):
     """Local 4x3x3 integrals (T, K, Tx, Kx) of one triangle pair without RWG
     coefficients; vertex ids ti/si decide which vertices are shared.
@@ -154,7 +167,32 @@ def pair_integrals(ti, P, si, Q, k, nq=0, kernel="full", return_order=False):
     return (res, rc) if return_order else res
 
 
-def matvec(verts, tris, k, x, op=OP_C, rows=None, leaf=None, nq=0, classes=False):
+# Test-triangle and remainder rules of the singularity-subtraction route:
+# grading ratio, levels and points towards the singular set, points and
+# levels along the sweep base, remainder points per source-triangle axis.
+SUB_DEFAULT = (0.35, 24, 10, 6, 8, 12)
+
+
+def pair_integrals_sub(ti, P, si, Q, k, params=SUB_DEFAULT):
+    """Local 4x3x3 integrals (T, K, Tx, Kx) of one touching triangle pair by
+    the second route: singularity subtraction with closed-form static
+    integrals over the source triangle and graded Gauss rules over the test
+    triangle (independent of pair_integrals' relative-coordinate rules).
+    params = (sigma, levels, n, n_inner, n_s, s_levels)."""
+    ti = np.ascontiguousarray(ti, np.int32)
+    si = np.ascontiguousarray(si, np.int32)
+    P = np.ascontiguousarray(P, np.float64)
+    Q = np.ascontiguousarray(Q, np.float64)
+    pr = np.ascontiguousarray(params, np.float64)
+    out = np.zeros(72, np.float64)
+    rc = _load().oracle_pair_sub(ti.ctypes.data, P.ctypes.data, si.ctypes.data, Q.ctypes.data, k, pr.ctypes.data,
+                                 out.ctypes.data)
+    if rc < 0:
+        raise ValueError("bad arguments")
+    return (out[0::2] + 1j * out[1::2]).reshape(4, 3, 3)
+
+
+def matvec(verts, tris, k, x, op=OP_C, rows=None, leaf=None, nq=0, classes=False, route="duffy"):
     """Dense Galerkin product.
 
     x: (2N, nrhs) or (2N,) complex.  Returns y with shape (2*len(rows), nrhs)
@@ -163,7 +201,14 @@ def matvec(verts, tris, k, x, op=OP_C, rows=None, leaf=None, nq=0, classes=False
     (then only the J half of x is used and only the J half of y is filled).
     With classes=True (needs leaf), returns (ncls, 2nr, nrhs): class 0 is the
     near part (leaf boxes adjacent), class l >= 2 the part translated at level l.
+    route: "duffy" (relative-coordinate transformations, order search or the
+    fixed order nq) or "subtraction" (pair_integrals_sub) for the triangle
+    pairs that share a vertex, an edge or the triangle.
     """
+    if route == "subtraction":
+        nq = -1
+    elif route != "duffy":
+        raise ValueError("route must be 'duffy' or 'subtraction'")
     v, t = _mesh(verts, tris)
     N = 3 * len(t) // 2
     x = np.asarray(x, dtype=np.complex128)

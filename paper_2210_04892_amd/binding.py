@@ -7,6 +7,8 @@ imported before the library is loaded so both use one HIP runtime.
 import ctypes
 import math
 import os
+import threading
+import time
 
 import numpy as np
 import torch
@@ -45,6 +47,11 @@ class ServerOptions(ctypes.Structure):
     _fields_ = [("streams", ctypes.c_int), ("max_batch_rhs", ctypes.c_int), ("device", ctypes.c_int),
                 ("hbm_budget_bytes", ctypes.c_ulonglong), ("use_graphs", ctypes.c_int)]
 
+
+# int solve(void *user, int dtype, long long n, long long nrhs, const void *b, long long ldb,
+#           void *xq, long long ldxq, void *hip_stream)
+QSOLVE = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_longlong,
+                          ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p)
 
 _lib = None
 
@@ -87,11 +94,17 @@ def lib():
         L.mlfma_far_field.argtypes = [P, ctypes.c_int, LL, P, LL, LL, P, P, P]
         L.mlfma_server_opts_default.argtypes = [ctypes.POINTER(ServerOptions)]
         L.mlfma_server_create.argtypes = [ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
-        L.mlfma_server_submit.argtypes = [P, P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, ctypes.POINTER(LL)]
+        L.mlfma_server_submit.argtypes = [P, P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, P, ctypes.POINTER(LL)]
         L.mlfma_server_wait.argtypes = [P, LL, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int)]
         L.mlfma_server_stats.argtypes = [P, P]
         L.mlfma_server_destroy.argtypes = [P]
+        L.mlfma_peak_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.mlfma_hybrid_create.argtypes = [P, LL, P, P, P, P, P, P, QSOLVE, P, P, P, LL, LL, ctypes.POINTER(P)]
+        L.mlfma_hybrid_matvec.argtypes = [P, ctypes.c_int, LL, P, LL, P, LL, P]
+        L.mlfma_hybrid_gmres.argtypes = [P, ctypes.c_int, LL, P, LL, P, LL, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), P, P]
+        L.mlfma_hybrid_destroy.argtypes = [P]
         L.mlfma_profile.argtypes = [P, ctypes.c_int]
         L.mlfma_profile_read.argtypes = [P, P, ctypes.POINTER(LL)]
         _lib = L
@@ -377,27 +390,61 @@ class Server:
             _check(lib().mlfma_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._s = h
         self._keep = {}
+        # wait() calls inside the library; close() lets them leave before it
+        # destroys the server (a waiter returns within one wait slice)
+        self._cv = threading.Condition()
+        self._active = 0
+        self._closing = False
 
     def submit(self, geom, x, y, op="C"):
         """Enqueue y = A x; x, y: column-major storage given as (nrhs, 2N)
         contiguous CUDA tensors (row r = right-hand side r).  Returns a ticket.
-        The tensors are kept alive until the ticket is waited for."""
+        The tensors are kept alive until the ticket is waited for.  The server
+        uses x and y only after the work queued so far on torch's current
+        stream, so an x computed there just before is read as computed."""
         dt = C128 if x.dtype == torch.complex128 else C64
         nrhs, n2 = x.shape
         t = ctypes.c_longlong()
+        with torch.cuda.device(self.device):
+            st = torch.cuda.current_stream().cuda_stream
         _check(lib().mlfma_server_submit(self._s, geom._h, _OPS.get(op, op), dt, nrhs, x.data_ptr(), n2,
-                                         y.data_ptr(), n2, ctypes.byref(t)))
+                                         y.data_ptr(), n2, st, ctypes.byref(t)))
         self._keep[t.value] = (x, y)
         return t.value
 
-    def wait(self, ticket, timeout=-1.0):
-        """Block until the ticket is done; returns (latency_s, batch_rhs)."""
+    def wait(self, ticket, timeout=-1.0, _slice=0.05):
+        """Block until the ticket is done; returns (latency_s, batch_rhs).
+        Raises MlfmaError (MLFMA_ERR_STATE) on timeout or when the server is
+        closed meanwhile."""
         lat = ctypes.c_double()
         br = ctypes.c_int()
+        with self._cv:
+            if self._closing or not self._s:
+                raise MlfmaError(-5, "the server is closed")
+            self._active += 1
+        done = False
         try:
-            _check(lib().mlfma_server_wait(self._s, ticket, timeout, ctypes.byref(lat), ctypes.byref(br)))
+            t_end = None if timeout < 0 else time.monotonic() + timeout
+            while True:
+                left = _slice if t_end is None else min(_slice, max(0.0, t_end - time.monotonic()))
+                rc = lib().mlfma_server_wait(self._s, ticket, left, ctypes.byref(lat), ctypes.byref(br))
+                if rc == 0:
+                    done = True
+                    break
+                msg = lib().mlfma_last_error().decode()
+                if rc != -5 or "within the timeout" not in msg:
+                    done = True
+                    raise MlfmaError(rc, msg)
+                if self._closing:
+                    raise MlfmaError(-5, "the server was closed before the request finished")
+                if t_end is not None and time.monotonic() >= t_end:
+                    raise MlfmaError(-5, msg)
         finally:
-            self._keep.pop(ticket, None)
+            if done:
+                self._keep.pop(ticket, None)
+            with self._cv:
+                self._active -= 1
+                self._cv.notify_all()
         return lat.value, br.value
 
     def stats(self):
@@ -407,15 +454,149 @@ class Server:
                 "graph_captures": int(out[4])}
 
     def close(self):
-        if getattr(self, "_s", None):
-            lib().mlfma_server_destroy(self._s)
-            self._s = None
+        """Destroy the server: requests still queued or running fail, waiting
+        threads return with MLFMA_ERR_STATE first."""
+        cv = getattr(self, "_cv", None)
+        if cv is None or not getattr(self, "_s", None):
+            return
+        with cv:
+            if self._closing:
+                return
+            self._closing = True
+            cv.wait_for(lambda: self._active == 0)
+        lib().mlfma_server_destroy(self._s)
+        self._s = None
+        self._keep.clear()
 
     def __del__(self):
         try:
             self.close()
         except Exception:
             pass
+
+
+def _csr(m, shape):
+    """(ptr int64, col int32, val complex128 interleaved) host arrays of a
+    scipy.sparse matrix or a (ptr, col, val) triple."""
+    if hasattr(m, "tocsr"):
+        m = m.tocsr()
+        if m.shape != shape:
+            raise ValueError("sparse matrix has shape %s, expected %s" % (m.shape, shape))
+        ptr, col, val = m.indptr, m.indices, m.data
+    else:
+        ptr, col, val = m
+    ptr = np.ascontiguousarray(ptr, np.int64)
+    col = np.ascontiguousarray(col, np.int32)
+    val = np.ascontiguousarray(val, np.complex128)
+    if len(ptr) != shape[0] + 1:
+        raise ValueError("row pointer array must have %d entries" % (shape[0] + 1))
+    return ptr, col, val
+
+
+class Hybrid:
+    """Reduced operator of the hybrid solver (eq. 52; mlfma_hybrid_*):
+    y = (C - D_xl Q^-1 D_lx) x with the sparse couplings D_lx (n_hdg x 2N)
+    and D_xl (2N x n_hdg) and the caller's solve with Q.
+
+    solve(b, xq) is called with two (nrhs, n_hdg) CUDA tensor views of the
+    operator's own buffers (complex128 or complex64 like the product) and
+    must write xq = Q^-1 b on torch's current stream."""
+
+    def __init__(self, geom, n_hdg, D_lx, D_xl, solve, max_rhs=1):
+        self.geom = geom
+        self.n_hdg = int(n_hdg)
+        self.max_rhs = int(max_rhs)
+        n2 = 2 * geom.n_rwg
+        self._arrays = _csr(D_lx, (self.n_hdg, n2)) + _csr(D_xl, (n2, self.n_hdg))
+        self._buf1 = torch.zeros((self.max_rhs, self.n_hdg), dtype=torch.complex128, device="cuda:%d" % geom.device)
+        self._buf2 = torch.zeros_like(self._buf1)
+        self._solve = solve
+
+        def _cb(user, dtype, n, nrhs, b, ldb, xq, ldxq, stream):
+            try:
+                views = []
+                for buf, ptr in ((self._buf1, b), (self._buf2, xq)):
+                    if ptr != buf.data_ptr():
+                        return 2
+                    flat = buf.view(-1)
+                    if dtype == C64:
+                        flat = flat.view(torch.float64).view(torch.complex64)
+                    views.append(flat[:nrhs * self.n_hdg].view(nrhs, self.n_hdg))
+                self._solve(views[0], views[1])
+                return 0
+            except Exception:          # reported as a failed product
+                import traceback
+                traceback.print_exc()
+                return 1
+
+        self._cb = QSOLVE(_cb)
+        lx, xl = self._arrays[:3], self._arrays[3:]
+        h = ctypes.c_void_p()
+        with torch.cuda.device(geom.device):
+            _check(lib().mlfma_hybrid_create(geom._h, self.n_hdg, lx[0].ctypes.data, lx[1].ctypes.data,
+                                             lx[2].ctypes.data, xl[0].ctypes.data, xl[1].ctypes.data,
+                                             xl[2].ctypes.data, self._cb, None, self._buf1.data_ptr(),
+                                             self._buf2.data_ptr(), self.n_hdg, self.max_rhs, ctypes.byref(h)))
+        self._h = h
+
+    def matvec(self, x):
+        """y = (C - D_xl Q^-1 D_lx) x; x complex CUDA tensor (2N,) or (2N, nrhs)."""
+        dt = C128 if x.dtype == torch.complex128 else C64
+        squeeze = x.dim() == 1
+        X = x[:, None] if squeeze else x
+        nrhs = X.shape[1]
+        xt = X.t().contiguous()
+        yt = torch.empty_like(xt)
+        n2 = 2 * self.geom.n_rwg
+        with torch.cuda.device(self.geom.device):
+            st = torch.cuda.current_stream().cuda_stream
+            _check(lib().mlfma_hybrid_matvec(self._h, dt, nrhs, xt.data_ptr(), n2, yt.data_ptr(), n2, st))
+        y = yt.t()
+        return y[:, 0] if squeeze else y
+
+    def gmres(self, b, x0=None, restart=30, max_iters=500, tol=1e-3, precond=None):
+        """GMRES on the reduced system (mlfma_hybrid_gmres); returns (x, steps,
+        true relative residual per column)."""
+        dt = C128 if b.dtype == torch.complex128 else C64
+        squeeze = b.dim() == 1
+        B = b[:, None] if squeeze else b
+        nrhs = B.shape[1]
+        bt = B.t().contiguous()
+        xt = torch.zeros_like(bt) if x0 is None else (x0[:, None] if squeeze else x0).t().contiguous().clone()
+        it = ctypes.c_int()
+        rel = np.zeros(nrhs, np.float64)
+        n2 = 2 * self.geom.n_rwg
+        pc = PRECOND_SAI if precond == "sai" else PRECOND_NONE
+        with torch.cuda.device(self.geom.device):
+            st = torch.cuda.current_stream().cuda_stream
+            _check(lib().mlfma_hybrid_gmres(self._h, dt, nrhs, bt.data_ptr(), n2, xt.data_ptr(), n2, restart,
+                                            max_iters, tol, pc, ctypes.byref(it), rel.ctypes.data, st))
+        x = xt.t()
+        return (x[:, 0] if squeeze else x), it.value, rel
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mlfma_hybrid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def peak_probe(kind, device=None):
+    """mlfma_peak_probe: measured HBM copy bandwidth (kind "hbm", GB/s), FP32
+    matrix-core rate ("mfma_f32", TFLOP/s) or FP32 vector FMA rate
+    ("valu_f32", TFLOP/s) of the device."""
+    code = {"hbm": 0, "mfma_f32": 1, "valu_f32": 2}[kind]
+    v = ctypes.c_double()
+    dev = torch.cuda.current_device() if device is None else int(device)
+    rc = lib().mlfma_peak_probe(code, dev, ctypes.byref(v))
+    if rc != 0:
+        raise MlfmaError(rc, "peak probe %s failed" % kind)
+    return v.value
 
 
 def matvec_batch(items, stream=None):

@@ -190,6 +190,7 @@ struct mlfma_ctx {
     }
     void free_ws()
     {
+        ws_gen++;             // graphs captured over the old buffers may no longer replay
         bytes -= ws.bytes;
         ws.release();
     }
@@ -875,85 +876,74 @@ void build_sai(mlfma_ctx *c, int op, int k_nearest)
 }
 
 // ---------------------------------------------------------------- workspace
-// Bytes of a workspace for nrhs right-hand sides.
-unsigned long long workspace_bytes(const mlfma_ctx *c, int nrhs)
+// Layout of the per-product scratch for nrhs right-hand sides in elements of
+// esz bytes (16: complex double, also used by the complex float path; 8:
+// complex float only), every buffer starting on a 256-byte boundary: the
+// internal vectors X and Y, the box patterns U and V of every level and the
+// level-step intermediate.  Returns the bytes; with w and base set, points
+// w's buffers into base.
+unsigned long long layout_workspace(const mlfma_ctx *c, int nrhs, size_t esz, char *base, Workspace *w)
 {
     const Tree &tr = c->tr;
-    const unsigned long long cd = sizeof(cpx<double>);
-    unsigned long long n = 2ULL * (unsigned long long)c->r.n * 2 * nrhs;
+    unsigned long long off = 0;
+    auto take = [&](unsigned long long elems) -> void * {
+        void *p = base ? base + off : nullptr;
+        off += (std::max<unsigned long long>(elems, 1) * esz + 255) & ~255ULL;
+        return p;
+    };
+    const unsigned long long N = (unsigned long long)c->r.n;
+    void *X = take(N * 2 * nrhs), *Y = take(N * 2 * nrhs);
+    if (w) {
+        w->X = X;
+        w->Y = Y;
+        w->U.assign(tr.levels, nullptr);
+        w->V.assign(tr.levels, nullptr);
+    }
     unsigned long long midmax = 1;
     for (int l = 2; l < tr.levels; l++) {
         const Level &L = tr.lv[l];
-        n += 2ULL * L.nbox * L.K * 2 * nrhs;
+        void *U = take((unsigned long long)L.nbox * L.K * 2 * nrhs);
+        void *V = take((unsigned long long)L.nbox * L.K * 2 * nrhs);
+        if (w) {
+            w->U[l] = U;
+            w->V[l] = V;
+        }
         if (l + 1 < tr.levels) {
             const Level &C = tr.lv[l + 1];
             midmax = std::max<unsigned long long>(midmax, (unsigned long long)C.nbox * L.nth * C.nph * 2 * nrhs);
         }
     }
-    return (n + midmax) * cd;
+    void *mid = take(midmax);
+    if (w) {
+        w->mid = mid;
+        w->rhs = nrhs;
+    }
+    return off;
+}
+
+// Bytes of a workspace for nrhs right-hand sides (complex double units).
+unsigned long long workspace_bytes(const mlfma_ctx *c, int nrhs)
+{
+    return layout_workspace(c, nrhs, sizeof(cpx<double>), nullptr, nullptr);
 }
 
 // Allocate w for nrhs right-hand sides (no budget check: the caller admits).
 void alloc_workspace(const mlfma_ctx *c, Workspace &w, int nrhs)
 {
     w.release();
-    const Tree &tr = c->tr;
-    const size_t cd = sizeof(cpx<double>);
-    auto get = [&](size_t elems) {
-        void *p = nullptr;
-        HIPCHK(hipMalloc(&p, std::max<size_t>(elems, 1) * cd));
-        w.allocs.push_back(p);
-        w.bytes += std::max<size_t>(elems, 1) * cd;
-        return p;
-    };
-    const int N = c->r.n;
-    w.X = get((size_t)N * 2 * nrhs);
-    w.Y = get((size_t)N * 2 * nrhs);
-    w.U.assign(tr.levels, nullptr);
-    w.V.assign(tr.levels, nullptr);
-    size_t midmax = 1;
-    for (int l = 2; l < tr.levels; l++) {
-        const Level &L = tr.lv[l];
-        w.U[l] = get((size_t)L.nbox * L.K * 2 * nrhs);
-        w.V[l] = get((size_t)L.nbox * L.K * 2 * nrhs);
-        if (l + 1 < tr.levels) {
-            const Level &C = tr.lv[l + 1];
-            midmax = std::max(midmax, (size_t)C.nbox * L.nth * C.nph * 2 * nrhs);
-        }
-    }
-    w.mid = get(midmax);
-    w.rhs = nrhs;
+    const unsigned long long need = workspace_bytes(c, nrhs);
+    void *p = nullptr;
+    HIPCHK(hipMalloc(&p, need));
+    w.allocs.push_back(p);
+    w.bytes = need;
+    layout_workspace(c, nrhs, sizeof(cpx<double>), (char *)p, &w);
 }
 
 // Lay a workspace for nrhs right-hand sides over an existing arena of at
 // least workspace_bytes(c, nrhs) bytes (no allocation).
 void carve_workspace(const mlfma_ctx *c, Workspace &w, char *base, int nrhs)
 {
-    const Tree &tr = c->tr;
-    const size_t cd = sizeof(cpx<double>);
-    size_t off = 0;
-    auto take = [&](size_t elems) {
-        void *p = base + off;
-        off += elems * cd;
-        return p;
-    };
-    const int N = c->r.n;
-    w.X = take((size_t)N * 2 * nrhs);
-    w.Y = take((size_t)N * 2 * nrhs);
-    w.U.assign(tr.levels, nullptr);
-    w.V.assign(tr.levels, nullptr);
-    size_t midmax = 1;
-    for (int l = 2; l < tr.levels; l++) {
-        const Level &L = tr.lv[l];
-        w.U[l] = take((size_t)L.nbox * L.K * 2 * nrhs);
-        w.V[l] = take((size_t)L.nbox * L.K * 2 * nrhs);
-        if (l + 1 < tr.levels) {
-            const Level &C = tr.lv[l + 1];
-            midmax = std::max(midmax, (size_t)C.nbox * L.nth * C.nph * 2 * nrhs);
-        }
-    }
-    w.mid = take(midmax);
-    w.rhs = nrhs;
+    layout_workspace(c, nrhs, sizeof(cpx<double>), base, &w);
 }
 
 void ensure_workspace(mlfma_ctx *c, int nrhs)
@@ -963,9 +953,13 @@ void ensure_workspace(mlfma_ctx *c, int nrhs)
     const unsigned long long need = workspace_bytes(c, nrhs);
     if (c->opt.hbm_budget_bytes && c->bytes + need > c->opt.hbm_budget_bytes)
         throw Error(MLFMA_ERR_OOM, "device memory budget exceeded by the workspace");
-    alloc_workspace(c, c->ws, nrhs);
+    try {
+        alloc_workspace(c, c->ws, nrhs);
+    } catch (...) {
+        c->ws.release();      // the buffers allocated before the failure; c->bytes never counted them
+        throw;
+    }
     c->bytes += c->ws.bytes;
-    c->ws_gen++;
     if (!c->side) {
         HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
@@ -1151,6 +1145,46 @@ const cpx<double> *sai_values<double>(const SaiData &d) { return d.M64; }
 template <>
 const cpx<float> *sai_values<float>(const SaiData &d) { return d.M32; }
 
+// The HDG side of the hybrid solver's product (Sec. II-E, eq. 52, steps
+// 2(b)-(e)): the sparse couplings D^{Lambda X} (n_hdg x 2N) and D^{X Lambda}
+// (2N x n_hdg) in CSR form on the device, in both precisions, and the
+// caller's solve with Q (the sparse-direct factorisation of the HDG block)
+// over the caller's two n_hdg x max_rhs buffers.
+struct HybridSide {
+    long long n_hdg = 0, nnz_lx = 0, nnz_xl = 0;
+    long long *lx_ptr = nullptr, *xl_ptr = nullptr;
+    int *lx_col = nullptr, *xl_col = nullptr;
+    cpx<double> *lx64 = nullptr, *xl64 = nullptr;
+    cpx<float> *lx32 = nullptr, *xl32 = nullptr;
+    mlfma_qsolve_fn solve = nullptr;
+    void *user = nullptr;
+    void *buf1 = nullptr, *buf2 = nullptr;
+    long long ldbuf = 0, max_rhs = 0;
+};
+
+template <class T>
+const cpx<T> *hy_vals(const HybridSide &h, bool lx);
+template <>
+const cpx<double> *hy_vals<double>(const HybridSide &h, bool lx) { return lx ? h.lx64 : h.xl64; }
+template <>
+const cpx<float> *hy_vals<float>(const HybridSide &h, bool lx) { return lx ? h.lx32 : h.xl32; }
+
+// out -= D^{X Lambda} Q^{-1} D^{Lambda X} in, after out holds C in
+template <class T>
+void hybrid_correction(const HybridSide &hy, int n2, int nrhs, const cpx<T> *in, long long ldi, cpx<T> *out,
+                       long long ldo, hipStream_t st)
+{
+    const int dtype = std::is_same<T, double>::value ? MLFMA_C128 : MLFMA_C64;
+    cpx<T> *x1 = (cpx<T> *)hy.buf1, *x2 = (cpx<T> *)hy.buf2;
+    launch_csr_spmm<T>(hy.n_hdg, nrhs, hy.lx_ptr, hy.lx_col, hy_vals<T>(hy, true), in, ldi, x1, hy.ldbuf, 1.0, false,
+                       st);
+    HIPCHK(hipGetLastError());
+    const int rc = hy.solve(hy.user, dtype, hy.n_hdg, nrhs, x1, hy.ldbuf, x2, hy.ldbuf, (void *)st);
+    if (rc != 0) throw Error(MLFMA_ERR_ARG, "the solve with Q returned " + std::to_string(rc));
+    launch_csr_spmm<T>(n2, nrhs, hy.xl_ptr, hy.xl_col, hy_vals<T>(hy, false), x2, hy.ldbuf, out, ldo, -1.0, true, st);
+    HIPCHK(hipGetLastError());
+}
+
 // Restarted GMRES(m) on y = A x (op, precision T), one Krylov space per
 // right-hand-side column; every Arnoldi step is one batched product of all
 // columns.  Classical Gram-Schmidt applied twice on the device (inner
@@ -1160,9 +1194,12 @@ const cpx<float> *sai_values<float>(const SaiData &d) { return d.M32; }
 // relative residual ||b - A x|| / ||b|| of every column, recomputed at exit.
 // With sai (right preconditioning) the Krylov space is built for A M and the
 // solution is x0 + M V y; residuals and tol are those of A x = b itself.
+// With hy the operator is the reduced matrix of eq. 52, C - D^{X Lambda}
+// Q^{-1} D^{Lambda X} (op C).
 template <class T>
 void gmres(mlfma_ctx *c, Prec<T> &P, int op, int nrhs, const cpx<T> *b, long long ldb, cpx<T> *x, long long ldx,
-           int m, int max_iters, double tol, int *iters_out, double *relres, const SaiData *sai, hipStream_t st)
+           int m, int max_iters, double tol, int *iters_out, double *relres, const SaiData *sai, hipStream_t st,
+           const HybridSide *hy = nullptr)
 {
     typedef std::complex<double> C;
     const long long n = 2LL * c->r.n;
@@ -1191,6 +1228,7 @@ void gmres(mlfma_ctx *c, Prec<T> &P, int op, int nrhs, const cpx<T> *b, long lon
     cpx<double> *cb = (cpx<double> *)dev(sizeof(cpx<double>) * nrhs);
     auto matvec = [&](const cpx<T> *in, long long ldi, cpx<T> *out, long long ldo) {
         run_matvec<T>(c, c->ws, P, op, MLFMA_PART_ALL, nrhs, in, ldi, out, ldo, st, false);
+        if (hy) hybrid_correction<T>(*hy, (int)n, nrhs, in, ldi, out, ldo, st);
     };
     cpx<T> *z = sai ? (cpx<T> *)dev(sizeof(cpx<T>) * (size_t)vstride) : nullptr;
     cpx<T> *tv = sai ? (cpx<T> *)dev(sizeof(cpx<T>) * (size_t)vstride) : nullptr;
@@ -1346,6 +1384,52 @@ int fail(const Error &e)
 {
     g_last_error = e.what();
     return e.code;
+}
+
+// Checks and runs mlfma_gmres_precond; with hy, on the reduced operator of
+// eq. 52 (op C only).
+int gmres_entry(mlfma_handle h, int op, int dtype, long long nrhs, const void *b, long long ldb, void *x,
+                long long ldx, int restart, int max_iters, double tol, int precond, int *iters, double *relres,
+                void *hip_stream, const HybridSide *hy)
+{
+    g_last_error.clear();
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    if (!h->near_ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_precompute_nearfield has not been called"));
+    if (op != MLFMA_OP_C && op != MLFMA_OP_EM) return fail(Error(MLFMA_ERR_ARG, "unknown op"));
+    if (dtype != MLFMA_C128 && dtype != MLFMA_C64) return fail(Error(MLFMA_ERR_ARG, "unknown dtype"));
+    const long long N2 = 2LL * h->r.n;
+    if (nrhs < 1 || nrhs > 4096 || !b || !x || !relres || ldb < N2 || ldx < N2 || restart < 1 || restart > 512 ||
+        max_iters < 1 || !(tol > 0))
+        return fail(Error(MLFMA_ERR_ARG, "bad nrhs, pointer, leading dimension, restart, max_iters or tol"));
+    if (hy && (op != MLFMA_OP_C || nrhs > hy->max_rhs))
+        return fail(Error(MLFMA_ERR_ARG, "the hybrid operator is op C with at most max_rhs columns"));
+    if (precond != MLFMA_PRECOND_NONE && precond != MLFMA_PRECOND_SAI)
+        return fail(Error(MLFMA_ERR_ARG, "unknown preconditioner"));
+    const SaiData *sai = nullptr;
+    if (precond == MLFMA_PRECOND_SAI) {
+        if (!h->sai[op].ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_sai_build has not been called for this op"));
+        sai = &h->sai[op];
+    }
+    const size_t esz = dtype == MLFMA_C128 ? 16 : 8;
+    const char *bb = (const char *)b, *xb = (const char *)x;
+    if (bb < xb + (size_t)(ldx * (nrhs - 1) + N2) * esz && xb < bb + (size_t)(ldb * (nrhs - 1) + N2) * esz)
+        return fail(Error(MLFMA_ERR_ARG, "b and x overlap"));
+    try {
+        DeviceGuard g(h->device);
+        HIPCHK(hipGetLastError());
+        ensure_workspace(h, (int)nrhs);
+        hipStream_t st = (hipStream_t)hip_stream;
+        if (dtype == MLFMA_C128)
+            gmres<double>(h, h->p64, op, (int)nrhs, (const cpx<double> *)b, ldb, (cpx<double> *)x, ldx, restart,
+                          max_iters, tol, iters, relres, sai, st, hy);
+        else
+            gmres<float>(h, h->p32, op, (int)nrhs, (const cpx<float> *)b, ldb, (cpx<float> *)x, ldx, restart,
+                         max_iters, tol, iters, relres, sai, st, hy);
+        HIPCHK(hipGetLastError());
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
 }
 
 }  // namespace
@@ -1615,42 +1699,128 @@ int mlfma_gmres_precond(mlfma_handle h, int op, int dtype, long long nrhs, const
                         long long ldx, int restart, int max_iters, double tol, int precond, int *iters,
                         double *relres, void *hip_stream)
 {
+    return gmres_entry(h, op, dtype, nrhs, b, ldb, x, ldx, restart, max_iters, tol, precond, iters, relres,
+                       hip_stream, nullptr);
+}
+
+// ------------------------------------------------------ hybrid product
+struct mlfma_hybrid_s {
+    mlfma_handle h = nullptr;
+    HybridSide side;
+    std::vector<void *> allocs;
+};
+
+int mlfma_hybrid_create(mlfma_handle h, long long n_hdg, const long long *dlx_ptr, const int *dlx_col,
+                        const double *dlx_val, const long long *dxl_ptr, const int *dxl_col, const double *dxl_val,
+                        mlfma_qsolve_fn solve, void *user, void *buf1, void *buf2, long long ldbuf,
+                        long long max_rhs, mlfma_hybrid *out)
+{
     g_last_error.clear();
-    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
-    if (!h->near_ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_precompute_nearfield has not been called"));
-    if (op != MLFMA_OP_C && op != MLFMA_OP_EM) return fail(Error(MLFMA_ERR_ARG, "unknown op"));
-    if (dtype != MLFMA_C128 && dtype != MLFMA_C64) return fail(Error(MLFMA_ERR_ARG, "unknown dtype"));
+    if (!out) return fail(Error(MLFMA_ERR_ARG, "out pointer is NULL"));
+    *out = nullptr;
+    if (!h || !solve || !buf1 || !buf2 || !dlx_ptr || !dxl_ptr) return fail(Error(MLFMA_ERR_ARG, "NULL argument"));
     const long long N2 = 2LL * h->r.n;
-    if (nrhs < 1 || nrhs > 4096 || !b || !x || !relres || ldb < N2 || ldx < N2 || restart < 1 || restart > 512 ||
-        max_iters < 1 || !(tol > 0))
-        return fail(Error(MLFMA_ERR_ARG, "bad nrhs, pointer, leading dimension, restart, max_iters or tol"));
-    if (precond != MLFMA_PRECOND_NONE && precond != MLFMA_PRECOND_SAI)
-        return fail(Error(MLFMA_ERR_ARG, "unknown preconditioner"));
-    const SaiData *sai = nullptr;
-    if (precond == MLFMA_PRECOND_SAI) {
-        if (!h->sai[op].ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_sai_build has not been called for this op"));
-        sai = &h->sai[op];
-    }
-    const size_t esz = dtype == MLFMA_C128 ? 16 : 8;
-    const char *bb = (const char *)b, *xb = (const char *)x;
-    if (bb < xb + (size_t)(ldx * (nrhs - 1) + N2) * esz && xb < bb + (size_t)(ldb * (nrhs - 1) + N2) * esz)
-        return fail(Error(MLFMA_ERR_ARG, "b and x overlap"));
+    if (n_hdg < 1 || n_hdg > (1LL << 31) - 1 || max_rhs < 1 || max_rhs > 4096 || ldbuf < n_hdg)
+        return fail(Error(MLFMA_ERR_ARG, "bad n_hdg, max_rhs or buffer leading dimension"));
+    // CSR checks: row pointers start at 0 and never decrease, columns in range
+    auto check = [&](const long long *ptr, const int *col, const double *val, long long rows, long long ncols,
+                     const char *what) {
+        if (ptr[0] != 0) throw Error(MLFMA_ERR_ARG, std::string(what) + ": row pointers must start at 0");
+        for (long long i = 0; i < rows; i++)
+            if (ptr[i + 1] < ptr[i]) throw Error(MLFMA_ERR_ARG, std::string(what) + ": decreasing row pointers");
+        const long long nnz = ptr[rows];
+        if (nnz > 0 && (!col || !val)) throw Error(MLFMA_ERR_ARG, std::string(what) + ": NULL columns or values");
+        for (long long k = 0; k < nnz; k++)
+            if (col[k] < 0 || col[k] >= ncols) throw Error(MLFMA_ERR_ARG, std::string(what) + ": column out of range");
+        return nnz;
+    };
+    std::unique_ptr<mlfma_hybrid_s> hy(new mlfma_hybrid_s());
     try {
+        const long long nlx = check(dlx_ptr, dlx_col, dlx_val, n_hdg, N2, "D^{Lambda X}");
+        const long long nxl = check(dxl_ptr, dxl_col, dxl_val, N2, n_hdg, "D^{X Lambda}");
         DeviceGuard g(h->device);
-        HIPCHK(hipGetLastError());
-        ensure_workspace(h, (int)nrhs);
+        auto up = [&](const void *src, size_t bytes) {
+            void *d = nullptr;
+            HIPCHK(hipMalloc(&d, std::max<size_t>(bytes, 1)));
+            hy->allocs.push_back(d);
+            if (bytes) HIPCHK(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
+            return d;
+        };
+        auto single = [](const double *v, long long nnz) {
+            std::vector<cpx<float>> f((size_t)nnz);
+            for (long long k = 0; k < nnz; k++) f[(size_t)k] = {(float)v[2 * k], (float)v[2 * k + 1]};
+            return f;
+        };
+        HybridSide &sd = hy->side;
+        sd.n_hdg = n_hdg;
+        sd.nnz_lx = nlx;
+        sd.nnz_xl = nxl;
+        sd.lx_ptr = (long long *)up(dlx_ptr, sizeof(long long) * (size_t)(n_hdg + 1));
+        sd.xl_ptr = (long long *)up(dxl_ptr, sizeof(long long) * (size_t)(N2 + 1));
+        sd.lx_col = (int *)up(dlx_col, sizeof(int) * (size_t)nlx);
+        sd.xl_col = (int *)up(dxl_col, sizeof(int) * (size_t)nxl);
+        sd.lx64 = (cpx<double> *)up(dlx_val, sizeof(cpx<double>) * (size_t)nlx);
+        sd.xl64 = (cpx<double> *)up(dxl_val, sizeof(cpx<double>) * (size_t)nxl);
+        const std::vector<cpx<float>> lx32 = single(dlx_val, nlx), xl32 = single(dxl_val, nxl);
+        sd.lx32 = (cpx<float> *)up(lx32.data(), sizeof(cpx<float>) * lx32.size());
+        sd.xl32 = (cpx<float> *)up(xl32.data(), sizeof(cpx<float>) * xl32.size());
+        sd.solve = solve;
+        sd.user = user;
+        sd.buf1 = buf1;
+        sd.buf2 = buf2;
+        sd.ldbuf = ldbuf;
+        sd.max_rhs = max_rhs;
+        hy->h = h;
+        *out = hy.release();
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        for (void *p : hy->allocs) (void)hipFree(p);
+        return fail(e);
+    }
+}
+
+int mlfma_hybrid_matvec(mlfma_hybrid hy, int dtype, long long nrhs, const void *x, long long ldx, void *y,
+                        long long ldy, void *hip_stream)
+{
+    g_last_error.clear();
+    if (!hy) return fail(Error(MLFMA_ERR_ARG, "NULL hybrid operator"));
+    if (nrhs > hy->side.max_rhs) return fail(Error(MLFMA_ERR_ARG, "nrhs exceeds the solve buffers' max_rhs"));
+    const int rc = mlfma_matvec_part(hy->h, MLFMA_OP_C, dtype, MLFMA_PART_ALL, nrhs, x, ldx, y, ldy, hip_stream);
+    if (rc != MLFMA_OK) return rc;
+    try {
+        DeviceGuard g(hy->h->device);
+        const int n2 = 2 * hy->h->r.n;
         hipStream_t st = (hipStream_t)hip_stream;
         if (dtype == MLFMA_C128)
-            gmres<double>(h, h->p64, op, (int)nrhs, (const cpx<double> *)b, ldb, (cpx<double> *)x, ldx, restart,
-                          max_iters, tol, iters, relres, sai, st);
+            hybrid_correction<double>(hy->side, n2, (int)nrhs, (const cpx<double> *)x, ldx, (cpx<double> *)y, ldy, st);
         else
-            gmres<float>(h, h->p32, op, (int)nrhs, (const cpx<float> *)b, ldb, (cpx<float> *)x, ldx, restart,
-                         max_iters, tol, iters, relres, sai, st);
-        HIPCHK(hipGetLastError());
+            hybrid_correction<float>(hy->side, n2, (int)nrhs, (const cpx<float> *)x, ldx, (cpx<float> *)y, ldy, st);
         return MLFMA_OK;
     } catch (const Error &e) {
         return fail(e);
     }
+}
+
+int mlfma_hybrid_gmres(mlfma_hybrid hy, int dtype, long long nrhs, const void *b, long long ldb, void *x,
+                       long long ldx, int restart, int max_iters, double tol, int precond, int *iters,
+                       double *relres, void *hip_stream)
+{
+    g_last_error.clear();
+    if (!hy) return fail(Error(MLFMA_ERR_ARG, "NULL hybrid operator"));
+    return gmres_entry(hy->h, MLFMA_OP_C, dtype, nrhs, b, ldb, x, ldx, restart, max_iters, tol, precond, iters,
+                       relres, hip_stream, &hy->side);
+}
+
+int mlfma_hybrid_destroy(mlfma_hybrid hy)
+{
+    if (!hy) return MLFMA_OK;
+    {
+        DeviceGuard g(hy->h->device);
+        (void)hipDeviceSynchronize();
+        for (void *p : hy->allocs) (void)hipFree(p);
+    }
+    delete hy;
+    return MLFMA_OK;
 }
 
 int mlfma_graph_destroy(mlfma_graph g)
@@ -1948,9 +2118,11 @@ struct Request {
     const void *x = nullptr;
     void *y = nullptr;
     long long ldx = 0, ldy = 0;
+    hipEvent_t ready = nullptr;   // recorded on the caller's stream at submit: x and y are usable after it
     Clock::time_point t_submit, t_start, t_done;
     int state = 0;        // 0 queued, 1 running, 2 done, < 0 error code
     int batch_rhs = 0;    // right-hand sides of the product it ran in
+    std::string error;    // why the request failed (state < 0)
 };
 
 struct Slot {
@@ -1988,7 +2160,8 @@ struct mlfma_server_s {
     long long next_ticket = 1;
     long long launches = 0, batched_requests = 0;
     bool stop = false;
-    std::string thread_error;
+    int waiters = 0;                   // threads inside mlfma_server_wait
+    std::vector<hipEvent_t> free_events;   // pool of the requests' ready events
     std::thread sched, poll;
     hipStream_t capture = nullptr;     // stream the scheduler captures products on
     long long graph_captures = 0;
@@ -2005,6 +2178,9 @@ void launch_batch(mlfma_server_s *S, Slot &slot, std::vector<Request *> &batch, 
     const int op = batch[0]->op, dtype = batch[0]->dtype;
     const size_t esz = dtype == MLFMA_C128 ? 16 : 8;
     const long long N2 = 2LL * h->r.n;
+    // nothing of a request is read or written before the caller's work that
+    // preceded its submission
+    for (Request *r : batch) HIPCHK(hipStreamWaitEvent(slot.stream, r->ready, 0));
     int col = 0;
     for (Request *r : batch) {
         HIPCHK(hipMemcpy2DAsync(slot.xb + (size_t)col * N2 * esz, N2 * esz, r->x, r->ldx * esz, N2 * esz, r->nrhs,
@@ -2117,6 +2293,7 @@ void scheduler_loop(mlfma_server_s *S)
             for (auto &sl : S->slots) any_busy |= sl.busy;
             if (!any_busy) {          // can never fit: fail the request
                 S->queue.pop_front();
+                r0->error = "the request's product does not fit the memory budget";
                 r0->state = MLFMA_ERR_OOM;
                 r0->t_done = Clock::now();
                 S->cv_done.notify_all();
@@ -2148,6 +2325,7 @@ void scheduler_loop(mlfma_server_s *S)
         }
         lk.unlock();
         int err = 0;
+        std::string why;
         try {
             if (grow) {
                 clear_graphs(slot);
@@ -2171,15 +2349,17 @@ void scheduler_loop(mlfma_server_s *S)
             launch_batch(S, slot, batch, total);
         } catch (const Error &e) {
             err = e.code;
-            lk.lock();
-            S->thread_error = e.what();
-            lk.unlock();
+            why = e.what();
+            // copies and kernels already queued may still use the requests'
+            // buffers: the caller learns of the failure only once they are done
+            (void)hipStreamSynchronize(slot.stream);
         }
         lk.lock();
         S->launches++;
         S->batched_requests += (long long)batch.size();
         if (err) {
             for (Request *r : batch) {
+                r->error = why;
                 r->state = err;
                 r->t_done = Clock::now();
             }
@@ -2204,6 +2384,7 @@ void poller_loop(mlfma_server_s *S)
             if (q == hipErrorNotReady) continue;
             const auto now = Clock::now();
             for (Request *r : sl.reqs) {
+                if (q != hipSuccess) r->error = std::string("device error: ") + hipGetErrorString(q);
                 r->state = q == hipSuccess ? 2 : MLFMA_ERR_HIP;
                 r->t_done = now;
             }
@@ -2265,7 +2446,7 @@ int mlfma_server_create(const mlfma_server_opts *opt, mlfma_server *out)
 }
 
 int mlfma_server_submit(mlfma_server s, mlfma_handle h, int op, int dtype, long long nrhs, const void *x,
-                        long long ldx, void *y, long long ldy, long long *ticket)
+                        long long ldx, void *y, long long ldy, void *hip_stream, long long *ticket)
 {
     g_last_error.clear();
     if (!s || !h || !ticket) return fail(Error(MLFMA_ERR_ARG, "NULL argument"));
@@ -2276,7 +2457,28 @@ int mlfma_server_submit(mlfma_server s, mlfma_handle h, int op, int dtype, long 
     const long long N2 = 2LL * h->r.n;
     if (nrhs < 1 || nrhs > (1 << 16) || !x || !y || ldx < N2 || ldy < N2)
         return fail(Error(MLFMA_ERR_ARG, "bad nrhs, pointer or leading dimension"));
+    hipEvent_t ready = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) return fail(Error(MLFMA_ERR_STATE, "the server is being destroyed"));
+        if (!s->free_events.empty()) {
+            ready = s->free_events.back();
+            s->free_events.pop_back();
+        }
+    }
+    try {
+        DeviceGuard g(s->device);
+        if (!ready) HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(ready, (hipStream_t)hip_stream));
+    } catch (const Error &e) {
+        if (ready) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->free_events.push_back(ready);
+        }
+        return fail(e);
+    }
     Request *r = new Request();
+    r->ready = ready;
     r->h = h;
     r->op = op;
     r->dtype = dtype;
@@ -2286,14 +2488,20 @@ int mlfma_server_submit(mlfma_server s, mlfma_handle h, int op, int dtype, long 
     r->ldx = ldx;
     r->ldy = ldy;
     r->t_submit = Clock::now();
+    long long t = 0;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        r->ticket = s->next_ticket++;
+        if (s->stop) {
+            s->free_events.push_back(ready);
+            delete r;
+            return fail(Error(MLFMA_ERR_STATE, "the server is being destroyed"));
+        }
+        t = r->ticket = s->next_ticket++;
         s->reqs[r->ticket] = r;
         s->queue.push_back(r);
     }
     s->cv_sched.notify_all();
-    *ticket = r->ticket;
+    *ticket = t;
     return MLFMA_OK;
 }
 
@@ -2306,15 +2514,26 @@ int mlfma_server_wait(mlfma_server s, long long ticket, double timeout_s, double
     if (it == s->reqs.end()) return fail(Error(MLFMA_ERR_ARG, "unknown ticket"));
     Request *r = it->second;
     auto pred = [&] { return r->state == 2 || r->state < 0; };
+    s->waiters++;
+    bool finished = true;
     if (timeout_s < 0) s->cv_done.wait(lk, pred);
-    else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred))
+    else finished = s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred);
+    if (!finished) {
+        s->waiters--;
+        s->cv_done.notify_all();
+        lk.unlock();
         return fail(Error(MLFMA_ERR_STATE, "request not finished within the timeout"));
+    }
     const int st = r->state;
     if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
     if (batch_rhs) *batch_rhs = r->batch_rhs;
     s->reqs.erase(it);
-    std::string why = s->thread_error;
+    const std::string why = r->error;
+    if (r->ready) s->free_events.push_back(r->ready);
     delete r;
+    s->waiters--;
+    s->cv_done.notify_all();     // mlfma_server_destroy waits for the last waiter to leave
+    lk.unlock();
     if (st < 0) return fail(Error(st, why.empty() ? "request failed" : why));
     return MLFMA_OK;
 }
@@ -2355,7 +2574,27 @@ int mlfma_server_destroy(mlfma_server s)
         }
         if (s->capture) (void)hipStreamDestroy(s->capture);
     }
-    for (auto &kv : s->reqs) delete kv.second;
+    {
+        // requests still queued or running fail; threads waiting for them
+        // return before the server is freed
+        std::unique_lock<std::mutex> lk(s->mu);
+        for (auto &kv : s->reqs)
+            if (kv.second->state == 0 || kv.second->state == 1) {
+                kv.second->error = "the server was destroyed before the request finished";
+                kv.second->state = MLFMA_ERR_STATE;
+                kv.second->t_done = Clock::now();
+            }
+        s->cv_done.notify_all();
+        s->cv_done.wait(lk, [&] { return s->waiters == 0; });
+    }
+    {
+        DeviceGuard g(s->device);
+        for (auto &kv : s->reqs) {
+            if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+            delete kv.second;
+        }
+        for (auto e : s->free_events) (void)hipEventDestroy(e);
+    }
     delete s;
     return MLFMA_OK;
 }

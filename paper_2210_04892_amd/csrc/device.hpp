@@ -227,6 +227,13 @@ template <class T>
 void krylov_axpby(const cpx<double> *a, const cpx<T> *x, long long ldx, const cpx<double> *b, const cpx<T> *z,
                   long long ldz, cpx<T> *y, long long ldy, long long n, int nrhs, hipStream_t s);
 
+// Sparse (CSR) times a column-major block: y(i, r) = alpha * sum_k val[k]
+// x(col[k], r) (+ y(i, r) with accumulate), rows i < nrows.
+template <class T>
+void launch_csr_spmm(long long nrows, int nrhs, const long long *ptr, const int *col, const cpx<T> *val,
+                     const cpx<T> *x, long long ldx, cpx<T> *y, long long ldy, double alpha, bool accumulate,
+                     hipStream_t s);
+
 template <class T>
 void launch_disagg_mid(int nchild, int mid_len, int Kp, const int *parent, const int *oct, const cpx<T> *shift,
                        const int *st, const int *col, const T *w, const cpx<T> *Vp, cpx<T> *mid, int nrhs,

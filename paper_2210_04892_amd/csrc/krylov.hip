@@ -115,9 +115,44 @@ __global__ __launch_bounds__(KT) void k_axpby(const cpx<double> *__restrict__ a,
     y[(long long)r * ldy + k] = {(T)re, (T)im};
 }
 
+// y(i, r) = alpha * sum_k val[k] x(col[k], r) over row i's entries of a CSR
+// matrix (plus y(i, r) when accumulate); thread per (row, right-hand side),
+// rows fastest so a wave writes consecutive elements of one column.
+template <class T>
+__global__ __launch_bounds__(KT) void k_csr_spmm(long long nrows, int nrhs, const long long *__restrict__ ptr,
+                                                 const int *__restrict__ col, const cpx<T> *__restrict__ val,
+                                                 const cpx<T> *__restrict__ x, long long ldx, cpx<T> *__restrict__ y,
+                                                 long long ldy, double alpha, int accumulate)
+{
+    const long long g = (long long)blockIdx.x * KT + threadIdx.x;
+    if (g >= nrows * nrhs) return;
+    const int r = (int)(g / nrows);
+    const long long i = g % nrows;
+    const cpx<T> *xr = x + (long long)r * ldx;
+    double re = 0, im = 0;
+    for (long long k = ptr[i]; k < ptr[i + 1]; k++) {
+        const cpx<T> a = val[k], b = xr[col[k]];
+        re += (double)a.re * b.re - (double)a.im * b.im;
+        im += (double)a.re * b.im + (double)a.im * b.re;
+    }
+    cpx<T> &o = y[(long long)r * ldy + i];
+    if (accumulate) o = {(T)((double)o.re + alpha * re), (T)((double)o.im + alpha * im)};
+    else o = {(T)(alpha * re), (T)(alpha * im)};
+}
+
 inline unsigned blocks(long long n) { return (unsigned)((n + KT - 1) / KT); }
 
 }  // namespace
+
+template <class T>
+void launch_csr_spmm(long long nrows, int nrhs, const long long *ptr, const int *col, const cpx<T> *val,
+                     const cpx<T> *x, long long ldx, cpx<T> *y, long long ldy, double alpha, bool accumulate,
+                     hipStream_t s)
+{
+    if (nrows <= 0) return;
+    hipLaunchKernelGGL(k_csr_spmm<T>, dim3(blocks(nrows * nrhs)), dim3(KT), 0, s, nrows, nrhs, ptr, col, val, x, ldx,
+                       y, ldy, alpha, accumulate ? 1 : 0);
+}
 
 template <class T>
 void krylov_dots(const cpx<T> *V, long long vstride, long long ldv, int nv, const cpx<T> *w, long long ldw, long long n,
@@ -150,7 +185,9 @@ void krylov_axpby(const cpx<double> *a, const cpx<T> *x, long long ldx, const cp
     template void krylov_combine<T>(const cpx<T> *, long long, long long, int, const cpx<double> *, double,       \
                                     cpx<T> *, long long, long long, int, hipStream_t);                             \
     template void krylov_axpby<T>(const cpx<double> *, const cpx<T> *, long long, const cpx<double> *,           \
-                                  const cpx<T> *, long long, cpx<T> *, long long, long long, int, hipStream_t);
+                                  const cpx<T> *, long long, cpx<T> *, long long, long long, int, hipStream_t);   \
+    template void launch_csr_spmm<T>(long long, int, const long long *, const int *, const cpx<T> *,             \
+                                     const cpx<T> *, long long, cpx<T> *, long long, double, bool, hipStream_t);
 KRYLOV_INST(float)
 KRYLOV_INST(double)
 

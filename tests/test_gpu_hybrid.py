@@ -1,0 +1,131 @@
+"""The hybrid solver's product of the reduced system (eq. 52, Sec. II-E
+steps 2(a)-(e)) on the GPU: y = (C - D_xl Q^-1 D_lx) x with C by MLFMA and
+a seeded sparse stand-in for the HDG side (sparse couplings D_lx, D_xl and
+a sparse Hermitian positive definite Q solved by the caller).
+
+References: the oracle's dense C plus a dense numpy evaluation of the
+sparse term.  The sparse term alone (the difference of the hybrid and the
+plain product on the same x) is plain sparse arithmetic and must agree to
+rounding; the whole product to the MLFMA tolerance."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+K0 = 2 * np.pi
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _stand_in(n2, n_hdg, seed):
+    """Sparse D_lx (n_hdg x 2N, about 3 entries a row), D_xl (2N x n_hdg,
+    about 3 a row) and Q = B B^H + 2 I with B sparse (Hermitian positive
+    definite), all complex, from the seed."""
+    rng = np.random.default_rng(seed)
+
+    def rand_sparse(m, n, per_row):
+        rows = np.repeat(np.arange(m), per_row)
+        cols = rng.integers(0, n, size=m * per_row)
+        vals = rng.standard_normal(m * per_row) + 1j * rng.standard_normal(m * per_row)
+        return sp.csr_matrix((vals, (rows, cols)), shape=(m, n))
+
+    D_lx = rand_sparse(n_hdg, n2, 3)
+    D_xl = rand_sparse(n2, n_hdg, 3)
+    B = rand_sparse(n_hdg, n_hdg, 4)
+    Q = (B @ B.conj().T + 2.0 * sp.identity(n_hdg)).tocsr()
+    return D_lx, D_xl, Q
+
+
+def _setup(name_mesh, n_hdg, seed, max_rhs):
+    torch = _torch()
+    import paper_2210_04892_amd as mf
+    v, t = name_mesh
+    g = mf.Geometry(v, t, k=K0, max_rhs=max_rhs).precompute()
+    n2 = 2 * g.n_rwg
+    D_lx, D_xl, Q = _stand_in(n2, n_hdg, seed)
+    Qinv = np.linalg.inv(Q.toarray())
+    return torch, mf, g, D_lx, D_xl, Q, Qinv
+
+
+def test_hybrid_product_and_solve():
+    v, t = synth.icosphere(6, 0.5)
+    torch, mf, g, D_lx, D_xl, Q, Qinv = _setup((v, t), 700, 81, 3)
+    n2 = 2 * g.n_rwg
+    x = synth.gaussian_coeffs(n2, 3, 82)
+    Cx = oracle.matvec(v, t, K0, x, op=oracle.OP_C)
+    # scale the coupling so that the sparse term is as large as C x
+    corr0 = -(D_xl @ (Qinv @ (D_lx @ x)))
+    D_xl = D_xl * (np.linalg.norm(Cx) / np.linalg.norm(corr0))
+    corr = -(D_xl @ (Qinv @ (D_lx @ x)))
+    calls = []
+    Qinv_dev = {torch.complex128: torch.from_numpy(Qinv).cuda()}
+    Qinv_dev[torch.complex64] = Qinv_dev[torch.complex128].to(torch.complex64)
+
+    def solve(b, xq):           # the caller's Q^-1: a dense stand-in for a sparse direct solve
+        calls.append(b.shape[0])
+        xq.copy_((Qinv_dev[b.dtype] @ b.t().contiguous()).t())
+
+    hy = mf.Hybrid(g, 700, D_lx, D_xl, solve, max_rhs=3)
+    for dtype, tol_sparse in ((torch.complex128, 1e-12), (torch.complex64, 2e-6)):
+        xt = torch.from_numpy(x).to(dtype).cuda()
+        yh = hy.matvec(xt).cpu().numpy().astype(np.complex128)
+        yc = g.matvec(xt).cpu().numpy().astype(np.complex128)
+        torch.cuda.synchronize()
+        e_sparse = _rel(yh - yc, corr)
+        e_full = _rel(yh, Cx + corr)
+        print("[gpu] hybrid %s: sparse term rel err %.2e, whole product vs oracle %.2e"
+              % (dtype, e_sparse, e_full), flush=True)
+        assert e_sparse <= tol_sparse
+        assert e_full <= 1e-3
+    assert calls and all(c == 3 for c in calls)
+    # GMRES on the reduced system for two plane waves: the oracle's dense
+    # reduced operator applied to the GPU solution reproduces b
+    khat, pol = synth.plane_waves(2, 83)
+    b = oracle.plane_wave_rhs(v, t, K0, khat, pol)
+    for dtype, tol, check in ((torch.complex128, 1e-6, 2e-3), (torch.complex64, 1e-3, 3e-3)):
+        xs, its, rel = hy.gmres(torch.from_numpy(np.ascontiguousarray(b)).to(dtype).cuda(), restart=40,
+                                max_iters=400, tol=tol)
+        xs = xs.cpu().numpy().astype(np.complex128)
+        red = oracle.matvec(v, t, K0, xs, op=oracle.OP_C) - D_xl @ (Qinv @ (D_lx @ xs))
+        err = _rel(red, b)
+        print("[gpu] hybrid gmres %s: %d steps, true residual %s, oracle reduced |A x - b|/|b| = %.2e"
+              % (dtype, its, " ".join("%.1e" % r for r in rel), err), flush=True)
+        assert np.all(rel <= tol * 1.001)
+        assert err <= check
+    hy.close()
+    g.release()
+
+
+def test_hybrid_rejects_bad_input_and_failed_solve():
+    v, t = synth.icosphere(4, 0.5)
+    torch, mf, g, D_lx, D_xl, Q, Qinv = _setup((v, t), 50, 84, 1)
+    n2 = 2 * g.n_rwg
+    bad = sp.csr_matrix((np.ones(1), ([0], [n2 + 3])), shape=(50, n2 + 4))
+    with pytest.raises(mf.MlfmaError) as e:
+        mf.Hybrid(g, 50, (bad.indptr, bad.indices, bad.data), D_xl, lambda b, x: None)
+    assert e.value.code == -1
+
+    def failing(b, xq):
+        raise RuntimeError("solver unavailable")
+
+    hy = mf.Hybrid(g, 50, D_lx, D_xl, failing)
+    x = torch.zeros(n2, dtype=torch.complex128, device="cuda")
+    with pytest.raises(mf.MlfmaError) as e:
+        hy.matvec(x)
+    assert e.value.code == -1 and "solve" in str(e.value)
+    hy.close()
+    torch.cuda.synchronize()
+    g.release()

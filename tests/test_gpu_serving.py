@@ -92,3 +92,62 @@ def test_budget_admission():
         srv.wait(srv.submit(geoms[0], x, torch.empty_like(x)))
     assert e.value.code == -3
     srv.close()
+
+
+def test_submit_is_ordered_after_the_callers_stream():
+    """x is produced on torch's current stream by work still queued when the
+    request is submitted (a long chain of products followed by the copy that
+    writes x): the server must read x only after that work, so the served
+    result equals the product of the final x computed alone."""
+    torch = _torch()
+    import paper_2210_04892_amd as mf
+    geoms = _geoms(mf)
+    g = geoms[1]
+    n2 = 2 * g.n_rwg
+    x_true = torch.from_numpy(synth.gaussian_coeffs(n2, 3, 61).T.copy()).to(torch.complex64).cuda()
+    srv = mf.Server(streams=2, max_batch_rhs=16)
+    for rep in range(3):
+        x = torch.zeros_like(x_true)
+        y = torch.empty_like(x_true)
+        torch.cuda.synchronize()
+        a = torch.randn(2048, 2048, device="cuda")
+        for _ in range(40):                  # about 20 ms of queued work ahead of the copy
+            a = torch.tanh(a @ a) * 0.5
+        x.copy_(x_true + 0 * a[0, 0])        # written only after the chain
+        t = srv.submit(g, x, y)
+        srv.wait(t)
+        alone = g.matvec(x_true.t()).t()
+        torch.cuda.synchronize()
+        d = float(torch.linalg.norm(alone - y) / torch.linalg.norm(alone))
+        print("[gpu] submit after queued work, rep %d: rel diff %.2e" % (rep, d), flush=True)
+        assert d <= 2e-5, d
+    srv.close()
+
+
+def test_destroy_with_pending_requests():
+    """Requests still queued when the server is destroyed fail cleanly and
+    a thread blocked waiting for one of them returns (no use after free)."""
+    torch = _torch()
+    import paper_2210_04892_amd as mf
+    geoms = _geoms(mf)
+    g = geoms[2]
+    x = torch.randn(2, 2 * g.n_rwg, dtype=torch.complex64, device="cuda")
+    srv = mf.Server(streams=1, max_batch_rhs=2)
+    ys = [torch.empty_like(x) for _ in range(12)]
+    tickets = [srv.submit(g, x, y) for y in ys]
+    outcome = {}
+
+    def waiter():
+        try:
+            srv.wait(tickets[-1])
+            outcome["rc"] = 0
+        except mf.MlfmaError as e:
+            outcome["rc"] = e.code
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    srv.close()
+    th.join(timeout=60)
+    assert not th.is_alive()
+    assert outcome["rc"] in (0, -5)
+    torch.cuda.synchronize()

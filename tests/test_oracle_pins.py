@@ -237,6 +237,66 @@ def test_touching_pairs_converged(rel):
             assert np.abs(auto[op] - hi[op]).max() <= 2e-12 * scale
 
 
+# ----------------------------------------- P-F: the two touching-pair routes
+def _touching_sample(v, t, seed, ntest=3):
+    """Seeded test triangles (one of them where the surface is curved, when
+    it has curved parts) with their coincident pair, one edge-adjacent and
+    two vertex-adjacent source triangles."""
+    rng = np.random.default_rng(seed)
+    nrm = np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]])
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    curved = np.where(np.abs(nrm).max(axis=1) < 0.99)[0]
+    picks = list(rng.choice(len(t), ntest - 1, replace=False))
+    picks.append(int(rng.choice(curved)) if len(curved) else int(rng.integers(len(t))))
+    out = []
+    for ti in picks:
+        sets = {1: [], 2: [], 3: []}
+        for j in range(len(t)):
+            c = len(set(t[ti]) & set(t[j]))
+            if c:
+                sets[c].append(j)
+        out += [(ti, sets[3][0], 3), (ti, sets[2][rng.integers(len(sets[2]))], 2)]
+        out += [(ti, j, 1) for j in rng.choice(sets[1], 2, replace=False)]
+    return out
+
+
+@pytest.mark.parametrize("name", ["icosphere", "rounded_box"])
+def test_touching_routes_agree(name):
+    """The oracle's two independent routes for pairs that share the
+    triangle, an edge or a vertex agree to 1e-11 of the pair's largest entry
+    for every operator: relative-coordinate (Duffy-type) transformations with
+    the order search, and singularity subtraction with closed-form static
+    integrals over the source triangle and graded rules over the test
+    triangle."""
+    if name == "icosphere":
+        v, t = synth.icosphere(8, 0.5)
+    else:
+        v, t = synth.rounded_box((1.0, 1.0, 0.5), 0.2, 0.073)
+    worst = {1: 0.0, 2: 0.0, 3: 0.0}
+    for ti, sj, kind in _touching_sample(v, t, 91):
+        a = oracle.pair_integrals(t[ti], v[t[ti]], t[sj], v[t[sj]], K0)
+        b = oracle.pair_integrals_sub(t[ti], v[t[ti]], t[sj], v[t[sj]], K0)
+        scale = np.abs(a).max()
+        worst[kind] = max(worst[kind], float(np.abs(a - b).max() / scale))
+    print("routes: max |diff| / pair scale by shared vertices:", worst)
+    assert max(worst.values()) <= 1e-11
+
+
+def test_subtraction_route_in_the_product():
+    """oracle.matvec with route="subtraction" equals the default route's
+    product on unit columns (the near field of two RWGs, touching pairs
+    included) to the routes' agreement."""
+    v, t = synth.icosphere(4, 0.5)
+    N = 3 * len(t) // 2
+    x = np.zeros((2 * N, 2), complex)
+    x[5, 0] = 1.0
+    x[N + 77, 1] = 1.0j
+    for op in (oracle.OP_C, oracle.OP_EM):
+        a = oracle.matvec(v, t, K0, x, op=op)
+        b = oracle.matvec(v, t, K0, x, op=op, route="subtraction")
+        assert np.abs(a - b).max() <= 1e-11 * np.abs(a).max()
+
+
 # ------------------------------------------------------------ P-B symmetry
 @pytest.mark.parametrize("mesh", [synth.tetrahedron, synth.octahedron, synth.icosahedron])
 def test_T_and_K_symmetric(mesh):
@@ -399,6 +459,58 @@ def test_box_rule_counts(m, r, levels, boxes, near):
     assert len({tuple(c) for c in coords}) == boxes
     d = np.abs(coords[:, None, :] - coords[None, :, :]).max(axis=2)
     assert int((d <= 1).sum()) == near
+
+
+# Translations per level (levels >= 2, finest first) of the quarter-wavelength
+# octree, counted from generated meshes before any code of this repository
+# existed: icosphere r = 0.5 (frequency 8), r = 3 (frequency 36), r = 8
+# (frequency 96).
+TRANSLATION_COUNTS = [
+    (8, 0.5, {2: 2504}),
+    (36, 3.0, {5: 104448, 4: 28176, 3: 3632, 2: 2256}),
+    (96, 8.0, {6: 754008, 5: 210960, 4: 54000, 3: 12216, 2: 2504}),
+]
+
+
+@pytest.mark.parametrize("m,r,counts", TRANSLATION_COUNTS)
+def test_interaction_class_counts(m, r, counts):
+    """The oracle's interaction class of an RWG pair (near, or the level at
+    which their boxes are first well separated: the split of the per-level
+    error), aggregated to box pairs per level, reproduces the recorded
+    translation counts of the three spheres."""
+    v, t = synth.icosphere(m, r)
+    assert oracle.class_box_pairs(v, t, 0.25) == counts
+
+
+def _interaction_lists_brute_force(coords, levels):
+    """Translations per level straight from the definition: B is in the
+    interaction list of A at level l when both hold RWGs, their parents are
+    adjacent (Chebyshev distance <= 1) and A and B are not."""
+    out = {}
+    for l in range(2, levels):
+        sh = levels - 1 - l
+        boxes = np.unique(coords >> sh, axis=0)
+        d = np.abs(boxes[:, None, :] - boxes[None, :, :]).max(axis=2)
+        dp = np.abs((boxes[:, None, :] >> 1) - (boxes[None, :, :] >> 1)).max(axis=2)
+        out[l] = int(((d >= 2) & (dp <= 1)).sum())
+    return out
+
+
+@pytest.mark.parametrize("name", ["sphere_r0.5", "box", "two_bodies"])
+def test_interaction_classes_match_definition(name):
+    """Same aggregation against the interaction lists computed by brute force
+    over the occupied boxes of every level, on surfaces without recorded
+    counts (the rounded box, two disjoint spheres)."""
+    if name == "sphere_r0.5":
+        v, t = synth.icosphere(8, 0.5)
+    elif name == "box":
+        v, t = synth.rounded_box((2.0, 2.0, 0.5), 0.1, 0.1)
+    else:
+        v, t = synth.scene(synth.icosphere(6, 0.5) + ((0, 0, 0),), synth.icosphere(4, 0.3) + ((1.4, 0.2, -0.1),))
+    coords, levels = oracle.leaf_boxes(v, t, 0.25)
+    want = _interaction_lists_brute_force(coords, levels)
+    assert levels >= 4 or name == "sphere_r0.5"
+    assert oracle.class_box_pairs(v, t, 0.25) == want
 
 
 def test_plane_wave_rhs_matches_projection():
