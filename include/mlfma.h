@@ -67,10 +67,13 @@ typedef struct {
     int max_rhs;         /* right-hand sides the workspace is sized for (1)         */
     int device;          /* HIP device ordinal (-1: the current device)             */
     unsigned long long hbm_budget_bytes;   /* 0 = no limit                          */
+    int trans_kernel;    /* translation kernel: MLFMA_TRANS_AUTO (autotuner picks)   */
 } mlfma_options;
+enum { MLFMA_TRANS_AUTO = 0, MLFMA_TRANS_TILED = 1, MLFMA_TRANS_GROUPS = 2 };
 
 /* Fill *opt with defaults: k = 2 pi, leaf 0.25, d0 = 3, order 8, extra 2,
- * one RHS, current device, no budget.  Returns MLFMA_ERR_ARG on NULL. */
+ * one RHS, current device, no budget, autotuned translation kernel.  Returns
+ * MLFMA_ERR_ARG on NULL. */
 int mlfma_options_default(mlfma_options *opt);
 
 /*
@@ -377,12 +380,15 @@ int mlfma_level_info(mlfma_handle h, int level, long long info[6]);
  * mlfma_precompute_nearfield. */
 int mlfma_near_info(mlfma_handle h, long long info[4]);
 
-/* Translation tile shape chosen by the autotuner that mlfma_build_tree runs
- * (Sec. II-E diagonal translations; every shape within the kernel's LDS and
- * register limits is timed on the device with the handle's right-hand-side
- * count, capped at 16): shape[0] = target boxes per tile (= waves per
- * workgroup), shape[1] = source boxes per LDS batch, shape[2] = right-hand
- * sides per lane; *ms (may be NULL) = the timed translation of all levels,
+/* Translation kernel and shape chosen by the autotuner that mlfma_build_tree
+ * runs (Sec. II-E diagonal translations; every shape of the two kernels
+ * within their LDS and register limits is timed on the device with the
+ * handle's right-hand-side count, capped at 16).  LDS-tiled kernel:
+ * shape[0] = target boxes per tile (= waves per workgroup), shape[1] =
+ * source boxes per LDS batch; sibling-group kernel (sums of all targets of a
+ * group of siblings kept in registers, sources streamed once per group):
+ * shape[0] = targets per group, shape[1] = 0.  shape[2] = right-hand sides
+ * per lane; *ms (may be NULL) = the timed translation of all levels,
  * milliseconds.  dtype MLFMA_C128 or MLFMA_C64; MLFMA_ERR_ARG otherwise. */
 int mlfma_tuning(mlfma_handle h, int dtype, int shape[3], double *ms);
 

@@ -35,7 +35,7 @@ class MlfmaError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("wavenumber", ctypes.c_double), ("leaf_size", ctypes.c_double), ("digits", ctypes.c_int),
                 ("interp_order", ctypes.c_int), ("leaf_extra_L", ctypes.c_int), ("max_rhs", ctypes.c_int),
-                ("device", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_ulonglong)]
+                ("device", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_ulonglong), ("trans_kernel", ctypes.c_int)]
 
 
 class BatchItem(ctypes.Structure):
@@ -127,8 +127,9 @@ class Geometry:
     resident on one GPU (mlfma_build_tree / mlfma_precompute_nearfield)."""
 
     def __init__(self, verts, tris, k=2 * math.pi, leaf=0.25, digits=3, interp_order=8, leaf_extra_L=2,
-                 max_rhs=1, device=None, hbm_budget_bytes=0):
+                 max_rhs=1, device=None, hbm_budget_bytes=0, trans_kernel="auto"):
         o = default_options()
+        o.trans_kernel = {"auto": 0, "tiled": 1, "groups": 2}[trans_kernel]
         o.wavenumber = k
         o.leaf_size = leaf
         o.digits = digits
@@ -217,8 +218,9 @@ class Geometry:
                 "leaf_boxes": int(info[3])}
 
     def tuning(self):
-        """Translation tile shape picked by the autotuner, per precision:
-        {"c64": (targets per tile, sources per batch, rhs per lane, ms), "c128": ...}."""
+        """Translation kernel and shape picked by the autotuner, per precision:
+        {"c64": (targets per tile or group, sources per LDS batch (0 = the
+        sibling-group kernel), rhs per lane, ms), "c128": ...}."""
         out = {}
         for name, dt in (("c64", C64), ("c128", C128)):
             sh = np.zeros(3, np.int32)

@@ -80,10 +80,15 @@ struct Prec {
     T *id_w = nullptr;                            // identity terms (gram, gx)
     std::vector<PrecLevel<T>> lv;
     int trans_tmax = 0, trans_smax = 0, trans_rb = 1;   // translation tile shape (autotuned)
+    int trans_group = 0;                          // > 0: sibling-group kernel with this many targets per group
     double trans_ms = 0;                          // its timed translation, ms
 };
 
 struct IntLevel {
+    // sibling groups of the register-blocked translation, for 4 and 8 targets
+    int g_ngroup[2] = {0, 0};
+    int *g_first[2] = {nullptr, nullptr}, *g_count[2] = {nullptr, nullptr}, *g_rec[2] = {nullptr, nullptr};
+    int *g_src[2] = {nullptr, nullptr}, *g_off[2] = {nullptr, nullptr};
     int *il_start = nullptr, *il_box = nullptr, *il_off = nullptr;
     int *child_start = nullptr, *parent = nullptr, *oct = nullptr;
     int *ath_s = nullptr, *ath_c = nullptr, *aph_s = nullptr, *aph_c = nullptr;
@@ -369,12 +374,52 @@ TransArgs<T> trans_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level)
     return ta;
 }
 
-// Autotuner of the translation tile shape: every candidate (targets per
-// tile 4/8/16, LDS batch of 16/32/64 KB, 1/2/4 right-hand sides per lane)
-// that satisfies the kernel's limits is built and its translation of all
-// levels timed on the device (HIP events, one warm-up and three timed
-// launches with the right-hand-side count the handle is built for, capped at
-// 16); the fastest shape is kept.
+// arguments of the sibling-group translation (tg targets per group)
+template <class T>
+GroupArgs<T> group_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, int tg, int rb)
+{
+    const Tree &tr = c->tr;
+    const int gi = tg == 8 ? 1 : 0;
+    GroupArgs<T> ga;
+    ga.tg = tg;
+    ga.rb = rb;
+    for (int l = 2; l < tr.levels; l++) {
+        if (only_level >= 0 && l != only_level) continue;
+        const IntLevel &I = c->lv[l];
+        GroupLevel<T> &d = ga.lv[ga.nlev++];
+        d.K = tr.lv[l].K;
+        d.ngroup = I.g_ngroup[gi];
+        d.first_tgt = I.g_first[gi];
+        d.count = I.g_count[gi];
+        d.rec_start = I.g_rec[gi];
+        d.src = I.g_src[gi];
+        d.off = I.g_off[gi];
+        d.trans = P.lv[l].trans;
+        d.U = (const cpx<T> *)w.U[l];
+        d.V = (cpx<T> *)w.V[l];
+    }
+    return ga;
+}
+
+// the translation of all levels (or of only_level) with the tuned kernel
+template <class T>
+void launch_translation(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, int nrhs, hipStream_t st)
+{
+    if (P.trans_group > 0) {
+        if (!launch_translate_groups<T>(group_args<T>(c, P, w, only_level, P.trans_group, P.trans_rb), nrhs, st))
+            throw Error(MLFMA_ERR_STATE, "invalid sibling-group translation shape");
+    } else if (!launch_translate_tiled<T>(trans_args<T>(c, P, w, only_level), nrhs, st)) {
+        throw Error(MLFMA_ERR_STATE, "translation tiles missing");
+    }
+}
+
+// Autotuner of the translation: every candidate of the LDS-tiled kernel
+// (targets per tile 4/8/16, LDS batch of 16/32/64 KB, 1/2/4 right-hand sides
+// per lane) that satisfies the kernel's limits, and of the sibling-group
+// kernel (4 or 8 targets per group, 1/2/4 right-hand sides per lane), is
+// timed on the device (HIP events, one warm-up and three timed launches of
+// the translation of all levels with the right-hand-side count the handle
+// is built for, capped at 16); the fastest is kept.
 template <class T>
 void tune_translation(mlfma_ctx *c, Prec<T> &P)
 {
@@ -394,6 +439,7 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
     int bt = 0, bs = 0, bb = 1;
     for (int rb : {1, 2, 4}) {
         if (rb > 1 && (trans_rw(nrhs) != 4 || nrhs < 4 * rb)) continue;
+        if (c->opt.trans_kernel == MLFMA_TRANS_GROUPS) break;
         for (int tmax : {4, 8, 16})
             for (int kb : {16, 32, 64}) {
                 const int smax = (kb * 1024) / (int)(2 * 64 * rb * sizeof(cpx<T>));
@@ -426,10 +472,38 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
                 }
             }
     }
+    int bg = 0;
+    for (int tg : {4, 8})
+        for (int rb : {1, 2, 4}) {
+            if (c->opt.trans_kernel == MLFMA_TRANS_TILED) break;
+            if (rb > 1 && (trans_rw(nrhs) != 4 || nrhs < 4 * rb)) continue;
+            if (sizeof(T) == 8 && tg * rb > 8) continue;   // register budget of the double-precision sums
+            const GroupArgs<T> ga = group_args<T>(c, P, c->ws, -1, tg, rb);
+            if (!launch_translate_groups<T>(ga, nrhs, st)) throw Error(MLFMA_ERR_HIP, "invalid sibling-group shape");
+            HIPCHK(hipEventRecord(e0, st));
+            for (int i = 0; i < 3; i++) launch_translate_groups<T>(ga, nrhs, st);
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bg = tg;
+                bb = rb;
+            }
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(st);
-    upload_trans_tiles<T>(c, P, bt, bs, nullptr);
+    if (bg > 0) {
+        // the tiled kernel's tables of its best shape are not needed; keep a
+        // small valid set so that the kernel stays callable
+        upload_trans_tiles<T>(c, P, 8, 16, nullptr);
+        P.trans_group = bg;
+    } else {
+        upload_trans_tiles<T>(c, P, bt, bs, nullptr);
+        P.trans_group = 0;
+    }
     P.trans_rb = bb;
     P.trans_ms = best / 3;
 }
@@ -470,6 +544,16 @@ void build_device_tables(mlfma_ctx *c)
         I.il_off = c->upload(L.il_off);
         I.parent = c->upload(L.parent);
         I.oct = c->upload(L.child_oct);
+        for (int gi = 0; gi < 2; gi++) {
+            GroupTiles gt;
+            build_group_tiles(L, gi ? 8 : 4, gt);
+            I.g_ngroup[gi] = (int)gt.first.size();
+            I.g_first[gi] = c->upload(gt.first);
+            I.g_count[gi] = c->upload(gt.count);
+            I.g_rec[gi] = c->upload(gt.rec_start);
+            I.g_src[gi] = c->upload(gt.src);
+            I.g_off[gi] = c->upload(gt.off);
+        }
         std::vector<double> khat;
         level_directions(L, khat);
         // translation operators for the 7^3 offsets (unused entries stay 0)
@@ -1041,7 +1125,7 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     // launches fewer on the critical path
     const bool fold = overlap && nrhs == 1;
     mark(0);
-    if (!fold) launch_perm_in<T>(x, ldx, X, c->perm, N, nrhs, st);
+    if (!fold) launch_perm_in<T>(x, ldx, X, c->perm, c->iperm, N, nrhs, st);
     mark(1);
     auto near = [&](hipStream_t sn) {
         const cpx<T> *vals = op == MLFMA_OP_EM ? P.near_em : P.near_c;
@@ -1102,8 +1186,7 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
         for (int l = 2; l <= leafl; l++)
             if (only_level >= 0 && l != only_level)
                 launch_zero<T>((cpx<T> *)w.V[l], (long long)tr.lv[l].nbox * tr.lv[l].K * 2 * nrhs, st);
-        if (!launch_translate_tiled<T>(trans_args<T>(c, P, w, only_level), nrhs, st))
-            throw Error(MLFMA_ERR_STATE, "translation tiles missing");
+        launch_translation<T>(c, P, w, only_level, nrhs, st);
     }
     mark(5);
     if (far) {
@@ -1450,6 +1533,7 @@ int mlfma_options_default(mlfma_options *opt)
     opt->max_rhs = 1;
     opt->device = -1;
     opt->hbm_budget_bytes = 0;
+    opt->trans_kernel = MLFMA_TRANS_AUTO;
     return MLFMA_OK;
 }
 
@@ -1466,6 +1550,8 @@ int mlfma_build_tree(const double *verts, long long n_verts, const int *tris, lo
         if (opt) c->opt = *opt;
         else mlfma_options_default(&c->opt);
         if (c->opt.max_rhs < 1) throw Error(MLFMA_ERR_ARG, "max_rhs must be >= 1");
+        if (c->opt.trans_kernel < MLFMA_TRANS_AUTO || c->opt.trans_kernel > MLFMA_TRANS_GROUPS)
+            throw Error(MLFMA_ERR_ARG, "unknown translation kernel");
         build_surface(c->s, verts, n_verts, tris, n_tris);
         build_rwg(c->s, c->r);
         build_tree(c->s, c->r, c->opt.wavenumber, c->opt.leaf_size, c->opt.digits, c->opt.interp_order,
@@ -1893,8 +1979,9 @@ int mlfma_level_info(mlfma_handle h, int level, long long info[6])
 int mlfma_tuning(mlfma_handle h, int dtype, int shape[3], double *ms)
 {
     if (!h || !shape || (dtype != MLFMA_C128 && dtype != MLFMA_C64)) return fail(Error(MLFMA_ERR_ARG, "bad argument"));
-    shape[0] = dtype == MLFMA_C64 ? h->p32.trans_tmax : h->p64.trans_tmax;
-    shape[1] = dtype == MLFMA_C64 ? h->p32.trans_smax : h->p64.trans_smax;
+    const int group = dtype == MLFMA_C64 ? h->p32.trans_group : h->p64.trans_group;
+    shape[0] = group > 0 ? group : (dtype == MLFMA_C64 ? h->p32.trans_tmax : h->p64.trans_tmax);
+    shape[1] = group > 0 ? 0 : (dtype == MLFMA_C64 ? h->p32.trans_smax : h->p64.trans_smax);
     shape[2] = dtype == MLFMA_C64 ? h->p32.trans_rb : h->p64.trans_rb;
     if (ms) *ms = dtype == MLFMA_C64 ? h->p32.trans_ms : h->p64.trans_ms;
     return MLFMA_OK;

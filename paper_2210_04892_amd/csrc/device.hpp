@@ -87,7 +87,8 @@ __host__ __device__ inline void axpy_to(cpx<T> &acc, T s, cpx<T> x)
 // Launchers of the hot path (matvec.hip).  X, Y internal vectors
 // [rwg][half][rhs]; U, V patterns [box][sample][component][rhs].
 template <class T>
-void launch_perm_in(const cpx<T> *x, long long ldx, cpx<T> *X, const int *perm, int N, int nrhs, hipStream_t s);
+void launch_perm_in(const cpx<T> *x, long long ldx, cpx<T> *X, const int *perm, const int *iperm, int N, int nrhs,
+                    hipStream_t s);
 template <class T>
 void launch_perm_out(const cpx<T> *Y, cpx<T> *y, long long ldy, const int *iperm, int N, int nrhs, hipStream_t s);
 template <class T>
@@ -157,6 +158,28 @@ struct TransArgs {
 // false when the tile shape is invalid
 template <class T>
 bool launch_translate_tiled(const TransArgs<T> &a, int nrhs, hipStream_t s);
+
+// Register-blocked translation over sibling groups (translate.hip; tables
+// of GroupTiles in setup.hpp): every lane keeps the sums of all targets of
+// its group and streams the group's source records, so a source value is
+// loaded once for all the targets whose interaction lists hold it.
+template <class T>
+struct GroupLevel {
+    int K = 0, ngroup = 0;
+    int nqc = 0, first = 0;     // sample chunks of a workgroup; first position per XCD (launcher)
+    const int *first_tgt = nullptr, *count = nullptr, *rec_start = nullptr, *src = nullptr;
+    const int *off = nullptr;   // per record tg offset ids, -1 = not in that target's list
+    const cpx<T> *trans = nullptr, *U = nullptr;
+    cpx<T> *V = nullptr;
+};
+template <class T>
+struct GroupArgs {
+    int nlev = 0, nblocks = 0, tg = 4, rb = 1;   // tg: targets per group (4 or 8); rb: RHS per lane
+    GroupLevel<T> lv[TRANS_MAXLEV];
+};
+// false when (tg, rb) has no kernel
+template <class T>
+bool launch_translate_groups(const GroupArgs<T> &a, int nrhs, hipStream_t s);
 // One octree step of aggregation (children at level l+1 -> parents at l) or
 // disaggregation (parents -> children), done per box and chunk of theta rows
 // in LDS (levels.hip).  Sample index = theta row * nph + phi column.

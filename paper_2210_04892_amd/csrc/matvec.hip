@@ -82,6 +82,45 @@ __global__ void k_perm_out(const cpx<T> *__restrict__ Y, cpx<T> *__restrict__ y,
     y[(long long)r * ldy + (long long)h * N + u] = Y[((long long)iperm[u] * 2 + h) * nrhs + r];
 }
 
+// Several right-hand sides: tiles of 64 user rows x 16 right-hand sides of
+// one half, transposed through LDS.  The internal side (RHS innermost) is
+// read or written as whole 16-element rows, the user side (column-major) as
+// runs of 64 consecutive rows per column; the permutation is applied to the
+// row index of the internal side (iperm: user RWG -> tree position).
+constexpr int PT_U = 64, PT_R = 16;
+template <class T, bool IN>
+__global__ __launch_bounds__(256) void k_perm_tile(const cpx<T> *__restrict__ src, long long ld,
+                                                   cpx<T> *__restrict__ dst, const int *__restrict__ iperm, int N,
+                                                   int nrhs)
+{
+    __shared__ cpx<T> tile[PT_U][PT_R + 1];
+    const int u0 = blockIdx.x * PT_U, h = blockIdx.y, r0 = blockIdx.z * PT_R;
+    const int nu = min(PT_U, N - u0), nr = min(PT_R, nrhs - r0);
+    if (IN) {
+        // user x (coalesced along u) -> tile -> X rows of 16 right-hand sides
+        for (int k = threadIdx.x; k < PT_U * PT_R; k += 256) {
+            const int rr = k / PT_U, ul = k % PT_U;
+            if (rr < nr && ul < nu) tile[ul][rr] = src[(long long)(r0 + rr) * ld + (long long)h * N + u0 + ul];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < PT_U * PT_R; k += 256) {
+            const int ul = k / PT_R, rr = k % PT_R;
+            if (rr < nr && ul < nu) dst[((long long)iperm[u0 + ul] * 2 + h) * nrhs + r0 + rr] = tile[ul][rr];
+        }
+    } else {
+        // Y rows of 16 right-hand sides -> tile -> user y (coalesced along u)
+        for (int k = threadIdx.x; k < PT_U * PT_R; k += 256) {
+            const int ul = k / PT_R, rr = k % PT_R;
+            if (rr < nr && ul < nu) tile[ul][rr] = src[((long long)iperm[u0 + ul] * 2 + h) * nrhs + r0 + rr];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < PT_U * PT_R; k += 256) {
+            const int rr = k / PT_U, ul = k % PT_U;
+            if (rr < nr && ul < nu) dst[(long long)(r0 + rr) * ld + (long long)h * N + u0 + ul] = tile[ul][rr];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- near field
 // One workgroup per leaf box; each wave owns rows of the box, its lanes
 // stride over the row's near columns (the concatenated RWG ranges of the
@@ -1093,14 +1132,25 @@ __global__ void k_zero(cpx<T> *__restrict__ p, long long n)
 static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 template <class T>
-void launch_perm_in(const cpx<T> *x, long long ldx, cpx<T> *X, const int *perm, int N, int nrhs, hipStream_t s)
+void launch_perm_in(const cpx<T> *x, long long ldx, cpx<T> *X, const int *perm, const int *iperm, int N, int nrhs,
+                    hipStream_t s)
 {
+    if (nrhs >= 4) {
+        const dim3 grid((N + PT_U - 1) / PT_U, 2, (nrhs + PT_R - 1) / PT_R);
+        hipLaunchKernelGGL((k_perm_tile<T, true>), grid, dim3(256), 0, s, x, ldx, X, iperm, N, nrhs);
+        return;
+    }
     long long n = (long long)N * 2 * nrhs;
     hipLaunchKernelGGL(k_perm_in<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, ldx, X, perm, N, nrhs);
 }
 template <class T>
 void launch_perm_out(const cpx<T> *Y, cpx<T> *y, long long ldy, const int *iperm, int N, int nrhs, hipStream_t s)
 {
+    if (nrhs >= 4) {
+        const dim3 grid((N + PT_U - 1) / PT_U, 2, (nrhs + PT_R - 1) / PT_R);
+        hipLaunchKernelGGL((k_perm_tile<T, false>), grid, dim3(256), 0, s, Y, ldy, y, iperm, N, nrhs);
+        return;
+    }
     long long n = (long long)N * 2 * nrhs;
     hipLaunchKernelGGL(k_perm_out<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, Y, y, ldy, iperm, N, nrhs);
 }
@@ -1320,7 +1370,8 @@ void launch_receive1_user(int op, int N, int K, const int *leaf_of, const cpx<T>
                                           int, cpx<T> *, cpx<T> *, hipStream_t);                                  \
     template void launch_receive1_user<T>(int, int, int, const int *, const cpx<T> *, const cpx<T> *, const T *,  \
                                           const cpx<T> *, const cpx<T> *, cpx<T> *, const int *, hipStream_t);    \
-    template void launch_perm_in<T>(const cpx<T> *, long long, cpx<T> *, const int *, int, int, hipStream_t);     \
+    template void launch_perm_in<T>(const cpx<T> *, long long, cpx<T> *, const int *, const int *, int, int,     \
+                                    hipStream_t);                                                                 \
     template void launch_perm_out<T>(const cpx<T> *, cpx<T> *, long long, const int *, int, int, hipStream_t);    \
     template void launch_near_tile<T>(int, const int2 *, const int *, const int *, const int *, const long long *, \
                                       const cpx<T> *, const int *, const int *, const T *, const cpx<T> *, cpx<T> *, \

@@ -17,11 +17,18 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_probe_copy(const float4 *__restrict__ src, float4 *__restrict__ dst,
-                                                    long long n)
+// A workgroup copies one contiguous 16 KiB block: four 16-byte elements per
+// thread, consecutive threads on consecutive elements, all loads issued
+// before the stores.
+__global__ __launch_bounds__(256) void k_probe_copy(const f4 *__restrict__ src, f4 *__restrict__ dst, long long n)
 {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+    const long long base = (long long)blockIdx.x * 1024 + threadIdx.x;
+    f4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) v[u] = base + u * 256 < n ? src[base + u * 256] : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+        if (base + u * 256 < n) dst[base + u * 256] = v[u];
 }
 
 // Eight independent accumulator chains per wave keep the matrix unit busy;
@@ -97,8 +104,8 @@ extern "C" int mlfma_peak_probe(int kind, int device, double *value)
         const int iters = 4096;
         auto launch = [&]() {
             if (kind == 0)
-                hipLaunchKernelGGL(k_probe_copy, dim3(cus * 16), dim3(threads), 0, st, (const float4 *)a,
-                                   (float4 *)b, copy_bytes / 16);
+                hipLaunchKernelGGL(k_probe_copy, dim3((unsigned)(copy_bytes / 16 / 1024)), dim3(threads), 0, st,
+                                   (const f4 *)a, (f4 *)b, copy_bytes / 16);
             else if (kind == 1)
                 hipLaunchKernelGGL(k_probe_mfma, dim3(blocks), dim3(threads), 0, st, iters, 1.0f, (float *)a);
             else

@@ -606,6 +606,38 @@ void build_translation_tiles(const Level &L, int smax, int tmax, TransTiles &t)
     }
 }
 
+void build_group_tiles(const Level &L, int tg, GroupTiles &g)
+{
+    if (tg < 1 || tg > 16) throw Error(MLFMA_ERR_ARG, "bad sibling group size");
+    g = GroupTiles();
+    g.tg = tg;
+    g.rec_start.push_back(0);
+    std::vector<std::pair<int, int>> ent;   // (source box, target slot * 512 + offset id)
+    int A0 = 0;
+    while (A0 < L.nbox) {
+        int A1 = A0 + 1;
+        while (A1 < L.nbox && A1 - A0 < tg && L.parent[A1] == L.parent[A0]) A1++;
+        ent.clear();
+        for (int A = A0; A < A1; A++)
+            for (int e = L.il_start[A]; e < L.il_start[A + 1]; e++) {
+                if (L.il_off[e] < 0 || L.il_off[e] >= 343) throw Error(MLFMA_ERR_ARG, "bad interaction offset");
+                ent.push_back({L.il_box[e], (A - A0) * 512 + L.il_off[e]});
+            }
+        std::sort(ent.begin(), ent.end());
+        for (size_t i = 0; i < ent.size(); i++) {
+            if (i == 0 || ent[i].first != ent[i - 1].first) {
+                g.src.push_back(ent[i].first);
+                g.off.insert(g.off.end(), tg, -1);
+            }
+            g.off[(g.src.size() - 1) * tg + ent[i].second / 512] = ent[i].second % 512;
+        }
+        g.first.push_back(A0);
+        g.count.push_back(A1 - A0);
+        g.rec_start.push_back((int)g.src.size());
+        A0 = A1;
+    }
+}
+
 // ------------------------------------------------------- level-step chunks
 void plan_theta_chunks(const Csr &theta, int n_out, int nph, int rows0,
                        const std::function<size_t(int, int)> &lds, size_t lds_max, ChunkPlan &pl)

@@ -91,6 +91,22 @@ struct TransTiles {
 };
 void build_translation_tiles(const Level &L, int smax, int tmax, TransTiles &t);
 
+// Interaction lists regrouped by sibling groups for the register-blocked
+// translation.  A group is a run of at most `tg` consecutive boxes (Morton
+// order) with one parent; siblings share most of their interaction lists
+// (children of the parent's neighbours), so every source of the group's
+// union is read once and applied to all of the group's targets.  Group g
+// has targets first[g] .. first[g] + count[g] - 1 and source records
+// rec_start[g] .. rec_start[g + 1] - 1; record r is source box src[r] and,
+// for target slot j < tg, offset id off[r * tg + j] (0..342, the 7 x 7 x 7
+// window of the operator table) or -1 when the source is not in that
+// target's interaction list.  Records are sorted by source box.
+struct GroupTiles {
+    int tg = 0;
+    std::vector<int> first, count, rec_start, src, off;
+};
+void build_group_tiles(const Level &L, int tg, GroupTiles &g);
+
 // Theta-row chunks for a level step done in LDS.  `theta` is the step's theta
 // stencil, whose rows are (output theta row) * nph + phi column and whose
 // columns are (input theta row) * nph + phi column.  Output theta rows are cut

@@ -43,7 +43,11 @@ def _stand_in(n2, n_hdg, seed):
         return sp.csr_matrix((vals, (rows, cols)), shape=(m, n))
 
     D_lx = rand_sparse(n_hdg, n2, 3)
-    D_xl = rand_sparse(n2, n_hdg, 3)
+    # the coupling back is the adjoint of the coupling out (as for the
+    # symmetric HDG-BI couplings), so the sparse term -D_xl Q^-1 D_lx is a
+    # Hermitian semi-definite perturbation of C and the reduced system stays
+    # well posed for GMRES
+    D_xl = -D_lx.conj().T.tocsr()
     B = rand_sparse(n_hdg, n_hdg, 4)
     Q = (B @ B.conj().T + 2.0 * sp.identity(n_hdg)).tocsr()
     return D_lx, D_xl, Q
@@ -66,9 +70,9 @@ def test_hybrid_product_and_solve():
     n2 = 2 * g.n_rwg
     x = synth.gaussian_coeffs(n2, 3, 82)
     Cx = oracle.matvec(v, t, K0, x, op=oracle.OP_C)
-    # scale the coupling so that the sparse term is as large as C x
+    # scale the coupling so that the sparse term is half as large as C x
     corr0 = -(D_xl @ (Qinv @ (D_lx @ x)))
-    D_xl = D_xl * (np.linalg.norm(Cx) / np.linalg.norm(corr0))
+    D_xl = D_xl * (0.5 * np.linalg.norm(Cx) / np.linalg.norm(corr0))
     corr = -(D_xl @ (Qinv @ (D_lx @ x)))
     calls = []
     Qinv_dev = {torch.complex128: torch.from_numpy(Qinv).cuda()}
@@ -110,7 +114,7 @@ def test_hybrid_product_and_solve():
 
 
 def test_hybrid_rejects_bad_input_and_failed_solve():
-    v, t = synth.icosphere(4, 0.5)
+    v, t = synth.icosphere(6, 0.5)
     torch, mf, g, D_lx, D_xl, Q, Qinv = _setup((v, t), 50, 84, 1)
     n2 = 2 * g.n_rwg
     bad = sp.csr_matrix((np.ones(1), ([0], [n2 + 3])), shape=(50, n2 + 4))
