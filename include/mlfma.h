@@ -125,6 +125,27 @@ int mlfma_matvec_LK(mlfma_handle h, int op, int dtype, long long nrhs, const voi
                     void *y, long long ldy, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Allocation-free product, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, hosts that forbid
+ * allocation inside the loop).  Same arguments, result and asynchrony as
+ * mlfma_matvec_LK, but the product's scratch (internal vectors, box
+ * patterns of every level, level-step intermediate) lives in one static
+ * device array of MLFMA_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends; nothing is allocated or
+ * freed, and the near field runs on hip_stream itself (no second stream).
+ * A product whose scratch exceeds the array (about (4N + sum over levels of
+ * 4 boxes K + the largest level-step intermediate) x nrhs complex elements,
+ * each padded to 256 bytes) is refused with MLFMA_ERR_ARG, nothing enqueued.
+ * Every call on one GPU uses that GPU's one array: calls whose products may
+ * overlap on the device (other streams, other threads) race and must be
+ * ordered by the caller.  The array keeps the last call's contents; the
+ * product writes every scratch element before reading it.
+ * ------------------------------------------------------------------------ */
+#define MLFMA_NOALLOC_SCRATCH_BYTES (256ULL << 20)
+int mlfma_matvec_LK_noalloc(mlfma_handle h, int op, int dtype, long long nrhs, const void *x, long long ldx,
+                            void *y, long long ldy, void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Several products in one call (the batched form of Sec. II-E step 2(a) for
  * many geometries or operators): every item is y = A x as in
  * mlfma_matvec_LK.  Items of different geometries run concurrently on

@@ -69,6 +69,7 @@ def lib():
         L.mlfma_precompute_nearfield.argtypes = [P]
         L.mlfma_matvec_LK.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, P]
         L.mlfma_matvec_part.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, P]
+        L.mlfma_matvec_LK_noalloc.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, P]
         L.mlfma_release.argtypes = [P]
         L.mlfma_query.argtypes = [P, ctypes.POINTER(LL), ctypes.POINTER(ctypes.c_int),
                                   ctypes.POINTER(ctypes.c_ulonglong)]
@@ -272,6 +273,12 @@ class Geometry:
     def matvec_raw(self, op, dtype, nrhs, x_ptr, ldx, y_ptr, ldy, stream_ptr):
         """Direct call of mlfma_matvec_LK on device pointers (column-major)."""
         _check(lib().mlfma_matvec_LK(self._h, _OPS.get(op, op), dtype, nrhs, x_ptr, ldx, y_ptr, ldy, stream_ptr))
+
+    def matvec_noalloc_raw(self, op, dtype, nrhs, x_ptr, ldx, y_ptr, ldy, stream_ptr):
+        """Direct call of mlfma_matvec_LK_noalloc (no allocation; the
+        library's static scratch array) on device pointers (column-major)."""
+        _check(lib().mlfma_matvec_LK_noalloc(self._h, _OPS.get(op, op), dtype, nrhs, x_ptr, ldx, y_ptr, ldy,
+                                             stream_ptr))
 
     def sai_build(self, op="C", k_nearest=16):
         """mlfma_sai_build: SAI preconditioner of op's near field over

@@ -19,6 +19,7 @@
 #include "device.hpp"
 #include "nearfield.hpp"
 #include "sai.hpp"
+#include "scratch.hpp"
 #include "setup.hpp"
 
 using namespace mlfma;
@@ -2177,6 +2178,58 @@ int mlfma_translation_operator(double k, int L, const double X[3], long long nk,
 }
 
 }  // extern "C"
+
+// ============================================================ scratch product
+// The product of mlfma_matvec_LK with its per-product scratch laid over
+// caller-provided device memory instead of the handle's workspace: no
+// allocation, no second stream (the near field runs on hip_stream), no
+// stage timing.  Used by the allocation-free entry point (noalloc.hip).
+namespace mlfma {
+
+int handle_device(mlfma_handle h) { return h ? h->device : -1; }
+
+int set_error(int code, const char *msg) { return fail(Error(code, msg)); }
+
+int matvec_in_scratch(mlfma_handle h, int op, int dtype, long long nrhs, const void *x, long long ldx, void *y,
+                      long long ldy, void *hip_stream, void *scratch, unsigned long long cap)
+{
+    g_last_error.clear();
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    if (!h->near_ready) return fail(Error(MLFMA_ERR_STATE, "mlfma_precompute_nearfield has not been called"));
+    if (op != MLFMA_OP_C && op != MLFMA_OP_EM) return fail(Error(MLFMA_ERR_ARG, "unknown op"));
+    if (dtype != MLFMA_C128 && dtype != MLFMA_C64) return fail(Error(MLFMA_ERR_ARG, "unknown dtype"));
+    const long long N2 = 2LL * h->r.n;
+    if (nrhs < 1 || nrhs > (1 << 20) || !x || !y || ldx < N2 || ldy < N2)
+        return fail(Error(MLFMA_ERR_ARG, "bad nrhs, pointer or leading dimension"));
+    const size_t esz = dtype == MLFMA_C128 ? 16 : 8;
+    const char *xb = (const char *)x, *yb = (const char *)y;
+    if (xb < yb + (size_t)(ldy * (nrhs - 1) + N2) * esz && yb < xb + (size_t)(ldx * (nrhs - 1) + N2) * esz)
+        return fail(Error(MLFMA_ERR_ARG, "x and y overlap"));
+    const unsigned long long need = layout_workspace(h, (int)nrhs, esz, nullptr, nullptr);
+    if (!scratch || need > cap)
+        return fail(Error(MLFMA_ERR_ARG, "the product needs " + std::to_string(need) +
+                                             " bytes of scratch, more than the " + std::to_string(cap) +
+                                             " bytes available"));
+    try {
+        DeviceGuard g(h->device);
+        HIPCHK(hipGetLastError());
+        Workspace w;
+        layout_workspace(h, (int)nrhs, esz, (char *)scratch, &w);
+        hipStream_t st = (hipStream_t)hip_stream;
+        if (dtype == MLFMA_C128)
+            run_matvec<double>(h, w, h->p64, op, MLFMA_PART_ALL, (int)nrhs, (const cpx<double> *)x, ldx,
+                               (cpx<double> *)y, ldy, st, false);
+        else
+            run_matvec<float>(h, w, h->p32, op, MLFMA_PART_ALL, (int)nrhs, (const cpx<float> *)x, ldx,
+                              (cpx<float> *)y, ldy, st, false);
+        HIPCHK(hipGetLastError());
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+}  // namespace mlfma
 
 // ====================================================================== serving
 // Continuous batching: client threads submit products for resident
