@@ -48,6 +48,10 @@ def parse():
     p.add_argument("--leaf-extra", type=int, default=2, help="extra multipoles at the leaf level")
     p.add_argument("--interp-order", type=int, default=8, help="Lagrange points per angle")
     p.add_argument("--digits", type=int, default=3, help="MLFMA accuracy parameter d0")
+    p.add_argument("--trans-kernel", default="auto", choices=["auto", "tiled", "groups"],
+                   help="translation kernel (default: the autotuner's pick)")
+    p.add_argument("--level-kernel", default="auto", choices=["auto", "vector", "matrix"],
+                   help="complex64 level-step kernels (default: the autotuner's pick)")
     p.add_argument("--no-box", action="store_true", help="skip the batched box comparison")
     p.add_argument("--no-solver", action="store_true", help="skip GMRES / SAI / RCS")
     p.add_argument("--serve-requests", type=int, default=512,
@@ -253,7 +257,7 @@ def main():
     k = 2 * math.pi
     t0 = time.perf_counter()
     g = mf.Geometry(v, t, k=k, leaf=spec["leaf"], max_rhs=nrhs, digits=a.digits, interp_order=a.interp_order,
-                    leaf_extra_L=a.leaf_extra)
+                    leaf_extra_L=a.leaf_extra, trans_kernel=a.trans_kernel, level_kernel=a.level_kernel)
     t1 = time.perf_counter()
     g.precompute()
     torch.cuda.synchronize()
@@ -321,6 +325,7 @@ def main():
     d64 = rel(ys["c64"], ys["c128"])
     hbm_bytes = g.hbm_bytes
     tuning = g.tuning()
+    tuning["level_steps_c64"] = g.tuning_steps()
 
     # outer solver on the same geometry: GMRES(30) on the BI block for the
     # first right-hand side, tol 1e-3, plain and with the SAI preconditioner,

@@ -68,12 +68,23 @@ typedef struct {
     int device;          /* HIP device ordinal (-1: the current device)             */
     unsigned long long hbm_budget_bytes;   /* 0 = no limit                          */
     int trans_kernel;    /* translation kernel: MLFMA_TRANS_AUTO (autotuner picks)   */
+    int level_kernel;    /* complex64 level steps: MLFMA_LEVELS_AUTO (autotuner picks) */
+    int near_precision;  /* arithmetic of the near part of complex128 products      */
+    int far_precision;   /* and of their MLFMA far part: MLFMA_PREC_* (as the dtype) */
 } mlfma_options;
+/* Precision of a part of complex128 products (complex64 products always
+ * compute in FP32): MLFMA_PREC_DTYPE = the vector's (FP64), MLFMA_PREC_FP32
+ * = complex FP32 accumulated in FP32 on tables precomputed in FP64 (the
+ * input is rounded to complex64 for that part, its result added to the
+ * other part in FP64). */
+enum { MLFMA_PREC_DTYPE = 0, MLFMA_PREC_FP64 = 1, MLFMA_PREC_FP32 = 2 };
 enum { MLFMA_TRANS_AUTO = 0, MLFMA_TRANS_TILED = 1, MLFMA_TRANS_GROUPS = 2 };
+enum { MLFMA_LEVELS_AUTO = 0, MLFMA_LEVELS_VECTOR = 1, MLFMA_LEVELS_MATRIX = 2 };
 
 /* Fill *opt with defaults: k = 2 pi, leaf 0.25, d0 = 3, order 8, extra 2,
- * one RHS, current device, no budget, autotuned translation kernel.  Returns
- * MLFMA_ERR_ARG on NULL. */
+ * one RHS, current device, no budget, autotuned translation and level-step
+ * kernels, both parts of complex128 products in FP64.  Returns MLFMA_ERR_ARG
+ * on NULL. */
 int mlfma_options_default(mlfma_options *opt);
 
 /*
@@ -104,9 +115,10 @@ int mlfma_precompute_nearfield(mlfma_handle h);
  * part from the stored blocks, the far part by MLFMA (radiation, aggregation
  * with Lagrange interpolation, diagonal translation, anterpolation and
  * disaggregation, receive).  Sec. II-E step 2(a).
- *   dtype: MLFMA_C128 (complex double in/out, double arithmetic) or MLFMA_C64
- *          (complex float in/out, single arithmetic on tables precomputed in
- *          double);
+ *   dtype: MLFMA_C128 (complex double in/out, double arithmetic unless the
+ *          handle's near_precision / far_precision options ask for FP32
+ *          parts) or MLFMA_C64 (complex float in/out, single arithmetic on
+ *          tables precomputed in double);
  *   x, y : DEVICE pointers, 2N x nrhs column-major, leading dimensions ldx,
  *          ldy >= 2N (elements); y is overwritten; x and y must not overlap;
  *   hip_stream: hipStream_t to enqueue on (NULL = default stream).
@@ -412,6 +424,17 @@ int mlfma_near_info(mlfma_handle h, long long info[4]);
  * per lane; *ms (may be NULL) = the timed translation of all levels,
  * milliseconds.  dtype MLFMA_C128 or MLFMA_C64; MLFMA_ERR_ARG otherwise. */
 int mlfma_tuning(mlfma_handle h, int dtype, int shape[3], double *ms);
+
+/* Level steps of complex64 products (aggregation with Lagrange
+ * interpolation, disaggregation with anterpolation; Sec. II-E): on the
+ * vector units or as real-split 16 x 16 x 4 FP32 MFMA products of the
+ * separable stencil matrices, as the autotuner of mlfma_build_tree picked
+ * (timing both for every level with the handle's right-hand-side count,
+ * capped at 16) or mlfma_options.level_kernel fixed.  *matrix_cores = 1 for
+ * the matrix-core kernels; ms[0], ms[1] (may be NULL) = the timed steps of
+ * all levels, vector and matrix cores (0 when not timed).  MLFMA_ERR_ARG for
+ * a NULL handle. */
+int mlfma_tuning_steps(mlfma_handle h, int *matrix_cores, double ms[2]);
 
 /*
  * Stage timing with HIP events recorded on the matvec's stream.  Stages:

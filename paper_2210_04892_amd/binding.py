@@ -35,7 +35,8 @@ class MlfmaError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("wavenumber", ctypes.c_double), ("leaf_size", ctypes.c_double), ("digits", ctypes.c_int),
                 ("interp_order", ctypes.c_int), ("leaf_extra_L", ctypes.c_int), ("max_rhs", ctypes.c_int),
-                ("device", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_ulonglong), ("trans_kernel", ctypes.c_int)]
+                ("device", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_ulonglong), ("trans_kernel", ctypes.c_int),
+                ("level_kernel", ctypes.c_int), ("near_precision", ctypes.c_int), ("far_precision", ctypes.c_int)]
 
 
 class BatchItem(ctypes.Structure):
@@ -79,6 +80,7 @@ def lib():
         L.mlfma_translation_operator.argtypes = [ctypes.c_double, ctypes.c_int, P, LL, P, P]
         L.mlfma_near_info.argtypes = [P, P]
         L.mlfma_tuning.argtypes = [P, ctypes.c_int, P, P]
+        L.mlfma_tuning_steps.argtypes = [P, ctypes.POINTER(ctypes.c_int), P]
         L.mlfma_graph_create.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, ctypes.POINTER(P)]
         L.mlfma_graph_launch.argtypes = [P, P]
         L.mlfma_graph_destroy.argtypes = [P]
@@ -128,9 +130,14 @@ class Geometry:
     resident on one GPU (mlfma_build_tree / mlfma_precompute_nearfield)."""
 
     def __init__(self, verts, tris, k=2 * math.pi, leaf=0.25, digits=3, interp_order=8, leaf_extra_L=2,
-                 max_rhs=1, device=None, hbm_budget_bytes=0, trans_kernel="auto"):
+                 max_rhs=1, device=None, hbm_budget_bytes=0, trans_kernel="auto", level_kernel="auto",
+                 near_precision="fp64", far_precision="fp64"):
         o = default_options()
         o.trans_kernel = {"auto": 0, "tiled": 1, "groups": 2}[trans_kernel]
+        o.level_kernel = {"auto": 0, "vector": 1, "matrix": 2}[level_kernel]
+        # arithmetic of the near and far parts of complex128 products
+        o.near_precision = {"fp64": 1, "fp32": 2}[near_precision]
+        o.far_precision = {"fp64": 1, "fp32": 2}[far_precision]
         o.wavenumber = k
         o.leaf_size = leaf
         o.digits = digits
@@ -229,6 +236,14 @@ class Geometry:
             _check(lib().mlfma_tuning(self._h, dt, sh.ctypes.data, ctypes.byref(ms)))
             out[name] = (int(sh[0]), int(sh[1]), int(sh[2]), float(ms.value))
         return out
+
+    def tuning_steps(self):
+        """Level-step kernels of complex64 products: {"matrix_cores": bool,
+        "ms_vector": t, "ms_matrix": t} (timed at build, 0 if not timed)."""
+        m = ctypes.c_int()
+        ms = np.zeros(2, np.float64)
+        _check(lib().mlfma_tuning_steps(self._h, ctypes.byref(m), ms.ctypes.data))
+        return {"matrix_cores": bool(m.value), "ms_vector": float(ms[0]), "ms_matrix": float(ms[1])}
 
     def profile(self, enable=True):
         _check(lib().mlfma_profile(self._h, 1 if enable else 0))

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "_mlfma.so")
-SOURCES = ["setup.cpp", "capi.cpp", "matvec.hip", "levels.hip", "mfma.hip", "krylov.hip", "nearfield.hip", "sai.hip", "probe.hip", "noalloc.hip", "translate.hip"]
+SOURCES = ["setup.cpp", "capi.cpp", "matvec.hip", "levels.hip", "mfma.hip", "krylov.hip", "nearfield.hip", "sai.hip", "probe.hip", "noalloc.hip", "translate.hip", "levels_mfma.hip"]
 
 # Packed FP32 instructions are kept out of the generated code.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

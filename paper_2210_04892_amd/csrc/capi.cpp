@@ -66,6 +66,8 @@ struct PrecLevel {
     int tphi = 0, tth = 0;  // separable disaggregation stencils (0 = not separable)
     int *phi_col = nullptr, *th_row = nullptr, *th_sh = nullptr;
     T *phi_w = nullptr, *rowf = nullptr, *th_w = nullptr;
+    // the step to level l + 1 on the matrix cores (complex64 only)
+    StepMfma agg_m, dis_m;
     // translation tiles (a batch of sources fills 32 KB of LDS)
     int ntile = 0;
     int *tile_tgt = nullptr, *tile_bat = nullptr, *bat_src = nullptr, *src = nullptr;
@@ -82,6 +84,8 @@ struct Prec {
     std::vector<PrecLevel<T>> lv;
     int trans_tmax = 0, trans_smax = 0, trans_rb = 1;   // translation tile shape (autotuned)
     int trans_group = 0;                          // > 0: sibling-group kernel with this many targets per group
+    int level_mfma = 0;                           // level steps on the matrix cores (complex64, autotuned)
+    double step_ms[2] = {0, 0};                   // timed level steps: vector, matrix cores
     double trans_ms = 0;                          // its timed translation, ms
 };
 
@@ -104,6 +108,7 @@ struct Workspace {
     unsigned long long bytes = 0;
     std::vector<void *> allocs;
     void *X = nullptr, *Y = nullptr, *mid = nullptr;
+    void *X2 = nullptr, *Y2 = nullptr;   // complex64 copies in the caller's layout (products with FP32 parts)
     std::vector<void *> U, V;
     // optional second stream (not owned): the near field then runs beside
     // the far-field chain, forked after the radiation and joined before the
@@ -159,6 +164,7 @@ struct mlfma_ctx {
     Prec<double> p64;
     Prec<float> p32;
     bool near_ready = false;
+    bool mixed = false;       // complex128 products with an FP32 part (options)
     SaiData sai[2];           // per op (MLFMA_OP_C, MLFMA_OP_EM)
     hipStream_t side = nullptr;                    // near-field stream of ws
     hipEvent_t fork = nullptr, join = nullptr;
@@ -297,6 +303,161 @@ void plan_level_steps(mlfma_ctx *c, int l, PrecLevel<T> &PL)
     PL.phi_w = c->upload(cast_vec<T>(sep.phi_w));
     PL.rowf = c->upload(cast_vec<T>(sep.rowf));
     PL.th_w = c->upload(cast_vec<T>(sep.th_w));
+}
+
+// The step between parent level l and child level l + 1 as dense real
+// matrices for the matrix-core kernels, checked to be separable: the theta
+// interpolation the same for every child phi column (up to the half turn of
+// the pole extension), the phi interpolation the same for every parent theta
+// row; the anterpolation from the separable form (SepStencil).
+void build_step_mfma(mlfma_ctx *c, int l, StepMfma &agg, StepMfma &dis)
+{
+    const Tree &tr = c->tr;
+    const Level &L = tr.lv[l], &C = tr.lv[l + 1];
+    agg = StepMfma();
+    dis = StepMfma();
+    const int nthp = L.nth, nphp = L.nph, nthc = C.nth, nphc = C.nph, half = nphc / 2;
+    if (nphc % 2 || nphp > 128 || nthp > 64 || nphc > 256) return;
+    const int npt = (nphp + 15) / 16, njt = (nphc + 15) / 16, nit = (nthp + 15) / 16, nict = (nthc + 15) / 16;
+    // ---- aggregation
+    const Csr &th = tr.agg_theta[l], &ph = tr.agg_phi[l];
+    const int ne = 3 * nthc, e_pad = (ne + 3) / 4 * 4;
+    std::vector<int> ext_row(ne), ext_sh(ne);
+    for (int e = 0; e < ne; e++) {
+        ext_row[e] = e < nthc ? nthc - 1 - e : (e < 2 * nthc ? e - nthc : 3 * nthc - 1 - e);
+        ext_sh[e] = (e < nthc || e >= 2 * nthc) ? half : 0;
+    }
+    std::vector<float> ath((size_t)nit * 16 * e_pad, 0.f);
+    std::vector<int> ks_lo(nit, 1 << 30), ks_hi(nit, 0);
+    for (int ip = 0; ip < nthp; ip++) {
+        const bool north = L.ct[ip] > 0;   // theta below pi/2: reflected nodes across the north pole
+        struct Tap { int idx, refl; double w; };
+        auto taps = [&](int jc, std::vector<Tap> &v) {
+            v.clear();
+            const int row = ip * nphc + jc;
+            for (int e = th.start[row]; e < th.start[row + 1]; e++) {
+                const int idx = th.col[e] / nphc, jj = th.col[e] % nphc;
+                int refl;
+                if (jj == jc) refl = 0;
+                else if (jj == (jc + half) % nphc) refl = 1;
+                else return false;
+                v.push_back({idx, refl, th.w[e]});
+            }
+            std::sort(v.begin(), v.end(), [](const Tap &x, const Tap &y) { return x.idx != y.idx ? x.idx < y.idx : x.refl < y.refl; });
+            return true;
+        };
+        std::vector<Tap> t0, tj;
+        if (!taps(0, t0)) return;
+        for (int jc = 1; jc < nphc; jc++) {
+            if (!taps(jc, tj) || tj.size() != t0.size()) return;
+            for (size_t i = 0; i < t0.size(); i++)
+                if (tj[i].idx != t0[i].idx || tj[i].refl != t0[i].refl || std::abs(tj[i].w - t0[i].w) > 1e-13 * (1 + std::abs(t0[i].w)))
+                    return;
+        }
+        for (const Tap &x : t0) {
+            const int e = x.refl ? (north ? nthc - 1 - x.idx : 3 * nthc - 1 - x.idx) : nthc + x.idx;
+            ath[(size_t)ip * e_pad + e] += (float)x.w;
+            ks_lo[ip / 16] = std::min(ks_lo[ip / 16], e / 4);
+            ks_hi[ip / 16] = std::max(ks_hi[ip / 16], e / 4 + 1);
+        }
+    }
+    for (int it = 0; it < nit; it++) {
+        if (ks_lo[it] > ks_hi[it]) ks_lo[it] = ks_hi[it] = 0;
+        if (ks_hi[it] - ks_lo[it] > 8) return;   // the kernel holds at most 8 k-steps of one tile
+    }
+    const int jc_pad = njt * 16;
+    std::vector<float> bph((size_t)npt * 16 * jc_pad, 0.f);
+    for (int jp = 0; jp < nphp; jp++)
+        for (int e = ph.start[jp]; e < ph.start[jp + 1]; e++) bph[(size_t)jp * jc_pad + ph.col[e]] += (float)ph.w[e];
+    for (int ip = 1; ip < nthp; ip++)
+        for (int jp = 0; jp < nphp; jp++) {
+            const int row = ip * nphp + jp;
+            if (ph.start[row + 1] - ph.start[row] != ph.start[jp + 1] - ph.start[jp]) return;
+            for (int e = ph.start[row], e0 = ph.start[jp]; e < ph.start[row + 1]; e++, e0++)
+                if (ph.col[e] != ip * nphc + ph.col[e0] || ph.w[e] != ph.w[e0]) return;
+        }
+    std::vector<unsigned> bmask(njt, 0u);
+    for (int jp = 0; jp < nphp; jp++)
+        for (int j = 0; j < nphc; j++)
+            if (bph[(size_t)jp * jc_pad + j] != 0.f) bmask[j / 16] |= 1u << (jp / 16);
+    // ---- disaggregation
+    SepStencil sep;
+    if (!separable_disaggregation(L, C, tr.dis_phi[l], tr.dis_theta[l], sep)) return;
+    const int nks = (nphp + 3) / 4, jp_pad = nks * 4, nip = (nthp + 15) / 16, ip_pad = nip * 16;
+    if (nks > 64) return;
+    std::vector<float> dph((size_t)njt * 16 * jp_pad, 0.f);
+    for (int j = 0; j < nphc; j++)
+        for (int t = 0; t < sep.tphi; t++)
+            dph[(size_t)j * jp_pad + sep.phi_col[(size_t)j * sep.tphi + t]] += (float)sep.phi_w[(size_t)j * sep.tphi + t];
+    std::vector<unsigned long long> kmask(njt, 0ull), kmask_s(njt, 0ull);
+    for (int j = 0; j < nphc; j++) {
+        const int js = (j + half) % nphc;
+        for (int jp = 0; jp < nphp; jp++) {
+            if (dph[(size_t)j * jp_pad + jp] != 0.f) kmask[j / 16] |= 1ull << (jp / 4);
+            if (dph[(size_t)js * jp_pad + jp] != 0.f) kmask_s[j / 16] |= 1ull << (jp / 4);
+        }
+    }
+    std::vector<float> rowf(ip_pad, 0.f), dthd((size_t)nict * 16 * ip_pad, 0.f), dthr((size_t)nict * 16 * ip_pad, 0.f);
+    for (int ip = 0; ip < nthp; ip++) rowf[ip] = (float)sep.rowf[ip];
+    for (int ic = 0; ic < nthc; ic++)
+        for (int t = 0; t < sep.tth; t++) {
+            const size_t k = (size_t)ic * sep.tth + t;
+            if (sep.th_w[k] == 0) continue;
+            if (sep.th_sh[k] == 0) dthd[(size_t)ic * ip_pad + sep.th_row[k]] += (float)sep.th_w[k];
+            else if (sep.th_sh[k] == half) dthr[(size_t)ic * ip_pad + sep.th_row[k]] += (float)sep.th_w[k];
+            else return;
+        }
+    std::vector<unsigned> dmask(nict, 0u), rmask_c(nict, 0u);
+    unsigned rmask = 0;
+    for (int ic = 0; ic < nthc; ic++)
+        for (int ip = 0; ip < nthp; ip++) {
+            if (dthd[(size_t)ic * ip_pad + ip] != 0.f) dmask[ic / 16] |= 1u << (ip / 16);
+            if (dthr[(size_t)ic * ip_pad + ip] != 0.f) {
+                rmask_c[ic / 16] |= 1u << (ip / 16);
+                rmask |= 1u << (ip / 16);
+            }
+        }
+    // ---- device tables
+    StepMfma base;
+    base.nth_p = nthp;
+    base.nph_p = nphp;
+    base.nth_c = nthc;
+    base.nph_c = nphc;
+    base.child_start = c->lv[l].child_start;
+    base.parent = c->lv[l + 1].parent;
+    base.oct = c->lv[l + 1].oct;
+    base.shift = c->p32.lv[l].shift;
+    base.njt = njt;
+    agg = base;
+    agg.nbox = L.nbox;
+    agg.nit = nit;
+    agg.ne = ne;
+    agg.e_pad = e_pad;
+    agg.jc_pad = jc_pad;
+    agg.ext_row = c->upload(ext_row);
+    agg.ext_sh = c->upload(ext_sh);
+    agg.ks_lo = c->upload(ks_lo);
+    agg.ks_hi = c->upload(ks_hi);
+    agg.ath = c->upload(ath);
+    agg.bph = c->upload(bph);
+    agg.bmask = c->upload(bmask);
+    agg.ok = 1;
+    dis = base;
+    dis.nbox = C.nbox;
+    dis.nks = nks;
+    dis.jp_pad = jp_pad;
+    dis.nict = nict;
+    dis.ip_pad = ip_pad;
+    dis.rmask = rmask;
+    dis.kmask = c->upload(kmask);
+    dis.kmask_s = c->upload(kmask_s);
+    dis.dph = c->upload(dph);
+    dis.rowf = c->upload(rowf);
+    dis.dthd = c->upload(dthd);
+    dis.dthr = c->upload(dthr);
+    dis.dmask = c->upload(dmask);
+    dis.rmask_c = c->upload(rmask_c);
+    dis.ok = 1;
 }
 
 template <class T>
@@ -594,6 +755,7 @@ void build_device_tables(mlfma_ctx *c)
     }
     upload_level_tables<double>(c, c->p64, trans, shift);
     upload_level_tables<float>(c, c->p32, trans, shift);
+    for (int l = 2; l + 1 < tr.levels; l++) build_step_mfma(c, l, c->p32.lv[l].agg_m, c->p32.lv[l].dis_m);
 
     // geometry in internal RWG order (kept: near field, plane waves)
     {
@@ -999,8 +1161,16 @@ unsigned long long layout_workspace(const mlfma_ctx *c, int nrhs, size_t esz, ch
         }
     }
     void *mid = take(midmax);
+    void *X2 = nullptr, *Y2 = nullptr;
+    if (c->mixed) {   // complex float copies of X and Y
+        const unsigned long long f = (N * 2 * nrhs * sizeof(cpx<float>) + esz - 1) / esz;
+        X2 = take(f);
+        Y2 = take(f);
+    }
     if (w) {
         w->mid = mid;
+        w->X2 = X2;
+        w->Y2 = Y2;
         w->rhs = nrhs;
     }
     return off;
@@ -1098,6 +1268,76 @@ LevelStep<T> step_args(mlfma_ctx *c, Prec<T> &P, int l, bool agg, int nrhs)
     return a;
 }
 
+// Level steps of complex64 products: the vector kernels (levels.hip) or the
+// matrix-core ones (levels_mfma.hip), whichever runs the aggregation and
+// disaggregation of all levels faster with the handle's right-hand-side
+// count (capped at 16; one warm-up and three timed runs each), unless the
+// options fix the choice.
+void tune_level_steps(mlfma_ctx *c)
+{
+    Prec<float> &P = c->p32;
+    const Tree &tr = c->tr;
+    P.level_mfma = 0;
+    bool any = false;
+    for (int l = 2; l + 1 < tr.levels; l++) any |= P.lv[l].agg_m.ok && P.lv[l].dis_m.ok;
+    if (!any || c->opt.level_kernel == MLFMA_LEVELS_VECTOR) return;
+    if (c->opt.level_kernel == MLFMA_LEVELS_MATRIX) {
+        P.level_mfma = 1;
+        return;
+    }
+    const int nrhs = std::min(c->opt.max_rhs, 16);
+    hipStream_t st;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    Workspace &w = c->ws;
+    // zeroed patterns: the timing must not depend on what the workspace held
+    for (int l = 2; l < tr.levels; l++) {
+        launch_zero<float>((cpx<float> *)w.U[l], (long long)tr.lv[l].nbox * tr.lv[l].K * 2 * nrhs, st);
+        launch_zero<float>((cpx<float> *)w.V[l], (long long)tr.lv[l].nbox * tr.lv[l].K * 2 * nrhs, st);
+    }
+    auto steps = [&](int mfma) {
+        P.level_mfma = mfma;
+        for (int l = tr.levels - 2; l >= 2; l--) {
+            if (mfma && launch_aggregate_mfma(P.lv[l].agg_m, (const cpx<float> *)w.U[l + 1], (cpx<float> *)w.U[l], nrhs,
+                                              st))
+                continue;
+            LevelStep<float> a = step_args<float>(c, P, l, true, nrhs);
+            a.in = (const cpx<float> *)w.U[l + 1];
+            a.out = (cpx<float> *)w.U[l];
+            launch_aggregate_step<float>(a, nrhs, st);
+        }
+        for (int l = 3; l < tr.levels; l++) {
+            if (mfma && launch_disaggregate_mfma(P.lv[l - 1].dis_m, (const cpx<float> *)w.V[l - 1], (cpx<float> *)w.V[l],
+                                                 nrhs, st))
+                continue;
+            LevelStep<float> a = step_args<float>(c, P, l - 1, false, nrhs);
+            a.in = (const cpx<float> *)w.V[l - 1];
+            a.out = (cpx<float> *)w.V[l];
+            launch_disaggregate_step<float>(a, nrhs, st);
+        }
+    };
+    double ms[2] = {0, 0};
+    for (int mfma = 0; mfma < 2; mfma++) {
+        steps(mfma);
+        HIPCHK(hipEventRecord(e0, st));
+        for (int i = 0; i < 3; i++) steps(mfma);
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float t = 0;
+        HIPCHK(hipEventElapsedTime(&t, e0, e1));
+        ms[mfma] = t / 3;
+    }
+    HIPCHK(hipGetLastError());
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    P.step_ms[0] = ms[0];
+    P.step_ms[1] = ms[1];
+    P.level_mfma = ms[1] < ms[0] ? 1 : 0;
+}
+
 template <class T>
 void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nrhs, const cpx<T> *x, long long ldx,
                 cpx<T> *y, long long ldy, hipStream_t st, bool profile)
@@ -1168,6 +1408,10 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
             const IntLevel &I = c->lv[l];
             const int midlen = L.nth * C.nph;
             const int taps = c->opt.interp_order;
+            if constexpr (std::is_same<T, float>::value)
+                if (P.level_mfma && P.lv[l].agg_m.ok &&
+                    launch_aggregate_mfma(P.lv[l].agg_m, (const cpx<float> *)w.U[l + 1], (cpx<float> *)w.U[l], nrhs, st))
+                    continue;
             LevelStep<T> a = step_args<T>(c, P, l, true, nrhs);
             a.in = (const cpx<T> *)w.U[l + 1];
             a.out = (cpx<T> *)w.U[l];
@@ -1195,6 +1439,11 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
             const Level &L = tr.lv[l], &Pl = tr.lv[l - 1];
             const IntLevel &Ip = c->lv[l - 1];
             const int midlen = Pl.nth * L.nph;
+            if constexpr (std::is_same<T, float>::value)
+                if (P.level_mfma && P.lv[l - 1].dis_m.ok &&
+                    launch_disaggregate_mfma(P.lv[l - 1].dis_m, (const cpx<float> *)w.V[l - 1], (cpx<float> *)w.V[l],
+                                             nrhs, st))
+                    continue;
             LevelStep<T> a = step_args<T>(c, P, l - 1, false, nrhs);
             a.in = (const cpx<T> *)w.V[l - 1];
             a.out = (cpx<T> *)w.V[l];
@@ -1220,6 +1469,45 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
     if (!fold) launch_perm_out<T>(Y, y, ldy, c->iperm, N, nrhs, st);
     mark(8);
     if (profile) c->ev_pending.push_back(ev);
+}
+
+// One product in precision T of the vectors.  complex128 products whose
+// near or far part is asked for in FP32 (the handle's options) run that part
+// as a complex64 product of the same x rounded to single precision (part
+// selection of run_matvec), added to the FP64 part; stage timing covers
+// the FP64 part (the FP32 one when there is no FP64 part).
+template <class T>
+void product(mlfma_ctx *c, Workspace &w, int op, int part, int nrhs, const cpx<T> *x, long long ldx, cpx<T> *y,
+             long long ldy, hipStream_t st, bool profile);
+template <>
+void product<float>(mlfma_ctx *c, Workspace &w, int op, int part, int nrhs, const cpx<float> *x, long long ldx,
+                    cpx<float> *y, long long ldy, hipStream_t st, bool profile)
+{
+    run_matvec<float>(c, w, c->p32, op, part, nrhs, x, ldx, y, ldy, st, profile);
+}
+template <>
+void product<double>(mlfma_ctx *c, Workspace &w, int op, int part, int nrhs, const cpx<double> *x, long long ldx,
+                     cpx<double> *y, long long ldy, hipStream_t st, bool profile)
+{
+    if (!c->mixed) {
+        run_matvec<double>(c, w, c->p64, op, part, nrhs, x, ldx, y, ldy, st, profile);
+        return;
+    }
+    const bool near32 = c->opt.near_precision == MLFMA_PREC_FP32, far32 = c->opt.far_precision == MLFMA_PREC_FP32;
+    const bool level = part >= MLFMA_PART_LEVEL;
+    const bool want_near = !level && (part & MLFMA_PART_NEAR), want_far = level || (part & MLFMA_PART_FAR);
+    int p64 = 0, p32 = 0;
+    if (want_near) (near32 ? p32 : p64) |= MLFMA_PART_NEAR;
+    if (want_far && !level) (far32 ? p32 : p64) |= MLFMA_PART_FAR;
+    if (level) (far32 ? p32 : p64) = part;
+    const long long n = 2LL * c->r.n;
+    cpx<float> *xf = (cpx<float> *)w.X2, *yf = (cpx<float> *)w.Y2;
+    if (p64) run_matvec<double>(c, w, c->p64, op, p64, nrhs, x, ldx, y, ldy, st, profile);
+    if (p32) {
+        launch_to_single(x, ldx, xf, n, n, nrhs, st);
+        run_matvec<float>(c, w, c->p32, op, p32, nrhs, xf, n, yf, n, st, profile && !p64);
+        launch_from_single(y, ldy, yf, n, n, nrhs, p64 != 0, st);
+    }
 }
 
 template <class T>
@@ -1311,7 +1599,7 @@ void gmres(mlfma_ctx *c, Prec<T> &P, int op, int nrhs, const cpx<T> *b, long lon
     cpx<double> *ca = (cpx<double> *)dev(sizeof(cpx<double>) * nrhs);
     cpx<double> *cb = (cpx<double> *)dev(sizeof(cpx<double>) * nrhs);
     auto matvec = [&](const cpx<T> *in, long long ldi, cpx<T> *out, long long ldo) {
-        run_matvec<T>(c, c->ws, P, op, MLFMA_PART_ALL, nrhs, in, ldi, out, ldo, st, false);
+        product<T>(c, c->ws, op, MLFMA_PART_ALL, nrhs, in, ldi, out, ldo, st, false);
         if (hy) hybrid_correction<T>(*hy, (int)n, nrhs, in, ldi, out, ldo, st);
     };
     cpx<T> *z = sai ? (cpx<T> *)dev(sizeof(cpx<T>) * (size_t)vstride) : nullptr;
@@ -1535,6 +1823,9 @@ int mlfma_options_default(mlfma_options *opt)
     opt->device = -1;
     opt->hbm_budget_bytes = 0;
     opt->trans_kernel = MLFMA_TRANS_AUTO;
+    opt->level_kernel = MLFMA_LEVELS_AUTO;
+    opt->near_precision = MLFMA_PREC_DTYPE;
+    opt->far_precision = MLFMA_PREC_DTYPE;
     return MLFMA_OK;
 }
 
@@ -1553,6 +1844,11 @@ int mlfma_build_tree(const double *verts, long long n_verts, const int *tris, lo
         if (c->opt.max_rhs < 1) throw Error(MLFMA_ERR_ARG, "max_rhs must be >= 1");
         if (c->opt.trans_kernel < MLFMA_TRANS_AUTO || c->opt.trans_kernel > MLFMA_TRANS_GROUPS)
             throw Error(MLFMA_ERR_ARG, "unknown translation kernel");
+        if (c->opt.level_kernel < MLFMA_LEVELS_AUTO || c->opt.level_kernel > MLFMA_LEVELS_MATRIX)
+            throw Error(MLFMA_ERR_ARG, "unknown level-step kernel");
+        for (int pr : {c->opt.near_precision, c->opt.far_precision})
+            if (pr < MLFMA_PREC_DTYPE || pr > MLFMA_PREC_FP32) throw Error(MLFMA_ERR_ARG, "unknown precision");
+        c->mixed = c->opt.near_precision == MLFMA_PREC_FP32 || c->opt.far_precision == MLFMA_PREC_FP32;
         build_surface(c->s, verts, n_verts, tris, n_tris);
         build_rwg(c->s, c->r);
         build_tree(c->s, c->r, c->opt.wavenumber, c->opt.leaf_size, c->opt.digits, c->opt.interp_order,
@@ -1566,6 +1862,7 @@ int mlfma_build_tree(const double *verts, long long n_verts, const int *tris, lo
         ensure_workspace(c.get(), c->opt.max_rhs);
         tune_translation<double>(c.get(), c->p64);
         tune_translation<float>(c.get(), c->p32);
+        tune_level_steps(c.get());
         *out = c.release();
         return MLFMA_OK;
     } catch (const Error &e) {
@@ -1615,11 +1912,11 @@ int mlfma_matvec_part(mlfma_handle h, int op, int dtype, int part, long long nrh
         ensure_workspace(h, (int)nrhs);
         hipStream_t st = (hipStream_t)hip_stream;
         if (dtype == MLFMA_C128)
-            run_matvec<double>(h, h->ws, h->p64, op, part, (int)nrhs, (const cpx<double> *)x, ldx, (cpx<double> *)y,
-                               ldy, st, h->prof);
+            product<double>(h, h->ws, op, part, (int)nrhs, (const cpx<double> *)x, ldx, (cpx<double> *)y,
+                            ldy, st, h->prof);
         else
-            run_matvec<float>(h, h->ws, h->p32, op, part, (int)nrhs, (const cpx<float> *)x, ldx, (cpx<float> *)y,
-                              ldy, st, h->prof);
+            product<float>(h, h->ws, op, part, (int)nrhs, (const cpx<float> *)x, ldx, (cpx<float> *)y,
+                           ldy, st, h->prof);
         HIPCHK(hipGetLastError());
         return MLFMA_OK;
     } catch (const Error &e) {
@@ -1680,11 +1977,11 @@ int mlfma_matvec_batch(const mlfma_batch_item *items, int n_items, void *hip_str
             mlfma_ctx *h = it.h;
             hipStream_t s = fork ? h->bstream : st;
             if (it.dtype == MLFMA_C128)
-                run_matvec<double>(h, h->ws, h->p64, it.op, MLFMA_PART_ALL, (int)it.nrhs, (const cpx<double> *)it.x,
-                                   it.ldx, (cpx<double> *)it.y, it.ldy, s, h->prof);
+                product<double>(h, h->ws, it.op, MLFMA_PART_ALL, (int)it.nrhs, (const cpx<double> *)it.x,
+                                it.ldx, (cpx<double> *)it.y, it.ldy, s, h->prof);
             else
-                run_matvec<float>(h, h->ws, h->p32, it.op, MLFMA_PART_ALL, (int)it.nrhs, (const cpx<float> *)it.x,
-                                  it.ldx, (cpx<float> *)it.y, it.ldy, s, h->prof);
+                product<float>(h, h->ws, it.op, MLFMA_PART_ALL, (int)it.nrhs, (const cpx<float> *)it.x,
+                               it.ldx, (cpx<float> *)it.y, it.ldy, s, h->prof);
         }
         if (fork)
             for (auto &p : hs) {
@@ -1733,11 +2030,11 @@ int mlfma_graph_create(mlfma_handle h, int op, int dtype, long long nrhs, const 
         HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         try {
             if (dtype == MLFMA_C128)
-                run_matvec<double>(h, h->ws, h->p64, op, MLFMA_PART_ALL, (int)nrhs, (const cpx<double> *)x, ldx,
-                                   (cpx<double> *)y, ldy, cs, false);
+                product<double>(h, h->ws, op, MLFMA_PART_ALL, (int)nrhs, (const cpx<double> *)x, ldx,
+                                (cpx<double> *)y, ldy, cs, false);
             else
-                run_matvec<float>(h, h->ws, h->p32, op, MLFMA_PART_ALL, (int)nrhs, (const cpx<float> *)x, ldx,
-                                  (cpx<float> *)y, ldy, cs, false);
+                product<float>(h, h->ws, op, MLFMA_PART_ALL, (int)nrhs, (const cpx<float> *)x, ldx,
+                               (cpx<float> *)y, ldy, cs, false);
         } catch (...) {
             hipGraph_t junk = nullptr;
             (void)hipStreamEndCapture(cs, &junk);
@@ -1988,6 +2285,17 @@ int mlfma_tuning(mlfma_handle h, int dtype, int shape[3], double *ms)
     return MLFMA_OK;
 }
 
+int mlfma_tuning_steps(mlfma_handle h, int *matrix_cores, double ms[2])
+{
+    if (!h) return fail(Error(MLFMA_ERR_ARG, "NULL handle"));
+    if (matrix_cores) *matrix_cores = h->p32.level_mfma;
+    if (ms) {
+        ms[0] = h->p32.step_ms[0];
+        ms[1] = h->p32.step_ms[1];
+    }
+    return MLFMA_OK;
+}
+
 int mlfma_near_info(mlfma_handle h, long long info[4])
 {
     if (!h || !info) return fail(Error(MLFMA_ERR_ARG, "NULL argument"));
@@ -2217,11 +2525,11 @@ int matvec_in_scratch(mlfma_handle h, int op, int dtype, long long nrhs, const v
         layout_workspace(h, (int)nrhs, esz, (char *)scratch, &w);
         hipStream_t st = (hipStream_t)hip_stream;
         if (dtype == MLFMA_C128)
-            run_matvec<double>(h, w, h->p64, op, MLFMA_PART_ALL, (int)nrhs, (const cpx<double> *)x, ldx,
-                               (cpx<double> *)y, ldy, st, false);
+            product<double>(h, w, op, MLFMA_PART_ALL, (int)nrhs, (const cpx<double> *)x, ldx,
+                            (cpx<double> *)y, ldy, st, false);
         else
-            run_matvec<float>(h, w, h->p32, op, MLFMA_PART_ALL, (int)nrhs, (const cpx<float> *)x, ldx,
-                              (cpx<float> *)y, ldy, st, false);
+            product<float>(h, w, op, MLFMA_PART_ALL, (int)nrhs, (const cpx<float> *)x, ldx,
+                           (cpx<float> *)y, ldy, st, false);
         HIPCHK(hipGetLastError());
         return MLFMA_OK;
     } catch (const Error &e) {
@@ -2329,13 +2637,13 @@ void launch_batch(mlfma_server_s *S, Slot &slot, std::vector<Request *> &batch, 
     }
     Workspace w;
     carve_workspace(h, w, slot.arena, total);
-    auto product = [&](hipStream_t st) {
+    auto run = [&](hipStream_t st) {
         if (dtype == MLFMA_C128)
-            run_matvec<double>(h, w, h->p64, op, MLFMA_PART_ALL, total, (const cpx<double> *)slot.xb, N2,
-                               (cpx<double> *)slot.yb, N2, st, false);
+            product<double>(h, w, op, MLFMA_PART_ALL, total, (const cpx<double> *)slot.xb, N2,
+                            (cpx<double> *)slot.yb, N2, st, false);
         else
-            run_matvec<float>(h, w, h->p32, op, MLFMA_PART_ALL, total, (const cpx<float> *)slot.xb, N2,
-                              (cpx<float> *)slot.yb, N2, st, false);
+            product<float>(h, w, op, MLFMA_PART_ALL, total, (const cpx<float> *)slot.xb, N2,
+                           (cpx<float> *)slot.yb, N2, st, false);
     };
     if (S->opt.use_graphs) {
         // replay the product captured for this slot, geometry, op, dtype and
@@ -2347,7 +2655,7 @@ void launch_batch(mlfma_server_s *S, Slot &slot, std::vector<Request *> &batch, 
             hipGraph_t graph = nullptr;
             HIPCHK(hipStreamBeginCapture(S->capture, hipStreamCaptureModeThreadLocal));
             try {
-                product(S->capture);
+                run(S->capture);
             } catch (...) {
                 (void)hipStreamEndCapture(S->capture, &graph);
                 if (graph) (void)hipGraphDestroy(graph);
@@ -2363,7 +2671,7 @@ void launch_batch(mlfma_server_s *S, Slot &slot, std::vector<Request *> &batch, 
         }
         HIPCHK(hipGraphLaunch(it->second, slot.stream));
     } else {
-        product(slot.stream);
+        run(slot.stream);
     }
     col = 0;
     for (Request *r : batch) {

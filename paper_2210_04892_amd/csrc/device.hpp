@@ -214,6 +214,35 @@ inline size_t agg_lds_bytes(int wrows, int rows, int nph_c) { return 2 * (size_t
 template <class T>
 inline size_t dis_lds_bytes(int wrows, int nph_p, int nph_c) { return 2 * (size_t)wrows * (nph_p + nph_c) * sizeof(cpx<T>); }
 constexpr size_t STEP_LDS_MAX = 64 * 1024;
+// One level step on the matrix cores (levels_mfma.hip, complex64): the
+// stencils as dense, zero-padded real matrices (see the kernels).  ok = 0
+// when the step's stencils are not separable in that form or exceed the
+// kernels' tile limits (16 x 8 parent phi columns, 16 x 4 parent theta rows).
+struct StepMfma {
+    int ok = 0;
+    int nbox = 0;                       // parents (aggregation) or children (disaggregation)
+    int nth_p = 0, nph_p = 0, nth_c = 0, nph_c = 0;
+    const int *child_start = nullptr, *parent = nullptr, *oct = nullptr;
+    const cpx<float> *shift = nullptr;
+    int njt = 0;                        // tiles of 16 child phi columns
+    // aggregation: theta over the child rows extended across the poles
+    int nit = 0, ne = 0, e_pad = 0, jc_pad = 0;
+    const int *ext_row = nullptr, *ext_sh = nullptr, *ks_lo = nullptr, *ks_hi = nullptr;
+    const float *ath = nullptr;         // [nit * 16][e_pad]
+    const float *bph = nullptr;         // [16 * ceil(nph_p / 16)][jc_pad]
+    const unsigned *bmask = nullptr;    // per child phi tile: bit p = block p of bph is non-zero
+    // disaggregation
+    int nks = 0, jp_pad = 0, nict = 0, ip_pad = 0;
+    unsigned rmask = 0;                 // parent theta tiles reached across a pole
+    const unsigned long long *kmask = nullptr, *kmask_s = nullptr;   // per child phi tile: non-zero k-steps
+    const float *dph = nullptr;         // [njt * 16][jp_pad]
+    const float *rowf = nullptr;        // [ip_pad]
+    const float *dthd = nullptr, *dthr = nullptr;   // [nict * 16][ip_pad]
+    const unsigned *dmask = nullptr, *rmask_c = nullptr;   // per child theta tile
+};
+bool launch_aggregate_mfma(const StepMfma &a, const cpx<float> *in, cpx<float> *out, int nrhs, hipStream_t s);
+bool launch_disaggregate_mfma(const StepMfma &a, const cpx<float> *in, cpx<float> *out, int nrhs, hipStream_t s);
+
 // return false when the step has no fused kernel (taps or LDS size)
 template <class T>
 bool launch_aggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s);
@@ -249,6 +278,13 @@ void krylov_combine(const cpx<T> *V, long long vstride, long long ldv, int nv, c
 template <class T>
 void krylov_axpby(const cpx<double> *a, const cpx<T> *x, long long ldx, const cpx<double> *b, const cpx<T> *z,
                   long long ldz, cpx<T> *y, long long ldy, long long n, int nrhs, hipStream_t s);
+
+// Column-major blocks between precisions: b = (complex float) a; a = b, or
+// a += b with add.
+void launch_to_single(const cpx<double> *a, long long lda, cpx<float> *b, long long ldb, long long n, int nrhs,
+                      hipStream_t s);
+void launch_from_single(cpx<double> *a, long long lda, const cpx<float> *b, long long ldb, long long n, int nrhs,
+                        bool add, hipStream_t s);
 
 // Sparse (CSR) times a column-major block: y(i, r) = alpha * sum_k val[k]
 // x(col[k], r) (+ y(i, r) with accumulate), rows i < nrows.

@@ -140,9 +140,49 @@ __global__ __launch_bounds__(KT) void k_csr_spmm(long long nrows, int nrhs, cons
     else o = {(T)(alpha * re), (T)(alpha * im)};
 }
 
+// b(:, r) = (complex float) a(:, r)  (rows n, leading dimensions lda, ldb)
+__global__ __launch_bounds__(KT) void k_to_single(const cpx<double> *__restrict__ a, long long lda,
+                                                  cpx<float> *__restrict__ b, long long ldb, long long n, int nrhs)
+{
+    const long long g = (long long)blockIdx.x * KT + threadIdx.x;
+    if (g >= n * nrhs) return;
+    const int r = (int)(g / n);
+    const long long k = g % n;
+    const cpx<double> v = a[(long long)r * lda + k];
+    b[(long long)r * ldb + k] = {(float)v.re, (float)v.im};
+}
+
+// a(:, r) = b(:, r), or a(:, r) += b(:, r) with add  (complex double from complex float)
+__global__ __launch_bounds__(KT) void k_from_single(cpx<double> *__restrict__ a, long long lda,
+                                                    const cpx<float> *__restrict__ b, long long ldb, long long n,
+                                                    int nrhs, int add)
+{
+    const long long g = (long long)blockIdx.x * KT + threadIdx.x;
+    if (g >= n * nrhs) return;
+    const int r = (int)(g / n);
+    const long long k = g % n;
+    const cpx<float> v = b[(long long)r * ldb + k];
+    cpx<double> &o = a[(long long)r * lda + k];
+    if (add) o = {o.re + (double)v.re, o.im + (double)v.im};
+    else o = {(double)v.re, (double)v.im};
+}
+
 inline unsigned blocks(long long n) { return (unsigned)((n + KT - 1) / KT); }
 
 }  // namespace
+
+void launch_to_single(const cpx<double> *a, long long lda, cpx<float> *b, long long ldb, long long n, int nrhs,
+                      hipStream_t s)
+{
+    if (n * nrhs > 0) hipLaunchKernelGGL(k_to_single, dim3(blocks(n * nrhs)), dim3(KT), 0, s, a, lda, b, ldb, n, nrhs);
+}
+
+void launch_from_single(cpx<double> *a, long long lda, const cpx<float> *b, long long ldb, long long n, int nrhs,
+                        bool add, hipStream_t s)
+{
+    if (n * nrhs > 0)
+        hipLaunchKernelGGL(k_from_single, dim3(blocks(n * nrhs)), dim3(KT), 0, s, a, lda, b, ldb, n, nrhs, add ? 1 : 0);
+}
 
 template <class T>
 void launch_csr_spmm(long long nrows, int nrhs, const long long *ptr, const int *col, const cpx<T> *val,
