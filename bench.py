@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--digits", type=int, default=3, help="MLFMA accuracy parameter d0")
     p.add_argument("--trans-kernel", default="auto", choices=["auto", "tiled", "groups"],
                    help="translation kernel (default: the autotuner's pick)")
-    p.add_argument("--level-kernel", default="auto", choices=["auto", "vector", "matrix"],
+    p.add_argument("--level-kernel", default="auto", choices=["auto", "vector", "matrix", "blocked", "pipelined"],
                    help="complex64 level-step kernels (default: the autotuner's pick)")
     p.add_argument("--no-box", action="store_true", help="skip the batched box comparison")
     p.add_argument("--no-solver", action="store_true", help="skip GMRES / SAI / RCS")

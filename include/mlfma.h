@@ -68,7 +68,7 @@ typedef struct {
     int device;          /* HIP device ordinal (-1: the current device)             */
     unsigned long long hbm_budget_bytes;   /* 0 = no limit                          */
     int trans_kernel;    /* translation kernel: MLFMA_TRANS_AUTO (autotuner picks)   */
-    int level_kernel;    /* complex64 level steps: MLFMA_LEVELS_AUTO (autotuner picks) */
+    int level_kernel;    /* level steps: MLFMA_LEVELS_AUTO (autotuner picks)         */
     int near_precision;  /* arithmetic of the near part of complex128 products      */
     int far_precision;   /* and of their MLFMA far part: MLFMA_PREC_* (as the dtype) */
 } mlfma_options;
@@ -79,7 +79,20 @@ typedef struct {
  * other part in FP64). */
 enum { MLFMA_PREC_DTYPE = 0, MLFMA_PREC_FP64 = 1, MLFMA_PREC_FP32 = 2 };
 enum { MLFMA_TRANS_AUTO = 0, MLFMA_TRANS_TILED = 1, MLFMA_TRANS_GROUPS = 2 };
-enum { MLFMA_LEVELS_AUTO = 0, MLFMA_LEVELS_VECTOR = 1, MLFMA_LEVELS_MATRIX = 2 };
+/* Level-step kernels.  AUTO: the autotuner picks (complex64: vector or
+ * matrix cores; the vector kernels' shape per level and precision).  VECTOR:
+ * vector kernels of autotuned shape.  MATRIX: complex64 steps on the matrix
+ * cores.  BLOCKED: vector kernels with right-hand sides blocked per
+ * workgroup only.  PIPELINED: vector kernels pipelined over the right-hand
+ * sides (and children) wherever a step fits their limits, for products of
+ * four or more right-hand sides. */
+enum {
+    MLFMA_LEVELS_AUTO = 0,
+    MLFMA_LEVELS_VECTOR = 1,
+    MLFMA_LEVELS_MATRIX = 2,
+    MLFMA_LEVELS_BLOCKED = 3,
+    MLFMA_LEVELS_PIPELINED = 4
+};
 
 /* Fill *opt with defaults: k = 2 pi, leaf 0.25, d0 = 3, order 8, extra 2,
  * one RHS, current device, no budget, autotuned translation and level-step
@@ -435,6 +448,15 @@ int mlfma_tuning(mlfma_handle h, int dtype, int shape[3], double *ms);
  * all levels, vector and matrix cores (0 when not timed).  MLFMA_ERR_ARG for
  * a NULL handle. */
 int mlfma_tuning_steps(mlfma_handle h, int *matrix_cores, double ms[2]);
+
+/* Shape of the vector level-step kernels of the step between octree level
+ * `level` (2 <= level < levels - 1) and level + 1 for products of four or
+ * more right-hand sides in precision dtype: shape[0], shape[1] = the
+ * aggregation's right-hand sides per workgroup (0: the launcher's default)
+ * and pipelined right-hand sides per pass (0: not pipelined); shape[2],
+ * shape[3] the same for the disaggregation.  MLFMA_ERR_ARG for a NULL handle
+ * or shape, an unknown dtype or a level out of range. */
+int mlfma_tuning_level(mlfma_handle h, int dtype, int level, int shape[4]);
 
 /*
  * Stage timing with HIP events recorded on the matvec's stream.  Stages:

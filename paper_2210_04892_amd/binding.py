@@ -81,6 +81,7 @@ def lib():
         L.mlfma_near_info.argtypes = [P, P]
         L.mlfma_tuning.argtypes = [P, ctypes.c_int, P, P]
         L.mlfma_tuning_steps.argtypes = [P, ctypes.POINTER(ctypes.c_int), P]
+        L.mlfma_tuning_level.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
         L.mlfma_graph_create.argtypes = [P, ctypes.c_int, ctypes.c_int, LL, P, LL, P, LL, ctypes.POINTER(P)]
         L.mlfma_graph_launch.argtypes = [P, P]
         L.mlfma_graph_destroy.argtypes = [P]
@@ -134,7 +135,7 @@ class Geometry:
                  near_precision="fp64", far_precision="fp64"):
         o = default_options()
         o.trans_kernel = {"auto": 0, "tiled": 1, "groups": 2}[trans_kernel]
-        o.level_kernel = {"auto": 0, "vector": 1, "matrix": 2}[level_kernel]
+        o.level_kernel = {"auto": 0, "vector": 1, "matrix": 2, "blocked": 3, "pipelined": 4}[level_kernel]
         # arithmetic of the near and far parts of complex128 products
         o.near_precision = {"fp64": 1, "fp32": 2}[near_precision]
         o.far_precision = {"fp64": 1, "fp32": 2}[far_precision]
@@ -244,6 +245,18 @@ class Geometry:
         ms = np.zeros(2, np.float64)
         _check(lib().mlfma_tuning_steps(self._h, ctypes.byref(m), ms.ctypes.data))
         return {"matrix_cores": bool(m.value), "ms_vector": float(ms[0]), "ms_matrix": float(ms[1])}
+
+    def tuning_levels(self, dtype=torch.complex64):
+        """Vector level-step kernel shapes for four or more right-hand sides
+        (mlfma_tuning_level): {level: {"agg_rb", "agg_pipe", "dis_rb",
+        "dis_pipe"}} for the steps between level and level + 1."""
+        dt = C128 if dtype == torch.complex128 else C64
+        out = {}
+        for lev in range(2, self.levels - 1):
+            s = np.zeros(4, np.int32)
+            _check(lib().mlfma_tuning_level(self._h, dt, lev, s.ctypes.data))
+            out[lev] = {"agg_rb": int(s[0]), "agg_pipe": int(s[1]), "dis_rb": int(s[2]), "dis_pipe": int(s[3])}
+        return out
 
     def profile(self, enable=True):
         _check(lib().mlfma_profile(self._h, 1 if enable else 0))

@@ -63,6 +63,13 @@ struct PrecLevel {
     T *ath_w = nullptr, *aph_w = nullptr, *dph_w = nullptr, *dth_w = nullptr;
     StepPlan agg, dis;      // step from level l + 1 up to l, and from l down to l + 1
     StepPlan agg1, dis1;    // the same with smaller chunks (more workgroups) for fewer than four RHS
+    int agg_rb = 0, dis_rb = 0;   // right-hand sides per workgroup with four or more (autotuned; 0 = default)
+    int dis_pipe = 0;             // > 0: pipelined disaggregation with this many per pass (autotuned)
+    int agg_pipe = 0;             // the same for the aggregation
+    // separable aggregation stencils (SepStencil; tth = 0: not separable)
+    int ag_tth = 0, ag_tphi = 0;
+    int *ag_th_row = nullptr, *ag_th_sh = nullptr, *ag_phi_col = nullptr;
+    T *ag_th_w = nullptr, *ag_phi_w = nullptr;
     int tphi = 0, tth = 0;  // separable disaggregation stencils (0 = not separable)
     int *phi_col = nullptr, *th_row = nullptr, *th_sh = nullptr;
     T *phi_w = nullptr, *rowf = nullptr, *th_w = nullptr;
@@ -286,6 +293,16 @@ void plan_level_steps(mlfma_ctx *c, int l, PrecLevel<T> &PL)
                           [&](int wrows, int rows) { return agg_lds_bytes<T>(wrows, rows, C.nph); }, STEP_LDS_MAX,
                           cp);
         (small ? PL.agg1 : PL.agg) = {cp.rows, cp.nchunk, cp.wrows, cp.rows ? c->upload(cp.win) : nullptr};
+    }
+    SepStencil sa;
+    if (separable_aggregation(L, C, tr.agg_phi[l], tr.agg_theta[l], sa)) {
+        PL.ag_tth = sa.tth;
+        PL.ag_tphi = sa.tphi;
+        PL.ag_th_row = c->upload(sa.th_row);
+        PL.ag_th_sh = c->upload(sa.th_sh);
+        PL.ag_th_w = c->upload(cast_vec<T>(sa.th_w));
+        PL.ag_phi_col = c->upload(sa.phi_col);
+        PL.ag_phi_w = c->upload(cast_vec<T>(sa.phi_w));
     }
     SepStencil sep;
     if (!separable_disaggregation(L, C, tr.dis_phi[l], tr.dis_theta[l], sep)) return;
@@ -1245,6 +1262,8 @@ LevelStep<T> step_args(mlfma_ctx *c, Prec<T> &P, int l, bool agg, int nrhs)
     a.nchunk = pl.nchunk;
     a.wrows = pl.wrows;
     a.win = pl.win;
+    a.rb = small ? 0 : (agg ? PL.agg_rb : PL.dis_rb);
+    a.pipe = small ? 0 : (agg ? PL.agg_pipe : PL.dis_pipe);
     a.taps = c->opt.interp_order;
     a.child_start = I.child_start;
     a.parent = c->lv[l + 1].parent;
@@ -1255,6 +1274,14 @@ LevelStep<T> step_args(mlfma_ctx *c, Prec<T> &P, int l, bool agg, int nrhs)
         a.w1 = PL.ath_w;
         a.c2 = I.aph_c;
         a.w2 = PL.aph_w;
+        // the separable form, for the pipelined kernel
+        a.tphi = PL.ag_tphi;
+        a.tth = PL.ag_tth;
+        a.phi_col = PL.ag_phi_col;
+        a.th_row = PL.ag_th_row;
+        a.th_sh = PL.ag_th_sh;
+        a.phi_w = PL.ag_phi_w;
+        a.th_w = PL.ag_th_w;
     } else {
         a.tphi = PL.tphi;
         a.tth = PL.tth;
@@ -1266,6 +1293,74 @@ LevelStep<T> step_args(mlfma_ctx *c, Prec<T> &P, int l, bool agg, int nrhs)
         a.th_w = PL.th_w;
     }
     return a;
+}
+
+// Kernel shape of every vector level step (aggregation and disaggregation,
+// each level on its own): 1, 2 or 4 right-hand sides per workgroup, or the
+// pipelined kernel with 1 or 2 per pass,
+// whichever runs the step fastest with the handle's right-hand-side count
+// (capped at 16; one warm-up and three timed runs each, on zeroed patterns).
+// Handles for fewer than four right-hand sides keep the launchers' default;
+// the options can fix the choice (blocked kernels only, or pipelined ones
+// wherever they fit).
+template <class T>
+void tune_step_rb(mlfma_ctx *c, Prec<T> &P)
+{
+    const Tree &tr = c->tr;
+    if (c->opt.level_kernel == MLFMA_LEVELS_PIPELINED) {
+        for (int l = 2; l + 1 < tr.levels; l++) P.lv[l].agg_pipe = P.lv[l].dis_pipe = 2;
+        return;
+    }
+    const bool blocked = c->opt.level_kernel == MLFMA_LEVELS_BLOCKED;
+    const int nrhs = std::min(c->opt.max_rhs, 16);
+    if (nrhs < 4) return;
+    hipStream_t st;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    Workspace &w = c->ws;
+    for (int l = 2; l < tr.levels; l++) {
+        launch_zero<T>((cpx<T> *)w.U[l], (long long)tr.lv[l].nbox * tr.lv[l].K * 2 * nrhs, st);
+        launch_zero<T>((cpx<T> *)w.V[l], (long long)tr.lv[l].nbox * tr.lv[l].K * 2 * nrhs, st);
+    }
+    for (int l = 2; l + 1 < tr.levels; l++) {
+        for (int agg = 0; agg < 2; agg++) {
+            int &rb = agg ? P.lv[l].agg_rb : P.lv[l].dis_rb;
+            int &pipe = agg ? P.lv[l].agg_pipe : P.lv[l].dis_pipe;
+            double best = 1e30;
+            int pick = 0, pick_pipe = 0;
+            for (int cand : {1, 2, 4, -1, -2}) {
+                if (cand < 0 && blocked) break;
+                rb = cand > 0 ? cand : 0;
+                pipe = cand < 0 ? -cand : 0;
+                LevelStep<T> a = step_args<T>(c, P, l, agg != 0, nrhs);
+                a.in = (const cpx<T> *)(agg ? w.U[l + 1] : w.V[l]);
+                a.out = (cpx<T> *)(agg ? w.U[l] : w.V[l + 1]);
+                auto run = [&] {
+                    return agg ? launch_aggregate_step<T>(a, nrhs, st) : launch_disaggregate_step<T>(a, nrhs, st);
+                };
+                if (!run()) break;   // the step has no fused kernel: nothing to tune
+                HIPCHK(hipEventRecord(e0, st));
+                for (int i = 0; i < 3; i++) run();
+                HIPCHK(hipEventRecord(e1, st));
+                HIPCHK(hipEventSynchronize(e1));
+                float t = 0;
+                HIPCHK(hipEventElapsedTime(&t, e0, e1));
+                if (t < best) {
+                    best = t;
+                    pick = rb;
+                    pick_pipe = pipe;
+                }
+            }
+            rb = pick;
+            pipe = pick_pipe;
+        }
+    }
+    HIPCHK(hipGetLastError());
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
 }
 
 // Level steps of complex64 products: the vector kernels (levels.hip) or the
@@ -1280,7 +1375,7 @@ void tune_level_steps(mlfma_ctx *c)
     P.level_mfma = 0;
     bool any = false;
     for (int l = 2; l + 1 < tr.levels; l++) any |= P.lv[l].agg_m.ok && P.lv[l].dis_m.ok;
-    if (!any || c->opt.level_kernel == MLFMA_LEVELS_VECTOR) return;
+    if (!any || (c->opt.level_kernel != MLFMA_LEVELS_AUTO && c->opt.level_kernel != MLFMA_LEVELS_MATRIX)) return;
     if (c->opt.level_kernel == MLFMA_LEVELS_MATRIX) {
         P.level_mfma = 1;
         return;
@@ -1844,7 +1939,7 @@ int mlfma_build_tree(const double *verts, long long n_verts, const int *tris, lo
         if (c->opt.max_rhs < 1) throw Error(MLFMA_ERR_ARG, "max_rhs must be >= 1");
         if (c->opt.trans_kernel < MLFMA_TRANS_AUTO || c->opt.trans_kernel > MLFMA_TRANS_GROUPS)
             throw Error(MLFMA_ERR_ARG, "unknown translation kernel");
-        if (c->opt.level_kernel < MLFMA_LEVELS_AUTO || c->opt.level_kernel > MLFMA_LEVELS_MATRIX)
+        if (c->opt.level_kernel < MLFMA_LEVELS_AUTO || c->opt.level_kernel > MLFMA_LEVELS_PIPELINED)
             throw Error(MLFMA_ERR_ARG, "unknown level-step kernel");
         for (int pr : {c->opt.near_precision, c->opt.far_precision})
             if (pr < MLFMA_PREC_DTYPE || pr > MLFMA_PREC_FP32) throw Error(MLFMA_ERR_ARG, "unknown precision");
@@ -1862,6 +1957,8 @@ int mlfma_build_tree(const double *verts, long long n_verts, const int *tris, lo
         ensure_workspace(c.get(), c->opt.max_rhs);
         tune_translation<double>(c.get(), c->p64);
         tune_translation<float>(c.get(), c->p32);
+        tune_step_rb<double>(c.get(), c->p64);
+        tune_step_rb<float>(c.get(), c->p32);
         tune_level_steps(c.get());
         *out = c.release();
         return MLFMA_OK;
@@ -2293,6 +2390,22 @@ int mlfma_tuning_steps(mlfma_handle h, int *matrix_cores, double ms[2])
         ms[0] = h->p32.step_ms[0];
         ms[1] = h->p32.step_ms[1];
     }
+    return MLFMA_OK;
+}
+
+int mlfma_tuning_level(mlfma_handle h, int dtype, int level, int shape[4])
+{
+    if (!h || !shape || (dtype != MLFMA_C128 && dtype != MLFMA_C64)) return fail(Error(MLFMA_ERR_ARG, "bad argument"));
+    if (level < 2 || level + 1 >= h->tr.levels) return fail(Error(MLFMA_ERR_ARG, "level out of range"));
+    auto get = [&](const auto &P) {
+        const auto &PL = P.lv[level];
+        shape[0] = PL.agg_rb;
+        shape[1] = PL.agg_pipe;
+        shape[2] = PL.dis_rb;
+        shape[3] = PL.dis_pipe;
+    };
+    if (dtype == MLFMA_C64) get(h->p32);
+    else get(h->p64);
     return MLFMA_OK;
 }
 

@@ -676,6 +676,66 @@ void plan_theta_chunks(const Csr &theta, int n_out, int nph, int rows0,
     }
 }
 
+// -------------------------------------------- separable aggregation stencils
+bool separable_aggregation(const Level &P, const Level &C, const Csr &aph, const Csr &ath, SepStencil &o)
+{
+    o = SepStencil();
+    const int nthp = P.nth, nphp = P.nph, nphc = C.nph;
+    if (ath.rows != nthp * nphc || aph.rows != nthp * nphp) return false;
+    auto same = [](double a, double b) { return a == b; };
+    // theta: taps of (parent row ip, child column 0), then every column j
+    for (int ip = 0; ip < nthp; ip++) o.tth = std::max(o.tth, ath.start[ip * nphc + 1] - ath.start[ip * nphc]);
+    for (int jp = 0; jp < nphp; jp++) o.tphi = std::max(o.tphi, aph.start[jp + 1] - aph.start[jp]);
+    if (o.tth < 1 || o.tphi < 1) return false;
+    o.th_row.assign((size_t)nthp * o.tth, 0);
+    o.th_sh.assign((size_t)nthp * o.tth, 0);
+    o.th_w.assign((size_t)nthp * o.tth, 0.0);
+    for (int ip = 0; ip < nthp; ip++) {
+        const int r0 = ip * nphc, n0 = ath.start[r0 + 1] - ath.start[r0];
+        if (n0 != o.tth) return false;
+        for (int t = 0; t < n0; t++) {
+            const int e = ath.start[r0] + t;
+            o.th_row[(size_t)ip * o.tth + t] = ath.col[e] / nphc;
+            o.th_sh[(size_t)ip * o.tth + t] = ath.col[e] % nphc;
+            o.th_w[(size_t)ip * o.tth + t] = ath.w[e];
+        }
+        for (int j = 1; j < nphc; j++) {
+            const int r = ip * nphc + j;
+            if (ath.start[r + 1] - ath.start[r] != n0) return false;
+            for (int t = 0; t < n0; t++) {
+                const int e = ath.start[r] + t;
+                const int row = ath.col[e] / nphc, sh = ((ath.col[e] % nphc - j) % nphc + nphc) % nphc;
+                if (row != o.th_row[(size_t)ip * o.tth + t] || sh != o.th_sh[(size_t)ip * o.tth + t] ||
+                    !same(ath.w[e], o.th_w[(size_t)ip * o.tth + t]))
+                    return false;
+            }
+        }
+    }
+    // phi: taps of (parent row 0, parent column jp), then every row ip
+    o.phi_col.assign((size_t)nphp * o.tphi, 0);
+    o.phi_w.assign((size_t)nphp * o.tphi, 0.0);
+    for (int jp = 0; jp < nphp; jp++) {
+        const int n0 = aph.start[jp + 1] - aph.start[jp];
+        if (n0 != o.tphi) return false;
+        for (int t = 0; t < n0; t++) {
+            const int e = aph.start[jp] + t;
+            o.phi_col[(size_t)jp * o.tphi + t] = aph.col[e];
+            o.phi_w[(size_t)jp * o.tphi + t] = aph.w[e];
+        }
+        for (int ip = 1; ip < nthp; ip++) {
+            const int r = ip * nphp + jp;
+            if (aph.start[r + 1] - aph.start[r] != n0) return false;
+            for (int t = 0; t < n0; t++) {
+                const int e = aph.start[r] + t;
+                if (aph.col[e] != ip * nphc + o.phi_col[(size_t)jp * o.tphi + t] ||
+                    !same(aph.w[e], o.phi_w[(size_t)jp * o.tphi + t]))
+                    return false;
+            }
+        }
+    }
+    return true;
+}
+
 // ------------------------------------------ separable disaggregation stencils
 bool separable_disaggregation(const Level &P, const Level &C, const Csr &dph, const Csr &dth, SepStencil &o)
 {

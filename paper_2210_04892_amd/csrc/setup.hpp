@@ -136,6 +136,14 @@ struct SepStencil {
 // false when the step's stencils are not separable in this way
 bool separable_disaggregation(const Level &parent, const Level &child, const Csr &dph, const Csr &dth,
                               SepStencil &out);
+// The aggregation stencils of one step in the same form (rowf empty), taps in
+// the stencils' own order: the theta stencil of a parent theta row is the
+// same for every child phi column up to the half-turn shift, and the phi
+// stencil of a parent phi column the same for every parent theta row:
+//   intermediate(ip, j) = sum_t th_w[ip][t] * child(th_row[ip][t], (j + th_sh[ip][t]) mod nph_c)
+//   parent(ip, jp) = sum_t phi_w[jp][t] * intermediate(ip, phi_col[jp][t])
+bool separable_aggregation(const Level &parent, const Level &child, const Csr &aph, const Csr &ath,
+                           SepStencil &out);
 
 void build_surface(Surface &s, const double *verts, long long nv, const int *tris, long long nt);
 void build_rwg(const Surface &s, RwgTable &r);

@@ -62,31 +62,41 @@ __global__ __launch_bounds__(GWAVES * WAVE) void k_translate_groups(const GroupA
     for (int t = 0; t < TG; t++)
 #pragma unroll
         for (int j = 0; j < RB; j++) acc[t][0][j] = acc[t][1][j] = mk<T>(0, 0);
-    // the next record's source samples are loaded while the current one is summed
-    cpx<T> u0[RB], u1[RB];
+    // the next record (its source samples, operator values and offsets) is
+    // loaded while the current one is summed, so that the wait for its data
+    // does not also wait for loads issued in the same iteration
+    cpx<T> u0[RB], u1[RB], opn[TG];
+    int offn[TG];
+    const int *srcp = L.src, *offp = L.off;
+    const cpx<T> *Ub = L.U;
     auto load = [&](int r) {
-        const cpx<T> *us = L.U + (long long)ldu(L.src, r) * S;
+        const cpx<T> *us = Ub + (long long)ldu(srcp, r) * S;
 #pragma unroll
         for (int j = 0; j < RB; j++) {
             u0[j] = us[ro[j]];
             u1[j] = us[half + ro[j]];
         }
+#pragma unroll
+        for (int t = 0; t < TG; t++) {
+            offn[t] = ldu(offp, r * TG + t);
+            opn[t] = tq[(long long)max(offn[t], 0) * K];   // a valid row also where the source is absent
+        }
     };
     if (r0 < r1) load(r0);
     for (int r = r0; r < r1; r++) {
-        cpx<T> v0[RB], v1[RB];
+        cpx<T> v0[RB], v1[RB], op[TG];
+        int off[TG];
 #pragma unroll
         for (int j = 0; j < RB; j++) {
             v0[j] = u0[j];
             v1[j] = u1[j];
         }
+#pragma unroll
+        for (int t = 0; t < TG; t++) {
+            op[t] = opn[t];
+            off[t] = offn[t];
+        }
         if (r + 1 < r1) load(r + 1);
-        int off[TG];
-#pragma unroll
-        for (int t = 0; t < TG; t++) off[t] = ldu(L.off, r * TG + t);
-        cpx<T> op[TG];
-#pragma unroll
-        for (int t = 0; t < TG; t++) op[t] = off[t] >= 0 ? tq[(long long)off[t] * K] : mk<T>(0, 0);
 #pragma unroll
         for (int t = 0; t < TG; t++) {
             if (off[t] < 0) continue;   // uniform: the source is not in target t's list

@@ -244,6 +244,50 @@ def test_translation_kernels(kernel):
 
 
 @pytest.mark.parametrize("name,nrows", [("sphere_r3", 160), ("box_4x4x1", 96)])
+def test_pipelined_level_steps(name, nrows):
+    """The vector level steps pipelined over the right-hand sides (and, in
+    the aggregation, over the children) against the blocked ones, forced in
+    turn, for 5 and 20 right-hand sides (a ragged pass of two) in both
+    precisions: every level's far-field part against the oracle's pairs of
+    that level, the whole product against the oracle, and the far fields of
+    the two kernels against each other (same arithmetic term for term, so
+    they agree to rounding; in single precision the rounding of the
+    patterns is amplified by the cancellation of the large translation
+    operators, as between the two precisions)."""
+    torch = _torch()
+    import paper_2210_04892_amd as mf
+    v, t = mesh(name)
+    gp = mf.Geometry(v, t, k=K0, max_rhs=20, level_kernel="pipelined").precompute()
+    gb = mf.Geometry(v, t, k=K0, max_rhs=20, level_kernel="blocked").precompute()
+    shapes = gp.tuning_levels()
+    assert all(s["agg_pipe"] == 2 and s["dis_pipe"] == 2 for s in shapes.values())
+    assert all(s["agg_pipe"] == 0 and s["dis_pipe"] == 0 for s in gb.tuning_levels().values())
+    for nrhs in (5, 20):
+        x, rows, ref = reference(name, nrows, nrhs, 7)
+        N = x.shape[0] // 2
+        for dtype, tol_far in ((np.complex64, 2e-3), (np.complex128, 1e-9)):
+            xt = torch.from_numpy(x.astype(dtype)).cuda()
+            for op in ("C", "EM"):
+                y = gp.matvec(xt, op=op).cpu().numpy().astype(np.complex128)
+                err = _rel(_pick(y, rows, N), ref[op].sum(axis=0))
+                fp = gp.matvec(xt, op=op, part=mf.PART_FAR).cpu().numpy().astype(np.complex128)
+                fb = gb.matvec(xt, op=op, part=mf.PART_FAR).cpu().numpy().astype(np.complex128)
+                d = _rel(fp, fb)
+                print("[gpu] %s pipelined level steps, nrhs %d %s op %s: rel err %.2e, far field vs blocked %.2e"
+                      % (name, nrhs, np.dtype(dtype).name, op, err, d), flush=True)
+                assert err <= MLFMA_TOL
+                assert d <= tol_far
+        xt = torch.from_numpy(x.astype(np.complex64)).cuda()
+        for lev in range(2, gp.levels):
+            yl = gp.matvec(xt, op="C", part=mf.PART_LEVEL + lev).cpu().numpy().astype(np.complex128)
+            own = np.linalg.norm(_pick(yl, rows, N) - ref["C"][lev]) / np.linalg.norm(ref["C"][lev])
+            print("[gpu] %s pipelined steps level %d: own rel err %.2e" % (name, lev, own), flush=True)
+            assert own <= LEVEL_OWN_TOL
+    gp.release()
+    gb.release()
+
+
+@pytest.mark.parametrize("name,nrows", [("sphere_r3", 160), ("box_4x4x1", 96)])
 def test_level_step_kernels(name, nrows):
     """complex64 level steps on the matrix cores and on the vector units,
     forced in turn: the whole product against the oracle for 1 and 20
