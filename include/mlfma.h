@@ -433,10 +433,13 @@ int mlfma_near_info(mlfma_handle h, long long info[4]);
  * shape[0] = target boxes per tile (= waves per workgroup), shape[1] =
  * source boxes per LDS batch; sibling-group kernel (sums of all targets of a
  * group of siblings kept in registers, sources streamed once per group):
- * shape[0] = targets per group, shape[1] = 0.  shape[2] = right-hand sides
- * per lane; *ms (may be NULL) = the timed translation of all levels,
- * milliseconds.  dtype MLFMA_C128 or MLFMA_C64; MLFMA_ERR_ARG otherwise. */
-int mlfma_tuning(mlfma_handle h, int dtype, int shape[3], double *ms);
+ * shape[0] = targets per group, shape[1] = 0 (a group is one sibling set or
+ * part of one) or -1 (whole sibling sets merged up to shape[0] targets).  shape[2] = right-hand sides
+ * per lane; shape[3] = lanes of a wavefront over the right-hand sides
+ * (sibling-group kernel; 0 for the tiled one); *ms (may be NULL) = the timed
+ * translation of all levels, milliseconds.  dtype MLFMA_C128 or MLFMA_C64;
+ * MLFMA_ERR_ARG otherwise. */
+int mlfma_tuning(mlfma_handle h, int dtype, int shape[4], double *ms);
 
 /* Level steps of complex64 products (aggregation with Lagrange
  * interpolation, disaggregation with anterpolation; Sec. II-E): on the

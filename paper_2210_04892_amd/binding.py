@@ -229,13 +229,14 @@ class Geometry:
     def tuning(self):
         """Translation kernel and shape picked by the autotuner, per precision:
         {"c64": (targets per tile or group, sources per LDS batch (0 = the
-        sibling-group kernel), rhs per lane, ms), "c128": ...}."""
+        sibling-group kernel, -1 = it on merged sibling sets), rhs per lane,
+        ms, lanes over the rhs (0 for the tiled kernel)), "c128": ...}."""
         out = {}
         for name, dt in (("c64", C64), ("c128", C128)):
-            sh = np.zeros(3, np.int32)
+            sh = np.zeros(4, np.int32)
             ms = ctypes.c_double(0)
             _check(lib().mlfma_tuning(self._h, dt, sh.ctypes.data, ctypes.byref(ms)))
-            out[name] = (int(sh[0]), int(sh[1]), int(sh[2]), float(ms.value))
+            out[name] = (int(sh[0]), int(sh[1]), int(sh[2]), float(ms.value), int(sh[3]))
         return out
 
     def tuning_steps(self):

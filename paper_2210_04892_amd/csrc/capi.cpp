@@ -91,16 +91,19 @@ struct Prec {
     std::vector<PrecLevel<T>> lv;
     int trans_tmax = 0, trans_smax = 0, trans_rb = 1;   // translation tile shape (autotuned)
     int trans_group = 0;                          // > 0: sibling-group kernel with this many targets per group
+    int trans_rw = 0;                             // its lanes over the right-hand sides (0: default)
+    int trans_gi = 0;                             // its group table (group_args)
     int level_mfma = 0;                           // level steps on the matrix cores (complex64, autotuned)
     double step_ms[2] = {0, 0};                   // timed level steps: vector, matrix cores
     double trans_ms = 0;                          // its timed translation, ms
 };
 
 struct IntLevel {
-    // sibling groups of the register-blocked translation, for 4 and 8 targets
-    int g_ngroup[2] = {0, 0};
-    int *g_first[2] = {nullptr, nullptr}, *g_count[2] = {nullptr, nullptr}, *g_rec[2] = {nullptr, nullptr};
-    int *g_src[2] = {nullptr, nullptr}, *g_off[2] = {nullptr, nullptr};
+    // sibling groups of the register-blocked translation: 4 targets, 8
+    // targets, 8 targets of merged whole sibling sets
+    int g_ngroup[3] = {0, 0, 0};
+    int *g_first[3] = {}, *g_count[3] = {}, *g_rec[3] = {};
+    int *g_src[3] = {}, *g_off[3] = {};
     int *il_start = nullptr, *il_box = nullptr, *il_off = nullptr;
     int *child_start = nullptr, *parent = nullptr, *oct = nullptr;
     int *ath_s = nullptr, *ath_c = nullptr, *aph_s = nullptr, *aph_c = nullptr;
@@ -553,15 +556,16 @@ TransArgs<T> trans_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level)
     return ta;
 }
 
-// arguments of the sibling-group translation (tg targets per group)
+// arguments of the sibling-group translation with group table gi (0: 4
+// targets, 1: 8 targets, 2: 8 targets of merged sibling sets)
 template <class T>
-GroupArgs<T> group_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, int tg, int rb)
+GroupArgs<T> group_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, int gi, int rb, int rw)
 {
     const Tree &tr = c->tr;
-    const int gi = tg == 8 ? 1 : 0;
     GroupArgs<T> ga;
-    ga.tg = tg;
+    ga.tg = gi == 0 ? 4 : 8;
     ga.rb = rb;
+    ga.rw = rw;
     for (int l = 2; l < tr.levels; l++) {
         if (only_level >= 0 && l != only_level) continue;
         const IntLevel &I = c->lv[l];
@@ -585,7 +589,8 @@ template <class T>
 void launch_translation(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, int nrhs, hipStream_t st)
 {
     if (P.trans_group > 0) {
-        if (!launch_translate_groups<T>(group_args<T>(c, P, w, only_level, P.trans_group, P.trans_rb), nrhs, st))
+        if (!launch_translate_groups<T>(group_args<T>(c, P, w, only_level, P.trans_gi, P.trans_rb, P.trans_rw),
+                                        nrhs, st))
             throw Error(MLFMA_ERR_STATE, "invalid sibling-group translation shape");
     } else if (!launch_translate_tiled<T>(trans_args<T>(c, P, w, only_level), nrhs, st)) {
         throw Error(MLFMA_ERR_STATE, "translation tiles missing");
@@ -651,13 +656,20 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
                 }
             }
     }
-    int bg = 0;
-    for (int tg : {4, 8})
-        for (int rb : {1, 2, 4}) {
+    int bg = 0, bw = 0, bgi = 0;
+    // sibling-group shapes: (lanes over the RHS, RHS per lane) within the
+    // handle's right-hand sides (the default lane split always)
+    const int shapes[9][2] = {{1, 1}, {2, 1}, {4, 1}, {4, 2}, {4, 4}, {8, 1}, {8, 2}, {16, 1}, {2, 8}};
+    for (int gi : {0, 1, 2})
+        for (const auto &sh : shapes) {
             if (c->opt.trans_kernel == MLFMA_TRANS_TILED) break;
-            if (rb > 1 && (trans_rw(nrhs) != 4 || nrhs < 4 * rb)) continue;
+            const int tg = gi == 0 ? 4 : 8;
+            const int rw = sh[0], rb = sh[1];
+            const int def = trans_rw(nrhs);
+            if (!(rw == def && rb == 1) && (rw * rb > nrhs || rw * rb < def)) continue;
             if (sizeof(T) == 8 && tg * rb > 8) continue;   // register budget of the double-precision sums
-            const GroupArgs<T> ga = group_args<T>(c, P, c->ws, -1, tg, rb);
+            if (rb == 8 && (tg != 4 || sizeof(T) != 4 || nrhs < 16)) continue;
+            const GroupArgs<T> ga = group_args<T>(c, P, c->ws, -1, gi, rb, rw);
             if (!launch_translate_groups<T>(ga, nrhs, st)) throw Error(MLFMA_ERR_HIP, "invalid sibling-group shape");
             HIPCHK(hipEventRecord(e0, st));
             for (int i = 0; i < 3; i++) launch_translate_groups<T>(ga, nrhs, st);
@@ -669,6 +681,8 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
                 best = ms;
                 bg = tg;
                 bb = rb;
+                bw = rw;
+                bgi = gi;
             }
         }
     (void)hipEventDestroy(e0);
@@ -679,6 +693,8 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
         // small valid set so that the kernel stays callable
         upload_trans_tiles<T>(c, P, 8, 16, nullptr);
         P.trans_group = bg;
+        P.trans_rw = bw;
+        P.trans_gi = bgi;
     } else {
         upload_trans_tiles<T>(c, P, bt, bs, nullptr);
         P.trans_group = 0;
@@ -723,9 +739,9 @@ void build_device_tables(mlfma_ctx *c)
         I.il_off = c->upload(L.il_off);
         I.parent = c->upload(L.parent);
         I.oct = c->upload(L.child_oct);
-        for (int gi = 0; gi < 2; gi++) {
+        for (int gi = 0; gi < 3; gi++) {
             GroupTiles gt;
-            build_group_tiles(L, gi ? 8 : 4, gt);
+            build_group_tiles(L, gi ? 8 : 4, gt, gi == 2);
             I.g_ngroup[gi] = (int)gt.first.size();
             I.g_first[gi] = c->upload(gt.first);
             I.g_count[gi] = c->upload(gt.count);
@@ -2371,13 +2387,15 @@ int mlfma_level_info(mlfma_handle h, int level, long long info[6])
     return MLFMA_OK;
 }
 
-int mlfma_tuning(mlfma_handle h, int dtype, int shape[3], double *ms)
+int mlfma_tuning(mlfma_handle h, int dtype, int shape[4], double *ms)
 {
     if (!h || !shape || (dtype != MLFMA_C128 && dtype != MLFMA_C64)) return fail(Error(MLFMA_ERR_ARG, "bad argument"));
     const int group = dtype == MLFMA_C64 ? h->p32.trans_group : h->p64.trans_group;
     shape[0] = group > 0 ? group : (dtype == MLFMA_C64 ? h->p32.trans_tmax : h->p64.trans_tmax);
-    shape[1] = group > 0 ? 0 : (dtype == MLFMA_C64 ? h->p32.trans_smax : h->p64.trans_smax);
+    const int merged = (dtype == MLFMA_C64 ? h->p32.trans_gi : h->p64.trans_gi) == 2;
+    shape[1] = group > 0 ? -merged : (dtype == MLFMA_C64 ? h->p32.trans_smax : h->p64.trans_smax);
     shape[2] = dtype == MLFMA_C64 ? h->p32.trans_rb : h->p64.trans_rb;
+    shape[3] = group > 0 ? (dtype == MLFMA_C64 ? h->p32.trans_rw : h->p64.trans_rw) : 0;
     if (ms) *ms = dtype == MLFMA_C64 ? h->p32.trans_ms : h->p64.trans_ms;
     return MLFMA_OK;
 }

@@ -175,9 +175,10 @@ struct GroupLevel {
 template <class T>
 struct GroupArgs {
     int nlev = 0, nblocks = 0, tg = 4, rb = 1;   // tg: targets per group (4 or 8); rb: RHS per lane
+    int rw = 0;                                  // lanes over the RHS (1, 2, 4, 8, 16; 0: trans_rw(nrhs))
     GroupLevel<T> lv[TRANS_MAXLEV];
 };
-// false when (tg, rb) has no kernel
+// false when (tg, rw, rb) has no kernel
 template <class T>
 bool launch_translate_groups(const GroupArgs<T> &a, int nrhs, hipStream_t s);
 // One octree step of aggregation (children at level l+1 -> parents at l) or

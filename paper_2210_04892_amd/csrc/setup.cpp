@@ -606,7 +606,7 @@ void build_translation_tiles(const Level &L, int smax, int tmax, TransTiles &t)
     }
 }
 
-void build_group_tiles(const Level &L, int tg, GroupTiles &g)
+void build_group_tiles(const Level &L, int tg, GroupTiles &g, bool merge)
 {
     if (tg < 1 || tg > 16) throw Error(MLFMA_ERR_ARG, "bad sibling group size");
     g = GroupTiles();
@@ -617,6 +617,16 @@ void build_group_tiles(const Level &L, int tg, GroupTiles &g)
     while (A0 < L.nbox) {
         int A1 = A0 + 1;
         while (A1 < L.nbox && A1 - A0 < tg && L.parent[A1] == L.parent[A0]) A1++;
+        // with merge, a whole sibling set takes the following whole sibling
+        // sets while the group has room
+        const bool whole = (A1 >= L.nbox || L.parent[A1] != L.parent[A1 - 1]) &&
+                           (A0 == 0 || L.parent[A0] != L.parent[A0 - 1]);
+        while (merge && whole && A1 < L.nbox) {
+            int B1 = A1 + 1;
+            while (B1 < L.nbox && L.parent[B1] == L.parent[A1]) B1++;
+            if (B1 - A0 > tg) break;
+            A1 = B1;
+        }
         ent.clear();
         for (int A = A0; A < A1; A++)
             for (int e = L.il_start[A]; e < L.il_start[A + 1]; e++) {

@@ -100,12 +100,15 @@ void build_translation_tiles(const Level &L, int smax, int tmax, TransTiles &t);
 // rec_start[g] .. rec_start[g + 1] - 1; record r is source box src[r] and,
 // for target slot j < tg, offset id off[r * tg + j] (0..342, the 7 x 7 x 7
 // window of the operator table) or -1 when the source is not in that
-// target's interaction list.  Records are sorted by source box.
+// target's interaction list.  Records are sorted by source box.  With
+// merge, a whole sibling set also takes the following whole sibling sets
+// (consecutive in Morton order) while the group has room: fewer groups,
+// more targets each, sources shared by more of them.
 struct GroupTiles {
     int tg = 0;
     std::vector<int> first, count, rec_start, src, off;
 };
-void build_group_tiles(const Level &L, int tg, GroupTiles &g);
+void build_group_tiles(const Level &L, int tg, GroupTiles &g, bool merge = false);
 
 // Theta-row chunks for a level step done in LDS.  `theta` is the step's theta
 // stencil, whose rows are (output theta row) * nph + phi column and whose

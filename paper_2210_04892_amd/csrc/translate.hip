@@ -10,7 +10,9 @@
 // value is loaded once per group instead of once per (target, source) pair.
 //
 // Lanes: QW = 64 / RW consecutive samples x RW right-hand sides; each lane
-// handles RB right-hand sides (rbase + j RW).  A workgroup of four waves
+// handles RB right-hand sides (rbase + j RW).  Fewer samples per wave (more
+// lanes over the right-hand sides) load each operator value for fewer sums
+// but keep fewer sums per lane (more waves resident): the autotuner picks.  A workgroup of four waves
 // takes four consecutive sample chunks of one group.  Workgroups are ordered
 // sample chunk first, group second, and every XCD takes a contiguous range
 // of each level: consecutive groups (Morton order) share sources through the
@@ -127,12 +129,16 @@ __global__ __launch_bounds__(GWAVES * WAVE) void k_translate_groups(const GroupA
 template <class T>
 bool launch_translate_groups(const GroupArgs<T> &args, int nrhs, hipStream_t s)
 {
-    const int tg = args.tg, rb = args.rb;
-    if (!((tg == 4 || tg == 8) && (rb == 1 || rb == 2 || rb == 4))) return false;
+    const int tg = args.tg, rb = args.rb, rw = args.rw > 0 ? args.rw : trans_rw(nrhs);
+    if (tg != 4 && tg != 8) return false;
+    // (lanes over the RHS, RHS per lane) with a kernel
+    const bool ok = (rb == 1 && (rw == 1 || rw == 2 || rw == 4 || rw == 8 || rw == 16)) ||
+                    (rw == 4 && (rb == 2 || rb == 4)) || (rw == 8 && rb == 2) ||
+                    (rw == 2 && rb == 8 && tg == 4 && sizeof(T) == 4);
+    if (!ok) return false;
     if (args.nlev <= 0 || nrhs <= 0) return true;
-    const int rw = trans_rw(nrhs), qw = WAVE / rw, rbe = rw == 4 ? rb : 1;
+    const int qw = WAVE / rw;
     GroupArgs<T> a = args;
-    a.rb = rbe;
     a.nblocks = 0;
     for (int l = 0; l < a.nlev; l++) {
         a.lv[l].nqc = (a.lv[l].K + GWAVES * qw - 1) / (GWAVES * qw);
@@ -140,21 +146,25 @@ bool launch_translate_groups(const GroupArgs<T> &args, int nrhs, hipStream_t s)
         a.nblocks += (a.lv[l].ngroup * a.lv[l].nqc + NXCD - 1) / NXCD;
     }
     if (a.nblocks <= 0) return true;
-    const dim3 grid((unsigned)a.nblocks * NXCD, (nrhs + rw * rbe - 1) / (rw * rbe)), block(GWAVES * WAVE);
+    const dim3 grid((unsigned)a.nblocks * NXCD, (nrhs + rw * rb - 1) / (rw * rb)), block(GWAVES * WAVE);
 #define GROUP_LAUNCH(TG_, RW_, RB_) hipLaunchKernelGGL((k_translate_groups<T, TG_, RW_, RB_>), grid, block, 0, s, a, nrhs)
-    if (tg == 4) {
-        if (rw == 4 && rbe == 4) GROUP_LAUNCH(4, 4, 4);
-        else if (rw == 4 && rbe == 2) GROUP_LAUNCH(4, 4, 2);
-        else if (rw == 4) GROUP_LAUNCH(4, 4, 1);
-        else if (rw == 2) GROUP_LAUNCH(4, 2, 1);
-        else GROUP_LAUNCH(4, 1, 1);
+#define GROUP_SHAPES(TG_)                          \
+    if (rw == 4 && rb == 4) GROUP_LAUNCH(TG_, 4, 4);       \
+    else if (rw == 4 && rb == 2) GROUP_LAUNCH(TG_, 4, 2);  \
+    else if (rw == 8 && rb == 2) GROUP_LAUNCH(TG_, 8, 2);  \
+    else if (rw == 16) GROUP_LAUNCH(TG_, 16, 1);           \
+    else if (rw == 8) GROUP_LAUNCH(TG_, 8, 1);             \
+    else if (rw == 4) GROUP_LAUNCH(TG_, 4, 1);             \
+    else if (rw == 2) GROUP_LAUNCH(TG_, 2, 1);             \
+    else GROUP_LAUNCH(TG_, 1, 1);
+    if (tg == 4 && rw == 2 && rb == 8) {
+        if constexpr (sizeof(T) == 4) GROUP_LAUNCH(4, 2, 8);   // single precision only (register budget)
+    } else if (tg == 4) {
+        GROUP_SHAPES(4)
     } else {
-        if (rw == 4 && rbe == 4) GROUP_LAUNCH(8, 4, 4);
-        else if (rw == 4 && rbe == 2) GROUP_LAUNCH(8, 4, 2);
-        else if (rw == 4) GROUP_LAUNCH(8, 4, 1);
-        else if (rw == 2) GROUP_LAUNCH(8, 2, 1);
-        else GROUP_LAUNCH(8, 1, 1);
+        GROUP_SHAPES(8)
     }
+#undef GROUP_SHAPES
 #undef GROUP_LAUNCH
     return true;
 }

@@ -221,7 +221,7 @@ def test_translation_kernels(kernel):
     g = mf.Geometry(v, t, k=K0, max_rhs=20, trans_kernel=kernel).precompute()
     other = mf.Geometry(v, t, k=K0, max_rhs=20, trans_kernel="groups" if kernel == "tiled" else "tiled").precompute()
     sh = g.tuning()
-    assert (sh["c64"][1] == 0) == (kernel == "groups") and (sh["c128"][1] == 0) == (kernel == "groups")
+    assert (sh["c64"][1] <= 0) == (kernel == "groups") and (sh["c128"][1] <= 0) == (kernel == "groups")
     for nrhs in (1, 3, 20):
         x, rows, ref = reference(name, 192, nrhs, 5)
         N = x.shape[0] // 2
