@@ -192,6 +192,23 @@ typedef struct {
 } mlfma_batch_item;
 int mlfma_matvec_batch(const mlfma_batch_item *items, int n_items, void *hip_stream);
 
+/* Products of several geometries in lockstep with shared translation
+ * launches (the batched form of Sec. II-E step 2(a) for many uneven
+ * geometries): the diagonal translations of every level of every item run
+ * as one work list over (geometry, level, group of target boxes, sample
+ * chunk, right-hand-side slice), at most 20 levels per launch, in the
+ * sibling-group kernel shape the autotuner picked for the item with the most
+ * translation work; the other stages run concurrently on the handles' own
+ * streams, forked from hip_stream before and after the shared translations
+ * (each near field on its handle's side stream).  Items: distinct handles on one
+ * device, one dtype and one nrhs for all, no handle with FP32 parts of
+ * complex128 products; otherwise MLFMA_ERR_ARG ("item i: ...") and nothing
+ * is enqueued.  The results equal the single products bit for bit where a
+ * handle's own translation is the sibling-group kernel (every target sums
+ * its sources in the same order in every shape), else to rounding.
+ * Asynchronous; grows workspaces as mlfma_matvec_LK does. */
+int mlfma_matvec_batch_fused(const mlfma_batch_item *items, int n_items, void *hip_stream);
+
 /*
  * Diagnostic split of mlfma_matvec_LK (same arguments, same asynchrony):
  *   part = MLFMA_PART_NEAR : near-field blocks (and identity terms) only;
@@ -457,9 +474,10 @@ int mlfma_tuning_steps(mlfma_handle h, int *matrix_cores, double ms[2]);
  * more right-hand sides in precision dtype: shape[0], shape[1] = the
  * aggregation's right-hand sides per workgroup (0: the launcher's default)
  * and pipelined right-hand sides per pass (0: not pipelined); shape[2],
- * shape[3] the same for the disaggregation.  MLFMA_ERR_ARG for a NULL handle
- * or shape, an unknown dtype or a level out of range. */
-int mlfma_tuning_level(mlfma_handle h, int dtype, int level, int shape[4]);
+ * shape[3] the same for the disaggregation; shape[4] = the aggregation's
+ * children staged together (0: the launcher's default).  MLFMA_ERR_ARG for a
+ * NULL handle or shape, an unknown dtype or a level out of range. */
+int mlfma_tuning_level(mlfma_handle h, int dtype, int level, int shape[5]);
 
 /*
  * Stage timing with HIP events recorded on the matvec's stream.  Stages:

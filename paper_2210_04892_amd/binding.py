@@ -94,6 +94,7 @@ def lib():
         L.mlfma_sai_info.argtypes = [P, ctypes.c_int, ctypes.POINTER(LL), ctypes.POINTER(ctypes.c_int),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_ulonglong)]
         L.mlfma_matvec_batch.argtypes = [P, ctypes.c_int, P]
+        L.mlfma_matvec_batch_fused.argtypes = [P, ctypes.c_int, P]
         L.mlfma_plane_wave_rhs.argtypes = [P, ctypes.c_int, LL, P, P, P, LL, P]
         L.mlfma_far_field.argtypes = [P, ctypes.c_int, LL, P, LL, LL, P, P, P]
         L.mlfma_server_opts_default.argtypes = [ctypes.POINTER(ServerOptions)]
@@ -250,13 +251,14 @@ class Geometry:
     def tuning_levels(self, dtype=torch.complex64):
         """Vector level-step kernel shapes for four or more right-hand sides
         (mlfma_tuning_level): {level: {"agg_rb", "agg_pipe", "dis_rb",
-        "dis_pipe"}} for the steps between level and level + 1."""
+        "dis_pipe", "agg_group"}} for the steps between level and level + 1."""
         dt = C128 if dtype == torch.complex128 else C64
         out = {}
         for lev in range(2, self.levels - 1):
-            s = np.zeros(4, np.int32)
+            s = np.zeros(5, np.int32)
             _check(lib().mlfma_tuning_level(self._h, dt, lev, s.ctypes.data))
-            out[lev] = {"agg_rb": int(s[0]), "agg_pipe": int(s[1]), "dis_rb": int(s[2]), "dis_pipe": int(s[3])}
+            out[lev] = {"agg_rb": int(s[0]), "agg_pipe": int(s[1]), "dis_rb": int(s[2]), "dis_pipe": int(s[3]),
+                        "agg_group": int(s[4])}
         return out
 
     def profile(self, enable=True):
@@ -637,10 +639,12 @@ def peak_probe(kind, device=None):
     return v.value
 
 
-def matvec_batch(items, stream=None):
+def matvec_batch(items, stream=None, fused=False):
     """mlfma_matvec_batch: items = [(geometry, x, op), ...] with x complex CUDA
     tensors (2N,) or (2N, nrhs); returns the products in the same order.
-    Products of different geometries run concurrently."""
+    Products of different geometries run concurrently.  fused: the lockstep
+    form with shared translation launches (mlfma_matvec_batch_fused;
+    distinct geometries, one dtype and one right-hand-side count)."""
     arr = (BatchItem * len(items))()
     keep, outs = [], []
     for i, (g, x, op) in enumerate(items):
@@ -661,7 +665,8 @@ def matvec_batch(items, stream=None):
     dev = items[0][0].device if items else 0
     s = torch.cuda.current_stream(dev) if stream is None else stream
     with torch.cuda.device(dev):
-        _check(lib().mlfma_matvec_batch(ctypes.cast(arr, ctypes.c_void_p), len(items), s.cuda_stream))
+        fn = lib().mlfma_matvec_batch_fused if fused else lib().mlfma_matvec_batch
+        _check(fn(ctypes.cast(arr, ctypes.c_void_p), len(items), s.cuda_stream))
     res = []
     for yt, squeeze in outs:
         y = yt.t()

@@ -64,6 +64,7 @@ struct PrecLevel {
     StepPlan agg, dis;      // step from level l + 1 up to l, and from l down to l + 1
     StepPlan agg1, dis1;    // the same with smaller chunks (more workgroups) for fewer than four RHS
     int agg_rb = 0, dis_rb = 0;   // right-hand sides per workgroup with four or more (autotuned; 0 = default)
+    int agg_group = 0;            // aggregation: children staged together (autotuned; 0 = default)
     int dis_pipe = 0;             // > 0: pipelined disaggregation with this many per pass (autotuned)
     int agg_pipe = 0;             // the same for the aggregation
     // separable aggregation stencils (SepStencil; tth = 0: not separable)
@@ -1279,6 +1280,7 @@ LevelStep<T> step_args(mlfma_ctx *c, Prec<T> &P, int l, bool agg, int nrhs)
     a.wrows = pl.wrows;
     a.win = pl.win;
     a.rb = small ? 0 : (agg ? PL.agg_rb : PL.dis_rb);
+    a.group = small || !agg ? 0 : PL.agg_group;
     a.pipe = small ? 0 : (agg ? PL.agg_pipe : PL.dis_pipe);
     a.taps = c->opt.interp_order;
     a.child_start = I.child_start;
@@ -1312,8 +1314,10 @@ LevelStep<T> step_args(mlfma_ctx *c, Prec<T> &P, int l, bool agg, int nrhs)
 }
 
 // Kernel shape of every vector level step (aggregation and disaggregation,
-// each level on its own): 1, 2 or 4 right-hand sides per workgroup, or the
-// pipelined kernel with 1 or 2 per pass,
+// each level on its own): 1, 2 or 4 right-hand sides per workgroup (for the
+// aggregation also 2 or 4 children staged together, one right-hand side
+// each), or the pipelined
+// kernel with 1 or 2 per pass,
 // whichever runs the step fastest with the handle's right-hand-side count
 // (capped at 16; one warm-up and three timed runs each, on zeroed patterns).
 // Handles for fewer than four right-hand sides keep the launchers' default;
@@ -1344,12 +1348,18 @@ void tune_step_rb(mlfma_ctx *c, Prec<T> &P)
         for (int agg = 0; agg < 2; agg++) {
             int &rb = agg ? P.lv[l].agg_rb : P.lv[l].dis_rb;
             int &pipe = agg ? P.lv[l].agg_pipe : P.lv[l].dis_pipe;
+            int dummy = 0;
+            int &group = agg ? P.lv[l].agg_group : dummy;
+            // (right-hand sides per workgroup, pipelined per pass, children per group)
+            const int cands[7][3] = {{1, 0, 0}, {2, 0, 0}, {4, 0, 0}, {0, 1, 0}, {0, 2, 0}, {1, 0, 2}, {1, 0, 4}};
             double best = 1e30;
-            int pick = 0, pick_pipe = 0;
-            for (int cand : {1, 2, 4, -1, -2}) {
-                if (cand < 0 && blocked) break;
-                rb = cand > 0 ? cand : 0;
-                pipe = cand < 0 ? -cand : 0;
+            int pick[3] = {0, 0, 0};
+            for (const auto &cd : cands) {
+                if (cd[1] > 0 && blocked) continue;
+                if (cd[2] > 0 && !agg) continue;
+                rb = cd[0];
+                pipe = cd[1];
+                group = cd[2];
                 LevelStep<T> a = step_args<T>(c, P, l, agg != 0, nrhs);
                 a.in = (const cpx<T> *)(agg ? w.U[l + 1] : w.V[l]);
                 a.out = (cpx<T> *)(agg ? w.U[l] : w.V[l + 1]);
@@ -1365,12 +1375,14 @@ void tune_step_rb(mlfma_ctx *c, Prec<T> &P)
                 HIPCHK(hipEventElapsedTime(&t, e0, e1));
                 if (t < best) {
                     best = t;
-                    pick = rb;
-                    pick_pipe = pipe;
+                    pick[0] = rb;
+                    pick[1] = pipe;
+                    pick[2] = group;
                 }
             }
-            rb = pick;
-            pipe = pick_pipe;
+            rb = pick[0];
+            pipe = pick[1];
+            group = pick[2];
         }
     }
     HIPCHK(hipGetLastError());
@@ -1449,71 +1461,112 @@ void tune_level_steps(mlfma_ctx *c)
     P.level_mfma = ms[1] < ms[0] ? 1 : 0;
 }
 
+// One product, in three phases so that a batch of geometries can share the
+// translation launch: begin (permutation, near field, radiation,
+// aggregation), translate, end (disaggregation, receive, permutation).
 template <class T>
-void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nrhs, const cpx<T> *x, long long ldx,
-                cpx<T> *y, long long ldy, hipStream_t st, bool profile)
-{
-    const Tree &tr = c->tr;
-    const int N = c->r.n, leafl = tr.levels - 1;
-    cpx<T> *X = (cpx<T> *)w.X, *Y = (cpx<T> *)w.Y, *mid = (cpx<T> *)w.mid;
+struct MvRun {
+    mlfma_ctx *c = nullptr;
+    Workspace *w = nullptr;
+    Prec<T> *P = nullptr;
+    int op = 0, part = 0, nrhs = 0;
+    hipStream_t st = nullptr;
+    bool profile = false;
+    int N = 0, leafl = 0, only_level = -1;
+    bool want_near = false, far = false, overlap = false, fold = false;
+    cpx<T> *X = nullptr, *Y = nullptr, *mid = nullptr;
     std::vector<hipEvent_t> ev;
-    if (profile) ev = c->take_events();
-    auto mark = [&](int i) {
+    void mark(int i)
+    {
         if (profile) HIPCHK(hipEventRecord(ev[i], st));
-    };
-    const Level &Lf = tr.lv[leafl];
-    const int only_level = part >= MLFMA_PART_LEVEL ? part - MLFMA_PART_LEVEL : -1;
-    const bool want_near = only_level < 0 && (part & MLFMA_PART_NEAR);
-    const bool want_far = only_level >= 0 || (part & MLFMA_PART_FAR);
-    const bool far = tr.levels >= 3 && want_far;
-    // the near field beside the far-field chain (stage timing keeps them in
-    // sequence): forked after the radiation, whose memory traffic it would
-    // otherwise compete with, so that it shares the GPU with the
-    // latency-bound level steps and translation
-    const bool overlap = !profile && want_near && far && w.side;
-    // with one right-hand side and the near field after the radiation, the
-    // radiation reads x through the permutation (and stores the tree-order
-    // copy the near field reads) and the receive writes y in user order: two
-    // launches fewer on the critical path
-    const bool fold = overlap && nrhs == 1;
-    mark(0);
-    if (!fold) launch_perm_in<T>(x, ldx, X, c->perm, c->iperm, N, nrhs, st);
-    mark(1);
-    auto near = [&](hipStream_t sn) {
-        const cpx<T> *vals = op == MLFMA_OP_EM ? P.near_em : P.near_c;
+    }
+    void near(hipStream_t sn)
+    {
+        const cpx<T> *vals = op == MLFMA_OP_EM ? P->near_em : P->near_c;
         const int *ids = op == MLFMA_OP_C ? c->id_start : nullptr;
         bool done = false;
         if constexpr (std::is_same<T, float>::value)
             done = launch_near_mfma(c->n_items, c->items, c->box_start, c->col_off, c->cols, c->val_off, vals, ids,
-                                    c->id_col, P.id_w, X, Y, nrhs, sn);
+                                    c->id_col, P->id_w, X, Y, nrhs, sn);
         if (!done && nrhs == 1) {
             launch_near_tile<T>(c->n_items, c->items, c->box_start, c->col_off, c->cols, c->val_off, vals, ids,
-                                c->id_col, P.id_w, X, Y, sn);
+                                c->id_col, P->id_w, X, Y, sn);
             done = true;
         }
         if (!done)
             launch_near<T>(N, c->leaf_of, c->box_start, c->near_start, c->near_box, c->val_off, vals, ids, c->id_col,
-                           P.id_w, X, Y, nrhs, sn);
-    };
-    if (!want_near) launch_zero<T>(Y, (long long)N * 2 * nrhs, st);
-    else if (!overlap) near(st);
-    mark(2);
-    if (fold) {
-        launch_radiate1_user<T>(op, Lf.nbox, Lf.K, c->box_start, P.R, x, c->perm, N, X, (cpx<T> *)w.U[leafl], st);
-    } else if (far) {
+                           P->id_w, X, Y, nrhs, sn);
+    }
+};
+
+template <class T>
+MvRun<T> mv_setup(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nrhs, hipStream_t st, bool profile)
+{
+    MvRun<T> m;
+    const Tree &tr = c->tr;
+    m.c = c;
+    m.w = &w;
+    m.P = &P;
+    m.op = op;
+    m.part = part;
+    m.nrhs = nrhs;
+    m.st = st;
+    m.profile = profile;
+    m.N = c->r.n;
+    m.leafl = tr.levels - 1;
+    m.X = (cpx<T> *)w.X;
+    m.Y = (cpx<T> *)w.Y;
+    m.mid = (cpx<T> *)w.mid;
+    if (profile) m.ev = c->take_events();
+    m.only_level = part >= MLFMA_PART_LEVEL ? part - MLFMA_PART_LEVEL : -1;
+    m.want_near = m.only_level < 0 && (part & MLFMA_PART_NEAR);
+    const bool want_far = m.only_level >= 0 || (part & MLFMA_PART_FAR);
+    m.far = tr.levels >= 3 && want_far;
+    // the near field beside the far-field chain (stage timing keeps them in
+    // sequence): forked after the radiation, whose memory traffic it would
+    // otherwise compete with, so that it shares the GPU with the
+    // latency-bound level steps and translation
+    m.overlap = !profile && m.want_near && m.far && w.side;
+    // with one right-hand side and the near field after the radiation, the
+    // radiation reads x through the permutation (and stores the tree-order
+    // copy the near field reads) and the receive writes y in user order: two
+    // launches fewer on the critical path
+    m.fold = m.overlap && nrhs == 1;
+    return m;
+}
+
+template <class T>
+void mv_begin(MvRun<T> &m, const cpx<T> *x, long long ldx)
+{
+    mlfma_ctx *c = m.c;
+    Workspace &w = *m.w;
+    Prec<T> &P = *m.P;
+    const Tree &tr = c->tr;
+    const int nrhs = m.nrhs, leafl = m.leafl;
+    hipStream_t st = m.st;
+    const Level &Lf = tr.lv[leafl];
+    m.mark(0);
+    if (!m.fold) launch_perm_in<T>(x, ldx, m.X, c->perm, c->iperm, m.N, nrhs, st);
+    m.mark(1);
+    if (!m.want_near) launch_zero<T>(m.Y, (long long)m.N * 2 * nrhs, st);
+    else if (!m.overlap) m.near(st);
+    m.mark(2);
+    if (m.fold) {
+        launch_radiate1_user<T>(m.op, Lf.nbox, Lf.K, c->box_start, P.R, x, c->perm, m.N, m.X, (cpx<T> *)w.U[leafl], st);
+    } else if (m.far) {
         bool done = false;
         if constexpr (std::is_same<T, float>::value)
-            done = launch_radiate_mfma(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)w.U[leafl], nrhs, st);
-        if (!done) launch_radiate<T>(op, Lf.nbox, Lf.K, c->box_start, P.R, X, (cpx<T> *)w.U[leafl], nrhs, st);
+            done = launch_radiate_mfma(m.op, Lf.nbox, Lf.K, c->box_start, P.R, m.X, (cpx<T> *)w.U[leafl], nrhs, st);
+        if (!done) launch_radiate<T>(m.op, Lf.nbox, Lf.K, c->box_start, P.R, m.X, (cpx<T> *)w.U[leafl], nrhs, st);
     }
-    if (overlap) {
+    if (m.overlap) {
         HIPCHK(hipEventRecord(w.fork, st));
         HIPCHK(hipStreamWaitEvent(w.side, w.fork, 0));
-        near(w.side);
+        m.near(w.side);
         HIPCHK(hipEventRecord(w.join, w.side));
     }
-    mark(3);
-    if (far) {
+    m.mark(3);
+    if (m.far) {
         for (int l = leafl - 1; l >= 2; l--) {
             const Level &L = tr.lv[l], &C = tr.lv[l + 1];
             const IntLevel &I = c->lv[l];
@@ -1527,25 +1580,50 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
             a.in = (const cpx<T> *)w.U[l + 1];
             a.out = (cpx<T> *)w.U[l];
             if (launch_aggregate_step<T>(a, nrhs, st)) continue;
-            if (!launch_interp_fixed<T>(taps, C.nbox, midlen, C.K, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], mid,
+            if (!launch_interp_fixed<T>(taps, C.nbox, midlen, C.K, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], m.mid,
                                         nrhs, st))
-                launch_interp<T>(C.nbox, midlen, C.K, I.ath_s, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], mid,
+                launch_interp<T>(C.nbox, midlen, C.K, I.ath_s, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], m.mid,
                                  nrhs, false, st);
             if (!launch_agg_phi_fixed<T>(taps, L.nbox, L.K, midlen, I.child_start, c->lv[l + 1].oct, P.lv[l].shift,
-                                         I.aph_c, P.lv[l].aph_w, mid, (cpx<T> *)w.U[l], nrhs, st))
+                                         I.aph_c, P.lv[l].aph_w, m.mid, (cpx<T> *)w.U[l], nrhs, st))
                 launch_agg_phi<T>(L.nbox, L.K, midlen, I.child_start, c->lv[l + 1].oct, P.lv[l].shift, I.aph_s,
-                                  I.aph_c, P.lv[l].aph_w, mid, (cpx<T> *)w.U[l], nrhs, st);
+                                  I.aph_c, P.lv[l].aph_w, m.mid, (cpx<T> *)w.U[l], nrhs, st);
         }
     }
-    mark(4);
-    if (far) {
-        for (int l = 2; l <= leafl; l++)
-            if (only_level >= 0 && l != only_level)
-                launch_zero<T>((cpx<T> *)w.V[l], (long long)tr.lv[l].nbox * tr.lv[l].K * 2 * nrhs, st);
-        launch_translation<T>(c, P, w, only_level, nrhs, st);
+    m.mark(4);
+}
+
+// levels whose translation is not asked for (a single level's part) start at zero
+template <class T>
+void mv_clear_levels(MvRun<T> &m)
+{
+    const Tree &tr = m.c->tr;
+    for (int l = 2; l <= m.leafl; l++)
+        if (m.only_level >= 0 && l != m.only_level)
+            launch_zero<T>((cpx<T> *)m.w->V[l], (long long)tr.lv[l].nbox * tr.lv[l].K * 2 * m.nrhs, m.st);
+}
+
+template <class T>
+void mv_translate(MvRun<T> &m)
+{
+    if (m.far) {
+        mv_clear_levels(m);
+        launch_translation<T>(m.c, *m.P, *m.w, m.only_level, m.nrhs, m.st);
     }
-    mark(5);
-    if (far) {
+    m.mark(5);
+}
+
+template <class T>
+void mv_end(MvRun<T> &m, cpx<T> *y, long long ldy)
+{
+    mlfma_ctx *c = m.c;
+    Workspace &w = *m.w;
+    Prec<T> &P = *m.P;
+    const Tree &tr = c->tr;
+    const int nrhs = m.nrhs, leafl = m.leafl;
+    hipStream_t st = m.st;
+    const Level &Lf = tr.lv[leafl];
+    if (m.far) {
         for (int l = 3; l <= leafl; l++) {
             const Level &L = tr.lv[l], &Pl = tr.lv[l - 1];
             const IntLevel &Ip = c->lv[l - 1];
@@ -1560,26 +1638,37 @@ void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nr
             a.out = (cpx<T> *)w.V[l];
             if (launch_disaggregate_step<T>(a, nrhs, st)) continue;
             launch_disagg_mid<T>(L.nbox, midlen, Pl.K, c->lv[l].parent, c->lv[l].oct, P.lv[l - 1].shift, Ip.dph_s,
-                                 Ip.dph_c, P.lv[l - 1].dph_w, (cpx<T> *)w.V[l - 1], mid, nrhs, st);
-            launch_interp<T>(L.nbox, L.K, midlen, Ip.dth_s, Ip.dth_c, P.lv[l - 1].dth_w, mid, (cpx<T> *)w.V[l],
+                                 Ip.dph_c, P.lv[l - 1].dph_w, (cpx<T> *)w.V[l - 1], m.mid, nrhs, st);
+            launch_interp<T>(L.nbox, L.K, midlen, Ip.dth_s, Ip.dth_c, P.lv[l - 1].dth_w, m.mid, (cpx<T> *)w.V[l],
                              nrhs, true, st);
         }
     }
-    mark(6);
-    if (overlap) HIPCHK(hipStreamWaitEvent(st, w.join, 0));
-    if (fold) {
-        launch_receive1_user<T>(op, N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], Y, y, c->perm, st);
-    } else if (far) {
+    m.mark(6);
+    if (m.overlap) HIPCHK(hipStreamWaitEvent(st, w.join, 0));
+    if (m.fold) {
+        launch_receive1_user<T>(m.op, m.N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], m.Y, y, c->perm, st);
+    } else if (m.far) {
         bool done = false;
         if constexpr (std::is_same<T, float>::value)
-            done = launch_receive_mfma(op, c->n_items, c->items, Lf.K, c->box_start, P.R, P.Q, P.wq,
-                                       (cpx<T> *)w.V[leafl], Y, nrhs, st);
-        if (!done) launch_receive<T>(op, N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], Y, nrhs, st);
+            done = launch_receive_mfma(m.op, c->n_items, c->items, Lf.K, c->box_start, P.R, P.Q, P.wq,
+                                       (cpx<T> *)w.V[leafl], m.Y, nrhs, st);
+        if (!done)
+            launch_receive<T>(m.op, m.N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], m.Y, nrhs, st);
     }
-    mark(7);
-    if (!fold) launch_perm_out<T>(Y, y, ldy, c->iperm, N, nrhs, st);
-    mark(8);
-    if (profile) c->ev_pending.push_back(ev);
+    m.mark(7);
+    if (!m.fold) launch_perm_out<T>(m.Y, y, ldy, c->iperm, m.N, nrhs, st);
+    m.mark(8);
+    if (m.profile) c->ev_pending.push_back(m.ev);
+}
+
+template <class T>
+void run_matvec(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int nrhs, const cpx<T> *x, long long ldx,
+                cpx<T> *y, long long ldy, hipStream_t st, bool profile)
+{
+    MvRun<T> m = mv_setup<T>(c, w, P, op, part, nrhs, st, profile);
+    mv_begin<T>(m, x, ldx);
+    mv_translate<T>(m);
+    mv_end<T>(m, y, ldy);
 }
 
 // One product in precision T of the vectors.  complex128 products whose
@@ -1918,6 +2007,87 @@ int gmres_entry(mlfma_handle h, int op, int dtype, long long nrhs, const void *b
 }  // namespace
 
 // =================================================================== C ABI
+namespace mlfma {
+namespace {
+
+template <class T>
+Prec<T> &prec_of(mlfma_ctx *c)
+{
+    if constexpr (std::is_same<T, double>::value) return c->p64;
+    else return c->p32;
+}
+
+// Items in lockstep: every item's first phase, then the translations of all
+// items' levels as sibling-group work lists (at most TRANS_MAXLEV levels per
+// launch) with the shape tuned for the item with the most translation work,
+// then every item's last phase.
+template <class T>
+void batch_fused(const mlfma_batch_item *items, int n, hipStream_t st)
+{
+    // the items' own phases run concurrently on their handles' batch
+    // streams, forked from st before and after the shared translations
+    auto fork = [&] {
+        HIPCHK(hipEventRecord(items[0].h->bfork, st));
+        for (int i = 0; i < n; i++) HIPCHK(hipStreamWaitEvent(items[i].h->bstream, items[0].h->bfork, 0));
+    };
+    auto join = [&] {
+        for (int i = 0; i < n; i++) {
+            HIPCHK(hipEventRecord(items[i].h->bjoin, items[i].h->bstream));
+            HIPCHK(hipStreamWaitEvent(st, items[i].h->bjoin, 0));
+        }
+    };
+    std::vector<MvRun<T>> runs;
+    runs.reserve(n);
+    for (int i = 0; i < n; i++) {
+        mlfma_ctx *h = items[i].h;
+        runs.push_back(mv_setup<T>(h, h->ws, prec_of<T>(h), items[i].op, MLFMA_PART_ALL, (int)items[i].nrhs,
+                                   h->bstream, false));
+    }
+    fork();
+    for (int i = 0; i < n; i++) mv_begin<T>(runs[i], (const cpx<T> *)items[i].x, items[i].ldx);
+    join();
+    const int nrhs = (int)items[0].nrhs;
+    int ref = 0;
+    long long most = -1;
+    for (int i = 0; i < n; i++) {
+        long long work = 0;
+        const Tree &tr = items[i].h->tr;
+        for (int l = 2; l < tr.levels; l++) work += (long long)tr.lv[l].il_start[tr.lv[l].nbox] * tr.lv[l].K;
+        if (work > most) {
+            most = work;
+            ref = i;
+        }
+    }
+    const Prec<T> &PR = prec_of<T>(items[ref].h);
+    const int gi = PR.trans_group > 0 ? PR.trans_gi : 0, rb = PR.trans_group > 0 ? PR.trans_rb : 1;
+    const int rw = PR.trans_group > 0 ? PR.trans_rw : 0;
+    GroupArgs<T> ga;
+    ga.tg = gi == 0 ? 4 : 8;
+    ga.rb = rb;
+    ga.rw = rw;
+    auto flush = [&] {
+        if (ga.nlev > 0 && !launch_translate_groups<T>(ga, nrhs, st))
+            throw Error(MLFMA_ERR_STATE, "invalid sibling-group translation shape");
+        ga.nlev = 0;
+    };
+    for (int i = 0; i < n; i++) {
+        if (!runs[i].far) continue;
+        mlfma_ctx *h = items[i].h;
+        const GroupArgs<T> one = group_args<T>(h, prec_of<T>(h), h->ws, -1, gi, rb, rw);
+        for (int l = 0; l < one.nlev; l++) {
+            if (ga.nlev == TRANS_MAXLEV) flush();
+            ga.lv[ga.nlev++] = one.lv[l];
+        }
+    }
+    flush();
+    fork();
+    for (int i = 0; i < n; i++) mv_end<T>(runs[i], (cpx<T> *)items[i].y, items[i].ldy);
+    join();
+}
+
+}  // namespace
+}  // namespace mlfma
+
 extern "C" {
 
 const char *mlfma_last_error(void) { return g_last_error.c_str(); }
@@ -2030,6 +2200,56 @@ int mlfma_matvec_part(mlfma_handle h, int op, int dtype, int part, long long nrh
         else
             product<float>(h, h->ws, op, part, (int)nrhs, (const cpx<float> *)x, ldx, (cpx<float> *)y,
                            ldy, st, h->prof);
+        HIPCHK(hipGetLastError());
+        return MLFMA_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int mlfma_matvec_batch_fused(const mlfma_batch_item *items, int n_items, void *hip_stream)
+{
+    g_last_error.clear();
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(Error(MLFMA_ERR_ARG, "bad item list"));
+    if (n_items == 0) return MLFMA_OK;
+    for (int i = 0; i < n_items; i++) {
+        const mlfma_batch_item &it = items[i];
+        const std::string at = "item " + std::to_string(i) + ": ";
+        if (!it.h) return fail(Error(MLFMA_ERR_ARG, at + "NULL handle"));
+        if (!it.h->near_ready)
+            return fail(Error(MLFMA_ERR_STATE, at + "mlfma_precompute_nearfield has not been called"));
+        if (it.h->device != items[0].h->device) return fail(Error(MLFMA_ERR_ARG, at + "geometry on another device"));
+        for (int j = 0; j < i; j++)
+            if (items[j].h == it.h) return fail(Error(MLFMA_ERR_ARG, at + "geometry already in the batch"));
+        if (it.h->mixed) return fail(Error(MLFMA_ERR_ARG, at + "handle with FP32 parts of complex128 products"));
+        if (it.op != MLFMA_OP_C && it.op != MLFMA_OP_EM) return fail(Error(MLFMA_ERR_ARG, at + "unknown op"));
+        if (it.dtype != MLFMA_C128 && it.dtype != MLFMA_C64) return fail(Error(MLFMA_ERR_ARG, at + "unknown dtype"));
+        if (it.dtype != items[0].dtype || it.nrhs != items[0].nrhs)
+            return fail(Error(MLFMA_ERR_ARG, at + "dtype or nrhs differs from item 0"));
+        const long long N2 = 2LL * it.h->r.n;
+        if (it.nrhs < 1 || it.nrhs > (1 << 20) || !it.x || !it.y || it.ldx < N2 || it.ldy < N2)
+            return fail(Error(MLFMA_ERR_ARG, at + "bad nrhs, pointer or leading dimension"));
+        const size_t esz = it.dtype == MLFMA_C128 ? 16 : 8;
+        const char *xb = (const char *)it.x, *yb = (const char *)it.y;
+        if (xb < yb + (size_t)(it.ldy * (it.nrhs - 1) + N2) * esz &&
+            yb < xb + (size_t)(it.ldx * (it.nrhs - 1) + N2) * esz)
+            return fail(Error(MLFMA_ERR_ARG, at + "x and y overlap"));
+    }
+    try {
+        DeviceGuard g(items[0].h->device);
+        HIPCHK(hipGetLastError());
+        for (int i = 0; i < n_items; i++) {
+            mlfma_ctx *h = items[i].h;
+            ensure_workspace(h, (int)items[i].nrhs);
+            if (!h->bstream) {
+                HIPCHK(hipStreamCreateWithFlags(&h->bstream, hipStreamNonBlocking));
+                HIPCHK(hipEventCreateWithFlags(&h->bfork, hipEventDisableTiming));
+                HIPCHK(hipEventCreateWithFlags(&h->bjoin, hipEventDisableTiming));
+            }
+        }
+        hipStream_t st = (hipStream_t)hip_stream;
+        if (items[0].dtype == MLFMA_C128) batch_fused<double>(items, n_items, st);
+        else batch_fused<float>(items, n_items, st);
         HIPCHK(hipGetLastError());
         return MLFMA_OK;
     } catch (const Error &e) {
@@ -2411,7 +2631,7 @@ int mlfma_tuning_steps(mlfma_handle h, int *matrix_cores, double ms[2])
     return MLFMA_OK;
 }
 
-int mlfma_tuning_level(mlfma_handle h, int dtype, int level, int shape[4])
+int mlfma_tuning_level(mlfma_handle h, int dtype, int level, int shape[5])
 {
     if (!h || !shape || (dtype != MLFMA_C128 && dtype != MLFMA_C64)) return fail(Error(MLFMA_ERR_ARG, "bad argument"));
     if (level < 2 || level + 1 >= h->tr.levels) return fail(Error(MLFMA_ERR_ARG, "level out of range"));
@@ -2421,6 +2641,7 @@ int mlfma_tuning_level(mlfma_handle h, int dtype, int level, int shape[4])
         shape[1] = PL.agg_pipe;
         shape[2] = PL.dis_rb;
         shape[3] = PL.dis_pipe;
+        shape[4] = PL.agg_group;
     };
     if (dtype == MLFMA_C64) get(h->p32);
     else get(h->p64);

@@ -195,6 +195,7 @@ struct LevelStep {
     int nth_p = 0, nph_p = 0, nth_c = 0, nph_c = 0;
     int rows = 0, nchunk = 0, wrows = 0, taps = 0;
     int rb = 0;                         // right-hand sides per workgroup (0: the launcher's choice)
+    int group = 0;                      // aggregation: children staged together (0: the launcher's choice)
     int pipe = 0;                       // > 0: the pipelined kernel with this many right-hand sides per pass
     const int *win = nullptr;
     const int *child_start = nullptr;   // aggregation: children of each parent

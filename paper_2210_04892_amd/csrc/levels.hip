@@ -704,10 +704,15 @@ bool launch_aggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s)
     // groups hold LDS that costs occupancy); with more right-hand sides, one
     // child at a time and RB right-hand sides per workgroup
     const int gmax = sizeof(T) == 4 ? 4 : 2;
-    const int G = nrhs < 4 ? (int)std::min<size_t>(gmax, STEP_LDS_MAX / lds1) : 1;
-    const int rb = G > 1 ? 1 : step_rb(a.rb > 0 ? a.rb : 1, lds1, nrhs);
+    int G = nrhs < 4 ? (int)std::min<size_t>(gmax, STEP_LDS_MAX / lds1) : 1;
+    int rb = G > 1 ? 1 : step_rb(a.rb > 0 ? a.rb : 1, lds1, nrhs);
+    if (a.group > 1) {   // the autotuner's children per group (one right-hand side each) where the LDS allows
+        G = std::min(a.group, 4);
+        while (G > 1 && (size_t)G * lds1 > STEP_LDS_MAX) G /= 2;
+        rb = G > 1 ? 1 : step_rb(a.rb, lds1, nrhs);
+    }
     const dim3 grid(xcd_grid_l((long long)a.nbox * a.nchunk), (nrhs + rb - 1) / rb), block(STEP_THREADS);
-    const size_t lds = G * rb * lds1;
+    const size_t lds = (size_t)G * rb * lds1;
     if (a.taps == 6) agg_launch<T, 6>(G, rb, grid, block, lds, s, a, nrhs);
     else if (a.taps == 8) agg_launch<T, 8>(G, rb, grid, block, lds, s, a, nrhs);
     else agg_launch<T, 10>(G, rb, grid, block, lds, s, a, nrhs);

@@ -129,16 +129,29 @@ __global__ __launch_bounds__(GWAVES * WAVE) void k_translate_groups(const GroupA
 template <class T>
 bool launch_translate_groups(const GroupArgs<T> &args, int nrhs, hipStream_t s)
 {
-    const int tg = args.tg, rb = args.rb, rw = args.rw > 0 ? args.rw : trans_rw(nrhs);
+    const int tg = args.tg;
+    int rb = args.rb, rw = args.rw > 0 ? args.rw : trans_rw(nrhs);
     if (tg != 4 && tg != 8) return false;
     // (lanes over the RHS, RHS per lane) with a kernel
-    const bool ok = (rb == 1 && (rw == 1 || rw == 2 || rw == 4 || rw == 8 || rw == 16)) ||
-                    (rw == 4 && (rb == 2 || rb == 4)) || (rw == 8 && rb == 2) ||
-                    (rw == 2 && rb == 8 && tg == 4 && sizeof(T) == 4);
-    if (!ok) return false;
+    auto valid = [&](int w, int b) {
+        return (b == 1 && (w == 1 || w == 2 || w == 4 || w == 8 || w == 16)) || (w == 4 && (b == 2 || b == 4)) ||
+               (w == 8 && b == 2) || (w == 2 && b == 8 && tg == 4 && sizeof(T) == 4);
+    };
+    if (!valid(rw, rb)) return false;
+    // a shape tuned for more right-hand sides than this call has: fewer per
+    // lane, else the default lane split (no lanes idle for lack of them)
+    if (rw * rb > nrhs && nrhs > 0) {
+        while (rb > 1 && (rw * rb > nrhs || !valid(rw, rb))) rb /= 2;
+        if (rw * rb > nrhs) {
+            rw = trans_rw(nrhs);
+            rb = 1;
+        }
+    }
     if (args.nlev <= 0 || nrhs <= 0) return true;
     const int qw = WAVE / rw;
     GroupArgs<T> a = args;
+    a.rb = rb;
+    a.rw = rw;
     a.nblocks = 0;
     for (int l = 0; l < a.nlev; l++) {
         a.lv[l].nqc = (a.lv[l].K + GWAVES * qw - 1) / (GWAVES * qw);

@@ -91,6 +91,45 @@ def one_at_a_time(geoms, reqs, arrivals, op="C"):
     return lat, busy
 
 
+def geometry_batch(geoms, nrhs=4, seed=9, reps=10, op="C", dtype=torch.complex64):
+    """One product of every resident geometry (nrhs right-hand sides each),
+    three ways: one after another on one stream, mlfma_matvec_batch (each
+    geometry on its own stream) and mlfma_matvec_batch_fused (the same, with
+    the translations of all geometries in shared launches).  Milliseconds per
+    round (mean of reps after one warm-up) and the largest relative
+    difference of the fused products from the single ones."""
+    rng = np.random.default_rng(seed)
+    xs = []
+    for g in geoms:
+        n2 = 2 * g.n_rwg
+        x = rng.standard_normal((n2, nrhs)) + 1j * rng.standard_normal((n2, nrhs))
+        xs.append(torch.from_numpy(x).to(dtype).cuda())
+    items = [(g, x, op) for g, x in zip(geoms, xs)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    single = lambda: [g.matvec(x, op=op) for g, x in zip(geoms, xs)]
+    ms_seq = timed(single)
+    ms_fork = timed(lambda: mf.matvec_batch(items))
+    ms_fused = timed(lambda: mf.matvec_batch(items, fused=True))
+    ys = mf.matvec_batch(items, fused=True)
+    ref = single()
+    torch.cuda.synchronize()
+    diff = max(float(torch.linalg.norm(y - r) / torch.linalg.norm(r)) for y, r in zip(ys, ref))
+    unknowns = sum(2 * g.n_rwg * nrhs for g in geoms)
+    return {"geometries": len(geoms), "nrhs": nrhs, "dtype": str(dtype).replace("torch.", ""),
+            "sequential_ms": ms_seq, "forked_streams_ms": ms_fork, "fused_ms": ms_fused,
+            "fused_unknowns_rhs_per_s": unknowns / (ms_fused * 1e-3),
+            "max_rel_diff_fused_vs_single": diff}
+
+
 def run(geom_list, n_requests=512, seed=5, streams=4, max_batch_rhs=16, load=0.7, op="C",
         dtype=np.complex64, log=print, use_graphs=True):
     geoms = []
@@ -133,6 +172,9 @@ def run(geom_list, n_requests=512, seed=5, streams=4, max_batch_rhs=16, load=0.7
     # same arrivals
     lat_b, busy = one_at_a_time(geoms, reqs, arrivals, op)
     b50, b99 = _percentiles(lat_b)
+    batch = geometry_batch(geoms, op=op)
+    log("[serve] one product of each geometry (4 RHS): sequential %.2f ms, forked %.2f ms, fused %.2f ms"
+        % (batch["sequential_ms"], batch["forked_streams_ms"], batch["fused_ms"]))
     res = {
         "requests": len(reqs), "geometries": [g.n_rwg for g in geoms], "streams": streams,
         "max_batch_rhs": max_batch_rhs, "dtype": np.dtype(dtype).name, "budget_bytes": budget,
@@ -149,6 +191,7 @@ def run(geom_list, n_requests=512, seed=5, streams=4, max_batch_rhs=16, load=0.7
                                        "products from one host thread",
                                "throughput_unknowns_rhs_per_s": unknowns / busy,
                                "p50_ms": 1e3 * b50, "p99_ms": 1e3 * b99},
+        "geometry_batch": batch,
     }
     for g in geoms:
         g.release()

@@ -74,6 +74,10 @@ def test_null_handle_and_empty_batch_checks():
     items = (b.BatchItem * 1)()
     assert L.mlfma_matvec_batch(ctypes.cast(items, ctypes.c_void_p), 1, None) == -1     # NULL handle
     assert b"item 0" in L.mlfma_last_error()
+    assert L.mlfma_matvec_batch_fused(None, 0, None) == 0
+    assert L.mlfma_matvec_batch_fused(None, -1, None) == -1
+    assert L.mlfma_matvec_batch_fused(ctypes.cast(items, ctypes.c_void_p), 1, None) == -1
+    assert b"item 0" in L.mlfma_last_error()
     assert L.mlfma_sai_build(None, 0, 16) == -1
     assert L.mlfma_sai_apply(None, 0, 0, 1, None, 1, None, 1, None) == -1
     assert L.mlfma_release(None) == 0
