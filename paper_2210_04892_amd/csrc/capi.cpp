@@ -65,6 +65,7 @@ struct PrecLevel {
     StepPlan agg1, dis1;    // the same with smaller chunks (more workgroups) for fewer than four RHS
     int agg_rb = 0, dis_rb = 0;   // right-hand sides per workgroup with four or more (autotuned; 0 = default)
     int agg_group = 0;            // aggregation: children staged together (autotuned; 0 = default)
+    int agg_two = 0, dis_two = 0; // 1: the step as two kernels through the global intermediate (autotuned)
     int dis_pipe = 0;             // > 0: pipelined disaggregation with this many per pass (autotuned)
     int agg_pipe = 0;             // the same for the aggregation
     // separable aggregation stencils (SepStencil; tth = 0: not separable)
@@ -1316,7 +1317,7 @@ LevelStep<T> step_args(mlfma_ctx *c, Prec<T> &P, int l, bool agg, int nrhs)
 // Kernel shape of every vector level step (aggregation and disaggregation,
 // each level on its own): 1, 2 or 4 right-hand sides per workgroup (for the
 // aggregation also 2 or 4 children staged together, one right-hand side
-// each), or the pipelined
+// each), the two kernels through the global intermediate, or the pipelined
 // kernel with 1 or 2 per pass,
 // whichever runs the step fastest with the handle's right-hand-side count
 // (capped at 16; one warm-up and three timed runs each, on zeroed patterns).
@@ -1350,20 +1351,29 @@ void tune_step_rb(mlfma_ctx *c, Prec<T> &P)
             int &pipe = agg ? P.lv[l].agg_pipe : P.lv[l].dis_pipe;
             int dummy = 0;
             int &group = agg ? P.lv[l].agg_group : dummy;
-            // (right-hand sides per workgroup, pipelined per pass, children per group)
-            const int cands[7][3] = {{1, 0, 0}, {2, 0, 0}, {4, 0, 0}, {0, 1, 0}, {0, 2, 0}, {1, 0, 2}, {1, 0, 4}};
+            int &two = agg ? P.lv[l].agg_two : P.lv[l].dis_two;
+            // (right-hand sides per workgroup, pipelined per pass, children per
+            // group, two kernels through the global intermediate)
+            const int cands[8][4] = {{1, 0, 0, 0}, {2, 0, 0, 0}, {4, 0, 0, 0}, {0, 1, 0, 0},
+                                     {0, 2, 0, 0}, {1, 0, 2, 0}, {1, 0, 4, 0}, {0, 0, 0, 1}};
             double best = 1e30;
-            int pick[3] = {0, 0, 0};
+            int pick[4] = {0, 0, 0, 0};
             for (const auto &cd : cands) {
-                if (cd[1] > 0 && blocked) continue;
+                if ((cd[1] > 0 || cd[3] > 0) && blocked) continue;
                 if (cd[2] > 0 && !agg) continue;
                 rb = cd[0];
                 pipe = cd[1];
                 group = cd[2];
+                two = cd[3];
                 LevelStep<T> a = step_args<T>(c, P, l, agg != 0, nrhs);
                 a.in = (const cpx<T> *)(agg ? w.U[l + 1] : w.V[l]);
                 a.out = (cpx<T> *)(agg ? w.U[l] : w.V[l + 1]);
                 auto run = [&] {
+                    if (two) {
+                        if (agg) agg_two<T>(c, P, w, l, nrhs, st);
+                        else dis_two<T>(c, P, w, l, nrhs, st);
+                        return true;
+                    }
                     return agg ? launch_aggregate_step<T>(a, nrhs, st) : launch_disaggregate_step<T>(a, nrhs, st);
                 };
                 if (!run()) break;   // the step has no fused kernel: nothing to tune
@@ -1378,11 +1388,13 @@ void tune_step_rb(mlfma_ctx *c, Prec<T> &P)
                     pick[0] = rb;
                     pick[1] = pipe;
                     pick[2] = group;
+                    pick[3] = two;
                 }
             }
             rb = pick[0];
             pipe = pick[1];
             group = pick[2];
+            two = pick[3];
         }
     }
     HIPCHK(hipGetLastError());
@@ -1535,6 +1547,41 @@ MvRun<T> mv_setup(mlfma_ctx *c, Workspace &w, Prec<T> &P, int op, int part, int 
     return m;
 }
 
+// A level step as two kernels through the global intermediate (no LDS
+// windows): aggregation from level l + 1 to l (theta, then phi and shift);
+// disaggregation from level l to l + 1 (shift and phi, then theta).
+template <class T>
+void agg_two(mlfma_ctx *c, Prec<T> &P, Workspace &w, int l, int nrhs, hipStream_t st)
+{
+    const Tree &tr = c->tr;
+    const Level &L = tr.lv[l], &C = tr.lv[l + 1];
+    const IntLevel &I = c->lv[l];
+    const int midlen = L.nth * C.nph, taps = c->opt.interp_order;
+    cpx<T> *mid = (cpx<T> *)w.mid;
+    if (!launch_interp_fixed<T>(taps, C.nbox, midlen, C.K, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], mid, nrhs,
+                                st))
+        launch_interp<T>(C.nbox, midlen, C.K, I.ath_s, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], mid, nrhs, false,
+                         st);
+    if (!launch_agg_phi_fixed<T>(taps, L.nbox, L.K, midlen, I.child_start, c->lv[l + 1].oct, P.lv[l].shift, I.aph_c,
+                                 P.lv[l].aph_w, mid, (cpx<T> *)w.U[l], nrhs, st))
+        launch_agg_phi<T>(L.nbox, L.K, midlen, I.child_start, c->lv[l + 1].oct, P.lv[l].shift, I.aph_s, I.aph_c,
+                          P.lv[l].aph_w, mid, (cpx<T> *)w.U[l], nrhs, st);
+}
+
+template <class T>
+void dis_two(mlfma_ctx *c, Prec<T> &P, Workspace &w, int l, int nrhs, hipStream_t st)
+{
+    const Tree &tr = c->tr;
+    const Level &Pl = tr.lv[l], &L = tr.lv[l + 1];
+    const IntLevel &Ip = c->lv[l];
+    const int midlen = Pl.nth * L.nph;
+    cpx<T> *mid = (cpx<T> *)w.mid;
+    launch_disagg_mid<T>(L.nbox, midlen, Pl.K, c->lv[l + 1].parent, c->lv[l + 1].oct, P.lv[l].shift, Ip.dph_s,
+                         Ip.dph_c, P.lv[l].dph_w, (cpx<T> *)w.V[l], mid, nrhs, st);
+    launch_interp<T>(L.nbox, L.K, midlen, Ip.dth_s, Ip.dth_c, P.lv[l].dth_w, mid, (cpx<T> *)w.V[l + 1], nrhs, true,
+                     st);
+}
+
 template <class T>
 void mv_begin(MvRun<T> &m, const cpx<T> *x, long long ldx)
 {
@@ -1568,10 +1615,6 @@ void mv_begin(MvRun<T> &m, const cpx<T> *x, long long ldx)
     m.mark(3);
     if (m.far) {
         for (int l = leafl - 1; l >= 2; l--) {
-            const Level &L = tr.lv[l], &C = tr.lv[l + 1];
-            const IntLevel &I = c->lv[l];
-            const int midlen = L.nth * C.nph;
-            const int taps = c->opt.interp_order;
             if constexpr (std::is_same<T, float>::value)
                 if (P.level_mfma && P.lv[l].agg_m.ok &&
                     launch_aggregate_mfma(P.lv[l].agg_m, (const cpx<float> *)w.U[l + 1], (cpx<float> *)w.U[l], nrhs, st))
@@ -1579,15 +1622,8 @@ void mv_begin(MvRun<T> &m, const cpx<T> *x, long long ldx)
             LevelStep<T> a = step_args<T>(c, P, l, true, nrhs);
             a.in = (const cpx<T> *)w.U[l + 1];
             a.out = (cpx<T> *)w.U[l];
-            if (launch_aggregate_step<T>(a, nrhs, st)) continue;
-            if (!launch_interp_fixed<T>(taps, C.nbox, midlen, C.K, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], m.mid,
-                                        nrhs, st))
-                launch_interp<T>(C.nbox, midlen, C.K, I.ath_s, I.ath_c, P.lv[l].ath_w, (cpx<T> *)w.U[l + 1], m.mid,
-                                 nrhs, false, st);
-            if (!launch_agg_phi_fixed<T>(taps, L.nbox, L.K, midlen, I.child_start, c->lv[l + 1].oct, P.lv[l].shift,
-                                         I.aph_c, P.lv[l].aph_w, m.mid, (cpx<T> *)w.U[l], nrhs, st))
-                launch_agg_phi<T>(L.nbox, L.K, midlen, I.child_start, c->lv[l + 1].oct, P.lv[l].shift, I.aph_s,
-                                  I.aph_c, P.lv[l].aph_w, m.mid, (cpx<T> *)w.U[l], nrhs, st);
+            if (!(nrhs >= 4 && P.lv[l].agg_two) && launch_aggregate_step<T>(a, nrhs, st)) continue;
+            agg_two<T>(c, P, w, l, nrhs, st);
         }
     }
     m.mark(4);
@@ -1625,9 +1661,6 @@ void mv_end(MvRun<T> &m, cpx<T> *y, long long ldy)
     const Level &Lf = tr.lv[leafl];
     if (m.far) {
         for (int l = 3; l <= leafl; l++) {
-            const Level &L = tr.lv[l], &Pl = tr.lv[l - 1];
-            const IntLevel &Ip = c->lv[l - 1];
-            const int midlen = Pl.nth * L.nph;
             if constexpr (std::is_same<T, float>::value)
                 if (P.level_mfma && P.lv[l - 1].dis_m.ok &&
                     launch_disaggregate_mfma(P.lv[l - 1].dis_m, (const cpx<float> *)w.V[l - 1], (cpx<float> *)w.V[l],
@@ -1636,11 +1669,8 @@ void mv_end(MvRun<T> &m, cpx<T> *y, long long ldy)
             LevelStep<T> a = step_args<T>(c, P, l - 1, false, nrhs);
             a.in = (const cpx<T> *)w.V[l - 1];
             a.out = (cpx<T> *)w.V[l];
-            if (launch_disaggregate_step<T>(a, nrhs, st)) continue;
-            launch_disagg_mid<T>(L.nbox, midlen, Pl.K, c->lv[l].parent, c->lv[l].oct, P.lv[l - 1].shift, Ip.dph_s,
-                                 Ip.dph_c, P.lv[l - 1].dph_w, (cpx<T> *)w.V[l - 1], m.mid, nrhs, st);
-            launch_interp<T>(L.nbox, L.K, midlen, Ip.dth_s, Ip.dth_c, P.lv[l - 1].dth_w, m.mid, (cpx<T> *)w.V[l],
-                             nrhs, true, st);
+            if (!(nrhs >= 4 && P.lv[l - 1].dis_two) && launch_disaggregate_step<T>(a, nrhs, st)) continue;
+            dis_two<T>(c, P, w, l - 1, nrhs, st);
         }
     }
     m.mark(6);

@@ -129,11 +129,16 @@ __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, i
 
 // Receive.  Work item = (leaf box, row tile of 16 rows (RWG m, half h),
 // tile of 16 right-hand sides), one per wave, right-hand-side tiles
-// innermost; D[i = (m, h)][j = rhs], inner index k = (component, sample),
-// four samples per MFMA step, the next step's operands loaded before the
-// current step's MFMAs.  Rows: h = 0 uses (Pt, Pp), h = 1 uses (Pp, -Pt),
-// with P = conj(R) for the EM pair and P = Q for the C block, weights wq
-// folded in.
+// innermost; D[i = (m, h)][j = rhs], inner index k = (component, sample).
+// Rows: h = 0 uses (Pt, Pp), h = 1 uses (Pp, -Pt), with P = conj(R) for the
+// EM pair and P = Q for the C block, weights wq folded in.  The samples go
+// in blocks of 16: lane group kk (lanes 16 kk .. 16 kk + 15) loads samples
+// 4 kk .. 4 kk + 3 of the block for its row (both components, 64 contiguous
+// bytes) and for its right-hand side (32 bytes per component), and step u
+// of the block takes sample 4 kk + u in every lane group: the same order of
+// the inner index for the A and B operands, so that each lane reads whole
+// runs of samples.  The next block is loaded while the current one is
+// multiplied.
 __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const int2 *__restrict__ items, int K,
                                                       const int *__restrict__ box_start,
                                                       const cpx<float> *__restrict__ R,
@@ -154,62 +159,67 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
     const int lo = lane & 15, kk = lane >> 4;
     const cpx<float> *pat = op == MLFMA_OP_EM ? R : Q;
     const bool cj = op == MLFMA_OP_EM;
-    const int kq = (K + 3) / 4;                     // steps of 4 samples per component
     const int row = tile * 16 + lo, r = rt * 16 + lo;
     const bool mok = row < rows, rok = r < nrhs;
     const int h = row & 1;
     const cpx<float> *pm = pat + (long long)(n0 + (mok ? row / 2 : 0)) * K * 2;
+    const cpx<float> *v0 = V + ((long long)(b * 2) * nrhs + (rok ? r : 0)) * K;
+    const long long vstep = (long long)nrhs * K;   // second component of V
+    const int nblk = (K + 15) / 16;
+    // the lane's A operand in component pass c is one component of its row's
+    // pattern: theta for (h, c) = (0, 0), phi for (0, 1) and (1, 0), minus
+    // theta for (1, 1)
+    const int comp0 = h == 0 ? 0 : 1, comp1 = h == 0 ? 1 : 0;
+    const float sg1 = h == 1 ? -1.0f : 1.0f;
+    struct Blk {
+        cpx<float> q[4][2];   // pattern, samples x components
+        cpx<float> v[2][4];   // V, components x samples
+        float w[4];
+    };
+    auto load = [&](int bk, Blk &o) {
+        const int q0 = bk * 16 + kk * 4;
+        if (q0 + 3 < K) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                o.w[u] = wq[q0 + u];
+                o.q[u][0] = mok ? pm[2 * (q0 + u)] : mk<float>(0, 0);
+                o.q[u][1] = mok ? pm[2 * (q0 + u) + 1] : mk<float>(0, 0);
+                o.v[0][u] = rok ? v0[q0 + u] : mk<float>(0, 0);
+                o.v[1][u] = rok ? v0[vstep + q0 + u] : mk<float>(0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int q = q0 + u;
+                const bool qok = q < K;
+                o.w[u] = qok ? wq[q] : 0.0f;
+                o.q[u][0] = mok && qok ? pm[2 * q] : mk<float>(0, 0);
+                o.q[u][1] = mok && qok ? pm[2 * q + 1] : mk<float>(0, 0);
+                o.v[0][u] = rok && qok ? v0[q] : mk<float>(0, 0);
+                o.v[1][u] = rok && qok ? v0[vstep + q] : mk<float>(0, 0);
+            }
+        }
+    };
     f4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
-    for (int c = 0; c < 2; c++) {
-        // the lane's A operand is one component of its row's pattern: theta
-        // for (h, c) = (0, 0), phi for (0, 1) and (1, 0), minus theta for (1, 1)
-        const int comp = (h == 0) == (c == 0) ? 0 : 1;
-        const float sg = (h == 1 && c == 1) ? -1.0f : 1.0f;
-        const cpx<float> *vc = V + ((long long)(b * 2 + c) * nrhs + (rok ? r : 0)) * K;
-        auto load = [&](int qs, cpx<float> &a, cpx<float> &bv) {
-            const int q = qs * 4 + kk;
-            const bool qok = q < K;
-            a = mk<float>(0, 0);
-            bv = mk<float>(0, 0);
-            if (mok && qok) {
-                cpx<float> p = pm[2 * q + comp];
+    Blk cur, nxt;
+    load(0, cur);
+    for (int bk = 0; bk < nblk; bk++) {
+        if (bk + 1 < nblk) load(bk + 1, nxt);
+#pragma unroll
+        for (int c = 0; c < 2; c++)
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int cp = c == 0 ? comp0 : comp1;
+                cpx<float> p = cp ? cur.q[u][1] : cur.q[u][0];   // a select, not a dynamic register index
                 if (cj) p = conjg(p);
-                a = (sg * wq[q]) * p;
+                const cpx<float> a = ((c == 1 ? sg1 : 1.0f) * cur.w[u]) * p;
+                const cpx<float> bv = cur.v[c][u];
+                dre = mfma4(a.re, bv.re, dre);
+                dim = mfma4(a.re, bv.im, dim);
+                dre = mfma4(-a.im, bv.im, dre);
+                dim = mfma4(a.im, bv.re, dim);
             }
-            if (qok && rok) bv = vc[q];
-        };
-        cpx<float> a, bv, an, bn;
-        load(0, a, bv);
-        int qs = 0;
-        // steps whose successor has all four samples inside K: its operands
-        // without sample predicates (right-hand sides past nrhs read clamped,
-        // valid elements; only their own outputs, which are never stored,
-        // see them)
-        for (; qs + 1 < K / 4; qs++) {
-            const int q = (qs + 1) * 4 + kk;
-            an = mk<float>(0, 0);
-            if (mok) {   // rows past the tile: no loads (fewer requests for small boxes)
-                cpx<float> p = pm[2 * q + comp];
-                if (cj) p = conjg(p);
-                an = (sg * wq[q]) * p;
-            }
-            bn = vc[q];
-            dre = mfma4(a.re, bv.re, dre);
-            dim = mfma4(a.re, bv.im, dim);
-            dre = mfma4(-a.im, bv.im, dre);
-            dim = mfma4(a.im, bv.re, dim);
-            a = an;
-            bv = bn;
-        }
-        for (; qs < kq; qs++) {
-            if (qs + 1 < kq) load(qs + 1, an, bn);
-            dre = mfma4(a.re, bv.re, dre);
-            dim = mfma4(a.re, bv.im, dim);
-            dre = mfma4(-a.im, bv.im, dre);
-            dim = mfma4(a.im, bv.re, dim);
-            a = an;
-            bv = bn;
-        }
+        cur = nxt;
     }
 #pragma unroll
     for (int v = 0; v < 4; v++) {
