@@ -137,8 +137,7 @@ __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, i
 // bytes) and for its right-hand side (32 bytes per component), and step u
 // of the block takes sample 4 kk + u in every lane group: the same order of
 // the inner index for the A and B operands, so that each lane reads whole
-// runs of samples.  The next block is loaded while the current one is
-// multiplied.
+// runs of samples.  Two blocks are in flight while one is multiplied.
 __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const int2 *__restrict__ items, int K,
                                                       const int *__restrict__ box_start,
                                                       const cpx<float> *__restrict__ R,
@@ -201,10 +200,11 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
         }
     };
     f4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
-    Blk cur, nxt;
-    load(0, cur);
-    for (int bk = 0; bk < nblk; bk++) {
-        if (bk + 1 < nblk) load(bk + 1, nxt);
+    // two blocks in flight: block bk + 2 is loaded while block bk is multiplied
+    Blk b0, b1, b2;
+    load(0, b0);
+    if (nblk > 1) load(1, b1);
+    auto mult = [&](const Blk &cur) {
 #pragma unroll
         for (int c = 0; c < 2; c++)
 #pragma unroll
@@ -219,7 +219,12 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
                 dre = mfma4(-a.im, bv.im, dre);
                 dim = mfma4(a.im, bv.re, dim);
             }
-        cur = nxt;
+    };
+    for (int bk = 0; bk < nblk; bk++) {
+        if (bk + 2 < nblk) load(bk + 2, b2);
+        mult(b0);
+        b0 = b1;
+        b1 = b2;
     }
 #pragma unroll
     for (int v = 0; v < 4; v++) {
