@@ -473,8 +473,9 @@ int mlfma_tuning_steps(mlfma_handle h, int *matrix_cores, double ms[2]);
  * `level` (2 <= level < levels - 1) and level + 1 for products of four or
  * more right-hand sides in precision dtype: shape[0], shape[1] = the
  * aggregation's right-hand sides per workgroup (0: the launcher's default)
- * and pipelined right-hand sides per pass (0: not pipelined); shape[2],
- * shape[3] the same for the disaggregation; shape[4] = the aggregation's
+ * and pipelined right-hand sides per pass (0: not pipelined; 4 counts as
+ * 2); shape[2], shape[3] the same for the disaggregation, whose pipelined
+ * passes count vectors (one component of one right-hand side: 1, 2 or 4); shape[4] = the aggregation's
  * children staged together (0: the launcher's default).  MLFMA_ERR_ARG for a
  * NULL handle or shape, an unknown dtype or a level out of range. */
 int mlfma_tuning_level(mlfma_handle h, int dtype, int level, int shape[5]);

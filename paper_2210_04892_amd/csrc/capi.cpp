@@ -66,7 +66,7 @@ struct PrecLevel {
     int agg_rb = 0, dis_rb = 0;   // right-hand sides per workgroup with four or more (autotuned; 0 = default)
     int agg_group = 0;            // aggregation: children staged together (autotuned; 0 = default)
     int agg_two = 0, dis_two = 0; // 1: the step as two kernels through the global intermediate (autotuned)
-    int dis_pipe = 0;             // > 0: pipelined disaggregation with this many per pass (autotuned)
+    int dis_pipe = 0;             // > 0: pipelined disaggregation with this many vectors per pass (autotuned)
     int agg_pipe = 0;             // the same for the aggregation
     // separable aggregation stencils (SepStencil; tth = 0: not separable)
     int ag_tth = 0, ag_tphi = 0;
@@ -1329,7 +1329,10 @@ void tune_step_rb(mlfma_ctx *c, Prec<T> &P)
 {
     const Tree &tr = c->tr;
     if (c->opt.level_kernel == MLFMA_LEVELS_PIPELINED) {
-        for (int l = 2; l + 1 < tr.levels; l++) P.lv[l].agg_pipe = P.lv[l].dis_pipe = 2;
+        for (int l = 2; l + 1 < tr.levels; l++) {   // the widest passes; the launchers narrow them where needed
+            P.lv[l].agg_pipe = 2;
+            P.lv[l].dis_pipe = 4;
+        }
         return;
     }
     const bool blocked = c->opt.level_kernel == MLFMA_LEVELS_BLOCKED;
@@ -1354,8 +1357,8 @@ void tune_step_rb(mlfma_ctx *c, Prec<T> &P)
             int &two = agg ? P.lv[l].agg_two : P.lv[l].dis_two;
             // (right-hand sides per workgroup, pipelined per pass, children per
             // group, two kernels through the global intermediate)
-            const int cands[8][4] = {{1, 0, 0, 0}, {2, 0, 0, 0}, {4, 0, 0, 0}, {0, 1, 0, 0},
-                                     {0, 2, 0, 0}, {1, 0, 2, 0}, {1, 0, 4, 0}, {0, 0, 0, 1}};
+            const int cands[9][4] = {{1, 0, 0, 0}, {2, 0, 0, 0}, {4, 0, 0, 0}, {0, 1, 0, 0}, {0, 2, 0, 0},
+                                     {0, 4, 0, 0}, {1, 0, 2, 0}, {1, 0, 4, 0}, {0, 0, 0, 1}};
             double best = 1e30;
             int pick[4] = {0, 0, 0, 0};
             for (const auto &cd : cands) {

@@ -196,7 +196,9 @@ struct LevelStep {
     int rows = 0, nchunk = 0, wrows = 0, taps = 0;
     int rb = 0;                         // right-hand sides per workgroup (0: the launcher's choice)
     int group = 0;                      // aggregation: children staged together (0: the launcher's choice)
-    int pipe = 0;                       // > 0: the pipelined kernel with this many right-hand sides per pass
+    int pipe = 0;                       // > 0: the pipelined kernel; per pass this many vectors (component x
+                                        // right-hand side; 1, 2, 4) in the disaggregation, right-hand sides
+                                        // (1, 2; 4 counts as 2) in the aggregation
     const int *win = nullptr;
     const int *child_start = nullptr;   // aggregation: children of each parent
     const int *parent = nullptr;        // disaggregation: parent of each child

@@ -246,23 +246,27 @@ __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate(const LevelStep<T
     }
 }
 
-// disaggregation, pipelined over the right-hand sides: workgroup = (child,
-// chunk of child theta rows, slice of the right-hand sides).  It walks its
-// slice RB right-hand sides at a time; while one pass anterpolates in LDS,
-// the next pass's parent window (NPF samples per thread) and this pass's
-// old child values (NO per thread) are in flight in registers, so the
-// memory latency of one pass hides behind the arithmetic of another.  The
-// chunk's stencils are staged in LDS once.  Same arithmetic as
-// k_disaggregate, term for term.
-template <class T, int RB, int NPF, int NO>
+// disaggregation, pipelined over the vectors: a box's patterns are 2 nrhs
+// vectors of K samples (component c, right-hand side r at c nrhs + r), all
+// transformed by the same stencils.  Workgroup = (child, chunk of child theta
+// rows, slice of the vectors).  It walks its slice NV vectors at a time (one
+// vector: half the LDS of a right-hand side's two components, for the wide
+// windows of the coarse levels); while one pass anterpolates in LDS, the
+// next pass's parent window (NPF samples per thread) and this pass's old
+// child values (NO per thread) are in flight in registers, so the memory
+// latency of one pass hides behind the arithmetic of another.  The chunk's
+// stencils are staged in LDS once.  Same arithmetic as k_disaggregate, term
+// for term.
+template <class T, int NV, int NPF, int NO>
 __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate_pipe(const LevelStep<T> a, int nrhs, int per_slice)
 {
     extern __shared__ double step_lds_raw[];
     const long long blk = xcd_block_l((long long)a.nbox * a.nchunk);
     if (blk < 0) return;
     const int c = (int)(blk / a.nchunk), ch = (int)(blk % a.nchunk);
-    const int rs0 = blockIdx.y * per_slice, rs1 = min(nrhs, rs0 + per_slice);
-    if (rs0 >= rs1) return;
+    const int nvec = 2 * nrhs;
+    const int vs0 = blockIdx.y * per_slice, vs1 = min(nvec, vs0 + per_slice);
+    if (vs0 >= vs1) return;
     const int tid = threadIdx.x;
     const int Kc = a.nth_c * a.nph_c, Kp = a.nth_p * a.nph_p;
     const int nph_c = a.nph_c, nph_p = a.nph_p, tphi = a.tphi, tth = a.tth;
@@ -271,9 +275,9 @@ __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate_pipe(const LevelS
     const int plen = (w1 - w0) * nph_p, pmax = a.wrows * nph_p;
     const int mlen = (w1 - w0) * nph_c, mmax = a.wrows * nph_c;
     const int olen = (i1 - i0) * nph_c;
-    cpx<T> *pw = reinterpret_cast<cpx<T> *>(step_lds_raw);   // [RB][2][pmax] shifted parent rows
-    cpx<T> *mid = pw + 2 * RB * pmax;                         // [RB][2][mmax] intermediate rows
-    T *s_phw = reinterpret_cast<T *>(mid + 2 * RB * mmax);    // [nph_c][tphi]
+    cpx<T> *pw = reinterpret_cast<cpx<T> *>(step_lds_raw);   // [NV][pmax] shifted parent rows
+    cpx<T> *mid = pw + NV * pmax;                             // [NV][mmax] intermediate rows
+    T *s_phw = reinterpret_cast<T *>(mid + NV * mmax);        // [nph_c][tphi]
     T *s_rowf = s_phw + nph_c * tphi;                         // [wrows]
     T *s_thw = s_rowf + a.wrows;                              // [rows][tth]
     int *s_phc = reinterpret_cast<int *>(s_thw + a.rows * tth);   // [nph_c][tphi]
@@ -291,9 +295,8 @@ __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate_pipe(const LevelS
         s_thw[i] = a.th_w[g];
     }
     const int Pb = a.parent[c];
-    const cpx<T> *pin = a.in + (long long)Pb * 2 * nrhs * Kp + (long long)w0 * nph_p;
-    cpx<T> *pout = a.out + (long long)c * 2 * nrhs * Kc + (long long)i0 * nph_c;
-    const long long hp = (long long)nrhs * Kp, hc = (long long)nrhs * Kc;   // second component
+    const cpx<T> *pin = a.in + (long long)Pb * nvec * Kp + (long long)w0 * nph_p;
+    cpx<T> *pout = a.out + (long long)c * nvec * Kc + (long long)i0 * nph_c;
     const cpx<T> *sh = a.shift + (long long)a.oct[c] * Kp + (long long)w0 * nph_p;
     cpx<T> shf[NPF];
 #pragma unroll
@@ -301,49 +304,41 @@ __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate_pipe(const LevelS
         const int i = tid + k * STEP_THREADS;
         shf[k] = i < plen ? conjg(sh[i]) : mk<T>(0, 0);
     }
-    cpx<T> pf0[NPF][RB], pf1[NPF][RB];
-    auto load_window = [&](int r0) {
+    cpx<T> pf[NPF][NV];
+    auto load_window = [&](int v0) {
 #pragma unroll
         for (int k = 0; k < NPF; k++) {
             const int i = tid + k * STEP_THREADS;
 #pragma unroll
-            for (int j = 0; j < RB; j++) {
-                const long long o = (long long)min(r0 + j, nrhs - 1) * Kp + i;
-                pf0[k][j] = i < plen ? pin[o] : mk<T>(0, 0);
-                pf1[k][j] = i < plen ? pin[hp + o] : mk<T>(0, 0);
+            for (int j = 0; j < NV; j++) {
+                const long long o = (long long)min(v0 + j, nvec - 1) * Kp + i;
+                pf[k][j] = i < plen ? pin[o] : mk<T>(0, 0);
             }
         }
     };
-    load_window(rs0);
+    load_window(vs0);
     // (row, column) of this thread's first intermediate and output slots; a
     // stride of STEP_THREADS advances them by (dq, dr)
     const int dq = STEP_THREADS / nph_c, dr = STEP_THREADS - dq * nph_c;
     const int il0 = tid / nph_c, jc0 = tid - il0 * nph_c;
-    for (int r0 = rs0; r0 < rs1; r0 += RB) {
+    for (int v0 = vs0; v0 < vs1; v0 += NV) {
         // the previous pass's phi stage is done (second barrier): overwrite pw
 #pragma unroll
         for (int k = 0; k < NPF; k++) {
             const int i = tid + k * STEP_THREADS;
             if (i < plen) {
 #pragma unroll
-                for (int j = 0; j < RB; j++) {
-                    pw[(2 * j) * pmax + i] = shf[k] * pf0[k][j];
-                    pw[(2 * j + 1) * pmax + i] = shf[k] * pf1[k][j];
-                }
+                for (int j = 0; j < NV; j++) pw[j * pmax + i] = shf[k] * pf[k][j];
             }
         }
-        if (r0 + RB < rs1) load_window(r0 + RB);
-        cpx<T> old0[NO][RB], old1[NO][RB];
+        if (v0 + NV < vs1) load_window(v0 + NV);
+        cpx<T> old[NO][NV];
 #pragma unroll
         for (int q = 0; q < NO; q++) {
             const int o = tid + q * STEP_THREADS;
 #pragma unroll
-            for (int j = 0; j < RB; j++) {
-                const long long e = (long long)(r0 + j) * Kc + o;
-                const bool ok = o < olen && r0 + j < rs1;
-                old0[q][j] = ok ? pout[e] : mk<T>(0, 0);
-                old1[q][j] = ok ? pout[hc + e] : mk<T>(0, 0);
-            }
+            for (int j = 0; j < NV; j++)
+                old[q][j] = o < olen && v0 + j < vs1 ? pout[(long long)(v0 + j) * Kc + o] : mk<T>(0, 0);
         }
         __syncthreads();
         // phi anterpolation: intermediate rows from the parent rows of the window
@@ -353,25 +348,19 @@ __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate_pipe(const LevelS
                 const int *pc = s_phc + jc * tphi;
                 const T *pwt = s_phw + jc * tphi;
                 const int rb_ = il * nph_p;
-                cpx<T> s0[RB], s1[RB];
+                cpx<T> sv[NV];
 #pragma unroll
-                for (int j = 0; j < RB; j++) s0[j] = s1[j] = mk<T>(0, 0);
+                for (int j = 0; j < NV; j++) sv[j] = mk<T>(0, 0);
 #pragma unroll 4
                 for (int t = 0; t < tphi; t++) {
                     const int jj = rb_ + pc[t];
                     const T wt = pwt[t];
 #pragma unroll
-                    for (int j = 0; j < RB; j++) {
-                        axpy_to(s0[j], wt, pw[(2 * j) * pmax + jj]);
-                        axpy_to(s1[j], wt, pw[(2 * j + 1) * pmax + jj]);
-                    }
+                    for (int j = 0; j < NV; j++) axpy_to(sv[j], wt, pw[j * pmax + jj]);
                 }
                 const T f = s_rowf[il];
 #pragma unroll
-                for (int j = 0; j < RB; j++) {
-                    mid[(2 * j) * mmax + m] = f * s0[j];
-                    mid[(2 * j + 1) * mmax + m] = f * s1[j];
-                }
+                for (int j = 0; j < NV; j++) mid[j * mmax + m] = f * sv[j];
                 il += dq;
                 jc += dr;
                 if (jc >= nph_c) {
@@ -390,9 +379,9 @@ __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate_pipe(const LevelS
                 if (o < olen) {
                     const int *tr = s_thr + il * tth, *ts = s_ths + il * tth;
                     const T *tw = s_thw + il * tth;
-                    cpx<T> s0[RB], s1[RB];
+                    cpx<T> sv[NV];
 #pragma unroll
-                    for (int j = 0; j < RB; j++) s0[j] = s1[j] = mk<T>(0, 0);
+                    for (int j = 0; j < NV; j++) sv[j] = mk<T>(0, 0);
 #pragma unroll 4
                     for (int t = 0; t < tth; t++) {
                         int col = jc + ts[t];
@@ -400,17 +389,12 @@ __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate_pipe(const LevelS
                         const int jj = tr[t] + col;
                         const T wt = tw[t];
 #pragma unroll
-                        for (int j = 0; j < RB; j++) {
-                            axpy_to(s0[j], wt, mid[(2 * j) * mmax + jj]);
-                            axpy_to(s1[j], wt, mid[(2 * j + 1) * mmax + jj]);
-                        }
+                        for (int j = 0; j < NV; j++) axpy_to(sv[j], wt, mid[j * mmax + jj]);
                     }
 #pragma unroll
-                    for (int j = 0; j < RB; j++) {
-                        if (r0 + j >= rs1) continue;
-                        const long long e = (long long)(r0 + j) * Kc + o;
-                        pout[e] = old0[q][j] + s0[j];
-                        pout[hc + e] = old1[q][j] + s1[j];
+                    for (int j = 0; j < NV; j++) {
+                        if (v0 + j >= vs1) continue;
+                        pout[(long long)(v0 + j) * Kc + o] = old[q][j] + sv[j];
                     }
                 }
                 il += dq;
@@ -719,15 +703,16 @@ bool launch_aggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s)
     return true;
 }
 
-template <class T, int RB, int NPF>
+template <class T, int NV, int NPF>
 void dis_pipe_launch(int no, dim3 grid, size_t lds, hipStream_t s, const LevelStep<T> &a, int nrhs, int per)
 {
-    if (no == 1) hipLaunchKernelGGL((k_disaggregate_pipe<T, RB, NPF, 1>), grid, dim3(STEP_THREADS), lds, s, a, nrhs, per);
-    else hipLaunchKernelGGL((k_disaggregate_pipe<T, RB, NPF, 2>), grid, dim3(STEP_THREADS), lds, s, a, nrhs, per);
+    if (no == 1) hipLaunchKernelGGL((k_disaggregate_pipe<T, NV, NPF, 1>), grid, dim3(STEP_THREADS), lds, s, a, nrhs, per);
+    else hipLaunchKernelGGL((k_disaggregate_pipe<T, NV, NPF, 2>), grid, dim3(STEP_THREADS), lds, s, a, nrhs, per);
 }
 
-// the pipelined disaggregation with RB right-hand sides per pass; false when
-// the chunk does not fit its register and LDS limits
+// the pipelined disaggregation with a.pipe vectors per pass (1, 2 or 4: one
+// component, one right-hand side, two right-hand sides); fewer where the
+// window does not fit the registers or LDS; false when even one does not
 template <class T>
 bool launch_disaggregate_pipe(const LevelStep<T> &a, int nrhs, hipStream_t s)
 {
@@ -741,18 +726,24 @@ bool launch_disaggregate_pipe(const LevelStep<T> &a, int nrhs, hipStream_t s)
     if (!npf || !no) return false;
     const size_t tables = (size_t)a.nph_c * a.tphi * (sizeof(T) + sizeof(int)) + (size_t)a.wrows * sizeof(T) +
                           (size_t)a.rows * a.tth * (sizeof(T) + 2 * sizeof(int));
-    // two right-hand sides per pass where asked for and within the limits, else one
-    int RB = a.pipe >= 2 && nrhs >= 2 && npf <= 2 ? 2 : 1;
-    if (RB == 2 && 2 * dis_lds_bytes<T>(a.wrows, a.nph_p, a.nph_c) + tables > STEP_LDS_MAX) RB = 1;
-    const size_t lds = RB * dis_lds_bytes<T>(a.wrows, a.nph_p, a.nph_c) + tables;
+    const size_t lds1 = dis_lds_bytes<T>(a.wrows, a.nph_p, a.nph_c) / 2;   // one vector
+    int nv = a.pipe >= 4 ? 4 : a.pipe >= 2 ? 2 : 1;
+    nv = std::min(nv, 2 * nrhs);
+    while (nv > 1 && (nv * npf > 16 || nv * lds1 + tables > STEP_LDS_MAX)) nv /= 2;
+    const size_t lds = nv * lds1 + tables;
     if (lds > STEP_LDS_MAX) return false;
     if (a.nbox <= 0 || nrhs <= 0) return true;
     const long long nblk = (long long)a.nbox * a.nchunk;
     int per = 0;
-    const int slices = pipe_slices(nblk, nrhs, RB, per);
+    const int slices = pipe_slices(nblk, 2 * nrhs, nv, per);
     const dim3 grid(xcd_grid_l(nblk), slices);
-    if (RB == 2 && npf == 1) dis_pipe_launch<T, 2, 1>(no, grid, lds, s, a, nrhs, per);
-    else if (RB == 2) dis_pipe_launch<T, 2, 2>(no, grid, lds, s, a, nrhs, per);
+    if (nv == 4 && npf == 1) dis_pipe_launch<T, 4, 1>(no, grid, lds, s, a, nrhs, per);
+    else if (nv == 4 && npf == 2) dis_pipe_launch<T, 4, 2>(no, grid, lds, s, a, nrhs, per);
+    else if (nv == 4) dis_pipe_launch<T, 4, 4>(no, grid, lds, s, a, nrhs, per);
+    else if (nv == 2 && npf == 1) dis_pipe_launch<T, 2, 1>(no, grid, lds, s, a, nrhs, per);
+    else if (nv == 2 && npf == 2) dis_pipe_launch<T, 2, 2>(no, grid, lds, s, a, nrhs, per);
+    else if (nv == 2 && npf == 4) dis_pipe_launch<T, 2, 4>(no, grid, lds, s, a, nrhs, per);
+    else if (nv == 2) dis_pipe_launch<T, 2, 8>(no, grid, lds, s, a, nrhs, per);
     else if (npf == 1) dis_pipe_launch<T, 1, 1>(no, grid, lds, s, a, nrhs, per);
     else if (npf == 2) dis_pipe_launch<T, 1, 2>(no, grid, lds, s, a, nrhs, per);
     else if (npf == 4) dis_pipe_launch<T, 1, 4>(no, grid, lds, s, a, nrhs, per);

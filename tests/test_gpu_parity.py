@@ -260,7 +260,7 @@ def test_pipelined_level_steps(name, nrows):
     gp = mf.Geometry(v, t, k=K0, max_rhs=20, level_kernel="pipelined").precompute()
     gb = mf.Geometry(v, t, k=K0, max_rhs=20, level_kernel="blocked").precompute()
     shapes = gp.tuning_levels()
-    assert all(s["agg_pipe"] == 2 and s["dis_pipe"] == 2 for s in shapes.values())
+    assert all(s["agg_pipe"] == 2 and s["dis_pipe"] == 4 for s in shapes.values())
     assert all(s["agg_pipe"] == 0 and s["dis_pipe"] == 0 for s in gb.tuning_levels().values())
     for nrhs in (5, 20):
         x, rows, ref = reference(name, nrows, nrhs, 7)
