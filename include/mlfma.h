@@ -96,8 +96,11 @@ enum {
 
 /* Fill *opt with defaults: k = 2 pi, leaf 0.25, d0 = 3, order 8, extra 2,
  * one RHS, current device, no budget, autotuned translation and level-step
- * kernels, both parts of complex128 products in FP64.  Returns MLFMA_ERR_ARG
- * on NULL. */
+ * kernels, both parts of complex128 products in FP64.  The paper cites MLFMA
+ * without its parameters: the truncation rule (d0), the Lagrange order and
+ * the leaf size are this library's, chosen to reach 3 digits (Sec. II-E
+ * asks for the product, not for a parameter set).  Returns MLFMA_ERR_ARG on
+ * NULL. */
 int mlfma_options_default(mlfma_options *opt);
 
 /*
@@ -251,19 +254,6 @@ int mlfma_plane_wave_rhs(mlfma_handle h, int dtype, long long nrhs, const double
 int mlfma_far_field(mlfma_handle h, int dtype, long long nrhs, const void *x, long long ldx, long long ndir,
                     const double *dirs, void *F, void *hip_stream);
 
-/*
- * Serving: concurrent Krylov clients submit products for resident
- * geometries; the server batches continuously.  A scheduler thread merges
- * queued requests of the same (geometry, op, dtype) into one multi-RHS
- * product of at most max_batch_rhs columns and admits it to a free launch
- * slot (one stream and one workspace arena each; the arenas together stay
- * within hbm_budget_bytes, 0 = no limit); requests arriving while others run
- * are admitted as soon as a slot frees, so products for different geometries
- * overlap on the device.  x and y of a request are DEVICE buffers owned by
- * the caller and must stay valid until mlfma_server_wait returns; results are
- * the same as mlfma_matvec_LK's up to rounding.  Handles must outlive the
- * server's use of them.  All calls are thread-safe.
- */
 /* ------------------------------------------------------------------------
  * Captured products (HIP graphs).  mlfma_graph_create records the whole
  * product y = A x of mlfma_matvec_LK (same arguments and checks; op, dtype,
@@ -389,6 +379,20 @@ int mlfma_hybrid_gmres(mlfma_hybrid hy, int dtype, long long nrhs, const void *b
 /* NULL accepted; waits for the device. */
 int mlfma_hybrid_destroy(mlfma_hybrid hy);
 
+/* ------------------------------------------------------------------------
+ * Serving (the request loop around step 2(a) of Sec. II-E for many outer
+ * solvers at once): concurrent Krylov clients submit products for resident
+ * geometries; the server batches continuously.  A scheduler thread merges
+ * queued requests of the same (geometry, op, dtype) into one multi-RHS
+ * product of at most max_batch_rhs columns and admits it to a free launch
+ * slot (one stream and one workspace arena each; the arenas together stay
+ * within hbm_budget_bytes, 0 = no limit); requests arriving while others run
+ * are admitted as soon as a slot frees, so products for different geometries
+ * overlap on the device.  x and y of a request are DEVICE buffers owned by
+ * the caller and must stay valid until mlfma_server_wait returns; results are
+ * the same as mlfma_matvec_LK's up to rounding.  Handles must outlive the
+ * server's use of them.  All calls are thread-safe.
+ * ------------------------------------------------------------------------ */
 typedef struct mlfma_server_s *mlfma_server;
 typedef struct {
     int streams;                          /* launch slots (1..16, default 4)      */
@@ -422,11 +426,13 @@ int mlfma_server_stats(mlfma_server s, long long out[5]);
  * freed.  No call on s may start once destroy has begun.  NULL accepted. */
 int mlfma_server_destroy(mlfma_server s);
 
-/* Free every device and host resource of the handle.  NULL is accepted. */
+/* Free every device and host resource of the handle (library housekeeping:
+ * no passage of the paper defines it).  NULL is accepted. */
 int mlfma_release(mlfma_handle h);
 
-/* Sizes: RWG count N, octree levels (root = level 0), bytes of device memory
- * held by the handle.  Any output pointer may be NULL. */
+/* Sizes: RWG count N (the paper's BI unknowns are 2N: J and M per RWG),
+ * octree levels (root = level 0), bytes of device memory held by the
+ * handle.  Any output pointer may be NULL. */
 int mlfma_query(mlfma_handle h, long long *n_rwg, int *levels, unsigned long long *hbm_bytes);
 
 /* RWG table in the order of the vectors: edge_ab (N x 2, a < b) and tri_pm
@@ -506,7 +512,8 @@ int mlfma_profile_read(mlfma_handle h, double ms[8], long long *calls);
  */
 int mlfma_peak_probe(int kind, int device, double *value);
 
-/* Text of the last error of the calling thread ("" if none). */
+/* Text of the last error of the calling thread ("" if none; library
+ * housekeeping). */
 const char *mlfma_last_error(void);
 
 /*
