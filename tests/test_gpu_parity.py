@@ -636,11 +636,13 @@ def test_matvec_batch_matches_single_products():
     assert torch.all(yt == 5.0)
 
 
-@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
-def test_fused_batch_of_geometries(dtype):
+@pytest.mark.parametrize("dtype,nrhs", [(np.complex64, 5), (np.complex128, 5), (np.complex64, 1)])
+def test_fused_batch_of_geometries(dtype, nrhs):
     """mlfma_matvec_batch_fused over four uneven geometries (320 to 39k RWGs,
     3 to 6 levels; one of them two disconnected bodies) with 5 right-hand
-    sides, the translations of all their levels in shared launches: every
+    sides (and with one, where the radiation and receive read and write the
+    caller's vectors directly), the translations of all their levels in
+    shared launches: every
     product against the oracle, and against the geometry's own product (bit
     for bit where that geometry's translation is the sibling-group kernel,
     which sums every target's sources in the same order in every shape);
@@ -649,7 +651,6 @@ def test_fused_batch_of_geometries(dtype):
     torch = _torch()
     import paper_2210_04892_amd as mf
     names = [("ico6_r0.5", None), ("sphere_r3", 96), ("two_bodies", 96), ("box_4x4x1", 96)]
-    nrhs = 5
     gs, xs, refs = [], [], []
     for name, nrows in names:
         x, rows, ref = reference(name, nrows, nrhs, 13)
@@ -676,8 +677,9 @@ def test_fused_batch_of_geometries(dtype):
             assert d <= (1e-4 if dtype == np.complex64 else 1e-10)
     with pytest.raises(mf.MlfmaError):
         mf.matvec_batch([(gs[0], xs[0], "C"), (gs[0], xs[0], "EM")], fused=True)
-    with pytest.raises(mf.MlfmaError):
-        mf.matvec_batch([(gs[0], xs[0], "C"), (gs[1], xs[1][:, :2], "C")], fused=True)
+    if nrhs > 2:
+        with pytest.raises(mf.MlfmaError):
+            mf.matvec_batch([(gs[0], xs[0], "C"), (gs[1], xs[1][:, :2], "C")], fused=True)
 
 
 @pytest.mark.gpu
