@@ -13,6 +13,7 @@
 #include <memory>
 #include <string>
 #include <type_traits>
+#include <thread>
 #include <vector>
 
 #include "../../include/mlfma.h"
@@ -189,6 +190,9 @@ struct mlfma_ctx {
     bool prof = false;
     std::vector<hipEvent_t> ev_free;
     std::vector<std::vector<hipEvent_t>> ev_pending;
+    // host tables of the tiled translation per (targets per tile, sources
+    // per batch), kept only while the autotuner runs
+    std::map<std::pair<int, int>, std::vector<TransTiles>> tile_cache;
     double stage_ms[MLFMA_STAGES] = {0};
     long long prof_calls = 0;
     long long n_touch = 0, n_slots = 0, n_id = 0;
@@ -503,13 +507,30 @@ void upload_level_tables(mlfma_ctx *c, Prec<T> &P, const std::vector<std::vector
 
 // translation tiles of every level for one tile shape; allocations go to
 // `list` (tuning trials) or to the handle
+// The tiled translation's tables of every level for one tile shape, built on
+// host threads (one per level) and kept while the handle is built: the
+// autotuner's candidates of both precisions share them.
+const std::vector<TransTiles> &tiles_for(mlfma_ctx *c, int tmax, int smax)
+{
+    auto &slot = c->tile_cache[{tmax, smax}];
+    if (slot.empty()) {
+        const Tree &tr = c->tr;
+        slot.resize(tr.levels);
+        std::vector<std::thread> pool;
+        for (int l = 2; l < tr.levels; l++)
+            pool.emplace_back([&, l] { build_translation_tiles(tr.lv[l], smax, tmax, slot[l]); });
+        for (auto &t : pool) t.join();
+    }
+    return slot;
+}
+
 template <class T>
 void upload_trans_tiles(mlfma_ctx *c, Prec<T> &P, int tmax, int smax, std::vector<void *> *list)
 {
     const Tree &tr = c->tr;
+    const std::vector<TransTiles> &tiles = tiles_for(c, tmax, smax);
     for (int l = 2; l < tr.levels; l++) {
-        TransTiles tt;
-        build_translation_tiles(tr.lv[l], smax, tmax, tt);
+        const TransTiles &tt = tiles[l];
         PrecLevel<T> &PL = P.lv[l];
         auto up = [&](const std::vector<int> &v) {
             int *d = c->dalloc<int>(v.size(), list);
@@ -753,15 +774,25 @@ void build_device_tables(mlfma_ctx *c)
         }
         std::vector<double> khat;
         level_directions(L, khat);
-        // translation operators for the 7^3 offsets (unused entries stay 0)
+        // translation operators for the 7^3 offsets (unused entries stay 0),
+        // the offsets shared out over host threads (each writes its own rows)
         trans[l].assign(343 * (size_t)L.K, cdouble(0, 0));
-        std::vector<cdouble> tl;
-        for (int o = 0; o < 343; o++) {
-            int d[3] = {o / 49 - 3, (o / 7) % 7 - 3, o % 7 - 3};
-            if (std::max(std::abs(d[0]), std::max(std::abs(d[1]), std::abs(d[2]))) < 2) continue;
-            double X[3] = {d[0] * L.a, d[1] * L.a, d[2] * L.a};
-            translation_table(k, L.L, X, khat, tl);
-            std::copy(tl.begin(), tl.end(), trans[l].begin() + (size_t)o * L.K);
+        {
+            const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+            auto work = [&](int first) {
+                std::vector<cdouble> tl;
+                for (int o = first; o < 343; o += nth) {
+                    int d[3] = {o / 49 - 3, (o / 7) % 7 - 3, o % 7 - 3};
+                    if (std::max(std::abs(d[0]), std::max(std::abs(d[1]), std::abs(d[2]))) < 2) continue;
+                    double X[3] = {d[0] * L.a, d[1] * L.a, d[2] * L.a};
+                    translation_table(k, L.L, X, khat, tl);
+                    std::copy(tl.begin(), tl.end(), trans[l].begin() + (size_t)o * L.K);
+                }
+            };
+            std::vector<std::thread> pool;
+            for (int i = 1; i < nth; i++) pool.emplace_back(work, i);
+            work(0);
+            for (auto &t : pool) t.join();
         }
         if (l + 1 < tr.levels) {
             const Level &C = tr.lv[l + 1];
@@ -2186,6 +2217,7 @@ int mlfma_build_tree(const double *verts, long long n_verts, const int *tris, lo
         ensure_workspace(c.get(), c->opt.max_rhs);
         tune_translation<double>(c.get(), c->p64);
         tune_translation<float>(c.get(), c->p32);
+        c->tile_cache.clear();
         tune_step_rb<double>(c.get(), c->p64);
         tune_step_rb<float>(c.get(), c->p32);
         tune_level_steps(c.get());
