@@ -12,7 +12,10 @@
 // of theta rows: it stages the theta rows of the input pattern that the chunk
 // needs in LDS with coalesced loads, forms the intermediate (parent theta x
 // child phi) rows in LDS, and writes only its own outputs.  The intermediate
-// never goes to memory.
+// never goes to memory.  Two forms of each step: blocked (a workgroup per
+// chunk and block of right-hand sides) and pipelined (a workgroup walks
+// several passes with the next pass's loads in flight); the autotuner picks
+// per level.
 #include <algorithm>
 
 #include "device.hpp"
