@@ -97,6 +97,7 @@ struct Prec {
     int trans_rw = 0;                             // its lanes over the right-hand sides (0: default)
     int trans_gi = 0;                             // its group table (group_args)
     int level_mfma = 0;                           // level steps on the matrix cores (complex64, autotuned)
+    int mfma_ends = 1;                            // near field, radiation and receive on the matrix cores
     double step_ms[2] = {0, 0};                   // timed level steps: vector, matrix cores
     double trans_ms = 0;                          // its timed translation, ms
 };
@@ -1541,8 +1542,8 @@ struct MvRun {
         const cpx<T> *vals = op == MLFMA_OP_EM ? P->near_em : P->near_c;
         const int *ids = op == MLFMA_OP_C ? c->id_start : nullptr;
         bool done = false;
-        if constexpr (std::is_same<T, float>::value)
-            done = launch_near_mfma(c->n_items, c->items, c->box_start, c->col_off, c->cols, c->val_off, vals, ids,
+        if (P->mfma_ends)
+            done = launch_near_mfma<T>(c->n_items, c->items, c->box_start, c->col_off, c->cols, c->val_off, vals, ids,
                                     c->id_col, P->id_w, X, Y, nrhs, sn);
         if (!done && nrhs == 1) {
             launch_near_tile<T>(c->n_items, c->items, c->box_start, c->col_off, c->cols, c->val_off, vals, ids,
@@ -1646,8 +1647,8 @@ void mv_begin(MvRun<T> &m, const cpx<T> *x, long long ldx)
         launch_radiate1_user<T>(m.op, Lf.nbox, Lf.K, c->box_start, P.R, x, c->perm, m.N, m.X, (cpx<T> *)w.U[leafl], st);
     } else if (m.far) {
         bool done = false;
-        if constexpr (std::is_same<T, float>::value)
-            done = launch_radiate_mfma(m.op, Lf.nbox, Lf.K, c->box_start, P.R, m.X, (cpx<T> *)w.U[leafl], nrhs, st);
+        if (P.mfma_ends)
+            done = launch_radiate_mfma<T>(m.op, Lf.nbox, Lf.K, c->box_start, P.R, m.X, (cpx<T> *)w.U[leafl], nrhs, st);
         if (!done) launch_radiate<T>(m.op, Lf.nbox, Lf.K, c->box_start, P.R, m.X, (cpx<T> *)w.U[leafl], nrhs, st);
     }
     if (m.overlap) {
@@ -1723,8 +1724,8 @@ void mv_end(MvRun<T> &m, cpx<T> *y, long long ldy)
         launch_receive1_user<T>(m.op, m.N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], m.Y, y, c->perm, st);
     } else if (m.far) {
         bool done = false;
-        if constexpr (std::is_same<T, float>::value)
-            done = launch_receive_mfma(m.op, c->n_items, c->items, Lf.K, c->box_start, P.R, P.Q, P.wq,
+        if (P.mfma_ends)
+            done = launch_receive_mfma<T>(m.op, c->n_items, c->items, Lf.K, c->box_start, P.R, P.Q, P.wq,
                                        (cpx<T> *)w.V[leafl], m.Y, nrhs, st);
         if (!done)
             launch_receive<T>(m.op, m.N, Lf.K, c->leaf_of, P.R, P.Q, P.wq, (cpx<T> *)w.V[leafl], m.Y, nrhs, st);

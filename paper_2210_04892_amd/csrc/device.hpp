@@ -255,19 +255,22 @@ bool launch_aggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s);
 template <class T>
 bool launch_disaggregate_step(const LevelStep<T> &a, int nrhs, hipStream_t s);
 
-// Radiation on the matrix cores (mfma.hip), complex float and at least 16
-// right-hand sides; return false otherwise
-bool launch_radiate_mfma(int op, int nbox, int K, const int *box_start, const cpx<float> *R, const cpx<float> *X,
-                         cpx<float> *U, int nrhs, hipStream_t s);
-// Near field and receive on the matrix cores (complex float, 16+ right-hand
-// sides).  items = (leaf box, row tile of 16 rows) pairs; cols[col_off[b] ..]
-// = the RWGs of leaf box b's adjacent boxes in block-row order.
+// Radiation on the matrix cores (mfma.hip): FP32 MFMAs for complex float,
+// FP64 MFMAs for complex double, at least 16 right-hand sides; return false
+// otherwise
+template <class T>
+bool launch_radiate_mfma(int op, int nbox, int K, const int *box_start, const cpx<T> *R, const cpx<T> *X, cpx<T> *U,
+                         int nrhs, hipStream_t s);
+// Near field and receive on the matrix cores (16+ right-hand sides).
+// items = (leaf box, row tile of 16 rows) pairs; cols[col_off[b] ..] = the
+// RWGs of leaf box b's adjacent boxes in block-row order.
+template <class T>
 bool launch_near_mfma(int nitem, const int2 *items, const int *box_start, const int *col_off, const int *cols,
-                      const long long *val_off, const cpx<float> *vals, const int *id_start, const int *id_col,
-                      const float *id_w, const cpx<float> *X, cpx<float> *Y, int nrhs, hipStream_t s);
-bool launch_receive_mfma(int op, int nitem, const int2 *items, int K, const int *box_start, const cpx<float> *R,
-                         const cpx<float> *Q, const float *wq, const cpx<float> *V, cpx<float> *Y, int nrhs,
-                         hipStream_t s);
+                      const long long *val_off, const cpx<T> *vals, const int *id_start, const int *id_col,
+                      const T *id_w, const cpx<T> *X, cpx<T> *Y, int nrhs, hipStream_t s);
+template <class T>
+bool launch_receive_mfma(int op, int nitem, const int2 *items, int K, const int *box_start, const cpx<T> *R,
+                         const cpx<T> *Q, const T *wq, const cpx<T> *V, cpx<T> *Y, int nrhs, hipStream_t s);
 
 // Outer GMRES vector kernels (krylov.hip); column-major blocks, element
 // (n, r) at r * ld + n; basis vector i of V starts at V + i * vstride.

@@ -5,10 +5,12 @@
 // pair):
 //   radiation  U_b[c](q, r) = sum_{n in b} alpha_n(r) R_n[c](q) + beta_n(r) (khat x R_n)[c](q)
 //   receive    y_(m,h)(r)   += sum_{c, q} P_(m,h)[c](q) V_b[c](q, r)
-// Each complex product is four real 16x16x4 FP32 MFMAs (real part: re*re and
-// -im*im, imaginary part: re*im and im*re).  Lane layout of
-// v_mfma_f32_16x16x4f32 (wave64): lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16] and holds D[(l / 16) * 4 + v][l % 16], v = 0..3.
+// Each complex product is four real 16x16x4 MFMAs (real part: re*re and
+// -im*im, imaginary part: re*im and im*re), FP32 for complex64 and FP64 for
+// complex128.  Lane layout (wave64, both checked on the device): lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; it holds D[(l / 16) * 4 +
+// v][l % 16] (v_mfma_f32_16x16x4f32) or D[l / 16 + 4 v][l % 16]
+// (v_mfma_f64_16x16x4f64), v = 0..3.
 #include "device.hpp"
 #include "../../include/mlfma.h"
 
@@ -16,9 +18,22 @@ namespace mlfma {
 
 namespace {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-__device__ inline f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+// the 16x16x4 matrix-core product of each precision and the D row that
+// accumulator slot v of lane group kk holds
+template <class T>
+struct Mf;
+template <>
+struct Mf<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int kk, int v) { return kk * 4 + v; }
+};
+template <>
+struct Mf<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 mma(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int kk, int v) { return kk + 4 * v; }
+};
 
 constexpr int NXCD_M = 8;
 __device__ inline long long xcd_block_m(long long nblk)
@@ -36,28 +51,29 @@ __device__ inline long long pidx_m(long long b, int c, int r, int q, int nrhs, i
 }
 
 // complex D += A B on RT accumulator pairs sharing the B operand
-template <int RT>
-__device__ inline void cmfma(f4 (&dre)[RT], f4 (&dim)[RT], const cpx<float> (&a)[RT], cpx<float> b)
+template <class T, int RT>
+__device__ inline void cmfma(typename Mf<T>::v4 (&dre)[RT], typename Mf<T>::v4 (&dim)[RT], const cpx<T> (&a)[RT],
+                             cpx<T> b)
 {
 #pragma unroll
-    for (int t = 0; t < RT; t++) dre[t] = mfma4(a[t].re, b.re, dre[t]);
+    for (int t = 0; t < RT; t++) dre[t] = Mf<T>::mma(a[t].re, b.re, dre[t]);
 #pragma unroll
-    for (int t = 0; t < RT; t++) dim[t] = mfma4(a[t].re, b.im, dim[t]);
+    for (int t = 0; t < RT; t++) dim[t] = Mf<T>::mma(a[t].re, b.im, dim[t]);
 #pragma unroll
-    for (int t = 0; t < RT; t++) dre[t] = mfma4(-a[t].im, b.im, dre[t]);
+    for (int t = 0; t < RT; t++) dre[t] = Mf<T>::mma(-a[t].im, b.im, dre[t]);
 #pragma unroll
-    for (int t = 0; t < RT; t++) dim[t] = mfma4(a[t].im, b.re, dim[t]);
+    for (int t = 0; t < RT; t++) dim[t] = Mf<T>::mma(a[t].im, b.re, dim[t]);
 }
 
 // Radiation.  Wave = (box, component c, tile of 16 samples) x RT tiles of 16
 // right-hand sides; D[i = rhs][j = sample], inner index k = (RWG, alpha|beta):
 // one MFMA step covers two RWGs.  EM pair: alpha = x1, beta = -x2; C block:
 // alpha = x2 / 2, beta = x1 / 2.
-template <int RT>
+template <class T, int RT>
 __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, int nqt,
                                                       const int *__restrict__ box_start,
-                                                      const cpx<float> *__restrict__ R,
-                                                      const cpx<float> *__restrict__ X, cpx<float> *__restrict__ U,
+                                                      const cpx<T> *__restrict__ R,
+                                                      const cpx<T> *__restrict__ X, cpx<T> *__restrict__ U,
                                                       int nrhs)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -76,13 +92,13 @@ __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, i
     const int s = kk & 1;
     // which half of X feeds this lane's alpha/beta, and its factor
     const int h = op == MLFMA_OP_EM ? s : 1 - s;
-    const float fac = op == MLFMA_OP_EM ? (s ? -1.0f : 1.0f) : 0.5f;
+    const T fac = op == MLFMA_OP_EM ? (s ? T(-1) : T(1)) : T(0.5);
     const int rcomp = s == 0 ? c : 1 - c;
-    const float rsg = (s == 1 && c == 0) ? -1.0f : 1.0f;
+    const T rsg = (s == 1 && c == 0) ? T(-1) : T(1);
     const int n0 = box_start[b], n1 = box_start[b + 1];
-    f4 dre[RT], dim[RT];
+    typename Mf<T>::v4 dre[RT], dim[RT];
 #pragma unroll
-    for (int u = 0; u < RT; u++) dre[u] = dim[u] = f4{0, 0, 0, 0};
+    for (int u = 0; u < RT; u++) dre[u] = dim[u] = typename Mf<T>::v4{0, 0, 0, 0};
     int n = n0;
     // steps with both RWGs inside the box: operands without predicates
     // (samples past K and right-hand sides past nrhs read clamped, valid
@@ -90,40 +106,40 @@ __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, i
     const int qq = qok ? q : K - 1;
     for (; n + 1 < n1; n += 2) {
         const int nn = n + (kk >> 1);
-        const cpx<float> v = R[((long long)nn * K + qq) * 2 + rcomp];
-        const cpx<float> bv = mk<float>(rsg * v.re, rsg * v.im);
-        cpx<float> av[RT];
+        const cpx<T> v = R[((long long)nn * K + qq) * 2 + rcomp];
+        const cpx<T> bv = mk<T>(rsg * v.re, rsg * v.im);
+        cpx<T> av[RT];
 #pragma unroll
         for (int u = 0; u < RT; u++) {
             const int r = min((rg * RT + u) * 16 + lo, nrhs - 1);
             av[u] = fac * X[((long long)nn * 2 + h) * nrhs + r];
         }
-        cmfma<RT>(dre, dim, av, bv);
+        cmfma<T, RT>(dre, dim, av, bv);
     }
     for (; n < n1; n += 2) {
         const int nn = n + (kk >> 1);
         const bool nok = nn < n1;
-        cpx<float> bv = mk<float>(0, 0);
+        cpx<T> bv = mk<T>(0, 0);
         if (nok && qok) {
             // alpha lanes take R[c]; beta lanes (khat x R)[c]: (-R_phi, R_theta)
-            const cpx<float> v = R[((long long)nn * K + q) * 2 + rcomp];
-            bv = mk<float>(rsg * v.re, rsg * v.im);
+            const cpx<T> v = R[((long long)nn * K + q) * 2 + rcomp];
+            bv = mk<T>(rsg * v.re, rsg * v.im);
         }
-        cpx<float> av[RT];
+        cpx<T> av[RT];
 #pragma unroll
         for (int u = 0; u < RT; u++) {
             const int r = (rg * RT + u) * 16 + lo;
-            av[u] = mk<float>(0, 0);
+            av[u] = mk<T>(0, 0);
             if (nok && r < nrhs) av[u] = fac * X[((long long)nn * 2 + h) * nrhs + r];
         }
-        cmfma<RT>(dre, dim, av, bv);
+        cmfma<T, RT>(dre, dim, av, bv);
     }
 #pragma unroll
     for (int u = 0; u < RT; u++)
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-            const int r = (rg * RT + u) * 16 + kk * 4 + v;
-            if (qok && r < nrhs) U[pidx_m(b, c, r, q, nrhs, K)] = mk<float>(dre[u][v], dim[u][v]);
+            const int r = (rg * RT + u) * 16 + Mf<T>::row(kk, v);
+            if (qok && r < nrhs) U[pidx_m(b, c, r, q, nrhs, K)] = mk<T>(dre[u][v], dim[u][v]);
         }
 }
 
@@ -138,11 +154,12 @@ __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, i
 // of the block takes sample 4 kk + u in every lane group: the same order of
 // the inner index for the A and B operands, so that each lane reads whole
 // runs of samples.  Two blocks are in flight while one is multiplied.
+template <class T>
 __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const int2 *__restrict__ items, int K,
                                                       const int *__restrict__ box_start,
-                                                      const cpx<float> *__restrict__ R,
-                                                      const cpx<float> *__restrict__ Q, const float *__restrict__ wq,
-                                                      const cpx<float> *__restrict__ V, cpx<float> *__restrict__ Y,
+                                                      const cpx<T> *__restrict__ R,
+                                                      const cpx<T> *__restrict__ Q, const T *__restrict__ wq,
+                                                      const cpx<T> *__restrict__ V, cpx<T> *__restrict__ Y,
                                                       int nrhs)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -156,24 +173,24 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
     const int b = it.x, tile = it.y;
     const int n0 = box_start[b], rows = 2 * (box_start[b + 1] - n0);
     const int lo = lane & 15, kk = lane >> 4;
-    const cpx<float> *pat = op == MLFMA_OP_EM ? R : Q;
+    const cpx<T> *pat = op == MLFMA_OP_EM ? R : Q;
     const bool cj = op == MLFMA_OP_EM;
     const int row = tile * 16 + lo, r = rt * 16 + lo;
     const bool mok = row < rows, rok = r < nrhs;
     const int h = row & 1;
-    const cpx<float> *pm = pat + (long long)(n0 + (mok ? row / 2 : 0)) * K * 2;
-    const cpx<float> *v0 = V + ((long long)(b * 2) * nrhs + (rok ? r : 0)) * K;
+    const cpx<T> *pm = pat + (long long)(n0 + (mok ? row / 2 : 0)) * K * 2;
+    const cpx<T> *v0 = V + ((long long)(b * 2) * nrhs + (rok ? r : 0)) * K;
     const long long vstep = (long long)nrhs * K;   // second component of V
     const int nblk = (K + 15) / 16;
     // the lane's A operand in component pass c is one component of its row's
     // pattern: theta for (h, c) = (0, 0), phi for (0, 1) and (1, 0), minus
     // theta for (1, 1)
     const int comp0 = h == 0 ? 0 : 1, comp1 = h == 0 ? 1 : 0;
-    const float sg1 = h == 1 ? -1.0f : 1.0f;
+    const T sg1 = h == 1 ? T(-1) : T(1);
     struct Blk {
-        cpx<float> q[4][2];   // pattern, samples x components
-        cpx<float> v[2][4];   // V, components x samples
-        float w[4];
+        cpx<T> q[4][2];   // pattern, samples x components
+        cpx<T> v[2][4];   // V, components x samples
+        T w[4];
     };
     auto load = [&](int bk, Blk &o) {
         const int q0 = bk * 16 + kk * 4;
@@ -181,57 +198,59 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 o.w[u] = wq[q0 + u];
-                o.q[u][0] = mok ? pm[2 * (q0 + u)] : mk<float>(0, 0);
-                o.q[u][1] = mok ? pm[2 * (q0 + u) + 1] : mk<float>(0, 0);
-                o.v[0][u] = rok ? v0[q0 + u] : mk<float>(0, 0);
-                o.v[1][u] = rok ? v0[vstep + q0 + u] : mk<float>(0, 0);
+                o.q[u][0] = mok ? pm[2 * (q0 + u)] : mk<T>(0, 0);
+                o.q[u][1] = mok ? pm[2 * (q0 + u) + 1] : mk<T>(0, 0);
+                o.v[0][u] = rok ? v0[q0 + u] : mk<T>(0, 0);
+                o.v[1][u] = rok ? v0[vstep + q0 + u] : mk<T>(0, 0);
             }
         } else {
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const int q = q0 + u;
                 const bool qok = q < K;
-                o.w[u] = qok ? wq[q] : 0.0f;
-                o.q[u][0] = mok && qok ? pm[2 * q] : mk<float>(0, 0);
-                o.q[u][1] = mok && qok ? pm[2 * q + 1] : mk<float>(0, 0);
-                o.v[0][u] = rok && qok ? v0[q] : mk<float>(0, 0);
-                o.v[1][u] = rok && qok ? v0[vstep + q] : mk<float>(0, 0);
+                o.w[u] = qok ? wq[q] : T(0);
+                o.q[u][0] = mok && qok ? pm[2 * q] : mk<T>(0, 0);
+                o.q[u][1] = mok && qok ? pm[2 * q + 1] : mk<T>(0, 0);
+                o.v[0][u] = rok && qok ? v0[q] : mk<T>(0, 0);
+                o.v[1][u] = rok && qok ? v0[vstep + q] : mk<T>(0, 0);
             }
         }
     };
-    f4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
-    // two blocks in flight: block bk + 2 is loaded while block bk is multiplied
+    typename Mf<T>::v4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+    // DEPTH blocks in flight: block bk + DEPTH is loaded while block bk is
+    // multiplied (one in double precision, where a block takes 72 registers)
+    constexpr int DEPTH = sizeof(T) == 8 ? 1 : 2;
     Blk b0, b1, b2;
     load(0, b0);
-    if (nblk > 1) load(1, b1);
+    if (DEPTH == 2 && nblk > 1) load(1, b1);
     auto mult = [&](const Blk &cur) {
 #pragma unroll
         for (int c = 0; c < 2; c++)
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const int cp = c == 0 ? comp0 : comp1;
-                cpx<float> p = cp ? cur.q[u][1] : cur.q[u][0];   // a select, not a dynamic register index
+                cpx<T> p = cp ? cur.q[u][1] : cur.q[u][0];   // a select, not a dynamic register index
                 if (cj) p = conjg(p);
-                const cpx<float> a = ((c == 1 ? sg1 : 1.0f) * cur.w[u]) * p;
-                const cpx<float> bv = cur.v[c][u];
-                dre = mfma4(a.re, bv.re, dre);
-                dim = mfma4(a.re, bv.im, dim);
-                dre = mfma4(-a.im, bv.im, dre);
-                dim = mfma4(a.im, bv.re, dim);
+                const cpx<T> a = ((c == 1 ? sg1 : T(1)) * cur.w[u]) * p;
+                const cpx<T> bv = cur.v[c][u];
+                dre = Mf<T>::mma(a.re, bv.re, dre);
+                dim = Mf<T>::mma(a.re, bv.im, dim);
+                dre = Mf<T>::mma(-a.im, bv.im, dre);
+                dim = Mf<T>::mma(a.im, bv.re, dim);
             }
     };
     for (int bk = 0; bk < nblk; bk++) {
-        if (bk + 2 < nblk) load(bk + 2, b2);
+        if (bk + DEPTH < nblk) load(bk + DEPTH, DEPTH == 2 ? b2 : b1);
         mult(b0);
         b0 = b1;
-        b1 = b2;
+        if (DEPTH == 2) b1 = b2;
     }
 #pragma unroll
     for (int v = 0; v < 4; v++) {
-        const int orow = tile * 16 + kk * 4 + v;
+        const int orow = tile * 16 + Mf<T>::row(kk, v);
         if (orow < rows && rok) {
-            cpx<float> &y = Y[((long long)(n0 + orow / 2) * 2 + (orow & 1)) * nrhs + r];
-            y = y + mk<float>(dre[v], dim[v]);
+            cpx<T> &y = Y[((long long)(n0 + orow / 2) * 2 + (orow & 1)) * nrhs + r];
+            y = y + mk<T>(dre[v], dim[v]);
         }
     }
 }
@@ -246,14 +265,15 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
 // MFMAs.  The 2 x 2 block of a pair is [[A, -B], [B, A]].  The identity
 // terms of the C block (Gram and rotated Gram, same triangle only) are added
 // in the epilogue; Y is overwritten.
+template <class T>
 __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__restrict__ items,
                                                    const int *__restrict__ box_start,
                                                    const int *__restrict__ col_off, const int *__restrict__ cols,
                                                    const long long *__restrict__ val_off,
-                                                   const cpx<float> *__restrict__ vals,
+                                                   const cpx<T> *__restrict__ vals,
                                                    const int *__restrict__ id_start, const int *__restrict__ id_col,
-                                                   const float *__restrict__ id_w, const cpx<float> *__restrict__ X,
-                                                   cpx<float> *__restrict__ Y, int nrhs)
+                                                   const T *__restrict__ id_w, const cpx<T> *__restrict__ X,
+                                                   cpx<T> *__restrict__ Y, int nrhs)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nrt = (nrhs + 15) / 16;
@@ -272,13 +292,13 @@ __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__rest
     const int row = tile * 16 + lo, r = rt * 16 + lo;
     const bool mok = row < rows, rok = r < nrhs;
     const int h = row & 1;
-    const cpx<float> *vr = vals + 2 * (val_off[b] + (long long)(mok ? row / 2 : 0) * ncols);
+    const cpx<T> *vr = vals + 2 * (val_off[b] + (long long)(mok ? row / 2 : 0) * ncols);
     const int vsel = h == hp ? 0 : 1;
-    const float vsg = (h == 0 && hp == 1) ? -1.0f : 1.0f;
+    const T vsg = (h == 0 && hp == 1) ? T(-1) : T(1);
     // column indices 64 at a time, one per lane, handed out by lane shuffles
     // (so the x load of a step does not wait for an index load)
     int cbase = -64, myc = 0;
-    auto load = [&](int j0, cpx<float> &a, cpx<float> &bv) {
+    auto load = [&](int j0, cpx<T> &a, cpx<T> &bv) {
         if (j0 >= cbase + 64) {              // j0 is even: a step never straddles two groups
             cbase = j0;
             myc = cl[min(cbase + lane, ncols - 1)];
@@ -286,22 +306,22 @@ __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__rest
         const int j = j0 + jc;
         const bool jok = j < ncols;
         const int col = __shfl(myc, j - cbase);
-        a = mk<float>(0, 0);
-        bv = mk<float>(0, 0);
+        a = mk<T>(0, 0);
+        bv = mk<T>(0, 0);
         if (jok && mok) {
             // [[A, -B], [B, A]]: the lane needs A on the diagonal, B (or -B) off it
-            const cpx<float> v = vr[2 * j + vsel];
-            a = mk<float>(vsg * v.re, vsg * v.im);
+            const cpx<T> v = vr[2 * j + vsel];
+            a = mk<T>(vsg * v.re, vsg * v.im);
         }
         if (jok && rok) bv = X[((long long)col * 2 + hp) * nrhs + r];
     };
-    f4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
-    cpx<float> a, bv, an, bn;
+    typename Mf<T>::v4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+    cpx<T> a, bv, an, bn;
     auto step = [&]() {
-        dre = mfma4(a.re, bv.re, dre);
-        dim = mfma4(a.re, bv.im, dim);
-        dre = mfma4(-a.im, bv.im, dre);
-        dim = mfma4(a.im, bv.re, dim);
+        dre = Mf<T>::mma(a.re, bv.re, dre);
+        dim = Mf<T>::mma(a.re, bv.im, dim);
+        dre = Mf<T>::mma(-a.im, bv.im, dre);
+        dim = Mf<T>::mma(a.im, bv.re, dim);
         a = an;
         bv = bn;
     };
@@ -319,8 +339,8 @@ __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__rest
             myc = cl[min(cbase + lane, ncols - 1)];
         }
         const int col = __shfl(myc, j - cbase);
-        const cpx<float> v = vr[2 * j + vsel];
-        an = mk<float>(vsg * v.re, vsg * v.im);
+        const cpx<T> v = vr[2 * j + vsel];
+        an = mk<T>(vsg * v.re, vsg * v.im);
         bn = X[((long long)col * 2 + hp) * nrhs + rc];
         step();
     }
@@ -330,20 +350,20 @@ __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__rest
     }
 #pragma unroll
     for (int v = 0; v < 4; v++) {
-        const int orow = tile * 16 + kk * 4 + v;
+        const int orow = tile * 16 + Mf<T>::row(kk, v);
         if (orow >= rows || !rok) continue;
         const int m = n0 + orow / 2, oh = orow & 1;
-        cpx<float> y = mk<float>(dre[v], dim[v]);
+        cpx<T> y = mk<T>(dre[v], dim[v]);
         if (id_start) {
             for (int e = id_start[m]; e < id_start[m + 1]; e++) {
                 const long long col = id_col[e];
-                const float g = id_w[2 * e], gx = id_w[2 * e + 1];
-                const cpx<float> x1 = X[(col * 2) * nrhs + r], x2 = X[(col * 2 + 1) * nrhs + r];
+                const T g = id_w[2 * e], gx = id_w[2 * e + 1];
+                const cpx<T> x1 = X[(col * 2) * nrhs + r], x2 = X[(col * 2 + 1) * nrhs + r];
                 if (oh == 0) {
                     axpy_to(y, g, x1);
-                    axpy_to(y, 0.5f * gx, x2);
+                    axpy_to(y, T(0.5) * gx, x2);
                 } else {
-                    axpy_to(y, 0.5f * g, x2);
+                    axpy_to(y, T(0.5) * g, x2);
                 }
             }
         }
@@ -353,43 +373,60 @@ __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__rest
 
 }  // namespace
 
+template <class T>
 bool launch_near_mfma(int nitem, const int2 *items, const int *box_start, const int *col_off, const int *cols,
-                      const long long *val_off, const cpx<float> *vals, const int *id_start, const int *id_col,
-                      const float *id_w, const cpx<float> *X, cpx<float> *Y, int nrhs, hipStream_t s)
+                      const long long *val_off, const cpx<T> *vals, const int *id_start, const int *id_col,
+                      const T *id_w, const cpx<T> *X, cpx<T> *Y, int nrhs, hipStream_t s)
 {
     if (nrhs < 16 || !items || !cols) return false;
     const long long nblk = ((long long)nitem * ((nrhs + 15) / 16) + 3) / 4;
     if (nblk <= 0) return true;
-    hipLaunchKernelGGL(k_near_mfma, dim3(xcd_grid_m(nblk)), dim3(256), 0, s, nitem, items, box_start, col_off, cols,
-                       val_off, vals, id_start, id_col, id_w, X, Y, nrhs);
+    hipLaunchKernelGGL(k_near_mfma<T>, dim3(xcd_grid_m(nblk)), dim3(256), 0, s, nitem, items, box_start, col_off,
+                       cols, val_off, vals, id_start, id_col, id_w, X, Y, nrhs);
     return true;
 }
 
-bool launch_radiate_mfma(int op, int nbox, int K, const int *box_start, const cpx<float> *R, const cpx<float> *X,
-                         cpx<float> *U, int nrhs, hipStream_t s)
+template <class T>
+bool launch_radiate_mfma(int op, int nbox, int K, const int *box_start, const cpx<T> *R, const cpx<T> *X, cpx<T> *U,
+                         int nrhs, hipStream_t s)
 {
     if (nrhs < 16) return false;
     const int nqt = (K + 15) / 16, per_box = (2 * nqt + 3) / 4;
-    const int rt = nrhs >= 64 ? 4 : (nrhs >= 32 ? 2 : 1);
+    // right-hand-side tiles per wave (the double-precision sums take twice the registers)
+    const int rt = sizeof(T) == 8 ? (nrhs >= 32 ? 2 : 1) : (nrhs >= 64 ? 4 : (nrhs >= 32 ? 2 : 1));
     const long long nblk = (long long)nbox * per_box * ((nrhs + 16 * rt - 1) / (16 * rt));
     if (nblk <= 0) return true;
     const dim3 grid(xcd_grid_m(nblk)), block(256);
-    if (rt == 4) hipLaunchKernelGGL(k_radiate_mfma<4>, grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
-    else if (rt == 2) hipLaunchKernelGGL(k_radiate_mfma<2>, grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
-    else hipLaunchKernelGGL(k_radiate_mfma<1>, grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
+    if (rt == 4)
+        hipLaunchKernelGGL((k_radiate_mfma<T, 4>), grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
+    else if (rt == 2)
+        hipLaunchKernelGGL((k_radiate_mfma<T, 2>), grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
+    else hipLaunchKernelGGL((k_radiate_mfma<T, 1>), grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
     return true;
 }
 
-bool launch_receive_mfma(int op, int nitem, const int2 *items, int K, const int *box_start, const cpx<float> *R,
-                         const cpx<float> *Q, const float *wq, const cpx<float> *V, cpx<float> *Y, int nrhs,
-                         hipStream_t s)
+template <class T>
+bool launch_receive_mfma(int op, int nitem, const int2 *items, int K, const int *box_start, const cpx<T> *R,
+                         const cpx<T> *Q, const T *wq, const cpx<T> *V, cpx<T> *Y, int nrhs, hipStream_t s)
 {
     if (nrhs < 16 || !items) return false;
     const long long nblk = ((long long)nitem * ((nrhs + 15) / 16) + 3) / 4;
     if (nblk <= 0) return true;
-    hipLaunchKernelGGL(k_receive_mfma, dim3(xcd_grid_m(nblk)), dim3(256), 0, s, op, nitem, items, K, box_start, R, Q,
-                       wq, V, Y, nrhs);
+    hipLaunchKernelGGL(k_receive_mfma<T>, dim3(xcd_grid_m(nblk)), dim3(256), 0, s, op, nitem, items, K, box_start, R,
+                       Q, wq, V, Y, nrhs);
     return true;
 }
+
+#define MFMA_INST(T)                                                                                                 \
+    template bool launch_near_mfma<T>(int, const int2 *, const int *, const int *, const int *, const long long *,    \
+                                      const cpx<T> *, const int *, const int *, const T *, const cpx<T> *, cpx<T> *,  \
+                                      int, hipStream_t);                                                              \
+    template bool launch_radiate_mfma<T>(int, int, int, const int *, const cpx<T> *, const cpx<T> *, cpx<T> *, int,   \
+                                         hipStream_t);                                                                \
+    template bool launch_receive_mfma<T>(int, int, const int2 *, int, const int *, const cpx<T> *, const cpx<T> *,    \
+                                         const T *, const cpx<T> *, cpx<T> *, int, hipStream_t);
+MFMA_INST(float)
+MFMA_INST(double)
+#undef MFMA_INST
 
 }  // namespace mlfma
