@@ -102,12 +102,17 @@ struct Prec {
     double trans_ms = 0;                          // its timed translation, ms
 };
 
+constexpr int NGROUP_TABLES = 4;
+// targets per group of group table gi
+inline int group_tg(int gi) { return gi == 0 ? 4 : (gi == 3 ? 16 : 8); }
+
 struct IntLevel {
-    // sibling groups of the register-blocked translation: 4 targets, 8
-    // targets, 8 targets of merged whole sibling sets
-    int g_ngroup[3] = {0, 0, 0};
-    int *g_first[3] = {}, *g_count[3] = {}, *g_rec[3] = {};
-    int *g_src[3] = {}, *g_off[3] = {};
+    // sibling groups of the translation: 4 targets, 8 targets, 8 targets of
+    // merged whole sibling sets (register-blocked kernel), 16 targets of
+    // merged whole sibling sets (matrix-core kernel)
+    int g_ngroup[NGROUP_TABLES] = {};
+    int *g_first[NGROUP_TABLES] = {}, *g_count[NGROUP_TABLES] = {}, *g_rec[NGROUP_TABLES] = {};
+    int *g_src[NGROUP_TABLES] = {}, *g_off[NGROUP_TABLES] = {};
     int *il_start = nullptr, *il_box = nullptr, *il_off = nullptr;
     int *child_start = nullptr, *parent = nullptr, *oct = nullptr;
     int *ath_s = nullptr, *ath_c = nullptr, *aph_s = nullptr, *aph_c = nullptr;
@@ -587,7 +592,7 @@ GroupArgs<T> group_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, 
 {
     const Tree &tr = c->tr;
     GroupArgs<T> ga;
-    ga.tg = gi == 0 ? 4 : 8;
+    ga.tg = group_tg(gi);
     ga.rb = rb;
     ga.rw = rw;
     for (int l = 2; l < tr.levels; l++) {
@@ -623,9 +628,10 @@ void launch_translation(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, 
 
 // Autotuner of the translation: every candidate of the LDS-tiled kernel
 // (targets per tile 4/8/16, LDS batch of 16/32/64 KB, 1/2/4 right-hand sides
-// per lane) that satisfies the kernel's limits, and of the sibling-group
-// kernel (4 or 8 targets per group, 1/2/4 right-hand sides per lane), is
-// timed on the device (HIP events, one warm-up and three timed launches of
+// per lane) that satisfies the kernel's limits and of the sibling-group
+// kernel (4 or 8 targets per group, lanes and right-hand sides per lane), or
+// with MLFMA_TRANS_MATRIX of the matrix-core kernel (16-target groups,
+// samples and column tiles per wave), is timed on the device (HIP events, one warm-up and three timed launches of
 // the translation of all levels with the right-hand-side count the handle
 // is built for, capped at 16); the fastest is kept.
 template <class T>
@@ -647,7 +653,7 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
     int bt = 0, bs = 0, bb = 1;
     for (int rb : {1, 2, 4}) {
         if (rb > 1 && (trans_rw(nrhs) != 4 || nrhs < 4 * rb)) continue;
-        if (c->opt.trans_kernel == MLFMA_TRANS_GROUPS) break;
+        if (c->opt.trans_kernel == MLFMA_TRANS_GROUPS || c->opt.trans_kernel == MLFMA_TRANS_MATRIX) break;
         for (int tmax : {4, 8, 16})
             for (int kb : {16, 32, 64}) {
                 const int smax = (kb * 1024) / (int)(2 * 64 * rb * sizeof(cpx<T>));
@@ -686,8 +692,8 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
     const int shapes[9][2] = {{1, 1}, {2, 1}, {4, 1}, {4, 2}, {4, 4}, {8, 1}, {8, 2}, {16, 1}, {2, 8}};
     for (int gi : {0, 1, 2})
         for (const auto &sh : shapes) {
-            if (c->opt.trans_kernel == MLFMA_TRANS_TILED) break;
-            const int tg = gi == 0 ? 4 : 8;
+            if (c->opt.trans_kernel == MLFMA_TRANS_TILED || c->opt.trans_kernel == MLFMA_TRANS_MATRIX) break;
+            const int tg = group_tg(gi);
             const int rw = sh[0], rb = sh[1];
             const int def = trans_rw(nrhs);
             if (!(rw == def && rb == 1) && (rw * rb > nrhs || rw * rb < def)) continue;
@@ -709,6 +715,35 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
                 bgi = gi;
             }
         }
+    // matrix-core kernel (16-target groups): (samples per wave, tiles of 16
+    // columns per wave); two column tiles only where there are two.  Timed
+    // only when asked for: on surface meshes a 16-target group's targets
+    // share few sources (36-44 % of the target x source operand is nonzero
+    // on a sphere of radius 8 wavelengths), so the matrix cores do 2-3x the
+    // useful work and the kernel is slower than the sibling-group one.
+    const int mshapes[4][2] = {{4, 1}, {8, 1}, {4, 2}, {8, 2}};
+    const int dshapes[3][2] = {{4, 1}, {4, 2}, {2, 2}};
+    for (int i = 0; i < (sizeof(T) == 4 ? 4 : 3); i++) {
+        if (c->opt.trans_kernel != MLFMA_TRANS_MATRIX) break;
+        const int qt = sizeof(T) == 4 ? mshapes[i][0] : dshapes[i][0];
+        const int ct = sizeof(T) == 4 ? mshapes[i][1] : dshapes[i][1];
+        if (ct == 2 && 2 * nrhs <= 16) continue;
+        const GroupArgs<T> ga = group_args<T>(c, P, c->ws, -1, 3, qt, ct);
+        if (!launch_translate_groups<T>(ga, nrhs, st)) throw Error(MLFMA_ERR_HIP, "invalid matrix-core translation shape");
+        HIPCHK(hipEventRecord(e0, st));
+        for (int k = 0; k < 3; k++) launch_translate_groups<T>(ga, nrhs, st);
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            bg = 16;
+            bb = qt;
+            bw = ct;
+            bgi = 3;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(st);
@@ -763,9 +798,9 @@ void build_device_tables(mlfma_ctx *c)
         I.il_off = c->upload(L.il_off);
         I.parent = c->upload(L.parent);
         I.oct = c->upload(L.child_oct);
-        for (int gi = 0; gi < 3; gi++) {
+        for (int gi = 0; gi < NGROUP_TABLES; gi++) {
             GroupTiles gt;
-            build_group_tiles(L, gi ? 8 : 4, gt, gi == 2);
+            build_group_tiles(L, group_tg(gi), gt, gi >= 2);
             I.g_ngroup[gi] = (int)gt.first.size();
             I.g_first[gi] = c->upload(gt.first);
             I.g_count[gi] = c->upload(gt.count);
@@ -2137,7 +2172,7 @@ void batch_fused(const mlfma_batch_item *items, int n, hipStream_t st)
     const int gi = PR.trans_group > 0 ? PR.trans_gi : 0, rb = PR.trans_group > 0 ? PR.trans_rb : 1;
     const int rw = PR.trans_group > 0 ? PR.trans_rw : 0;
     GroupArgs<T> ga;
-    ga.tg = gi == 0 ? 4 : 8;
+    ga.tg = group_tg(gi);
     ga.rb = rb;
     ga.rw = rw;
     auto flush = [&] {
@@ -2198,7 +2233,7 @@ int mlfma_build_tree(const double *verts, long long n_verts, const int *tris, lo
         if (opt) c->opt = *opt;
         else mlfma_options_default(&c->opt);
         if (c->opt.max_rhs < 1) throw Error(MLFMA_ERR_ARG, "max_rhs must be >= 1");
-        if (c->opt.trans_kernel < MLFMA_TRANS_AUTO || c->opt.trans_kernel > MLFMA_TRANS_GROUPS)
+        if (c->opt.trans_kernel < MLFMA_TRANS_AUTO || c->opt.trans_kernel > MLFMA_TRANS_MATRIX)
             throw Error(MLFMA_ERR_ARG, "unknown translation kernel");
         if (c->opt.level_kernel < MLFMA_LEVELS_AUTO || c->opt.level_kernel > MLFMA_LEVELS_PIPELINED)
             throw Error(MLFMA_ERR_ARG, "unknown level-step kernel");
@@ -2688,7 +2723,7 @@ int mlfma_tuning(mlfma_handle h, int dtype, int shape[4], double *ms)
     if (!h || !shape || (dtype != MLFMA_C128 && dtype != MLFMA_C64)) return fail(Error(MLFMA_ERR_ARG, "bad argument"));
     const int group = dtype == MLFMA_C64 ? h->p32.trans_group : h->p64.trans_group;
     shape[0] = group > 0 ? group : (dtype == MLFMA_C64 ? h->p32.trans_tmax : h->p64.trans_tmax);
-    const int merged = (dtype == MLFMA_C64 ? h->p32.trans_gi : h->p64.trans_gi) == 2;
+    const int merged = (dtype == MLFMA_C64 ? h->p32.trans_gi : h->p64.trans_gi) >= 2;
     shape[1] = group > 0 ? -merged : (dtype == MLFMA_C64 ? h->p32.trans_smax : h->p64.trans_smax);
     shape[2] = dtype == MLFMA_C64 ? h->p32.trans_rb : h->p64.trans_rb;
     shape[3] = group > 0 ? (dtype == MLFMA_C64 ? h->p32.trans_rw : h->p64.trans_rw) : 0;

@@ -12,28 +12,12 @@
 // v][l % 16] (v_mfma_f32_16x16x4f32) or D[l / 16 + 4 v][l % 16]
 // (v_mfma_f64_16x16x4f64), v = 0..3.
 #include "device.hpp"
+#include "mfma_ops.hpp"
 #include "../../include/mlfma.h"
 
 namespace mlfma {
 
 namespace {
-
-// the 16x16x4 matrix-core product of each precision and the D row that
-// accumulator slot v of lane group kk holds
-template <class T>
-struct Mf;
-template <>
-struct Mf<float> {
-    typedef float v4 __attribute__((ext_vector_type(4)));
-    static __device__ inline v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-    static __device__ inline int row(int kk, int v) { return kk * 4 + v; }
-};
-template <>
-struct Mf<double> {
-    typedef double v4 __attribute__((ext_vector_type(4)));
-    static __device__ inline v4 mma(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-    static __device__ inline int row(int kk, int v) { return kk + 4 * v; }
-};
 
 constexpr int NXCD_M = 8;
 __device__ inline long long xcd_block_m(long long nblk)

@@ -18,6 +18,7 @@
 // of each level: consecutive groups (Morton order) share sources through the
 // XCD's L2, and the operator rows of one sample chunk stay resident there.
 #include "device.hpp"
+#include "mfma_ops.hpp"
 
 namespace mlfma {
 
@@ -124,12 +125,166 @@ __global__ __launch_bounds__(GWAVES * WAVE) void k_translate_groups(const GroupA
     }
 }
 
+
+// Translation on the matrix cores, for groups of up to 16 targets (whole
+// sibling sets merged).  For one sample q a group's sums are a complex
+// product
+//   D[col][t] = sum_s U_s[col](q) T_{o(t, s)}(q),
+// col = (component, right-hand side) and s running over the union of the
+// targets' sources, four sources per MFMA step (T = 0 where s is not in
+// t's list).  A wave takes QT consecutive samples (one accumulator pair per
+// sample) and CT tiles of 16 columns; lane l feeds column and target l % 16
+// and source slot l / 16 of a step, and loads its QT samples of one U row
+// and one operator row as a run.  The next step's operands are loaded while
+// the current step's MFMAs run.  Workgroups are ordered as in the
+// sibling-group kernel (group innermost, every XCD a contiguous range).
+template <class T, int QT, int CT>
+__global__ __launch_bounds__(GWAVES * WAVE) void k_translate_mfma(const GroupArgs<T> a, int nrhs)
+{
+    typedef typename Mf<T>::v4 v4;
+    const int xcd = blockIdx.x % NXCD, pos = blockIdx.x / NXCD;
+    if (pos >= a.nblocks) return;
+    int l = 0;
+    while (l + 1 < a.nlev && pos >= a.lv[l + 1].first) l++;
+    const GroupLevel<T> &L = a.lv[l];
+    const int ncol = 2 * nrhs, nct = (ncol + 16 * CT - 1) / (16 * CT);
+    const int nblk = L.ngroup * nct * L.nqc, per = (nblk + NXCD - 1) / NXCD;
+    const int lb = xcd * per + (pos - L.first);
+    if (lb >= nblk) return;
+    const int g = lb % L.ngroup, rest = lb / L.ngroup;
+    const int ct = rest % nct, qc = rest / nct;
+    const int K = L.K;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int q0 = (qc * GWAVES + wave) * QT;
+    if (q0 >= K) return;
+    const bool full = q0 + QT <= K;
+    const int qlast = K - 1 - q0;   // last valid sample of the run
+    const int lo = lane & 15, kk = lane >> 4;
+    const long long S = (long long)ncol * K;   // one box's patterns
+    long long co[CT];   // this lane's column rows (clamped to a valid one)
+#pragma unroll
+    for (int c = 0; c < CT; c++) co[c] = (long long)min((ct * CT + c) * 16 + lo, ncol - 1) * K + q0;
+    const int t0 = ldu(L.first_tgt, g), nt = ldu(L.count, g);
+    const int r0 = ldu(L.rec_start, g), r1 = ldu(L.rec_start, g + 1);
+    v4 dre[CT][QT], dim[CT][QT];
+#pragma unroll
+    for (int c = 0; c < CT; c++)
+#pragma unroll
+        for (int u = 0; u < QT; u++) dre[c][u] = dim[c][u] = v4{0, 0, 0, 0};
+    cpx<T> un[CT][QT], tn[QT];
+    const int *srcp = L.src, *offp = L.off;
+    const cpx<T> *Ub = L.U, *Tb = L.trans + q0;
+    auto load = [&](int r) {
+        const int rec = r + kk;
+        const bool ok = rec < r1;
+        const int sb = srcp[ok ? rec : r0];
+        const int o = ok ? offp[(long long)rec * 16 + lo] : -1;
+        const cpx<T> *us = Ub + (long long)sb * S;
+        const cpx<T> *tp = Tb + (long long)max(o, 0) * K;
+        if (full) {
+#pragma unroll
+            for (int c = 0; c < CT; c++)
+#pragma unroll
+                for (int u = 0; u < QT; u++) un[c][u] = us[co[c] + u];
+#pragma unroll
+            for (int u = 0; u < QT; u++) tn[u] = tp[u];
+        } else {
+#pragma unroll
+            for (int c = 0; c < CT; c++)
+#pragma unroll
+                for (int u = 0; u < QT; u++) un[c][u] = us[co[c] + min(u, qlast)];
+#pragma unroll
+            for (int u = 0; u < QT; u++) tn[u] = tp[min(u, qlast)];
+        }
+        if (o < 0)
+#pragma unroll
+            for (int u = 0; u < QT; u++) tn[u] = mk<T>(0, 0);
+    };
+    if (r0 < r1) load(r0);
+    for (int r = r0; r < r1; r += 4) {
+        cpx<T> uc[CT][QT], tc[QT];
+#pragma unroll
+        for (int u = 0; u < QT; u++) {
+            tc[u] = tn[u];
+#pragma unroll
+            for (int c = 0; c < CT; c++) uc[c][u] = un[c][u];
+        }
+        if (r + 4 < r1) load(r + 4);
+#pragma unroll
+        for (int u = 0; u < QT; u++)
+#pragma unroll
+            for (int c = 0; c < CT; c++) dre[c][u] = Mf<T>::mma(uc[c][u].re, tc[u].re, dre[c][u]);
+#pragma unroll
+        for (int u = 0; u < QT; u++)
+#pragma unroll
+            for (int c = 0; c < CT; c++) dim[c][u] = Mf<T>::mma(uc[c][u].re, tc[u].im, dim[c][u]);
+#pragma unroll
+        for (int u = 0; u < QT; u++)
+#pragma unroll
+            for (int c = 0; c < CT; c++) dre[c][u] = Mf<T>::mma(-uc[c][u].im, tc[u].im, dre[c][u]);
+#pragma unroll
+        for (int u = 0; u < QT; u++)
+#pragma unroll
+            for (int c = 0; c < CT; c++) dim[c][u] = Mf<T>::mma(uc[c][u].im, tc[u].re, dim[c][u]);
+    }
+    if (lo >= nt) return;
+    cpx<T> *vt = L.V + (long long)(t0 + lo) * S + q0;
+#pragma unroll
+    for (int c = 0; c < CT; c++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int col = (ct * CT + c) * 16 + Mf<T>::row(kk, v);
+            if (col >= ncol) continue;
+#pragma unroll
+            for (int u = 0; u < QT; u++)
+                if (full || u <= qlast) vt[(long long)col * K + u] = mk<T>(dre[c][u][v], dim[c][u][v]);
+        }
+}
+
 }  // namespace
+
+
+// the matrix-core kernel: args.rb = samples per wave (QT), args.rw = tiles of
+// 16 columns per wave (CT)
+template <class T>
+bool launch_translate_mfma(const GroupArgs<T> &args, int nrhs, hipStream_t s)
+{
+    const int qt = args.rb, ct = args.rw;
+    const bool ok = sizeof(T) == 4 ? ((qt == 4 || qt == 8) && (ct == 1 || ct == 2))
+                                   : ((qt == 4 && (ct == 1 || ct == 2)) || (qt == 2 && ct == 2));
+    if (!ok) return false;
+    if (args.nlev <= 0 || nrhs <= 0) return true;
+    const int nct = (2 * nrhs + 16 * ct - 1) / (16 * ct);
+    GroupArgs<T> a = args;
+    a.nblocks = 0;
+    for (int l = 0; l < a.nlev; l++) {
+        a.lv[l].nqc = (a.lv[l].K + GWAVES * qt - 1) / (GWAVES * qt);
+        a.lv[l].first = a.nblocks;
+        a.nblocks += (a.lv[l].ngroup * nct * a.lv[l].nqc + NXCD - 1) / NXCD;
+    }
+    if (a.nblocks <= 0) return true;
+    const dim3 grid((unsigned)a.nblocks * NXCD), block(GWAVES * WAVE);
+#define MFMA_LAUNCH(QT_, CT_) hipLaunchKernelGGL((k_translate_mfma<T, QT_, CT_>), grid, block, 0, s, a, nrhs)
+    if constexpr (sizeof(T) == 4) {
+        if (qt == 8 && ct == 2) MFMA_LAUNCH(8, 2);
+        else if (qt == 8) MFMA_LAUNCH(8, 1);
+        else if (ct == 2) MFMA_LAUNCH(4, 2);
+        else MFMA_LAUNCH(4, 1);
+    } else {
+        if (qt == 2) MFMA_LAUNCH(2, 2);
+        else if (ct == 2) MFMA_LAUNCH(4, 2);
+        else MFMA_LAUNCH(4, 1);
+    }
+#undef MFMA_LAUNCH
+    return true;
+}
 
 template <class T>
 bool launch_translate_groups(const GroupArgs<T> &args, int nrhs, hipStream_t s)
 {
     const int tg = args.tg;
+    if (tg == 16) return launch_translate_mfma<T>(args, nrhs, s);
     int rb = args.rb, rw = args.rw > 0 ? args.rw : trans_rw(nrhs);
     if (tg != 4 && tg != 8) return false;
     // (lanes over the RHS, RHS per lane) with a kernel

@@ -207,13 +207,14 @@ def test_sphere_r8_2000_rows_per_level():
         assert own <= LEVEL_OWN_TOL
 
 
-@pytest.mark.parametrize("kernel", ["tiled", "groups"])
+@pytest.mark.parametrize("kernel", ["tiled", "groups", "matrix"])
 def test_translation_kernels(kernel):
-    """Both translation kernels, forced in turn (the autotuner otherwise picks
-    one per handle): the whole product against the oracle for 1, 3 and 20
-    right-hand sides in both precisions and both operators, and the far
-    field of the two kernels against each other (same sums in another
-    order: agreement to rounding)."""
+    """The three translation kernels, forced in turn (the autotuner otherwise
+    picks one per handle): the whole product against the oracle for 1, 3 and
+    20 right-hand sides (20: column tiles of the matrix-core kernel cut
+    short) in both precisions and both operators, and the far field against
+    that of another kernel (same sums in another order: agreement to
+    rounding)."""
     torch = _torch()
     import paper_2210_04892_amd as mf
     name = "sphere_r0.5"
@@ -221,7 +222,10 @@ def test_translation_kernels(kernel):
     g = mf.Geometry(v, t, k=K0, max_rhs=20, trans_kernel=kernel).precompute()
     other = mf.Geometry(v, t, k=K0, max_rhs=20, trans_kernel="groups" if kernel == "tiled" else "tiled").precompute()
     sh = g.tuning()
-    assert (sh["c64"][1] <= 0) == (kernel == "groups") and (sh["c128"][1] <= 0) == (kernel == "groups")
+    grouped = kernel != "tiled"
+    assert (sh["c64"][1] <= 0) == grouped and (sh["c128"][1] <= 0) == grouped
+    for d in ("c64", "c128"):
+        assert (sh[d][0] == 16 and sh[d][1] <= 0) == (kernel == "matrix")
     for nrhs in (1, 3, 20):
         x, rows, ref = reference(name, 192, nrhs, 5)
         N = x.shape[0] // 2
