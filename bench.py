@@ -48,7 +48,7 @@ def parse():
     p.add_argument("--leaf-extra", type=int, default=2, help="extra multipoles at the leaf level")
     p.add_argument("--interp-order", type=int, default=8, help="Lagrange points per angle")
     p.add_argument("--digits", type=int, default=3, help="MLFMA accuracy parameter d0")
-    p.add_argument("--trans-kernel", default="auto", choices=["auto", "tiled", "groups", "matrix"],
+    p.add_argument("--trans-kernel", default="auto", choices=["auto", "tiled", "groups", "matrix", "lds"],
                    help="translation kernel (default: the autotuner's pick)")
     p.add_argument("--level-kernel", default="auto", choices=["auto", "vector", "matrix", "blocked", "pipelined"],
                    help="complex64 level-step kernels (default: the autotuner's pick)")

@@ -79,13 +79,21 @@ typedef struct {
  * other part in FP64). */
 enum { MLFMA_PREC_DTYPE = 0, MLFMA_PREC_FP64 = 1, MLFMA_PREC_FP32 = 2 };
 /* Translation kernels.  TILED: LDS tiles of targets; GROUPS: sibling groups
- * with the sums in registers (vector FMAs); AUTO: the autotuner times the
- * shapes of both and keeps the fastest; MATRIX: groups of 16 targets whose
- * sums per sample are a complex product on the matrix cores (FP32 MFMAs for
- * complex64, FP64 for complex128), its shapes timed.  MATRIX pays where the
- * targets of a group share most of their sources (volumes); on surface
- * meshes most of its operand is zero and GROUPS is faster. */
-enum { MLFMA_TRANS_AUTO = 0, MLFMA_TRANS_TILED = 1, MLFMA_TRANS_GROUPS = 2, MLFMA_TRANS_MATRIX = 3 };
+ * with the sums in registers (vector FMAs), the operator values loaded per
+ * lane or staged in LDS per workgroup; LDS: only the latter; AUTO: the
+ * autotuner times the shapes of TILED and GROUPS and keeps the fastest;
+ * MATRIX: groups of 16 targets whose sums per sample are a complex product
+ * on the matrix cores (FP32 MFMAs for complex64, FP64 for complex128), its
+ * shapes timed.  MATRIX pays where the targets of a group share most of
+ * their sources (volumes); on surface meshes most of its operand is zero and
+ * GROUPS is faster. */
+enum {
+    MLFMA_TRANS_AUTO = 0,
+    MLFMA_TRANS_TILED = 1,
+    MLFMA_TRANS_GROUPS = 2,
+    MLFMA_TRANS_MATRIX = 3,
+    MLFMA_TRANS_LDS = 4
+};
 /* Level-step kernels.  AUTO: the autotuner picks (complex64: vector or
  * matrix cores; the vector kernels' shape per level and precision).  VECTOR:
  * vector kernels of autotuned shape.  MATRIX: complex64 steps on the matrix
@@ -465,9 +473,10 @@ int mlfma_near_info(mlfma_handle h, long long info[4]);
  * sides per lane, shape[3] = 0.  Sibling-group kernel (sums of all targets
  * of a group of siblings kept in registers, sources streamed once per
  * group): shape[0] = targets per group, shape[1] = 0 (a group is one sibling
- * set or part of one) or -1 (whole sibling sets merged up to shape[0]
- * targets), shape[2] = right-hand sides per lane, shape[3] = lanes of a
- * wavefront over the right-hand sides.  Matrix-core kernel: shape[0] = 16,
+ * set or part of one), -1 (whole sibling sets merged up to shape[0]
+ * targets) or -2 (merged, and a workgroup of four groups stages the
+ * translation operators of its sample chunk in LDS), shape[2] = right-hand
+ * sides per lane, shape[3] = lanes of a wavefront over the right-hand sides.  Matrix-core kernel: shape[0] = 16,
  * shape[1] = -1, shape[2] = samples per wavefront, shape[3] = tiles of 16
  * (component, right-hand side) columns per wavefront.  *ms (may be NULL) =
  * the timed translation of all levels, milliseconds.  dtype MLFMA_C128 or

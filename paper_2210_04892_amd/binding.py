@@ -135,7 +135,7 @@ class Geometry:
                  max_rhs=1, device=None, hbm_budget_bytes=0, trans_kernel="auto", level_kernel="auto",
                  near_precision="fp64", far_precision="fp64"):
         o = default_options()
-        o.trans_kernel = {"auto": 0, "tiled": 1, "groups": 2, "matrix": 3}[trans_kernel]
+        o.trans_kernel = {"auto": 0, "tiled": 1, "groups": 2, "matrix": 3, "lds": 4}[trans_kernel]
         o.level_kernel = {"auto": 0, "vector": 1, "matrix": 2, "blocked": 3, "pipelined": 4}[level_kernel]
         # arithmetic of the near and far parts of complex128 products
         o.near_precision = {"fp64": 1, "fp32": 2}[near_precision]

@@ -96,6 +96,7 @@ struct Prec {
     int trans_group = 0;                          // > 0: sibling-group kernel with this many targets per group
     int trans_rw = 0;                             // its lanes over the right-hand sides (0: default)
     int trans_gi = 0;                             // its group table (group_args)
+    int trans_lds = 0;                            // 1: its operator values staged in LDS
     int level_mfma = 0;                           // level steps on the matrix cores (complex64, autotuned)
     int mfma_ends = 1;                            // near field, radiation and receive on the matrix cores
     double step_ms[2] = {0, 0};                   // timed level steps: vector, matrix cores
@@ -588,13 +589,14 @@ TransArgs<T> trans_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level)
 // arguments of the sibling-group translation with group table gi (0: 4
 // targets, 1: 8 targets, 2: 8 targets of merged sibling sets)
 template <class T>
-GroupArgs<T> group_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, int gi, int rb, int rw)
+GroupArgs<T> group_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, int gi, int rb, int rw, int lds = 0)
 {
     const Tree &tr = c->tr;
     GroupArgs<T> ga;
     ga.tg = group_tg(gi);
     ga.rb = rb;
     ga.rw = rw;
+    ga.lds = lds;
     for (int l = 2; l < tr.levels; l++) {
         if (only_level >= 0 && l != only_level) continue;
         const IntLevel &I = c->lv[l];
@@ -618,7 +620,7 @@ template <class T>
 void launch_translation(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, int nrhs, hipStream_t st)
 {
     if (P.trans_group > 0) {
-        if (!launch_translate_groups<T>(group_args<T>(c, P, w, only_level, P.trans_gi, P.trans_rb, P.trans_rw),
+        if (!launch_translate_groups<T>(group_args<T>(c, P, w, only_level, P.trans_gi, P.trans_rb, P.trans_rw, P.trans_lds),
                                         nrhs, st))
             throw Error(MLFMA_ERR_STATE, "invalid sibling-group translation shape");
     } else if (!launch_translate_tiled<T>(trans_args<T>(c, P, w, only_level), nrhs, st)) {
@@ -653,7 +655,7 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
     int bt = 0, bs = 0, bb = 1;
     for (int rb : {1, 2, 4}) {
         if (rb > 1 && (trans_rw(nrhs) != 4 || nrhs < 4 * rb)) continue;
-        if (c->opt.trans_kernel == MLFMA_TRANS_GROUPS || c->opt.trans_kernel == MLFMA_TRANS_MATRIX) break;
+        if (c->opt.trans_kernel != MLFMA_TRANS_AUTO && c->opt.trans_kernel != MLFMA_TRANS_TILED) break;
         for (int tmax : {4, 8, 16})
             for (int kb : {16, 32, 64}) {
                 const int smax = (kb * 1024) / (int)(2 * 64 * rb * sizeof(cpx<T>));
@@ -686,13 +688,13 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
                 }
             }
     }
-    int bg = 0, bw = 0, bgi = 0;
+    int bg = 0, bw = 0, bgi = 0, blds = 0;
     // sibling-group shapes: (lanes over the RHS, RHS per lane) within the
     // handle's right-hand sides (the default lane split always)
     const int shapes[9][2] = {{1, 1}, {2, 1}, {4, 1}, {4, 2}, {4, 4}, {8, 1}, {8, 2}, {16, 1}, {2, 8}};
     for (int gi : {0, 1, 2})
         for (const auto &sh : shapes) {
-            if (c->opt.trans_kernel == MLFMA_TRANS_TILED || c->opt.trans_kernel == MLFMA_TRANS_MATRIX) break;
+            if (c->opt.trans_kernel != MLFMA_TRANS_AUTO && c->opt.trans_kernel != MLFMA_TRANS_GROUPS) break;
             const int tg = group_tg(gi);
             const int rw = sh[0], rb = sh[1];
             const int def = trans_rw(nrhs);
@@ -713,6 +715,34 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
                 bb = rb;
                 bw = rw;
                 bgi = gi;
+                blds = 0;
+            }
+        }
+    // the same with the operator values staged in LDS (merged groups of 8 or
+    // 16 targets; shapes without a kernel are skipped)
+    const int lshapes[4][2] = {{4, 4}, {8, 2}, {16, 1}, {8, 1}};
+    for (int gi : {2, 3})
+        for (const auto &sh : lshapes) {
+            if (c->opt.trans_kernel != MLFMA_TRANS_AUTO && c->opt.trans_kernel != MLFMA_TRANS_GROUPS &&
+                c->opt.trans_kernel != MLFMA_TRANS_LDS)
+                break;
+            const int rw = sh[0], rb = sh[1];
+            if (rw * rb > nrhs && !(rw == trans_rw(nrhs) && rb == 1)) continue;
+            const GroupArgs<T> ga = group_args<T>(c, P, c->ws, -1, gi, rb, rw, 1);
+            if (!launch_translate_groups<T>(ga, nrhs, st)) continue;
+            HIPCHK(hipEventRecord(e0, st));
+            for (int i = 0; i < 3; i++) launch_translate_groups<T>(ga, nrhs, st);
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bg = group_tg(gi);
+                bb = rb;
+                bw = rw;
+                bgi = gi;
+                blds = 1;
             }
         }
     // matrix-core kernel (16-target groups): (samples per wave, tiles of 16
@@ -742,6 +772,7 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
             bb = qt;
             bw = ct;
             bgi = 3;
+            blds = 0;
         }
     }
     (void)hipEventDestroy(e0);
@@ -754,6 +785,7 @@ void tune_translation(mlfma_ctx *c, Prec<T> &P)
         P.trans_group = bg;
         P.trans_rw = bw;
         P.trans_gi = bgi;
+        P.trans_lds = blds;
     } else {
         upload_trans_tiles<T>(c, P, bt, bs, nullptr);
         P.trans_group = 0;
@@ -2170,11 +2202,12 @@ void batch_fused(const mlfma_batch_item *items, int n, hipStream_t st)
     }
     const Prec<T> &PR = prec_of<T>(items[ref].h);
     const int gi = PR.trans_group > 0 ? PR.trans_gi : 0, rb = PR.trans_group > 0 ? PR.trans_rb : 1;
-    const int rw = PR.trans_group > 0 ? PR.trans_rw : 0;
+    const int rw = PR.trans_group > 0 ? PR.trans_rw : 0, lds = PR.trans_group > 0 ? PR.trans_lds : 0;
     GroupArgs<T> ga;
     ga.tg = group_tg(gi);
     ga.rb = rb;
     ga.rw = rw;
+    ga.lds = lds;
     auto flush = [&] {
         if (ga.nlev > 0 && !launch_translate_groups<T>(ga, nrhs, st))
             throw Error(MLFMA_ERR_STATE, "invalid sibling-group translation shape");
@@ -2183,7 +2216,7 @@ void batch_fused(const mlfma_batch_item *items, int n, hipStream_t st)
     for (int i = 0; i < n; i++) {
         if (!runs[i].far) continue;
         mlfma_ctx *h = items[i].h;
-        const GroupArgs<T> one = group_args<T>(h, prec_of<T>(h), h->ws, -1, gi, rb, rw);
+        const GroupArgs<T> one = group_args<T>(h, prec_of<T>(h), h->ws, -1, gi, rb, rw, lds);
         for (int l = 0; l < one.nlev; l++) {
             if (ga.nlev == TRANS_MAXLEV) flush();
             ga.lv[ga.nlev++] = one.lv[l];
@@ -2233,7 +2266,7 @@ int mlfma_build_tree(const double *verts, long long n_verts, const int *tris, lo
         if (opt) c->opt = *opt;
         else mlfma_options_default(&c->opt);
         if (c->opt.max_rhs < 1) throw Error(MLFMA_ERR_ARG, "max_rhs must be >= 1");
-        if (c->opt.trans_kernel < MLFMA_TRANS_AUTO || c->opt.trans_kernel > MLFMA_TRANS_MATRIX)
+        if (c->opt.trans_kernel < MLFMA_TRANS_AUTO || c->opt.trans_kernel > MLFMA_TRANS_LDS)
             throw Error(MLFMA_ERR_ARG, "unknown translation kernel");
         if (c->opt.level_kernel < MLFMA_LEVELS_AUTO || c->opt.level_kernel > MLFMA_LEVELS_PIPELINED)
             throw Error(MLFMA_ERR_ARG, "unknown level-step kernel");
@@ -2724,7 +2757,8 @@ int mlfma_tuning(mlfma_handle h, int dtype, int shape[4], double *ms)
     const int group = dtype == MLFMA_C64 ? h->p32.trans_group : h->p64.trans_group;
     shape[0] = group > 0 ? group : (dtype == MLFMA_C64 ? h->p32.trans_tmax : h->p64.trans_tmax);
     const int merged = (dtype == MLFMA_C64 ? h->p32.trans_gi : h->p64.trans_gi) >= 2;
-    shape[1] = group > 0 ? -merged : (dtype == MLFMA_C64 ? h->p32.trans_smax : h->p64.trans_smax);
+    const int lds = dtype == MLFMA_C64 ? h->p32.trans_lds : h->p64.trans_lds;
+    shape[1] = group > 0 ? (lds ? -2 : -merged) : (dtype == MLFMA_C64 ? h->p32.trans_smax : h->p64.trans_smax);
     shape[2] = dtype == MLFMA_C64 ? h->p32.trans_rb : h->p64.trans_rb;
     shape[3] = group > 0 ? (dtype == MLFMA_C64 ? h->p32.trans_rw : h->p64.trans_rw) : 0;
     if (ms) *ms = dtype == MLFMA_C64 ? h->p32.trans_ms : h->p64.trans_ms;

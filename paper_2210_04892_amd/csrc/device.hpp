@@ -176,6 +176,7 @@ template <class T>
 struct GroupArgs {
     int nlev = 0, nblocks = 0, tg = 4, rb = 1;   // tg: targets per group (4 or 8); rb: RHS per lane
     int rw = 0;                                  // lanes over the RHS (1, 2, 4, 8, 16; 0: trans_rw(nrhs))
+    int lds = 0;                                 // 1: operator values staged in LDS (k_translate_lds)
     GroupLevel<T> lv[TRANS_MAXLEV];
 };
 // false when (tg, rw, rb) has no kernel

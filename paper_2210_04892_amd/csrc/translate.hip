@@ -31,6 +31,28 @@ constexpr int GWAVES = 4;
 typedef const __attribute__((address_space(4))) int cint_g;
 __device__ inline int ldu(const int *p, int i) { return ((cint_g *)p)[i]; }
 
+// Raw buffer loads: a resource descriptor for a uniform base address (no
+// range check: every offset used lies inside the array) and a per-lane
+// 32-bit byte offset, so that a loop's loads need no 64-bit vector address
+// arithmetic.  Descriptor word 3 = 0x00020000 (the gfx9 family's 32-bit
+// data format, no swizzle).
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void *base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, -1, 0x00020000);
+}
+template <class T>
+__device__ inline cpx<T> bload(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ inline cpx<float> bload<float>(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(cpx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ inline cpx<double> bload<double>(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(cpx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
 template <class T, int TG, int RW, int RB>
 __global__ __launch_bounds__(GWAVES * WAVE) void k_translate_groups(const GroupArgs<T> a, int nrhs)
 {
@@ -53,62 +75,68 @@ __global__ __launch_bounds__(GWAVES * WAVE) void k_translate_groups(const GroupA
     const int qr = qok ? q : K - 1;   // lanes past the last sample read a valid element, store nothing
     const int rbase = blockIdx.y * RW * RB + ri;
     const long long S = 2LL * nrhs * K;   // one box's patterns
-    long long ro[RB];
-#pragma unroll
-    for (int j = 0; j < RB; j++) ro[j] = (long long)min(rbase + j * RW, nrhs - 1) * K + qr;
     const long long half = (long long)nrhs * K;   // second component
+    // per-lane byte offsets within a box's patterns and within an operator
+    // row: every load takes a uniform 64-bit base (scalar registers, from
+    // the record's source and offset ids) and one of these 32-bit offsets
+    unsigned rob[RB];
+#pragma unroll
+    for (int j = 0; j < RB; j++)
+        rob[j] = (unsigned)(((long long)min(rbase + j * RW, nrhs - 1) * K + qr) * (long long)sizeof(cpx<T>));
+    const unsigned qb = (unsigned)(qr * sizeof(cpx<T>));
     const int t0 = ldu(L.first_tgt, g), nt = ldu(L.count, g);
     const int r0 = ldu(L.rec_start, g), r1 = ldu(L.rec_start, g + 1);
-    const cpx<T> *tq = L.trans + qr;
     cpx<T> acc[TG][2][RB];
 #pragma unroll
     for (int t = 0; t < TG; t++)
 #pragma unroll
         for (int j = 0; j < RB; j++) acc[t][0][j] = acc[t][1][j] = mk<T>(0, 0);
-    // the next record (its source samples, operator values and offsets) is
-    // loaded while the current one is summed, so that the wait for its data
-    // does not also wait for loads issued in the same iteration
-    cpx<T> u0[RB], u1[RB], opn[TG];
-    int offn[TG];
+    // a record: its source's samples, the group's operator values and offset
+    // ids; the next record is loaded while the current one is summed (two
+    // register sets used in turn)
+    struct Rec {
+        cpx<T> u0[RB], u1[RB], op[TG];
+        int off[TG];
+    };
     const int *srcp = L.src, *offp = L.off;
-    const cpx<T> *Ub = L.U;
-    auto load = [&](int r) {
+    const cpx<T> *Ub = L.U, *Tb = L.trans;
+    auto load = [&](int r, Rec &o) {
         const cpx<T> *us = Ub + (long long)ldu(srcp, r) * S;
+        const auto ru0 = rsrc(us), ru1 = rsrc(us + half);
 #pragma unroll
         for (int j = 0; j < RB; j++) {
-            u0[j] = us[ro[j]];
-            u1[j] = us[half + ro[j]];
+            o.u0[j] = bload<T>(ru0, rob[j]);
+            o.u1[j] = bload<T>(ru1, rob[j]);
         }
 #pragma unroll
         for (int t = 0; t < TG; t++) {
-            offn[t] = ldu(offp, r * TG + t);
-            opn[t] = tq[(long long)max(offn[t], 0) * K];   // a valid row also where the source is absent
+            o.off[t] = ldu(offp, r * TG + t);
+            // a valid row also where the source is absent
+            o.op[t] = bload<T>(rsrc(Tb + (long long)max(o.off[t], 0) * K), qb);
         }
     };
-    if (r0 < r1) load(r0);
-    for (int r = r0; r < r1; r++) {
-        cpx<T> v0[RB], v1[RB], op[TG];
-        int off[TG];
-#pragma unroll
-        for (int j = 0; j < RB; j++) {
-            v0[j] = u0[j];
-            v1[j] = u1[j];
-        }
+    auto sum = [&](const Rec &c) {
 #pragma unroll
         for (int t = 0; t < TG; t++) {
-            op[t] = opn[t];
-            off[t] = offn[t];
-        }
-        if (r + 1 < r1) load(r + 1);
-#pragma unroll
-        for (int t = 0; t < TG; t++) {
-            if (off[t] < 0) continue;   // uniform: the source is not in target t's list
+            if (c.off[t] < 0) continue;   // uniform: the source is not in target t's list
 #pragma unroll
             for (int j = 0; j < RB; j++) {
-                fma_to(acc[t][0][j], op[t], v0[j]);
-                fma_to(acc[t][1][j], op[t], v1[j]);
+                fma_to(acc[t][0][j], c.op[t], c.u0[j]);
+                fma_to(acc[t][1][j], c.op[t], c.u1[j]);
             }
         }
+    };
+    // the loads of the next record are issued on every path (past the last
+    // record they repeat it), so that the wait before a sum counts the other
+    // set's loads as in flight instead of merging with a path without them
+    Rec ra, rb2;
+    if (r0 < r1) load(r0, ra);
+    for (int r = r0; r < r1; r += 2) {
+        load(min(r + 1, r1 - 1), rb2);
+        sum(ra);
+        if (r + 1 >= r1) break;
+        load(min(r + 2, r1 - 1), ra);
+        sum(rb2);
     }
     if (!qok) return;
 #pragma unroll
@@ -125,6 +153,114 @@ __global__ __launch_bounds__(GWAVES * WAVE) void k_translate_groups(const GroupA
     }
 }
 
+
+// The sibling-group kernel with the operator values in LDS.  A workgroup
+// takes four consecutive groups (one per wave) at one chunk of QW samples and
+// first stages the operator rows of all 343 offsets for that chunk in LDS
+// (343 QW complex values); the record loop then loads only source samples
+// through the vector memory path and reads each present target's operator
+// value from LDS.  Summing, record prefetch and stores are those of
+// k_translate_groups.
+template <class T, int TG, int RW, int RB>
+__global__ __launch_bounds__(GWAVES * WAVE) void k_translate_lds(const GroupArgs<T> a, int nrhs)
+{
+    constexpr int QW = WAVE / RW;
+    __shared__ cpx<T> tl[343 * QW];
+    const int xcd = blockIdx.x % NXCD, pos = blockIdx.x / NXCD;
+    if (pos >= a.nblocks) return;
+    int l = 0;
+    while (l + 1 < a.nlev && pos >= a.lv[l + 1].first) l++;
+    const GroupLevel<T> &L = a.lv[l];
+    const int ngb = (L.ngroup + GWAVES - 1) / GWAVES;
+    const int nblk = ngb * L.nqc, per = (nblk + NXCD - 1) / NXCD;
+    const int lb = xcd * per + (pos - L.first);
+    if (lb >= nblk) return;
+    const int gb = lb % ngb, qc = lb / ngb;
+    const int K = L.K, q0 = qc * QW;
+    // stage the chunk's operator rows (samples past K as zeros)
+    for (int i = threadIdx.x; i < 343 * QW; i += GWAVES * WAVE) {
+        const int o = i / QW, qq = q0 + i % QW;
+        tl[i] = qq < K ? L.trans[(long long)o * K + qq] : mk<T>(0, 0);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int g = gb * GWAVES + wave;
+    if (g >= L.ngroup) return;
+    const int qi = lane % QW, ri = lane / QW;
+    const int q = q0 + qi;
+    const bool qok = q < K;
+    const int qr = qok ? q : K - 1;   // lanes past the last sample read a valid element, store nothing
+    const int rbase = blockIdx.y * RW * RB + ri;
+    const long long S = 2LL * nrhs * K;   // one box's patterns
+    const long long half = (long long)nrhs * K;   // second component
+    unsigned rob[RB];
+#pragma unroll
+    for (int j = 0; j < RB; j++)
+        rob[j] = (unsigned)(((long long)min(rbase + j * RW, nrhs - 1) * K + qr) * (long long)sizeof(cpx<T>));
+    const int t0 = ldu(L.first_tgt, g), nt = ldu(L.count, g);
+    const int r0 = ldu(L.rec_start, g), r1 = ldu(L.rec_start, g + 1);
+    cpx<T> acc[TG][2][RB];
+#pragma unroll
+    for (int t = 0; t < TG; t++)
+#pragma unroll
+        for (int j = 0; j < RB; j++) acc[t][0][j] = acc[t][1][j] = mk<T>(0, 0);
+    struct Rec {
+        cpx<T> u0[RB], u1[RB];
+        int off[TG];
+    };
+    const int *srcp = L.src, *offp = L.off;
+    const cpx<T> *Ub = L.U;
+    const cpx<T> *tq = tl + qi;
+    auto load = [&](int r, Rec &o) {
+        const cpx<T> *us = Ub + (long long)ldu(srcp, r) * S;
+        const auto ru0 = rsrc(us), ru1 = rsrc(us + half);
+#pragma unroll
+        for (int j = 0; j < RB; j++) {
+            o.u0[j] = bload<T>(ru0, rob[j]);
+            o.u1[j] = bload<T>(ru1, rob[j]);
+        }
+#pragma unroll
+        for (int t = 0; t < TG; t++) o.off[t] = ldu(offp, r * TG + t);
+    };
+    auto sum = [&](const Rec &c) {
+#pragma unroll
+        for (int t = 0; t < TG; t++) {
+            if (c.off[t] >= 0) {   // uniform: the source is in target t's list
+                const cpx<T> op = tq[c.off[t] * QW];
+#pragma unroll
+                for (int j = 0; j < RB; j++) {
+                    fma_to(acc[t][0][j], op, c.u0[j]);
+                    fma_to(acc[t][1][j], op, c.u1[j]);
+                }
+            }
+        }
+    };
+    Rec ra, rb2;
+    if (r0 < r1) load(r0, ra);
+    for (int r = r0; r < r1; r += 2) {
+        load(min(r + 1, r1 - 1), rb2);
+        sum(ra);
+        if (r + 1 >= r1) break;
+        load(min(r + 2, r1 - 1), ra);
+        sum(rb2);
+    }
+    if (!qok) return;
+#pragma unroll
+    for (int t = 0; t < TG; t++) {
+        if (t < nt) {
+            cpx<T> *vt = L.V + (long long)(t0 + t) * S;
+#pragma unroll
+            for (int j = 0; j < RB; j++) {
+                const int rr = rbase + j * RW;
+                if (rr < nrhs) {
+                    vt[(long long)rr * K + q] = acc[t][0][j];
+                    vt[half + (long long)rr * K + q] = acc[t][1][j];
+                }
+            }
+        }
+    }
+}
 
 // Translation on the matrix cores, for groups of up to 16 targets (whole
 // sibling sets merged).  For one sample q a group's sums are a complex
@@ -245,6 +381,73 @@ __global__ __launch_bounds__(GWAVES * WAVE) void k_translate_mfma(const GroupArg
 }  // namespace
 
 
+// the LDS-operator kernel: (targets per group, lanes over the RHS, RHS per
+// lane) in {8, 16} x {(4, 4), (8, 2), (16, 1), (8, 1)}, double precision only
+// with at most 8 samples per wave (the LDS table) and TG * RB <= 16
+template <class T>
+bool launch_translate_lds(const GroupArgs<T> &args, int nrhs, hipStream_t s)
+{
+    const int tg = args.tg;
+    int rw = args.rw, rb = args.rb;
+    const bool shape = (rw == 4 && rb == 4) || (rw == 8 && rb == 2) || (rw == 16 && rb == 1) || (rw == 8 && rb == 1);
+    if ((tg != 8 && tg != 16) || !shape || tg * rb > 32) return false;
+    if (sizeof(T) == 8 && (rw < 8 || tg * rb > 16)) return false;
+    if (args.nlev <= 0 || nrhs <= 0) return true;
+    // a shape tuned for more right-hand sides than this call has: eight
+    // lanes over them, or (groups of 8, fewer than 8 RHS) the register
+    // kernel's default split
+    if (rw * rb > nrhs) {
+        if (tg == 8 && nrhs < 8) {
+            GroupArgs<T> b = args;
+            b.lds = 0;
+            b.rw = 0;
+            b.rb = 1;
+            return launch_translate_groups<T>(b, nrhs, s);
+        }
+        rw = 8;
+        rb = 1;
+    }
+    for (int l = 0; l < args.nlev; l++)   // 32-bit byte offsets within one box's patterns
+        if (2.0 * nrhs * args.lv[l].K * sizeof(cpx<T>) >= 4294967296.0) return false;
+    const int qw = WAVE / rw;
+    GroupArgs<T> a = args;
+    a.nblocks = 0;
+    for (int l = 0; l < a.nlev; l++) {
+        const int ngb = (a.lv[l].ngroup + GWAVES - 1) / GWAVES;
+        a.lv[l].nqc = (a.lv[l].K + qw - 1) / qw;
+        a.lv[l].first = a.nblocks;
+        a.nblocks += (ngb * a.lv[l].nqc + NXCD - 1) / NXCD;
+    }
+    if (a.nblocks <= 0) return true;
+    const dim3 grid((unsigned)a.nblocks * NXCD, (nrhs + rw * rb - 1) / (rw * rb)), block(GWAVES * WAVE);
+#define LDS_LAUNCH(TG_, RW_, RB_) hipLaunchKernelGGL((k_translate_lds<T, TG_, RW_, RB_>), grid, block, 0, s, a, nrhs)
+    if constexpr (sizeof(T) == 4) {
+        if (tg == 8) {
+            if (rw == 4) LDS_LAUNCH(8, 4, 4);
+            else if (rw == 16) LDS_LAUNCH(8, 16, 1);
+            else if (rb == 2) LDS_LAUNCH(8, 8, 2);
+            else LDS_LAUNCH(8, 8, 1);
+        } else {
+            if (rw == 16) LDS_LAUNCH(16, 16, 1);
+            else if (rb == 2) LDS_LAUNCH(16, 8, 2);
+            else if (rw == 8) LDS_LAUNCH(16, 8, 1);
+            else return false;
+        }
+    } else {
+        if (tg == 8) {
+            if (rw == 16) LDS_LAUNCH(8, 16, 1);
+            else if (rb == 2) LDS_LAUNCH(8, 8, 2);
+            else LDS_LAUNCH(8, 8, 1);
+        } else {
+            if (rw == 16) LDS_LAUNCH(16, 16, 1);
+            else if (rb == 1) LDS_LAUNCH(16, 8, 1);
+            else return false;
+        }
+    }
+#undef LDS_LAUNCH
+    return true;
+}
+
 // the matrix-core kernel: args.rb = samples per wave (QT), args.rw = tiles of
 // 16 columns per wave (CT)
 template <class T>
@@ -284,6 +487,7 @@ template <class T>
 bool launch_translate_groups(const GroupArgs<T> &args, int nrhs, hipStream_t s)
 {
     const int tg = args.tg;
+    if (args.lds) return launch_translate_lds<T>(args, nrhs, s);
     if (tg == 16) return launch_translate_mfma<T>(args, nrhs, s);
     int rb = args.rb, rw = args.rw > 0 ? args.rw : trans_rw(nrhs);
     if (tg != 4 && tg != 8) return false;
@@ -303,6 +507,8 @@ bool launch_translate_groups(const GroupArgs<T> &args, int nrhs, hipStream_t s)
         }
     }
     if (args.nlev <= 0 || nrhs <= 0) return true;
+    for (int l = 0; l < args.nlev; l++)   // 32-bit byte offsets within one box's patterns
+        if (2.0 * nrhs * args.lv[l].K * sizeof(cpx<T>) >= 4294967296.0) return false;
     const int qw = WAVE / rw;
     GroupArgs<T> a = args;
     a.rb = rb;

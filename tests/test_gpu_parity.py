@@ -207,14 +207,15 @@ def test_sphere_r8_2000_rows_per_level():
         assert own <= LEVEL_OWN_TOL
 
 
-@pytest.mark.parametrize("kernel", ["tiled", "groups", "matrix"])
+@pytest.mark.parametrize("kernel", ["tiled", "groups", "matrix", "lds"])
 def test_translation_kernels(kernel):
-    """The three translation kernels, forced in turn (the autotuner otherwise
-    picks one per handle): the whole product against the oracle for 1, 3 and
-    20 right-hand sides (20: column tiles of the matrix-core kernel cut
-    short) in both precisions and both operators, and the far field against
-    that of another kernel (same sums in another order: agreement to
-    rounding)."""
+    """The translation kernels, forced in turn (the autotuner otherwise picks
+    one per handle; "lds" = sibling groups with the operators staged in LDS):
+    the whole product against the oracle for 1, 3 and 20 right-hand sides
+    (20: column tiles of the matrix-core kernel cut short; 1 and 3: shapes
+    tuned for more right-hand sides narrowed) in both precisions and both
+    operators, and the far field against that of another kernel (same sums
+    in another order: agreement to rounding)."""
     torch = _torch()
     import paper_2210_04892_amd as mf
     name = "sphere_r0.5"
@@ -222,10 +223,14 @@ def test_translation_kernels(kernel):
     g = mf.Geometry(v, t, k=K0, max_rhs=20, trans_kernel=kernel).precompute()
     other = mf.Geometry(v, t, k=K0, max_rhs=20, trans_kernel="groups" if kernel == "tiled" else "tiled").precompute()
     sh = g.tuning()
-    grouped = kernel != "tiled"
-    assert (sh["c64"][1] <= 0) == grouped and (sh["c128"][1] <= 0) == grouped
     for d in ("c64", "c128"):
-        assert (sh[d][0] == 16 and sh[d][1] <= 0) == (kernel == "matrix")
+        matrix = sh[d][0] == 16 and sh[d][1] == -1
+        assert (sh[d][1] > 0) == (kernel == "tiled")
+        assert matrix == (kernel == "matrix")
+        if kernel == "lds":
+            assert sh[d][1] == -2
+        if kernel == "groups":
+            assert sh[d][1] <= 0 and not matrix
     for nrhs in (1, 3, 20):
         x, rows, ref = reference(name, 192, nrhs, 5)
         N = x.shape[0] // 2
