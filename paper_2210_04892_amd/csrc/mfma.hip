@@ -178,14 +178,17 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
     };
     auto load = [&](int bk, Blk &o) {
         const int q0 = bk * 16 + kk * 4;
-        if (q0 + 3 < K) {
+        if (bk * 16 + 16 <= K) {   // the whole block (wave-uniform: one path per block)
+            // rows past the box and right-hand sides past nrhs read row 0 /
+            // right-hand side 0 (pm, v0 are clamped): they feed only D rows
+            // and columns that are never stored
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 o.w[u] = wq[q0 + u];
-                o.q[u][0] = mok ? pm[2 * (q0 + u)] : mk<T>(0, 0);
-                o.q[u][1] = mok ? pm[2 * (q0 + u) + 1] : mk<T>(0, 0);
-                o.v[0][u] = rok ? v0[q0 + u] : mk<T>(0, 0);
-                o.v[1][u] = rok ? v0[vstep + q0 + u] : mk<T>(0, 0);
+                o.q[u][0] = pm[2 * (q0 + u)];
+                o.q[u][1] = pm[2 * (q0 + u) + 1];
+                o.v[0][u] = v0[q0 + u];
+                o.v[1][u] = v0[vstep + q0 + u];
             }
         } else {
 #pragma unroll
@@ -202,11 +205,11 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
     };
     typename Mf<T>::v4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
     // DEPTH blocks in flight: block bk + DEPTH is loaded while block bk is
-    // multiplied (one in double precision, where a block takes 72 registers)
+    // multiplied (one in double precision, where a block takes 72
+    // registers).  The register sets take turns (no copies), and every path
+    // issues the same loads (past the last block they repeat it), so that
+    // the wait before a product counts the newer blocks' loads as in flight.
     constexpr int DEPTH = sizeof(T) == 8 ? 1 : 2;
-    Blk b0, b1, b2;
-    load(0, b0);
-    if (DEPTH == 2 && nblk > 1) load(1, b1);
     auto mult = [&](const Blk &cur) {
 #pragma unroll
         for (int c = 0; c < 2; c++)
@@ -223,11 +226,29 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
                 dim = Mf<T>::mma(a.im, bv.re, dim);
             }
     };
-    for (int bk = 0; bk < nblk; bk++) {
-        if (bk + DEPTH < nblk) load(bk + DEPTH, DEPTH == 2 ? b2 : b1);
-        mult(b0);
-        b0 = b1;
-        if (DEPTH == 2) b1 = b2;
+    auto at = [&](int bk) { return min(bk, nblk - 1); };
+    Blk b0, b1, b2;
+    load(0, b0);
+    if constexpr (DEPTH == 2) {
+        load(at(1), b1);
+        for (int bk = 0; bk < nblk; bk += 3) {
+            load(at(bk + 2), b2);
+            mult(b0);
+            if (bk + 1 >= nblk) break;
+            load(at(bk + 3), b0);
+            mult(b1);
+            if (bk + 2 >= nblk) break;
+            load(at(bk + 4), b1);
+            mult(b2);
+        }
+    } else {
+        for (int bk = 0; bk < nblk; bk += 2) {
+            load(at(bk + 1), b1);
+            mult(b0);
+            if (bk + 1 >= nblk) break;
+            load(at(bk + 2), b0);
+            mult(b1);
+        }
     }
 #pragma unroll
     for (int v = 0; v < 4; v++) {
