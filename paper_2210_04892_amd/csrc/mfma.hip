@@ -49,11 +49,15 @@ __device__ inline void cmfma(typename Mf<T>::v4 (&dre)[RT], typename Mf<T>::v4 (
     for (int t = 0; t < RT; t++) dim[t] = Mf<T>::mma(a[t].im, b.re, dim[t]);
 }
 
-// Radiation.  Wave = (box, component c, tile of 16 samples) x RT tiles of 16
-// right-hand sides; D[i = rhs][j = sample], inner index k = (RWG, alpha|beta):
-// one MFMA step covers two RWGs.  EM pair: alpha = x1, beta = -x2; C block:
-// alpha = x2 / 2, beta = x1 / 2.
-template <class T, int RT>
+// Radiation.  Wave = (box, component c, ST tiles of 16 samples) x RT tiles
+// of 16 right-hand sides; D[i = rhs][j = sample], inner index k = (RWG,
+// alpha|beta): one MFMA step covers two RWGs.  EM pair: alpha = x1, beta =
+// -x2; C block: alpha = x2 / 2, beta = x1 / 2.  The x values of a step (A
+// operand) serve all ST sample tiles.  Steps with both RWGs in the box load
+// without predicates, the next step's operands in flight while the current
+// one is multiplied (two register sets taking turns; past the last step the
+// loads repeat it).
+template <class T, int RT, int ST>
 __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, int nqt,
                                                       const int *__restrict__ box_start,
                                                       const cpx<T> *__restrict__ R,
@@ -61,7 +65,8 @@ __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, i
                                                       int nrhs)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tiles = 2 * nqt, per_box = (tiles + 3) / 4;
+    const int nqg = (nqt + ST - 1) / ST;   // groups of ST sample tiles
+    const int tiles = 2 * nqg, per_box = (tiles + 3) / 4;
     const int nrg = (nrhs + 16 * RT - 1) / (16 * RT);
     const long long blk = xcd_block_m((long long)nbox * per_box * nrg);
     if (blk < 0) return;
@@ -69,10 +74,15 @@ __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, i
     const long long bt = blk / nrg;
     const int b = (int)(bt / per_box), t = (int)(bt % per_box) * 4 + wave;
     if (t >= tiles) return;
-    const int c = t / nqt, q0 = (t % nqt) * 16;
+    const int c = t / nqg, qg = t % nqg;
     const int lo = lane & 15, kk = lane >> 4;
-    const int q = q0 + lo;
-    const bool qok = q < K;
+    int qs[ST];        // this lane's sample in each tile
+    long long qo[ST];  // its pattern offset, clamped to a valid sample
+#pragma unroll
+    for (int st = 0; st < ST; st++) {
+        qs[st] = (qg * ST + st) * 16 + lo;
+        qo[st] = min(qs[st], K - 1);
+    }
     const int s = kk & 1;
     // which half of X feeds this lane's alpha/beta, and its factor
     const int h = op == MLFMA_OP_EM ? s : 1 - s;
@@ -80,51 +90,75 @@ __global__ __launch_bounds__(256) void k_radiate_mfma(int op, int nbox, int K, i
     const int rcomp = s == 0 ? c : 1 - c;
     const T rsg = (s == 1 && c == 0) ? T(-1) : T(1);
     const int n0 = box_start[b], n1 = box_start[b + 1];
-    typename Mf<T>::v4 dre[RT], dim[RT];
+    int rr[RT];   // this lane's right-hand side per tile, clamped
 #pragma unroll
-    for (int u = 0; u < RT; u++) dre[u] = dim[u] = typename Mf<T>::v4{0, 0, 0, 0};
-    int n = n0;
-    // steps with both RWGs inside the box: operands without predicates
-    // (samples past K and right-hand sides past nrhs read clamped, valid
-    // elements; only their own outputs, which are never stored, see them)
-    const int qq = qok ? q : K - 1;
-    for (; n + 1 < n1; n += 2) {
-        const int nn = n + (kk >> 1);
-        const cpx<T> v = R[((long long)nn * K + qq) * 2 + rcomp];
-        const cpx<T> bv = mk<T>(rsg * v.re, rsg * v.im);
+    for (int u = 0; u < RT; u++) rr[u] = min((rg * RT + u) * 16 + lo, nrhs - 1);
+    typename Mf<T>::v4 dre[ST][RT], dim[ST][RT];
+#pragma unroll
+    for (int st = 0; st < ST; st++)
+#pragma unroll
+        for (int u = 0; u < RT; u++) dre[st][u] = dim[st][u] = typename Mf<T>::v4{0, 0, 0, 0};
+    struct Step {
+        cpx<T> v[ST], x[RT];
+    };
+    auto load = [&](int nn, Step &o) {
+        const cpx<T> *rn = R + (long long)nn * K * 2 + rcomp;
+#pragma unroll
+        for (int st = 0; st < ST; st++) o.v[st] = rn[qo[st] * 2];
+        const cpx<T> *xn = X + ((long long)nn * 2 + h) * nrhs;
+#pragma unroll
+        for (int u = 0; u < RT; u++) o.x[u] = xn[rr[u]];
+    };
+    auto mult = [&](const Step &o) {
         cpx<T> av[RT];
 #pragma unroll
-        for (int u = 0; u < RT; u++) {
-            const int r = min((rg * RT + u) * 16 + lo, nrhs - 1);
-            av[u] = fac * X[((long long)nn * 2 + h) * nrhs + r];
-        }
-        cmfma<T, RT>(dre, dim, av, bv);
-    }
-    for (; n < n1; n += 2) {
-        const int nn = n + (kk >> 1);
-        const bool nok = nn < n1;
-        cpx<T> bv = mk<T>(0, 0);
-        if (nok && qok) {
+        for (int u = 0; u < RT; u++) av[u] = fac * o.x[u];
+#pragma unroll
+        for (int st = 0; st < ST; st++) {
             // alpha lanes take R[c]; beta lanes (khat x R)[c]: (-R_phi, R_theta)
-            const cpx<T> v = R[((long long)nn * K + q) * 2 + rcomp];
-            bv = mk<T>(rsg * v.re, rsg * v.im);
+            const cpx<T> bv = mk<T>(rsg * o.v[st].re, rsg * o.v[st].im);
+            cmfma<T, RT>(dre[st], dim[st], av, bv);
         }
-        cpx<T> av[RT];
+    };
+    // steps with both RWGs inside the box (samples past K and right-hand
+    // sides past nrhs read clamped, valid elements; only their own outputs,
+    // which are never stored, see them)
+    const int nfull = (n1 - n0) / 2;
+    auto rwg = [&](int step) { return n0 + 2 * min(step, nfull - 1) + (kk >> 1); };
+    if (nfull > 0) {
+        Step s0, s1;
+        load(rwg(0), s0);
+        for (int step = 0; step < nfull; step += 2) {
+            load(rwg(step + 1), s1);
+            mult(s0);
+            if (step + 1 >= nfull) break;
+            load(rwg(step + 2), s0);
+            mult(s1);
+        }
+    }
+    if (n0 + 2 * nfull < n1) {   // the last RWG of an odd box: lanes of the absent second RWG feed zeros
+        const int nn = n0 + 2 * nfull + (kk >> 1);
+        Step o;
+        load(min(nn, n1 - 1), o);
+        if (nn >= n1) {
 #pragma unroll
-        for (int u = 0; u < RT; u++) {
-            const int r = (rg * RT + u) * 16 + lo;
-            av[u] = mk<T>(0, 0);
-            if (nok && r < nrhs) av[u] = fac * X[((long long)nn * 2 + h) * nrhs + r];
+            for (int st = 0; st < ST; st++) o.v[st] = mk<T>(0, 0);
+#pragma unroll
+            for (int u = 0; u < RT; u++) o.x[u] = mk<T>(0, 0);
         }
-        cmfma<T, RT>(dre, dim, av, bv);
+        mult(o);
     }
 #pragma unroll
-    for (int u = 0; u < RT; u++)
+    for (int st = 0; st < ST; st++) {
+        if (qs[st] >= K) continue;
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const int r = (rg * RT + u) * 16 + Mf<T>::row(kk, v);
-            if (qok && r < nrhs) U[pidx_m(b, c, r, q, nrhs, K)] = mk<T>(dre[u][v], dim[u][v]);
-        }
+        for (int u = 0; u < RT; u++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int r = (rg * RT + u) * 16 + Mf<T>::row(kk, v);
+                if (r < nrhs) U[pidx_m(b, c, r, qs[st], nrhs, K)] = mk<T>(dre[st][u][v], dim[st][u][v]);
+            }
+    }
 }
 
 // Receive.  Work item = (leaf box, row tile of 16 rows (RWG m, half h),
@@ -396,17 +430,20 @@ bool launch_radiate_mfma(int op, int nbox, int K, const int *box_start, const cp
                          int nrhs, hipStream_t s)
 {
     if (nrhs < 16) return false;
-    const int nqt = (K + 15) / 16, per_box = (2 * nqt + 3) / 4;
-    // right-hand-side tiles per wave (the double-precision sums take twice the registers)
+    const int nqt = (K + 15) / 16;
+    // right-hand-side tiles per wave (the double-precision sums take twice
+    // the registers); with one, two sample tiles share each x load
     const int rt = sizeof(T) == 8 ? (nrhs >= 32 ? 2 : 1) : (nrhs >= 64 ? 4 : (nrhs >= 32 ? 2 : 1));
+    const int st = rt == 1 ? 2 : 1;
+    const int per_box = (2 * ((nqt + st - 1) / st) + 3) / 4;
     const long long nblk = (long long)nbox * per_box * ((nrhs + 16 * rt - 1) / (16 * rt));
     if (nblk <= 0) return true;
     const dim3 grid(xcd_grid_m(nblk)), block(256);
     if (rt == 4)
-        hipLaunchKernelGGL((k_radiate_mfma<T, 4>), grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
+        hipLaunchKernelGGL((k_radiate_mfma<T, 4, 1>), grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
     else if (rt == 2)
-        hipLaunchKernelGGL((k_radiate_mfma<T, 2>), grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
-    else hipLaunchKernelGGL((k_radiate_mfma<T, 1>), grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
+        hipLaunchKernelGGL((k_radiate_mfma<T, 2, 1>), grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
+    else hipLaunchKernelGGL((k_radiate_mfma<T, 1, 2>), grid, block, 0, s, op, nbox, K, nqt, box_start, R, X, U, nrhs);
     return true;
 }
 
