@@ -307,16 +307,16 @@ __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate_pipe(const LevelS
         const int i = tid + k * STEP_THREADS;
         shf[k] = i < plen ? conjg(sh[i]) : mk<T>(0, 0);
     }
+    // the window and old-value loads take clamped (valid) addresses and no
+    // predicate: slots past the window or the output are never written, and
+    // a load whose value is not selected right away stays in flight
     cpx<T> pf[NPF][NV];
     auto load_window = [&](int v0) {
 #pragma unroll
         for (int k = 0; k < NPF; k++) {
-            const int i = tid + k * STEP_THREADS;
+            const int i = min(tid + k * STEP_THREADS, plen - 1);
 #pragma unroll
-            for (int j = 0; j < NV; j++) {
-                const long long o = (long long)min(v0 + j, nvec - 1) * Kp + i;
-                pf[k][j] = i < plen ? pin[o] : mk<T>(0, 0);
-            }
+            for (int j = 0; j < NV; j++) pf[k][j] = pin[(long long)min(v0 + j, nvec - 1) * Kp + i];
         }
     };
     load_window(vs0);
@@ -334,14 +334,13 @@ __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate_pipe(const LevelS
                 for (int j = 0; j < NV; j++) pw[j * pmax + i] = shf[k] * pf[k][j];
             }
         }
-        if (v0 + NV < vs1) load_window(v0 + NV);
+        load_window(min(v0 + NV, vs1 - 1));   // past the last pass: repeats a valid window
         cpx<T> old[NO][NV];
 #pragma unroll
         for (int q = 0; q < NO; q++) {
-            const int o = tid + q * STEP_THREADS;
+            const int o = min(tid + q * STEP_THREADS, olen - 1);
 #pragma unroll
-            for (int j = 0; j < NV; j++)
-                old[q][j] = o < olen && v0 + j < vs1 ? pout[(long long)(v0 + j) * Kc + o] : mk<T>(0, 0);
+            for (int j = 0; j < NV; j++) old[q][j] = pout[(long long)min(v0 + j, vs1 - 1) * Kc + o];
         }
         __syncthreads();
         // phi anterpolation: intermediate rows from the parent rows of the window
