@@ -615,13 +615,29 @@ GroupArgs<T> group_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, 
     return ga;
 }
 
+// The sibling-group shape a call with nrhs right-hand sides runs: the tuned
+// one, except that a tuned LDS-operator shape with more lanes times
+// right-hand sides per lane than the call has (its lanes would idle) gives
+// way to the register kernel on the merged 8-target groups with the default
+// lane split.
+struct TransShape {
+    int gi, rb, rw, lds;
+};
+template <class T>
+TransShape trans_shape(const Prec<T> &P, int nrhs)
+{
+    if (P.trans_group <= 0) return {0, 1, 0, 0};
+    if (P.trans_lds && P.trans_rw * P.trans_rb > nrhs) return {2, 1, 0, 0};
+    return {P.trans_gi, P.trans_rb, P.trans_rw, P.trans_lds};
+}
+
 // the translation of all levels (or of only_level) with the tuned kernel
 template <class T>
 void launch_translation(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, int nrhs, hipStream_t st)
 {
     if (P.trans_group > 0) {
-        if (!launch_translate_groups<T>(group_args<T>(c, P, w, only_level, P.trans_gi, P.trans_rb, P.trans_rw, P.trans_lds),
-                                        nrhs, st))
+        const TransShape gs = trans_shape(P, nrhs);
+        if (!launch_translate_groups<T>(group_args<T>(c, P, w, only_level, gs.gi, gs.rb, gs.rw, gs.lds), nrhs, st))
             throw Error(MLFMA_ERR_STATE, "invalid sibling-group translation shape");
     } else if (!launch_translate_tiled<T>(trans_args<T>(c, P, w, only_level), nrhs, st)) {
         throw Error(MLFMA_ERR_STATE, "translation tiles missing");
@@ -2201,8 +2217,8 @@ void batch_fused(const mlfma_batch_item *items, int n, hipStream_t st)
         }
     }
     const Prec<T> &PR = prec_of<T>(items[ref].h);
-    const int gi = PR.trans_group > 0 ? PR.trans_gi : 0, rb = PR.trans_group > 0 ? PR.trans_rb : 1;
-    const int rw = PR.trans_group > 0 ? PR.trans_rw : 0, lds = PR.trans_group > 0 ? PR.trans_lds : 0;
+    const TransShape gs = trans_shape(PR, nrhs);
+    const int gi = gs.gi, rb = gs.rb, rw = gs.rw, lds = gs.lds;
     GroupArgs<T> ga;
     ga.tg = group_tg(gi);
     ga.rb = rb;
