@@ -314,7 +314,7 @@ __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate_pipe(const LevelS
     auto load_window = [&](int v0) {
 #pragma unroll
         for (int k = 0; k < NPF; k++) {
-            const int i = min(tid + k * STEP_THREADS, plen - 1);
+            const int i = min(tid + k * STEP_THREADS, max(plen - 1, 0));
 #pragma unroll
             for (int j = 0; j < NV; j++) pf[k][j] = pin[(long long)min(v0 + j, nvec - 1) * Kp + i];
         }
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(STEP_THREADS) void k_disaggregate_pipe(const LevelS
         cpx<T> old[NO][NV];
 #pragma unroll
         for (int q = 0; q < NO; q++) {
-            const int o = min(tid + q * STEP_THREADS, olen - 1);
+            const int o = min(tid + q * STEP_THREADS, max(olen - 1, 0));
 #pragma unroll
             for (int j = 0; j < NV; j++) old[q][j] = pout[(long long)min(v0 + j, vs1 - 1) * Kc + o];
         }
@@ -455,25 +455,25 @@ __global__ __launch_bounds__(STEP_THREADS) void k_aggregate_pipe(const LevelStep
     }
     const long long hc = (long long)nrhs * Kc;   // second component
     const cpx<T> *shq = a.shift + (long long)i0 * nph_p;
+    // the window and shift loads take clamped (valid) addresses and no
+    // predicate: slots past the window or the outputs are never used, and a
+    // load whose value is not selected right away stays in flight
     cpx<T> pf0[NPF][RB], pf1[NPF][RB], sfn[NO];
     auto load = [&](int r0, int cg) {
         const cpx<T> *u = a.in + (long long)cg * 2 * nrhs * Kc + (long long)w0 * nph_c;
 #pragma unroll
         for (int k = 0; k < NPF; k++) {
-            const int i = tid + k * STEP_THREADS;
+            const int i = min(tid + k * STEP_THREADS, max(wlen - 1, 0));
 #pragma unroll
             for (int j = 0; j < RB; j++) {
                 const long long o = (long long)min(r0 + j, nrhs - 1) * Kc + i;
-                pf0[k][j] = i < wlen ? u[o] : mk<T>(0, 0);
-                pf1[k][j] = i < wlen ? u[hc + o] : mk<T>(0, 0);
+                pf0[k][j] = u[o];
+                pf1[k][j] = u[hc + o];
             }
         }
         const cpx<T> *f = shq + (long long)a.oct[cg] * Kp;
 #pragma unroll
-        for (int q = 0; q < NO; q++) {
-            const int o = tid + q * STEP_THREADS;
-            sfn[q] = o < olen ? f[o] : mk<T>(0, 0);
-        }
+        for (int q = 0; q < NO; q++) sfn[q] = f[min(tid + q * STEP_THREADS, max(olen - 1, 0))];
     };
     if (cb < ce) load(rs0, cb);
     const int dq = STEP_THREADS / nph_c, dr = STEP_THREADS - dq * nph_c;     // intermediate slots
@@ -504,8 +504,10 @@ __global__ __launch_bounds__(STEP_THREADS) void k_aggregate_pipe(const LevelStep
             cpx<T> sfc[NO];
 #pragma unroll
             for (int q = 0; q < NO; q++) sfc[q] = sfn[q];
+            // the next child, else the next pass's first child, else this
+            // child again (loads issued on every path)
             if (cg + 1 < ce) load(r0, cg + 1);
-            else if (r0 + RB < rs1) load(r0 + RB, cb);
+            else load(r0 + RB < rs1 ? r0 + RB : r0, r0 + RB < rs1 ? cb : cg);
             __syncthreads();
             // theta: intermediate (parent theta row, child phi column)
             {
