@@ -300,8 +300,9 @@ __global__ __launch_bounds__(256) void k_receive_mfma(int op, int nitem, const i
 // columns are the RWGs of its <= 27 adjacent boxes, concatenated (the order
 // the stored (A, B) rows follow), listed in cols[col_off[b] ..].
 // D[i = (m, h)][j = rhs] with inner index k = (column, half h'): two columns
-// per MFMA step, the next step's operands loaded before the current step's
-// MFMAs.  The 2 x 2 block of a pair is [[A, -B], [B, A]].  The identity
+// per MFMA step, taken in blocks of eight columns (four steps) whose inner
+// index is permuted so that each lane reads its row's entries as runs.  The
+// 2 x 2 block of a pair is [[A, -B], [B, A]].  The identity
 // terms of the C block (Gram and rotated Gram, same triangle only) are added
 // in the epilogue; Y is overwritten.
 template <class T>
@@ -337,14 +338,72 @@ __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__rest
     // column indices 64 at a time, one per lane, handed out by lane shuffles
     // (so the x load of a step does not wait for an index load)
     int cbase = -64, myc = 0;
-    auto load = [&](int j0, cpx<T> &a, cpx<T> &bv) {
-        if (j0 >= cbase + 64) {              // j0 is even: a step never straddles two groups
-            cbase = j0;
+    auto cols_for = [&](int j0) {
+        if (j0 >= cbase + 64) {   // j0 is even: a step never straddles two groups
+            cbase = j0 - j0 % 64;
             myc = cl[min(cbase + lane, ncols - 1)];
         }
+    };
+    typename Mf<T>::v4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+    auto mma = [&](cpx<T> a, cpx<T> bv) {
+        dre = Mf<T>::mma(a.re, bv.re, dre);
+        dim = Mf<T>::mma(a.re, bv.im, dim);
+        dre = Mf<T>::mma(-a.im, bv.im, dre);
+        dim = Mf<T>::mma(a.im, bv.re, dim);
+    };
+    const int rc = rok ? r : 0;
+    // Blocks of 8 columns, four MFMA steps: lane group kk takes columns
+    // j = j0 + 2 kk + c (c = 0, 1) and step u = 2 c + h' feeds column
+    // j0 + 2 kk + c, half h' -- the same inner index for the A and B operands
+    // -- so that a lane reads the (A, B) entries of its two columns as one
+    // run of its row (rows past the tile and right-hand sides past nrhs read
+    // clamped, valid elements that only feed outputs never stored).  The next
+    // block's operands are in flight while a block is multiplied (two
+    // register sets taking turns; past the last block the loads repeat it).
+    const int nb8 = ncols / 8;
+    const T sgb = h == 0 ? T(-1) : T(1);   // B's sign where h' != h
+    struct Blk8 {
+        cpx<T> v[4];   // A, B of the lane's first column, A, B of its second
+        cpx<T> x[4];   // x of (column c, half h') at 2 c + h'
+    };
+    auto load8 = [&](int bi, Blk8 &o) {
+        const int j0 = bi * 8, j = j0 + 2 * kk;
+        cols_for(j0);
+#pragma unroll
+        for (int e = 0; e < 4; e++) o.v[e] = vr[2 * j + e];
+        const int c0 = __shfl(myc, j - cbase), c1 = __shfl(myc, j + 1 - cbase);
+#pragma unroll
+        for (int hh = 0; hh < 2; hh++) {
+            o.x[hh] = X[((long long)c0 * 2 + hh) * nrhs + rc];
+            o.x[2 + hh] = X[((long long)c1 * 2 + hh) * nrhs + rc];
+        }
+    };
+    auto mult8 = [&](const Blk8 &o) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int c = u >> 1, hh = u & 1;
+            const cpx<T> av = hh == h ? o.v[2 * c] : sgb * o.v[2 * c + 1];
+            mma(av, o.x[u]);
+        }
+    };
+    if (nb8 > 0) {
+        Blk8 s0, s1;
+        load8(0, s0);
+        for (int bi = 0; bi < nb8; bi += 2) {
+            load8(min(bi + 1, nb8 - 1), s1);
+            mult8(s0);
+            if (bi + 1 >= nb8) break;
+            load8(min(bi + 2, nb8 - 1), s0);
+            mult8(s1);
+        }
+    }
+    // the last ncols % 8 columns, two per step (lane group kk: column j0 +
+    // kk / 2, half kk % 2)
+    auto load = [&](int j0, cpx<T> &a, cpx<T> &bv) {
+        cols_for(j0);
         const int j = j0 + jc;
         const bool jok = j < ncols;
-        const int col = __shfl(myc, j - cbase);
+        const int col = __shfl(myc, min(j, ncols - 1) - cbase);
         a = mk<T>(0, 0);
         bv = mk<T>(0, 0);
         if (jok && mok) {
@@ -354,38 +413,10 @@ __global__ __launch_bounds__(256) void k_near_mfma(int nitem, const int2 *__rest
         }
         if (jok && rok) bv = X[((long long)col * 2 + hp) * nrhs + r];
     };
-    typename Mf<T>::v4 dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
-    cpx<T> a, bv, an, bn;
-    auto step = [&]() {
-        dre = Mf<T>::mma(a.re, bv.re, dre);
-        dim = Mf<T>::mma(a.re, bv.im, dim);
-        dre = Mf<T>::mma(-a.im, bv.im, dre);
-        dim = Mf<T>::mma(a.im, bv.re, dim);
-        a = an;
-        bv = bn;
-    };
-    load(0, a, bv);
-    int j0 = 0;
-    // steps whose successor lies wholly inside the row: the successor's
-    // operands without predicates (rows past the tile and right-hand sides
-    // past nrhs read clamped, valid elements; only their own outputs, which
-    // are never stored, see them)
-    const int rc = rok ? r : 0;
-    for (; j0 + 4 <= ncols; j0 += 2) {
-        const int j = j0 + 2 + jc;
-        if (j0 + 2 >= cbase + 64) {
-            cbase = j0 + 2;
-            myc = cl[min(cbase + lane, ncols - 1)];
-        }
-        const int col = __shfl(myc, j - cbase);
-        const cpx<T> v = vr[2 * j + vsel];
-        an = mk<T>(vsg * v.re, vsg * v.im);
-        bn = X[((long long)col * 2 + hp) * nrhs + rc];
-        step();
-    }
-    for (; j0 < ncols; j0 += 2) {
-        if (j0 + 2 < ncols) load(j0 + 2, an, bn);
-        step();
+    for (int j0 = nb8 * 8; j0 < ncols; j0 += 2) {
+        cpx<T> a, bv;
+        load(j0, a, bv);
+        mma(a, bv);
     }
 #pragma unroll
     for (int v = 0; v < 4; v++) {
