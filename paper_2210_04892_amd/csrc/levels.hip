@@ -74,16 +74,36 @@ __global__ __launch_bounds__(STEP_THREADS) void k_aggregate(const LevelStep<T> a
     const int cb = a.child_start[Pb], ce = a.child_start[Pb + 1];
     for (int cg = cb; cg < ce; cg += G) {
         const int ng = GROUPED ? min(G, ce - cg) : 1;
+        // stage the group's windows: each thread loads up to SW samples of
+        // every right-hand side and component (clamped addresses, all loads
+        // in flight together) before it writes any of them to LDS
+        constexpr int SW = 2;
         for (int g = 0; g < ng; g++) {
+            const cpx<T> *ub = a.in + pat(cg + g, 0, 0, w0 * a.nph_c, nrhs, Kc);
+            for (int ib = threadIdx.x; ib < wlen; ib += SW * STEP_THREADS) {
+                cpx<T> v0[SW][RB], v1[SW][RB];
 #pragma unroll
-            for (int j = 0; j < RB; j++) {
-                const int r = min(r0 + j, nrhs - 1);
-                const cpx<T> *u0 = a.in + pat(cg + g, 0, r, w0 * a.nph_c, nrhs, Kc);
-                const cpx<T> *u1 = u0 + (long long)nrhs * Kc;
-                cpx<T> *d = cw + (size_t)(2 * (g * RB + j)) * wmax;
-                for (int i = threadIdx.x; i < wlen; i += STEP_THREADS) {
-                    d[i] = u0[i];
-                    d[wmax + i] = u1[i];
+                for (int k = 0; k < SW; k++) {
+                    const int i = min(ib + k * STEP_THREADS, wlen - 1);
+#pragma unroll
+                    for (int j = 0; j < RB; j++) {
+                        const cpx<T> *u0 = ub + (long long)min(r0 + j, nrhs - 1) * Kc;
+                        v0[k][j] = u0[i];
+                        v1[k][j] = u0[(long long)nrhs * Kc + i];
+                    }
+                }
+                // slots past the window write the last sample's value to its
+                // own slot again (the same value: no predicate, so the loads
+                // are not moved below a branch)
+#pragma unroll
+                for (int k = 0; k < SW; k++) {
+                    const int i = min(ib + k * STEP_THREADS, wlen - 1);
+#pragma unroll
+                    for (int j = 0; j < RB; j++) {
+                        cpx<T> *d = cw + (size_t)(2 * (g * RB + j)) * wmax;
+                        d[i] = v0[k][j];
+                        d[wmax + i] = v1[k][j];
+                    }
                 }
             }
         }
