@@ -616,10 +616,11 @@ GroupArgs<T> group_args(mlfma_ctx *c, Prec<T> &P, Workspace &w, int only_level, 
 }
 
 // The sibling-group shape a call with nrhs right-hand sides runs: the tuned
-// one, except that a tuned LDS-operator shape with more lanes times
-// right-hand sides per lane than the call has (its lanes would idle) gives
-// way to the register kernel on the merged 8-target groups with the default
-// lane split.
+// one (whose launcher narrows a shape wider than the call: eight lanes over
+// the right-hand sides, or for 8-target groups and fewer than 8 of them the
+// register kernel), except that a tuned LDS-operator shape on 16-target
+// groups gives way, below 8 right-hand sides (its lanes would idle), to the
+// register kernel on the merged 8-target groups with the default lane split.
 struct TransShape {
     int gi, rb, rw, lds;
 };
@@ -627,7 +628,7 @@ template <class T>
 TransShape trans_shape(const Prec<T> &P, int nrhs)
 {
     if (P.trans_group <= 0) return {0, 1, 0, 0};
-    if (P.trans_lds && P.trans_rw * P.trans_rb > nrhs) return {2, 1, 0, 0};
+    if (P.trans_lds && P.trans_gi == 3 && nrhs < 8) return {2, 1, 0, 0};
     return {P.trans_gi, P.trans_rb, P.trans_rw, P.trans_lds};
 }
 

@@ -77,9 +77,26 @@ __global__ __launch_bounds__(STEP_THREADS) void k_aggregate(const LevelStep<T> a
         // stage the group's windows: each thread loads up to SW samples of
         // every right-hand side and component (clamped addresses, all loads
         // in flight together) before it writes any of them to LDS
-        constexpr int SW = 2;
         for (int g = 0; g < ng; g++) {
             const cpx<T> *ub = a.in + pat(cg + g, 0, 0, w0 * a.nph_c, nrhs, Kc);
+            if (wlen <= STEP_THREADS) {   // one slot per thread
+                const int i = min((int)threadIdx.x, max(wlen - 1, 0));
+                cpx<T> v0[RB], v1[RB];
+#pragma unroll
+                for (int j = 0; j < RB; j++) {
+                    const cpx<T> *u0 = ub + (long long)min(r0 + j, nrhs - 1) * Kc;
+                    v0[j] = u0[i];
+                    v1[j] = u0[(long long)nrhs * Kc + i];
+                }
+#pragma unroll
+                for (int j = 0; j < RB; j++) {
+                    cpx<T> *d = cw + (size_t)(2 * (g * RB + j)) * wmax;
+                    d[i] = v0[j];
+                    d[wmax + i] = v1[j];
+                }
+                continue;
+            }
+            constexpr int SW = 2;
             for (int ib = threadIdx.x; ib < wlen; ib += SW * STEP_THREADS) {
                 cpx<T> v0[SW][RB], v1[SW][RB];
 #pragma unroll
