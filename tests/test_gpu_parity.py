@@ -114,6 +114,33 @@ def test_near_field_fp64(name, nrows, op):
     assert err <= NEAR_TOL
 
 
+@pytest.mark.parametrize("name,nrows", [("ico6_r0.5", None), ("box_4x4x1", 320)])
+@pytest.mark.parametrize("op", ["C", "EM"])
+def test_near_field_fp64_matrix_cores(name, nrows, op):
+    """The double-precision near field with 20 right-hand sides, which runs
+    on the FP64 matrix cores (one full 16-wide tile and a ragged one): all
+    columns against the oracle's near field to the bound of the
+    one-right-hand-side test (relative 2-norm over the block), and three
+    columns against the one-right-hand-side vector kernel on the same tables
+    to 1e-12 (the two differ only in the order of the FP64 sums, so this
+    pins the matrix-core kernel apart from the quadrature)."""
+    import paper_2210_04892_amd as mf
+    x, rows, ref = reference(name, nrows, 20, 3)
+    N = x.shape[0] // 2
+    yfull = _gpu(name, x, op, np.complex128, part=mf.PART_NEAR)
+    y = _pick(yfull, rows, N)
+    err = _rel(y, ref[op][0])
+    worst = max(_rel(y[:, r], ref[op][0][:, r]) for r in range(x.shape[1]))
+    print("[gpu] %s op %s near c128 20 RHS (matrix cores) rel err %.3e (worst column %.3e)"
+          % (name, op, err, worst), flush=True)
+    assert err <= NEAR_TOL
+    for r in (0, 7, 19):
+        y1 = _gpu(name, x[:, r:r + 1], op, np.complex128, part=mf.PART_NEAR)[:, 0]
+        d = _rel(yfull[:, r], y1)
+        print("[gpu] %s op %s column %d: matrix cores vs vector kernel %.3e" % (name, op, r, d), flush=True)
+        assert d <= 1e-12
+
+
 @pytest.mark.parametrize("name", ["ico6_r0.5", "sphere_r0.5", "box_4x4x1", "two_bodies"])
 def test_near_field_fp64_vs_subtraction_route(name):
     """The double-precision near field on unit columns (seeded RWGs, J and M
