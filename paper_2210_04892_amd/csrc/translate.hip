@@ -12,11 +12,18 @@
 // Lanes: QW = 64 / RW consecutive samples x RW right-hand sides; each lane
 // handles RB right-hand sides (rbase + j RW).  Fewer samples per wave (more
 // lanes over the right-hand sides) load each operator value for fewer sums
-// but keep fewer sums per lane (more waves resident): the autotuner picks.  A workgroup of four waves
-// takes four consecutive sample chunks of one group.  Workgroups are ordered
-// sample chunk first, group second, and every XCD takes a contiguous range
-// of each level: consecutive groups (Morton order) share sources through the
-// XCD's L2, and the operator rows of one sample chunk stay resident there.
+// but keep fewer sums per lane (more waves resident): the autotuner picks.
+// A workgroup of four waves takes four consecutive sample chunks of one
+// group.  Workgroups are ordered sample chunk first, group second, and every
+// XCD takes a contiguous range of each level: consecutive groups (Morton
+// order) share sources through the XCD's L2, and the operator rows of one
+// sample chunk stay resident there.
+//
+// Two variants share the group tables: k_translate_lds stages the operator
+// rows of a sample chunk in LDS for a workgroup of four groups (only source
+// samples then travel through the vector memory path), and k_translate_mfma
+// forms the sums of a 16-target group as one complex product per sample on
+// the matrix cores.
 #include "device.hpp"
 #include "mfma_ops.hpp"
 
